@@ -1,0 +1,193 @@
+"""Benchmark of the SSCN hot path on one MI355X.
+
+Workload (default): the 2D rotating-GP problem on a 512 x 512 grid on
+[-12.8, 12.8)^2, gamma = 1, nu = 1.05, g = 1000, Omega = 0.9, dt = 5e-4,
+imaginary time with renormalisation every step, complex128 arithmetic,
+starting from the one-vortex random-phase state of Eq. (fun) (seed 13).
+One step = H1 + x-sweep + y-sweep + FP64 norm (the rescale is folded into
+the next step).  `value` = grid-point updates per second over exactly
+--steps timed steps, inputs resident on the GPU.
+
+Also reported on the same JSON line:
+  roofline      the dominant sweep kernel: algorithmic bytes (one read and
+                one write of the state) / its average duration measured with
+                HIP events on the stream it runs on, against 8 TB/s HBM;
+  variants      the same workload with complex64 sweeps, its real-time
+                phase, and the 3D 256 x 256 x 64 complex64 workload;
+  converge      time to a converged lattice on the 128^2 workload (mu
+                changing by < 1e-8 over 0.1 time units at two consecutive
+                checks with an unchanged vortex count);
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the default
+                workload, on the host cores.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20000)
+    ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--precision", choices=("c128", "c64"), default="c128")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip variants and convergence")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def timed_steps(P, torch, cfg, steps, warmup, mode=0):
+    s = P.Solver(W.solver_params(cfg, mode=mode))
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    s.init_state(cfg.get("kind", 1), ph, cfg.get("d_xy", 1.0), cfg.get("d_z", 0.0))
+    s.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return s, dt
+
+
+def kernel_roofline(s, cfg, nsteps=200):
+    """Average duration of each sweep kernel (HIP events on the solver's
+    stream) and the dominant one's algorithmic bandwidth."""
+    ms = s.profile_step(nsteps)
+    pts = cfg["nx"] * cfg["ny"] * (cfg["nz"] if cfg["dim"] == 3 else 1)
+    esize = 16 if cfg.get("precision", 0) == 0 else 8
+    per_launch = 2 * esize * pts  # one read + one write of the state
+    names = ("x", "y", "z") if cfg["dim"] == 3 else ("x", "y")
+    dom = max(names, key=lambda k: ms[k])
+    gbs = per_launch / (ms[dom] * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
+            "kernel": f"{dom}-sweep", "bytes_per_launch": per_launch,
+            "kernel_ms": {k: round(ms[k], 5) for k in names}, "step_ms_events": round(ms["step"], 5)}
+
+
+def converge_run(P, torch, cfg, max_steps=400000):
+    """Imaginary time from Eq. (fun) until |mu_n - mu_{n-1}| < 1e-8 at two
+    consecutive checks 0.1 time units apart with the vortex count unchanged."""
+    s = P.Solver(W.solver_params(cfg))
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    chk = max(1, int(round(0.1 / cfg["dt"])))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.init_state(1, ph, 1.0)
+    prev, hits, steps, count_prev = None, 0, 0, None
+    while steps < max_steps:
+        s.step(chk)
+        steps += chk
+        mu = s.observables()["mu"]
+        if prev is not None and abs(mu - prev) < 1e-8:
+            c = s.vortex_count()
+            hits = hits + 1 if (count_prev is None or c == count_prev) else 0
+            count_prev = c
+            if hits >= 2:
+                break
+        else:
+            hits, count_prev = 0, None
+        prev = mu
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ob = s.observables()
+    out = {"workload": "128x128 2D, g=100, Omega=0.6, dt=1e-3, complex128", "steps": steps,
+           "converged": hits >= 2, "wall_s": round(wall, 4), "mu": ob["mu"],
+           "energy": ob["energy"], "vortices": s.vortex_count()}
+    s.close()
+    return out
+
+
+def cpu_baseline(cfg, seconds):
+    """The FP64 oracle as it stands on the host cores, on a bounded sample
+    (consecutive steps of the same workload from the same initial state)."""
+    import oracle as O
+    p = O.make_params(**W.solver_params(cfg))
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    psi = O.init_state(p, 1, ph, 1.0)
+    psi = O.step(p, psi, 2)  # warm-up
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        psi = O.step(p, psi, 25)
+        steps += 25
+    dt = time.perf_counter() - t0
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    pts = cfg["nx"] * cfg["ny"]
+    return {"value": round(pts * steps / dt, 1), "unit": "updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} consecutive imaginary-time steps of the 512x512 complex128 "
+                      f"workload ({dt:.1f} s), OpenMP over lines with {threads} threads"}
+
+
+def main():
+    a = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus > 1 or world > 1:
+        print(f"bench.py measures one GPU only: this solver has no multi-GPU path "
+              f"(asked for --gpus {a.gpus}, WORLD_SIZE {world}).", flush=True)
+        sys.exit(2)
+    import torch
+    import paper_1906_06327_amd as P
+    P.lib()
+    cfg = dict(W.CONFIGS["c2"], precision=0 if a.precision == "c128" else 1)
+    torch.cuda.set_device(0)
+
+    s, dt = timed_steps(P, torch, cfg, a.steps, a.warmup)
+    pts = cfg["nx"] * cfg["ny"]
+    value = pts * a.steps / dt
+    roof = kernel_roofline(s, cfg)
+    s.close()
+
+    out = {
+        "metric": "grid-point updates/s per SSCN step (% HBM roofline) + time-to-converged lattice",
+        "value": round(value, 1), "unit": "updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(dt / a.steps * 1e3, 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if a.precision == "c128" else "f32",
+        "data": "synthetic (one-vortex random-phase initial state, seed 13)",
+        "config": {"workload": "2D rotating GP, 512x512 on [-12.8,12.8)^2, gamma=1, nu=1.05, "
+                               "g=1000, Omega=0.9, dt=5e-4, imaginary time, renormalised each step",
+                   "grid": [cfg["nx"], cfg["ny"]], "precision": a.precision,
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+    }
+    if not a.no_extras:
+        variants = {}
+        c64 = dict(W.CONFIGS["c2"], precision=1)
+        s, dt = timed_steps(P, torch, c64, 5000, 256)
+        variants["c2_complex64"] = {"updates_per_s": round(pts * 5000 / dt, 1),
+                                    "ms_per_step": round(dt / 5000 * 1e3, 6),
+                                    "roofline": kernel_roofline(s, c64)}
+        s.close()
+        s, dt = timed_steps(P, torch, W.CONFIGS["c2"], 5000, 256, mode=1)
+        variants["c2_real_time_complex128"] = {"updates_per_s": round(pts * 5000 / dt, 1),
+                                               "ms_per_step": round(dt / 5000 * 1e3, 6)}
+        s.close()
+        c3 = W.CONFIGS["c3"]
+        s, dt = timed_steps(P, torch, c3, 1000, 64)
+        p3 = c3["nx"] * c3["ny"] * c3["nz"]
+        variants["c3_3d_complex64"] = {"updates_per_s": round(p3 * 1000 / dt, 1),
+                                       "ms_per_step": round(dt / 1000 * 1e3, 6),
+                                       "roofline": kernel_roofline(s, c3, 100)}
+        s.close()
+        out["variants"] = variants
+        out["converge"] = converge_run(P, torch, W.CONFIGS["c1"])
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(W.CONFIGS["c2"], a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,166 @@
+/*
+ * sscn.h -- C ABI of the MI355X (gfx950) split-step Crank-Nicolson solver
+ * for the rotating Gross-Pitaevskii equation.
+ *
+ * Method: Kumar, Loncar, Muruganandam, Adhikari, Balaz, "C and Fortran
+ * OpenMP programs for rotating Bose-Einstein condensates" (arXiv:1906.06327),
+ * Sec. 2.  One time step is the Lie splitting H1 -> H2 -> H3 (-> z part in
+ * 3D) of Eqs. (eq1)-(eq3) and (split): the pointwise potential/nonlinear
+ * factor, then Crank-Nicolson line solves along x (Eqs. (eqD.9:kn1),
+ * (eqD.11), (eq5)), along y ("similarly", rotation coefficient y_j -> -x_i)
+ * and, in 3D, along z (no rotation term).  Imaginary time replaces Delta by
+ * -i Delta everywhere and renormalises after every step.
+ *
+ * Grid: each axis stores n points x_i = -n*h/2 + i*h, i = 0..n-1; index 0 is
+ * a Dirichlet wall (psi = 0) and the wall at i = n is implied.  The paper's
+ * (N+1)-point grid is this grid plus its always-zero last row.
+ *
+ * Data: psi is a caller-owned DEVICE buffer, contiguous, x fastest:
+ * psi[(k*ny + j)*nx + i].  Elements are interleaved (re, im) pairs of double
+ * (precision SSCN_C128, 16 bytes) or float (SSCN_C64, 8 bytes) -- the layout
+ * of torch.complex128 / torch.complex64.  The library borrows the buffer
+ * from sscn_init until sscn_destroy; it owns only a second state-sized work
+ * buffer and small reduction buffers.
+ *
+ * Streams: every call enqueues its work on the hipStream_t given to
+ * sscn_init (pass the caller's stream; NULL means the null stream).  Calls
+ * that return data to the host synchronise that stream.  A handle is not
+ * thread safe: use one handle per host thread.
+ *
+ * Errors: every int-returning call returns 0 on success or a negative
+ * SSCN_E* code; sscn_last_error() describes the most recent failure of the
+ * calling thread.  On error no state is modified unless stated.
+ */
+#ifndef SSCN_H
+#define SSCN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SSCN_OK = 0,
+    SSCN_EINVAL = -1,     /* bad sizes, non-positive steps, null pointers     */
+    SSCN_EOMEGA = -2,     /* Omega >= min(gamma, nu): no rotating ground state */
+    SSCN_EUNSTABLE = -3,  /* line systems not diagonally dominant (see init)  */
+    SSCN_ENONFINITE = -4, /* a NaN or Inf appeared in the state               */
+    SSCN_EHIP = -5,       /* a HIP runtime call failed                        */
+    SSCN_ENOMEM = -6      /* device allocation failed                         */
+};
+
+enum { SSCN_IMAG = 0, SSCN_REAL = 1 };      /* propagation mode              */
+enum { SSCN_C128 = 0, SSCN_C64 = 1 };       /* storage/arithmetic precision  */
+
+typedef struct sscn_params {
+    int dim;                  /* 2 or 3                                        */
+    int nx, ny, nz;           /* stored points per axis, each >= 3 (nz ignored
+                                 when dim == 2)                                */
+    double hx, hy, hz;        /* space steps, > 0                              */
+    double gamma, nu, lambda; /* trap anisotropies of Eq. (3d) / Eq. (2d)      */
+    double g;                 /* g_2D (dim 2) or g_3D (dim 3)                   */
+    double omega;             /* rotation frequency, |omega| < min(gamma, nu)  */
+    double dt;                /* time step Delta, > 0                          */
+    int mode;                 /* SSCN_IMAG or SSCN_REAL                        */
+    int precision;            /* SSCN_C128, or SSCN_C64 (complex64 sweeps with
+                                 FP64 reductions)                              */
+} sscn_params;
+
+/* Observables of the current state (paper Sec. 2: Eqs. (e2dr)/(e3dr) for mu
+ * and energy with alpha = 1 and 1/2, the kinetic term entering with +1/2;
+ * Eqs. (e2d)/(e3d) for the full functional; rms sizes sqrt(<x^2>) etc.).
+ * Integrals are h^d times plain sums; derivatives are forward differences
+ * in the kinetic terms and central differences in the rotation terms. */
+typedef struct sscn_obs {
+    double norm;          /* h^d sum |psi|^2                                  */
+    double mu, energy;    /* real-part form                                   */
+    double mu_full, energy_full; /* full functional, divided by the norm      */
+    double rms_x, rms_y, rms_z, rms_r;
+    double max_density;   /* max |psi|^2                                      */
+    int64_t step;         /* steps taken since sscn_init                      */
+    double sums[14];      /* the raw reductions (see sscn_observables)        */
+} sscn_obs;
+
+typedef struct sscn_handle sscn_handle;
+
+/* Create a solver on the current HIP device for the state buffer psi_dev
+ * (layout above, precision params->precision).  Validates the parameters:
+ * SSCN_EOMEGA when |omega| >= min(gamma, nu) (the rotating-frame energy is
+ * unbounded below, Sec. 2); SSCN_EUNSTABLE when a line system is not
+ * strictly diagonally dominant, which in real time means
+ * dt*|omega|*max|coordinate| / (2h) >= 1 on an axis.  psi is not touched;
+ * the caller fills it with sscn_init_state or sscn_set_state (or writes it
+ * directly and then calls sscn_set_state_device).  On success *out is set. */
+int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream,
+              sscn_handle **out);
+
+/* Initial state of Eq. (fun): kind 1 = one vortex (x + i y) at the centre,
+ * kind 0 = Gaussian ((x + i y) -> 1), width d_xy; in 3D times the z Gaussian
+ * of width d_z (d_z <= 0 selects 1/sqrt(lambda), the ansatz of Eq. (anz)).
+ * phase_host: NULL for no random phase, else ny*nx host doubles R(x, y)
+ * (row-major, x fastest) entering as exp(2 pi i R), constant along z.  Walls
+ * are zeroed and the state is normalised to 1.  Synchronises the stream. */
+int sscn_init_state(sscn_handle *h, int kind, const double *phase_host,
+                    double d_xy, double d_z);
+
+/* Enqueue nsteps >= 0 SSCN steps (paper's NPAS loop body).  Asynchronous:
+ * no host synchronisation.  In imaginary time the state left in psi after
+ * the call is normalised. */
+int sscn_step(sscn_handle *h, int64_t nsteps);
+
+/* Observables of the current state; synchronises the stream.  Returns
+ * SSCN_ENONFINITE (and still fills *out) when any reduction is NaN/Inf.
+ * sums[]: 0 |psi|^2, 1 psi_R^2, 2 kinetic(psi_R), 3 V psi_R^2,
+ * 4 g|psi|^2 psi_R^2, 5 rotation(psi_R, psi_I), 6 kinetic(psi), 7 V|psi|^2,
+ * 8 g|psi|^4, 9 Omega Im[psi^*(y d/dx - x d/dy)psi], 10-12 x^2,y^2,z^2
+ * |psi|^2 (all times h^d), 13 max |psi|^2. */
+int sscn_observables(sscn_handle *h, sscn_obs *out);
+
+/* Copy a host state (same layout and precision as psi) into psi, zeroing
+ * the walls (paper's NSTP = 0 restart).  Synchronises the stream. */
+int sscn_set_state(sscn_handle *h, const void *host_psi);
+
+/* Tell the handle psi was written by the caller on the device: zeroes the
+ * walls.  Asynchronous. */
+int sscn_set_state_device(sscn_handle *h);
+
+/* Copy psi to a host buffer of the same layout.  Synchronises the stream. */
+int sscn_get_state(sscn_handle *h, void *host_psi);
+
+/* Switch propagation mode (imaginary -> real hand-off of the paper's
+ * workflow) and/or precision.  A precision change converts the state into
+ * new_psi_dev (caller-owned, the new precision's layout), which the handle
+ * borrows from then on; pass NULL when the precision is unchanged.  New
+ * parameters are validated as in sscn_init; on error nothing changes. */
+int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev);
+
+/* Vortex count on the z = 0 plane (k = nz/2 in 3D; the only plane in 2D):
+ * plaquettes whose counter-clockwise sum of wrapped phase differences is
+ * 2 pi w, w > 0, counted w times, when the largest density within `box`
+ * points of the plaquette is >= density_frac * max density of the plane;
+ * plaquettes with a corner of exactly zero amplitude are skipped.  The
+ * paper counts by eye (Sec. 4).  Synchronises the stream. */
+int sscn_vortex_count(sscn_handle *h, double density_frac, int box, int *count);
+
+/* Advance nsteps >= 1 steps with a HIP event recorded on the handle's
+ * stream before and after every sweep kernel, and return in ms_out[0..3] the
+ * average duration (milliseconds) of the x-sweep (with the fused H1), the
+ * y-sweep, the z-sweep (0 in 2D) and of a whole step.  For measurement: it
+ * launches each kernel on its own, without graphs.  Synchronises the stream. */
+int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out);
+
+/* Window (rows of look-ahead) used by the truncated line solves per axis;
+ * 0 means the exact whole-line solve.  For diagnostics and tests. */
+int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz);
+
+void sscn_destroy(sscn_handle *h);
+
+const char *sscn_strerror(int code);
+const char *sscn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSCN_H */

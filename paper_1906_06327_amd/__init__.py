@@ -1,0 +1,213 @@
+"""Python binding of the MI355X SSCN library (libsscn.so, C ABI in include/sscn.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  PyTorch supplies the device memory (the state tensor) and the
+stream.  The binding refuses to run when the compiled library is missing; it
+has no fallback of any kind.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsscn.so")
+
+SSCN_IMAG, SSCN_REAL = 0, 1
+SSCN_C128, SSCN_C64 = 0, 1
+
+ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABLE",
+          -4: "SSCN_ENONFINITE", -5: "SSCN_EHIP", -6: "SSCN_ENOMEM"}
+
+# Every symbol include/sscn.h declares.
+EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
+           "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
+           "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_solver_info",
+           "sscn_destroy", "sscn_strerror", "sscn_last_error")
+
+
+class SSCNError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int), ("nx", ctypes.c_int), ("ny", ctypes.c_int),
+                ("nz", ctypes.c_int), ("hx", ctypes.c_double), ("hy", ctypes.c_double),
+                ("hz", ctypes.c_double), ("gamma", ctypes.c_double), ("nu", ctypes.c_double),
+                ("lam", ctypes.c_double), ("g", ctypes.c_double), ("omega", ctypes.c_double),
+                ("dt", ctypes.c_double), ("mode", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class Obs(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double), ("mu", ctypes.c_double), ("energy", ctypes.c_double),
+                ("mu_full", ctypes.c_double), ("energy_full", ctypes.c_double),
+                ("rms_x", ctypes.c_double), ("rms_y", ctypes.c_double), ("rms_z", ctypes.c_double),
+                ("rms_r", ctypes.c_double), ("max_density", ctypes.c_double),
+                ("step", ctypes.c_int64), ("sums", ctypes.c_double * 14)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libsscn.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "paper_1906_06327_amd/build.py (hipcc, gfx950)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        L.sscn_init.argtypes = [ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
+        L.sscn_init_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double]
+        L.sscn_step.argtypes = [vp, i64]
+        L.sscn_observables.argtypes = [vp, ctypes.POINTER(Obs)]
+        L.sscn_set_state.argtypes = [vp, vp]
+        L.sscn_set_state_device.argtypes = [vp]
+        L.sscn_get_state.argtypes = [vp, vp]
+        L.sscn_set_mode.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
+        L.sscn_vortex_count.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        L.sscn_solver_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.sscn_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+        L.sscn_destroy.argtypes = [vp]
+        L.sscn_destroy.restype = None
+        L.sscn_strerror.argtypes = [ctypes.c_int]
+        L.sscn_strerror.restype = ctypes.c_char_p
+        L.sscn_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if not hasattr(L, name):
+                raise RuntimeError(f"libsscn.so does not export {name}")
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != 0:
+        raise SSCNError(code, lib().sscn_last_error().decode())
+
+
+def make_params(dim=2, nx=64, ny=64, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu=1.0,
+                lam=1.0, g=0.0, omega=0.0, dt=1e-3, mode=0, precision=0, **_ignored):
+    return Params(int(dim), int(nx), int(ny), int(nz if dim == 3 else 1), float(hx), float(hy),
+                  float(hz), float(gamma), float(nu), float(lam), float(g), float(omega),
+                  float(dt), int(mode), int(precision))
+
+
+OBS_KEYS = ("norm", "mu", "energy", "mu_full", "energy_full", "rms_x", "rms_y", "rms_z",
+            "rms_r", "max_density")
+
+
+class Solver:
+    """One SSCN problem on the current GPU.
+
+    ``psi`` (a contiguous torch complex128/complex64 CUDA tensor of shape
+    (ny, nx) or (nz, ny, nx)) is allocated here unless given; the library
+    borrows it.  All work goes to ``stream`` (default: torch's current
+    stream)."""
+
+    def __init__(self, params, psi=None, stream=None):
+        import torch
+        self._torch = torch
+        p = params if isinstance(params, Params) else make_params(**params)
+        self.params = p
+        dtype = torch.complex128 if p.precision == SSCN_C128 else torch.complex64
+        shape = (p.nz, p.ny, p.nx) if p.dim == 3 else (p.ny, p.nx)
+        if psi is None:
+            psi = torch.zeros(shape, dtype=dtype, device="cuda")
+        if psi.dtype != dtype or tuple(psi.shape) != shape or not psi.is_contiguous() or not psi.is_cuda:
+            raise ValueError("psi must be a contiguous CUDA tensor of the grid shape and precision")
+        self.psi = psi
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().sscn_init(ctypes.byref(p), ctypes.c_void_p(psi.data_ptr()),
+                               ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def shape(self):
+        p = self.params
+        return (p.nz, p.ny, p.nx) if p.dim == 3 else (p.ny, p.nx)
+
+    def init_state(self, kind=1, phase=None, d_xy=1.0, d_z=0.0):
+        ph = None
+        if phase is not None:
+            ph = np.ascontiguousarray(phase, dtype=np.float64)
+            if ph.shape != (self.params.ny, self.params.nx):
+                raise ValueError("phase must have shape (ny, nx)")
+        _check(lib().sscn_init_state(self._h, int(kind), ph.ctypes.data if ph is not None else None,
+                                     float(d_xy), float(d_z)))
+
+    def step(self, n=1):
+        _check(lib().sscn_step(self._h, int(n)))
+
+    def observables(self, raise_nonfinite=True):
+        o = Obs()
+        code = lib().sscn_observables(self._h, ctypes.byref(o))
+        if code != 0 and (raise_nonfinite or code != -4):
+            _check(code)
+        d = {k: getattr(o, k) for k in OBS_KEYS}
+        d["step"] = int(o.step)
+        d["sums"] = np.array(list(o.sums))
+        return d
+
+    def set_state(self, host):
+        dtype = np.complex128 if self.params.precision == SSCN_C128 else np.complex64
+        a = np.ascontiguousarray(host, dtype=dtype)
+        if a.shape != self.shape:
+            raise ValueError(f"state shape {a.shape} != {self.shape}")
+        _check(lib().sscn_set_state(self._h, a.ctypes.data))
+
+    def set_state_device(self):
+        _check(lib().sscn_set_state_device(self._h))
+
+    def get_state(self):
+        dtype = np.complex128 if self.params.precision == SSCN_C128 else np.complex64
+        out = np.empty(self.shape, dtype=dtype)
+        _check(lib().sscn_get_state(self._h, out.ctypes.data))
+        return out
+
+    def set_mode(self, mode, precision=None):
+        torch = self._torch
+        if precision is None:
+            precision = self.params.precision
+        new = None
+        if precision != self.params.precision:
+            dtype = torch.complex128 if precision == SSCN_C128 else torch.complex64
+            new = torch.empty(self.shape, dtype=dtype, device=self.psi.device)
+        _check(lib().sscn_set_mode(self._h, int(mode), int(precision),
+                                   ctypes.c_void_p(new.data_ptr()) if new is not None else None))
+        self.params.mode = int(mode)
+        self.params.precision = int(precision)
+        if new is not None:
+            self.psi = new
+
+    def vortex_count(self, density_frac=0.05, box=3):
+        c = ctypes.c_int()
+        _check(lib().sscn_vortex_count(self._h, float(density_frac), int(box), ctypes.byref(c)))
+        return int(c.value)
+
+    def profile_step(self, n):
+        """Advance n steps, each kernel launched alone between HIP events;
+        returns average milliseconds of the x, y, z sweeps and of a step."""
+        ms = (ctypes.c_double * 4)()
+        _check(lib().sscn_profile_step(self._h, int(n), ms))
+        return {"x": ms[0], "y": ms[1], "z": ms[2], "step": ms[3]}
+
+    def solver_info(self):
+        w = (ctypes.c_int * 3)()
+        s = (ctypes.c_int * 3)()
+        _check(lib().sscn_solver_info(self._h, w, s))
+        return {"window": list(w), "segment": list(s)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sscn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

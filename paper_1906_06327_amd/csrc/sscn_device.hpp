@@ -1,0 +1,728 @@
+// Device code of the SSCN solver for gfx950 (CDNA4, wave64).
+//
+// One SSCN step (paper Sec. 2, Eqs. (eq1)-(eq3), (split)) is:
+//   H1:  psi <- exp(-i tau (V + g|s psi|^2)) s psi       (s: pending rescale)
+//   x :  Crank-Nicolson along x for every (j,k) line     (Eqs. (eqD.9:kn1),
+//   y :  along y, rotation coefficient y_j -> -x_i        (eqD.11), (eq5))
+//   z :  along z (3D), no rotation term
+// and, in imaginary time, the FP64 norm of the result, whose rescale s is
+// folded into the next step's H1.
+//
+// Each line solve uses the Cayley form of Crank-Nicolson: with
+// A = I + K, K = (i tau/2) H_line (tridiagonal: A0 = 1 + k0 on the diagonal,
+// A- below, A+ above) the paper's right-hand side is b = (2I - A) psi, so
+//   psi' = A^{-1} b = 2 A^{-1} psi - psi = psi + 2 delta,  (I + K) delta = -K psi.
+// Solving for the small correction delta keeps the rounding of the O(1)
+// diagonal (1 + k0 in the storage precision) out of the result: only small
+// quantities are rounded, which is what lets complex64 sweeps track the FP64
+// oracle.  Every line system is strictly diagonally
+// dominant, so the influence of a right-hand-side entry decays geometrically
+// with distance; a line is cut into segments of S outputs, each solved by
+// Thomas elimination over its own window of W extra rows on each side
+// (clipped at the walls, where the window start/end is exact).  W is chosen
+// on the host from a decay bound so that the truncation is below the
+// arithmetic's rounding; when that would need W > 32 the whole-line exact
+// kernels are used instead.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sscn {
+
+template <class R> struct Cx {
+    R re, im;
+};
+
+template <class R> __device__ __forceinline__ Cx<R> cx(R a, R b) { return Cx<R>{a, b}; }
+template <class R> __device__ __forceinline__ Cx<R> operator+(Cx<R> a, Cx<R> b) { return {a.re + b.re, a.im + b.im}; }
+template <class R> __device__ __forceinline__ Cx<R> operator-(Cx<R> a, Cx<R> b) { return {a.re - b.re, a.im - b.im}; }
+template <class R> __device__ __forceinline__ Cx<R> operator*(Cx<R> a, Cx<R> b)
+{
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+template <class R> __device__ __forceinline__ Cx<R> operator*(R s, Cx<R> a) { return {s * a.re, s * a.im}; }
+template <class R> __device__ __forceinline__ R norm2(Cx<R> a) { return a.re * a.re + a.im * a.im; }
+template <class R> __device__ __forceinline__ Cx<R> recip(Cx<R> a)
+{
+    R inv = R(1) / (a.re * a.re + a.im * a.im);
+    return {a.re * inv, -a.im * inv};
+}
+
+// storage vector type of one complex element
+template <class R> struct Vec;
+template <> struct Vec<double> { using T = double2; };
+template <> struct Vec<float> { using T = float2; };
+
+template <class R> __device__ __forceinline__ Cx<R> ld(const typename Vec<R>::T *p, int64_t i)
+{
+    typename Vec<R>::T v = p[i];
+    return {v.x, v.y};
+}
+template <class R> __device__ __forceinline__ void st(typename Vec<R>::T *p, int64_t i, Cx<R> a)
+{
+    typename Vec<R>::T v;
+    v.x = a.re;
+    v.y = a.im;
+    p[i] = v;
+}
+
+// Per-axis Crank-Nicolson coefficients (FP64, from the host):
+//   A0 = 1 + k0, k0 = i tau/(2h^2),  A+- = u +- q rot,  u = -i tau/(4h^2),
+//   q = tau/(4h); rot = Omega y_j (x-lines), -Omega x_i (y-lines), 0 (z).
+struct AxisCoef {
+    double a0r, a0i, k0r, k0i, ur, ui, qr, qi;
+};
+
+struct StepArgs {
+    int dim, nx, ny, nz;
+    double hx, hy, hz;
+    double x0, y0, z0;          // first stored coordinate, -n h / 2
+    double vx, vy, vz;          // 1/2 gamma^2, 1/2 nu^2, 1/2 lambda^2
+    double g, omega, dt, dV;
+    AxisCoef ax[3];
+};
+
+// Line coefficients for a line whose rotation coefficient is `rot`.
+template <class R> struct LineCoef {
+    Cx<R> A0, k0, Ap, Am;
+};
+
+template <class R>
+__device__ __forceinline__ LineCoef<R> line_coef(const AxisCoef &c, double rot)
+{
+    LineCoef<R> L;
+    L.A0 = {R(c.a0r), R(c.a0i)};
+    L.k0 = {R(c.k0r), R(c.k0i)};
+    L.Ap = {R(c.ur + c.qr * rot), R(c.ui + c.qi * rot)};
+    L.Am = {R(c.ur - c.qr * rot), R(c.ui - c.qi * rot)};
+    return L;
+}
+
+// -(K v)_u for the line operator K = A - I.
+template <class R>
+__device__ __forceinline__ Cx<R> minus_kv(const LineCoef<R> &L, Cx<R> vm, Cx<R> v0, Cx<R> vp)
+{
+    const Cx<R> t = L.k0 * v0 + L.Am * vm + L.Ap * vp;
+    return Cx<R>{-t.re, -t.im};
+}
+
+// Windowed Thomas solve of (I + K) delta = -K v for the S unknowns
+// s..s+S-1 of a line with unknowns 1..n-1 (values outside are zero), then
+// out = v + 2 delta.  `load(u)` returns v_u for 1 <= u <= n-1.  On return
+// io[r] holds the output of row s + r.
+template <class R, int S, int W, class Load>
+__device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Load load, Cx<R> (&io)[S])
+{
+    Cx<R> cps[S + W], dps[S + W];
+    Cx<R> cprev = {R(0), R(0)}, dprev = {R(0), R(0)};
+    const Cx<R> zero = {R(0), R(0)};
+    auto fetch = [&](int u) { return (u >= 1 && u <= n - 1) ? load(u) : zero; };
+    Cx<R> vm = fetch(s - W - 1), v0 = fetch(s - W);
+#pragma unroll
+    for (int r = 0; r < S + 2 * W; ++r) {
+        const int u = s - W + r;
+        const bool valid = (u >= 1) && (u <= n - 1);
+        const Cx<R> vp = fetch(u + 1);
+        if (r >= W && r < W + S)
+            io[r - W] = v0;
+        Cx<R> cp = zero, dp = zero;
+        if (valid) {
+            const Cx<R> rr = recip(L.A0 - L.Am * cprev);
+            cp = L.Ap * rr;
+            dp = (minus_kv(L, vm, v0, vp) - L.Am * dprev) * rr;
+        }
+        cprev = cp;
+        dprev = dp;
+        if (r >= W) {
+            cps[r - W] = cp;
+            dps[r - W] = dp;
+        }
+        vm = v0;
+        v0 = vp;
+    }
+    Cx<R> dnext = zero;
+#pragma unroll
+    for (int r = S + 2 * W - 1; r >= W; --r) {
+        const Cx<R> d = dps[r - W] - cps[r - W] * dnext;
+        if (r < W + S)
+            io[r - W] = io[r - W] + R(2) * d;
+        dnext = d;
+    }
+}
+
+// Deterministic block sum of one double over a 256-thread block; the result
+// is valid in thread 0.  Fixed butterfly order, no atomics.
+__device__ __forceinline__ double block_sum_256(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    __syncthreads();
+    if ((tid & 63) == 0)
+        red[tid >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0)
+        r = (red[0] + red[1]) + (red[2] + red[3]);
+    return r;
+}
+
+__device__ __forceinline__ double block_max_256(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v = fmax(v, __shfl_xor(v, off, 64));
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    __syncthreads();
+    if ((tid & 63) == 0)
+        red[tid >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0)
+        r = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    return r;
+}
+
+// Sum of npart FP64 partials by a 256-thread block, in a fixed order; every
+// block that calls this gets the same bits.  Result broadcast to all threads.
+__device__ __forceinline__ double block_sum_partials(const double *part, int npart, double *red)
+{
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    double v = 0.0;
+    for (int t = tid; t < npart; t += 256)
+        v += part[t];
+    double r = block_sum_256(v, red);
+    __syncthreads();
+    if (tid == 0)
+        red[4] = r;
+    __syncthreads();
+    r = red[4];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
+__device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
+
+// Pointwise H1 factor exp(-i tau w) applied as v + (exp(-i tau w) - 1) v, so
+// that only the small difference from 1 is rounded: real time (tau = dt)
+// exp(-i dt w) - 1 = -2 sin^2(dt w/2) - i sin(dt w); imaginary time
+// (tau = -i dt) expm1(-dt w).
+template <class R, bool RT>
+__device__ __forceinline__ Cx<R> h1_apply(Cx<R> v, R w, R dt)
+{
+    if constexpr (RT) {
+        R sn, cs, sh, ch;
+        sin_cos(dt * w, &sn, &cs);
+        sin_cos(R(0.5) * dt * w, &sh, &ch);
+        const Cx<R> f = {R(-2) * sh * sh, -sn};
+        return v + f * v;
+    } else {
+        return v + expm1(-dt * w) * v;
+    }
+}
+
+// psi <- s psi applied as psi + (s - 1) psi with s - 1 formed in FP64.
+template <class R>
+__device__ __forceinline__ Cx<R> rescale(Cx<R> v, R sm1)
+{
+    return v + sm1 * v;
+}
+
+// ---------------------------------------------------------------------------
+// x-sweep with the H1 sub-step and the pending rescale fused in front.
+// A block stages L whole x-lines in LDS (padded every S elements so that
+// consecutive threads, which own consecutive segments, hit distinct banks),
+// solves all (line, segment) pairs, and writes the lines back coalesced.
+// src may equal dst: a line is owned by exactly one block.
+template <class R, int S, int W, bool RT>
+__global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
+                                                StepArgs a, int L, const double *partials, int npart)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ double red[8];
+    Cx<R> *lin = reinterpret_cast<Cx<R> *>(smem_raw);
+    const int nx = a.nx, ny = a.ny;
+    const int LS = nx + nx / S + 1;
+    Cx<R> *lout = lin + (size_t)L * LS;
+    const int nlines = ny * (a.dim == 3 ? a.nz : 1);
+    const int nseg = (nx - 2) / S + 1;
+    const int line0 = blockIdx.x * L;
+    const int tid = threadIdx.x;
+
+    double sm1 = 0.0;
+    if (!RT && npart > 0) {
+        const double tot = block_sum_partials(partials, npart, red);
+        sm1 = 1.0 / sqrt(a.dV * tot) - 1.0;
+    }
+    const R sr = R(sm1);
+
+    for (int e = tid; e < L * nx; e += 256) {
+        const int l = e / nx, t = e - l * nx;
+        const int line = line0 + l;
+        Cx<R> v = {R(0), R(0)};
+        if (line < nlines && t > 0) {
+            const int j = line % ny, k = line / ny;
+            if (j > 0 && (a.dim == 2 || k > 0)) {
+                v = rescale(ld<R>(src, (int64_t)line * nx + t), sr);
+                const double x = a.x0 + t * a.hx, y = a.y0 + j * a.hy;
+                double V = a.vx * x * x + a.vy * y * y;
+                if (a.dim == 3) {
+                    const double z = a.z0 + k * a.hz;
+                    V += a.vz * z * z;
+                }
+                const R w = R(V) + R(a.g) * norm2(v);
+                v = h1_apply<R, RT>(v, w, R(a.dt));
+            }
+        }
+        lin[l * LS + t + t / S] = v;
+    }
+    __syncthreads();
+
+    for (int p = tid; p < L * nseg; p += 256) {
+        const int l = p / nseg, q = p - l * nseg;
+        const int line = line0 + l;
+        if (line >= nlines)
+            continue;
+        const int j = line % ny, k = line / ny;
+        if (j == 0 || (a.dim == 3 && k == 0))
+            continue;
+        const LineCoef<R> Lc = line_coef<R>(a.ax[0], a.omega * (a.y0 + j * a.hy));
+        const Cx<R> *row = lin + l * LS;
+        Cx<R> io[S];
+        const int s0 = 1 + q * S;
+        window_solve<R, S, W>(s0, nx, Lc, [&](int u) { return row[u + u / S]; }, io);
+        Cx<R> *orow = lout + l * LS;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            const int u = s0 + r;
+            if (u <= nx - 1)
+                orow[u + u / S] = io[r];
+        }
+    }
+    __syncthreads();
+
+    for (int e = tid; e < L * nx; e += 256) {
+        const int l = e / nx, t = e - l * nx;
+        const int line = line0 + l;
+        if (line < nlines && t > 0) {
+            const int j = line % ny, k = line / ny;
+            if (j > 0 && (a.dim == 2 || k > 0))
+                st<R>(dst, (int64_t)line * nx + t, lout[l * LS + t + t / S]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Strided sweeps (y: stride nx, z: stride nx*ny).  Thread = (line, segment);
+// the 64 lanes of a wave take 64 consecutive lines, so every row access of a
+// wave is one contiguous run.  src != dst (windows overlap).  With EMIT the
+// block writes the FP64 partial sum of |psi'|^2 of its outputs.
+template <class R, int S, int W, bool EMIT>
+__global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__restrict__ src,
+                                                typename Vec<R>::T *__restrict__ dst, StepArgs a,
+                                                double *partials)
+{
+    __shared__ double red[8];
+    const int nx = a.nx, ny = a.ny;
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    const int q = blockIdx.y * 4 + threadIdx.y;
+    const int k = blockIdx.z;
+    const int nseg = (ny - 2) / S + 1;
+    double acc = 0.0;
+    if (i > 0 && i < nx && q < nseg && (a.dim == 2 || k > 0)) {
+        const LineCoef<R> Lc = line_coef<R>(a.ax[1], -a.omega * (a.x0 + i * a.hx));
+        const int64_t base = (int64_t)k * nx * ny + i;
+        Cx<R> io[S];
+        const int s0 = 1 + q * S;
+        window_solve<R, S, W>(s0, ny, Lc, [&](int u) { return ld<R>(src, base + (int64_t)u * nx); }, io);
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            const int u = s0 + r;
+            if (u <= ny - 1) {
+                st<R>(dst, base + (int64_t)u * nx, io[r]);
+                if (EMIT)
+                    acc += (double)io[r].re * (double)io[r].re + (double)io[r].im * (double)io[r].im;
+            }
+        }
+    }
+    if (EMIT) {
+        const double b = block_sum_256(acc, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0)
+            partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = b;
+    }
+}
+
+template <class R, int S, int W, bool EMIT>
+__global__ __launch_bounds__(256) void k_zsweep(const typename Vec<R>::T *__restrict__ src,
+                                                typename Vec<R>::T *__restrict__ dst, StepArgs a,
+                                                double *partials)
+{
+    __shared__ double red[8];
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const int64_t plane = (int64_t)nx * ny;
+    const int pidx = blockIdx.x * 64 + threadIdx.x;
+    const int q = blockIdx.y * 4 + threadIdx.y;
+    const int nseg = (nz - 2) / S + 1;
+    double acc = 0.0;
+    const int i = pidx % nx, j = pidx / nx;
+    if (pidx < nx * ny && i > 0 && j > 0 && q < nseg) {
+        const LineCoef<R> Lc = line_coef<R>(a.ax[2], 0.0);
+        Cx<R> io[S];
+        const int s0 = 1 + q * S;
+        window_solve<R, S, W>(s0, nz, Lc, [&](int u) { return ld<R>(src, pidx + (int64_t)u * plane); }, io);
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            const int u = s0 + r;
+            if (u <= nz - 1) {
+                st<R>(dst, pidx + (int64_t)u * plane, io[r]);
+                if (EMIT)
+                    acc += (double)io[r].re * (double)io[r].re + (double)io[r].im * (double)io[r].im;
+            }
+        }
+    }
+    if (EMIT) {
+        const double b = block_sum_256(acc, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0)
+            partials[blockIdx.x + gridDim.x * blockIdx.y] = b;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Exact whole-line path (used when the decay bound would need W > 32).
+
+// Pointwise H1 with the pending rescale, src -> dst.
+template <class R, bool RT>
+__global__ __launch_bounds__(256) void k_h1(const typename Vec<R>::T *src, typename Vec<R>::T *dst, StepArgs a,
+                                            const double *partials, int npart)
+{
+    __shared__ double red[8];
+    double sm1 = 0.0;
+    if (!RT && npart > 0)
+        sm1 = 1.0 / sqrt(a.dV * block_sum_partials(partials, npart, red)) - 1.0;
+    const R sr = R(sm1);
+    const int64_t n = (int64_t)a.nx * a.ny * (a.dim == 3 ? a.nz : 1);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int i = (int)(p % a.nx);
+        const int64_t rest = p / a.nx;
+        const int j = (int)(rest % a.ny), k = (int)(rest / a.ny);
+        Cx<R> v = rescale(ld<R>(src, p), sr);
+        const double x = a.x0 + i * a.hx, y = a.y0 + j * a.hy;
+        double V = a.vx * x * x + a.vy * y * y;
+        if (a.dim == 3) {
+            const double z = a.z0 + k * a.hz;
+            V += a.vz * z * z;
+        }
+        const R w = R(V) + R(a.g) * norm2(v);
+        st<R>(dst, p, h1_apply<R, RT>(v, w, R(a.dt)));
+    }
+}
+
+// One thread per line; textbook Thomas over the whole line with the
+// elimination factors in a global workspace (2 complex per point).
+template <class R>
+__global__ __launch_bounds__(256) void k_line_exact(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
+                                                    StepArgs a, int axis, Cx<R> *ws)
+{
+    const int nx = a.nx, ny = a.ny, nz = (a.dim == 3 ? a.nz : 1);
+    int n, nlines;
+    if (axis == 0) { n = nx; nlines = ny * nz; }
+    else if (axis == 1) { n = ny; nlines = nx * nz; }
+    else { n = nz; nlines = nx * ny; }
+    const int line = blockIdx.x * 256 + threadIdx.x;
+    if (line >= nlines)
+        return;
+    int64_t base, stride;
+    double rot;
+    bool wall;
+    if (axis == 0) {
+        const int j = line % ny, k = line / ny;
+        base = ((int64_t)k * ny + j) * nx; stride = 1;
+        rot = a.omega * (a.y0 + j * a.hy);
+        wall = (j == 0) || (a.dim == 3 && k == 0);
+    } else if (axis == 1) {
+        const int i = line % nx, k = line / nx;
+        base = (int64_t)k * nx * ny + i; stride = nx;
+        rot = -a.omega * (a.x0 + i * a.hx);
+        wall = (i == 0) || (a.dim == 3 && k == 0);
+    } else {
+        const int i = line % nx, j = line / nx;
+        base = (int64_t)j * nx + i; stride = (int64_t)nx * ny;
+        rot = 0.0;
+        wall = (i == 0) || (j == 0);
+    }
+    if (wall)
+        return;
+    const LineCoef<R> Lc = line_coef<R>(a.ax[axis], rot);
+    Cx<R> *cpw = ws + (int64_t)line * 2 * n;
+    Cx<R> *dpw = cpw + n;
+    const Cx<R> zero = {R(0), R(0)};
+    Cx<R> cprev = zero, dprev = zero, vm = zero;
+    Cx<R> v0 = ld<R>(src, base + stride);
+    for (int u = 1; u <= n - 1; ++u) {
+        const Cx<R> vp = (u + 1 <= n - 1) ? ld<R>(src, base + (u + 1) * stride) : zero;
+        const Cx<R> rr = recip(Lc.A0 - Lc.Am * cprev);
+        cprev = Lc.Ap * rr;
+        dprev = (minus_kv(Lc, vm, v0, vp) - Lc.Am * dprev) * rr;
+        cpw[u] = cprev;
+        dpw[u] = dprev;
+        vm = v0;
+        v0 = vp;
+    }
+    Cx<R> dnext = zero;
+    for (int u = n - 1; u >= 1; --u) {
+        const Cx<R> d = dpw[u] - cpw[u] * dnext;
+        const Cx<R> v = ld<R>(src, base + u * stride);
+        st<R>(dst, base + u * stride, v + R(2) * d);
+        dnext = d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Reductions and small kernels.
+
+// FP64 partial sums of |psi|^2 over a grid-stride range (one per block).
+template <class R>
+__global__ __launch_bounds__(256) void k_norm_partials(const typename Vec<R>::T *psi, int64_t n, double *partials)
+{
+    __shared__ double red[8];
+    double acc = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const Cx<R> v = ld<R>(psi, p);
+        acc += (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    }
+    const double b = block_sum_256(acc, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = b;
+}
+
+// psi_dst = s psi_src with s = 1/sqrt(dV sum partials).
+template <class R>
+__global__ __launch_bounds__(256) void k_rescale(const typename Vec<R>::T *src, typename Vec<R>::T *dst, int64_t n,
+                                                 double dV, const double *partials, int npart)
+{
+    __shared__ double red[8];
+    const double sm1 = 1.0 / sqrt(dV * block_sum_partials(partials, npart, red)) - 1.0;
+    const R sr = R(sm1);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
+        st<R>(dst, p, rescale(ld<R>(src, p), sr));
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_copy(const typename Vec<R>::T *src, typename Vec<R>::T *dst, int64_t n)
+{
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
+        dst[p] = src[p];
+}
+
+// Precision conversion between the two storage layouts.
+template <class RS, class RD>
+__global__ __launch_bounds__(256) void k_convert(const typename Vec<RS>::T *src, typename Vec<RD>::T *dst, int64_t n)
+{
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const Cx<RS> v = ld<RS>(src, p);
+        st<RD>(dst, p, Cx<RD>{RD(v.re), RD(v.im)});
+    }
+}
+
+// Zero every wall point (index 0 on any axis).
+template <class R>
+__global__ __launch_bounds__(256) void k_zero_walls(typename Vec<R>::T *psi, StepArgs a)
+{
+    const int64_t n = (int64_t)a.nx * a.ny * (a.dim == 3 ? a.nz : 1);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int i = (int)(p % a.nx);
+        const int64_t rest = p / a.nx;
+        const int j = (int)(rest % a.ny), k = (int)(rest / a.ny);
+        if (i == 0 || j == 0 || (a.dim == 3 && k == 0))
+            st<R>(psi, p, Cx<R>{R(0), R(0)});
+    }
+}
+
+// Initial state of Eq. (fun) (not normalised; the host normalises after).
+template <class R>
+__global__ __launch_bounds__(256) void k_init(typename Vec<R>::T *psi, StepArgs a, int kind, const double *phase,
+                                              double dxy, double dz)
+{
+    const double pi = 3.14159265358979323846;
+    const int64_t n = (int64_t)a.nx * a.ny * (a.dim == 3 ? a.nz : 1);
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int i = (int)(p % a.nx);
+        const int64_t rest = p / a.nx;
+        const int j = (int)(rest % a.ny), k = (int)(rest / a.ny);
+        double re = 0.0, im = 0.0;
+        if (i > 0 && j > 0 && (a.dim == 2 || k > 0)) {
+            const double x = a.x0 + i * a.hx, y = a.y0 + j * a.hy;
+            double fr = 1.0, fi = 0.0;
+            if (kind == 1) { fr = x; fi = y; }
+            const double amp = exp(-(x * x + y * y) / (2.0 * dxy * dxy)) / sqrt(pi * dxy * dxy);
+            re = fr * amp;
+            im = fi * amp;
+            if (phase) {
+                double sn, cs;
+                sincos(2.0 * pi * phase[(int64_t)j * a.nx + i], &sn, &cs);
+                const double r2 = re * cs - im * sn, i2 = re * sn + im * cs;
+                re = r2;
+                im = i2;
+            }
+            if (a.dim == 3) {
+                const double z = a.z0 + k * a.hz;
+                const double fz = pow(pi * dz * dz, -0.25) * exp(-z * z / (2.0 * dz * dz));
+                re *= fz;
+                im *= fz;
+            }
+        }
+        st<R>(psi, p, Cx<R>{R(re), R(im)});
+    }
+}
+
+// Observables: 13 FP64 sums + max density per block (see sscn_obs.sums).
+template <class R>
+__device__ __forceinline__ Cx<double> at(const typename Vec<R>::T *psi, const StepArgs &a, int i, int j, int k)
+{
+    const int nz = a.dim == 3 ? a.nz : 1;
+    if (i < 0 || j < 0 || k < 0 || i >= a.nx || j >= a.ny || k >= nz)
+        return Cx<double>{0.0, 0.0};
+    const Cx<R> v = ld<R>(psi, ((int64_t)k * a.ny + j) * a.nx + i);
+    return Cx<double>{(double)v.re, (double)v.im};
+}
+
+template <class R>
+__global__ __launch_bounds__(256) void k_observables(const typename Vec<R>::T *psi, StepArgs a, double *partials)
+{
+    __shared__ double red[8];
+    const int64_t n = (int64_t)a.nx * a.ny * (a.dim == 3 ? a.nz : 1);
+    double s[14];
+#pragma unroll
+    for (int t = 0; t < 14; ++t)
+        s[t] = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int i = (int)(p % a.nx);
+        const int64_t rest = p / a.nx;
+        const int j = (int)(rest % a.ny), k = (int)(rest / a.ny);
+        const double x = a.x0 + i * a.hx, y = a.y0 + j * a.hy;
+        const double z = a.dim == 3 ? a.z0 + k * a.hz : 0.0;
+        const Cx<double> v = at<R>(psi, a, i, j, k);
+        const double dens = v.re * v.re + v.im * v.im;
+        double V = a.vx * x * x + a.vy * y * y;
+        if (a.dim == 3)
+            V += a.vz * z * z;
+        const Cx<double> xp = at<R>(psi, a, i + 1, j, k), xm = at<R>(psi, a, i - 1, j, k);
+        const Cx<double> yp = at<R>(psi, a, i, j + 1, k), ym = at<R>(psi, a, i, j - 1, k);
+        const Cx<double> fx = (1.0 / a.hx) * (xp - v), fy = (1.0 / a.hy) * (yp - v);
+        Cx<double> fz = {0.0, 0.0};
+        if (a.dim == 3)
+            fz = (1.0 / a.hz) * (at<R>(psi, a, i, j, k + 1) - v);
+        const double kin_r = fx.re * fx.re + fy.re * fy.re + fz.re * fz.re;
+        const double kin = norm2(fx) + norm2(fy) + norm2(fz);
+        const Cx<double> cxd = (1.0 / (2.0 * a.hx)) * (xp - xm), cyd = (1.0 / (2.0 * a.hy)) * (yp - ym);
+        const Cx<double> lz = y * cxd - x * cyd;  // (y d/dx - x d/dy) psi
+        s[0] += dens;
+        s[1] += v.re * v.re;
+        s[2] += 0.5 * kin_r;
+        s[3] += V * v.re * v.re;
+        s[4] += a.g * dens * v.re * v.re;
+        s[5] += a.omega * v.re * lz.im;
+        s[6] += 0.5 * kin;
+        s[7] += V * dens;
+        s[8] += a.g * dens * dens;
+        s[9] += a.omega * (v.re * lz.im - v.im * lz.re);  // Im(conj(v) lz)
+        s[10] += x * x * dens;
+        s[11] += y * y * dens;
+        s[12] += z * z * dens;
+        s[13] = fmax(s[13], dens);
+    }
+#pragma unroll
+    for (int t = 0; t < 13; ++t) {
+        const double b = block_sum_256(s[t], red);
+        if (threadIdx.x == 0)
+            partials[(int64_t)blockIdx.x * 14 + t] = b;
+    }
+    const double m = block_max_256(s[13], red);
+    if (threadIdx.x == 0)
+        partials[(int64_t)blockIdx.x * 14 + 13] = m;
+}
+
+// Fixed-order final reduction of nblk rows of nval partials: values with
+// maxmask bit set take the max, the others the sum.  One 256-thread block.
+__global__ __launch_bounds__(256) void k_reduce_final(const double *partials, int nblk, int nval, unsigned maxmask,
+                                                      double *out)
+{
+    __shared__ double red[8];
+    for (int v = 0; v < nval; ++v) {
+        const bool mx = (maxmask >> v) & 1u;
+        double acc = 0.0;
+        for (int b = threadIdx.x; b < nblk; b += 256) {
+            const double x = partials[(int64_t)b * nval + v];
+            acc = mx ? fmax(acc, x) : acc + x;
+        }
+        const double r = mx ? block_max_256(acc, red) : block_sum_256(acc, red);
+        if (threadIdx.x == 0)
+            out[v] = r;
+        __syncthreads();
+    }
+}
+
+// Max density over the plane k0 (one partial per block).
+template <class R>
+__global__ __launch_bounds__(256) void k_plane_max(const typename Vec<R>::T *psi, StepArgs a, int k0, double *partials)
+{
+    __shared__ double red[8];
+    const int64_t n = (int64_t)a.nx * a.ny;
+    double m = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const Cx<R> v = ld<R>(psi, (int64_t)k0 * n + p);
+        const double re = v.re, im = v.im;
+        m = fmax(m, __dadd_rn(__dmul_rn(re, re), __dmul_rn(im, im)));
+    }
+    const double b = block_max_256(m, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = b;
+}
+
+// Vortex count on plane k0: per plaquette winding of the wrapped phase
+// differences, masked by the largest density within `box` points.
+template <class R>
+__global__ __launch_bounds__(256) void k_vortex(const typename Vec<R>::T *psi, StepArgs a, int k0, double frac,
+                                                int box, const double *dmax, double *partials)
+{
+    __shared__ double red[8];
+    const double two_pi = 6.283185307179586476925286766559;
+    const int nx = a.nx, ny = a.ny;
+    const int64_t n = (int64_t)(nx - 1) * (ny - 1);
+    const double thr = frac * dmax[0];
+    double cnt = 0.0;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int i = (int)(p % (nx - 1)), j = (int)(p / (nx - 1));
+        const Cx<double> c00 = at<R>(psi, a, i, j, k0), c10 = at<R>(psi, a, i + 1, j, k0);
+        const Cx<double> c11 = at<R>(psi, a, i + 1, j + 1, k0), c01 = at<R>(psi, a, i, j + 1, k0);
+        auto zero = [](Cx<double> c) { return c.re == 0.0 && c.im == 0.0; };
+        if (zero(c00) || zero(c10) || zero(c11) || zero(c01))
+            continue;
+        // arg(b conj(a)) with the products rounded as written (no contraction)
+        auto darg = [](Cx<double> b, Cx<double> c) {
+            const double re = __dadd_rn(__dmul_rn(b.re, c.re), __dmul_rn(b.im, c.im));
+            const double im = __dsub_rn(__dmul_rn(b.im, c.re), __dmul_rn(b.re, c.im));
+            return atan2(im, re);
+        };
+        const double sum = darg(c10, c00) + darg(c11, c10) + darg(c01, c11) + darg(c00, c01);
+        const int w = (int)llround(sum / two_pi);
+        if (w <= 0)
+            continue;
+        double local = 0.0;
+        for (int jj = j - box; jj <= j + 1 + box; ++jj)
+            for (int ii = i - box; ii <= i + 1 + box; ++ii) {
+                const Cx<double> v = at<R>(psi, a, ii, jj, k0);
+                local = fmax(local, __dadd_rn(__dmul_rn(v.re, v.re), __dmul_rn(v.im, v.im)));
+            }
+        if (local >= thr)
+            cnt += w;
+    }
+    const double b = block_sum_256(cnt, red);
+    if (threadIdx.x == 0)
+        partials[blockIdx.x] = b;
+}
+
+}  // namespace sscn

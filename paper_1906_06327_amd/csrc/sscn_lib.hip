@@ -1,0 +1,832 @@
+// Host side of the SSCN C ABI (include/sscn.h): parameter validation, the
+// per-axis Crank-Nicolson coefficients, window selection, kernel dispatch,
+// step sequencing with HIP graphs, observables and vortex counting.
+#include "sscn.h"
+#include "sscn_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace sscn;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIPCHECK(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(SSCN_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)
+
+constexpr int kSeg = 8;             // outputs per thread segment (all axes)
+constexpr int kGraphSteps = 64;     // steps per captured graph
+constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
+constexpr size_t kXLdsCap = 64 * 1024;
+
+// Supported window sizes (template instantiations).
+const int kWindows[] = {4, 8, 12, 16, 24, 32};
+
+}  // namespace
+
+struct sscn_handle {
+    sscn_params p;
+    void *psi = nullptr;    // caller-owned state
+    void *work = nullptr;   // second state-sized buffer (strided sweeps)
+    void *ws = nullptr;     // exact-path workspace
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int64_t npts = 0;
+    size_t esize = 0;
+    StepArgs args{};
+    int W[3] = {0, 0, 0};   // window per axis; 0 = exact whole-line path
+    bool exact = false;
+    int xL = 1;             // lines per block of the x-sweep
+    size_t xlds = 0;
+    int nemit = 0;          // partials written by the last sweep
+    double *partials = nullptr;  // norm partials between steps
+    double *obs_part = nullptr;  // observables / vortex partials
+    double *obs_buf = nullptr;   // finished reductions (device)
+    double *phase = nullptr;
+    bool pending = false;   // partials hold the norm of an unnormalised state
+    int64_t steps = 0;
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+namespace {
+
+int64_t npoints(const sscn_params &p)
+{
+    return (int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
+}
+
+// Bound on the truncation error of a windowed line solve (relative to the
+// largest |rhs| on the line) for a strictly diagonally dominant tridiagonal
+// Toeplitz system with |A-| <= ab, |A0| = bb, |A+| <= cb:
+//  - Thomas factors satisfy |c'_k| <= mu = cb / (bb - ab);
+//  - the forward sweep damps by lam = ab / (bb - ab mu) per row;
+//  - the exact solution just outside a window is at most 1/(bb - ab - cb)
+//    times max|rhs| (Varah's bound), and enters the window through one
+//    off-diagonal coefficient at each end;
+//  - so at W rows from both window ends the error of y is at most
+//    yb kappa (ab lam^W / (1 - mu lam) + cb mu^W), kappa = 1/(bb - ab mu),
+//    and the Cayley output 2y - v doubles it.
+// Returns the smallest W meeting tol, or -1 if not diagonally dominant.
+int window_rows(double ab, double bb, double cb, double tol)
+{
+    if (!(ab + cb < bb))
+        return -1;
+    const double mu = cb / (bb - ab);
+    const double lam = ab / (bb - ab * mu);
+    const double kappa = 1.0 / (bb - ab * mu);
+    const double yb = 1.0 / (bb - ab - cb);
+    for (int w = 0; w <= 4096; ++w) {
+        const double err = 2.0 * yb * kappa * (ab * std::pow(lam, w) / (1.0 - mu * lam) + cb * std::pow(mu, w));
+        if (err <= tol)
+            return w;
+    }
+    return 4097;
+}
+
+int validate(const sscn_params &p)
+{
+    if (p.dim != 2 && p.dim != 3)
+        return fail(SSCN_EINVAL, "dim must be 2 or 3");
+    if (p.nx < 3 || p.ny < 3 || (p.dim == 3 && p.nz < 3))
+        return fail(SSCN_EINVAL, "every axis needs at least 3 stored points");
+    if ((int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1) > ((int64_t)1 << 40))
+        return fail(SSCN_EINVAL, "grid too large");
+    if (!(p.hx > 0) || !(p.hy > 0) || (p.dim == 3 && !(p.hz > 0)) || !(p.dt > 0))
+        return fail(SSCN_EINVAL, "space and time steps must be positive");
+    if (p.mode != SSCN_IMAG && p.mode != SSCN_REAL)
+        return fail(SSCN_EINVAL, "mode must be SSCN_IMAG or SSCN_REAL");
+    if (p.precision != SSCN_C128 && p.precision != SSCN_C64)
+        return fail(SSCN_EINVAL, "precision must be SSCN_C128 or SSCN_C64");
+    if (!std::isfinite(p.g) || !std::isfinite(p.omega) || !std::isfinite(p.gamma) || !std::isfinite(p.nu) ||
+        (p.dim == 3 && !std::isfinite(p.lambda)))
+        return fail(SSCN_EINVAL, "non-finite physical parameter");
+    if (!(std::fabs(p.omega) < std::min(p.gamma, p.nu)))
+        return fail(SSCN_EOMEGA, "|omega| must be below min(gamma, nu)");
+    return 0;
+}
+
+// Crank-Nicolson coefficients of one axis and its window size.
+int axis_setup(const sscn_params &p, int axis, AxisCoef &c, int &W)
+{
+    using cd = std::complex<double>;
+    const cd I(0.0, 1.0);
+    const cd tau = p.mode == SSCN_REAL ? cd(p.dt, 0.0) : cd(0.0, -p.dt);
+    const double h = axis == 0 ? p.hx : axis == 1 ? p.hy : p.hz;
+    const int n = axis == 0 ? p.nx : axis == 1 ? p.ny : p.nz;
+    const cd k0 = I * tau / (2.0 * h * h);
+    const cd A0 = 1.0 + k0;
+    const cd u = -I * tau / (4.0 * h * h);
+    const cd q = tau / (4.0 * h);
+    c = AxisCoef{A0.real(), A0.imag(), k0.real(), k0.imag(), u.real(), u.imag(), q.real(), q.imag()};
+    // the largest rotation coefficient on this axis's lines
+    double rmax = 0.0;
+    if (axis == 0)
+        rmax = std::fabs(p.omega) * 0.5 * p.ny * p.hy;
+    else if (axis == 1)
+        rmax = std::fabs(p.omega) * 0.5 * p.nx * p.hx;
+    const double amax = std::max(std::abs(u + q * rmax), std::abs(u - q * rmax));
+    const double tol = p.precision == SSCN_C128 ? std::ldexp(1.0, -56) : std::ldexp(1.0, -27);
+    const int w = window_rows(amax, std::abs(A0), amax, tol);
+    if (w < 0)
+        return fail(SSCN_EUNSTABLE, "line system of axis " + std::to_string(axis) +
+                                        " is not strictly diagonally dominant (dt*|omega|*max|coord|/(2h) too large)");
+    W = 0;
+    for (int cand : kWindows)
+        if (cand >= w) {
+            W = cand;
+            break;
+        }
+    (void)n;
+    return 0;
+}
+
+int setup(sscn_handle *h)
+{
+    const sscn_params &p = h->p;
+    StepArgs &a = h->args;
+    a.dim = p.dim;
+    a.nx = p.nx;
+    a.ny = p.ny;
+    a.nz = p.dim == 3 ? p.nz : 1;
+    a.hx = p.hx;
+    a.hy = p.hy;
+    a.hz = p.dim == 3 ? p.hz : 1.0;
+    a.x0 = -0.5 * p.nx * p.hx;
+    a.y0 = -0.5 * p.ny * p.hy;
+    a.z0 = p.dim == 3 ? -0.5 * p.nz * p.hz : 0.0;
+    a.vx = 0.5 * p.gamma * p.gamma;
+    a.vy = 0.5 * p.nu * p.nu;
+    a.vz = p.dim == 3 ? 0.5 * p.lambda * p.lambda : 0.0;
+    a.g = p.g;
+    a.omega = p.omega;
+    a.dt = p.dt;
+    a.dV = p.hx * p.hy * (p.dim == 3 ? p.hz : 1.0);
+    h->exact = false;
+    for (int ax = 0; ax < p.dim; ++ax) {
+        int r = axis_setup(p, ax, a.ax[ax], h->W[ax]);
+        if (r)
+            return r;
+        if (h->W[ax] == 0)
+            h->exact = true;
+    }
+    if (p.dim == 2)
+        a.ax[2] = a.ax[1], h->W[2] = 0;
+    h->npts = npoints(p);
+    h->esize = p.precision == SSCN_C128 ? 16 : 8;
+    // x-sweep staging: L lines per block so that L * segments ~ 256 threads
+    const int nseg = (p.nx - 2) / kSeg + 1;
+    const size_t LS = (size_t)p.nx + p.nx / kSeg + 1;
+    int L = std::max(1, 256 / nseg);
+    while (L > 1 && 2 * L * LS * h->esize > kXLdsCap)
+        --L;
+    h->xL = L;
+    h->xlds = 2 * L * LS * h->esize;
+    if (h->xlds > kXLdsCap)
+        h->exact = true;  // lines too long to stage; whole-line path
+    // partials written by the last sweep
+    if (p.dim == 2)
+        h->nemit = ((p.nx + 63) / 64) * (((p.ny - 2) / kSeg + 1 + 3) / 4);
+    else
+        h->nemit = (int)(((int64_t)p.nx * p.ny + 63) / 64) * (((p.nz - 2) / kSeg + 1 + 3) / 4);
+    if (h->exact) {
+        h->W[0] = h->W[1] = h->W[2] = 0;
+        h->nemit = kRedBlocks;
+    }
+    return 0;
+}
+
+int red_blocks(int64_t n) { return (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 255) / 256)); }
+
+// ---------------------------------------------------------------------------
+// Kernel dispatch.
+
+template <class R> using V = typename Vec<R>::T;
+
+template <class R, int W, bool RT>
+void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st)
+{
+    const int nlines = h->p.ny * (h->p.dim == 3 ? h->p.nz : 1);
+    const int blocks = (nlines + h->xL - 1) / h->xL;
+    hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
+                       (V<R> *)dst, h->args, h->xL, h->partials, npart);
+}
+
+template <class R, bool RT>
+void launch_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st)
+{
+    switch (h->W[0]) {
+    case 4: go_x<R, 4, RT>(h, src, dst, npart, st); break;
+    case 8: go_x<R, 8, RT>(h, src, dst, npart, st); break;
+    case 12: go_x<R, 12, RT>(h, src, dst, npart, st); break;
+    case 16: go_x<R, 16, RT>(h, src, dst, npart, st); break;
+    case 24: go_x<R, 24, RT>(h, src, dst, npart, st); break;
+    default: go_x<R, 32, RT>(h, src, dst, npart, st); break;
+    }
+}
+
+template <class R, int W, bool EMIT>
+void go_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+    const sscn_params &p = h->p;
+    const int nseg = (p.ny - 2) / kSeg + 1;
+    dim3 grid((p.nx + 63) / 64, (nseg + 3) / 4, p.dim == 3 ? p.nz : 1);
+    hipLaunchKernelGGL((k_ysweep<R, kSeg, W, EMIT>), grid, dim3(64, 4), 0, st, (const V<R> *)src, (V<R> *)dst,
+                       h->args, h->partials);
+}
+
+template <class R, bool EMIT>
+void launch_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+    switch (h->W[1]) {
+    case 4: go_y<R, 4, EMIT>(h, src, dst, st); break;
+    case 8: go_y<R, 8, EMIT>(h, src, dst, st); break;
+    case 12: go_y<R, 12, EMIT>(h, src, dst, st); break;
+    case 16: go_y<R, 16, EMIT>(h, src, dst, st); break;
+    case 24: go_y<R, 24, EMIT>(h, src, dst, st); break;
+    default: go_y<R, 32, EMIT>(h, src, dst, st); break;
+    }
+}
+
+template <class R, int W, bool EMIT>
+void go_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+    const sscn_params &p = h->p;
+    const int nseg = (p.nz - 2) / kSeg + 1;
+    dim3 grid((unsigned)(((int64_t)p.nx * p.ny + 63) / 64), (nseg + 3) / 4, 1);
+    hipLaunchKernelGGL((k_zsweep<R, kSeg, W, EMIT>), grid, dim3(64, 4), 0, st, (const V<R> *)src, (V<R> *)dst,
+                       h->args, h->partials);
+}
+
+template <class R, bool EMIT>
+void launch_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+    switch (h->W[2]) {
+    case 4: go_z<R, 4, EMIT>(h, src, dst, st); break;
+    case 8: go_z<R, 8, EMIT>(h, src, dst, st); break;
+    case 12: go_z<R, 12, EMIT>(h, src, dst, st); break;
+    case 16: go_z<R, 16, EMIT>(h, src, dst, st); break;
+    case 24: go_z<R, 24, EMIT>(h, src, dst, st); break;
+    default: go_z<R, 32, EMIT>(h, src, dst, st); break;
+    }
+}
+
+template <class R>
+void launch_rescale(sscn_handle *h, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_rescale<R>), dim3(red_blocks(h->npts)), dim3(256), 0, st, (const V<R> *)h->psi,
+                       (V<R> *)h->psi, h->npts, h->args.dV, h->partials, h->nemit);
+}
+
+template <class R>
+void launch_norm(sscn_handle *h, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_norm_partials<R>), dim3(kRedBlocks), dim3(256), 0, st, (const V<R> *)h->psi, h->npts,
+                       h->partials);
+}
+
+// One SSCN step on stream st.  npart > 0: the partials hold the norm of the
+// (unnormalised) state and the rescale is folded into H1.  ev (optional, 4
+// events) is recorded before the x-, y-, z-sweeps and after the step.
+template <class R>
+void enqueue_one(sscn_handle *h, int npart, hipStream_t st, hipEvent_t *ev = nullptr)
+{
+    auto mark = [&](int t) {
+        if (ev)
+            (void)hipEventRecord(ev[t], st);
+    };
+    const bool imag = h->p.mode == SSCN_IMAG;
+    void *A = h->psi, *B = h->work;
+    mark(0);
+    if (h->exact) {
+        const int nb = red_blocks(h->npts);
+        if (imag)
+            hipLaunchKernelGGL((k_h1<R, false>), dim3(nb), dim3(256), 0, st, (const V<R> *)A, (V<R> *)A, h->args,
+                               h->partials, npart);
+        else
+            hipLaunchKernelGGL((k_h1<R, true>), dim3(nb), dim3(256), 0, st, (const V<R> *)A, (V<R> *)A, h->args,
+                               h->partials, 0);
+        const sscn_params &p = h->p;
+        const int nz = p.dim == 3 ? p.nz : 1;
+        auto line = [&](int axis, void *s, void *d) {
+            const int nl = axis == 0 ? p.ny * nz : axis == 1 ? p.nx * nz : p.nx * p.ny;
+            hipLaunchKernelGGL((k_line_exact<R>), dim3((nl + 255) / 256), dim3(256), 0, st, (const V<R> *)s,
+                               (V<R> *)d, h->args, axis, (Cx<R> *)h->ws);
+        };
+        line(0, A, B);
+        mark(1);
+        line(1, B, A);
+        mark(2);
+        if (p.dim == 3) {
+            line(2, A, B);
+            hipLaunchKernelGGL((k_copy<R>), dim3(nb), dim3(256), 0, st, (const V<R> *)B, (V<R> *)A, h->npts);
+        }
+        if (imag)
+            launch_norm<R>(h, st);
+        mark(3);
+        return;
+    }
+    if (h->p.dim == 2) {
+        if (imag) {
+            launch_x<R, false>(h, A, B, npart, st);
+            mark(1);
+            launch_y<R, true>(h, B, A, st);
+        } else {
+            launch_x<R, true>(h, A, B, 0, st);
+            mark(1);
+            launch_y<R, false>(h, B, A, st);
+        }
+        mark(2);
+    } else {
+        if (imag) {
+            launch_x<R, false>(h, A, A, npart, st);
+            mark(1);
+            launch_y<R, false>(h, A, B, st);
+            mark(2);
+            launch_z<R, true>(h, B, A, st);
+        } else {
+            launch_x<R, true>(h, A, A, 0, st);
+            mark(1);
+            launch_y<R, false>(h, A, B, st);
+            mark(2);
+            launch_z<R, false>(h, B, A, st);
+        }
+    }
+    mark(3);
+}
+
+// n steps launched one by one, ending with a normalised state in imaginary
+// time.
+template <class R>
+void enqueue_direct(sscn_handle *h, int64_t n, hipStream_t st)
+{
+    const bool imag = h->p.mode == SSCN_IMAG;
+    for (int64_t s = 0; s < n; ++s) {
+        enqueue_one<R>(h, (imag && h->pending) ? h->nemit : 0, st);
+        if (imag)
+            h->pending = true;
+    }
+    if (imag && h->pending) {
+        launch_rescale<R>(h, st);
+        h->pending = false;
+    }
+}
+
+int build_graph(sscn_handle *h)
+{
+    if (h->gexec)
+        return 0;
+    HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
+    const bool was = h->pending;
+    h->pending = false;
+    if (h->p.precision == SSCN_C128)
+        enqueue_direct<double>(h, kGraphSteps, h->cap);
+    else
+        enqueue_direct<float>(h, kGraphSteps, h->cap);
+    h->pending = was;
+    hipError_t e = hipStreamEndCapture(h->cap, &h->graph);
+    if (e != hipSuccess)
+        return fail(SSCN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(h->graph);
+        h->graph = nullptr;
+        h->gexec = nullptr;
+        return fail(SSCN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    return 0;
+}
+
+void drop_graph(sscn_handle *h)
+{
+    if (h->gexec)
+        (void)hipGraphExecDestroy(h->gexec);
+    if (h->graph)
+        (void)hipGraphDestroy(h->graph);
+    h->gexec = nullptr;
+    h->graph = nullptr;
+}
+
+int alloc_buffers(sscn_handle *h)
+{
+    const size_t bytes = (size_t)h->npts * h->esize;
+    if (hipMalloc(&h->work, bytes) != hipSuccess)
+        return fail(SSCN_ENOMEM, "hipMalloc of the work buffer failed");
+    HIPCHECK(hipMemsetAsync(h->work, 0, bytes, h->stream));
+    if (h->exact) {
+        const sscn_params &p = h->p;
+        const int nz = p.dim == 3 ? p.nz : 1;
+        const int64_t lines_pts = std::max({(int64_t)p.ny * nz * p.nx, (int64_t)p.nx * nz * p.ny,
+                                            (int64_t)p.nx * p.ny * nz});
+        if (hipMalloc(&h->ws, (size_t)lines_pts * 2 * h->esize) != hipSuccess)
+            return fail(SSCN_ENOMEM, "hipMalloc of the exact-path workspace failed");
+    }
+    return 0;
+}
+
+void free_buffers(sscn_handle *h)
+{
+    if (h->work)
+        (void)hipFree(h->work);
+    if (h->ws)
+        (void)hipFree(h->ws);
+    h->work = nullptr;
+    h->ws = nullptr;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI.
+
+extern "C" {
+
+const char *sscn_last_error(void) { return g_err.c_str(); }
+
+const char *sscn_strerror(int code)
+{
+    switch (code) {
+    case SSCN_OK: return "ok";
+    case SSCN_EINVAL: return "invalid argument";
+    case SSCN_EOMEGA: return "omega >= min(gamma, nu)";
+    case SSCN_EUNSTABLE: return "line systems not diagonally dominant";
+    case SSCN_ENONFINITE: return "non-finite value in the state";
+    case SSCN_EHIP: return "HIP runtime error";
+    case SSCN_ENOMEM: return "device allocation failed";
+    default: return "unknown error";
+    }
+}
+
+int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_handle **out)
+{
+    if (!params || !psi_dev || !out)
+        return fail(SSCN_EINVAL, "null argument");
+    *out = nullptr;
+    int r = validate(*params);
+    if (r)
+        return r;
+    sscn_handle *h = new sscn_handle();
+    h->p = *params;
+    if (h->p.dim == 2)
+        h->p.nz = 1;
+    h->psi = psi_dev;
+    h->stream = (hipStream_t)hip_stream;
+    r = setup(h);
+    if (r) {
+        delete h;
+        return r;
+    }
+    auto bail = [&](int code) {
+        sscn_destroy(h);
+        return code;
+    };
+    if (hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(SSCN_EHIP, "hipStreamCreateWithFlags failed"));
+    r = alloc_buffers(h);
+    if (r)
+        return bail(r);
+    const size_t npart = std::max<size_t>((size_t)h->nemit, (size_t)kRedBlocks);
+    if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->obs_part, (size_t)kRedBlocks * 14 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->obs_buf, 64 * sizeof(double)) != hipSuccess)
+        return bail(fail(SSCN_ENOMEM, "hipMalloc of reduction buffers failed"));
+    if (hipMemsetAsync(h->partials, 0, npart * sizeof(double), h->stream) != hipSuccess)
+        return bail(fail(SSCN_EHIP, "hipMemsetAsync failed"));
+    *out = h;
+    return 0;
+}
+
+void sscn_destroy(sscn_handle *h)
+{
+    if (!h)
+        return;
+    (void)hipStreamSynchronize(h->stream);
+    drop_graph(h);
+    free_buffers(h);
+    if (h->partials)
+        (void)hipFree(h->partials);
+    if (h->obs_part)
+        (void)hipFree(h->obs_part);
+    if (h->obs_buf)
+        (void)hipFree(h->obs_buf);
+    if (h->phase)
+        (void)hipFree(h->phase);
+    if (h->cap)
+        (void)hipStreamDestroy(h->cap);
+    delete h;
+}
+
+int sscn_init_state(sscn_handle *h, int kind, const double *phase_host, double d_xy, double d_z)
+{
+    if (!h || (kind != 0 && kind != 1) || !(d_xy > 0))
+        return fail(SSCN_EINVAL, "bad init_state arguments");
+    const sscn_params &p = h->p;
+    if (p.dim == 3 && !(d_z > 0))
+        d_z = 1.0 / std::sqrt(p.lambda);
+    const double *ph = nullptr;
+    if (phase_host) {
+        const size_t bytes = (size_t)p.nx * p.ny * sizeof(double);
+        if (!h->phase && hipMalloc(&h->phase, bytes) != hipSuccess)
+            return fail(SSCN_ENOMEM, "hipMalloc of the phase buffer failed");
+        HIPCHECK(hipMemcpyAsync(h->phase, phase_host, bytes, hipMemcpyHostToDevice, h->stream));
+        ph = h->phase;
+    }
+    const int nb = red_blocks(h->npts);
+    if (p.precision == SSCN_C128) {
+        hipLaunchKernelGGL((k_init<double>), dim3(nb), dim3(256), 0, h->stream, (V<double> *)h->psi, h->args, kind,
+                           ph, d_xy, d_z);
+        launch_norm<double>(h, h->stream);
+    } else {
+        hipLaunchKernelGGL((k_init<float>), dim3(nb), dim3(256), 0, h->stream, (V<float> *)h->psi, h->args, kind,
+                           ph, d_xy, d_z);
+        launch_norm<float>(h, h->stream);
+    }
+    // normalise: the norm partials use kRedBlocks blocks
+    const int saved = h->nemit;
+    h->nemit = kRedBlocks;
+    if (p.precision == SSCN_C128)
+        launch_rescale<double>(h, h->stream);
+    else
+        launch_rescale<float>(h, h->stream);
+    h->nemit = saved;
+    h->pending = false;
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int sscn_step(sscn_handle *h, int64_t nsteps)
+{
+    if (!h || nsteps < 0)
+        return fail(SSCN_EINVAL, "bad step arguments");
+    if (nsteps == 0)
+        return 0;
+    int64_t rem = nsteps;
+    if (nsteps >= kGraphSteps && !h->pending) {
+        int r = build_graph(h);
+        if (r)
+            return r;
+        while (rem >= kGraphSteps) {
+            HIPCHECK(hipGraphLaunch(h->gexec, h->stream));
+            rem -= kGraphSteps;
+        }
+    }
+    if (h->p.precision == SSCN_C128)
+        enqueue_direct<double>(h, rem, h->stream);
+    else
+        enqueue_direct<float>(h, rem, h->stream);
+    HIPCHECK(hipGetLastError());
+    h->steps += nsteps;
+    return 0;
+}
+
+int sscn_observables(sscn_handle *h, sscn_obs *out)
+{
+    if (!h || !out)
+        return fail(SSCN_EINVAL, "null argument");
+    const int nb = red_blocks(h->npts);
+    if (h->p.precision == SSCN_C128)
+        hipLaunchKernelGGL((k_observables<double>), dim3(nb), dim3(256), 0, h->stream, (const V<double> *)h->psi,
+                           h->args, h->obs_part);
+    else
+        hipLaunchKernelGGL((k_observables<float>), dim3(nb), dim3(256), 0, h->stream, (const V<float> *)h->psi,
+                           h->args, h->obs_part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->obs_part, nb, 14, 1u << 13, h->obs_buf);
+    double s[14];
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(s, h->obs_buf, sizeof s, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    const double dV = h->args.dV;
+    for (int t = 0; t < 13; ++t)
+        s[t] *= dV;
+    std::memset(out, 0, sizeof *out);
+    std::memcpy(out->sums, s, sizeof s);
+    out->norm = s[0];
+    out->mu = (s[2] + s[3] + s[4] + s[5]) / s[1];
+    out->energy = (s[2] + s[3] + 0.5 * s[4] + s[5]) / s[1];
+    out->mu_full = (s[6] + s[7] + s[8] + s[9]) / s[0];
+    out->energy_full = (s[6] + s[7] + 0.5 * s[8] + s[9]) / s[0];
+    out->rms_x = std::sqrt(s[10] / s[0]);
+    out->rms_y = std::sqrt(s[11] / s[0]);
+    out->rms_z = std::sqrt(s[12] / s[0]);
+    out->rms_r = std::sqrt((s[10] + s[11] + s[12]) / s[0]);
+    out->max_density = s[13];
+    out->step = h->steps;
+    for (int t = 0; t < 14; ++t)
+        if (!std::isfinite(s[t]))
+            return fail(SSCN_ENONFINITE, "non-finite reduction in the observables");
+    return 0;
+}
+
+int sscn_set_state(sscn_handle *h, const void *host_psi)
+{
+    if (!h || !host_psi)
+        return fail(SSCN_EINVAL, "null argument");
+    HIPCHECK(hipMemcpyAsync(h->psi, host_psi, (size_t)h->npts * h->esize, hipMemcpyHostToDevice, h->stream));
+    int r = sscn_set_state_device(h);
+    if (r)
+        return r;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int sscn_set_state_device(sscn_handle *h)
+{
+    if (!h)
+        return fail(SSCN_EINVAL, "null argument");
+    const int nb = red_blocks(h->npts);
+    if (h->p.precision == SSCN_C128)
+        hipLaunchKernelGGL((k_zero_walls<double>), dim3(nb), dim3(256), 0, h->stream, (V<double> *)h->psi, h->args);
+    else
+        hipLaunchKernelGGL((k_zero_walls<float>), dim3(nb), dim3(256), 0, h->stream, (V<float> *)h->psi, h->args);
+    HIPCHECK(hipGetLastError());
+    h->pending = false;
+    return 0;
+}
+
+int sscn_get_state(sscn_handle *h, void *host_psi)
+{
+    if (!h || !host_psi)
+        return fail(SSCN_EINVAL, "null argument");
+    HIPCHECK(hipMemcpyAsync(host_psi, h->psi, (size_t)h->npts * h->esize, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
+{
+    if (!h)
+        return fail(SSCN_EINVAL, "null argument");
+    sscn_params np = h->p;
+    np.mode = mode;
+    np.precision = precision;
+    int r = validate(np);
+    if (r)
+        return r;
+    const bool conv = precision != h->p.precision;
+    if (conv && !new_psi_dev)
+        return fail(SSCN_EINVAL, "a precision change needs the new state buffer");
+    sscn_handle tmp;
+    tmp.p = np;
+    r = setup(&tmp);
+    if (r)
+        return r;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    if (conv) {
+        const int nb = red_blocks(h->npts);
+        if (h->p.precision == SSCN_C64)
+            hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(256), 0, h->stream,
+                               (const V<float> *)h->psi, (V<double> *)new_psi_dev, h->npts);
+        else
+            hipLaunchKernelGGL((k_convert<double, float>), dim3(nb), dim3(256), 0, h->stream,
+                               (const V<double> *)h->psi, (V<float> *)new_psi_dev, h->npts);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipStreamSynchronize(h->stream));
+        h->psi = new_psi_dev;
+    }
+    free_buffers(h);
+    const int64_t steps = h->steps;
+    h->p = np;
+    r = setup(h);
+    if (r)
+        return r;
+    r = alloc_buffers(h);
+    if (r)
+        return r;
+    // the partials buffer must hold the new emit count
+    (void)hipFree(h->partials);
+    const size_t npart = std::max<size_t>((size_t)h->nemit, (size_t)kRedBlocks);
+    if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess)
+        return fail(SSCN_ENOMEM, "hipMalloc of the partials failed");
+    h->steps = steps;
+    h->pending = false;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int sscn_vortex_count(sscn_handle *h, double density_frac, int box, int *count)
+{
+    if (!h || !count || box < 0 || !(density_frac >= 0))
+        return fail(SSCN_EINVAL, "bad vortex_count arguments");
+    const sscn_params &p = h->p;
+    const int k0 = p.dim == 3 ? p.nz / 2 : 0;
+    const int64_t plane = (int64_t)p.nx * p.ny;
+    const int nb = red_blocks(plane);
+    if (p.precision == SSCN_C128) {
+        hipLaunchKernelGGL((k_plane_max<double>), dim3(nb), dim3(256), 0, h->stream, (const V<double> *)h->psi,
+                           h->args, k0, h->obs_part);
+    } else {
+        hipLaunchKernelGGL((k_plane_max<float>), dim3(nb), dim3(256), 0, h->stream, (const V<float> *)h->psi,
+                           h->args, k0, h->obs_part);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->obs_part, nb, 1, 1u, h->obs_buf + 16);
+    const int nbv = red_blocks((int64_t)(p.nx - 1) * (p.ny - 1));
+    if (p.precision == SSCN_C128) {
+        hipLaunchKernelGGL((k_vortex<double>), dim3(nbv), dim3(256), 0, h->stream, (const V<double> *)h->psi,
+                           h->args, k0, density_frac, box, h->obs_buf + 16, h->obs_part);
+    } else {
+        hipLaunchKernelGGL((k_vortex<float>), dim3(nbv), dim3(256), 0, h->stream, (const V<float> *)h->psi,
+                           h->args, k0, density_frac, box, h->obs_buf + 16, h->obs_part);
+    }
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->obs_part, nbv, 1, 0u, h->obs_buf + 17);
+    double c = 0.0;
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(&c, h->obs_buf + 17, sizeof c, hipMemcpyDeviceToHost, h->stream));
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    *count = (int)c;
+    return 0;
+}
+
+int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out)
+{
+    if (!h || !ms_out || nsteps < 1 || nsteps > 100000)
+        return fail(SSCN_EINVAL, "bad profile_step arguments");
+    const bool imag = h->p.mode == SSCN_IMAG;
+    std::vector<hipEvent_t> ev((size_t)nsteps * 4, nullptr);
+    int rc = 0;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            rc = fail(SSCN_EHIP, "hipEventCreate failed");
+            break;
+        }
+    if (!rc) {
+        for (int64_t s = 0; s < nsteps; ++s) {
+            const int npart = (imag && h->pending) ? h->nemit : 0;
+            if (h->p.precision == SSCN_C128)
+                enqueue_one<double>(h, npart, h->stream, &ev[(size_t)s * 4]);
+            else
+                enqueue_one<float>(h, npart, h->stream, &ev[(size_t)s * 4]);
+            if (imag)
+                h->pending = true;
+        }
+        if (imag) {
+            if (h->p.precision == SSCN_C128)
+                launch_rescale<double>(h, h->stream);
+            else
+                launch_rescale<float>(h, h->stream);
+            h->pending = false;
+        }
+        h->steps += nsteps;
+        if (hipStreamSynchronize(h->stream) != hipSuccess)
+            rc = fail(SSCN_EHIP, "hipStreamSynchronize failed");
+    }
+    if (!rc) {
+        double acc[4] = {0, 0, 0, 0};
+        for (int64_t s = 0; s < nsteps && !rc; ++s) {
+            hipEvent_t *e = &ev[(size_t)s * 4];
+            float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+            if (hipEventElapsedTime(&t01, e[0], e[1]) != hipSuccess ||
+                hipEventElapsedTime(&t12, e[1], e[2]) != hipSuccess ||
+                hipEventElapsedTime(&t23, e[2], e[3]) != hipSuccess ||
+                hipEventElapsedTime(&t03, e[0], e[3]) != hipSuccess)
+                rc = fail(SSCN_EHIP, "hipEventElapsedTime failed");
+            acc[0] += t01;
+            acc[1] += t12;
+            acc[2] += t23;
+            acc[3] += t03;
+        }
+        for (int t = 0; t < 4; ++t)
+            ms_out[t] = acc[t] / (double)nsteps;
+        if (h->p.dim == 2 && !h->exact)
+            ms_out[2] = 0.0;
+    }
+    for (auto &e : ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    return rc;
+}
+
+int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz)
+{
+    if (!h)
+        return fail(SSCN_EINVAL, "null argument");
+    for (int a = 0; a < 3; ++a) {
+        if (window_xyz)
+            window_xyz[a] = h->exact ? 0 : h->W[a];
+        if (segment_xyz)
+            segment_xyz[a] = h->exact ? 0 : kSeg;
+    }
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,290 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Both sides start from the same seeded inputs (workloads module) and are
+compared element by element.  Tolerances: relative L2 error of the state
+<= 1e-10 for complex128 sweeps and <= 1e-5 for complex64 sweeps with FP64
+reductions; observables to the same relative bounds.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-5
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) /
+                 np.linalg.norm(np.asarray(b).ravel()))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1906_06327_amd as P
+    P.lib()
+    return P
+
+
+def both(P, cfg):
+    """(GPU solver, oracle params) for one parameter dict."""
+    sp = W.solver_params(cfg)
+    return P.Solver(sp), O.make_params(**sp)
+
+
+def check_obs(go, oo, tol):
+    for k in ("norm", "mu", "energy", "mu_full", "energy_full", "rms_x", "rms_y", "rms_r"):
+        assert abs(go[k] - oo[k]) <= tol * max(1.0, abs(oo[k])), (k, go[k], oo[k])
+
+
+def announce(msg):
+    print(f"[gpu-parity] {msg}", flush=True)
+
+
+# --------------------------------------------------------------------------
+
+def test_init_state_matches_oracle(P):
+    for cfg in (W.CONFIGS["c1"], dict(W.CONFIGS["c3"], nx=48, ny=40, nz=20, precision=0)):
+        announce(f"init dim={cfg['dim']}")
+        s, op = both(P, cfg)
+        ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+        dz = cfg.get("d_z", 0.0)
+        s.init_state(1, ph, cfg["d_xy"], dz)
+        ref = O.init_state(op, 1, ph, cfg["d_xy"], dz if dz > 0 else None)
+        assert rel(s.get_state(), ref) <= 1e-14
+        s.init_state(0, None, 1.3, dz)
+        ref = O.init_state(op, 0, None, 1.3, dz if dz > 0 else None)
+        assert rel(s.get_state(), ref) <= 1e-14
+        s.close()
+
+
+def test_config1_full_run_matches_oracle(P):
+    """128^2, g = 100, Omega = 0.6, dt = 1e-3, 1000 imaginary-time steps."""
+    cfg = W.CONFIGS["c1"]
+    announce("c1 1000 steps")
+    s, op = both(P, cfg)
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    s.init_state(1, ph, 1.0)
+    ref = O.init_state(op, 1, ph, 1.0)
+    assert s.solver_info()["window"][0] > 0  # windowed kernels, not the fallback
+    s.step(cfg["steps"])
+    ref = O.step(op, ref, cfg["steps"])
+    got = s.get_state()
+    assert rel(got, ref) <= TOL64
+    check_obs(s.observables(), O.observables(op, ref), TOL64)
+    assert s.vortex_count() == O.vortex_count(op, ref)
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("shape", [(100, 77), (64, 64), (130, 9), (5, 200)])
+def test_ragged_2d(P, mode, shape):
+    nx, ny = shape
+    announce(f"ragged 2d {shape} mode={mode}")
+    cfg = dict(dim=2, nx=nx, ny=ny, nz=1, hx=0.11, hy=0.09, hz=0.1, gamma=1.0, nu=1.1,
+               lam=1.0, g=60.0, omega=0.55, dt=2e-3, mode=mode, precision=0)
+    s, op = both(P, cfg)
+    psi0 = W.random_field(11, (ny, nx)) / np.sqrt(0.11 * 0.09)
+    s.set_state(psi0)
+    s.step(150)
+    ref = O.step(op, psi0, 150)
+    assert rel(s.get_state(), ref) <= TOL64
+    s.close()
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_ragged_3d(P, mode):
+    announce(f"ragged 3d mode={mode}")
+    cfg = dict(dim=3, nx=37, ny=30, nz=21, hx=0.2, hy=0.22, hz=0.15, gamma=1.0, nu=1.05,
+               lam=2.0, g=40.0, omega=0.4, dt=2e-3, mode=mode, precision=0)
+    s, op = both(P, cfg)
+    psi0 = W.random_field(12, (21, 30, 37)) / np.sqrt(0.2 * 0.22 * 0.15)
+    s.set_state(psi0)
+    s.step(70)
+    ref = O.step(op, psi0, 70)
+    assert rel(s.get_state(), ref) <= TOL64
+    s.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_complex64_bulk(P, dim, mode):
+    announce(f"c64 dim={dim} mode={mode}")
+    if dim == 2:
+        cfg = dict(dim=2, nx=96, ny=90, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu=1.05,
+                   lam=1.0, g=100.0, omega=0.6, dt=1e-3, mode=mode, precision=1)
+        shp = (90, 96)
+    else:
+        cfg = dict(dim=3, nx=40, ny=44, nz=24, hx=0.2, hy=0.2, hz=0.2, gamma=1.0, nu=1.0,
+                   lam=4.0, g=200.0, omega=0.5, dt=5e-4, mode=mode, precision=1)
+        shp = (24, 44, 40)
+    s, op = both(P, cfg)
+    ph = W.phase_field(5, cfg["ny"], cfg["nx"])
+    s.init_state(1, ph, 1.0, 0.5)
+    ref = O.init_state(op, 1, ph, 1.0, 0.5)
+    s.step(300)
+    ref = O.step(op, ref, 300)
+    got = s.get_state()
+    assert got.shape == shp
+    assert rel(got.astype(np.complex128), ref) <= TOL32
+    check_obs(s.observables(), O.observables(op, ref), TOL32)
+    s.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_exact_whole_line_path(P, dim):
+    """Parameters whose decay bound needs a window beyond 32 rows run the
+    exact whole-line kernels."""
+    announce(f"exact path dim={dim}")
+    if dim == 2:
+        cfg = dict(dim=2, nx=50, ny=45, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu=1.0,
+                   lam=1.0, g=20.0, omega=0.3, dt=0.2, mode=0, precision=0)
+        shp = (45, 50)
+    else:
+        cfg = dict(dim=3, nx=20, ny=22, nz=18, hx=0.3, hy=0.3, hz=0.1, gamma=1.0, nu=1.0,
+                   lam=3.0, g=20.0, omega=0.3, dt=0.1, mode=0, precision=0)
+        shp = (18, 22, 20)
+    s, op = both(P, cfg)
+    assert s.solver_info()["window"] == [0, 0, 0]
+    psi0 = W.random_field(13, shp)
+    s.set_state(psi0)
+    s.step(20)
+    ref = O.step(op, psi0, 20)
+    assert rel(s.get_state(), ref) <= TOL64
+    s.close()
+
+
+def test_config2_full_size(P):
+    """512^2 on [-12.8, 12.8)^2, g = 1000, Omega = 0.9, dt = 5e-4: a stretch
+    of the imaginary-time phase and of the real-time phase at full size."""
+    cfg = W.CONFIGS["c2"]
+    announce("c2 512^2 imag 80 + real 40 (c128)")
+    s, op = both(P, cfg)
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    s.init_state(1, ph, 1.0)
+    ref = O.init_state(op, 1, ph, 1.0)
+    s.step(80)
+    ref = O.step(op, ref, 80)
+    assert rel(s.get_state(), ref) <= TOL64
+    s.set_mode(1)
+    opr = O.make_params(**W.solver_params(cfg, mode=1))
+    s.step(40)
+    ref = O.step(opr, ref, 40)
+    assert rel(s.get_state(), ref) <= TOL64
+    check_obs(s.observables(), O.observables(opr, ref), TOL64)
+    s.close()
+
+
+def test_config2_complex64_variant(P):
+    cfg = dict(W.CONFIGS["c2"], precision=1)
+    announce("c2 512^2 imag 80 (c64)")
+    s, op = both(P, cfg)
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    s.init_state(1, ph, 1.0)
+    ref = O.init_state(op, 1, ph, 1.0)
+    s.step(80)
+    ref = O.step(op, ref, 80)
+    assert rel(s.get_state().astype(np.complex128), ref) <= TOL32
+    check_obs(s.observables(), O.observables(op, ref), TOL32)
+    s.close()
+
+
+def test_config3_full_size_complex64(P):
+    """256 x 256 x 64, complex64 sweeps with FP64 norm: a few steps at full
+    size against the FP64 oracle."""
+    cfg = W.CONFIGS["c3"]
+    announce("c3 256x256x64 c64, 6 steps")
+    s, op = both(P, cfg)
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    s.init_state(1, ph, 1.0, cfg["d_z"])
+    ref = O.init_state(op, 1, ph, 1.0, cfg["d_z"])
+    s.step(6)
+    ref = O.step(op, ref, 6)
+    assert rel(s.get_state().astype(np.complex128), ref) <= TOL32
+    check_obs(s.observables(), O.observables(op, ref), TOL32)
+    s.close()
+
+
+def test_real_time_norm_conserved(P):
+    announce("real-time unitarity")
+    cfg = dict(dim=2, nx=128, ny=128, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu=1.0,
+               lam=1.0, g=100.0, omega=0.6, dt=1e-3, mode=1, precision=0)
+    s = P.Solver(W.solver_params(cfg))
+    s.init_state(1, W.phase_field(3, 128, 128), 1.0)
+    n0 = s.observables()["norm"]
+    s.step(3000)
+    assert abs(s.observables()["norm"] - n0) <= 1e-12
+    s.close()
+
+
+def test_observables_and_vortex_count_match_oracle(P):
+    announce("observables / vortex count")
+    cfg = dict(dim=2, nx=128, ny=128, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu=1.2,
+               lam=1.0, g=80.0, omega=0.45, dt=1e-3, mode=0, precision=0)
+    s, op = both(P, cfg)
+    x = -6.4 + 0.1 * np.arange(128)
+    Y, X = np.meshgrid(x, x, indexing="ij")
+    Z = X + 1j * Y
+    psi = np.exp(-(X ** 2 + Y ** 2) / 8).astype(complex)
+    for z0 in [0.03 + 0.02j] + [1.5 * np.exp(1j * (np.pi / 3 * k + 0.1)) for k in range(6)]:
+        psi = psi * (Z - z0) / np.sqrt(np.abs(Z - z0) ** 2 + 0.04)
+    psi = psi * np.exp(0.3j * X)
+    psi[0, :] = 0
+    psi[:, 0] = 0
+    s.set_state(psi)
+    check_obs(s.observables(), O.observables(op, psi), 1e-12)
+    assert s.vortex_count() == O.vortex_count(op, psi) == 7
+    s.close()
+
+
+def test_deterministic_and_restartable(P):
+    announce("determinism / restart")
+    cfg = dict(W.CONFIGS["c1"])
+    sp = W.solver_params(cfg)
+    ph = W.phase_field(7, 128, 128)
+    a = P.Solver(sp)
+    a.init_state(1, ph, 1.0)
+    a.step(300)
+    ra = a.get_state()
+    b = P.Solver(sp)
+    b.init_state(1, ph, 1.0)
+    b.step(100)
+    mid = b.get_state()
+    b.close()
+    c = P.Solver(sp)
+    c.set_state(mid)
+    c.step(200)
+    rc = c.get_state()
+    a2 = P.Solver(sp)
+    a2.init_state(1, ph, 1.0)
+    a2.step(300)
+    assert np.array_equal(a2.get_state(), ra)       # run-to-run bitwise
+    assert rel(rc, ra) <= 1e-13                      # restart (graph split differs)
+    for s in (a, a2, c):
+        s.close()
+
+
+def test_precision_upcast(P):
+    """complex64 bulk, then upcast to complex128 and continue (FP64
+    refinement); the continuation matches the oracle run from the upcast
+    state."""
+    announce("c64 -> c128 upcast")
+    cfg = dict(dim=2, nx=96, ny=96, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu=1.0,
+               lam=1.0, g=100.0, omega=0.6, dt=1e-3, mode=0, precision=1)
+    s = P.Solver(W.solver_params(cfg))
+    s.init_state(1, W.phase_field(9, 96, 96), 1.0)
+    s.step(200)
+    mid = s.get_state().astype(np.complex128)
+    s.set_mode(0, 0)
+    assert s.psi.dtype.itemsize == 16
+    assert np.array_equal(s.get_state(), mid)
+    s.step(200)
+    op = O.make_params(**W.solver_params(cfg, precision=0))
+    assert rel(s.get_state(), O.step(op, mid, 200)) <= TOL64
+    s.close()
