@@ -18,17 +18,30 @@
 // oracle.  Every line system is strictly diagonally
 // dominant, so the influence of a right-hand-side entry decays geometrically
 // with distance; a line is cut into segments of S outputs, each solved by
-// Thomas elimination over its own window of W extra rows on each side
-// (clipped at the walls, where the window start/end is exact).  W is chosen
-// on the host from a decay bound so that the truncation is below the
+// Thomas elimination over its own window of W extra rows on each side.  W is
+// chosen on the host from a decay bound so that the truncation is below the
 // arithmetic's rounding; when that would need W > 32 the whole-line exact
 // kernels are used instead.
+//
+// The elimination factors are data independent.  Every window uses the fixed
+// point c* = A+ / (A0 - A- c*), r* = 1/(A0 - A- c*) of the Thomas recurrence,
+// which is the exact factorisation of T_abs, the line matrix with its first
+// diagonal entry A0 replaced by A0 - A- c* (a window starting inside the line
+// thereby sees the eliminated semi-infinite line before it).  The true matrix
+// is T = T_abs + (A- c*) e_1 e_1^T, so by the Sherman-Morrison formula
+//   T^{-1} b = T_abs^{-1} b - gamma (T_abs^{-1} b)_1 z,   z = T_abs^{-1} e_1,
+//   gamma = A- c* / (1 + A- c* z_1);
+// z decays away from the wall, and the host tabulates zeta_u = 2 gamma z_u for
+// the first W rows.  The sweep kernels apply out_u -= delta_1 zeta_u there.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace sscn {
+
+// Largest number of state elements one thread of the x-sweep stages.
+constexpr int kXLoad = 16;
 
 template <class R> struct Cx {
     R re, im;
@@ -107,48 +120,70 @@ __device__ __forceinline__ Cx<R> minus_kv(const LineCoef<R> &L, Cx<R> vm, Cx<R> 
     return Cx<R>{-t.re, -t.im};
 }
 
-// Windowed Thomas solve of (I + K) delta = -K v for the S unknowns
-// s..s+S-1 of a line with unknowns 1..n-1 (values outside are zero), then
-// out = v + 2 delta.  `load(u)` returns v_u for 1 <= u <= n-1.  On return
-// io[r] holds the output of row s + r.
-template <class R, int S, int W, class Load>
-__device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Load load, Cx<R> (&io)[S])
+// Windowed solve of (I + K) delta = -K v for the S unknowns s..s+S-1 of a line
+// with unknowns 1..n-1, by Thomas elimination with the fixed-point factors
+// (cst, rst) from row s-W on; then io[r] = v_{s+r} + 2 delta_{s+r} and
+// d_first = delta_s (both uncorrected for the wall; see above).
+// vals[r] = v_{s-W-1+r} (zero outside 1..n-1), loaded by the caller.
+template <class R, int S, int W>
+__device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Cx<R> cst, Cx<R> rst,
+                                             const Cx<R> (&vals)[S + 2 * W + 2], Cx<R> (&io)[S], Cx<R> &d_first)
 {
-    Cx<R> cps[S + W], dps[S + W];
-    Cx<R> cprev = {R(0), R(0)}, dprev = {R(0), R(0)};
     const Cx<R> zero = {R(0), R(0)};
-    auto fetch = [&](int u) { return (u >= 1 && u <= n - 1) ? load(u) : zero; };
-    Cx<R> vm = fetch(s - W - 1), v0 = fetch(s - W);
+    const Cx<R> ma = L.Am * rst;
+    const Cx<R> alpha = {-ma.re, -ma.im};  // d'_u = r* rhs_u + alpha d'_{u-1}
+    Cx<R> dps[S + W];
+    Cx<R> dprev = zero;
 #pragma unroll
     for (int r = 0; r < S + 2 * W; ++r) {
         const int u = s - W + r;
         const bool valid = (u >= 1) && (u <= n - 1);
-        const Cx<R> vp = fetch(u + 1);
         if (r >= W && r < W + S)
-            io[r - W] = v0;
-        Cx<R> cp = zero, dp = zero;
-        if (valid) {
-            const Cx<R> rr = recip(L.A0 - L.Am * cprev);
-            cp = L.Ap * rr;
-            dp = (minus_kv(L, vm, v0, vp) - L.Am * dprev) * rr;
-        }
-        cprev = cp;
+            io[r - W] = vals[r + 1];
+        Cx<R> dp = zero;
+        if (valid)
+            dp = rst * minus_kv(L, vals[r], vals[r + 1], vals[r + 2]) + alpha * dprev;
         dprev = dp;
-        if (r >= W) {
-            cps[r - W] = cp;
+        if (r >= W)
             dps[r - W] = dp;
-        }
-        vm = v0;
-        v0 = vp;
     }
     Cx<R> dnext = zero;
 #pragma unroll
     for (int r = S + 2 * W - 1; r >= W; --r) {
-        const Cx<R> d = dps[r - W] - cps[r - W] * dnext;
+        const Cx<R> d = dps[r - W] - cst * dnext;
         if (r < W + S)
             io[r - W] = io[r - W] + R(2) * d;
+        if (r == W)
+            d_first = d;
         dnext = d;
     }
+}
+
+// Load the window values v_{s-W-1} .. v_{s+S+W} of one segment (zero outside
+// the unknowns 1..n-1), every load issued before any is consumed.
+template <class R, int S, int W, class Load>
+__device__ __forceinline__ void window_load(int s, int n, Load load, Cx<R> (&vals)[S + 2 * W + 2])
+{
+#pragma unroll
+    for (int r = 0; r < S + 2 * W + 2; ++r) {
+        const int u = s - W - 1 + r;
+        vals[r] = Cx<R>{R(0), R(0)};
+        if (u >= 1 && u <= n - 1)
+            vals[r] = load(u);
+    }
+}
+
+// Block index remapping for the strided sweeps.  Consecutive hardware
+// workgroup ids go to the 8 XCDs in turn; the remap gives each XCD a
+// contiguous range of logical blocks, so the windows of neighbouring
+// segments (which share halo rows) run under the same L2.  Returns -1 for
+// the padding blocks of a grid rounded up to a multiple of 8.
+__device__ __forceinline__ int xcd_logical_block(int nblocks)
+{
+    const int b = blockIdx.x;
+    const int per = (nblocks + 7) / 8;
+    const int l = (b % 8) * per + b / 8;
+    return l < nblocks ? l : -1;
 }
 
 // Deterministic block sum of one double over a 256-thread block; the result
@@ -232,21 +267,27 @@ __device__ __forceinline__ Cx<R> rescale(Cx<R> v, R sm1)
 }
 
 // ---------------------------------------------------------------------------
+// Pivot table of one line type (x-lines by j, y-lines by i, one for z):
+// tab[0] = c*, tab[1] = r*, tab[1 + u] = zeta_u (u = 1..W).  Stride W + 2.
+
 // x-sweep with the H1 sub-step and the pending rescale fused in front.
 // A block stages L whole x-lines in LDS (padded every S elements so that
-// consecutive threads, which own consecutive segments, hit distinct banks),
-// solves all (line, segment) pairs, and writes the lines back coalesced.
-// src may equal dst: a line is owned by exactly one block.
+// consecutive threads, which own consecutive segments, hit distinct banks);
+// thread p solves segment p % nseg of line p / nseg (L * nseg <= 256), the
+// results overwrite the staged lines, and the block writes them back
+// coalesced.  src may equal dst: a line is owned by exactly one block.
 template <class R, int S, int W, bool RT>
 __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
-                                                StepArgs a, int L, const double *partials, int npart)
+                                                StepArgs a, int L, const double *partials, int npart,
+                                                const Cx<R> *__restrict__ tab)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ double red[8];
     Cx<R> *lin = reinterpret_cast<Cx<R> *>(smem_raw);
     const int nx = a.nx, ny = a.ny;
     const int LS = nx + nx / S + 1;
-    Cx<R> *lout = lin + (size_t)L * LS;
+    Cx<R> *ltab = lin + (size_t)L * LS;      // L rows of W + 2 table entries
+    Cx<R> *d1 = ltab + (size_t)L * (W + 2);  // delta_1 of each staged line
     const int nlines = ny * (a.dim == 3 ? a.nz : 1);
     const int nseg = (nx - 2) / S + 1;
     const int line0 = blockIdx.x * L;
@@ -259,134 +300,244 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
     }
     const R sr = R(sm1);
 
-    for (int e = tid; e < L * nx; e += 256) {
+    // stage the block's lines and their table rows: every thread issues its
+    // loads first, then applies the rescale and H1 and writes LDS
+    Cx<R> pre[kXLoad];
+#pragma unroll
+    for (int c = 0; c < kXLoad; ++c) {
+        const int e = tid + c * 256;
         const int l = e / nx, t = e - l * nx;
         const int line = line0 + l;
-        Cx<R> v = {R(0), R(0)};
-        if (line < nlines && t > 0) {
-            const int j = line % ny, k = line / ny;
-            if (j > 0 && (a.dim == 2 || k > 0)) {
-                v = rescale(ld<R>(src, (int64_t)line * nx + t), sr);
-                const double x = a.x0 + t * a.hx, y = a.y0 + j * a.hy;
-                double V = a.vx * x * x + a.vy * y * y;
-                if (a.dim == 3) {
-                    const double z = a.z0 + k * a.hz;
-                    V += a.vz * z * z;
-                }
-                const R w = R(V) + R(a.g) * norm2(v);
-                v = h1_apply<R, RT>(v, w, R(a.dt));
-            }
-        }
-        lin[l * LS + t + t / S] = v;
+        pre[c] = Cx<R>{R(0), R(0)};
+        if (e < L * nx && line < nlines && t > 0)
+            pre[c] = ld<R>(src, (int64_t)line * nx + t);
     }
+    Cx<R> tpre[2];
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+        const int te = tid + c2 * 256;
+        tpre[c2] = Cx<R>{R(0), R(0)};
+        if (te < L * (W + 2)) {
+            const int l = te / (W + 2), c = te - l * (W + 2);
+            const int line = line0 + l;
+            if (line < nlines)
+                tpre[c2] = tab[(size_t)(line % ny) * (W + 2) + c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kXLoad; ++c) {
+        const int e = tid + c * 256;
+        if (e < L * nx) {
+            const int l = e / nx, t = e - l * nx;
+            const int line = line0 + l;
+            Cx<R> v = {R(0), R(0)};
+            if (line < nlines && t > 0) {
+                const int j = line % ny, k = line / ny;
+                if (j > 0 && (a.dim == 2 || k > 0)) {
+                    v = rescale(pre[c], sr);
+                    const double x = a.x0 + t * a.hx, y = a.y0 + j * a.hy;
+                    double V = a.vx * x * x + a.vy * y * y;
+                    if (a.dim == 3) {
+                        const double z = a.z0 + k * a.hz;
+                        V += a.vz * z * z;
+                    }
+                    const R w = R(V) + R(a.g) * norm2(v);
+                    v = h1_apply<R, RT>(v, w, R(a.dt));
+                }
+            }
+            lin[l * LS + t + t / S] = v;
+        }
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2)
+        if (tid + c2 * 256 < L * (W + 2))
+            ltab[tid + c2 * 256] = tpre[c2];
     __syncthreads();
 
-    for (int p = tid; p < L * nseg; p += 256) {
-        const int l = p / nseg, q = p - l * nseg;
-        const int line = line0 + l;
-        if (line >= nlines)
-            continue;
-        const int j = line % ny, k = line / ny;
-        if (j == 0 || (a.dim == 3 && k == 0))
-            continue;
+    const int l = tid / nseg, q = tid - l * nseg;
+    const int line = line0 + l;
+    const int j = line % ny, k = line / ny;
+    const bool active = l < L && line < nlines && j > 0 && (a.dim == 2 || k > 0);
+    const int s0 = 1 + q * S;
+    Cx<R> io[S];
+    if (active) {
         const LineCoef<R> Lc = line_coef<R>(a.ax[0], a.omega * (a.y0 + j * a.hy));
         const Cx<R> *row = lin + l * LS;
-        Cx<R> io[S];
-        const int s0 = 1 + q * S;
-        window_solve<R, S, W>(s0, nx, Lc, [&](int u) { return row[u + u / S]; }, io);
-        Cx<R> *orow = lout + l * LS;
+        Cx<R> vals[S + 2 * W + 2];
+        window_load<R, S, W>(s0, nx, [&](int u) { return row[u + u / S]; }, vals);
+        Cx<R> df;
+        window_solve<R, S, W>(s0, nx, Lc, ltab[l * (W + 2)], ltab[l * (W + 2) + 1], vals, io, df);
+        if (q == 0)
+            d1[l] = df;
+    }
+    __syncthreads();
+    if (active) {
+        Cx<R> *row = lin + l * LS;
+        const Cx<R> df = d1[l];
 #pragma unroll
         for (int r = 0; r < S; ++r) {
             const int u = s0 + r;
+            if (u <= W)
+                io[r] = io[r] - df * ltab[l * (W + 2) + 1 + u];
             if (u <= nx - 1)
-                orow[u + u / S] = io[r];
+                row[u + u / S] = io[r];
         }
     }
     __syncthreads();
 
     for (int e = tid; e < L * nx; e += 256) {
-        const int l = e / nx, t = e - l * nx;
-        const int line = line0 + l;
-        if (line < nlines && t > 0) {
-            const int j = line % ny, k = line / ny;
-            if (j > 0 && (a.dim == 2 || k > 0))
-                st<R>(dst, (int64_t)line * nx + t, lout[l * LS + t + t / S]);
+        const int l2 = e / nx, t = e - l2 * nx;
+        const int line2 = line0 + l2;
+        if (line2 < nlines && t > 0) {
+            const int j2 = line2 % ny, k2 = line2 / ny;
+            if (j2 > 0 && (a.dim == 2 || k2 > 0))
+                st<R>(dst, (int64_t)line2 * nx + t, lin[l2 * LS + t + t / S]);
         }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Strided sweeps (y: stride nx, z: stride nx*ny).  Thread = (line, segment);
-// the 64 lanes of a wave take 64 consecutive lines, so every row access of a
-// wave is one contiguous run.  src != dst (windows overlap).  With EMIT the
-// block writes the FP64 partial sum of |psi'|^2 of its outputs.
-template <class R, int S, int W, bool EMIT>
-__global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__restrict__ src,
-                                                typename Vec<R>::T *__restrict__ dst, StepArgs a,
-                                                double *partials)
+// Strided sweeps (y: stride nx, z: stride nx*ny).  A block takes 64
+// consecutive lines (the lanes of a wave) and kSegBlock consecutive segments
+// (its waves); it stages the tile of kSegBlock*S + 2W + 2 rows x 64 lines
+// those windows cover in LDS with one coalesced pass (each row a contiguous
+// run), so the halo rows shared by neighbouring segments are read once.
+// Thread (lane, wave) solves one segment from LDS and writes its outputs
+// straight to global memory (coalesced across the lanes).  src != dst.  With
+// EMIT the block writes the FP64 partial sum of |psi'|^2 of its outputs at
+// its logical block index.  Grid: 1-D, rounded up to a multiple of 8 logical
+// blocks (gx line tiles x gy segment groups x gz planes).
+constexpr int kSegBlock = 4;
+
+template <class R, int S, int W>
+__device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__restrict__ src,
+                                                   typename Vec<R>::T *__restrict__ dst, int n, int64_t base,
+                                                   int64_t stride, int nlines, int line0, int by, bool plane_ok,
+                                                   const LineCoef<R> &Lc, const Cx<R> *__restrict__ trow,
+                                                   bool emit, double &acc)
 {
-    __shared__ double red[8];
-    const int nx = a.nx, ny = a.ny;
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    const int q = blockIdx.y * 4 + threadIdx.y;
-    const int k = blockIdx.z;
-    const int nseg = (ny - 2) / S + 1;
-    double acc = 0.0;
-    if (i > 0 && i < nx && q < nseg && (a.dim == 2 || k > 0)) {
-        const LineCoef<R> Lc = line_coef<R>(a.ax[1], -a.omega * (a.x0 + i * a.hx));
-        const int64_t base = (int64_t)k * nx * ny + i;
-        Cx<R> io[S];
-        const int s0 = 1 + q * S;
-        window_solve<R, S, W>(s0, ny, Lc, [&](int u) { return ld<R>(src, base + (int64_t)u * nx); }, io);
+    constexpr int TR = kSegBlock * S + 2 * W + 2;
+    constexpr int K = (TR * 64 + 255) / 256;
+    __shared__ Cx<R> tile[TR * 64];
+    __shared__ Cx<R> d1[64];
+    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tid = tx + 64 * ty;
+    const int row0 = by * kSegBlock * S - W;  // line index u of tile row 0
+    Cx<R> pre[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int e = tid + c * 256;
+        const int rr = e >> 6, col = e & 63;
+        const int u = row0 + rr;
+        pre[c] = Cx<R>{R(0), R(0)};
+        if (e < TR * 64 && plane_ok && u >= 1 && u <= n - 1 && line0 + col < nlines)
+            pre[c] = ld<R>(src, base + (int64_t)u * stride + line0 + col);
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const int e = tid + c * 256;
+        if (e < TR * 64)
+            tile[e] = pre[c];
+    }
+    __syncthreads();
+    const int nseg = (n - 2) / S + 1;
+    const int q = by * kSegBlock + ty;
+    const int s0 = 1 + q * S;
+    const bool active = trow != nullptr && q < nseg;
+    Cx<R> io[S];
+    if (active) {
+        Cx<R> vals[S + 2 * W + 2];
+#pragma unroll
+        for (int r = 0; r < S + 2 * W + 2; ++r)
+            vals[r] = tile[(ty * S + r) * 64 + tx];
+        Cx<R> df;
+        window_solve<R, S, W>(s0, n, Lc, trow[0], trow[1], vals, io, df);
+        if (q == 0)
+            d1[tx] = df;
+    }
+    if (by == 0) {  // the wall rows 1..W lie in the first segment group
+        __syncthreads();
+        if (active && s0 <= W) {
+            const Cx<R> df = d1[tx];
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                const int u = s0 + r;
+                if (u <= W)
+                    io[r] = io[r] - df * trow[1 + u];
+            }
+        }
+    }
+    if (active) {
 #pragma unroll
         for (int r = 0; r < S; ++r) {
             const int u = s0 + r;
-            if (u <= ny - 1) {
-                st<R>(dst, base + (int64_t)u * nx, io[r]);
-                if (EMIT)
+            if (u <= n - 1) {
+                st<R>(dst, base + (int64_t)u * stride + line0 + tx, io[r]);
+                if (emit)
                     acc += (double)io[r].re * (double)io[r].re + (double)io[r].im * (double)io[r].im;
             }
         }
     }
+}
+
+template <class R, int S, int W, bool EMIT>
+__global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__restrict__ src,
+                                                typename Vec<R>::T *__restrict__ dst, StepArgs a,
+                                                double *partials, int gx, int gy, int gz,
+                                                const Cx<R> *__restrict__ tab)
+{
+    __shared__ double red[8];
+    const int lb = xcd_logical_block(gx * gy * gz);
+    if (lb < 0)
+        return;
+    const int by = lb % gy, rest = lb / gy;
+    const int bx = rest % gx, bz = rest / gx;
+    const int nx = a.nx, ny = a.ny;
+    const int i = bx * 64 + threadIdx.x;
+    const bool plane_ok = (a.dim == 2 || bz > 0);
+    const Cx<R> *trow = nullptr;
+    LineCoef<R> Lc{};
+    if (i > 0 && i < nx && plane_ok) {
+        Lc = line_coef<R>(a.ax[1], -a.omega * (a.x0 + i * a.hx));
+        trow = tab + (size_t)i * (W + 2);
+    }
+    double acc = 0.0;
+    strided_sweep_tile<R, S, W>(src, dst, ny, (int64_t)bz * nx * ny, nx, nx, bx * 64, by, plane_ok, Lc, trow,
+                                EMIT, acc);
     if (EMIT) {
         const double b = block_sum_256(acc, red);
         if (threadIdx.x == 0 && threadIdx.y == 0)
-            partials[blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)] = b;
+            partials[lb] = b;
     }
 }
 
 template <class R, int S, int W, bool EMIT>
 __global__ __launch_bounds__(256) void k_zsweep(const typename Vec<R>::T *__restrict__ src,
                                                 typename Vec<R>::T *__restrict__ dst, StepArgs a,
-                                                double *partials)
+                                                double *partials, int gx, int gy,
+                                                const Cx<R> *__restrict__ tab)
 {
     __shared__ double red[8];
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const int64_t plane = (int64_t)nx * ny;
-    const int pidx = blockIdx.x * 64 + threadIdx.x;
-    const int q = blockIdx.y * 4 + threadIdx.y;
-    const int nseg = (nz - 2) / S + 1;
-    double acc = 0.0;
+    const int lb = xcd_logical_block(gx * gy);
+    if (lb < 0)
+        return;
+    const int by = lb % gy, bx = lb / gy;
+    const int nx = a.nx, ny = a.ny;
+    const int pidx = bx * 64 + threadIdx.x;
     const int i = pidx % nx, j = pidx / nx;
-    if (pidx < nx * ny && i > 0 && j > 0 && q < nseg) {
-        const LineCoef<R> Lc = line_coef<R>(a.ax[2], 0.0);
-        Cx<R> io[S];
-        const int s0 = 1 + q * S;
-        window_solve<R, S, W>(s0, nz, Lc, [&](int u) { return ld<R>(src, pidx + (int64_t)u * plane); }, io);
-#pragma unroll
-        for (int r = 0; r < S; ++r) {
-            const int u = s0 + r;
-            if (u <= nz - 1) {
-                st<R>(dst, pidx + (int64_t)u * plane, io[r]);
-                if (EMIT)
-                    acc += (double)io[r].re * (double)io[r].re + (double)io[r].im * (double)io[r].im;
-            }
-        }
+    const Cx<R> *trow = nullptr;
+    LineCoef<R> Lc{};
+    if (pidx < nx * ny && i > 0 && j > 0) {
+        Lc = line_coef<R>(a.ax[2], 0.0);
+        trow = tab;
     }
+    double acc = 0.0;
+    strided_sweep_tile<R, S, W>(src, dst, a.nz, 0, (int64_t)nx * ny, nx * ny, bx * 64, by, true, Lc, trow, EMIT,
+                                acc);
     if (EMIT) {
         const double b = block_sum_256(acc, red);
         if (threadIdx.x == 0 && threadIdx.y == 0)
-            partials[blockIdx.x + gridDim.x * blockIdx.y] = b;
+            partials[lb] = b;
     }
 }
 

@@ -39,7 +39,7 @@ constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
 constexpr size_t kXLdsCap = 64 * 1024;
 
 // Supported window sizes (template instantiations).
-const int kWindows[] = {4, 8, 12, 16, 24, 32};
+const int kWindows[] = {4, 6, 8, 10, 12, 16, 20, 24, 32};
 
 }  // namespace
 
@@ -62,6 +62,9 @@ struct sscn_handle {
     double *obs_part = nullptr;  // observables / vortex partials
     double *obs_buf = nullptr;   // finished reductions (device)
     double *phase = nullptr;
+    void *tab[3] = {nullptr, nullptr, nullptr};  // per-axis pivot tables
+    int ygrid[3] = {0, 0, 0};  // strided-sweep logical grids (gx, gy, gz)
+    int zgrid[2] = {0, 0};
     bool pending = false;   // partials hold the norm of an unnormalised state
     int64_t steps = 0;
     hipGraphExec_t gexec = nullptr;
@@ -193,24 +196,103 @@ int setup(sscn_handle *h)
         a.ax[2] = a.ax[1], h->W[2] = 0;
     h->npts = npoints(p);
     h->esize = p.precision == SSCN_C128 ? 16 : 8;
-    // x-sweep staging: L lines per block so that L * segments ~ 256 threads
+    // x-sweep staging: L lines per block, one (line, segment) per thread
     const int nseg = (p.nx - 2) / kSeg + 1;
     const size_t LS = (size_t)p.nx + p.nx / kSeg + 1;
-    int L = std::max(1, 256 / nseg);
-    while (L > 1 && 2 * L * LS * h->esize > kXLdsCap)
-        --L;
+    const int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / p.nx, 512 / (h->W[0] + 2)}));
     h->xL = L;
-    h->xlds = 2 * L * LS * h->esize;
-    if (h->xlds > kXLdsCap)
+    h->xlds = (L * LS + (size_t)L * (h->W[0] + 2) + L) * h->esize;
+    if (nseg > 256 || p.nx > 256 * kXLoad || h->xlds > kXLdsCap)
         h->exact = true;  // lines too long to stage; whole-line path
-    // partials written by the last sweep
+    // strided sweeps: logical grids and the partials written by the last one
+    h->ygrid[0] = (p.nx + 63) / 64;
+    h->ygrid[1] = ((p.ny - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock;
+    h->ygrid[2] = p.dim == 3 ? p.nz : 1;
+    h->zgrid[0] = (int)(((int64_t)p.nx * p.ny + 63) / 64);
+    h->zgrid[1] = p.dim == 3 ? ((p.nz - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock : 1;
     if (p.dim == 2)
-        h->nemit = ((p.nx + 63) / 64) * (((p.ny - 2) / kSeg + 1 + 3) / 4);
+        h->nemit = h->ygrid[0] * h->ygrid[1];
     else
-        h->nemit = (int)(((int64_t)p.nx * p.ny + 63) / 64) * (((p.nz - 2) / kSeg + 1 + 3) / 4);
+        h->nemit = h->zgrid[0] * h->zgrid[1];
     if (h->exact) {
         h->W[0] = h->W[1] = h->W[2] = 0;
         h->nemit = kRedBlocks;
+    }
+    return 0;
+}
+
+// Pivot tables of the windowed solves, one row per distinct line of an axis
+// (x-lines by j, y-lines by i, one for z), stride W + 2: the fixed point c*,
+// r* of the Thomas recurrence c' = A+ r, r = 1/(A0 - A- c'), then the wall
+// correction zeta_u = 2 gamma z_u (u = 1..W) with z = T_abs^{-1} e_1 over the
+// whole line and gamma = A- c* / (1 + A- c* z_1) (Sherman-Morrison for the
+// one diagonal entry in which the line matrix differs from T_abs).  FP64.
+int build_tables(sscn_handle *h)
+{
+    using cd = std::complex<double>;
+    const sscn_params &p = h->p;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (h->tab[ax])
+            (void)hipFree(h->tab[ax]);
+        h->tab[ax] = nullptr;
+    }
+    if (h->exact)
+        return 0;
+    for (int ax = 0; ax < p.dim; ++ax) {
+        const int W = h->W[ax];
+        const AxisCoef &c = h->args.ax[ax];
+        const cd A0(c.a0r, c.a0i), u(c.ur, c.ui), q(c.qr, c.qi);
+        const int ntypes = ax == 0 ? p.ny : ax == 1 ? p.nx : 1;
+        const int m = (ax == 0 ? p.nx : ax == 1 ? p.ny : p.nz) - 1;  // unknowns per line
+        const int stride = W + 2;
+        std::vector<cd> t((size_t)ntypes * stride);
+        std::vector<cd> z((size_t)m + 2);
+        for (int ty = 0; ty < ntypes; ++ty) {
+            double rot = 0.0;
+            if (ax == 0)
+                rot = p.omega * (h->args.y0 + ty * p.hy);
+            else if (ax == 1)
+                rot = -p.omega * (h->args.x0 + ty * p.hx);
+            const cd Ap = u + q * rot, Am = u - q * rot;
+            cd cs = 0.0;
+            for (int it = 0; it < 100000; ++it) {
+                const cd nc = Ap / (A0 - Am * cs);
+                const bool done = std::abs(nc - cs) <= 1e-18 * std::abs(nc);
+                cs = nc;
+                if (done)
+                    break;
+            }
+            const cd rs = 1.0 / (A0 - Am * cs);
+            // z = T_abs^{-1} e_1: forward d'_1 = r*, d'_k = -A- r* d'_{k-1};
+            // back z_m = d'_m, z_k = d'_k - c* z_{k+1}
+            cd d = rs;
+            z[1] = d;
+            for (int k = 2; k <= m; ++k) {
+                d = -Am * rs * d;
+                z[k] = d;
+            }
+            for (int k = m - 1; k >= 1; --k)
+                z[k] = z[k] - cs * z[k + 1];
+            const cd gam = Am * cs / (1.0 + Am * cs * z[1]);
+            cd *row = &t[(size_t)ty * stride];
+            row[0] = cs;
+            row[1] = rs;
+            for (int k = 1; k <= W; ++k)
+                row[1 + k] = k <= m ? 2.0 * gam * z[k] : cd(0.0);
+        }
+        const size_t n = t.size();
+        if (p.precision == SSCN_C128) {
+            if (hipMalloc(&h->tab[ax], n * sizeof(Cx<double>)) != hipSuccess)
+                return fail(SSCN_ENOMEM, "hipMalloc of a pivot table failed");
+            HIPCHECK(hipMemcpy(h->tab[ax], t.data(), n * sizeof(Cx<double>), hipMemcpyHostToDevice));
+        } else {
+            std::vector<Cx<float>> f(n);
+            for (size_t e = 0; e < n; ++e)
+                f[e] = Cx<float>{(float)t[e].real(), (float)t[e].imag()};
+            if (hipMalloc(&h->tab[ax], n * sizeof(Cx<float>)) != hipSuccess)
+                return fail(SSCN_ENOMEM, "hipMalloc of a pivot table failed");
+            HIPCHECK(hipMemcpy(h->tab[ax], f.data(), n * sizeof(Cx<float>), hipMemcpyHostToDevice));
+        }
     }
     return 0;
 }
@@ -222,72 +304,71 @@ int red_blocks(int64_t n) { return (int)std::min<int64_t>(kRedBlocks, std::max<i
 
 template <class R> using V = typename Vec<R>::T;
 
+// Dispatch on the window size W (a template parameter of the sweeps).
+#define SSCN_W_SWITCH(Wv, CALL)                                                                             \
+    switch (Wv) {                                                                                            \
+    case 4: CALL(4); break;                                                                                  \
+    case 6: CALL(6); break;                                                                                  \
+    case 8: CALL(8); break;                                                                                  \
+    case 10: CALL(10); break;                                                                                \
+    case 12: CALL(12); break;                                                                                \
+    case 16: CALL(16); break;                                                                                \
+    case 20: CALL(20); break;                                                                                \
+    case 24: CALL(24); break;                                                                                \
+    default: CALL(32); break;                                                                                \
+    }
+
+unsigned round8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
+
 template <class R, int W, bool RT>
 void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st)
 {
     const int nlines = h->p.ny * (h->p.dim == 3 ? h->p.nz : 1);
     const int blocks = (nlines + h->xL - 1) / h->xL;
     hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
-                       (V<R> *)dst, h->args, h->xL, h->partials, npart);
+                       (V<R> *)dst, h->args, h->xL, h->partials, npart, (const Cx<R> *)h->tab[0]);
 }
 
 template <class R, bool RT>
 void launch_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st)
 {
-    switch (h->W[0]) {
-    case 4: go_x<R, 4, RT>(h, src, dst, npart, st); break;
-    case 8: go_x<R, 8, RT>(h, src, dst, npart, st); break;
-    case 12: go_x<R, 12, RT>(h, src, dst, npart, st); break;
-    case 16: go_x<R, 16, RT>(h, src, dst, npart, st); break;
-    case 24: go_x<R, 24, RT>(h, src, dst, npart, st); break;
-    default: go_x<R, 32, RT>(h, src, dst, npart, st); break;
-    }
+#define SSCN_CALL_X(Wc) go_x<R, Wc, RT>(h, src, dst, npart, st)
+    SSCN_W_SWITCH(h->W[0], SSCN_CALL_X)
+#undef SSCN_CALL_X
 }
 
 template <class R, int W, bool EMIT>
 void go_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
 {
-    const sscn_params &p = h->p;
-    const int nseg = (p.ny - 2) / kSeg + 1;
-    dim3 grid((p.nx + 63) / 64, (nseg + 3) / 4, p.dim == 3 ? p.nz : 1);
-    hipLaunchKernelGGL((k_ysweep<R, kSeg, W, EMIT>), grid, dim3(64, 4), 0, st, (const V<R> *)src, (V<R> *)dst,
-                       h->args, h->partials);
+    const int *g = h->ygrid;
+    hipLaunchKernelGGL((k_ysweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1] * g[2])), dim3(64, 4), 0,
+                       st, (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1], g[2],
+                       (const Cx<R> *)h->tab[1]);
 }
 
 template <class R, bool EMIT>
 void launch_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
 {
-    switch (h->W[1]) {
-    case 4: go_y<R, 4, EMIT>(h, src, dst, st); break;
-    case 8: go_y<R, 8, EMIT>(h, src, dst, st); break;
-    case 12: go_y<R, 12, EMIT>(h, src, dst, st); break;
-    case 16: go_y<R, 16, EMIT>(h, src, dst, st); break;
-    case 24: go_y<R, 24, EMIT>(h, src, dst, st); break;
-    default: go_y<R, 32, EMIT>(h, src, dst, st); break;
-    }
+#define SSCN_CALL_Y(Wc) go_y<R, Wc, EMIT>(h, src, dst, st)
+    SSCN_W_SWITCH(h->W[1], SSCN_CALL_Y)
+#undef SSCN_CALL_Y
 }
 
 template <class R, int W, bool EMIT>
 void go_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
 {
-    const sscn_params &p = h->p;
-    const int nseg = (p.nz - 2) / kSeg + 1;
-    dim3 grid((unsigned)(((int64_t)p.nx * p.ny + 63) / 64), (nseg + 3) / 4, 1);
-    hipLaunchKernelGGL((k_zsweep<R, kSeg, W, EMIT>), grid, dim3(64, 4), 0, st, (const V<R> *)src, (V<R> *)dst,
-                       h->args, h->partials);
+    const int *g = h->zgrid;
+    hipLaunchKernelGGL((k_zsweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1])), dim3(64, 4), 0, st,
+                       (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1],
+                       (const Cx<R> *)h->tab[2]);
 }
 
 template <class R, bool EMIT>
 void launch_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
 {
-    switch (h->W[2]) {
-    case 4: go_z<R, 4, EMIT>(h, src, dst, st); break;
-    case 8: go_z<R, 8, EMIT>(h, src, dst, st); break;
-    case 12: go_z<R, 12, EMIT>(h, src, dst, st); break;
-    case 16: go_z<R, 16, EMIT>(h, src, dst, st); break;
-    case 24: go_z<R, 24, EMIT>(h, src, dst, st); break;
-    default: go_z<R, 32, EMIT>(h, src, dst, st); break;
-    }
+#define SSCN_CALL_Z(Wc) go_z<R, Wc, EMIT>(h, src, dst, st)
+    SSCN_W_SWITCH(h->W[2], SSCN_CALL_Z)
+#undef SSCN_CALL_Z
 }
 
 template <class R>
@@ -504,6 +585,9 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
     r = alloc_buffers(h);
     if (r)
         return bail(r);
+    r = build_tables(h);
+    if (r)
+        return bail(r);
     const size_t npart = std::max<size_t>((size_t)h->nemit, (size_t)kRedBlocks);
     if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_part, (size_t)kRedBlocks * 14 * sizeof(double)) != hipSuccess ||
@@ -522,6 +606,9 @@ void sscn_destroy(sscn_handle *h)
     (void)hipStreamSynchronize(h->stream);
     drop_graph(h);
     free_buffers(h);
+    for (int ax = 0; ax < 3; ++ax)
+        if (h->tab[ax])
+            (void)hipFree(h->tab[ax]);
     if (h->partials)
         (void)hipFree(h->partials);
     if (h->obs_part)
@@ -711,6 +798,9 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
     if (r)
         return r;
     r = alloc_buffers(h);
+    if (r)
+        return r;
+    r = build_tables(h);
     if (r)
         return r;
     // the partials buffer must hold the new emit count
