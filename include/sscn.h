@@ -51,6 +51,7 @@ enum {
 };
 
 enum { SSCN_IMAG = 0, SSCN_REAL = 1 };      /* propagation mode              */
+enum { SSCN_PLAN_AUTO = 0, SSCN_PLAN_SWEEPS = 1, SSCN_PLAN_FUSED = 2 }; /* kernels */
 enum { SSCN_C128 = 0, SSCN_C64 = 1 };       /* storage/arithmetic precision  */
 
 typedef struct sscn_params {
@@ -150,9 +151,21 @@ int sscn_vortex_count(sscn_handle *h, double density_frac, int box, int *count);
  * launches each kernel on its own, without graphs.  Synchronises the stream. */
 int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out);
 
-/* Window (rows of look-ahead) used by the truncated line solves per axis;
- * 0 means the exact whole-line solve.  For diagnostics and tests. */
-int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz);
+/* Choose the kernels of a step.  SSCN_PLAN_SWEEPS: one launch per axis
+ * (x with H1 and the pending rescale fused in front; y; z).
+ * SSCN_PLAN_FUSED (2D only): one launch per step over 32 x 32 tiles with
+ * halos, H1 + x + y fused.  SSCN_PLAN_AUTO (default): on the first step the
+ * library times the available plans from a saved copy of the state and
+ * keeps the fastest (cached per process).  All plans compute the same step
+ * to rounding.  SSCN_EINVAL if the fused plan is not available (3D, or a
+ * window above 20 rows in complex128 / 32 in complex64). */
+int sscn_set_plan(sscn_handle *h, int plan);
+
+/* Window (rows of look-ahead) used by the truncated line solves per axis
+ * (0 means the exact whole-line solve), segment length per axis, and the
+ * plan in use (SSCN_PLAN_AUTO until the first step resolves it).  Any
+ * output pointer may be NULL.  For diagnostics and tests. */
+int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *plan);
 
 void sscn_destroy(sscn_handle *h);
 

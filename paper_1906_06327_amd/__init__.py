@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libsscn.so")
 
 SSCN_IMAG, SSCN_REAL = 0, 1
 SSCN_C128, SSCN_C64 = 0, 1
+PLAN_AUTO, PLAN_SWEEPS, PLAN_FUSED = 0, 1, 2
 
 ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABLE",
           -4: "SSCN_ENONFINITE", -5: "SSCN_EHIP", -6: "SSCN_ENOMEM"}
@@ -22,7 +23,8 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
 # Every symbol include/sscn.h declares.
 EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
-           "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_solver_info",
+           "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
+           "sscn_solver_info",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -69,7 +71,9 @@ def lib():
         L.sscn_get_state.argtypes = [vp, vp]
         L.sscn_set_mode.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
         L.sscn_vortex_count.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
-        L.sscn_solver_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.sscn_solver_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
+                                       ctypes.POINTER(ctypes.c_int)]
+        L.sscn_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
         L.sscn_destroy.argtypes = [vp]
         L.sscn_destroy.restype = None
@@ -195,11 +199,15 @@ class Solver:
         _check(lib().sscn_profile_step(self._h, int(n), ms))
         return {"x": ms[0], "y": ms[1], "z": ms[2], "step": ms[3]}
 
+    def set_plan(self, plan):
+        _check(lib().sscn_set_plan(self._h, int(plan)))
+
     def solver_info(self):
         w = (ctypes.c_int * 3)()
         s = (ctypes.c_int * 3)()
-        _check(lib().sscn_solver_info(self._h, w, s))
-        return {"window": list(w), "segment": list(s)}
+        pl = ctypes.c_int()
+        _check(lib().sscn_solver_info(self._h, w, s, ctypes.byref(pl)))
+        return {"window": list(w), "segment": list(s), "plan": int(pl.value)}
 
     def close(self):
         if getattr(self, "_h", None):

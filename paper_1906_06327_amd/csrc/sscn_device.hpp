@@ -542,6 +542,195 @@ __global__ __launch_bounds__(256) void k_zsweep(const typename Vec<R>::T *__rest
 }
 
 // ---------------------------------------------------------------------------
+// Fused 2D step: one launch advances every listed (instance, tile) item by a
+// whole SSCN step.  An item is a TR x TC tile of outputs; the block stages
+// the tile plus a halo of W+1 rows and columns from the current buffer,
+// applies the pending rescale and H1 to every staged point, solves the
+// x-lines of all staged rows for the TC output columns, then the y-lines of
+// the TC columns for the TR output rows, and writes the tile to the other
+// buffer with its FP64 partial |psi'|^2.  Halos make neighbouring tiles
+// independent, so one launch needs no grid-wide synchronisation; the two
+// buffers of an instance alternate from step to step.  Blocks loop over the
+// work list, so the same launch serves one grid or a batch of instances of
+// different sizes and parameters.
+struct Inst2D {
+    int nx, ny, tiles_x, tiles_y, poff, active;
+    double hx, hy, x0, y0, vx, vy, g, omega, dt, dV;
+    AxisCoef ax[2];
+    void *buf[2];
+    const void *tab[2];   // pivot tables of x-lines (by j) and y-lines (by i)
+};
+
+// stage-buffer row stride: >= SC + SC/S + 1 and = 4 (mod 16), so that the
+// 8 (b128) or 16 (b64) lanes served together hit distinct banks
+constexpr int stage_stride(int SC, int S)
+{
+    int v = SC + SC / S + 1;
+    while (v % 16 != 4)
+        ++v;
+    return v;
+}
+
+template <class R, int S, int W, int TR, int TC>
+constexpr size_t step2d_lds_bytes()
+{
+    return (size_t)(TR + 2 * W + 2) * (stage_stride(TC + 2 * W + 2, S) + TC + 1) * sizeof(Cx<R>);
+}
+
+template <class R, int S, int W, int TR, int TC, bool RT>
+__global__ __launch_bounds__(256) void k_step2d(const Inst2D *__restrict__ insts, const int2 *__restrict__ work,
+                                                const int *__restrict__ nwork, int parity,
+                                                const double *__restrict__ pin, double *__restrict__ pout,
+                                                int use_pin)
+{
+    constexpr int H = W + 1;
+    constexpr int SR = TR + 2 * H, SC = TC + 2 * H;
+    constexpr int SCP = stage_stride(SC, S);
+    constexpr int C2 = TC + 1;
+    constexpr int NST = (SR * SC + 255) / 256;
+    constexpr int NSX = TC / S, NSY = TR / S;
+    static_assert(TC % S == 0 && TR % S == 0 && TC * NSY <= 256, "tile shape");
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    Cx<R> *st1 = reinterpret_cast<Cx<R> *>(smem_raw);  // SR x SCP staged, H1 applied
+    Cx<R> *st2 = st1 + SR * SCP;                         // SR x C2 after the x-solve
+    __shared__ Cx<R> d1x[SR];
+    __shared__ Cx<R> d1y[TC];
+    __shared__ double red[8];
+    const int tid = threadIdx.x;
+    const int nw = *nwork;
+    for (int it = blockIdx.x; it < nw; it += gridDim.x) {
+        const int2 wk = work[it];
+        const Inst2D &I = insts[wk.x];
+        const int nx = I.nx, ny = I.ny;
+        const int tyi = wk.y / I.tiles_x, txi = wk.y - tyi * I.tiles_x;
+        const int r0 = 1 + tyi * TR, c0 = 1 + txi * TC;  // first output row j / column i
+        const int jb = r0 - H, ib = c0 - H;              // staged origin
+        const typename Vec<R>::T *src = reinterpret_cast<const typename Vec<R>::T *>(I.buf[parity]);
+        typename Vec<R>::T *dst = reinterpret_cast<typename Vec<R>::T *>(I.buf[parity ^ 1]);
+        const Cx<R> *tabx = reinterpret_cast<const Cx<R> *>(I.tab[0]);
+        const Cx<R> *taby = reinterpret_cast<const Cx<R> *>(I.tab[1]);
+
+        // stage: issue every load first
+        Cx<R> pre[NST];
+#pragma unroll
+        for (int c = 0; c < NST; ++c) {
+            const int e = tid + c * 256;
+            const int rr = e / SC, cc = e - rr * SC;
+            const int j = jb + rr, i = ib + cc;
+            pre[c] = Cx<R>{R(0), R(0)};
+            if (e < SR * SC && j >= 1 && j <= ny - 1 && i >= 1 && i <= nx - 1)
+                pre[c] = ld<R>(src, (int64_t)j * nx + i);
+        }
+        double sm1 = 0.0;
+        if (!RT && use_pin)
+            sm1 = 1.0 / sqrt(I.dV * block_sum_partials(pin + I.poff, I.tiles_x * I.tiles_y, red)) - 1.0;
+        const R sr = R(sm1);
+#pragma unroll
+        for (int c = 0; c < NST; ++c) {
+            const int e = tid + c * 256;
+            if (e < SR * SC) {
+                const int rr = e / SC, cc = e - rr * SC;
+                const int j = jb + rr, i = ib + cc;
+                Cx<R> v = {R(0), R(0)};
+                if (j >= 1 && j <= ny - 1 && i >= 1 && i <= nx - 1) {
+                    v = rescale(pre[c], sr);
+                    const double x = I.x0 + i * I.hx, y = I.y0 + j * I.hy;
+                    const R w = R(I.vx * x * x + I.vy * y * y) + R(I.g) * norm2(v);
+                    v = h1_apply<R, RT>(v, w, R(I.dt));
+                }
+                st1[rr * SCP + cc + cc / S] = v;
+            }
+        }
+        __syncthreads();
+
+        // x-lines of every staged row, outputs for the TC tile columns
+        for (int p = tid; p < SR * NSX; p += 256) {
+            const int rr = p / NSX, q = p - rr * NSX;
+            const int j = jb + rr;
+            Cx<R> io[S];
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                io[r] = Cx<R>{R(0), R(0)};
+            if (j >= 1 && j <= ny - 1) {
+                const LineCoef<R> Lc = line_coef<R>(I.ax[0], I.omega * (I.y0 + j * I.hy));
+                const Cx<R> *trow = tabx + (size_t)j * (W + 2);
+                Cx<R> vals[S + 2 * W + 2];
+#pragma unroll
+                for (int r = 0; r < S + 2 * W + 2; ++r) {
+                    const int cc = q * S + r;
+                    vals[r] = st1[rr * SCP + cc + cc / S];
+                }
+                Cx<R> df;
+                const int s = c0 + q * S;
+                window_solve<R, S, W>(s, nx, Lc, trow[0], trow[1], vals, io, df);
+                if (s == 1)
+                    d1x[rr] = df;
+#pragma unroll
+                for (int r = 0; r < S; ++r)
+                    if (s + r > nx - 1)
+                        io[r] = Cx<R>{R(0), R(0)};
+            }
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+                st2[rr * C2 + q * S + r] = io[r];
+        }
+        __syncthreads();
+        if (c0 == 1) {  // wall rows of the x-lines: Sherman-Morrison term
+            for (int p = tid; p < SR * W; p += 256) {
+                const int rr = p / W, u = 1 + (p - rr * W);
+                const int j = jb + rr;
+                if (j >= 1 && j <= ny - 1 && u <= nx - 1 && u - c0 < TC)
+                    st2[rr * C2 + (u - c0)] = st2[rr * C2 + (u - c0)] - d1x[rr] * tabx[(size_t)j * (W + 2) + 1 + u];
+            }
+            __syncthreads();
+        }
+
+        // y-lines of the TC columns, outputs for the TR tile rows
+        const int col = tid % TC, q = tid / TC;
+        const int i = c0 + col;
+        const bool act = q < NSY && i <= nx - 1;
+        const int s = r0 + q * S;
+        Cx<R> io[S];
+        if (act) {
+            const LineCoef<R> Lc = line_coef<R>(I.ax[1], -I.omega * (I.x0 + i * I.hx));
+            const Cx<R> *trow = taby + (size_t)i * (W + 2);
+            Cx<R> vals[S + 2 * W + 2];
+#pragma unroll
+            for (int r = 0; r < S + 2 * W + 2; ++r)
+                vals[r] = st2[(q * S + r) * C2 + col];
+            Cx<R> df;
+            window_solve<R, S, W>(s, ny, Lc, trow[0], trow[1], vals, io, df);
+            if (s == 1)
+                d1y[col] = df;
+        }
+        if (r0 == 1)
+            __syncthreads();
+        double acc = 0.0;
+        if (act) {
+            const Cx<R> *trow = taby + (size_t)i * (W + 2);
+#pragma unroll
+            for (int r = 0; r < S; ++r) {
+                const int u = s + r;
+                if (u <= ny - 1) {
+                    Cx<R> o = io[r];
+                    if (r0 == 1 && u <= W)
+                        o = o - d1y[col] * trow[1 + u];
+                    st<R>(dst, (int64_t)u * nx + i, o);
+                    if (!RT)
+                        acc += (double)o.re * (double)o.re + (double)o.im * (double)o.im;
+                }
+            }
+        }
+        if (!RT) {
+            const double b = block_sum_256(acc, red);
+            if (tid == 0)
+                pout[I.poff + wk.y] = b;
+        }
+        __syncthreads();  // LDS reuse by the next item
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Exact whole-line path (used when the decay bound would need W > 32).
 
 // Pointwise H1 with the pending rescale, src -> dst.

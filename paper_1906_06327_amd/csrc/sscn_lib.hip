@@ -7,6 +7,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <type_traits>
 #include <cmath>
 #include <complex>
 #include <cstdio>
@@ -36,6 +41,7 @@ int fail(int code, const std::string &msg)
 constexpr int kSeg = 8;             // outputs per thread segment (all axes)
 constexpr int kGraphSteps = 64;     // steps per captured graph
 constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
+constexpr int kTile = 32;           // fused 2D step: output tile side
 constexpr size_t kXLdsCap = 64 * 1024;
 
 // Supported window sizes (template instantiations).
@@ -67,6 +73,18 @@ struct sscn_handle {
     int zgrid[2] = {0, 0};
     bool pending = false;   // partials hold the norm of an unnormalised state
     int64_t steps = 0;
+    // fused 2D step (one launch per step over a work list of tiles)
+    int plan = SSCN_PLAN_AUTO;   // requested plan
+    int active_plan = SSCN_PLAN_SWEEPS;
+    bool fused_ok = false;
+    Inst2D *d_inst = nullptr;
+    int2 *d_work = nullptr;
+    int *d_nwork = nullptr;
+    int ntiles = 0;
+    double *partials2 = nullptr;
+    int fparity = 0;        // buffer (0 = psi, 1 = work) holding the state
+    int pbuf = 0;           // partial buffer holding the pending norm
+    float tune_ms[3] = {0, 0, 0};
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
 };
@@ -192,8 +210,12 @@ int setup(sscn_handle *h)
         if (h->W[ax] == 0)
             h->exact = true;
     }
-    if (p.dim == 2)
-        a.ax[2] = a.ax[1], h->W[2] = 0;
+    if (p.dim == 2) {
+        a.ax[2] = a.ax[1];
+        h->W[2] = 0;
+        // one window for both axes (the fused step needs a common table stride)
+        h->W[0] = h->W[1] = std::max(h->W[0], h->W[1]);
+    }
     h->npts = npoints(p);
     h->esize = p.precision == SSCN_C128 ? 16 : 8;
     // x-sweep staging: L lines per block, one (line, segment) per thread
@@ -218,6 +240,9 @@ int setup(sscn_handle *h)
         h->W[0] = h->W[1] = h->W[2] = 0;
         h->nemit = kRedBlocks;
     }
+    h->fused_ok = p.dim == 2 && !h->exact && h->W[0] > 0 &&
+                  h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32);
+    h->ntiles = ((p.nx - 2) / kTile + 1) * ((p.ny - 2) / kTile + 1);
     return 0;
 }
 
@@ -385,6 +410,163 @@ void launch_norm(sscn_handle *h, hipStream_t st)
                        h->partials);
 }
 
+#define SSCN_W_SWITCH_FUSED(R, Wv, CALL)                                                                   \
+    switch (Wv) {                                                                                            \
+    case 4: CALL(4); break;                                                                                  \
+    case 6: CALL(6); break;                                                                                  \
+    case 8: CALL(8); break;                                                                                  \
+    case 10: CALL(10); break;                                                                                \
+    case 12: CALL(12); break;                                                                                \
+    case 16: CALL(16); break;                                                                                \
+    default: CALL(20); break;                                                                                \
+    }
+
+template <class R, int W, bool RT>
+void go_fused(const sscn_handle *h, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
+{
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTile, kTile>();
+    hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTile, kTile, RT>), dim3(h->ntiles), dim3(256), lds, st, h->d_inst,
+                       h->d_work, h->d_nwork, parity, pin, pout, use_pin);
+}
+
+template <class R, bool RT>
+void launch_fused(const sscn_handle *h, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
+{
+#define SSCN_CALL_F(Wc) go_fused<R, Wc, RT>(h, parity, pin, pout, use_pin, st)
+    if constexpr (std::is_same<R, float>::value) {
+        if (h->W[0] > 20) {
+            if (h->W[0] <= 24)
+                go_fused<R, 24, RT>(h, parity, pin, pout, use_pin, st);
+            else
+                go_fused<R, 32, RT>(h, parity, pin, pout, use_pin, st);
+            return;
+        }
+    }
+    SSCN_W_SWITCH_FUSED(R, h->W[0], SSCN_CALL_F)
+#undef SSCN_CALL_F
+}
+
+template <class R, int W, bool RT>
+hipError_t allow_fused_lds()
+{
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTile, kTile>();
+    return hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTile, kTile, RT>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+template <class R>
+hipError_t allow_fused_lds_all(int W)
+{
+    hipError_t e = hipSuccess;
+#define SSCN_ALLOW(Wc)                                         \
+    do {                                                       \
+        e = allow_fused_lds<R, Wc, false>();                   \
+        if (e == hipSuccess)                                   \
+            e = allow_fused_lds<R, Wc, true>();                \
+    } while (0)
+    if constexpr (std::is_same<R, float>::value) {
+        if (W > 20) {
+            if (W <= 24)
+                SSCN_ALLOW(24);
+            else
+                SSCN_ALLOW(32);
+            return e;
+        }
+    }
+    SSCN_W_SWITCH_FUSED(R, W, SSCN_ALLOW)
+#undef SSCN_ALLOW
+    return e;
+}
+
+// n fused steps (state ping-pongs between psi and work), ending with the
+// state in psi, normalised in imaginary time.
+template <class R>
+void enqueue_fused(sscn_handle *h, int64_t n, hipStream_t st, hipEvent_t *ev = nullptr)
+{
+    const bool imag = h->p.mode == SSCN_IMAG;
+    double *fp[2] = {h->partials, h->partials2};
+    for (int64_t s = 0; s < n; ++s) {
+        if (ev)
+            (void)hipEventRecord(ev[4 * s], st);
+        if (imag)
+            launch_fused<R, false>(h, h->fparity, fp[h->pbuf], fp[h->pbuf ^ 1], h->pending ? 1 : 0, st);
+        else
+            launch_fused<R, true>(h, h->fparity, nullptr, nullptr, 0, st);
+        if (ev)
+            for (int t = 1; t < 4; ++t)
+                (void)hipEventRecord(ev[4 * s + t], st);
+        h->fparity ^= 1;
+        if (imag) {
+            h->pbuf ^= 1;
+            h->pending = true;
+        }
+    }
+    void *bufs[2] = {h->psi, h->work};
+    const int nb = red_blocks(h->npts);
+    if (imag && h->pending) {
+        hipLaunchKernelGGL((k_rescale<R>), dim3(nb), dim3(256), 0, st, (const V<R> *)bufs[h->fparity],
+                           (V<R> *)h->psi, h->npts, h->args.dV, fp[h->pbuf], h->ntiles);
+        h->pending = false;
+    } else if (h->fparity == 1) {
+        hipLaunchKernelGGL((k_copy<R>), dim3(nb), dim3(256), 0, st, (const V<R> *)h->work, (V<R> *)h->psi,
+                           h->npts);
+    }
+    h->fparity = 0;
+}
+
+int setup_fused(sscn_handle *h)
+{
+    if (!h->fused_ok)
+        return 0;
+    const sscn_params &p = h->p;
+    Inst2D in{};
+    in.nx = p.nx;
+    in.ny = p.ny;
+    in.tiles_x = (p.nx - 2) / kTile + 1;
+    in.tiles_y = (p.ny - 2) / kTile + 1;
+    in.poff = 0;
+    in.active = 1;
+    in.hx = p.hx;
+    in.hy = p.hy;
+    in.x0 = h->args.x0;
+    in.y0 = h->args.y0;
+    in.vx = h->args.vx;
+    in.vy = h->args.vy;
+    in.g = p.g;
+    in.omega = p.omega;
+    in.dt = p.dt;
+    in.dV = h->args.dV;
+    in.ax[0] = h->args.ax[0];
+    in.ax[1] = h->args.ax[1];
+    in.buf[0] = h->psi;
+    in.buf[1] = h->work;
+    in.tab[0] = h->tab[0];
+    in.tab[1] = h->tab[1];
+    std::vector<int2> wl(h->ntiles);
+    for (int t = 0; t < h->ntiles; ++t)
+        wl[t] = int2{0, t};
+    if (!h->d_inst && (hipMalloc(&h->d_inst, sizeof(Inst2D)) != hipSuccess ||
+                       hipMalloc(&h->d_nwork, sizeof(int)) != hipSuccess))
+        return fail(SSCN_ENOMEM, "hipMalloc of the fused-step descriptors failed");
+    if (h->d_work)
+        (void)hipFree(h->d_work);
+    if (h->partials2)
+        (void)hipFree(h->partials2);
+    h->d_work = nullptr;
+    h->partials2 = nullptr;
+    if (hipMalloc(&h->d_work, sizeof(int2) * wl.size()) != hipSuccess ||
+        hipMalloc(&h->partials2, sizeof(double) * std::max(h->ntiles, kRedBlocks)) != hipSuccess)
+        return fail(SSCN_ENOMEM, "hipMalloc of the fused-step work list failed");
+    HIPCHECK(hipMemcpy(h->d_inst, &in, sizeof in, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->d_work, wl.data(), sizeof(int2) * wl.size(), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(h->d_nwork, &h->ntiles, sizeof(int), hipMemcpyHostToDevice));
+    hipError_t e = p.precision == SSCN_C128 ? allow_fused_lds_all<double>(h->W[0])
+                                            : allow_fused_lds_all<float>(h->W[0]);
+    if (e != hipSuccess)
+        return fail(SSCN_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    return 0;
+}
+
 // One SSCN step on stream st.  npart > 0: the partials hold the norm of the
 // (unnormalised) state and the rescale is folded into H1.  ev (optional, 4
 // events) is recorded before the x-, y-, z-sweeps and after the step.
@@ -460,6 +642,10 @@ void enqueue_one(sscn_handle *h, int npart, hipStream_t st, hipEvent_t *ev = nul
 template <class R>
 void enqueue_direct(sscn_handle *h, int64_t n, hipStream_t st)
 {
+    if (h->active_plan == SSCN_PLAN_FUSED) {
+        enqueue_fused<R>(h, n, st);
+        return;
+    }
     const bool imag = h->p.mode == SSCN_IMAG;
     for (int64_t s = 0; s < n; ++s) {
         enqueue_one<R>(h, (imag && h->pending) ? h->nemit : 0, st);
@@ -505,6 +691,82 @@ void drop_graph(sscn_handle *h)
         (void)hipGraphDestroy(h->graph);
     h->gexec = nullptr;
     h->graph = nullptr;
+}
+
+// Autotuner: on the first step of a handle whose plan is SSCN_PLAN_AUTO,
+// time every plan available for the problem (separate sweeps; fused 2D
+// step) over a few steps from a saved copy of the state, restore the state,
+// and keep the fastest.  Results are cached per process, keyed by the shape,
+// precision, mode and window.
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int, int, int, int>, int> g_tune_cache;
+
+template <class R>
+float time_plan(sscn_handle *h, int plan, const void *saved, int nsteps)
+{
+    const size_t bytes = (size_t)h->npts * h->esize;
+    h->active_plan = plan;
+    enqueue_direct<R>(h, 2, h->stream);
+    (void)hipMemcpyAsync(h->psi, saved, bytes, hipMemcpyDeviceToDevice, h->stream);
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    (void)hipEventRecord(e0, h->stream);
+    enqueue_direct<R>(h, nsteps, h->stream);
+    (void)hipEventRecord(e1, h->stream);
+    (void)hipEventSynchronize(e1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipMemcpyAsync(h->psi, saved, bytes, hipMemcpyDeviceToDevice, h->stream);
+    return ms;
+}
+
+int autotune(sscn_handle *h)
+{
+    if (h->plan != SSCN_PLAN_AUTO)
+        return 0;
+    h->plan = SSCN_PLAN_SWEEPS;  // resolved below
+    if (!h->fused_ok) {
+        h->active_plan = SSCN_PLAN_SWEEPS;
+        return 0;
+    }
+    const sscn_params &p = h->p;
+    const auto key = std::make_tuple(p.dim, p.nx, p.ny, p.nz, p.precision, p.mode, h->W[0]);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            h->active_plan = h->plan = it->second;
+            return 0;
+        }
+    }
+    void *saved = nullptr;
+    const size_t bytes = (size_t)h->npts * h->esize;
+    if (hipMalloc(&saved, bytes) != hipSuccess)
+        return fail(SSCN_ENOMEM, "hipMalloc of the autotune copy failed");
+    HIPCHECK(hipMemcpyAsync(saved, h->psi, bytes, hipMemcpyDeviceToDevice, h->stream));
+    const int plans[2] = {SSCN_PLAN_SWEEPS, SSCN_PLAN_FUSED};
+    int best = SSCN_PLAN_SWEEPS;
+    float best_ms = 0.f;
+    for (int k = 0; k < 2; ++k) {
+        const float ms = p.precision == SSCN_C128 ? time_plan<double>(h, plans[k], saved, 16)
+                                                  : time_plan<float>(h, plans[k], saved, 16);
+        h->tune_ms[plans[k]] = ms;
+        if (k == 0 || ms < best_ms) {
+            best = plans[k];
+            best_ms = ms;
+        }
+    }
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    (void)hipFree(saved);
+    h->pending = false;
+    h->fparity = 0;
+    h->active_plan = h->plan = best;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = best;
+    return 0;
 }
 
 int alloc_buffers(sscn_handle *h)
@@ -588,13 +850,23 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
     r = build_tables(h);
     if (r)
         return bail(r);
-    const size_t npart = std::max<size_t>((size_t)h->nemit, (size_t)kRedBlocks);
+    const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, (size_t)h->ntiles});
     if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_part, (size_t)kRedBlocks * 14 * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_buf, 64 * sizeof(double)) != hipSuccess)
         return bail(fail(SSCN_ENOMEM, "hipMalloc of reduction buffers failed"));
     if (hipMemsetAsync(h->partials, 0, npart * sizeof(double), h->stream) != hipSuccess)
         return bail(fail(SSCN_EHIP, "hipMemsetAsync failed"));
+    r = setup_fused(h);
+    if (r)
+        return bail(r);
+    if (const char *env = std::getenv("SSCN_PLAN")) {
+        if (!std::strcmp(env, "sweeps"))
+            h->plan = SSCN_PLAN_SWEEPS;
+        else if (!std::strcmp(env, "fused") && h->fused_ok)
+            h->plan = SSCN_PLAN_FUSED;
+    }
+    h->active_plan = h->plan == SSCN_PLAN_FUSED ? SSCN_PLAN_FUSED : SSCN_PLAN_SWEEPS;
     *out = h;
     return 0;
 }
@@ -609,6 +881,14 @@ void sscn_destroy(sscn_handle *h)
     for (int ax = 0; ax < 3; ++ax)
         if (h->tab[ax])
             (void)hipFree(h->tab[ax]);
+    if (h->d_inst)
+        (void)hipFree(h->d_inst);
+    if (h->d_work)
+        (void)hipFree(h->d_work);
+    if (h->d_nwork)
+        (void)hipFree(h->d_nwork);
+    if (h->partials2)
+        (void)hipFree(h->partials2);
     if (h->partials)
         (void)hipFree(h->partials);
     if (h->obs_part)
@@ -667,6 +947,9 @@ int sscn_step(sscn_handle *h, int64_t nsteps)
         return fail(SSCN_EINVAL, "bad step arguments");
     if (nsteps == 0)
         return 0;
+    int r0 = autotune(h);
+    if (r0)
+        return r0;
     int64_t rem = nsteps;
     if (nsteps >= kGraphSteps && !h->pending) {
         int r = build_graph(h);
@@ -805,9 +1088,16 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
         return r;
     // the partials buffer must hold the new emit count
     (void)hipFree(h->partials);
-    const size_t npart = std::max<size_t>((size_t)h->nemit, (size_t)kRedBlocks);
+    const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, (size_t)h->ntiles});
     if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess)
         return fail(SSCN_ENOMEM, "hipMalloc of the partials failed");
+    r = setup_fused(h);
+    if (r)
+        return r;
+    if (h->plan == SSCN_PLAN_FUSED && !h->fused_ok)
+        h->plan = SSCN_PLAN_AUTO;
+    h->active_plan = h->plan == SSCN_PLAN_FUSED ? SSCN_PLAN_FUSED : SSCN_PLAN_SWEEPS;
+    h->fparity = 0;
     h->steps = steps;
     h->pending = false;
     HIPCHECK(hipStreamSynchronize(h->stream));
@@ -851,6 +1141,9 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out)
 {
     if (!h || !ms_out || nsteps < 1 || nsteps > 100000)
         return fail(SSCN_EINVAL, "bad profile_step arguments");
+    int rt = autotune(h);
+    if (rt)
+        return rt;
     const bool imag = h->p.mode == SSCN_IMAG;
     std::vector<hipEvent_t> ev((size_t)nsteps * 4, nullptr);
     int rc = 0;
@@ -859,7 +1152,15 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out)
             rc = fail(SSCN_EHIP, "hipEventCreate failed");
             break;
         }
-    if (!rc) {
+    if (!rc && h->active_plan == SSCN_PLAN_FUSED) {
+        if (h->p.precision == SSCN_C128)
+            enqueue_fused<double>(h, nsteps, h->stream, ev.data());
+        else
+            enqueue_fused<float>(h, nsteps, h->stream, ev.data());
+        h->steps += nsteps;
+        if (hipStreamSynchronize(h->stream) != hipSuccess)
+            rc = fail(SSCN_EHIP, "hipStreamSynchronize failed");
+    } else if (!rc) {
         for (int64_t s = 0; s < nsteps; ++s) {
             const int npart = (imag && h->pending) ? h->nemit : 0;
             if (h->p.precision == SSCN_C128)
@@ -899,6 +1200,8 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out)
             ms_out[t] = acc[t] / (double)nsteps;
         if (h->p.dim == 2 && !h->exact)
             ms_out[2] = 0.0;
+        if (h->active_plan == SSCN_PLAN_FUSED)
+            ms_out[1] = ms_out[2] = 0.0;
     }
     for (auto &e : ev)
         if (e)
@@ -906,10 +1209,25 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out)
     return rc;
 }
 
-int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz)
+int sscn_set_plan(sscn_handle *h, int plan)
+{
+    if (!h || plan < SSCN_PLAN_AUTO || plan > SSCN_PLAN_FUSED)
+        return fail(SSCN_EINVAL, "bad plan");
+    if (plan == SSCN_PLAN_FUSED && !h->fused_ok)
+        return fail(SSCN_EINVAL, "the fused 2D step is not available for this problem");
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    drop_graph(h);
+    h->plan = plan;
+    h->active_plan = plan == SSCN_PLAN_FUSED ? SSCN_PLAN_FUSED : SSCN_PLAN_SWEEPS;
+    return 0;
+}
+
+int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *plan)
 {
     if (!h)
         return fail(SSCN_EINVAL, "null argument");
+    if (plan)
+        *plan = h->plan == SSCN_PLAN_AUTO ? SSCN_PLAN_AUTO : h->active_plan;
     for (int a = 0; a < 3; ++a) {
         if (window_xyz)
             window_xyz[a] = h->exact ? 0 : h->W[a];

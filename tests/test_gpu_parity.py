@@ -288,3 +288,49 @@ def test_precision_upcast(P):
     op = O.make_params(**W.solver_params(cfg, precision=0))
     assert rel(s.get_state(), O.step(op, mid, 200)) <= TOL64
     s.close()
+
+
+# --------------------------------------------------------------------------
+# Both step plans (separate sweeps; fused 2D tiles) against the oracle.
+
+@pytest.mark.parametrize("plan", [1, 2])
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("prec,shape", [(0, (100, 77)), (0, (130, 47)), (1, (96, 70)), (0, (33, 200))])
+def test_plans_2d(P, plan, mode, prec, shape):
+    nx, ny = shape
+    announce(f"plan={plan} mode={mode} prec={prec} shape={shape}")
+    cfg = dict(dim=2, nx=nx, ny=ny, nz=1, hx=0.11, hy=0.09, hz=0.1, gamma=1.0, nu=1.1,
+               lam=1.0, g=60.0, omega=0.55, dt=2e-3, mode=mode, precision=prec)
+    s, op = both(P, cfg)
+    s.set_plan(plan)
+    psi0 = W.random_field(21, (ny, nx)) / np.sqrt(0.11 * 0.09)
+    s.set_state(psi0)
+    s.step(131)  # odd: exercises the buffer hand-back
+    assert s.solver_info()["plan"] == plan
+    ref = O.step(op, psi0, 131)
+    got = s.get_state().astype(np.complex128)
+    assert rel(got, ref) <= (TOL64 if prec == 0 else TOL32)
+    s.close()
+
+
+@pytest.mark.parametrize("plan", [1, 2])
+def test_plans_config2_full_size(P, plan):
+    cfg = W.CONFIGS["c2"]
+    announce(f"c2 full size plan={plan}")
+    s, op = both(P, cfg)
+    s.set_plan(plan)
+    ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
+    s.init_state(1, ph, 1.0)
+    s.step(70)
+    ref = O.step(op, O.init_state(op, 1, ph, 1.0), 70)
+    assert rel(s.get_state(), ref) <= TOL64
+    s.close()
+
+
+def test_fused_plan_rejected_in_3d(P):
+    cfg = dict(dim=3, nx=20, ny=20, nz=20, hx=0.2, hy=0.2, hz=0.2, gamma=1.0, nu=1.0, lam=2.0,
+               g=10.0, omega=0.3, dt=1e-3, mode=0, precision=0)
+    s = P.Solver(cfg)
+    with pytest.raises(P.SSCNError):
+        s.set_plan(2)
+    s.close()
