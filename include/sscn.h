@@ -169,6 +169,49 @@ int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *pla
 
 void sscn_destroy(sscn_handle *h);
 
+/* ---------------------------------------------------------------------------
+ * Batched 2D instances: n problems of different grid sizes and parameters
+ * advanced together, one fused launch per step over all their 32 x 32 tiles
+ * (the SSCN_PLAN_FUSED step with a work list), HIP-graph replayed, with the
+ * convergence test done on the device and converged instances dropped from
+ * the work list.  Every params[k] must be 2D with a common precision and
+ * mode; the window (rows of look-ahead) is the largest any instance needs.
+ * psi_devs[k] is instance k's caller-owned state buffer (layout as above),
+ * borrowed until sscn_batch_destroy; the library owns one work buffer per
+ * instance.  All work goes to hip_stream. */
+typedef struct sscn_batch sscn_batch;
+
+int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, void *hip_stream,
+                    sscn_batch **out);
+
+/* Initial state of Eq. (fun) for instance k (2D form of sscn_init_state).
+ * Synchronises the stream. */
+int sscn_batch_init_state(sscn_batch *b, int k, int kind, const double *phase_host, double d_xy);
+
+/* Enqueue nsteps steps of every active instance; each state is left
+ * normalised (imaginary time) in its buffer.  Asynchronous. */
+int sscn_batch_step(sscn_batch *b, int64_t nsteps);
+
+/* Observables of all n instances into out[0..n-1] (out[k].step: the step at
+ * which instance k converged, else the batch step count).  Synchronises. */
+int sscn_batch_observables(sscn_batch *b, sscn_obs *out);
+
+/* Imaginary-time run to convergence: replay check_every (rounded up to even)
+ * steps, evaluate mu of every active instance on the device, and flag an
+ * instance converged when |mu - mu_prev| < tol_dmu at two consecutive checks;
+ * flagged instances leave the work list.  Stops when all have converged or
+ * max_steps steps were taken.  steps_out[k] (may be NULL): the batch step
+ * count at instance k's convergence, or -1.  Synchronises at every check. */
+int sscn_batch_run(sscn_batch *b, int64_t max_steps, int check_every, double tol_dmu, int64_t *steps_out);
+
+/* Make every instance active again and clear the convergence state. */
+int sscn_batch_reset(sscn_batch *b);
+
+/* Copy instance k's state to a host buffer.  Synchronises the stream. */
+int sscn_batch_get_state(sscn_batch *b, int k, void *host_psi);
+
+void sscn_batch_destroy(sscn_batch *b);
+
 const char *sscn_strerror(int code);
 const char *sscn_last_error(void);
 

@@ -24,7 +24,9 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
 EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
-           "sscn_solver_info",
+           "sscn_solver_info", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
+           "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
+           "sscn_batch_destroy",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -75,6 +77,16 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int)]
         L.sscn_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+        L.sscn_batch_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(vp), vp,
+                                      ctypes.POINTER(vp)]
+        L.sscn_batch_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double]
+        L.sscn_batch_step.argtypes = [vp, i64]
+        L.sscn_batch_observables.argtypes = [vp, ctypes.POINTER(Obs)]
+        L.sscn_batch_run.argtypes = [vp, i64, ctypes.c_int, ctypes.c_double, ctypes.POINTER(i64)]
+        L.sscn_batch_reset.argtypes = [vp]
+        L.sscn_batch_get_state.argtypes = [vp, ctypes.c_int, vp]
+        L.sscn_batch_destroy.argtypes = [vp]
+        L.sscn_batch_destroy.restype = None
         L.sscn_destroy.argtypes = [vp]
         L.sscn_destroy.restype = None
         L.sscn_strerror.argtypes = [ctypes.c_int]
@@ -212,6 +224,77 @@ class Solver:
     def close(self):
         if getattr(self, "_h", None):
             lib().sscn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """n 2D instances advanced together by the fused step (include/sscn.h,
+    sscn_batch_*).  State tensors are allocated here (torch, one per
+    instance) and borrowed by the library."""
+
+    def __init__(self, params_list, stream=None):
+        import torch
+        self._torch = torch
+        ps = [p if isinstance(p, Params) else make_params(**p) for p in params_list]
+        self.params = ps
+        n = len(ps)
+        arr = (Params * n)(*ps)
+        dtype = torch.complex128 if ps[0].precision == SSCN_C128 else torch.complex64
+        self.psi = [torch.zeros((p.ny, p.nx), dtype=dtype, device="cuda") for p in ps]
+        ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.psi])
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = ctypes.c_void_p()
+        _check(lib().sscn_batch_init(arr, n, ptrs, ctypes.c_void_p(self.stream.cuda_stream),
+                                     ctypes.byref(h)))
+        self._h = h
+        self.n = n
+
+    def init_state(self, k, kind=1, phase=None, d_xy=1.0):
+        ph = None
+        if phase is not None:
+            ph = np.ascontiguousarray(phase, dtype=np.float64)
+            if ph.shape != (self.params[k].ny, self.params[k].nx):
+                raise ValueError("phase must have shape (ny, nx)")
+        _check(lib().sscn_batch_init_state(self._h, int(k), int(kind),
+                                           ph.ctypes.data if ph is not None else None, float(d_xy)))
+
+    def step(self, n=1):
+        _check(lib().sscn_batch_step(self._h, int(n)))
+
+    def run(self, max_steps, check_every=100, tol=1e-8):
+        out = (ctypes.c_int64 * self.n)()
+        _check(lib().sscn_batch_run(self._h, int(max_steps), int(check_every), float(tol), out))
+        return [int(v) for v in out]
+
+    def reset(self):
+        _check(lib().sscn_batch_reset(self._h))
+
+    def observables(self):
+        out = (Obs * self.n)()
+        _check(lib().sscn_batch_observables(self._h, out))
+        res = []
+        for o in out:
+            d = {k: getattr(o, k) for k in OBS_KEYS}
+            d["step"] = int(o.step)
+            res.append(d)
+        return res
+
+    def get_state(self, k):
+        p = self.params[k]
+        dtype = np.complex128 if p.precision == SSCN_C128 else np.complex64
+        out = np.empty((p.ny, p.nx), dtype=dtype)
+        _check(lib().sscn_batch_get_state(self._h, int(k), out.ctypes.data))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().sscn_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -220,6 +220,42 @@ __device__ __forceinline__ double block_max_256(double v, double *red)
     return r;
 }
 
+// Deterministic block sum over NT threads (NT/64 waves), valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum_nt(double v, double *red)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        v += __shfl_xor(v, off, 64);
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    __syncthreads();
+    if ((tid & 63) == 0)
+        red[tid >> 6] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (tid == 0)
+        for (int w = 0; w < NT / 64; ++w)
+            r += red[w];
+    return r;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum_partials_nt(const double *part, int npart, double *red)
+{
+    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
+    double v = 0.0;
+    for (int t = tid; t < npart; t += NT)
+        v += part[t];
+    double r = block_sum_nt<NT>(v, red);
+    __syncthreads();
+    if (tid == 0)
+        red[16] = r;
+    __syncthreads();
+    r = red[16];
+    __syncthreads();
+    return r;
+}
+
 // Sum of npart FP64 partials by a 256-thread block, in a fixed order; every
 // block that calls this gets the same bits.  Result broadcast to all threads.
 __device__ __forceinline__ double block_sum_partials(const double *part, int npart, double *red)
@@ -577,25 +613,25 @@ constexpr size_t step2d_lds_bytes()
     return (size_t)(TR + 2 * W + 2) * (stage_stride(TC + 2 * W + 2, S) + TC + 1) * sizeof(Cx<R>);
 }
 
-template <class R, int S, int W, int TR, int TC, bool RT>
-__global__ __launch_bounds__(256) void k_step2d(const Inst2D *__restrict__ insts, const int2 *__restrict__ work,
-                                                const int *__restrict__ nwork, int parity,
-                                                const double *__restrict__ pin, double *__restrict__ pout,
-                                                int use_pin)
+template <class R, int S, int W, int TR, int TC, int NT, bool RT>
+__global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts, const int2 *__restrict__ work,
+                                               const int *__restrict__ nwork, int parity,
+                                               const double *__restrict__ pin, double *__restrict__ pout,
+                                               int use_pin)
 {
     constexpr int H = W + 1;
     constexpr int SR = TR + 2 * H, SC = TC + 2 * H;
     constexpr int SCP = stage_stride(SC, S);
     constexpr int C2 = TC + 1;
-    constexpr int NST = (SR * SC + 255) / 256;
+    constexpr int NST = (SR * SC + NT - 1) / NT;
     constexpr int NSX = TC / S, NSY = TR / S;
-    static_assert(TC % S == 0 && TR % S == 0 && TC * NSY <= 256, "tile shape");
+    static_assert(TC % S == 0 && TR % S == 0 && TC * NSY <= NT, "tile shape");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<R> *st1 = reinterpret_cast<Cx<R> *>(smem_raw);  // SR x SCP staged, H1 applied
     Cx<R> *st2 = st1 + SR * SCP;                         // SR x C2 after the x-solve
     __shared__ Cx<R> d1x[SR];
     __shared__ Cx<R> d1y[TC];
-    __shared__ double red[8];
+    __shared__ double red[20];
     const int tid = threadIdx.x;
     const int nw = *nwork;
     for (int it = blockIdx.x; it < nw; it += gridDim.x) {
@@ -614,7 +650,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Inst2D *__restrict__ insts
         Cx<R> pre[NST];
 #pragma unroll
         for (int c = 0; c < NST; ++c) {
-            const int e = tid + c * 256;
+            const int e = tid + c * NT;
             const int rr = e / SC, cc = e - rr * SC;
             const int j = jb + rr, i = ib + cc;
             pre[c] = Cx<R>{R(0), R(0)};
@@ -623,11 +659,11 @@ __global__ __launch_bounds__(256) void k_step2d(const Inst2D *__restrict__ insts
         }
         double sm1 = 0.0;
         if (!RT && use_pin)
-            sm1 = 1.0 / sqrt(I.dV * block_sum_partials(pin + I.poff, I.tiles_x * I.tiles_y, red)) - 1.0;
+            sm1 = 1.0 / sqrt(I.dV * block_sum_partials_nt<NT>(pin + I.poff, I.tiles_x * I.tiles_y, red)) - 1.0;
         const R sr = R(sm1);
 #pragma unroll
         for (int c = 0; c < NST; ++c) {
-            const int e = tid + c * 256;
+            const int e = tid + c * NT;
             if (e < SR * SC) {
                 const int rr = e / SC, cc = e - rr * SC;
                 const int j = jb + rr, i = ib + cc;
@@ -644,7 +680,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Inst2D *__restrict__ insts
         __syncthreads();
 
         // x-lines of every staged row, outputs for the TC tile columns
-        for (int p = tid; p < SR * NSX; p += 256) {
+        for (int p = tid; p < SR * NSX; p += NT) {
             const int rr = p / NSX, q = p - rr * NSX;
             const int j = jb + rr;
             Cx<R> io[S];
@@ -676,7 +712,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Inst2D *__restrict__ insts
         }
         __syncthreads();
         if (c0 == 1) {  // wall rows of the x-lines: Sherman-Morrison term
-            for (int p = tid; p < SR * W; p += 256) {
+            for (int p = tid; p < SR * W; p += NT) {
                 const int rr = p / W, u = 1 + (p - rr * W);
                 const int j = jb + rr;
                 if (j >= 1 && j <= ny - 1 && u <= nx - 1 && u - c0 < TC)
@@ -722,7 +758,7 @@ __global__ __launch_bounds__(256) void k_step2d(const Inst2D *__restrict__ insts
             }
         }
         if (!RT) {
-            const double b = block_sum_256(acc, red);
+            const double b = block_sum_nt<NT>(acc, red);
             if (tid == 0)
                 pout[I.poff + wk.y] = b;
         }
@@ -929,6 +965,60 @@ __device__ __forceinline__ Cx<double> at(const typename Vec<R>::T *psi, const St
     return Cx<double>{(double)v.re, (double)v.im};
 }
 
+// The 13 sums and the max of the observables at grid point p (see sscn_obs).
+template <class R>
+__device__ __forceinline__ void obs_point(const typename Vec<R>::T *psi, const StepArgs &a, int64_t p, double (&s)[14])
+{
+    const int i = (int)(p % a.nx);
+    const int64_t rest = p / a.nx;
+    const int j = (int)(rest % a.ny), k = (int)(rest / a.ny);
+    const double x = a.x0 + i * a.hx, y = a.y0 + j * a.hy;
+    const double z = a.dim == 3 ? a.z0 + k * a.hz : 0.0;
+    const Cx<double> v = at<R>(psi, a, i, j, k);
+    const double dens = v.re * v.re + v.im * v.im;
+    double V = a.vx * x * x + a.vy * y * y;
+    if (a.dim == 3)
+        V += a.vz * z * z;
+    const Cx<double> xp = at<R>(psi, a, i + 1, j, k), xm = at<R>(psi, a, i - 1, j, k);
+    const Cx<double> yp = at<R>(psi, a, i, j + 1, k), ym = at<R>(psi, a, i, j - 1, k);
+    const Cx<double> fx = (1.0 / a.hx) * (xp - v), fy = (1.0 / a.hy) * (yp - v);
+    Cx<double> fz = {0.0, 0.0};
+    if (a.dim == 3)
+        fz = (1.0 / a.hz) * (at<R>(psi, a, i, j, k + 1) - v);
+    const double kin_r = fx.re * fx.re + fy.re * fy.re + fz.re * fz.re;
+    const double kin = norm2(fx) + norm2(fy) + norm2(fz);
+    const Cx<double> cxd = (1.0 / (2.0 * a.hx)) * (xp - xm), cyd = (1.0 / (2.0 * a.hy)) * (yp - ym);
+    const Cx<double> lz = y * cxd - x * cyd;  // (y d/dx - x d/dy) psi
+    s[0] += dens;
+    s[1] += v.re * v.re;
+    s[2] += 0.5 * kin_r;
+    s[3] += V * v.re * v.re;
+    s[4] += a.g * dens * v.re * v.re;
+    s[5] += a.omega * v.re * lz.im;
+    s[6] += 0.5 * kin;
+    s[7] += V * dens;
+    s[8] += a.g * dens * dens;
+    s[9] += a.omega * (v.re * lz.im - v.im * lz.re);  // Im(conj(v) lz)
+    s[10] += x * x * dens;
+    s[11] += y * y * dens;
+    s[12] += z * z * dens;
+    s[13] = fmax(s[13], dens);
+}
+
+template <class R>
+__device__ __forceinline__ void obs_block_write(double (&s)[14], double *red, double *out)
+{
+#pragma unroll
+    for (int t = 0; t < 13; ++t) {
+        const double b = block_sum_256(s[t], red);
+        if (threadIdx.x == 0)
+            out[t] = b;
+    }
+    const double m = block_max_256(s[13], red);
+    if (threadIdx.x == 0)
+        out[13] = m;
+}
+
 template <class R>
 __global__ __launch_bounds__(256) void k_observables(const typename Vec<R>::T *psi, StepArgs a, double *partials)
 {
@@ -938,51 +1028,9 @@ __global__ __launch_bounds__(256) void k_observables(const typename Vec<R>::T *p
 #pragma unroll
     for (int t = 0; t < 14; ++t)
         s[t] = 0.0;
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
-        const int i = (int)(p % a.nx);
-        const int64_t rest = p / a.nx;
-        const int j = (int)(rest % a.ny), k = (int)(rest / a.ny);
-        const double x = a.x0 + i * a.hx, y = a.y0 + j * a.hy;
-        const double z = a.dim == 3 ? a.z0 + k * a.hz : 0.0;
-        const Cx<double> v = at<R>(psi, a, i, j, k);
-        const double dens = v.re * v.re + v.im * v.im;
-        double V = a.vx * x * x + a.vy * y * y;
-        if (a.dim == 3)
-            V += a.vz * z * z;
-        const Cx<double> xp = at<R>(psi, a, i + 1, j, k), xm = at<R>(psi, a, i - 1, j, k);
-        const Cx<double> yp = at<R>(psi, a, i, j + 1, k), ym = at<R>(psi, a, i, j - 1, k);
-        const Cx<double> fx = (1.0 / a.hx) * (xp - v), fy = (1.0 / a.hy) * (yp - v);
-        Cx<double> fz = {0.0, 0.0};
-        if (a.dim == 3)
-            fz = (1.0 / a.hz) * (at<R>(psi, a, i, j, k + 1) - v);
-        const double kin_r = fx.re * fx.re + fy.re * fy.re + fz.re * fz.re;
-        const double kin = norm2(fx) + norm2(fy) + norm2(fz);
-        const Cx<double> cxd = (1.0 / (2.0 * a.hx)) * (xp - xm), cyd = (1.0 / (2.0 * a.hy)) * (yp - ym);
-        const Cx<double> lz = y * cxd - x * cyd;  // (y d/dx - x d/dy) psi
-        s[0] += dens;
-        s[1] += v.re * v.re;
-        s[2] += 0.5 * kin_r;
-        s[3] += V * v.re * v.re;
-        s[4] += a.g * dens * v.re * v.re;
-        s[5] += a.omega * v.re * lz.im;
-        s[6] += 0.5 * kin;
-        s[7] += V * dens;
-        s[8] += a.g * dens * dens;
-        s[9] += a.omega * (v.re * lz.im - v.im * lz.re);  // Im(conj(v) lz)
-        s[10] += x * x * dens;
-        s[11] += y * y * dens;
-        s[12] += z * z * dens;
-        s[13] = fmax(s[13], dens);
-    }
-#pragma unroll
-    for (int t = 0; t < 13; ++t) {
-        const double b = block_sum_256(s[t], red);
-        if (threadIdx.x == 0)
-            partials[(int64_t)blockIdx.x * 14 + t] = b;
-    }
-    const double m = block_max_256(s[13], red);
-    if (threadIdx.x == 0)
-        partials[(int64_t)blockIdx.x * 14 + 13] = m;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
+        obs_point<R>(psi, a, p, s);
+    obs_block_write<R>(s, red, partials + (int64_t)blockIdx.x * 14);
 }
 
 // Fixed-order final reduction of nblk rows of nval partials: values with
@@ -1063,6 +1111,144 @@ __global__ __launch_bounds__(256) void k_vortex(const typename Vec<R>::T *psi, S
     const double b = block_sum_256(cnt, red);
     if (threadIdx.x == 0)
         partials[blockIdx.x] = b;
+}
+
+// ---------------------------------------------------------------------------
+// Batched instances: per-instance chunks of kChunk points as work items.
+constexpr int kChunk = 4096;
+
+__device__ __forceinline__ StepArgs inst_args(const Inst2D &I)
+{
+    StepArgs a{};
+    a.dim = 2;
+    a.nx = I.nx;
+    a.ny = I.ny;
+    a.nz = 1;
+    a.hx = I.hx;
+    a.hy = I.hy;
+    a.hz = 1.0;
+    a.x0 = I.x0;
+    a.y0 = I.y0;
+    a.vx = I.vx;
+    a.vy = I.vy;
+    a.g = I.g;
+    a.omega = I.omega;
+    a.dt = I.dt;
+    a.dV = I.dV;
+    return a;
+}
+
+// End of a batched stepping call: for every listed (instance, chunk) item,
+// buf[0] = s buf[parity] with s = 1/sqrt(dV sum of the instance's partials)
+// (imaginary time, rescale = 1) or a plain copy (rescale = 0).
+template <class R>
+__global__ __launch_bounds__(256) void k_batch_finish(const Inst2D *__restrict__ insts, const int2 *__restrict__ fwork,
+                                                      const int *__restrict__ nf, int parity,
+                                                      const double *__restrict__ partials, int rescale_on)
+{
+    __shared__ double red[20];
+    const int nfw = *nf;
+    for (int it = blockIdx.x; it < nfw; it += gridDim.x) {
+        const int2 wk = fwork[it];
+        const Inst2D &I = insts[wk.x];
+        const int64_t n = (int64_t)I.nx * I.ny;
+        double sm1 = 0.0;
+        if (rescale_on)
+            sm1 = 1.0 / sqrt(I.dV * block_sum_partials_nt<256>(partials + I.poff, I.tiles_x * I.tiles_y, red)) - 1.0;
+        const R sr = R(sm1);
+        const typename Vec<R>::T *src = reinterpret_cast<const typename Vec<R>::T *>(I.buf[parity]);
+        typename Vec<R>::T *dst = reinterpret_cast<typename Vec<R>::T *>(I.buf[0]);
+        const int64_t base = (int64_t)wk.y * kChunk;
+        Cx<R> v[kChunk / 256];
+#pragma unroll
+        for (int c = 0; c < kChunk / 256; ++c) {
+            const int64_t p = base + threadIdx.x + c * 256;
+            v[c] = Cx<R>{R(0), R(0)};
+            if (p < n)
+                v[c] = ld<R>(src, p);
+        }
+#pragma unroll
+        for (int c = 0; c < kChunk / 256; ++c) {
+            const int64_t p = base + threadIdx.x + c * 256;
+            if (p < n)
+                st<R>(dst, p, rescale(v[c], sr));
+        }
+        __syncthreads();
+    }
+}
+
+// Observables of every listed (instance, chunk) item into opart[item * 14].
+template <class R>
+__global__ __launch_bounds__(256) void k_batch_obs(const Inst2D *__restrict__ insts, const int2 *__restrict__ owork,
+                                                   const int *__restrict__ no, double *__restrict__ opart)
+{
+    __shared__ double red[8];
+    const int now = *no;
+    for (int it = blockIdx.x; it < now; it += gridDim.x) {
+        const int2 wk = owork[it];
+        const Inst2D &I = insts[wk.x];
+        const StepArgs a = inst_args(I);
+        const typename Vec<R>::T *psi = reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]);
+        const int64_t n = (int64_t)I.nx * I.ny;
+        const int64_t base = (int64_t)wk.y * kChunk;
+        double s[14];
+#pragma unroll
+        for (int t = 0; t < 14; ++t)
+            s[t] = 0.0;
+        for (int c = threadIdx.x; c < kChunk; c += 256)
+            if (base + c < n)
+                obs_point<R>(psi, a, base + c, s);
+        obs_block_write<R>(s, red, opart + (int64_t)it * 14);
+        __syncthreads();
+    }
+}
+
+// Per instance (one block each): fixed-order sum of its items' partials
+// (items obase[k] .. obase[k] + ocount[k] - 1 of the current list; ocount 0
+// for instances not listed), then the convergence bookkeeping: mu of the
+// real-part form, hits counts consecutive checks with |mu - mu_prev| < tol,
+// and an instance is flagged converged (conv[k] = step) at two hits.
+__global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const int *__restrict__ obase,
+                                                         const int *__restrict__ ocount,
+                                                         const double *__restrict__ opart, double *__restrict__ sums,
+                                                         double *__restrict__ mu_prev, int *__restrict__ hits,
+                                                         long long *__restrict__ conv, double tol, long long step)
+{
+    __shared__ double red[8];
+    const int k = blockIdx.x;
+    if (k >= ninst)
+        return;
+    const int cnt = ocount[k], b0 = obase[k];
+    if (cnt == 0)
+        return;
+    double acc[14];
+    for (int v = 0; v < 14; ++v) {
+        const bool mx = v == 13;
+        double x = 0.0;
+        for (int b = threadIdx.x; b < cnt; b += 256) {
+            const double y = opart[(int64_t)(b0 + b) * 14 + v];
+            x = mx ? fmax(x, y) : x + y;
+        }
+        acc[v] = mx ? block_max_256(x, red) : block_sum_256(x, red);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        for (int v = 0; v < 14; ++v)
+            sums[(int64_t)k * 14 + v] = acc[v];
+        if (tol > 0.0) {  // a convergence check (tol <= 0: observables only)
+            const double mu = (acc[2] + acc[3] + acc[4] + acc[5]) / acc[1];
+            const double prev = mu_prev[k];
+            if (conv[k] < 0) {
+                if (prev == prev && fabs(mu - prev) < tol)
+                    hits[k] += 1;
+                else
+                    hits[k] = 0;
+                if (hits[k] >= 2)
+                    conv[k] = step;
+            }
+            mu_prev[k] = mu;
+        }
+    }
 }
 
 }  // namespace sscn

@@ -41,7 +41,18 @@ int fail(int code, const std::string &msg)
 constexpr int kSeg = 8;             // outputs per thread segment (all axes)
 constexpr int kGraphSteps = 64;     // steps per captured graph
 constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
-constexpr int kTile = 32;           // fused 2D step: output tile side
+#ifndef SSCN_TILE_R
+#define SSCN_TILE_R 32
+#endif
+#ifndef SSCN_TILE_C
+#define SSCN_TILE_C 32
+#endif
+#ifndef SSCN_TILE_NT
+#define SSCN_TILE_NT 256
+#endif
+constexpr int kTileR = SSCN_TILE_R;   // fused 2D step: output tile rows (y)
+constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
+constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
 constexpr size_t kXLdsCap = 64 * 1024;
 
 // Supported window sizes (template instantiations).
@@ -240,9 +251,11 @@ int setup(sscn_handle *h)
         h->W[0] = h->W[1] = h->W[2] = 0;
         h->nemit = kRedBlocks;
     }
+    const size_t flds = (size_t)(kTileR + 2 * h->W[0] + 2) *
+                        (stage_stride(kTileC + 2 * h->W[0] + 2, kSeg) + kTileC + 1) * h->esize;
     h->fused_ok = p.dim == 2 && !h->exact && h->W[0] > 0 &&
-                  h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32);
-    h->ntiles = ((p.nx - 2) / kTile + 1) * ((p.ny - 2) / kTile + 1);
+                  h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32) && flds <= 150 * 1024;
+    h->ntiles = ((p.nx - 2) / kTileC + 1) * ((p.ny - 2) / kTileR + 1);
     return 0;
 }
 
@@ -421,36 +434,45 @@ void launch_norm(sscn_handle *h, hipStream_t st)
     default: CALL(20); break;                                                                                \
     }
 
+// Launch geometry of one fused 2D step over a work list.
+struct FusedLaunch {
+    const Inst2D *inst;
+    const int2 *work;
+    const int *nwork;
+    int grid;
+    int W;
+};
+
 template <class R, int W, bool RT>
-void go_fused(const sscn_handle *h, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
+void go_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
 {
-    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTile, kTile>();
-    hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTile, kTile, RT>), dim3(h->ntiles), dim3(256), lds, st, h->d_inst,
-                       h->d_work, h->d_nwork, parity, pin, pout, use_pin);
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
+    hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT>), dim3(f.grid), dim3(kTileNT), lds, st,
+                       f.inst, f.work, f.nwork, parity, pin, pout, use_pin);
 }
 
 template <class R, bool RT>
-void launch_fused(const sscn_handle *h, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
+void launch_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
 {
-#define SSCN_CALL_F(Wc) go_fused<R, Wc, RT>(h, parity, pin, pout, use_pin, st)
+#define SSCN_CALL_F(Wc) go_fused<R, Wc, RT>(f, parity, pin, pout, use_pin, st)
     if constexpr (std::is_same<R, float>::value) {
-        if (h->W[0] > 20) {
-            if (h->W[0] <= 24)
-                go_fused<R, 24, RT>(h, parity, pin, pout, use_pin, st);
+        if (f.W > 20) {
+            if (f.W <= 24)
+                go_fused<R, 24, RT>(f, parity, pin, pout, use_pin, st);
             else
-                go_fused<R, 32, RT>(h, parity, pin, pout, use_pin, st);
+                go_fused<R, 32, RT>(f, parity, pin, pout, use_pin, st);
             return;
         }
     }
-    SSCN_W_SWITCH_FUSED(R, h->W[0], SSCN_CALL_F)
+    SSCN_W_SWITCH_FUSED(R, f.W, SSCN_CALL_F)
 #undef SSCN_CALL_F
 }
 
 template <class R, int W, bool RT>
 hipError_t allow_fused_lds()
 {
-    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTile, kTile>();
-    return hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTile, kTile, RT>,
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
+    return hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
@@ -485,13 +507,14 @@ void enqueue_fused(sscn_handle *h, int64_t n, hipStream_t st, hipEvent_t *ev = n
 {
     const bool imag = h->p.mode == SSCN_IMAG;
     double *fp[2] = {h->partials, h->partials2};
+    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0]};
     for (int64_t s = 0; s < n; ++s) {
         if (ev)
             (void)hipEventRecord(ev[4 * s], st);
         if (imag)
-            launch_fused<R, false>(h, h->fparity, fp[h->pbuf], fp[h->pbuf ^ 1], h->pending ? 1 : 0, st);
+            launch_fused<R, false>(f, h->fparity, fp[h->pbuf], fp[h->pbuf ^ 1], h->pending ? 1 : 0, st);
         else
-            launch_fused<R, true>(h, h->fparity, nullptr, nullptr, 0, st);
+            launch_fused<R, true>(f, h->fparity, nullptr, nullptr, 0, st);
         if (ev)
             for (int t = 1; t < 4; ++t)
                 (void)hipEventRecord(ev[4 * s + t], st);
@@ -522,8 +545,8 @@ int setup_fused(sscn_handle *h)
     Inst2D in{};
     in.nx = p.nx;
     in.ny = p.ny;
-    in.tiles_x = (p.nx - 2) / kTile + 1;
-    in.tiles_y = (p.ny - 2) / kTile + 1;
+    in.tiles_x = (p.nx - 2) / kTileC + 1;
+    in.tiles_y = (p.ny - 2) / kTileR + 1;
     in.poff = 0;
     in.active = 1;
     in.hx = p.hx;
@@ -794,6 +817,167 @@ void free_buffers(sscn_handle *h)
         (void)hipFree(h->ws);
     h->work = nullptr;
     h->ws = nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// Batched 2D instances (one fused launch per step over all their tiles).
+}  // namespace
+
+struct sscn_batch {
+    int n = 0, precision = 0, mode = 0, W = 0;
+    hipStream_t stream = nullptr, cap = nullptr;
+    std::vector<sscn_params> p;
+    std::vector<StepArgs> args;
+    std::vector<void *> psi, work, tabx, taby;
+    std::vector<int> ntiles, nchunk;
+    std::vector<char> active;
+    std::vector<long long> conv;
+    std::vector<Inst2D> hinst;
+    Inst2D *d_inst = nullptr;
+    int2 *d_work = nullptr, *d_fwork = nullptr, *d_owork = nullptr;
+    int *d_nwork = nullptr, *d_nf = nullptr, *d_no = nullptr, *d_obase = nullptr, *d_ocount = nullptr;
+    int total_tiles = 0, total_chunks = 0;
+    int grid_tiles = 0, grid_chunks = 0;  // list lengths at the last rebuild
+    double *part[2] = {nullptr, nullptr};
+    double *opart = nullptr, *d_sums = nullptr, *d_mu_prev = nullptr;
+    int *d_hits = nullptr;
+    long long *d_conv = nullptr;
+    double *phase = nullptr;
+    int fparity = 0, pbuf = 0;
+    bool pending = false;
+    int64_t steps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_k = 0;
+};
+
+namespace {
+
+// Upload the work lists of the active instances: tiles (largest instances
+// first), finish chunks and observable chunks with each instance's range.
+int batch_lists(sscn_batch *b, bool all_for_obs = false)
+{
+    std::vector<int> order(b->n);
+    for (int k = 0; k < b->n; ++k)
+        order[k] = k;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return b->ntiles[x] > b->ntiles[y]; });
+    std::vector<int2> wl, fl, ol;
+    std::vector<int> obase(b->n, 0), ocount(b->n, 0);
+    for (int k : order)
+        if (b->active[k])
+            for (int t = 0; t < b->ntiles[k]; ++t)
+                wl.push_back(int2{k, t});
+    for (int k = 0; k < b->n; ++k) {
+        if (b->active[k])
+            for (int c = 0; c < b->nchunk[k]; ++c)
+                fl.push_back(int2{k, c});
+        if (b->active[k] || all_for_obs) {
+            obase[k] = (int)ol.size();
+            ocount[k] = b->nchunk[k];
+            for (int c = 0; c < b->nchunk[k]; ++c)
+                ol.push_back(int2{k, c});
+        }
+    }
+    const int nw = (int)wl.size(), nfl = (int)fl.size(), nol = (int)ol.size();
+    if (nw)
+        HIPCHECK(hipMemcpy(b->d_work, wl.data(), sizeof(int2) * nw, hipMemcpyHostToDevice));
+    if (nfl)
+        HIPCHECK(hipMemcpy(b->d_fwork, fl.data(), sizeof(int2) * nfl, hipMemcpyHostToDevice));
+    if (nol)
+        HIPCHECK(hipMemcpy(b->d_owork, ol.data(), sizeof(int2) * nol, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_nwork, &nw, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_nf, &nfl, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_no, &nol, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_obase, obase.data(), sizeof(int) * b->n, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_ocount, ocount.data(), sizeof(int) * b->n, hipMemcpyHostToDevice));
+    if (!all_for_obs) {
+        b->grid_tiles = nw;
+        b->grid_chunks = nfl;
+    }
+    return 0;
+}
+
+// nsteps fused steps of every listed instance, then the finish pass that
+// leaves each state normalised (imaginary time) in its caller buffer.
+template <class R>
+void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles, int grid_chunks)
+{
+    const bool imag = b->mode == SSCN_IMAG;
+    const FusedLaunch f{b->d_inst, b->d_work, b->d_nwork, std::max(grid_tiles, 1), b->W};
+    for (int64_t s = 0; s < nsteps; ++s) {
+        if (imag)
+            launch_fused<R, false>(f, b->fparity, b->part[b->pbuf], b->part[b->pbuf ^ 1], b->pending ? 1 : 0, st);
+        else
+            launch_fused<R, true>(f, b->fparity, nullptr, nullptr, 0, st);
+        b->fparity ^= 1;
+        if (imag) {
+            b->pbuf ^= 1;
+            b->pending = true;
+        }
+    }
+    if ((imag && b->pending) || b->fparity == 1)
+        hipLaunchKernelGGL((k_batch_finish<R>), dim3(std::max(grid_chunks, 1)), dim3(256), 0, st, b->d_inst,
+                           b->d_fwork, b->d_nf, b->fparity, b->part[b->pbuf], (imag && b->pending) ? 1 : 0);
+    b->pending = false;
+    b->fparity = 0;
+}
+
+void batch_drop_graph(sscn_batch *b)
+{
+    if (b->gexec)
+        (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
+    b->graph_k = 0;
+}
+
+int batch_graph(sscn_batch *b, int k)
+{
+    if (b->gexec && b->graph_k == k)
+        return 0;
+    batch_drop_graph(b);
+    HIPCHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+    if (b->precision == SSCN_C128)
+        batch_enqueue<double>(b, k, b->cap, b->total_tiles, b->total_chunks);
+    else
+        batch_enqueue<float>(b, k, b->cap, b->total_tiles, b->total_chunks);
+    hipError_t e = hipStreamEndCapture(b->cap, &b->graph);
+    if (e != hipSuccess)
+        return fail(SSCN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    e = hipGraphInstantiate(&b->gexec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess)
+        return fail(SSCN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    b->graph_k = k;
+    return 0;
+}
+
+template <class R>
+void batch_obs_launch(sscn_batch *b, int nchunks, double tol)
+{
+    hipLaunchKernelGGL((k_batch_obs<R>), dim3(std::max(nchunks, 1)), dim3(256), 0, b->stream, b->d_inst, b->d_owork,
+                       b->d_no, b->opart);
+    hipLaunchKernelGGL(k_batch_obs_final, dim3(b->n), dim3(256), 0, b->stream, b->n, b->d_obase, b->d_ocount,
+                       b->opart, b->d_sums, b->d_mu_prev, b->d_hits, b->d_conv, tol, (long long)b->steps);
+}
+
+void batch_free(sscn_batch *b)
+{
+    batch_drop_graph(b);
+    for (auto *v : {&b->work, &b->tabx, &b->taby})
+        for (void *q : *v)
+            if (q)
+                (void)hipFree(q);
+    void *bufs[] = {b->d_inst, b->d_work, b->d_fwork, b->d_owork, b->d_nwork, b->d_nf, b->d_no, b->d_obase,
+                    b->d_ocount, b->part[0], b->part[1], b->opart, b->d_sums, b->d_mu_prev, b->d_hits, b->d_conv,
+                    b->phase};
+    for (void *q : bufs)
+        if (q)
+            (void)hipFree(q);
+    if (b->cap)
+        (void)hipStreamDestroy(b->cap);
 }
 
 }  // namespace
@@ -1235,6 +1419,300 @@ int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *pla
             segment_xyz[a] = h->exact ? 0 : kSeg;
     }
     return 0;
+}
+
+int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, void *hip_stream, sscn_batch **out)
+{
+    if (!params || !psi_devs || !out || n < 1)
+        return fail(SSCN_EINVAL, "bad batch_init arguments");
+    *out = nullptr;
+    sscn_batch *b = new sscn_batch();
+    b->n = n;
+    b->stream = (hipStream_t)hip_stream;
+    b->precision = params[0].precision;
+    b->mode = params[0].mode;
+    auto bail = [&](int code) {
+        batch_free(b);
+        delete b;
+        return code;
+    };
+    std::vector<sscn_handle> tmp(n);
+    for (int k = 0; k < n; ++k) {
+        if (!psi_devs[k])
+            return bail(fail(SSCN_EINVAL, "null state buffer in the batch"));
+        int r = validate(params[k]);
+        if (r)
+            return bail(r);
+        if (params[k].dim != 2 || params[k].precision != b->precision || params[k].mode != b->mode)
+            return bail(fail(SSCN_EINVAL, "batch instances must be 2D with a common precision and mode"));
+        tmp[k].p = params[k];
+        tmp[k].p.nz = 1;
+        r = setup(&tmp[k]);
+        if (r)
+            return bail(r);
+        if (tmp[k].exact)
+            return bail(fail(SSCN_EINVAL, "a batch instance needs the exact whole-line path"));
+        b->W = std::max(b->W, tmp[k].W[0]);
+    }
+    const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
+    const size_t flds = (size_t)(kTileR + 2 * b->W + 2) * (stage_stride(kTileC + 2 * b->W + 2, kSeg) + kTileC + 1) * esize;
+    if (b->W > (b->precision == SSCN_C128 ? 20 : 32) || flds > 150 * 1024)
+        return bail(fail(SSCN_EINVAL, "the common window of the batch is too large for the fused step"));
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
+        return bail(fail(SSCN_EHIP, "hipStreamCreateWithFlags failed"));
+    int poff = 0;
+    for (int k = 0; k < n; ++k) {
+        sscn_handle &h = tmp[k];
+        h.W[0] = h.W[1] = b->W;
+        h.fused_ok = true;
+        int r = build_tables(&h);
+        if (r)
+            return bail(r);
+        b->p.push_back(h.p);
+        b->args.push_back(h.args);
+        b->psi.push_back(psi_devs[k]);
+        b->tabx.push_back(h.tab[0]);
+        b->taby.push_back(h.tab[1]);
+        h.tab[0] = h.tab[1] = nullptr;  // owned by the batch now
+        void *w = nullptr;
+        const size_t bytes = (size_t)h.npts * esize;
+        if (hipMalloc(&w, bytes) != hipSuccess)
+            return bail(fail(SSCN_ENOMEM, "hipMalloc of a batch work buffer failed"));
+        b->work.push_back(w);
+        HIPCHECK(hipMemset(w, 0, bytes));
+        const int tx = (h.p.nx - 2) / kTileC + 1, ty = (h.p.ny - 2) / kTileR + 1;
+        b->ntiles.push_back(tx * ty);
+        b->nchunk.push_back((int)((h.npts + kChunk - 1) / kChunk));
+        Inst2D in{};
+        in.nx = h.p.nx;
+        in.ny = h.p.ny;
+        in.tiles_x = tx;
+        in.tiles_y = ty;
+        in.poff = poff;
+        in.active = 1;
+        in.hx = h.p.hx;
+        in.hy = h.p.hy;
+        in.x0 = h.args.x0;
+        in.y0 = h.args.y0;
+        in.vx = h.args.vx;
+        in.vy = h.args.vy;
+        in.g = h.p.g;
+        in.omega = h.p.omega;
+        in.dt = h.p.dt;
+        in.dV = h.args.dV;
+        in.ax[0] = h.args.ax[0];
+        in.ax[1] = h.args.ax[1];
+        in.buf[0] = psi_devs[k];
+        in.buf[1] = w;
+        in.tab[0] = b->tabx.back();
+        in.tab[1] = b->taby.back();
+        b->hinst.push_back(in);
+        poff += tx * ty;
+        b->total_chunks += b->nchunk.back();
+    }
+    b->total_tiles = poff;
+    b->active.assign(n, 1);
+    b->conv.assign(n, -1);
+    const size_t nopart = std::max((size_t)b->total_chunks * 14, (size_t)kRedBlocks);
+    if (hipMalloc(&b->d_inst, sizeof(Inst2D) * n) != hipSuccess ||
+        hipMalloc(&b->d_work, sizeof(int2) * b->total_tiles) != hipSuccess ||
+        hipMalloc(&b->d_fwork, sizeof(int2) * b->total_chunks) != hipSuccess ||
+        hipMalloc(&b->d_owork, sizeof(int2) * b->total_chunks) != hipSuccess ||
+        hipMalloc(&b->d_nwork, sizeof(int)) != hipSuccess || hipMalloc(&b->d_nf, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->d_no, sizeof(int)) != hipSuccess || hipMalloc(&b->d_obase, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&b->d_ocount, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&b->part[0], sizeof(double) * std::max(b->total_tiles, kRedBlocks)) != hipSuccess ||
+        hipMalloc(&b->part[1], sizeof(double) * std::max(b->total_tiles, kRedBlocks)) != hipSuccess ||
+        hipMalloc(&b->opart, sizeof(double) * nopart) != hipSuccess ||
+        hipMalloc(&b->d_sums, sizeof(double) * 14 * n) != hipSuccess ||
+        hipMalloc(&b->d_mu_prev, sizeof(double) * n) != hipSuccess ||
+        hipMalloc(&b->d_hits, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&b->d_conv, sizeof(long long) * n) != hipSuccess)
+        return bail(fail(SSCN_ENOMEM, "hipMalloc of the batch buffers failed"));
+    HIPCHECK(hipMemcpy(b->d_inst, b->hinst.data(), sizeof(Inst2D) * n, hipMemcpyHostToDevice));
+    int r = sscn_batch_reset(b);
+    if (r)
+        return bail(r);
+    hipError_t e = b->precision == SSCN_C128 ? allow_fused_lds_all<double>(b->W) : allow_fused_lds_all<float>(b->W);
+    if (e != hipSuccess)
+        return bail(fail(SSCN_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e)));
+    *out = b;
+    return 0;
+}
+
+int sscn_batch_reset(sscn_batch *b)
+{
+    if (!b)
+        return fail(SSCN_EINVAL, "null argument");
+    b->active.assign(b->n, 1);
+    b->conv.assign(b->n, -1);
+    std::vector<double> nan(b->n, std::nan(""));
+    std::vector<int> zero(b->n, 0);
+    std::vector<long long> neg(b->n, -1);
+    HIPCHECK(hipMemcpy(b->d_mu_prev, nan.data(), sizeof(double) * b->n, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_hits, zero.data(), sizeof(int) * b->n, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_conv, neg.data(), sizeof(long long) * b->n, hipMemcpyHostToDevice));
+    return batch_lists(b);
+}
+
+int sscn_batch_init_state(sscn_batch *b, int k, int kind, const double *phase_host, double d_xy)
+{
+    if (!b || k < 0 || k >= b->n || (kind != 0 && kind != 1) || !(d_xy > 0))
+        return fail(SSCN_EINVAL, "bad batch_init_state arguments");
+    const sscn_params &p = b->p[k];
+    const StepArgs &a = b->args[k];
+    const int64_t npts = (int64_t)p.nx * p.ny;
+    const double *ph = nullptr;
+    if (phase_host) {
+        if (b->phase)
+            (void)hipFree(b->phase);
+        b->phase = nullptr;
+        if (hipMalloc(&b->phase, sizeof(double) * npts) != hipSuccess)
+            return fail(SSCN_ENOMEM, "hipMalloc of the phase buffer failed");
+        HIPCHECK(hipMemcpy(b->phase, phase_host, sizeof(double) * npts, hipMemcpyHostToDevice));
+        ph = b->phase;
+    }
+    const int nb = red_blocks(npts);
+    if (b->precision == SSCN_C128) {
+        hipLaunchKernelGGL((k_init<double>), dim3(nb), dim3(256), 0, b->stream, (V<double> *)b->psi[k], a, kind, ph,
+                           d_xy, 0.0);
+        hipLaunchKernelGGL((k_norm_partials<double>), dim3(kRedBlocks), dim3(256), 0, b->stream,
+                           (const V<double> *)b->psi[k], npts, b->opart);
+        hipLaunchKernelGGL((k_rescale<double>), dim3(nb), dim3(256), 0, b->stream, (const V<double> *)b->psi[k],
+                           (V<double> *)b->psi[k], npts, a.dV, b->opart, kRedBlocks);
+    } else {
+        hipLaunchKernelGGL((k_init<float>), dim3(nb), dim3(256), 0, b->stream, (V<float> *)b->psi[k], a, kind, ph,
+                           d_xy, 0.0);
+        hipLaunchKernelGGL((k_norm_partials<float>), dim3(kRedBlocks), dim3(256), 0, b->stream,
+                           (const V<float> *)b->psi[k], npts, b->opart);
+        hipLaunchKernelGGL((k_rescale<float>), dim3(nb), dim3(256), 0, b->stream, (const V<float> *)b->psi[k],
+                           (V<float> *)b->psi[k], npts, a.dV, b->opart, kRedBlocks);
+    }
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    return 0;
+}
+
+int sscn_batch_step(sscn_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0)
+        return fail(SSCN_EINVAL, "bad batch_step arguments");
+    if (b->precision == SSCN_C128)
+        batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks);
+    else
+        batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks);
+    HIPCHECK(hipGetLastError());
+    b->steps += nsteps;
+    return 0;
+}
+
+int sscn_batch_observables(sscn_batch *b, sscn_obs *out)
+{
+    if (!b || !out)
+        return fail(SSCN_EINVAL, "null argument");
+    int r = batch_lists(b, true);
+    if (r)
+        return r;
+    if (b->precision == SSCN_C128)
+        batch_obs_launch<double>(b, b->total_chunks, 0.0);
+    else
+        batch_obs_launch<float>(b, b->total_chunks, 0.0);
+    std::vector<double> sums((size_t)14 * b->n);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpyAsync(sums.data(), b->d_sums, sizeof(double) * 14 * b->n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    r = batch_lists(b);
+    if (r)
+        return r;
+    int rc = 0;
+    for (int k = 0; k < b->n; ++k) {
+        double s[14];
+        std::memcpy(s, &sums[(size_t)14 * k], sizeof s);
+        const double dV = b->args[k].dV;
+        for (int t = 0; t < 13; ++t)
+            s[t] *= dV;
+        sscn_obs &o = out[k];
+        std::memset(&o, 0, sizeof o);
+        std::memcpy(o.sums, s, sizeof s);
+        o.norm = s[0];
+        o.mu = (s[2] + s[3] + s[4] + s[5]) / s[1];
+        o.energy = (s[2] + s[3] + 0.5 * s[4] + s[5]) / s[1];
+        o.mu_full = (s[6] + s[7] + s[8] + s[9]) / s[0];
+        o.energy_full = (s[6] + s[7] + 0.5 * s[8] + s[9]) / s[0];
+        o.rms_x = std::sqrt(s[10] / s[0]);
+        o.rms_y = std::sqrt(s[11] / s[0]);
+        o.rms_r = std::sqrt((s[10] + s[11]) / s[0]);
+        o.max_density = s[13];
+        o.step = b->conv[k] >= 0 ? b->conv[k] : b->steps;
+        for (int t = 0; t < 14; ++t)
+            if (!std::isfinite(s[t]))
+                rc = fail(SSCN_ENONFINITE, "non-finite reduction in the batch observables");
+    }
+    return rc;
+}
+
+int sscn_batch_run(sscn_batch *b, int64_t max_steps, int check_every, double tol_dmu, int64_t *steps_out)
+{
+    if (!b || max_steps < 0 || check_every < 2 || !(tol_dmu > 0))
+        return fail(SSCN_EINVAL, "bad batch_run arguments");
+    const int K = check_every + (check_every & 1);
+    int r = batch_graph(b, K);
+    if (r)
+        return r;
+    int64_t done = 0;
+    std::vector<long long> cv(b->n);
+    while (done < max_steps) {
+        int nact = 0;
+        for (char a : b->active)
+            nact += a;
+        if (!nact)
+            break;
+        HIPCHECK(hipGraphLaunch(b->gexec, b->stream));
+        b->steps += K;
+        done += K;
+        if (b->precision == SSCN_C128)
+            batch_obs_launch<double>(b, b->total_chunks, tol_dmu);
+        else
+            batch_obs_launch<float>(b, b->total_chunks, tol_dmu);
+        HIPCHECK(hipGetLastError());
+        HIPCHECK(hipMemcpyAsync(cv.data(), b->d_conv, sizeof(long long) * b->n, hipMemcpyDeviceToHost, b->stream));
+        HIPCHECK(hipStreamSynchronize(b->stream));
+        bool changed = false;
+        for (int k = 0; k < b->n; ++k)
+            if (b->active[k] && cv[k] >= 0) {
+                b->active[k] = 0;
+                b->conv[k] = cv[k];
+                changed = true;
+            }
+        if (changed) {
+            r = batch_lists(b);
+            if (r)
+                return r;
+        }
+    }
+    if (steps_out)
+        for (int k = 0; k < b->n; ++k)
+            steps_out[k] = b->conv[k];
+    return 0;
+}
+
+int sscn_batch_get_state(sscn_batch *b, int k, void *host_psi)
+{
+    if (!b || k < 0 || k >= b->n || !host_psi)
+        return fail(SSCN_EINVAL, "bad batch_get_state arguments");
+    const size_t bytes = (size_t)b->p[k].nx * b->p[k].ny * (b->precision == SSCN_C128 ? 16 : 8);
+    HIPCHECK(hipMemcpyAsync(host_psi, b->psi[k], bytes, hipMemcpyDeviceToHost, b->stream));
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    return 0;
+}
+
+void sscn_batch_destroy(sscn_batch *b)
+{
+    if (!b)
+        return;
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    delete b;
 }
 
 }  // extern "C"

@@ -1,0 +1,97 @@
+"""GPU parity of the batched instances (fused step over a work list of tiles
+of many grids) against the FP64 oracle, instance by instance."""
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    return float(np.linalg.norm((np.asarray(a) - np.asarray(b)).ravel()) /
+                 np.linalg.norm(np.asarray(b).ravel()))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1906_06327_amd as P
+    P.lib()
+    return P
+
+
+def mixed(prec, mode=0):
+    shapes = [(100, 77), (64, 64), (130, 47), (33, 200), (128, 128)]
+    out = []
+    for t, (nx, ny) in enumerate(shapes):
+        out.append(dict(dim=2, nx=nx, ny=ny, nz=1, hx=0.1 + 0.01 * t, hy=0.09 + 0.005 * t, hz=0.1,
+                        gamma=1.0, nu=1.0 + 0.05 * t, lam=1.0, g=30.0 + 25.0 * t,
+                        omega=0.3 + 0.1 * t, dt=1e-3 * (1 + t % 2), mode=mode, precision=prec))
+    return out
+
+
+@pytest.mark.parametrize("prec,mode", [(0, 0), (0, 1), (1, 0)])
+def test_batch_step_matches_oracle_per_instance(P, prec, mode):
+    print(f"[gpu-batch] step prec={prec} mode={mode}", flush=True)
+    cfgs = mixed(prec, mode)
+    b = P.Batch(cfgs)
+    refs = []
+    for k, c in enumerate(cfgs):
+        ph = W.phase_field(30 + k, c["ny"], c["nx"])
+        b.init_state(k, 1, ph, 1.0)
+        op = O.make_params(**c)
+        refs.append((op, O.init_state(op, 1, ph, 1.0)))
+    b.step(77)
+    tol = 1e-10 if prec == 0 else 1e-5
+    obs = b.observables()
+    for k, (op, r0) in enumerate(refs):
+        ref = O.step(op, r0, 77)
+        got = b.get_state(k).astype(np.complex128)
+        assert rel(got, ref) <= tol, k
+        oo = O.observables(op, ref)
+        for key in ("norm", "mu", "energy", "rms_x"):
+            assert abs(obs[k][key] - oo[key]) <= tol * max(1.0, abs(oo[key])), (k, key)
+    b.close()
+
+
+def test_batch_run_drops_converged_instances(P):
+    """Instances converge at different steps; each stops exactly there: its
+    state equals the oracle's after that many steps."""
+    print("[gpu-batch] run to convergence", flush=True)
+    cfgs = []
+    for t in range(4):
+        cfgs.append(dict(dim=2, nx=48 + 8 * t, ny=44 + 4 * t, nz=1, hx=0.25, hy=0.25, hz=0.1,
+                         gamma=1.0, nu=1.1, lam=1.0, g=5.0 + 20.0 * t, omega=0.2 + 0.1 * t,
+                         dt=0.02, mode=0, precision=0))
+    b = P.Batch(cfgs)
+    for k, c in enumerate(cfgs):
+        b.init_state(k, 0, W.phase_field(50 + k, c["ny"], c["nx"]), 1.0)
+    steps = b.run(max_steps=20000, check_every=50, tol=1e-9)
+    assert all(s > 0 for s in steps), steps
+    assert len(set(steps)) > 1, steps  # they do not all stop together
+    for k, c in enumerate(cfgs):
+        op = O.make_params(**c)
+        ref = O.step(op, O.init_state(op, 0, W.phase_field(50 + k, c["ny"], c["nx"]), 1.0), steps[k])
+        assert rel(b.get_state(k), ref) <= 1e-10, k
+    b.close()
+
+
+def test_batch_workload_sampled(P):
+    """The 64-instance workload at full size: a few steps, sampled instances
+    against the oracle."""
+    print("[gpu-batch] 64-instance workload", flush=True)
+    cfgs = W.batch_instances()
+    b = P.Batch(cfgs)
+    for k, c in enumerate(cfgs):
+        b.init_state(k, 1, W.phase_field(c["seed"], c["ny"], c["nx"]), 1.0)
+    b.step(10)
+    for k in (0, 17, 40, 63):
+        c = cfgs[k]
+        op = O.make_params(**c)
+        ref = O.step(op, O.init_state(op, 1, W.phase_field(c["seed"], c["ny"], c["nx"]), 1.0), 10)
+        assert rel(b.get_state(k), ref) <= 1e-10, k
+    b.close()
