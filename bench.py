@@ -45,7 +45,29 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip variants and convergence")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--profile-sample", action="store_true",
+                    help="run a short fixed sample for hardware-counter passes and exit: a "
+                         "256 MiB device copy (counter calibration), 50 steps of the 512^2 "
+                         "complex128 workload, 20 steps of the 3D complex64 workload")
     return ap.parse_args()
+
+
+def profile_sample(P, torch):
+    n = 256 * 1024 * 1024 // 16
+    a = torch.ones(n, dtype=torch.complex128, device="cuda")
+    c = torch.empty_like(a)
+    for _ in range(3):
+        c.copy_(a)
+    torch.cuda.synchronize()
+    print("profile-sample: copy 256 MiB x3 done", flush=True)
+    for cfg, k in ((W.CONFIGS["c2"], 50), (W.CONFIGS["c3"], 20)):
+        s = P.Solver(W.solver_params(cfg))
+        s.init_state(1, W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"]), 1.0, cfg.get("d_z", 0.0))
+        s.step(k)
+        torch.cuda.synchronize()
+        print(f"profile-sample: {cfg['nx']}x{cfg['ny']}x{cfg['nz']} {k} steps, "
+              f"plan {s.solver_info()['plan']}", flush=True)
+        s.close()
 
 
 def timed_steps(P, torch, cfg, steps, warmup, mode=0):
@@ -62,50 +84,69 @@ def timed_steps(P, torch, cfg, steps, warmup, mode=0):
 
 
 def kernel_roofline(s, cfg, nsteps=200):
-    """Average duration of each sweep kernel (HIP events on the solver's
-    stream) and the dominant one's algorithmic bandwidth."""
+    """Average duration of the dominant kernel of a step (HIP events on the
+    solver's stream) and its algorithmic bandwidth: 2*c bytes per point per
+    axis sweep it performs (one read and one write of the state per sweep,
+    complex size c), i.e. 2*c*P per sweep kernel and 2*d*c*P for the fused
+    2D step, which performs both sweeps of a step in one launch."""
     ms = s.profile_step(nsteps)
-    pts = cfg["nx"] * cfg["ny"] * (cfg["nz"] if cfg["dim"] == 3 else 1)
+    plan = s.solver_info()["plan"]
+    dim = cfg["dim"]
+    pts = cfg["nx"] * cfg["ny"] * (cfg["nz"] if dim == 3 else 1)
     esize = 16 if cfg.get("precision", 0) == 0 else 8
-    per_launch = 2 * esize * pts  # one read + one write of the state
-    names = ("x", "y", "z") if cfg["dim"] == 3 else ("x", "y")
-    dom = max(names, key=lambda k: ms[k])
+    if plan == 2:
+        names, dom = ("x",), "x"
+        per_launch = 2 * dim * esize * pts
+        label = "fused 2D step (H1 + x + y)"
+    else:
+        names = ("x", "y", "z") if dim == 3 else ("x", "y")
+        dom = max(names, key=lambda k: ms[k])
+        per_launch = 2 * esize * pts
+        label = f"{dom}-sweep"
     gbs = per_launch / (ms[dom] * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None,
-            "kernel": f"{dom}-sweep", "bytes_per_launch": per_launch,
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None, "kernel": label,
+            "plan": {1: "sweeps", 2: "fused"}.get(plan, plan), "bytes_per_launch": per_launch,
             "kernel_ms": {k: round(ms[k], 5) for k in names}, "step_ms_events": round(ms["step"], 5)}
 
 
-def converge_run(P, torch, cfg, max_steps=400000):
-    """Imaginary time from Eq. (fun) until |mu_n - mu_{n-1}| < 1e-8 at two
-    consecutive checks 0.1 time units apart with the vortex count unchanged."""
-    s = P.Solver(W.solver_params(cfg))
+def batch_run(P, torch, steps=200):
+    """The 64-instance batch: updates/s of the fused batched step."""
+    cfgs = W.batch_instances()
+    b = P.Batch(cfgs)
+    for k, c in enumerate(cfgs):
+        b.init_state(k, 1, W.phase_field(c["seed"], c["ny"], c["nx"]), 1.0)
+    b.step(20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    pts = sum(c["nx"] * c["ny"] for c in cfgs)
+    b.close()
+    ups = pts * steps / dt
+    return {"instances": len(cfgs), "points": pts, "updates_per_s": round(ups, 1),
+            "ms_per_step": round(dt / steps * 1e3, 5),
+            "algorithmic_GBps": round(64 * ups / 1e9, 1), "frac_of_8TBps": round(64 * ups / 8e12, 4)}
+
+
+def converge_run(P, torch, cfg, precision, max_steps=3000000):
+    """Imaginary time from Eq. (fun) to |mu_n - mu_{n-1}| < 1e-8 at two
+    consecutive checks 0.1 time units apart with the vortex count unchanged
+    (sscn_converge; complex64 bulk switches to complex128 at its plateau)."""
+    s = P.Solver(W.solver_params(cfg, precision=precision))
     ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
     chk = max(1, int(round(0.1 / cfg["dt"])))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.init_state(1, ph, 1.0)
-    prev, hits, steps, count_prev = None, 0, 0, None
-    while steps < max_steps:
-        s.step(chk)
-        steps += chk
-        mu = s.observables()["mu"]
-        if prev is not None and abs(mu - prev) < 1e-8:
-            c = s.vortex_count()
-            hits = hits + 1 if (count_prev is None or c == count_prev) else 0
-            count_prev = c
-            if hits >= 2:
-                break
-        else:
-            hits, count_prev = 0, None
-        prev = mu
+    steps, ok = s.converge(max_steps, check_every=chk, tol=1e-8, switch_tol=2e-6)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ob = s.observables()
-    out = {"workload": "128x128 2D, g=100, Omega=0.6, dt=1e-3, complex128", "steps": steps,
-           "converged": hits >= 2, "wall_s": round(wall, 4), "mu": ob["mu"],
-           "energy": ob["energy"], "vortices": s.vortex_count()}
+    out = {"precision": "c128" if precision == 0 else "c64 bulk -> c128", "steps": steps,
+           "converged": ok, "wall_s": round(wall, 3), "mu": ob["mu"], "energy": ob["energy"],
+           "vortices": s.vortex_count()}
     s.close()
     return out
 
@@ -143,6 +184,9 @@ def main():
     P.lib()
     cfg = dict(W.CONFIGS["c2"], precision=0 if a.precision == "c128" else 1)
     torch.cuda.set_device(0)
+    if a.profile_sample:
+        profile_sample(P, torch)
+        return
 
     s, dt = timed_steps(P, torch, cfg, a.steps, a.warmup)
     pts = cfg["nx"] * cfg["ny"]
@@ -182,8 +226,16 @@ def main():
                                        "ms_per_step": round(dt / 1000 * 1e3, 6),
                                        "roofline": kernel_roofline(s, c3, 100)}
         s.close()
+        variants["c4_batch_64_instances_complex128"] = batch_run(P, torch)
         out["variants"] = variants
-        out["converge"] = converge_run(P, torch, W.CONFIGS["c1"])
+        c1 = W.CONFIGS["c1"]
+        conv = {"workload": "2D 128x128 on [-6.4,6.4)^2, g=100, Omega=0.6, dt=1e-3, one-vortex "
+                            "random-phase start (seed 13)",
+                "criterion": "|dmu| < 1e-8 at two consecutive checks 0.1 time units apart, "
+                             "vortex count unchanged"}
+        conv["c128"] = converge_run(P, torch, c1, 0)
+        conv["c64_then_c128"] = converge_run(P, torch, c1, 1)
+        out["converge"] = conv
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W.CONFIGS["c2"], a.cpu_seconds)
     print(json.dumps(out), flush=True)

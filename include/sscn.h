@@ -144,6 +144,23 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev);
  * paper counts by eye (Sec. 4).  Synchronises the stream. */
 int sscn_vortex_count(sscn_handle *h, double density_frac, int box, int *count);
 
+/* Current parameters of the handle (mode and precision change with
+ * sscn_set_mode and sscn_converge). */
+int sscn_get_params(sscn_handle *h, sscn_params *out);
+
+/* Imaginary-time run to a converged lattice.  Every check_every steps mu
+ * (real-part form) is evaluated; the state is converged when |mu - mu_prev| <
+ * tol at two consecutive checks with the vortex count (density_frac 0.05,
+ * box 3) unchanged between them.  The paper runs a fixed number of steps;
+ * this criterion is the library's.  In complex64 mode the bulk runs in FP32
+ * until its plateau (|dmu| < switch_tol, or no new minimum of |dmu| for 5
+ * checks), then the state is upcast into fp64_psi_dev (caller-owned
+ * complex128 buffer, borrowed from then on as by sscn_set_mode) and the run
+ * continues in FP64 to tol.  *steps_out = steps taken, *converged = 1 if the
+ * criterion was met within max_steps.  Synchronises at every check. */
+int sscn_converge(sscn_handle *h, int64_t max_steps, int check_every, double tol, double switch_tol,
+                  void *fp64_psi_dev, int64_t *steps_out, int *converged);
+
 /* Advance nsteps >= 1 steps with a HIP event recorded on the handle's
  * stream before and after every sweep kernel, and return in ms_out[0..3] the
  * average duration (milliseconds) of the x-sweep (with the fused H1), the

@@ -1,0 +1,97 @@
+/*
+ * sscn_nn.h -- C ABI of the kernels of the learned initial state.
+ *
+ * A small convolutional U-Net proposes the initial state of an imaginary-
+ * time run in place of the one-vortex random-phase state of Eq. (fun)
+ * (paper, Sec. 2).  The paper itself accelerates convergence by starting
+ * from a converged state of neighbouring parameters (Sec. 3 and Fig. 3); the
+ * network generalises that idea from converged states the solver produces.
+ * These entry points are the network's forward and backward building blocks;
+ * the layer sequence and the training loop live in
+ * paper_1906_06327_amd/nn.py.
+ *
+ * Tensors are DEVICE buffers, NHWC (channels fastest).  Activations and
+ * activation gradients are bf16 (uint16 bit patterns); weights of a 3x3
+ * convolution are bf16 [Cout][3][3][Cin]; biases, weight/bias gradients and
+ * the Adam state are fp32.  Channel counts of every convolution are
+ * multiples of 16 (pad with zeros).  "ld"/"off" arguments address channel
+ * slices: element (pixel p, channel c) of a slice is at p*ld + off + c.
+ * Every call enqueues on `stream` (a hipStream_t, NULL = null stream) and
+ * returns 0, or -1 for bad arguments, -5 for a HIP launch error;
+ * sscn_nn_last_error() describes the last failure of the calling thread.
+ * Reductions are fixed-order (no atomics): results are deterministic.
+ */
+#ifndef SSCN_NN_H
+#define SSCN_NN_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* y = act(conv3x3(x, w) + bias), zero padding 1, stride 1.  Matrix-core
+ * implicit GEMM (bf16 x bf16 -> fp32).  act: 0 none, 1 leaky ReLU (0.1).
+ * out_f32: y is fp32 instead of bf16.  bias may be NULL. */
+int sscn_nn_conv3x3(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
+                    int act, int out_f32, void *y, int ldy, int yoff, void *stream);
+
+/* Input gradient of a convolution: dx = conv3x3(dy, w flipped and
+ * transposed), bf16.  wt_scratch: 9*Cin*Cout bf16 elements. */
+int sscn_nn_conv3x3_dgrad(const void *dy, int N, int H, int W, int Cout, const void *w, int Cin,
+                          void *wt_scratch, void *dx, int lddx, int dxoff, void *stream);
+
+/* Size (floats) of the scratch sscn_nn_conv3x3_wgrad needs. */
+int sscn_nn_wgrad_scratch(int N, int H, int W, int Cin, int Cout, int64_t *floats);
+
+/* Weight gradient dw[co][tap][ci] = sum_p dy[p][co] x[p + tap][ci] (matrix
+ * cores, split over pixel ranges and summed in fixed order) and bias
+ * gradient db[co] = sum_p dy[p][co] (db may be NULL).  fp32 outputs. */
+int sscn_nn_conv3x3_wgrad(const void *x, int N, int H, int W, int Cin, const void *dy, int Cout, float *dw,
+                          float *db, float *scratch, int64_t scratch_floats, void *stream);
+
+/* In place: dy *= (y > 0 ? 1 : 0.1), the leaky-ReLU gradient from the
+ * layer's output y. */
+int sscn_nn_act_bwd(void *dy, const void *y, int64_t n, void *stream);
+
+/* 2x2 average pooling (H, W even; y is N x H/2 x W/2 x C) and its gradient
+ * (dy is N x H/2 x W/2 x C, dx is N x H x W x C). */
+int sscn_nn_pool2(const void *x, int N, int H, int W, int C, void *y, void *stream);
+int sscn_nn_pool2_bwd(const void *dy, int N, int H, int W, int C, void *dx, void *stream);
+
+/* Nearest 2x upsampling of x (N x H x W x C) into a channel slice of y
+ * (N x 2H x 2W, ldy channels), and its gradient into dx (N x H x W x C). */
+int sscn_nn_up2(const void *x, int N, int H, int W, int C, void *y, int ldy, int yoff, void *stream);
+int sscn_nn_up2_bwd(const void *dy, int ldy, int yoff, int N, int H, int W, int C, void *dx, void *stream);
+
+/* Copy (accumulate = 0) or add (accumulate = 1) a channel slice: dst slice
+ * (ldd, doff) of P pixels x C channels from the src slice (lds, soff). */
+int sscn_nn_chan_copy(const void *src, int lds, int soff, void *dst, int ldd, int doff, int P, int C,
+                      int accumulate, void *stream);
+
+/* Phase-aligned loss of B samples of S points: prediction pred (fp32, ld
+ * channels, Re and Im in channels 0 and 1), target psi (fp32 interleaved
+ * Re, Im).  stats[4b..4b+3] = Re<psi,pred>, Im<psi,pred>, |pred|^2, |psi|^2
+ * (fp64, device); the loss of sample b is |pred|^2 + |psi|^2 - 2|<psi,pred>|,
+ * i.e. |pred - e^{i phi} psi|^2 minimised over the global phase phi.  If
+ * dpred is not NULL it receives the gradient of the batch-mean loss, bf16,
+ * ld channels (channels beyond 1 zero). */
+int sscn_nn_loss(const float *pred, int ld, const float *psi, int B, int S, double *stats, void *dpred,
+                 void *stream);
+
+/* One Adam step (t >= 1) on fp32 master weights w with state m, v and
+ * gradient g; if wbf16 is not NULL the updated weights are also written
+ * there as bf16. */
+int sscn_nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
+                 int t, void *wbf16, void *stream);
+
+/* b = bf16(a), round to nearest even. */
+int sscn_nn_f32_to_bf16(const float *a, void *b, int64_t n, void *stream);
+
+const char *sscn_nn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSCN_NN_H */

@@ -24,7 +24,7 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
 EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
-           "sscn_solver_info", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
+           "sscn_solver_info", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_destroy",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
@@ -77,6 +77,9 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int)]
         L.sscn_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+        L.sscn_converge.argtypes = [vp, i64, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp,
+                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int)]
+        L.sscn_get_params.argtypes = [vp, ctypes.POINTER(Params)]
         L.sscn_batch_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(vp), vp,
                                       ctypes.POINTER(vp)]
         L.sscn_batch_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double]
@@ -198,6 +201,27 @@ class Solver:
         self.params.precision = int(precision)
         if new is not None:
             self.psi = new
+
+    def converge(self, max_steps, check_every=100, tol=1e-8, switch_tol=2e-6):
+        """Run imaginary time to |dmu| < tol at two consecutive checks with an
+        unchanged vortex count; complex64 runs switch to complex128 at their
+        plateau (into a complex128 tensor allocated here, which becomes
+        self.psi).  Returns (steps, converged)."""
+        torch = self._torch
+        new = None
+        if self.params.precision == SSCN_C64:
+            new = torch.empty(self.shape, dtype=torch.complex128, device=self.psi.device)
+        steps, ok = ctypes.c_int64(), ctypes.c_int()
+        _check(lib().sscn_converge(self._h, int(max_steps), int(check_every), float(tol),
+                                   float(switch_tol),
+                                   ctypes.c_void_p(new.data_ptr()) if new is not None else None,
+                                   ctypes.byref(steps), ctypes.byref(ok)))
+        p = Params()
+        _check(lib().sscn_get_params(self._h, ctypes.byref(p)))
+        if new is not None and p.precision == SSCN_C128:
+            self.psi = new
+        self.params = p
+        return int(steps.value), bool(ok.value)
 
     def vortex_count(self, density_frac=0.05, box=3):
         c = ctypes.c_int()

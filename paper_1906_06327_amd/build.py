@@ -4,7 +4,7 @@ import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", "sscn_lib.hip")]
+SRCS = [os.path.join(HERE, "csrc", "sscn_lib.hip"), os.path.join(HERE, "csrc", "sscn_nn.hip")]
 LIB = os.path.join(HERE, "libsscn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

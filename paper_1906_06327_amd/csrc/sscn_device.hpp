@@ -329,24 +329,36 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
     const int line0 = blockIdx.x * L;
     const int tid = threadIdx.x;
 
-    double sm1 = 0.0;
-    if (!RT && npart > 0) {
-        const double tot = block_sum_partials(partials, npart, red);
-        sm1 = 1.0 / sqrt(a.dV * tot) - 1.0;
-    }
-    const R sr = R(sm1);
 
     // stage the block's lines and their table rows: every thread issues its
     // loads first, then applies the rescale and H1 and writes LDS
+    // element e = tid + 256 c of the block's L lines is (line l, column t);
+    // the walk below advances (l, t) by 256 without integer division
+    int lc[kXLoad], tc[kXLoad];
+    {
+        int l = 0, t = tid;
+        while (t >= nx) {
+            t -= nx;
+            ++l;
+        }
+#pragma unroll
+        for (int c = 0; c < kXLoad; ++c) {
+            lc[c] = l;
+            tc[c] = t;
+            t += 256;
+            while (t >= nx) {
+                t -= nx;
+                ++l;
+            }
+        }
+    }
     Cx<R> pre[kXLoad];
 #pragma unroll
     for (int c = 0; c < kXLoad; ++c) {
-        const int e = tid + c * 256;
-        const int l = e / nx, t = e - l * nx;
-        const int line = line0 + l;
+        const int line = line0 + lc[c];
         pre[c] = Cx<R>{R(0), R(0)};
-        if (e < L * nx && line < nlines && t > 0)
-            pre[c] = ld<R>(src, (int64_t)line * nx + t);
+        if (lc[c] < L && line < nlines && tc[c] > 0)
+            pre[c] = ld<R>(src, (int64_t)line * nx + tc[c]);
     }
     Cx<R> tpre[2];
 #pragma unroll
@@ -360,15 +372,27 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
                 tpre[c2] = tab[(size_t)(line % ny) * (W + 2) + c];
         }
     }
+    // the pending rescale (its partial loads overlap the staging loads)
+    double sm1 = 0.0;
+    if (!RT && npart > 0) {
+        const double tot = block_sum_partials(partials, npart, red);
+        sm1 = 1.0 / sqrt(a.dV * tot) - 1.0;
+    }
+    const R sr = R(sm1);
+    // (j, k) of the staged lines: line0 = j0 + ny k0, advanced per line
+    const int j0 = line0 % ny, k0 = line0 / ny;
 #pragma unroll
     for (int c = 0; c < kXLoad; ++c) {
-        const int e = tid + c * 256;
-        if (e < L * nx) {
-            const int l = e / nx, t = e - l * nx;
+        if (lc[c] < L) {
+            const int l = lc[c], t = tc[c];
             const int line = line0 + l;
             Cx<R> v = {R(0), R(0)};
             if (line < nlines && t > 0) {
-                const int j = line % ny, k = line / ny;
+                int j = j0 + l, k = k0;
+                while (j >= ny) {
+                    j -= ny;
+                    ++k;
+                }
                 if (j > 0 && (a.dim == 2 || k > 0)) {
                     v = rescale(pre[c], sr);
                     const double x = a.x0 + t * a.hx, y = a.y0 + j * a.hy;
@@ -421,11 +445,16 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
     }
     __syncthreads();
 
-    for (int e = tid; e < L * nx; e += 256) {
-        const int l2 = e / nx, t = e - l2 * nx;
+#pragma unroll
+    for (int c = 0; c < kXLoad; ++c) {
+        const int l2 = lc[c], t = tc[c];
         const int line2 = line0 + l2;
-        if (line2 < nlines && t > 0) {
-            const int j2 = line2 % ny, k2 = line2 / ny;
+        if (l2 < L && line2 < nlines && t > 0) {
+            int j2 = j0 + l2, k2 = k0;
+            while (j2 >= ny) {
+                j2 -= ny;
+                ++k2;
+            }
             if (j2 > 0 && (a.dim == 2 || k2 > 0))
                 st<R>(dst, (int64_t)line2 * nx + t, lin[l2 * LS + t + t / S]);
         }

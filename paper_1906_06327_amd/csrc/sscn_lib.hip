@@ -1421,6 +1421,80 @@ int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *pla
     return 0;
 }
 
+int sscn_get_params(sscn_handle *h, sscn_params *out)
+{
+    if (!h || !out)
+        return fail(SSCN_EINVAL, "null argument");
+    *out = h->p;
+    return 0;
+}
+
+int sscn_converge(sscn_handle *h, int64_t max_steps, int check_every, double tol, double switch_tol,
+                  void *fp64_psi_dev, int64_t *steps_out, int *converged)
+{
+    if (!h || max_steps < 0 || check_every < 1 || !(tol > 0))
+        return fail(SSCN_EINVAL, "bad converge arguments");
+    if (h->p.mode != SSCN_IMAG)
+        return fail(SSCN_EINVAL, "convergence runs are imaginary-time runs");
+    if (h->p.precision == SSCN_C64 && !fp64_psi_dev)
+        return fail(SSCN_EINVAL, "a complex64 run needs the complex128 buffer for the refinement");
+    int64_t done = 0;
+    double prev = std::nan(""), best = INFINITY;
+    int hits = 0, stall = 0, count_prev = -1;
+    bool ok = false;
+    sscn_obs o;
+    while (done < max_steps) {
+        const int64_t k = std::min<int64_t>(check_every, max_steps - done);
+        int r = sscn_step(h, k);
+        if (r)
+            return r;
+        done += k;
+        r = sscn_observables(h, &o);
+        if (r)
+            return r;
+        const double d = std::fabs(o.mu - prev);
+        prev = o.mu;
+        if (h->p.precision == SSCN_C64) {
+            // FP32 plateau: |dmu| under switch_tol, or no new minimum for 5 checks
+            if (d < best) {
+                best = d;
+                stall = 0;
+            } else {
+                ++stall;
+            }
+            if (d < switch_tol || stall >= 5) {
+                r = sscn_set_mode(h, SSCN_IMAG, SSCN_C128, fp64_psi_dev);
+                if (r)
+                    return r;
+                prev = std::nan("");
+                hits = 0;
+                count_prev = -1;
+            }
+            continue;
+        }
+        if (d < tol) {
+            int c = 0;
+            r = sscn_vortex_count(h, 0.05, 3, &c);
+            if (r)
+                return r;
+            hits = (count_prev < 0 || c == count_prev) ? hits + 1 : 1;
+            count_prev = c;
+            if (hits >= 2) {
+                ok = true;
+                break;
+            }
+        } else {
+            hits = 0;
+            count_prev = -1;
+        }
+    }
+    if (steps_out)
+        *steps_out = done;
+    if (converged)
+        *converged = ok ? 1 : 0;
+    return 0;
+}
+
 int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, void *hip_stream, sscn_batch **out)
 {
     if (!params || !psi_devs || !out || n < 1)

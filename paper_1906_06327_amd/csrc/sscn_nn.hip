@@ -1,0 +1,201 @@
+// C ABI of the learned-initial-state network kernels (include/sscn_nn.h).
+#include "sscn_nn.h"
+#include "sscn_nn.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+
+using namespace sscn_nn;
+
+namespace {
+
+thread_local std::string g_nn_err;
+
+int nn_fail(int code, const std::string &msg)
+{
+    g_nn_err = msg;
+    return code;
+}
+
+int launched(const char *what)
+{
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return nn_fail(-5, std::string(what) + ": " + hipGetErrorString(e));
+    return 0;
+}
+
+int blocks(int64_t n) { return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256)); }
+
+}  // namespace
+
+extern "C" {
+
+const char *sscn_nn_last_error(void) { return g_nn_err.c_str(); }
+
+int sscn_nn_conv3x3(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
+                    int act, int out_f32, void *y, int ldy, int yoff, void *stream)
+{
+    if (!x || !w || !y || N < 1 || H < 1 || W < 1 || Cin < 16 || Cin % 16 || Cout < 16 || Cout % 16 ||
+        ldy < yoff + Cout || yoff < 0 || (act != ACT_NONE && act != ACT_LEAKY))
+        return nn_fail(-1, "bad conv3x3 arguments");
+    const int P = N * H * W;
+    dim3 grid((P + 63) / 64, Cout / 16);
+    hipStream_t st = (hipStream_t)stream;
+    const uint16_t *xs = (const uint16_t *)x, *ws = (const uint16_t *)w;
+    if (act == ACT_LEAKY && !out_f32)
+        hipLaunchKernelGGL((k_conv3x3<ACT_LEAKY, false>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
+                           y, ldy, yoff);
+    else if (act == ACT_LEAKY)
+        hipLaunchKernelGGL((k_conv3x3<ACT_LEAKY, true>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
+                           y, ldy, yoff);
+    else if (!out_f32)
+        hipLaunchKernelGGL((k_conv3x3<ACT_NONE, false>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
+                           y, ldy, yoff);
+    else
+        hipLaunchKernelGGL((k_conv3x3<ACT_NONE, true>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
+                           y, ldy, yoff);
+    return launched("conv3x3");
+}
+
+int sscn_nn_conv3x3_dgrad(const void *dy, int N, int H, int W, int Cout, const void *w, int Cin,
+                          void *wt_scratch, void *dx, int lddx, int dxoff, void *stream)
+{
+    if (!dy || !w || !wt_scratch || !dx || Cin % 16 || Cout % 16 || Cin < 16 || Cout < 16 || lddx < dxoff + Cin)
+        return nn_fail(-1, "bad conv3x3_dgrad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_wflip, dim3(blocks((int64_t)Cout * 9 * Cin)), dim3(256), 0, st, (const uint16_t *)w, Cout,
+                       Cin, (uint16_t *)wt_scratch);
+    const int P = N * H * W;
+    hipLaunchKernelGGL((k_conv3x3<ACT_NONE, false>), dim3((P + 63) / 64, Cin / 16), dim3(256), 0, st,
+                       (const uint16_t *)dy, N, H, W, Cout, (const uint16_t *)wt_scratch, nullptr, Cin, dx, lddx,
+                       dxoff);
+    return launched("conv3x3_dgrad");
+}
+
+int sscn_nn_wgrad_scratch(int N, int H, int W, int Cin, int Cout, int64_t *floats)
+{
+    if (!floats)
+        return nn_fail(-1, "null argument");
+    const int P = N * H * W;
+    const int nsplit = std::min(64, std::max(1, (P + 1023) / 1024));
+    *floats = (int64_t)nsplit * Cout * 9 * Cin + (int64_t)nsplit * Cout;
+    return 0;
+}
+
+int sscn_nn_conv3x3_wgrad(const void *x, int N, int H, int W, int Cin, const void *dy, int Cout, float *dw,
+                          float *db, float *scratch, int64_t scratch_floats, void *stream)
+{
+    if (!x || !dy || !dw || !scratch || Cin % 16 || Cout % 16 || Cin < 16 || Cout < 16)
+        return nn_fail(-1, "bad conv3x3_wgrad arguments");
+    int64_t need = 0;
+    sscn_nn_wgrad_scratch(N, H, W, Cin, Cout, &need);
+    if (scratch_floats < need)
+        return nn_fail(-1, "wgrad scratch too small");
+    const int P = N * H * W;
+    const int nsplit = std::min(64, std::max(1, (P + 1023) / 1024));
+    int chunk = (P + nsplit - 1) / nsplit;
+    chunk = (chunk + 15) / 16 * 16;
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsplit, Cout / 16, 9 * Cin / 16), dim3(64), 0, st,
+                       (const uint16_t *)x, N, H, W, Cin, (const uint16_t *)dy, Cout, chunk, scratch);
+    const int nw = Cout * 9 * Cin;
+    hipLaunchKernelGGL(k_sum_splits, dim3(blocks(nw)), dim3(256), 0, st, scratch, nsplit, nw, dw);
+    if (db) {
+        float *bp = scratch + (size_t)nsplit * nw;
+        hipLaunchKernelGGL(k_bias_grad, dim3(nsplit), dim3(256), 0, st, (const uint16_t *)dy, P, Cout, chunk, bp);
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(Cout)), dim3(256), 0, st, bp, nsplit, Cout, db);
+    }
+    return launched("conv3x3_wgrad");
+}
+
+int sscn_nn_act_bwd(void *dy, const void *y, int64_t n, void *stream)
+{
+    if (!dy || !y || n < 0)
+        return nn_fail(-1, "bad act_bwd arguments");
+    hipLaunchKernelGGL(k_act_bwd, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, (uint16_t *)dy,
+                       (const uint16_t *)y, (int)n);
+    return launched("act_bwd");
+}
+
+int sscn_nn_pool2(const void *x, int N, int H, int W, int C, void *y, void *stream)
+{
+    if (!x || !y || H % 2 || W % 2)
+        return nn_fail(-1, "bad pool2 arguments");
+    hipLaunchKernelGGL(k_pool2, dim3(blocks((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)x, N, H, W, C, (uint16_t *)y);
+    return launched("pool2");
+}
+
+int sscn_nn_pool2_bwd(const void *dy, int N, int H, int W, int C, void *dx, void *stream)
+{
+    if (!dy || !dx || H % 2 || W % 2)
+        return nn_fail(-1, "bad pool2_bwd arguments");
+    hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)dy, N, H, W, C, (uint16_t *)dx);
+    return launched("pool2_bwd");
+}
+
+int sscn_nn_up2(const void *x, int N, int H, int W, int C, void *y, int ldy, int yoff, void *stream)
+{
+    if (!x || !y || ldy < yoff + C)
+        return nn_fail(-1, "bad up2 arguments");
+    hipLaunchKernelGGL(k_up2, dim3(blocks((int64_t)N * 4 * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)x, N, H, W, C, (uint16_t *)y, ldy, yoff);
+    return launched("up2");
+}
+
+int sscn_nn_up2_bwd(const void *dy, int ldy, int yoff, int N, int H, int W, int C, void *dx, void *stream)
+{
+    if (!dy || !dx || ldy < yoff + C)
+        return nn_fail(-1, "bad up2_bwd arguments");
+    hipLaunchKernelGGL(k_up2_bwd, dim3(blocks((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)dy, ldy, yoff, N, H, W, C, (uint16_t *)dx);
+    return launched("up2_bwd");
+}
+
+int sscn_nn_chan_copy(const void *src, int lds, int soff, void *dst, int ldd, int doff, int P, int C,
+                      int accumulate, void *stream)
+{
+    if (!src || !dst || lds < soff + C || ldd < doff + C)
+        return nn_fail(-1, "bad chan_copy arguments");
+    hipLaunchKernelGGL(k_chan_copy, dim3(blocks((int64_t)P * C)), dim3(256), 0, (hipStream_t)stream,
+                       (const uint16_t *)src, lds, soff, (uint16_t *)dst, ldd, doff, P, C, accumulate);
+    return launched("chan_copy");
+}
+
+int sscn_nn_loss(const float *pred, int ld, const float *psi, int B, int S, double *stats, void *dpred,
+                 void *stream)
+{
+    if (!pred || !psi || !stats || ld < 2 || B < 1 || S < 1)
+        return nn_fail(-1, "bad loss arguments");
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(k_loss_stats, dim3(B), dim3(256), 0, st, pred, ld, psi, S, stats);
+    if (dpred)
+        hipLaunchKernelGGL(k_loss_grad, dim3(blocks((int64_t)B * S)), dim3(256), 0, st, pred, ld, psi, B, S, stats,
+                           (uint16_t *)dpred);
+    return launched("loss");
+}
+
+int sscn_nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
+                 int t, void *wbf16, void *stream)
+{
+    if (!w || !m || !v || !g || n < 0 || t < 1)
+        return nn_fail(-1, "bad adam arguments");
+    const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, w, m, v, g, (int)n, lr, b1, b2,
+                       eps, c1, c2, (uint16_t *)wbf16);
+    return launched("adam");
+}
+
+int sscn_nn_f32_to_bf16(const float *a, void *b, int64_t n, void *stream)
+{
+    if (!a || !b || n < 0)
+        return nn_fail(-1, "bad f32_to_bf16 arguments");
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, a, (uint16_t *)b, (int)n);
+    return launched("f32_to_bf16");
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+"""GPU tests of the learned-initial-state network kernels against the numpy
+reference oracle/unet_ref.py, called through the C ABI of include/sscn_nn.h.
+
+The convolution tests also check the matrix-core operand and result layout
+the kernels assume: any transposition or lane mix-up changes the result far
+beyond the tolerances.  Tolerances: products of bf16 operands are exact in
+fp32, so an fp32 output differs from the FP64 sum only by fp32 accumulation
+(bounded by 1e-5 times the sum of absolute terms for these depths); a bf16
+output can additionally sit one bf16 step (2^-7 relative) away where the
+two sums straddle a rounding boundary.
+"""
+import numpy as np
+import pytest
+
+from oracle import unet_ref as U
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def nn():
+    _need_gpu()
+    from paper_1906_06327_amd import nn as N
+    return N
+
+
+def to_bf(a):
+    """numpy -> device bf16 bit patterns (int16) and the float64 values."""
+    t = torch.tensor(np.asarray(a, np.float32)).to(torch.bfloat16)
+    return t.view(torch.int16).cuda(), t.float().numpy().astype(np.float64)
+
+
+def from_bf(t):
+    return t.cpu().view(torch.bfloat16).float().numpy().astype(np.float64)
+
+
+def f32(a):
+    return torch.tensor(np.asarray(a, np.float32)).cuda()
+
+
+def close_bf(gpu, ref, absum, name):
+    bad = np.abs(gpu - ref) > 2.0 ** -7 * np.abs(ref) + 2e-5 * absum + 1e-30
+    assert not bad.any(), f"{name}: {bad.sum()} of {bad.size} outside tolerance"
+
+
+@pytest.mark.parametrize("N,H,W,Cin,Cout,act", [(3, 13, 11, 48, 32, 1), (1, 8, 8, 16, 16, 0),
+                                                 (2, 24, 20, 160, 64, 1)])
+def test_conv3x3(nn, N, H, W, Cin, Cout, act):
+    rng = np.random.default_rng(N * 1000 + Cin)
+    xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
+    wd, w = to_bf(rng.standard_normal((Cout, 3, 3, Cin)) / np.sqrt(9 * Cin))
+    b = rng.standard_normal(Cout).astype(np.float32)
+    ref = U.conv3x3(x, w, b.astype(np.float64), act=act)
+    absum = U.conv3x3(np.abs(x), np.abs(w), np.abs(b).astype(np.float64))
+    y32 = torch.zeros((N, H, W, Cout), dtype=torch.float32, device="cuda")
+    nn.conv3x3(xd, N, H, W, Cin, wd, f32(b), Cout, act, y32, out_f32=True)
+    g = y32.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(g - ref) <= 1e-5 * absum + 1e-30)
+    # bf16 output into a channel slice of a wider tensor
+    ld, off = Cout + 32, 16
+    ybf = torch.full((N, H, W, ld), 7, dtype=torch.int16, device="cuda")
+    nn.conv3x3(xd, N, H, W, Cin, wd, f32(b), Cout, act, ybf, ldy=ld, yoff=off)
+    gb = from_bf(ybf)
+    close_bf(gb[..., off:off + Cout], ref, absum, "conv bf16")
+    untouched = ybf.cpu().numpy()
+    assert np.all(untouched[..., :off] == 7) and np.all(untouched[..., off + Cout:] == 7)
+
+
+def test_conv3x3_dgrad_and_wgrad(nn):
+    rng = np.random.default_rng(7)
+    N, H, W, Cin, Cout = 2, 12, 10, 32, 48
+    xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
+    wd, w = to_bf(rng.standard_normal((Cout, 3, 3, Cin)) / np.sqrt(9 * Cin))
+    dyd, dy = to_bf(rng.standard_normal((N, H, W, Cout)))
+    wt = torch.empty(9 * Cin * Cout, dtype=torch.int16, device="cuda")
+    ld, off = Cin + 16, 16
+    dx = torch.zeros((N, H, W, ld), dtype=torch.int16, device="cuda")
+    nn.conv3x3_dgrad(dyd, N, H, W, Cout, wd, Cin, wt, dx, lddx=ld, dxoff=off)
+    ref = U.conv3x3_dgrad(dy, w)
+    absum = U.conv3x3_dgrad(np.abs(dy), np.abs(w))
+    close_bf(from_bf(dx)[..., off:], ref, absum, "dgrad")
+    assert np.all(dx.cpu().numpy()[..., :off] == 0)
+
+    scr = torch.empty(nn.wgrad_scratch(N, H, W, Cin, Cout), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((Cout, 3, 3, Cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(Cout, dtype=torch.float32, device="cuda")
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw, db, scr)
+    rdw, rdb = U.conv3x3_wgrad(x, dy)
+    adw, _ = U.conv3x3_wgrad(np.abs(x), np.abs(dy))
+    assert np.all(np.abs(dw.cpu().numpy() - rdw) <= 1e-5 * adw + 1e-30)
+    assert np.allclose(db.cpu().numpy(), rdb, rtol=1e-5, atol=1e-4)
+
+
+def test_wgrad_many_splits_and_ragged_tail(nn):
+    # P = 2 * 45 * 37 = 3330 pixels: several pixel splits, last one partial
+    rng = np.random.default_rng(8)
+    N, H, W, Cin, Cout = 2, 45, 37, 16, 16
+    xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
+    dyd, dy = to_bf(rng.standard_normal((N, H, W, Cout)))
+    scr = torch.empty(nn.wgrad_scratch(N, H, W, Cin, Cout), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((Cout, 3, 3, Cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(Cout, dtype=torch.float32, device="cuda")
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw, db, scr)
+    rdw, rdb = U.conv3x3_wgrad(x, dy)
+    adw, _ = U.conv3x3_wgrad(np.abs(x), np.abs(dy))
+    assert np.all(np.abs(dw.cpu().numpy() - rdw) <= 1e-5 * adw + 1e-30)
+    assert np.allclose(db.cpu().numpy(), rdb, rtol=1e-5, atol=1e-3)
+    # deterministic: a second call gives the same bits
+    dw2 = torch.zeros_like(dw)
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw2, None, scr)
+    assert torch.equal(dw, dw2)
+
+
+def test_elementwise_and_resampling(nn):
+    rng = np.random.default_rng(9)
+    N, H, W, C = 2, 8, 6, 32
+    xd, x = to_bf(rng.standard_normal((N, H, W, C)))
+    # pooling and its gradient
+    y = torch.zeros((N, H // 2, W // 2, C), dtype=torch.int16, device="cuda")
+    nn.pool2(xd, N, H, W, C, y)
+    assert np.array_equal(from_bf(y), U.bf16(U.pool2(x)))
+    dx = torch.zeros_like(xd)
+    nn.pool2_bwd(y, N, H, W, C, dx)
+    assert np.array_equal(from_bf(dx), U.bf16(U.pool2_bwd(from_bf(y))))
+    # upsampling into a channel slice and its gradient
+    ld = C + 16
+    up = torch.zeros((N, 2 * H, 2 * W, ld), dtype=torch.int16, device="cuda")
+    nn.up2(xd, N, H, W, C, up, ld, 16)
+    assert np.array_equal(from_bf(up)[..., 16:], U.up2(x))
+    g = torch.zeros_like(xd)
+    nn.up2_bwd(up, ld, 16, N, H, W, C, g)
+    assert np.array_equal(from_bf(g), U.bf16(U.up2_bwd(U.up2(x))))
+    # channel copy and accumulate
+    dst = torch.zeros((N, H, W, 48), dtype=torch.int16, device="cuda")
+    nn.chan_copy(xd, C, 0, dst, 48, 8, N * H * W, 24)
+    nn.chan_copy(xd, C, 8, dst, 48, 8, N * H * W, 24, accumulate=True)
+    got = from_bf(dst)
+    assert np.array_equal(got[..., 8:32], U.bf16(x[..., 0:24] + x[..., 8:32]))
+    assert np.all(got[..., :8] == 0) and np.all(got[..., 32:] == 0)
+    # leaky-ReLU gradient
+    dyd, dy = to_bf(rng.standard_normal((N, H, W, C)))
+    nn.act_bwd(dyd, xd)
+    # the kernel scales by the fp32 value of 0.1 in fp32 arithmetic
+    scaled = (np.float32(U.LEAK) * dy.astype(np.float32)).astype(np.float64)
+    assert np.array_equal(from_bf(dyd), U.bf16(np.where(x > 0, dy, scaled)))
+
+
+def test_loss_and_adam(nn):
+    rng = np.random.default_rng(10)
+    B, H, W, ld = 3, 9, 7, 16
+    pred = rng.standard_normal((B, H, W, ld)).astype(np.float32)
+    psi = rng.standard_normal((B, H, W, 2)).astype(np.float32)
+    stats = torch.zeros(4 * B, dtype=torch.float64, device="cuda")
+    dpred = torch.full((B, H, W, ld), 5, dtype=torch.int16, device="cuda")
+    nn.loss(f32(pred), ld, f32(psi), B, H * W, stats, dpred)
+    rs = U.loss_stats(pred[..., :2].astype(np.float64), psi.astype(np.float64))
+    assert np.allclose(stats.cpu().numpy().reshape(B, 4), rs, rtol=1e-13, atol=1e-12)
+    rg = U.loss_grad(pred[..., :2].astype(np.float64), psi.astype(np.float64))
+    got = from_bf(dpred)
+    scale = 2.0 * (np.abs(pred[..., :2]) + np.abs(psi).sum(-1, keepdims=True)) / B
+    close_bf(got[..., :2], rg, scale, "loss grad")
+    assert np.all(got[..., 2:] == 0)
+
+    n = 1000
+    w = rng.standard_normal(n).astype(np.float32)
+    m = np.zeros(n, np.float32)
+    v = np.zeros(n, np.float32)
+    wd, md, vd = f32(w), f32(m), f32(v)
+    wbf = torch.zeros(n, dtype=torch.int16, device="cuda")
+    rw, rm, rv = w.astype(np.float64), m.astype(np.float64), v.astype(np.float64)
+    for t in range(1, 4):
+        gr = rng.standard_normal(n).astype(np.float32)
+        nn.adam(wd, md, vd, f32(gr), 1e-2, 0.9, 0.999, 1e-8, t, wbf)
+        rw, rm, rv = U.adam(rw, rm, rv, gr.astype(np.float64), 1e-2, 0.9, 0.999, 1e-8, t)
+    assert np.allclose(wd.cpu().numpy(), rw, rtol=1e-5, atol=1e-6)
+    assert np.array_equal(from_bf(wbf), U.bf16(wd.cpu().numpy()))
+
+
+@pytest.mark.parametrize("chans,bott,N,H", [((16, 32), 32, 2, 16), ((16, 32, 64, 64), 128, 2, 32)])
+def test_unet_forward_backward(nn, chans, bott, N, H):
+    """Whole network on the GPU against the reference with the same bf16
+    rounding points.  The two differ only where fp32 and FP64 accumulation
+    tip a bf16 rounding the other way, and such flips propagate, so the
+    comparison is in relative L2 norm: 2e-2 for the output; for a weight
+    gradient, 5e-2 or 0.6 times the whole effect of bf16 rounding on that
+    gradient (the bf16 reference against the FP64 reference), whichever is
+    larger.  A wrong index or operand layout gives errors of order one."""
+    rng = np.random.default_rng(11)
+    net = nn.UNet(N, H, H, chans=chans, bott=bott, seed=3)
+    # non-zero biases so the bias path is exercised
+    for name in net.b:
+        net.b[name].copy_(torch.tensor(0.05 * rng.standard_normal(net.b[name].numel()), dtype=torch.float32))
+    params = {k: (v[0].astype(np.float64), v[1].astype(np.float64)) for k, v in net.params_numpy().items()}
+    xin = np.zeros((N, H, H, 16))
+    xin[..., :5] = rng.standard_normal((N, H, H, 5))
+    xd, _ = to_bf(xin)
+    out = net.forward(xd).cpu().numpy().astype(np.float64)
+    ref, A = U.unet_forward(xin, params, chans, bott, bf16_on=True)
+    rel = np.linalg.norm(out - ref) / np.linalg.norm(ref)
+    assert rel < 2e-2, rel
+    psi = rng.standard_normal((N, H, H, 2)).astype(np.float32)
+    lossv = net.loss_and_grad(f32(psi))
+    rloss = U.loss_value(out[..., :2], psi.astype(np.float64))
+    assert np.allclose(lossv, rloss, rtol=1e-9)
+    dout = np.zeros((N, H, H, 16))
+    dout[..., :2] = U.loss_grad(out[..., :2], psi.astype(np.float64))
+    net.backward(net.gacts["out"])
+    G = U.unet_backward(dout, A, chans, bott, bf16_on=True)
+    out64, A64 = U.unet_forward(U.bf16(xin), params, chans, bott, bf16_on=False)
+    dout64 = np.zeros_like(dout)
+    dout64[..., :2] = U.loss_grad(out64[..., :2], psi.astype(np.float64))
+    G64 = U.unet_backward(dout64, A64, chans, bott, bf16_on=False)
+
+    def rel(a, b):
+        return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+    for name, _, _, _ in net.specs:
+        for k, got in enumerate((net.gw[name].cpu().numpy(), net.gb[name].cpu().numpy())):
+            err, floor = rel(got, G[name][k]), rel(G64[name][k], G[name][k])
+            assert err < max(5e-2, 0.6 * floor), (name, k, err, floor)
+
+
+def test_unet_training_reduces_loss(nn):
+    """Adam on a fixed batch of smooth targets: the loss must fall well
+    below its initial value."""
+    N, H = 4, 32
+    net = nn.UNet(N, H, H, chans=(16, 32), bott=32, seed=5)
+    ax = np.linspace(-1, 1, H)
+    X, Y = np.meshgrid(ax, ax)
+    xin = np.zeros((N, H, H, 16))
+    psi = np.zeros((N, H, H, 2))
+    for k in range(N):
+        xin[k, ..., 0], xin[k, ..., 1], xin[k, ..., 2] = X, Y, 0.25 * k
+        amp = np.exp(-(X ** 2 + Y ** 2) / (0.2 + 0.1 * k))
+        psi[k, ..., 0] = amp * np.cos(2 * X)
+        psi[k, ..., 1] = amp * np.sin(2 * Y)
+    xd, _ = to_bf(xin)
+    pd = f32(psi)
+    first = None
+    for it in range(300):
+        net.forward(xd)
+        lv = net.loss_and_grad(pd).mean()
+        first = lv if first is None else first
+        net.backward(net.gacts["out"])
+        net.adam_step(lr=2e-3)
+    assert np.isfinite(lv) and lv < 0.2 * first, (first, lv)

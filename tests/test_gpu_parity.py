@@ -334,3 +334,27 @@ def test_fused_plan_rejected_in_3d(P):
     with pytest.raises(P.SSCNError):
         s.set_plan(2)
     s.close()
+
+
+def test_converge_fp64_and_mixed_precision(P):
+    """sscn_converge: the FP64 run stops at the criterion and its state is the
+    oracle's after the same number of steps; the complex64 run switches to
+    complex128 at its plateau and reaches the same converged mu."""
+    announce("converge fp64 / c64->c128")
+    cfg = dict(dim=2, nx=56, ny=52, nz=1, hx=0.25, hy=0.25, hz=0.1, gamma=1.0, nu=1.1,
+               lam=1.0, g=25.0, omega=0.35, dt=0.01, mode=0, precision=0)
+    ph = W.phase_field(61, 52, 56)
+    s, op = both(P, cfg)
+    s.init_state(1, ph, 1.0)
+    steps, ok = s.converge(200000, check_every=20, tol=1e-9)
+    assert ok and steps < 200000
+    ref = O.step(op, O.init_state(op, 1, ph, 1.0), steps)
+    assert rel(s.get_state(), ref) <= TOL64
+    mu64 = s.observables()["mu"]
+    s.close()
+    s32 = P.Solver(W.solver_params(cfg, precision=1))
+    s32.init_state(1, ph, 1.0)
+    steps32, ok32 = s32.converge(200000, check_every=20, tol=1e-9, switch_tol=1e-6)
+    assert ok32 and s32.params.precision == 0 and s32.psi.dtype.itemsize == 16
+    assert abs(s32.observables()["mu"] - mu64) < 1e-7
+    s32.close()

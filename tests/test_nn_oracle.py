@@ -1,0 +1,111 @@
+"""Pins of the reference U-Net (oracle/unet_ref.py): every backward formula
+against central finite differences of the FP64 forward pass, the loss
+against a brute-force minimisation over the global phase, and bf16 rounding
+against its definition."""
+import numpy as np
+import pytest
+
+from oracle import unet_ref as U
+
+
+def fd(f, x, idx, eps=1e-6):
+    xp = x.copy()
+    xm = x.copy()
+    xp[idx] += eps
+    xm[idx] -= eps
+    return (f(xp) - f(xm)) / (2 * eps)
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5e-3, 3.0e38, 0.0])
+    r = U.bf16(vals)
+    assert r[0] == 1.0
+    assert r[1] == 1.0  # tie to even: 1 + 2^-8 is halfway between 1 and 1 + 2^-7
+    assert r[2] == 1.0 + 2 ** -7
+    # every result has at most 8 significant bits
+    m, _ = np.frexp(r[np.isfinite(r) & (r != 0)])
+    assert np.all(m * 2 ** 8 == np.round(m * 2 ** 8))
+
+
+def test_conv_gradients_match_finite_differences():
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal((2, 5, 6, 3))
+    w = rng.standard_normal((4, 3, 3, 3))
+    b = rng.standard_normal(4)
+    dy = rng.standard_normal((2, 5, 6, 4))
+
+    def L_of_x(xx):
+        return float((U.conv3x3(xx, w, b) * dy).sum())
+
+    def L_of_w(ww):
+        return float((U.conv3x3(x, ww, b) * dy).sum())
+
+    dx = U.conv3x3_dgrad(dy, w)
+    dw, db = U.conv3x3_wgrad(x, dy)
+    for idx in [(0, 0, 0, 0), (1, 4, 5, 2), (0, 2, 3, 1)]:
+        assert abs(dx[idx] - fd(L_of_x, x, idx)) < 1e-6
+    for idx in [(0, 0, 0, 0), (3, 2, 1, 2), (1, 1, 1, 1)]:
+        assert abs(dw[idx] - fd(L_of_w, w, idx)) < 1e-6
+    assert np.allclose(db, dy.sum(axis=(0, 1, 2)))
+
+
+def test_resampling_adjoints():
+    rng = np.random.default_rng(2)
+    x = rng.standard_normal((2, 8, 6, 3))
+    y = rng.standard_normal((2, 4, 3, 3))
+    # <pool(x), y> = <x, pool_bwd(y)> and <up(y), x> = <y, up_bwd(x)>
+    assert np.isclose((U.pool2(x) * y).sum(), (x * U.pool2_bwd(y)).sum())
+    assert np.isclose((U.up2(y) * x).sum(), (y * U.up2_bwd(x)).sum())
+
+
+def test_loss_is_minimum_over_global_phase():
+    rng = np.random.default_rng(3)
+    pred = rng.standard_normal((3, 4, 5, 2))
+    psi = rng.standard_normal((3, 4, 5, 2))
+    val = U.loss_value(pred, psi)
+    p = pred[..., 0] + 1j * pred[..., 1]
+    t = psi[..., 0] + 1j * psi[..., 1]
+    phis = np.linspace(0, 2 * np.pi, 20001)
+    for b in range(3):
+        brute = min(np.sum(np.abs(p[b] - np.exp(1j * f) * t[b]) ** 2) for f in phis[::50])
+        fine = np.array([np.sum(np.abs(p[b] - np.exp(1j * f) * t[b]) ** 2) for f in phis])
+        assert val[b] <= brute + 1e-12
+        assert abs(val[b] - fine.min()) < 1e-6
+    g = U.loss_grad(pred, psi)
+    f = lambda pp: float(U.loss_value(pp, psi).mean())
+    for idx in [(0, 1, 2, 0), (2, 3, 4, 1), (1, 0, 0, 1)]:
+        assert abs(g[idx] - fd(f, pred, idx)) < 1e-6
+
+
+@pytest.mark.parametrize("chans,bott", [((16, 16), 16), ((16, 32), 32)])
+def test_unet_backprop_matches_finite_differences(chans, bott):
+    rng = np.random.default_rng(4)
+    specs = U.layer_specs(chans, bott)
+    params = {n: (rng.standard_normal((co, 3, 3, ci)) * np.sqrt(2 / (9 * ci)),
+                  0.1 * rng.standard_normal(co)) for n, ci, co, _ in specs}
+    x = rng.standard_normal((2, 8, 8, 16))
+    psi = rng.standard_normal((2, 8, 8, 2))
+
+    def total(pp):
+        out, _ = U.unet_forward(x, pp, chans, bott, bf16_on=False)
+        return float(U.loss_value(out[..., :2], psi).mean())
+
+    out, A = U.unet_forward(x, params, chans, bott, bf16_on=False)
+    dout = np.zeros_like(out)
+    dout[..., :2] = U.loss_grad(out[..., :2], psi)
+    G = U.unet_backward(dout, A, chans, bott, bf16_on=False)
+    for name in ("enc0a", "dec0a", "bota", "out", f"dec{len(chans) - 1}b"):
+        w, b = params[name]
+        for idx in [(0, 0, 0, 0), (w.shape[0] - 1, 2, 1, w.shape[3] - 1)]:
+            def f_w(ww, name=name):
+                pp = dict(params)
+                pp[name] = (ww, params[name][1])
+                return total(pp)
+            num = fd(f_w, w, idx, eps=1e-5)
+            assert abs(G[name][0][idx] - num) <= 1e-6 + 1e-5 * abs(num), (name, idx)
+        def f_b(bb, name=name):
+            pp = dict(params)
+            pp[name] = (params[name][0], bb)
+            return total(pp)
+        num = fd(f_b, b, (0,), eps=1e-5)
+        assert abs(G[name][1][0] - num) <= 1e-6 + 1e-5 * abs(num), name
