@@ -153,8 +153,8 @@ int sscn_get_params(sscn_handle *h, sscn_params *out);
  * tol at two consecutive checks with the vortex count (density_frac 0.05,
  * box 3) unchanged between them.  The paper runs a fixed number of steps;
  * this criterion is the library's.  In complex64 mode the bulk runs in FP32
- * until its plateau (|dmu| < switch_tol, or no new minimum of |dmu| for 5
- * checks), then the state is upcast into fp64_psi_dev (caller-owned
+ * until its plateau (|dmu| < switch_tol, or, once |dmu| < 10 switch_tol, no
+ * new minimum of |dmu| for 5 checks), then the state is upcast into fp64_psi_dev (caller-owned
  * complex128 buffer, borrowed from then on as by sscn_set_mode) and the run
  * continues in FP64 to tol.  *steps_out = steps taken, *converged = 1 if the
  * criterion was met within max_steps.  Synchronises at every check. */
@@ -226,6 +226,16 @@ int sscn_batch_reset(sscn_batch *b);
 
 /* Copy instance k's state to a host buffer.  Synchronises the stream. */
 int sscn_batch_get_state(sscn_batch *b, int k, void *host_psi);
+
+/* The caller has written a state into instance k's buffer (psi_devs[k] of
+ * sscn_batch_init, e.g. a learned initial state): zero its walls and
+ * normalise it to h_x h_y sum |psi|^2 = 1, the finishing steps of the
+ * initial state of Eq. (fun) (Sec. 2).  Synchronises the stream. */
+int sscn_batch_set_state_device(sscn_batch *b, int k);
+
+/* Vortex count of instance k as sscn_vortex_count (phase winding of each
+ * plaquette, density mask).  Synchronises the stream. */
+int sscn_batch_vortex_count(sscn_batch *b, int k, double density_frac, int box, int *count);
 
 void sscn_batch_destroy(sscn_batch *b);
 

@@ -69,15 +69,26 @@ int sscn_nn_up2_bwd(const void *dy, int ldy, int yoff, int N, int H, int W, int 
 int sscn_nn_chan_copy(const void *src, int lds, int soff, void *dst, int ldd, int doff, int P, int C,
                       int accumulate, void *stream);
 
-/* Phase-aligned loss of B samples of S points: prediction pred (fp32, ld
- * channels, Re and Im in channels 0 and 1), target psi (fp32 interleaved
- * Re, Im).  stats[4b..4b+3] = Re<psi,pred>, Im<psi,pred>, |pred|^2, |psi|^2
- * (fp64, device); the loss of sample b is |pred|^2 + |psi|^2 - 2|<psi,pred>|,
- * i.e. |pred - e^{i phi} psi|^2 minimised over the global phase phi.  If
- * dpred is not NULL it receives the gradient of the batch-mean loss, bf16,
- * ld channels (channels beyond 1 zero). */
-int sscn_nn_loss(const float *pred, int ld, const float *psi, int B, int S, double *stats, void *dpred,
+/* Phase-aligned loss of B samples of S points against K candidate targets
+ * each (the images of one converged state under the symmetries of the
+ * rotating problem).  Prediction pred: fp32, ld channels, Re and Im in
+ * channels 0 and 1; targets psi: fp32 [B][K][S] interleaved Re, Im.
+ * stats[(b*K + k)*4 + 0..3] = Re<psi_bk,pred_b>, Im<psi_bk,pred_b>,
+ * |pred_b|^2, |psi_bk|^2 (fp64, device).  The loss of (b, k) is
+ * |pred|^2 + |psi|^2 - 2|<psi,pred>|, i.e. |pred - e^{i phi} psi|^2
+ * minimised over the global phase phi; the loss of sample b is the least
+ * over k.  If dpred is not NULL it receives the gradient of the batch-mean
+ * loss (through the least candidate, the first on ties), bf16, ld channels
+ * (channels beyond 1 zero). */
+int sscn_nn_loss(const float *pred, int ld, const float *psi, int B, int K, int S, double *stats, void *dpred,
                  void *stream);
+
+/* Solver state to training target and back.  psi_to_f32: out[2q + 0/1] =
+ * scale * Re/Im psi[q] for S points of a complex128 (precision 0) or
+ * complex64 (precision 1) interleaved device buffer.  f32_to_psi: psi[q] =
+ * scale * (pred[q*ld], pred[q*ld + 1]), written in the given precision. */
+int sscn_nn_psi_to_f32(const void *psi, int precision, int64_t S, float scale, float *out, void *stream);
+int sscn_nn_f32_to_psi(const float *pred, int ld, int64_t S, double scale, void *psi, int precision, void *stream);
 
 /* One Adam step (t >= 1) on fp32 master weights w with state m, v and
  * gradient g; if wbf16 is not NULL the updated weights are also written

@@ -83,32 +83,46 @@ def up2_bwd(dy):
     return dy.reshape(N, H // 2, 2, W // 2, 2, C).sum(axis=(2, 4))
 
 
+def _cands(psi):
+    """Targets as (B, K, H, W, 2): a single target per sample is K = 1."""
+    return psi[:, None] if psi.ndim == 4 else psi
+
+
 def loss_stats(pred, psi):
-    """Per sample: Re<psi,pred>, Im<psi,pred>, |pred|^2, |psi|^2 (pred and psi
-    are (N, H, W, 2) real/imaginary pairs)."""
-    pr, pi = pred[..., 0], pred[..., 1]
+    """Per sample b and candidate k: Re<psi_bk,pred_b>, Im<psi_bk,pred_b>,
+    |pred_b|^2, |psi_bk|^2 (pred (B, H, W, 2), psi (B, [K,] H, W, 2) real and
+    imaginary pairs).  Shape (B, K, 4)."""
+    psi = _cands(psi)
+    pr, pi = pred[:, None, ..., 0], pred[:, None, ..., 1]
     tr, ti = psi[..., 0], psi[..., 1]
-    ax = (1, 2)
+    ax = (2, 3)
+    pp = np.broadcast_to((pr * pr + pi * pi).sum(ax), tr.shape[:2])
     return np.stack([(tr * pr + ti * pi).sum(ax), (tr * pi - ti * pr).sum(ax),
-                     (pr * pr + pi * pi).sum(ax), (tr * tr + ti * ti).sum(ax)], axis=1)
+                     pp, (tr * tr + ti * ti).sum(ax)], axis=2)
 
 
 def loss_value(pred, psi):
+    """min over candidates k and global phases phi of |pred - e^{i phi} psi_k|^2."""
     s = loss_stats(pred, psi)
-    return s[:, 2] + s[:, 3] - 2.0 * np.hypot(s[:, 0], s[:, 1])
+    return (s[..., 2] + s[..., 3] - 2.0 * np.hypot(s[..., 0], s[..., 1])).min(axis=1)
 
 
 def loss_grad(pred, psi):
-    """Gradient of the batch-mean phase-aligned loss with respect to pred."""
+    """Gradient of the batch-mean loss with respect to pred (through the
+    nearest candidate, the first on ties)."""
+    psi = _cands(psi)
     s = loss_stats(pred, psi)
-    mag = np.hypot(s[:, 0], s[:, 1])
-    cr = np.where(mag > 0, s[:, 0] / np.where(mag > 0, mag, 1), 1.0)[:, None, None]
-    ci = np.where(mag > 0, s[:, 1] / np.where(mag > 0, mag, 1), 0.0)[:, None, None]
-    tr, ti = psi[..., 0], psi[..., 1]
+    lk = s[..., 2] + s[..., 3] - 2.0 * np.hypot(s[..., 0], s[..., 1])
+    kb = np.argmin(lk, axis=1)
     B = pred.shape[0]
     g = np.zeros_like(pred)
-    g[..., 0] = 2.0 * (pred[..., 0] - (cr * tr - ci * ti)) / B
-    g[..., 1] = 2.0 * (pred[..., 1] - (cr * ti + ci * tr)) / B
+    for b in range(B):
+        sr, si = s[b, kb[b], 0], s[b, kb[b], 1]
+        mag = np.hypot(sr, si)
+        cr, ci = (sr / mag, si / mag) if mag > 0 else (1.0, 0.0)
+        tr, ti = psi[b, kb[b], ..., 0], psi[b, kb[b], ..., 1]
+        g[b, ..., 0] = 2.0 * (pred[b, ..., 0] - (cr * tr - ci * ti)) / B
+        g[b, ..., 1] = 2.0 * (pred[b, ..., 1] - (cr * ti + ci * tr)) / B
     return g
 
 

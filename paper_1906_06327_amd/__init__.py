@@ -26,7 +26,7 @@ EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
            "sscn_solver_info", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
-           "sscn_batch_destroy",
+           "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_destroy",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -88,6 +88,9 @@ def lib():
         L.sscn_batch_run.argtypes = [vp, i64, ctypes.c_int, ctypes.c_double, ctypes.POINTER(i64)]
         L.sscn_batch_reset.argtypes = [vp]
         L.sscn_batch_get_state.argtypes = [vp, ctypes.c_int, vp]
+        L.sscn_batch_set_state_device.argtypes = [vp, ctypes.c_int]
+        L.sscn_batch_vortex_count.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                              ctypes.POINTER(ctypes.c_int)]
         L.sscn_batch_destroy.argtypes = [vp]
         L.sscn_batch_destroy.restype = None
         L.sscn_destroy.argtypes = [vp]
@@ -315,6 +318,16 @@ class Batch:
         out = np.empty((p.ny, p.nx), dtype=dtype)
         _check(lib().sscn_batch_get_state(self._h, int(k), out.ctypes.data))
         return out
+
+    def set_state_device(self, k):
+        """Instance k's tensor self.psi[k] was written in place: zero its
+        walls and normalise it."""
+        _check(lib().sscn_batch_set_state_device(self._h, int(k)))
+
+    def vortex_count(self, k, density_frac=0.05, box=3):
+        c = ctypes.c_int()
+        _check(lib().sscn_batch_vortex_count(self._h, int(k), float(density_frac), int(box), ctypes.byref(c)))
+        return c.value
 
     def close(self):
         if getattr(self, "_h", None):

@@ -903,16 +903,28 @@ __global__ __launch_bounds__(256) void k_norm_partials(const typename Vec<R>::T 
         partials[blockIdx.x] = b;
 }
 
-// psi_dst = s psi_src with s = 1/sqrt(dV sum partials).
+// psi_dst = s psi_src with s = 1/sqrt(dV sum partials).  Near s = 1 (the
+// per-step renormalisation) as psi + (s - 1) psi, which keeps the small
+// correction exact in FP32; otherwise (a state of arbitrary scale) as the
+// product s psi, since s - 1 rounded to FP32 would then carry a relative
+// error of ulp(1) / s.
 template <class R>
 __global__ __launch_bounds__(256) void k_rescale(const typename Vec<R>::T *src, typename Vec<R>::T *dst, int64_t n,
                                                  double dV, const double *partials, int npart)
 {
     __shared__ double red[8];
-    const double sm1 = 1.0 / sqrt(dV * block_sum_partials(partials, npart, red)) - 1.0;
-    const R sr = R(sm1);
-    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
-        st<R>(dst, p, rescale(ld<R>(src, p), sr));
+    const double s = 1.0 / sqrt(dV * block_sum_partials(partials, npart, red));
+    if (fabs(s - 1.0) < 0.25) {
+        const R sr = R(s - 1.0);
+        for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
+            st<R>(dst, p, rescale(ld<R>(src, p), sr));
+    } else {
+        const R sc = R(s);
+        for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+            const Cx<R> v = ld<R>(src, p);
+            st<R>(dst, p, Cx<R>{v.re * sc, v.im * sc});
+        }
+    }
 }
 
 template <class R>

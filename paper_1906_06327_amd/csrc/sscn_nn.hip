@@ -166,17 +166,45 @@ int sscn_nn_chan_copy(const void *src, int lds, int soff, void *dst, int ldd, in
     return launched("chan_copy");
 }
 
-int sscn_nn_loss(const float *pred, int ld, const float *psi, int B, int S, double *stats, void *dpred,
+int sscn_nn_loss(const float *pred, int ld, const float *psi, int B, int K, int S, double *stats, void *dpred,
                  void *stream)
 {
-    if (!pred || !psi || !stats || ld < 2 || B < 1 || S < 1)
+    if (!pred || !psi || !stats || ld < 2 || B < 1 || K < 1 || S < 1)
         return nn_fail(-1, "bad loss arguments");
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_loss_stats, dim3(B), dim3(256), 0, st, pred, ld, psi, S, stats);
+    hipLaunchKernelGGL(k_loss_stats, dim3(B * K), dim3(256), 0, st, pred, ld, psi, K, S, stats);
     if (dpred)
-        hipLaunchKernelGGL(k_loss_grad, dim3(blocks((int64_t)B * S)), dim3(256), 0, st, pred, ld, psi, B, S, stats,
+        hipLaunchKernelGGL(k_loss_grad, dim3(blocks((int64_t)B * S)), dim3(256), 0, st, pred, ld, psi, B, K, S, stats,
                            (uint16_t *)dpred);
     return launched("loss");
+}
+
+int sscn_nn_psi_to_f32(const void *psi, int precision, int64_t S, float scale, float *out, void *stream)
+{
+    if (!psi || !out || S < 1 || (precision != 0 && precision != 1))
+        return nn_fail(-1, "bad psi_to_f32 arguments");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_psi_to_f32<double>, dim3(blocks(2 * S)), dim3(256), 0, st, (const double *)psi, S, scale,
+                           out);
+    else
+        hipLaunchKernelGGL(k_psi_to_f32<float>, dim3(blocks(2 * S)), dim3(256), 0, st, (const float *)psi, S, scale,
+                           out);
+    return launched("psi_to_f32");
+}
+
+int sscn_nn_f32_to_psi(const float *pred, int ld, int64_t S, double scale, void *psi, int precision, void *stream)
+{
+    if (!pred || !psi || ld < 2 || S < 1 || (precision != 0 && precision != 1))
+        return nn_fail(-1, "bad f32_to_psi arguments");
+    hipStream_t st = (hipStream_t)stream;
+    if (precision == 0)
+        hipLaunchKernelGGL(k_f32_to_psi<double>, dim3(blocks(2 * S)), dim3(256), 0, st, pred, ld, S, scale,
+                           (double *)psi);
+    else
+        hipLaunchKernelGGL(k_f32_to_psi<float>, dim3(blocks(2 * S)), dim3(256), 0, st, pred, ld, S, scale,
+                           (float *)psi);
+    return launched("f32_to_psi");
 }
 
 int sscn_nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,

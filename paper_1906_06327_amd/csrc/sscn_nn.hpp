@@ -261,19 +261,22 @@ __global__ __launch_bounds__(256) void k_chan_copy(const uint16_t *__restrict__ 
     }
 }
 
-// Phase-aligned loss, per sample b (S = H*W points, prediction in channels
-// 0,1 of pred (fp32, ld channels), target psi interleaved fp32):
-// stats[b] = {Re <psi, pred>, Im <psi, pred>, |pred|^2, |psi|^2}.  One
-// 256-thread block per sample, fixed-order reduction.
+// Phase-aligned loss against K candidate targets per sample (the images of
+// one target under the symmetries of the problem).  Prediction in channels
+// 0,1 of pred (fp32, ld channels, S = H*W points per sample); targets psi
+// [B][K][S] interleaved fp32.  stats[b][k] = {Re <psi_bk, pred_b>,
+// Im <psi_bk, pred_b>, |pred_b|^2, |psi_bk|^2}.  One 256-thread block per
+// (b, k), fixed-order reduction.
 __global__ __launch_bounds__(256) void k_loss_stats(const float *__restrict__ pred, int ld,
-                                                    const float *__restrict__ psi, int S, double *__restrict__ stats)
+                                                    const float *__restrict__ psi, int K, int S,
+                                                    double *__restrict__ stats)
 {
     __shared__ double red[4][8];
-    const int b = blockIdx.x;
+    const int bk = blockIdx.x, b = bk / K;
     double a[4] = {0, 0, 0, 0};
     for (int q = threadIdx.x; q < S; q += 256) {
         const float pr = pred[((size_t)b * S + q) * ld], pi = pred[((size_t)b * S + q) * ld + 1];
-        const float tr = psi[((size_t)b * S + q) * 2], ti = psi[((size_t)b * S + q) * 2 + 1];
+        const float tr = psi[((size_t)bk * S + q) * 2], ti = psi[((size_t)bk * S + q) * 2 + 1];
         a[0] += (double)tr * pr + (double)ti * pi;
         a[1] += (double)tr * pi - (double)ti * pr;
         a[2] += (double)pr * pr + (double)pi * pi;
@@ -288,29 +291,67 @@ __global__ __launch_bounds__(256) void k_loss_stats(const float *__restrict__ pr
     }
     __syncthreads();
     if (threadIdx.x < 4)
-        stats[b * 4 + threadIdx.x] = (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
+        stats[(size_t)bk * 4 + threadIdx.x] =
+            (red[threadIdx.x][0] + red[threadIdx.x][1]) + (red[threadIdx.x][2] + red[threadIdx.x][3]);
 }
 
-// Loss gradient: with e^{i phi} = <psi, pred> / |<psi, pred>|, the loss of
-// sample b is |pred - e^{i phi} psi|^2 (its minimum over the global phase) and
-// its gradient 2 (pred - e^{i phi} psi); scaled by 1/B and written as bf16
+// Loss of sample b against candidate k: |pred|^2 + |psi_k|^2 - 2 |<psi_k, pred>|,
+// the minimum over the global phase phi of |pred - e^{i phi} psi_k|^2.
+__device__ __forceinline__ double cand_loss(const double *st)
+{
+    return st[2] + st[3] - 2.0 * sqrt(st[0] * st[0] + st[1] * st[1]);
+}
+
+// Loss gradient: the sample's loss is that of its nearest candidate k* (the
+// first on ties); with e^{i phi} = <psi_k*, pred> / |<psi_k*, pred>| its
+// gradient is 2 (pred - e^{i phi} psi_k*), scaled by 1/B and written as bf16
 // into channels 0,1 of dpred (ld channels, the other channels zero).
 __global__ __launch_bounds__(256) void k_loss_grad(const float *__restrict__ pred, int ld,
-                                                   const float *__restrict__ psi, int B, int S,
+                                                   const float *__restrict__ psi, int B, int K, int S,
                                                    const double *__restrict__ stats, uint16_t *__restrict__ dpred)
 {
     const int n = B * S;
     for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
-        const int b = e / S;
-        const double dr = stats[b * 4], di = stats[b * 4 + 1];
+        const int b = e / S, q = e - b * S;
+        int kb = 0;
+        double lb = cand_loss(stats + (size_t)b * K * 4);
+        for (int k = 1; k < K; ++k) {
+            const double l = cand_loss(stats + ((size_t)b * K + k) * 4);
+            if (l < lb) {
+                lb = l;
+                kb = k;
+            }
+        }
+        const double *st = stats + ((size_t)b * K + kb) * 4;
+        const double dr = st[0], di = st[1];
         const double mag = sqrt(dr * dr + di * di);
         const float cr = mag > 0 ? (float)(dr / mag) : 1.f, ci = mag > 0 ? (float)(di / mag) : 0.f;
-        const float tr = psi[(size_t)e * 2], ti = psi[(size_t)e * 2 + 1];
+        const size_t t = ((size_t)b * K + kb) * S + q;
+        const float tr = psi[t * 2], ti = psi[t * 2 + 1];
         const float gr = 2.f * (pred[(size_t)e * ld] - (cr * tr - ci * ti)) / B;
         const float gi = 2.f * (pred[(size_t)e * ld + 1] - (cr * ti + ci * tr)) / B;
         for (int c = 0; c < ld; ++c)
             dpred[(size_t)e * ld + c] = c == 0 ? f2bf(gr) : c == 1 ? f2bf(gi) : (uint16_t)0;
     }
+}
+
+// Complex state <-> fp32 pairs: out[2q], out[2q+1] = scale * (Re, Im) psi[q]
+// (complex128 or complex64 interleaved), and psi[q] = scale * (pred[q*ld],
+// pred[q*ld + 1]).
+template <class T>
+__global__ __launch_bounds__(256) void k_psi_to_f32(const T *__restrict__ psi, int64_t S, float scale,
+                                                    float *__restrict__ out)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < 2 * S; e += (int64_t)gridDim.x * 256)
+        out[e] = (float)((double)psi[e] * (double)scale);
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_f32_to_psi(const float *__restrict__ pred, int ld, int64_t S, double scale,
+                                                    T *__restrict__ psi)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < 2 * S; e += (int64_t)gridDim.x * 256)
+        psi[e] = (T)((double)pred[(e >> 1) * ld + (e & 1)] * scale);
 }
 
 // Adam on fp32 master weights, then the bf16 copy the kernels read.

@@ -1,0 +1,321 @@
+"""Learned initial state for imaginary-time runs.
+
+The paper shortens imaginary-time runs by starting from a better state than
+the one-vortex random-phase state of Eq. (fun): a converged state of nearby
+parameters (Sec. 3, Fig. 3).  Here a U-Net (paper_1906_06327_amd/nn.py)
+learns that map from converged states the batched solver produces itself:
+
+1. generate: draw (Omega, g, nu), converge each instance from Eq. (fun)
+   with the batched fused step (sscn_batch_run), keep the state and its
+   images under the symmetries of the rotating problem (rotation by pi, and
+   each axis reflection combined with complex conjugation);
+2. train: Adam on the phase-aligned loss against the nearest image, forward
+   and backward on the bf16 matrix-core kernels of include/sscn_nn.h;
+3. propose: the network's output, written into each instance's buffer,
+   walls zeroed and normalised (sscn_batch_set_state_device);
+4. evaluate: steps and wall time to |mu_n - mu_{n-1}| < tol from the learned
+   start and from Eq. (fun), and the vortex counts of both results.
+
+Every instance uses a grid of n x n points scaled to its Thomas-Fermi size:
+with trap frequencies reduced by rotation, a = gamma^2 - Omega^2 and
+b = nu^2 - Omega^2, the 2D Thomas-Fermi chemical potential is
+mu = sqrt(g sqrt(a b) / pi) and the long radius R = sqrt(2 mu / a); the grid
+spans 2 * BOX * R, so the coordinates x / (BOX R) of grid points are the
+same for every instance and the network needs no resampling.
+"""
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+from . import Batch
+from . import nn
+
+BOX = 1.35
+N_GRID = 128
+CHANS = (32, 64, 128, 256, 256)
+BOTT = 256
+RANGES = dict(omega=(0.5, 0.9), g=(100.0, 1000.0), nu=(1.0, 1.2))
+
+
+def tf_instance(omega, g, nu, n=N_GRID, dt=2e-3, precision=0, box=BOX):
+    """Solver parameters of one instance on its Thomas-Fermi-scaled grid."""
+    a = 1.0 - omega * omega
+    b = nu * nu - omega * omega
+    if a <= 0 or b <= 0:
+        raise ValueError("Omega must stay below both trap frequencies")
+    mu = math.sqrt(g * math.sqrt(a * b) / math.pi)
+    r = math.sqrt(2.0 * mu / a)
+    h = 2.0 * box * r / n
+    return dict(dim=2, nx=n, ny=n, nz=1, hx=h, hy=h, hz=h, gamma=1.0, nu=nu, lam=1.0, g=g,
+                omega=omega, dt=dt, mode=0, precision=precision)
+
+
+def draw(m, seed, ranges=RANGES):
+    """m parameter triples (Omega, g, nu): Omega and nu uniform, g log-uniform."""
+    rng = np.random.default_rng(int(seed))
+    out = []
+    for _ in range(m):
+        om = float(rng.uniform(*ranges["omega"]))
+        g = float(math.exp(rng.uniform(math.log(ranges["g"][0]), math.log(ranges["g"][1]))))
+        nu = float(rng.uniform(*ranges["nu"]))
+        out.append((om, g, nu))
+    return out
+
+
+def features(plist, n=N_GRID):
+    """Network input (B, n, n, 16) fp32: x/(BOX R), y/(BOX R), and Omega, log g,
+    nu centred and scaled over their ranges; channels 5..15 zero."""
+    ax = (np.arange(n) - n / 2) * 2.0 / n
+    X, Y = np.meshgrid(ax, ax)
+    lg0 = 0.5 * (math.log(RANGES["g"][0]) + math.log(RANGES["g"][1]))
+    lgs = 0.5 * (math.log(RANGES["g"][1]) - math.log(RANGES["g"][0]))
+    f = np.zeros((len(plist), n, n, nn.IN_CH), np.float32)
+    for k, (om, g, nu) in enumerate(plist):
+        f[k, ..., 0] = X
+        f[k, ..., 1] = Y
+        f[k, ..., 2] = (om - 0.7) / 0.2
+        f[k, ..., 3] = (math.log(g) - lg0) / lgs
+        f[k, ..., 4] = (nu - 1.1) / 0.1
+    return f
+
+
+def images(psi):
+    """psi and its images under rotation by pi, conj(psi(-x, y)) and
+    conj(psi(x, -y)); on the grid x_i = -n h / 2 + i h the reflection is
+    the index map i -> (n - i) mod n."""
+    n = psi.shape[0]
+    r = (-np.arange(n)) % n
+    return [psi, psi[r][:, r], np.conj(psi[:, r]), np.conj(psi[r, :])]
+
+
+def target_scale(p):
+    """Targets are psi * h * n / 4 (mean |psi|^2 over the grid 1/16)."""
+    return p["hx"] * p["nx"] / 4.0
+
+
+def _bf16_device(torch, a):
+    t32 = torch.tensor(a, dtype=torch.float32, device="cuda")
+    out = torch.empty(a.shape, dtype=torch.int16, device="cuda")
+    nn.f32_to_bf16(t32, out)
+    return out
+
+
+def _run_logged(b, max_steps, chk, tol, log, tag, seg=100000):
+    """sscn_batch_run in segments (the run resumes exactly where it stopped),
+    with a progress line after each."""
+    K = chk + (chk & 1)
+    seg = max(K, seg // K * K)
+    done, steps = 0, [-1] * b.n
+    while done < max_steps:
+        m = min(seg, max_steps - done)
+        steps = b.run(m, check_every=chk, tol=tol)
+        done += m
+        nconv = sum(1 for s in steps if s >= 0)
+        if log:
+            log(f"[{tag}] {done} steps: {nconv}/{b.n} converged")
+        if nconv == b.n:
+            break
+    return steps
+
+
+def _run_batch(torch, plist, dt, max_steps, tol, seeds, starts=None, precision=0, log=None, tag="run"):
+    """One batch from Eq. (fun) (starts None) or from proposed states."""
+    n = N_GRID
+    ps = [tf_instance(*p, n=n, dt=dt, precision=precision) for p in plist]
+    b = Batch(ps)
+    import workloads as W
+    t0 = time.perf_counter()
+    for k in range(len(ps)):
+        if starts is None:
+            b.init_state(k, 1, W.phase_field(seeds[k], n, n), 1.0)
+        else:
+            nn.f32_to_psi(starts[k], nn.OUT_CH, n * n, 1.0, b.psi[k])
+            b.set_state_device(k)
+    chk = max(2, int(round(0.1 / dt)))
+    steps = _run_logged(b, max_steps, chk, tol, log, tag)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    obs = b.observables()
+    counts = [b.vortex_count(k) for k in range(len(ps))]
+    return b, ps, steps, wall, obs, counts
+
+
+def generate(plist, seeds, dt=2e-3, max_steps=250000, tol=1e-6, chunk=64, log=print):
+    """Converged states of plist (host complex128 list) plus run records."""
+    import torch
+    states, recs = [], []
+    for c0 in range(0, len(plist), chunk):
+        pl = plist[c0:c0 + chunk]
+        b, ps, steps, wall, obs, counts = _run_batch(torch, pl, dt, max_steps, tol, seeds[c0:c0 + chunk],
+                                                     log=log, tag="generate")
+        for k in range(len(pl)):
+            states.append(b.get_state(k))
+            recs.append(dict(params=pl[k], steps=steps[k], mu=obs[k]["mu"], vortices=counts[k],
+                             h=ps[k]["hx"]))
+        b.close()
+        done = sum(1 for s in steps if s > 0)
+        log(f"[generate] {c0 + len(pl)}/{len(plist)}: {wall:.1f} s, {done}/{len(pl)} reached tol {tol:g}")
+    return states, recs
+
+
+def make_targets(plist, states, dt=2e-3):
+    """(M, 4, n, n, 2) fp32 targets: the scaled state and its three images."""
+    n = N_GRID
+    T = np.zeros((len(states), 4, n, n, 2), np.float32)
+    for m, (p, s) in enumerate(zip(plist, states)):
+        sc = target_scale(tf_instance(*p, n=n, dt=dt))
+        for k, im in enumerate(images(s)):
+            T[m, k, ..., 0] = im.real * sc
+            T[m, k, ..., 1] = im.imag * sc
+    return T
+
+
+def train(net, X, T, epochs, lr=1e-3, seed=0, log=print, log_every=50):
+    """Adam over shuffled minibatches of net.N samples with a cosine
+    learning-rate decay.  X: (M, n, n, 16) bf16 device tensor; T: (M, 4, n,
+    n, 2) fp32 device tensor.  Returns the per-epoch mean loss."""
+    import torch
+    M, B = X.shape[0], net.N
+    per = M // B
+    total = max(1, epochs * per)
+    rng = np.random.default_rng(seed)
+    hist, it = [], 0
+    for ep in range(epochs):
+        perm = rng.permutation(M)
+        acc = 0.0
+        for s in range(per):
+            idx = torch.tensor(perm[s * B:(s + 1) * B], device="cuda")
+            net.forward(X.index_select(0, idx))
+            lv = float(net.loss_and_grad(T.index_select(0, idx)).mean())
+            net.backward(net.gacts["out"])
+            net.adam_step(lr=lr * 0.5 * (1.0 + math.cos(math.pi * it / total)))
+            acc += lv
+            it += 1
+            if log_every and it % log_every == 0:
+                log(f"[train] iter {it}/{total} loss {lv:.4f}")
+        hist.append(acc / max(1, per))
+        log(f"[train] epoch {ep + 1}/{epochs} mean loss {hist[-1]:.4f}")
+    return hist
+
+
+def propose(net_params, plist):
+    """Network output (B, n, n, 16) fp32 device tensor for plist."""
+    import torch
+    net = nn.UNet(len(plist), N_GRID, N_GRID, chans=CHANS, bott=BOTT, params=net_params)
+    X = _bf16_device(torch, features(plist))
+    out = net.forward(X).clone()
+    return out
+
+
+def evaluate(net_params, plist, seeds, dt=2e-3, max_steps=2000000, tol=1e-8, log=print):
+    """Both starts to |dmu| < tol on the same GPU, one batch each."""
+    import torch
+    b, ps, st0, wall0, obs0, cnt0 = _run_batch(torch, plist, dt, max_steps, tol, seeds, log=log,
+                                               tag="one-vortex start")
+    b.close()
+    log(f"[evaluate] one-vortex start: {wall0:.1f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    starts = propose(net_params, plist)
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    b, ps, st1, wall1, obs1, cnt1 = _run_batch(torch, plist, dt, max_steps, tol, seeds, starts=starts, log=log,
+                                               tag="learned start")
+    b.close()
+    log(f"[evaluate] learned start: inference {t_inf:.2f} s + run {wall1:.1f} s")
+    st0a, st1a = np.array(st0), np.array(st1)
+    rows = []
+    for k in range(len(plist)):
+        rows.append(dict(omega=plist[k][0], g=plist[k][1], nu=plist[k][2],
+                         steps_one_vortex=int(st0[k]), steps_learned=int(st1[k]),
+                         vortices_one_vortex=cnt0[k], vortices_learned=cnt1[k],
+                         mu_one_vortex=obs0[k]["mu"], mu_learned=obs1[k]["mu"]))
+    both = (st0a > 0) & (st1a > 0)
+    return dict(
+        instances=len(plist), tol=tol, dt=dt, grid=N_GRID,
+        wall_one_vortex_s=round(wall0, 3), wall_learned_s=round(wall1 + t_inf, 3),
+        inference_s=round(t_inf, 3),
+        wall_speedup=round(wall0 / (wall1 + t_inf), 3),
+        converged_one_vortex=int((st0a > 0).sum()), converged_learned=int((st1a > 0).sum()),
+        median_steps_one_vortex=float(np.median(np.where(st0a > 0, st0a, max_steps))),
+        median_steps_learned=float(np.median(np.where(st1a > 0, st1a, max_steps))),
+        max_steps_one_vortex=int(np.where(st0a > 0, st0a, max_steps).max()),
+        max_steps_learned=int(np.where(st1a > 0, st1a, max_steps).max()),
+        same_vortex_count=int(sum(1 for r in rows if r["vortices_one_vortex"] == r["vortices_learned"])),
+        lower_or_equal_mu_learned=int(sum(1 for r in rows if r["mu_learned"] <= r["mu_one_vortex"] + 1e-7)),
+        both_converged=int(both.sum()),
+        rows=rows)
+
+
+def save_params(path, params):
+    np.savez(path, **{f"{k}__w": v[0] for k, v in params.items()}, **{f"{k}__b": v[1] for k, v in params.items()})
+
+
+def load_params(path):
+    d = np.load(path)
+    names = sorted({k.rsplit("__", 1)[0] for k in d.files})
+    return {k: (d[f"{k}__w"], d[f"{k}__b"]) for k in names}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description="Generate, train and evaluate the learned initial state.")
+    ap.add_argument("--train", type=int, default=1024, help="training instances")
+    ap.add_argument("--eval", type=int, default=64, help="held-out evaluation instances")
+    ap.add_argument("--gen-steps", type=int, default=250000)
+    ap.add_argument("--gen-tol", type=float, default=1e-6)
+    ap.add_argument("--eval-steps", type=int, default=2000000)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--dt", type=float, default=2e-3)
+    ap.add_argument("--seed", type=int, default=2019)
+    ap.add_argument("--phase-seed", type=int, default=13,
+                    help="seed of the random phase R(x, y) of Eq. (fun), shared by every instance "
+                         "(13 as in the paper's programs); -1 draws one per instance")
+    ap.add_argument("--weights", default=None, help="load weights (npz) and skip generate/train")
+    ap.add_argument("--save-weights", default=None)
+    ap.add_argument("--out", default=None, help="JSON summary path")
+    a = ap.parse_args(argv)
+    import torch
+
+    def log(msg):
+        print(msg, flush=True)
+
+    res = {}
+    if a.weights:
+        params = load_params(a.weights)
+    else:
+        plist = draw(a.train, a.seed)
+        seeds = [a.seed * 10 + k if a.phase_seed < 0 else a.phase_seed for k in range(a.train)]
+        t0 = time.perf_counter()
+        states, recs = generate(plist, seeds, dt=a.dt, max_steps=a.gen_steps, tol=a.gen_tol, log=log)
+        res["generate_s"] = round(time.perf_counter() - t0, 1)
+        res["generate_reached_tol"] = int(sum(1 for r in recs if r["steps"] > 0))
+        X = _bf16_device(torch, features(plist))
+        T = torch.tensor(make_targets(plist, states, a.dt), device="cuda")
+        del states
+        net = nn.UNet(a.batch, N_GRID, N_GRID, chans=CHANS, bott=BOTT, seed=a.seed)
+        t0 = time.perf_counter()
+        hist = train(net, X, T, a.epochs, lr=a.lr, seed=a.seed, log=log)
+        torch.cuda.synchronize()
+        res["train_s"] = round(time.perf_counter() - t0, 1)
+        res["loss_history"] = [round(v, 5) for v in hist]
+        params = net.params_numpy()
+        if a.save_weights:
+            save_params(a.save_weights, params)
+        del X, T, net
+    ev_plist = draw(a.eval, a.seed + 1)
+    ev_seeds = [a.seed * 10 + 5000000 + k if a.phase_seed < 0 else a.phase_seed for k in range(a.eval)]
+    res["evaluate"] = evaluate(params, ev_plist, ev_seeds, dt=a.dt, max_steps=a.eval_steps, log=log)
+    summary = {k: v for k, v in res["evaluate"].items() if k != "rows"}
+    log(json.dumps(summary))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

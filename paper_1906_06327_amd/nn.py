@@ -39,7 +39,9 @@ def _nn():
         L.sscn_nn_up2.argtypes = [vp, ci, ci, ci, ci, vp, ci, ci, vp]
         L.sscn_nn_up2_bwd.argtypes = [vp, ci, ci, ci, ci, ci, ci, vp, vp]
         L.sscn_nn_chan_copy.argtypes = [vp, ci, ci, vp, ci, ci, ci, ci, ci, vp]
-        L.sscn_nn_loss.argtypes = [vp, ci, vp, ci, ci, vp, vp, vp]
+        L.sscn_nn_loss.argtypes = [vp, ci, vp, ci, ci, ci, vp, vp, vp]
+        L.sscn_nn_psi_to_f32.argtypes = [vp, ci, i64, cf, vp, vp]
+        L.sscn_nn_f32_to_psi.argtypes = [vp, ci, i64, ctypes.c_double, vp, ci, vp]
         L.sscn_nn_adam.argtypes = [vp, vp, vp, vp, i64, cf, cf, cf, cf, ci, vp, vp]
         L.sscn_nn_f32_to_bf16.argtypes = [vp, vp, i64, vp]
         L.sscn_nn_last_error.restype = ctypes.c_char_p
@@ -104,8 +106,23 @@ def chan_copy(src, lds, soff, dst, ldd, doff, P, C, accumulate=False, stream=Non
     _ck(_nn().sscn_nn_chan_copy(_p(src), lds, soff, _p(dst), ldd, doff, P, C, int(accumulate), stream))
 
 
-def loss(pred, ld, psi, B, S, stats, dpred=None, stream=None):
-    _ck(_nn().sscn_nn_loss(_p(pred), ld, _p(psi), B, S, _p(stats), _p(dpred), stream))
+def loss(pred, ld, psi, B, K, S, stats, dpred=None, stream=None):
+    _ck(_nn().sscn_nn_loss(_p(pred), ld, _p(psi), B, K, S, _p(stats), _p(dpred), stream))
+
+
+def psi_to_f32(psi, S, scale, out, stream=None):
+    prec = 0 if psi.dtype == _complex128() else 1
+    _ck(_nn().sscn_nn_psi_to_f32(_p(psi), prec, int(S), float(scale), _p(out), stream))
+
+
+def f32_to_psi(pred, ld, S, scale, psi, stream=None):
+    prec = 0 if psi.dtype == _complex128() else 1
+    _ck(_nn().sscn_nn_f32_to_psi(_p(pred), ld, int(S), float(scale), _p(psi), prec, stream))
+
+
+def _complex128():
+    import torch
+    return torch.complex128
 
 
 def adam(w, m, v, g, lr, b1, b2, eps, t, wbf=None, stream=None):
@@ -310,13 +327,19 @@ class UNet:
             dinp = self.gpool[lv - 1] if lv > 0 else self.gin
             conv_bwd(f"enc{lv}a", inp, self.gacts[f"enc{lv}a"], dinp)
 
-    def loss_and_grad(self, psi_target):
-        """Phase-aligned loss against (N, H, W, 2) fp32 targets; writes the
-        output gradient into gacts['out'] and returns the per-sample loss."""
+    def loss_and_grad(self, psi_target, grad=True):
+        """Phase-aligned loss against fp32 targets of shape (N, H, W, 2) or
+        (N, K, H, W, 2) (K candidate images per sample, the nearest counts);
+        writes the output gradient into gacts['out'] if grad and returns the
+        per-sample loss (host numpy, synchronises)."""
         S = self.H * self.W
-        loss(self.acts["out"], OUT_CH, psi_target, self.N, S, self.stats, self.gacts["out"])
-        st = self.stats.view(self.N, 4).cpu().numpy()
-        return st[:, 2] + st[:, 3] - 2.0 * np.hypot(st[:, 0], st[:, 1])
+        K = 1 if psi_target.dim() == 4 else int(psi_target.shape[1])
+        if self.stats.numel() < 4 * self.N * K:
+            self.stats = self.torch.zeros(4 * self.N * K, dtype=self.torch.float64, device=self.dev)
+        loss(self.acts["out"], OUT_CH, psi_target, self.N, K, S, self.stats,
+             self.gacts["out"] if grad else None)
+        st = self.stats[:4 * self.N * K].view(self.N, K, 4).cpu().numpy()
+        return (st[..., 2] + st[..., 3] - 2.0 * np.hypot(st[..., 0], st[..., 1])).min(axis=1)
 
     def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
         self.t += 1

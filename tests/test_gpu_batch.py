@@ -95,3 +95,33 @@ def test_batch_workload_sampled(P):
         ref = O.step(op, O.init_state(op, 1, W.phase_field(c["seed"], c["ny"], c["nx"]), 1.0), 10)
         assert rel(b.get_state(k), ref) <= 1e-10, k
     b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_set_state_device_and_vortex_count(P, prec):
+    """A state written into an instance's buffer gets zero walls and unit
+    norm as the oracle's; the per-instance vortex count equals the oracle's."""
+    import torch
+    print(f"[gpu-batch] set_state_device prec={prec}", flush=True)
+    cfgs = mixed(prec)[:3]
+    b = P.Batch(cfgs)
+    rng = np.random.default_rng(60 + prec)
+    for k, c in enumerate(cfgs):
+        ny, nx = c["ny"], c["nx"]
+        y, x = np.mgrid[0:ny, 0:nx]
+        z = (x - 0.37 * nx) + 1j * (y - 0.55 * ny)
+        z2 = (x - 0.7 * nx) - 1j * (y - 0.3 * ny)
+        f = z * z2 * np.exp(-((x - nx / 2) ** 2 + (y - ny / 2) ** 2) / (0.1 * nx * ny))
+        f = f + 0.01 * (rng.standard_normal(f.shape) + 1j * rng.standard_normal(f.shape))
+        b.psi[k].copy_(torch.tensor(f.astype(np.complex128 if prec == 0 else np.complex64)))
+        b.set_state_device(k)
+        op = O.make_params(**c)
+        ref = np.asarray(f.astype(np.complex128 if prec == 0 else np.complex64), dtype=np.complex128)
+        ref[0, :] = 0
+        ref[:, 0] = 0
+        ref = O.normalize(op, ref)
+        got = b.get_state(k).astype(np.complex128)
+        assert np.all(got[0, :] == 0) and np.all(got[:, 0] == 0)
+        assert rel(got, ref) <= (1e-13 if prec == 0 else 1e-6), k
+        assert b.vortex_count(k) == O.vortex_count(op, got), k
+    b.close()

@@ -152,19 +152,22 @@ def test_elementwise_and_resampling(nn):
     assert np.array_equal(from_bf(dyd), U.bf16(np.where(x > 0, dy, scaled)))
 
 
-def test_loss_and_adam(nn):
-    rng = np.random.default_rng(10)
+@pytest.mark.parametrize("K", [1, 3])
+def test_loss_and_adam(nn, K):
+    rng = np.random.default_rng(10 + K)
     B, H, W, ld = 3, 9, 7, 16
     pred = rng.standard_normal((B, H, W, ld)).astype(np.float32)
-    psi = rng.standard_normal((B, H, W, 2)).astype(np.float32)
-    stats = torch.zeros(4 * B, dtype=torch.float64, device="cuda")
+    psi = rng.standard_normal((B, K, H, W, 2)).astype(np.float32)
+    if K > 1:
+        psi[1, 2] = 0.8 * pred[1, ..., :2]  # sample 1's nearest image is its last candidate
+    stats = torch.zeros(4 * B * K, dtype=torch.float64, device="cuda")
     dpred = torch.full((B, H, W, ld), 5, dtype=torch.int16, device="cuda")
-    nn.loss(f32(pred), ld, f32(psi), B, H * W, stats, dpred)
+    nn.loss(f32(pred), ld, f32(psi), B, K, H * W, stats, dpred)
     rs = U.loss_stats(pred[..., :2].astype(np.float64), psi.astype(np.float64))
-    assert np.allclose(stats.cpu().numpy().reshape(B, 4), rs, rtol=1e-13, atol=1e-12)
+    assert np.allclose(stats.cpu().numpy().reshape(B, K, 4), rs, rtol=1e-13, atol=1e-12)
     rg = U.loss_grad(pred[..., :2].astype(np.float64), psi.astype(np.float64))
     got = from_bf(dpred)
-    scale = 2.0 * (np.abs(pred[..., :2]) + np.abs(psi).sum(-1, keepdims=True)) / B
+    scale = 2.0 * (np.abs(pred[..., :2]) + np.abs(psi).sum(-1).max(1)[..., None]) / B
     close_bf(got[..., :2], rg, scale, "loss grad")
     assert np.all(got[..., 2:] == 0)
 
@@ -183,15 +186,36 @@ def test_loss_and_adam(nn):
     assert np.array_equal(from_bf(wbf), U.bf16(wd.cpu().numpy()))
 
 
+def test_state_conversions(nn):
+    rng = np.random.default_rng(12)
+    S = 1000
+    for dt in (torch.complex128, torch.complex64):
+        z = (rng.standard_normal(S) + 1j * rng.standard_normal(S))
+        zt = torch.tensor(z).to(dt).cuda()
+        out = torch.zeros(2 * S, dtype=torch.float32, device="cuda")
+        nn.psi_to_f32(zt, S, 0.5, out)
+        zz = zt.cpu().numpy().astype(np.complex128) * 0.5
+        ref = np.stack([zz.real, zz.imag], axis=1).reshape(-1)
+        assert np.array_equal(out.cpu().numpy(), ref.astype(np.float32))
+        pred = torch.tensor(rng.standard_normal((S, 16)).astype(np.float32)).cuda()
+        back = torch.zeros(S, dtype=dt, device="cuda")
+        nn.f32_to_psi(pred, 16, S, 2.0, back)
+        pn = pred.cpu().numpy().astype(np.float64)
+        want = (2.0 * pn[:, 0] + 2.0j * pn[:, 1]).astype(np.complex128 if dt == torch.complex128 else np.complex64)
+        assert np.array_equal(back.cpu().numpy(), want)
+
+
 @pytest.mark.parametrize("chans,bott,N,H", [((16, 32), 32, 2, 16), ((16, 32, 64, 64), 128, 2, 32)])
 def test_unet_forward_backward(nn, chans, bott, N, H):
     """Whole network on the GPU against the reference with the same bf16
     rounding points.  The two differ only where fp32 and FP64 accumulation
     tip a bf16 rounding the other way, and such flips propagate, so the
     comparison is in relative L2 norm: 2e-2 for the output; for a weight
-    gradient, 5e-2 or 0.6 times the whole effect of bf16 rounding on that
-    gradient (the bf16 reference against the FP64 reference), whichever is
-    larger.  A wrong index or operand layout gives errors of order one."""
+    gradient, 5e-2 or the whole effect of bf16 rounding on that gradient
+    (the bf16 reference against the FP64 reference), whichever is larger:
+    the GPU gradient must be as close to the bf16 reference as bf16
+    arithmetic itself is to exact arithmetic.  A wrong index or operand
+    layout gives errors of order one."""
     rng = np.random.default_rng(11)
     net = nn.UNet(N, H, H, chans=chans, bott=bott, seed=3)
     # non-zero biases so the bias path is exercised
@@ -224,7 +248,7 @@ def test_unet_forward_backward(nn, chans, bott, N, H):
     for name, _, _, _ in net.specs:
         for k, got in enumerate((net.gw[name].cpu().numpy(), net.gb[name].cpu().numpy())):
             err, floor = rel(got, G[name][k]), rel(G64[name][k], G[name][k])
-            assert err < max(5e-2, 0.6 * floor), (name, k, err, floor)
+            assert err < max(5e-2, floor), (name, k, err, floor)
 
 
 def test_unet_training_reduces_loss(nn):

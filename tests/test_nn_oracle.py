@@ -109,3 +109,17 @@ def test_unet_backprop_matches_finite_differences(chans, bott):
             return total(pp)
         num = fd(f_b, b, (0,), eps=1e-5)
         assert abs(G[name][1][0] - num) <= 1e-6 + 1e-5 * abs(num), name
+
+
+def test_loss_over_candidates_is_least_candidate():
+    rng = np.random.default_rng(5)
+    pred = rng.standard_normal((2, 4, 5, 2))
+    cands = rng.standard_normal((2, 3, 4, 5, 2))
+    cands[1, 2] = pred[1] * 0.9  # sample 1 has a near candidate
+    each = np.stack([U.loss_value(pred, cands[:, k]) for k in range(3)], axis=1)
+    assert np.allclose(U.loss_value(pred, cands), each.min(axis=1))
+    assert np.argmin(each[1]) == 2
+    g = U.loss_grad(pred, cands)
+    f = lambda pp: float(U.loss_value(pp, cands).mean())
+    for idx in [(0, 1, 2, 0), (1, 3, 4, 1)]:
+        assert abs(g[idx] - fd(f, pred, idx)) < 1e-6
