@@ -21,6 +21,7 @@ Also reported on the same JSON line:
                 workload, on the host cores.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -34,6 +35,38 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
+KERNEL_SOURCES = ("paper_1906_06327_amd/csrc/sscn_device.hpp", "paper_1906_06327_amd/csrc/sscn_lib.hip")
+
+
+def source_hash():
+    """sha256 over the solver kernel sources, in KERNEL_SOURCES order."""
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of a kernel from its committed counter summary
+    (profiles/traffic_<key>.md: FETCH_SIZE and WRITE_SIZE passes scaled by
+    the plain-copy calibration), or None when the summary is missing or was
+    taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{key}.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                vals[k.strip(" -*`")] = v.strip(" `\n")
+    if vals.get("source_sha256") != source_hash():
+        return None
+    try:
+        return int(vals["traffic_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def parse():
@@ -83,7 +116,7 @@ def timed_steps(P, torch, cfg, steps, warmup, mode=0):
     return s, dt
 
 
-def kernel_roofline(s, cfg, nsteps=200):
+def kernel_roofline(s, cfg, nsteps=200, traffic_key=None):
     """Average duration of the dominant kernel of a step (HIP events on the
     solver's stream) and its algorithmic bandwidth: 2*c bytes per point per
     axis sweep it performs (one read and one write of the state per sweep,
@@ -104,8 +137,13 @@ def kernel_roofline(s, cfg, nsteps=200):
         per_launch = 2 * esize * pts
         label = f"{dom}-sweep"
     gbs = per_launch / (ms[dom] * 1e-3) / 1e9
+    kind = "fused2d" if plan == 2 else f"{dom}sweep"
+    traffic = measured_traffic(traffic_key) if traffic_key and traffic_key.startswith(kind) else None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": None, "kernel": label,
+            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+            "traffic_unit": "bytes per launch (counters)",
+            "traffic_over_algorithmic": round(traffic / per_launch, 3) if traffic else None,
+            "kernel": label,
             "plan": {1: "sweeps", 2: "fused"}.get(plan, plan), "bytes_per_launch": per_launch,
             "kernel_ms": {k: round(ms[k], 5) for k in names}, "step_ms_events": round(ms["step"], 5)}
 
@@ -191,7 +229,7 @@ def main():
     s, dt = timed_steps(P, torch, cfg, a.steps, a.warmup)
     pts = cfg["nx"] * cfg["ny"]
     value = pts * a.steps / dt
-    roof = kernel_roofline(s, cfg)
+    roof = kernel_roofline(s, cfg, traffic_key=f"fused2d_512_{a.precision}")
     s.close()
 
     out = {
@@ -224,7 +262,8 @@ def main():
         p3 = c3["nx"] * c3["ny"] * c3["nz"]
         variants["c3_3d_complex64"] = {"updates_per_s": round(p3 * 1000 / dt, 1),
                                        "ms_per_step": round(dt / 1000 * 1e3, 6),
-                                       "roofline": kernel_roofline(s, c3, 100)}
+                                       "roofline": kernel_roofline(s, c3, 100,
+                                                                   traffic_key="xsweep_3d_256x256x64_c64")}
         s.close()
         variants["c4_batch_64_instances_complex128"] = batch_run(P, torch)
         out["variants"] = variants

@@ -179,10 +179,15 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out);
 int sscn_set_plan(sscn_handle *h, int plan);
 
 /* Window (rows of look-ahead) used by the truncated line solves per axis
- * (0 means the exact whole-line solve), segment length per axis, and the
- * plan in use (SSCN_PLAN_AUTO until the first step resolves it).  Any
- * output pointer may be NULL.  For diagnostics and tests. */
-int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *plan);
+ * (0 means the exact whole-line solve), segment length per axis, the plan
+ * in use (SSCN_PLAN_AUTO until the first step resolves it) and the lines
+ * per block of the x-sweep staging.  Any output pointer may be NULL.  For
+ * diagnostics and tests.  The first step of an SSCN_PLAN_AUTO handle picks
+ * the plan and the x-sweep lines per block by timing the candidates; with
+ * the environment variable SSCN_TUNE_CACHE naming a file, the choices are
+ * also kept there (JSON, keyed by architecture, shape, precision, mode and
+ * window). */
+int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *plan, int *x_lines);
 
 void sscn_destroy(sscn_handle *h);
 

@@ -74,7 +74,7 @@ def lib():
         L.sscn_set_mode.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp]
         L.sscn_vortex_count.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.sscn_solver_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
-                                       ctypes.POINTER(ctypes.c_int)]
+                                       ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.sscn_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
         L.sscn_converge.argtypes = [vp, i64, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp,
@@ -245,8 +245,9 @@ class Solver:
         w = (ctypes.c_int * 3)()
         s = (ctypes.c_int * 3)()
         pl = ctypes.c_int()
-        _check(lib().sscn_solver_info(self._h, w, s, ctypes.byref(pl)))
-        return {"window": list(w), "segment": list(s), "plan": int(pl.value)}
+        xl = ctypes.c_int()
+        _check(lib().sscn_solver_info(self._h, w, s, ctypes.byref(pl), ctypes.byref(xl)))
+        return {"window": list(w), "segment": list(s), "plan": int(pl.value), "x_lines": int(xl.value)}
 
     def close(self):
         if getattr(self, "_h", None):

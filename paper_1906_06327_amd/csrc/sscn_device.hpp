@@ -99,6 +99,7 @@ struct StepArgs {
 // Line coefficients for a line whose rotation coefficient is `rot`.
 template <class R> struct LineCoef {
     Cx<R> A0, k0, Ap, Am;
+    R kr, ki, ur, ui, wr, wi;  // k0, the mean u of A+ and A-, and their half difference w = q rot
 };
 
 template <class R>
@@ -109,6 +110,12 @@ __device__ __forceinline__ LineCoef<R> line_coef(const AxisCoef &c, double rot)
     L.k0 = {R(c.k0r), R(c.k0i)};
     L.Ap = {R(c.ur + c.qr * rot), R(c.ui + c.qi * rot)};
     L.Am = {R(c.ur - c.qr * rot), R(c.ui - c.qi * rot)};
+    L.kr = R(c.k0r);
+    L.ki = R(c.k0i);
+    L.ur = R(c.ur);
+    L.ui = R(c.ui);
+    L.wr = R(c.qr * rot);
+    L.wi = R(c.qi * rot);
     return L;
 }
 
@@ -120,12 +127,34 @@ __device__ __forceinline__ Cx<R> minus_kv(const LineCoef<R> &L, Cx<R> vm, Cx<R> 
     return Cx<R>{-t.re, -t.im};
 }
 
+// The same with the coefficient structure of one time mode, A+- = u +- w:
+// K v = k0 v0 + u (vm + vp) + w (vp - vm).  Imaginary time (ST = 1): k0 and
+// u are real and w is imaginary; real time (ST = 2): k0 and u are imaginary
+// and w is real (tau = -i dt or dt in k0 = i tau / 2h^2, u = -i tau / 4h^2,
+// w = tau rot / 4h).  ST = 0: general complex coefficients.
+template <class R, int ST>
+__device__ __forceinline__ Cx<R> minus_kv_st(const LineCoef<R> &L, Cx<R> vm, Cx<R> v0, Cx<R> vp)
+{
+    if constexpr (ST == 0) {
+        return minus_kv(L, vm, v0, vp);
+    } else {
+        const Cx<R> sm = {vm.re + vp.re, vm.im + vp.im};
+        const Cx<R> df = {vp.re - vm.re, vp.im - vm.im};
+        if constexpr (ST == 1)
+            return Cx<R>{-(L.kr * v0.re + L.ur * sm.re - L.wi * df.im),
+                         -(L.kr * v0.im + L.ur * sm.im + L.wi * df.re)};
+        else
+            return Cx<R>{-(-L.ki * v0.im - L.ui * sm.im + L.wr * df.re),
+                         -(L.ki * v0.re + L.ui * sm.re + L.wr * df.im)};
+    }
+}
+
 // Windowed solve of (I + K) delta = -K v for the S unknowns s..s+S-1 of a line
 // with unknowns 1..n-1, by Thomas elimination with the fixed-point factors
 // (cst, rst) from row s-W on; then io[r] = v_{s+r} + 2 delta_{s+r} and
 // d_first = delta_s (both uncorrected for the wall; see above).
 // vals[r] = v_{s-W-1+r} (zero outside 1..n-1), loaded by the caller.
-template <class R, int S, int W>
+template <class R, int S, int W, int ST = 0>
 __device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Cx<R> cst, Cx<R> rst,
                                              const Cx<R> (&vals)[S + 2 * W + 2], Cx<R> (&io)[S], Cx<R> &d_first)
 {
@@ -142,7 +171,7 @@ __device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L,
             io[r - W] = vals[r + 1];
         Cx<R> dp = zero;
         if (valid)
-            dp = rst * minus_kv(L, vals[r], vals[r + 1], vals[r + 2]) + alpha * dprev;
+            dp = rst * minus_kv_st<R, ST>(L, vals[r], vals[r + 1], vals[r + 2]) + alpha * dprev;
         dprev = dp;
         if (r >= W)
             dps[r - W] = dp;
@@ -306,19 +335,19 @@ __device__ __forceinline__ Cx<R> rescale(Cx<R> v, R sm1)
 // Pivot table of one line type (x-lines by j, y-lines by i, one for z):
 // tab[0] = c*, tab[1] = r*, tab[1 + u] = zeta_u (u = 1..W).  Stride W + 2.
 
-// x-sweep with the H1 sub-step and the pending rescale fused in front.
-// A block stages L whole x-lines in LDS (padded every S elements so that
-// consecutive threads, which own consecutive segments, hit distinct banks);
-// thread p solves segment p % nseg of line p / nseg (L * nseg <= 256), the
-// results overwrite the staged lines, and the block writes them back
-// coalesced.  src may equal dst: a line is owned by exactly one block.
+// x-sweep with the H1 sub-step and the pending rescale (s - 1 read from
+// sm1p, NULL for none) fused in front.  A block stages L whole x-lines in LDS
+// (padded every S elements so that consecutive threads, which own
+// consecutive segments, hit distinct banks); thread p loads, transforms and
+// solves segment p % nseg of line p / nseg (L * nseg <= 256) and stores its
+// S outputs.  src may equal dst: a line is owned by exactly one block, and
+// every load precedes the block's first barrier.
 template <class R, int S, int W, bool RT>
 __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
-                                                StepArgs a, int L, const double *partials, int npart,
+                                                StepArgs a, int L, const double *__restrict__ sm1p,
                                                 const Cx<R> *__restrict__ tab)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ double red[8];
     Cx<R> *lin = reinterpret_cast<Cx<R> *>(smem_raw);
     const int nx = a.nx, ny = a.ny;
     const int LS = nx + nx / S + 1;
@@ -329,36 +358,21 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
     const int line0 = blockIdx.x * L;
     const int tid = threadIdx.x;
 
-
-    // stage the block's lines and their table rows: every thread issues its
-    // loads first, then applies the rescale and H1 and writes LDS
-    // element e = tid + 256 c of the block's L lines is (line l, column t);
-    // the walk below advances (l, t) by 256 without integer division
-    int lc[kXLoad], tc[kXLoad];
-    {
-        int l = 0, t = tid;
-        while (t >= nx) {
-            t -= nx;
-            ++l;
-        }
+    // thread = (line l, segment q): it stages the S points of its segment
+    // and solves for them; every load is issued before any is used
+    const int l = tid / nseg, q = tid - l * nseg;
+    const int line = line0 + l;
+    const int j = line % ny, k = line / ny;
+    const bool inblk = l < L && line < nlines;
+    const bool active = inblk && j > 0 && (a.dim == 2 || k > 0);
+    const int s0 = 1 + q * S;
+    const int64_t base = (int64_t)line * nx;
+    Cx<R> pre[S];
 #pragma unroll
-        for (int c = 0; c < kXLoad; ++c) {
-            lc[c] = l;
-            tc[c] = t;
-            t += 256;
-            while (t >= nx) {
-                t -= nx;
-                ++l;
-            }
-        }
-    }
-    Cx<R> pre[kXLoad];
-#pragma unroll
-    for (int c = 0; c < kXLoad; ++c) {
-        const int line = line0 + lc[c];
-        pre[c] = Cx<R>{R(0), R(0)};
-        if (lc[c] < L && line < nlines && tc[c] > 0)
-            pre[c] = ld<R>(src, (int64_t)line * nx + tc[c]);
+    for (int r = 0; r < S; ++r) {
+        pre[r] = Cx<R>{R(0), R(0)};
+        if (active && s0 + r <= nx - 1)
+            pre[r] = ld<R>(src, base + s0 + r);
     }
     Cx<R> tpre[2];
 #pragma unroll
@@ -366,46 +380,30 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
         const int te = tid + c2 * 256;
         tpre[c2] = Cx<R>{R(0), R(0)};
         if (te < L * (W + 2)) {
-            const int l = te / (W + 2), c = te - l * (W + 2);
-            const int line = line0 + l;
-            if (line < nlines)
-                tpre[c2] = tab[(size_t)(line % ny) * (W + 2) + c];
+            const int tl = te / (W + 2), c = te - tl * (W + 2);
+            const int tline = line0 + tl;
+            if (tline < nlines)
+                tpre[c2] = tab[(size_t)(tline % ny) * (W + 2) + c];
         }
     }
-    // the pending rescale (its partial loads overlap the staging loads)
-    double sm1 = 0.0;
-    if (!RT && npart > 0) {
-        const double tot = block_sum_partials(partials, npart, red);
-        sm1 = 1.0 / sqrt(a.dV * tot) - 1.0;
-    }
-    const R sr = R(sm1);
-    // (j, k) of the staged lines: line0 = j0 + ny k0, advanced per line
-    const int j0 = line0 % ny, k0 = line0 / ny;
+    const R sr = R((!RT && sm1p) ? *sm1p : 0.0);  // the pending rescale, s - 1
+    if (inblk) {
+        Cx<R> *row = lin + l * LS;
+        const double y = a.y0 + j * a.hy, z = a.z0 + k * a.hz;
+        const double vyz = a.vy * y * y + (a.dim == 3 ? a.vz * z * z : 0.0);
 #pragma unroll
-    for (int c = 0; c < kXLoad; ++c) {
-        if (lc[c] < L) {
-            const int l = lc[c], t = tc[c];
-            const int line = line0 + l;
-            Cx<R> v = {R(0), R(0)};
-            if (line < nlines && t > 0) {
-                int j = j0 + l, k = k0;
-                while (j >= ny) {
-                    j -= ny;
-                    ++k;
-                }
-                if (j > 0 && (a.dim == 2 || k > 0)) {
-                    v = rescale(pre[c], sr);
-                    const double x = a.x0 + t * a.hx, y = a.y0 + j * a.hy;
-                    double V = a.vx * x * x + a.vy * y * y;
-                    if (a.dim == 3) {
-                        const double z = a.z0 + k * a.hz;
-                        V += a.vz * z * z;
-                    }
-                    const R w = R(V) + R(a.g) * norm2(v);
+        for (int r = 0; r < S; ++r) {
+            const int u = s0 + r;
+            if (u <= nx - 1) {
+                Cx<R> v = {R(0), R(0)};
+                if (active) {
+                    v = rescale(pre[r], sr);
+                    const double x = a.x0 + u * a.hx;
+                    const R w = R(a.vx * x * x + vyz) + R(a.g) * norm2(v);
                     v = h1_apply<R, RT>(v, w, R(a.dt));
                 }
+                row[u + u / S] = v;
             }
-            lin[l * LS + t + t / S] = v;
         }
     }
 #pragma unroll
@@ -414,11 +412,6 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
             ltab[tid + c2 * 256] = tpre[c2];
     __syncthreads();
 
-    const int l = tid / nseg, q = tid - l * nseg;
-    const int line = line0 + l;
-    const int j = line % ny, k = line / ny;
-    const bool active = l < L && line < nlines && j > 0 && (a.dim == 2 || k > 0);
-    const int s0 = 1 + q * S;
     Cx<R> io[S];
     if (active) {
         const LineCoef<R> Lc = line_coef<R>(a.ax[0], a.omega * (a.y0 + j * a.hy));
@@ -426,13 +419,12 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
         Cx<R> vals[S + 2 * W + 2];
         window_load<R, S, W>(s0, nx, [&](int u) { return row[u + u / S]; }, vals);
         Cx<R> df;
-        window_solve<R, S, W>(s0, nx, Lc, ltab[l * (W + 2)], ltab[l * (W + 2) + 1], vals, io, df);
+        window_solve<R, S, W, RT ? 2 : 1>(s0, nx, Lc, ltab[l * (W + 2)], ltab[l * (W + 2) + 1], vals, io, df);
         if (q == 0)
             d1[l] = df;
     }
     __syncthreads();
     if (active) {
-        Cx<R> *row = lin + l * LS;
         const Cx<R> df = d1[l];
 #pragma unroll
         for (int r = 0; r < S; ++r) {
@@ -440,25 +432,19 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
             if (u <= W)
                 io[r] = io[r] - df * ltab[l * (W + 2) + 1 + u];
             if (u <= nx - 1)
-                row[u + u / S] = io[r];
+                st<R>(dst, base + u, io[r]);
         }
     }
-    __syncthreads();
+}
 
-#pragma unroll
-    for (int c = 0; c < kXLoad; ++c) {
-        const int l2 = lc[c], t = tc[c];
-        const int line2 = line0 + l2;
-        if (l2 < L && line2 < nlines && t > 0) {
-            int j2 = j0 + l2, k2 = k0;
-            while (j2 >= ny) {
-                j2 -= ny;
-                ++k2;
-            }
-            if (j2 > 0 && (a.dim == 2 || k2 > 0))
-                st<R>(dst, (int64_t)line2 * nx + t, lin[l2 * LS + t + t / S]);
-        }
-    }
+// s - 1 of the pending rescale, s = 1/sqrt(dV sum of the npart norm
+// partials), summed in fixed order by one block.
+__global__ __launch_bounds__(256) void k_norm_scale(const double *partials, int npart, double dV, double *out)
+{
+    __shared__ double red[8];
+    const double tot = block_sum_partials(partials, npart, red);
+    if (threadIdx.x == 0)
+        out[0] = 1.0 / sqrt(dV * tot) - 1.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -642,9 +628,13 @@ constexpr size_t step2d_lds_bytes()
     return (size_t)(TR + 2 * W + 2) * (stage_stride(TC + 2 * W + 2, S) + TC + 1) * sizeof(Cx<R>);
 }
 
-template <class R, int S, int W, int TR, int TC, int NT, bool RT>
+// One step of a 2D instance per tile.  ONE: a single instance passed by
+// value (tile = work item) instead of a work list of (instance, tile).  The
+// x-windows have S outputs; the y-windows S/2, so that the TC x (2 TR / S)
+// y-segments of a tile occupy all NT threads.
+template <class R, int S, int W, int TR, int TC, int NT, bool RT, bool ONE>
 __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts, const int2 *__restrict__ work,
-                                               const int *__restrict__ nwork, int parity,
+                                               const int *__restrict__ nwork, Inst2D one, int parity,
                                                const double *__restrict__ pin, double *__restrict__ pout,
                                                int use_pin)
 {
@@ -653,8 +643,11 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
     constexpr int SCP = stage_stride(SC, S);
     constexpr int C2 = TC + 1;
     constexpr int NST = (SR * SC + NT - 1) / NT;
-    constexpr int NSX = TC / S, NSY = TR / S;
-    static_assert(TC % S == 0 && TR % S == 0 && TC * NSY <= NT, "tile shape");
+    constexpr int NSX = TC / S;
+    constexpr int SY = S / 2, NSY = TR / SY;
+    constexpr int ST = RT ? 2 : 1;
+    constexpr int PP = 4;  // norm partials prefetched per thread
+    static_assert(TC % S == 0 && TR % SY == 0 && TC * NSY <= NT, "tile shape");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     Cx<R> *st1 = reinterpret_cast<Cx<R> *>(smem_raw);  // SR x SCP staged, H1 applied
     Cx<R> *st2 = st1 + SR * SCP;                         // SR x C2 after the x-solve
@@ -662,12 +655,17 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
     __shared__ Cx<R> d1y[TC];
     __shared__ double red[20];
     const int tid = threadIdx.x;
-    const int nw = *nwork;
+    const int nw = ONE ? one.tiles_x * one.tiles_y : *nwork;
     for (int it = blockIdx.x; it < nw; it += gridDim.x) {
-        const int2 wk = work[it];
-        const Inst2D &I = insts[wk.x];
+        int ik = 0, tile = it;
+        if (!ONE) {
+            const int2 wk = work[it];
+            ik = wk.x;
+            tile = wk.y;
+        }
+        const Inst2D &I = ONE ? one : insts[ik];
         const int nx = I.nx, ny = I.ny;
-        const int tyi = wk.y / I.tiles_x, txi = wk.y - tyi * I.tiles_x;
+        const int tyi = tile / I.tiles_x, txi = tile - tyi * I.tiles_x;
         const int r0 = 1 + tyi * TR, c0 = 1 + txi * TC;  // first output row j / column i
         const int jb = r0 - H, ib = c0 - H;              // staged origin
         const typename Vec<R>::T *src = reinterpret_cast<const typename Vec<R>::T *>(I.buf[parity]);
@@ -675,7 +673,16 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         const Cx<R> *tabx = reinterpret_cast<const Cx<R> *>(I.tab[0]);
         const Cx<R> *taby = reinterpret_cast<const Cx<R> *>(I.tab[1]);
 
-        // stage: issue every load first
+        // norm partials of the previous step first (their wait does not
+        // wait for the state), then every load of the staged tile
+        const int np = I.tiles_x * I.tiles_y;
+        double pp[PP];
+#pragma unroll
+        for (int k = 0; k < PP; ++k) {
+            pp[k] = 0.0;
+            if (!RT && use_pin && tid + k * NT < np)
+                pp[k] = pin[I.poff + tid + k * NT];
+        }
         Cx<R> pre[NST];
 #pragma unroll
         for (int c = 0; c < NST; ++c) {
@@ -687,8 +694,16 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
                 pre[c] = ld<R>(src, (int64_t)j * nx + i);
         }
         double sm1 = 0.0;
-        if (!RT && use_pin)
-            sm1 = 1.0 / sqrt(I.dV * block_sum_partials_nt<NT>(pin + I.poff, I.tiles_x * I.tiles_y, red)) - 1.0;
+        if (!RT && use_pin) {
+            double v = (pp[0] + pp[1]) + (pp[2] + pp[3]);
+            for (int t = tid + PP * NT; t < np; t += NT)
+                v += pin[I.poff + t];
+            v = block_sum_nt<NT>(v, red);
+            if (tid == 0)
+                red[16] = v;
+            __syncthreads();
+            sm1 = 1.0 / sqrt(I.dV * red[16]) - 1.0;
+        }
         const R sr = R(sm1);
 #pragma unroll
         for (int c = 0; c < NST; ++c) {
@@ -727,7 +742,7 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
                 }
                 Cx<R> df;
                 const int s = c0 + q * S;
-                window_solve<R, S, W>(s, nx, Lc, trow[0], trow[1], vals, io, df);
+                window_solve<R, S, W, ST>(s, nx, Lc, trow[0], trow[1], vals, io, df);
                 if (s == 1)
                     d1x[rr] = df;
 #pragma unroll
@@ -754,17 +769,17 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         const int col = tid % TC, q = tid / TC;
         const int i = c0 + col;
         const bool act = q < NSY && i <= nx - 1;
-        const int s = r0 + q * S;
-        Cx<R> io[S];
+        const int s = r0 + q * SY;
+        Cx<R> io[SY];
         if (act) {
             const LineCoef<R> Lc = line_coef<R>(I.ax[1], -I.omega * (I.x0 + i * I.hx));
             const Cx<R> *trow = taby + (size_t)i * (W + 2);
-            Cx<R> vals[S + 2 * W + 2];
+            Cx<R> vals[SY + 2 * W + 2];
 #pragma unroll
-            for (int r = 0; r < S + 2 * W + 2; ++r)
-                vals[r] = st2[(q * S + r) * C2 + col];
+            for (int r = 0; r < SY + 2 * W + 2; ++r)
+                vals[r] = st2[(q * SY + r) * C2 + col];
             Cx<R> df;
-            window_solve<R, S, W>(s, ny, Lc, trow[0], trow[1], vals, io, df);
+            window_solve<R, SY, W, ST>(s, ny, Lc, trow[0], trow[1], vals, io, df);
             if (s == 1)
                 d1y[col] = df;
         }
@@ -774,7 +789,7 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         if (act) {
             const Cx<R> *trow = taby + (size_t)i * (W + 2);
 #pragma unroll
-            for (int r = 0; r < S; ++r) {
+            for (int r = 0; r < SY; ++r) {
                 const int u = s + r;
                 if (u <= ny - 1) {
                     Cx<R> o = io[r];
@@ -789,7 +804,7 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         if (!RT) {
             const double b = block_sum_nt<NT>(acc, red);
             if (tid == 0)
-                pout[I.poff + wk.y] = b;
+                pout[I.poff + tile] = b;
         }
         __syncthreads();  // LDS reuse by the next item
     }

@@ -73,6 +73,7 @@ struct sscn_handle {
     int W[3] = {0, 0, 0};   // window per axis; 0 = exact whole-line path
     bool exact = false;
     int xL = 1;             // lines per block of the x-sweep
+    int xLmax = 1;          // largest admissible xL
     size_t xlds = 0;
     int nemit = 0;          // partials written by the last sweep
     double *partials = nullptr;  // norm partials between steps
@@ -89,6 +90,7 @@ struct sscn_handle {
     int active_plan = SSCN_PLAN_SWEEPS;
     bool fused_ok = false;
     Inst2D *d_inst = nullptr;
+    Inst2D inst_host{};     // the same descriptor, passed by value to the fused step
     int2 *d_work = nullptr;
     int *d_nwork = nullptr;
     int ntiles = 0;
@@ -192,6 +194,15 @@ int axis_setup(const sscn_params &p, int axis, AxisCoef &c, int &W)
     return 0;
 }
 
+// Lines per block of the x-sweep and the LDS it stages: L lines of nx + nx/S
+// + 1 padded points, the pivot-table rows and the wall terms.
+void set_x_lines(sscn_handle *h, int L)
+{
+    const size_t LS = (size_t)h->p.nx + h->p.nx / kSeg + 1;
+    h->xL = L;
+    h->xlds = (L * LS + (size_t)L * (h->W[0] + 2) + L) * h->esize;
+}
+
 int setup(sscn_handle *h)
 {
     const sscn_params &p = h->p;
@@ -231,10 +242,9 @@ int setup(sscn_handle *h)
     h->esize = p.precision == SSCN_C128 ? 16 : 8;
     // x-sweep staging: L lines per block, one (line, segment) per thread
     const int nseg = (p.nx - 2) / kSeg + 1;
-    const size_t LS = (size_t)p.nx + p.nx / kSeg + 1;
     const int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / p.nx, 512 / (h->W[0] + 2)}));
-    h->xL = L;
-    h->xlds = (L * LS + (size_t)L * (h->W[0] + 2) + L) * h->esize;
+    h->xLmax = L;
+    set_x_lines(h, L);
     if (nseg > 256 || p.nx > 256 * kXLoad || h->xlds > kXLdsCap)
         h->exact = true;  // lines too long to stage; whole-line path
     // strided sweeps: logical grids and the partials written by the last one
@@ -358,13 +368,22 @@ template <class R> using V = typename Vec<R>::T;
 
 unsigned round8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
 
+// The rescale of the pending norm (npart > 0 partials) is reduced once by
+// k_norm_scale into obs_buf[kScaleSlot], which every x-sweep block reads.
+constexpr int kScaleSlot = 48;
+
 template <class R, int W, bool RT>
 void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st)
 {
     const int nlines = h->p.ny * (h->p.dim == 3 ? h->p.nz : 1);
     const int blocks = (nlines + h->xL - 1) / h->xL;
+    double *sm1 = nullptr;
+    if (!RT && npart > 0) {
+        sm1 = h->obs_buf + kScaleSlot;
+        hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, st, h->partials, npart, h->args.dV, sm1);
+    }
     hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
-                       (V<R> *)dst, h->args, h->xL, h->partials, npart, (const Cx<R> *)h->tab[0]);
+                       (V<R> *)dst, h->args, h->xL, (const double *)sm1, (const Cx<R> *)h->tab[0]);
 }
 
 template <class R, bool RT>
@@ -434,21 +453,28 @@ void launch_norm(sscn_handle *h, hipStream_t st)
     default: CALL(20); break;                                                                                \
     }
 
-// Launch geometry of one fused 2D step over a work list.
+// Launch geometry of one fused 2D step: a work list of (instance, tile)
+// over the descriptors inst, or (one != NULL) a single instance whose
+// descriptor goes by value with the tiles as work items.
 struct FusedLaunch {
     const Inst2D *inst;
     const int2 *work;
     const int *nwork;
     int grid;
     int W;
+    const Inst2D *one;
 };
 
 template <class R, int W, bool RT>
 void go_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
 {
     constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
-    hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT>), dim3(f.grid), dim3(kTileNT), lds, st,
-                       f.inst, f.work, f.nwork, parity, pin, pout, use_pin);
+    if (f.one)
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>), dim3(f.grid), dim3(kTileNT),
+                           lds, st, f.inst, f.work, f.nwork, *f.one, parity, pin, pout, use_pin);
+    else
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>), dim3(f.grid), dim3(kTileNT),
+                           lds, st, f.inst, f.work, f.nwork, Inst2D{}, parity, pin, pout, use_pin);
 }
 
 template <class R, bool RT>
@@ -472,8 +498,12 @@ template <class R, int W, bool RT>
 hipError_t allow_fused_lds()
 {
     constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
-    return hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return e;
 }
 
 template <class R>
@@ -507,7 +537,7 @@ void enqueue_fused(sscn_handle *h, int64_t n, hipStream_t st, hipEvent_t *ev = n
 {
     const bool imag = h->p.mode == SSCN_IMAG;
     double *fp[2] = {h->partials, h->partials2};
-    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0]};
+    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0], &h->inst_host};
     for (int64_t s = 0; s < n; ++s) {
         if (ev)
             (void)hipEventRecord(ev[4 * s], st);
@@ -580,6 +610,7 @@ int setup_fused(sscn_handle *h)
     if (hipMalloc(&h->d_work, sizeof(int2) * wl.size()) != hipSuccess ||
         hipMalloc(&h->partials2, sizeof(double) * std::max(h->ntiles, kRedBlocks)) != hipSuccess)
         return fail(SSCN_ENOMEM, "hipMalloc of the fused-step work list failed");
+    h->inst_host = in;
     HIPCHECK(hipMemcpy(h->d_inst, &in, sizeof in, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->d_work, wl.data(), sizeof(int2) * wl.size(), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(h->d_nwork, &h->ntiles, sizeof(int), hipMemcpyHostToDevice));
@@ -717,20 +748,109 @@ void drop_graph(sscn_handle *h)
 }
 
 // Autotuner: on the first step of a handle whose plan is SSCN_PLAN_AUTO,
-// time every plan available for the problem (separate sweeps; fused 2D
-// step) over a few steps from a saved copy of the state, restore the state,
-// and keep the fastest.  Results are cached per process, keyed by the shape,
-// precision, mode and window.
+// time every candidate configuration over a few steps from a saved copy of
+// the state, restore the state, and keep the fastest.  Candidates: the three
+// sweep kernels with the x-sweep staging L, L/2 or L/4 lines per block (L
+// the largest that fits), and the fused 2D step where it is admissible.  The
+// window W is not a candidate: the accuracy bound fixes it.  Results are
+// cached per process, keyed by architecture, shape, precision, mode and
+// window; with SSCN_TUNE_CACHE=<file> the cache is also read from and
+// written to that JSON file.
+struct TuneChoice {
+    int plan = SSCN_PLAN_SWEEPS;
+    int xl = 0;
+    float ms = 0.f;
+};
 std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int, int, int, int>, int> g_tune_cache;
+std::map<std::string, TuneChoice> g_tune_cache;
+std::string g_tune_path;  // the SSCN_TUNE_CACHE file merged into the cache last
+
+std::string device_arch()
+{
+    static std::string arch;
+    if (arch.empty()) {
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+            arch = prop.gcnArchName;
+            const size_t c = arch.find(':');
+            if (c != std::string::npos)
+                arch.resize(c);
+        }
+        if (arch.empty())
+            arch = "unknown";
+    }
+    return arch;
+}
+
+std::string tune_key(const sscn_handle *h)
+{
+    const sscn_params &p = h->p;
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "%s|%dd|%dx%dx%d|%s|%s|W%d", device_arch().c_str(), p.dim, p.nx, p.ny,
+                  p.dim == 3 ? p.nz : 1, p.precision == SSCN_C128 ? "c128" : "c64",
+                  p.mode == SSCN_IMAG ? "imag" : "real", h->W[0]);
+    return buf;
+}
+
+// Entries are lines of the form
+//   "<key>": {"plan": 1|2, "x_lines": L, "ms_per_step": t},
+void tune_cache_load()
+{
+    const char *path = std::getenv("SSCN_TUNE_CACHE");
+    if (!path || !*path || g_tune_path == path)
+        return;
+    g_tune_path = path;
+    FILE *f = std::fopen(path, "r");
+    if (!f)
+        return;
+    char line[512];
+    while (std::fgets(line, sizeof line, f)) {
+        const char *q0 = std::strchr(line, '"');
+        const char *q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char *pl = std::strstr(line, "\"plan\":");
+        const char *xl = std::strstr(line, "\"x_lines\":");
+        const char *ms = std::strstr(line, "\"ms_per_step\":");
+        if (!q1 || !pl || !xl)
+            continue;
+        TuneChoice c;
+        c.plan = std::atoi(pl + 7);
+        c.xl = std::atoi(xl + 10);
+        c.ms = ms ? (float)std::atof(ms + 14) : 0.f;
+        if ((c.plan == SSCN_PLAN_SWEEPS || c.plan == SSCN_PLAN_FUSED) && c.xl >= 1)
+            g_tune_cache[std::string(q0 + 1, q1)] = c;
+    }
+    std::fclose(f);
+}
+
+void tune_cache_save()
+{
+    const char *path = std::getenv("SSCN_TUNE_CACHE");
+    if (!path || !*path)
+        return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f)
+        return;
+    std::fprintf(f, "{\n");
+    size_t k = 0;
+    for (const auto &e : g_tune_cache)
+        std::fprintf(f, "  \"%s\": {\"plan\": %d, \"x_lines\": %d, \"ms_per_step\": %.6f}%s\n", e.first.c_str(),
+                     e.second.plan, e.second.xl, e.second.ms, ++k < g_tune_cache.size() ? "," : "");
+    std::fprintf(f, "}\n");
+    std::fclose(f);
+    std::rename(tmp.c_str(), path);
+}
 
 template <class R>
 float time_plan(sscn_handle *h, int plan, const void *saved, int nsteps)
 {
     const size_t bytes = (size_t)h->npts * h->esize;
     h->active_plan = plan;
+    h->pending = false;
     enqueue_direct<R>(h, 2, h->stream);
     (void)hipMemcpyAsync(h->psi, saved, bytes, hipMemcpyDeviceToDevice, h->stream);
+    h->pending = false;
     hipEvent_t e0, e1;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
@@ -751,44 +871,63 @@ int autotune(sscn_handle *h)
     if (h->plan != SSCN_PLAN_AUTO)
         return 0;
     h->plan = SSCN_PLAN_SWEEPS;  // resolved below
-    if (!h->fused_ok) {
-        h->active_plan = SSCN_PLAN_SWEEPS;
+    h->active_plan = SSCN_PLAN_SWEEPS;
+    if (h->exact)
         return 0;
-    }
-    const sscn_params &p = h->p;
-    const auto key = std::make_tuple(p.dim, p.nx, p.ny, p.nz, p.precision, p.mode, h->W[0]);
+    const std::string key = tune_key(h);
     {
         std::lock_guard<std::mutex> g(g_tune_mu);
+        tune_cache_load();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            h->active_plan = h->plan = it->second;
+        if (it != g_tune_cache.end() && it->second.xl <= h->xLmax &&
+            (it->second.plan == SSCN_PLAN_SWEEPS || h->fused_ok)) {
+            set_x_lines(h, it->second.xl);
+            h->active_plan = h->plan = it->second.plan;
             return 0;
         }
+    }
+    std::vector<TuneChoice> cand;
+    for (int d : {1, 2, 4}) {
+        const int xl = std::max(1, h->xLmax / d);
+        if (cand.empty() || cand.back().xl != xl) {
+            TuneChoice c;
+            c.plan = SSCN_PLAN_SWEEPS;
+            c.xl = xl;
+            cand.push_back(c);
+        }
+    }
+    if (h->fused_ok) {
+        TuneChoice c;
+        c.plan = SSCN_PLAN_FUSED;
+        c.xl = h->xLmax;
+        cand.push_back(c);
     }
     void *saved = nullptr;
     const size_t bytes = (size_t)h->npts * h->esize;
     if (hipMalloc(&saved, bytes) != hipSuccess)
         return fail(SSCN_ENOMEM, "hipMalloc of the autotune copy failed");
     HIPCHECK(hipMemcpyAsync(saved, h->psi, bytes, hipMemcpyDeviceToDevice, h->stream));
-    const int plans[2] = {SSCN_PLAN_SWEEPS, SSCN_PLAN_FUSED};
-    int best = SSCN_PLAN_SWEEPS;
-    float best_ms = 0.f;
-    for (int k = 0; k < 2; ++k) {
-        const float ms = p.precision == SSCN_C128 ? time_plan<double>(h, plans[k], saved, 16)
-                                                  : time_plan<float>(h, plans[k], saved, 16);
-        h->tune_ms[plans[k]] = ms;
-        if (k == 0 || ms < best_ms) {
-            best = plans[k];
-            best_ms = ms;
-        }
+    const int nsteps = 16;
+    size_t best = 0;
+    for (size_t k = 0; k < cand.size(); ++k) {
+        set_x_lines(h, cand[k].xl);
+        const float ms = h->p.precision == SSCN_C128 ? time_plan<double>(h, cand[k].plan, saved, nsteps)
+                                                     : time_plan<float>(h, cand[k].plan, saved, nsteps);
+        cand[k].ms = ms / nsteps;
+        float &tm = h->tune_ms[cand[k].plan];
+        tm = (tm == 0.f || ms < tm) ? ms : tm;
+        if (cand[k].ms < cand[best].ms)
+            best = k;
     }
     HIPCHECK(hipStreamSynchronize(h->stream));
     (void)hipFree(saved);
     h->pending = false;
     h->fparity = 0;
-    h->active_plan = h->plan = best;
+    set_x_lines(h, cand[best].xl);
+    h->active_plan = h->plan = cand[best].plan;
     std::lock_guard<std::mutex> g(g_tune_mu);
-    g_tune_cache[key] = best;
+    g_tune_cache[key] = cand[best];
+    tune_cache_save();
     return 0;
 }
 
@@ -904,7 +1043,7 @@ template <class R>
 void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles, int grid_chunks)
 {
     const bool imag = b->mode == SSCN_IMAG;
-    const FusedLaunch f{b->d_inst, b->d_work, b->d_nwork, std::max(grid_tiles, 1), b->W};
+    const FusedLaunch f{b->d_inst, b->d_work, b->d_nwork, std::max(grid_tiles, 1), b->W, nullptr};
     for (int64_t s = 0; s < nsteps; ++s) {
         if (imag)
             launch_fused<R, false>(f, b->fparity, b->part[b->pbuf], b->part[b->pbuf ^ 1], b->pending ? 1 : 0, st);
@@ -1406,10 +1545,12 @@ int sscn_set_plan(sscn_handle *h, int plan)
     return 0;
 }
 
-int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *plan)
+int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *plan, int *x_lines)
 {
     if (!h)
         return fail(SSCN_EINVAL, "null argument");
+    if (x_lines)
+        *x_lines = h->xL;
     if (plan)
         *plan = h->plan == SSCN_PLAN_AUTO ? SSCN_PLAN_AUTO : h->active_plan;
     for (int a = 0; a < 3; ++a) {

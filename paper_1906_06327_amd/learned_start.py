@@ -201,39 +201,83 @@ def train(net, X, T, epochs, lr=1e-3, seed=0, log=print, log_every=50):
     return hist
 
 
-def propose(net_params, plist):
+def propose(net_params, plist, chans=CHANS, bott=BOTT):
     """Network output (B, n, n, 16) fp32 device tensor for plist."""
     import torch
-    net = nn.UNet(len(plist), N_GRID, N_GRID, chans=CHANS, bott=BOTT, params=net_params)
+    net = nn.UNet(len(plist), N_GRID, N_GRID, chans=chans, bott=bott, params=net_params)
     X = _bf16_device(torch, features(plist))
     out = net.forward(X).clone()
     return out
 
 
-def evaluate(net_params, plist, seeds, dt=2e-3, max_steps=2000000, tol=1e-8, log=print):
-    """Both starts to |dmu| < tol on the same GPU, one batch each."""
+def plain_runs(plist, seeds, dt=2e-3, max_steps=2000000, tol=1e-8, log=print):
+    """The plain method: every instance alone from Eq. (fun), one after the
+    other (the same kernels and criterion as a batch of one)."""
     import torch
+    steps, walls, counts, mus = [], [], [], []
+    for k, p in enumerate(plist):
+        b, ps, st, wall, obs, cnt = _run_batch(torch, [p], dt, max_steps, tol, [seeds[k]], log=None)
+        b.close()
+        steps.append(st[0])
+        walls.append(wall)
+        counts.append(cnt[0])
+        mus.append(obs[0]["mu"])
+        log(f"[plain] instance {k + 1}/{len(plist)}: {st[0]} steps, {wall:.2f} s")
+    return steps, walls, counts, mus
+
+
+def evaluate(net_params, plist, seeds, dt=2e-3, max_steps=2000000, tol=1e-8, plain=False, log=print,
+             chans=CHANS, bott=BOTT):
+    """The learned start and Eq. (fun) to |dmu| < tol on the same GPU, one
+    batch each; with plain, also every instance alone from Eq. (fun)."""
+    import torch
+    res_plain = plain_runs(plist, seeds, dt, max_steps, tol, log) if plain else None
     b, ps, st0, wall0, obs0, cnt0 = _run_batch(torch, plist, dt, max_steps, tol, seeds, log=log,
                                                tag="one-vortex start")
+    finals = [b.get_state(k) for k in range(len(plist))]
     b.close()
     log(f"[evaluate] one-vortex start: {wall0:.1f} s")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    starts = propose(net_params, plist)
+    starts = propose(net_params, plist, chans, bott)
     torch.cuda.synchronize()
     t_inf = time.perf_counter() - t0
     b, ps, st1, wall1, obs1, cnt1 = _run_batch(torch, plist, dt, max_steps, tol, seeds, starts=starts, log=log,
                                                tag="learned start")
     b.close()
+    # distance of each start from the state the one-vortex run converged to
+    d_learned, d_fun = [], []
+    import workloads as W
+    pred = starts[..., :2].cpu().numpy().astype(np.float64)
+    b0 = Batch([tf_instance(*p, n=N_GRID, dt=dt) for p in plist])
+    for k in range(len(plist)):
+        b0.init_state(k, 1, W.phase_field(seeds[k], N_GRID, N_GRID), 1.0)
+        z = pred[k, ..., 0] + 1j * pred[k, ..., 1]
+        z[0, :] = 0
+        z[:, 0] = 0
+        d_learned.append(phase_distance(z, finals[k]))
+        d_fun.append(phase_distance(b0.get_state(k), finals[k]))
+    b0.close()
     log(f"[evaluate] learned start: inference {t_inf:.2f} s + run {wall1:.1f} s")
     st0a, st1a = np.array(st0), np.array(st1)
     rows = []
     for k in range(len(plist)):
         rows.append(dict(omega=plist[k][0], g=plist[k][1], nu=plist[k][2],
+                         distance_learned=round(d_learned[k], 5), distance_one_vortex=round(d_fun[k], 5),
                          steps_one_vortex=int(st0[k]), steps_learned=int(st1[k]),
                          vortices_one_vortex=cnt0[k], vortices_learned=cnt1[k],
                          mu_one_vortex=obs0[k]["mu"], mu_learned=obs1[k]["mu"]))
     both = (st0a > 0) & (st1a > 0)
+    extra = {}
+    if res_plain is not None:
+        pst, pwall, pcnt, pmu = res_plain
+        for k, r in enumerate(rows):
+            r["steps_plain"] = int(pst[k])
+            r["wall_plain_s"] = round(pwall[k], 3)
+        extra = dict(wall_plain_s=round(sum(pwall), 3),
+                     plain_steps_equal_batched=int(sum(1 for k in range(len(plist)) if pst[k] == st0[k])),
+                     speedup_learned_batched_vs_plain=round(sum(pwall) / (wall1 + t_inf), 3),
+                     speedup_batched_vs_plain=round(sum(pwall) / wall0, 3))
     return dict(
         instances=len(plist), tol=tol, dt=dt, grid=N_GRID,
         wall_one_vortex_s=round(wall0, 3), wall_learned_s=round(wall1 + t_inf, 3),
@@ -247,7 +291,22 @@ def evaluate(net_params, plist, seeds, dt=2e-3, max_steps=2000000, tol=1e-8, log
         same_vortex_count=int(sum(1 for r in rows if r["vortices_one_vortex"] == r["vortices_learned"])),
         lower_or_equal_mu_learned=int(sum(1 for r in rows if r["mu_learned"] <= r["mu_one_vortex"] + 1e-7)),
         both_converged=int(both.sum()),
+        median_distance_learned=round(float(np.median(d_learned)), 5),
+        median_distance_one_vortex=round(float(np.median(d_fun)), 5),
+        total_steps_both_converged_one_vortex=int(st0a[both].sum()),
+        total_steps_both_converged_learned=int(st1a[both].sum()),
+        learned_fewer_steps=int((st1a[both] < st0a[both]).sum()),
+        **extra,
         rows=rows)
+
+
+def phase_distance(a, b):
+    """min over phi of |a/|a| - e^{i phi} b/|b||: sqrt(2 - 2 |<a, b>|) for
+    unit vectors (0 = the same state up to a global phase, sqrt 2 =
+    orthogonal)."""
+    a = a / np.linalg.norm(a)
+    b = b / np.linalg.norm(b)
+    return float(np.sqrt(max(0.0, 2.0 - 2.0 * abs(np.vdot(b, a)))))
 
 
 def save_params(path, params):
@@ -278,6 +337,9 @@ def main(argv=None):
     ap.add_argument("--weights", default=None, help="load weights (npz) and skip generate/train")
     ap.add_argument("--save-weights", default=None)
     ap.add_argument("--out", default=None, help="JSON summary path")
+    ap.add_argument("--plain", action="store_true",
+                    help="also run every evaluation instance alone from Eq. (fun)")
+    ap.add_argument("--no-eval", action="store_true", help="generate and train only")
     a = ap.parse_args(argv)
     import torch
 
@@ -307,9 +369,15 @@ def main(argv=None):
         if a.save_weights:
             save_params(a.save_weights, params)
         del X, T, net
+    if a.no_eval:
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return
     ev_plist = draw(a.eval, a.seed + 1)
     ev_seeds = [a.seed * 10 + 5000000 + k if a.phase_seed < 0 else a.phase_seed for k in range(a.eval)]
-    res["evaluate"] = evaluate(params, ev_plist, ev_seeds, dt=a.dt, max_steps=a.eval_steps, log=log)
+    res["evaluate"] = evaluate(params, ev_plist, ev_seeds, dt=a.dt, max_steps=a.eval_steps, plain=a.plain,
+                               log=log)
     summary = {k: v for k, v in res["evaluate"].items() if k != "rows"}
     log(json.dumps(summary))
     if a.out:
