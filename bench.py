@@ -104,38 +104,52 @@ def profile_sample(P, torch):
 
 
 def timed_steps(P, torch, cfg, steps, warmup, mode=0):
-    s = P.Solver(W.solver_params(cfg, mode=mode))
+    """Warm up, then time exactly `steps` steps: wall clock between two
+    synchronisations, and HIP events recorded on the solver's stream (the
+    current torch stream, which the solver launches on) around the same
+    region.  Returns (solver, wall seconds, event milliseconds per step)."""
+    s = P.Solver(W.solver_params(cfg, mode=mode), stream=torch.cuda.current_stream())
     ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
     s.init_state(cfg.get("kind", 1), ph, cfg.get("d_xy", 1.0), cfg.get("d_z", 0.0))
     s.step(warmup)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
+    e0.record()
     s.step(steps)
+    e1.record()
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return s, dt
+    return s, dt, e0.elapsed_time(e1) / steps
 
 
-def kernel_roofline(s, cfg, nsteps=200, traffic_key=None):
-    """Average duration of the dominant kernel of a step (HIP events on the
-    solver's stream) and its algorithmic bandwidth: 2*c bytes per point per
-    axis sweep it performs (one read and one write of the state per sweep,
-    complex size c), i.e. 2*c*P per sweep kernel and 2*d*c*P for the fused
-    2D step, which performs both sweeps of a step in one launch."""
-    ms = s.profile_step(nsteps)
+def kernel_roofline(s, cfg, step_ms, nlaunch=200, traffic_key=None):
+    """Average duration of the dominant kernel of a step and its algorithmic
+    bandwidth.  The fused 2D plan launches one kernel per step (plus one
+    final rescale per 64-step graph), so its duration is the event time of
+    the timed region per step, step_ms.  The sweep plans launch several;
+    each is timed over nlaunch back-to-back launches between two HIP events
+    on the solver's stream (sscn_profile_kernel).  Algorithmic bytes: 2*c
+    per point per axis sweep the kernel performs (one read and one write of
+    the state per sweep, complex size c), i.e. 2*c*P per sweep kernel and
+    2*d*c*P for the fused 2D step, which performs both sweeps of a step in
+    one launch."""
     plan = s.solver_info()["plan"]
     dim = cfg["dim"]
     pts = cfg["nx"] * cfg["ny"] * (cfg["nz"] if dim == 3 else 1)
     esize = 16 if cfg.get("precision", 0) == 0 else 8
     if plan == 2:
-        names, dom = ("x",), "x"
+        names = ("fused",)
         per_launch = 2 * dim * esize * pts
-        label = "fused 2D step (H1 + x + y)"
     else:
-        names = ("x", "y", "z") if dim == 3 else ("x", "y")
-        dom = max(names, key=lambda k: ms[k])
+        names = ("x", "y", "z")[:dim]
         per_launch = 2 * esize * pts
-        label = f"{dom}-sweep"
+    if plan == 2:
+        ms = {"fused": step_ms}
+    else:
+        ms = {k: s.profile_kernel(w, nlaunch) for w, k in enumerate(names)}
+    dom = max(names, key=lambda k: ms[k])
+    label = "fused 2D step (H1 + x + y)" if plan == 2 else f"{dom}-sweep"
     gbs = per_launch / (ms[dom] * 1e-3) / 1e9
     kind = "fused2d" if plan == 2 else f"{dom}sweep"
     traffic = measured_traffic(traffic_key) if traffic_key and traffic_key.startswith(kind) else None
@@ -143,9 +157,11 @@ def kernel_roofline(s, cfg, nsteps=200, traffic_key=None):
             "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
             "traffic_unit": "bytes per launch (counters)",
             "traffic_over_algorithmic": round(traffic / per_launch, 3) if traffic else None,
-            "kernel": label,
-            "plan": {1: "sweeps", 2: "fused"}.get(plan, plan), "bytes_per_launch": per_launch,
-            "kernel_ms": {k: round(ms[k], 5) for k in names}, "step_ms_events": round(ms["step"], 5)}
+            "kernel": label, "plan": {1: "sweeps", 2: "fused"}.get(plan, plan),
+            "x_lines_per_block": s.solver_info()["x_lines"],
+            "bytes_per_launch": per_launch, "kernel_ms": {k: round(v, 6) for k, v in ms.items()},
+            "timing": "events around the timed steps" if plan == 2 else "events around back-to-back launches",
+            "step_ms_events": round(step_ms, 6)}
 
 
 def batch_run(P, torch, steps=200):
@@ -178,13 +194,13 @@ def converge_run(P, torch, cfg, precision, max_steps=3000000):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     s.init_state(1, ph, 1.0)
-    steps, ok = s.converge(max_steps, check_every=chk, tol=1e-8, switch_tol=2e-6)
+    steps, ok = s.converge(max_steps, check_every=chk, tol=1e-8, switch_tol=3e-7)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ob = s.observables()
     out = {"precision": "c128" if precision == 0 else "c64 bulk -> c128", "steps": steps,
            "converged": ok, "wall_s": round(wall, 3), "mu": ob["mu"], "energy": ob["energy"],
-           "vortices": s.vortex_count()}
+           "vortices": s.vortex_count(), "fp32_steps": s.switch_step if precision == 1 else 0}
     s.close()
     return out
 
@@ -226,10 +242,10 @@ def main():
         profile_sample(P, torch)
         return
 
-    s, dt = timed_steps(P, torch, cfg, a.steps, a.warmup)
+    s, dt, step_ms = timed_steps(P, torch, cfg, a.steps, a.warmup)
     pts = cfg["nx"] * cfg["ny"]
     value = pts * a.steps / dt
-    roof = kernel_roofline(s, cfg, traffic_key=f"fused2d_512_{a.precision}")
+    roof = kernel_roofline(s, cfg, step_ms, traffic_key=f"fused2d_512_{a.precision}")
     s.close()
 
     out = {
@@ -248,21 +264,21 @@ def main():
     if not a.no_extras:
         variants = {}
         c64 = dict(W.CONFIGS["c2"], precision=1)
-        s, dt = timed_steps(P, torch, c64, 5000, 256)
+        s, dt, sm = timed_steps(P, torch, c64, 5000, 256)
         variants["c2_complex64"] = {"updates_per_s": round(pts * 5000 / dt, 1),
                                     "ms_per_step": round(dt / 5000 * 1e3, 6),
-                                    "roofline": kernel_roofline(s, c64)}
+                                    "roofline": kernel_roofline(s, c64, sm)}
         s.close()
-        s, dt = timed_steps(P, torch, W.CONFIGS["c2"], 5000, 256, mode=1)
+        s, dt, _ = timed_steps(P, torch, W.CONFIGS["c2"], 5000, 256, mode=1)
         variants["c2_real_time_complex128"] = {"updates_per_s": round(pts * 5000 / dt, 1),
                                                "ms_per_step": round(dt / 5000 * 1e3, 6)}
         s.close()
         c3 = W.CONFIGS["c3"]
-        s, dt = timed_steps(P, torch, c3, 1000, 64)
+        s, dt, sm = timed_steps(P, torch, c3, 1000, 64)
         p3 = c3["nx"] * c3["ny"] * c3["nz"]
         variants["c3_3d_complex64"] = {"updates_per_s": round(p3 * 1000 / dt, 1),
                                        "ms_per_step": round(dt / 1000 * 1e3, 6),
-                                       "roofline": kernel_roofline(s, c3, 100,
+                                       "roofline": kernel_roofline(s, c3, sm, 100,
                                                                    traffic_key="xsweep_3d_256x256x64_c64")}
         s.close()
         variants["c4_batch_64_instances_complex128"] = batch_run(P, torch)

@@ -154,12 +154,14 @@ int sscn_get_params(sscn_handle *h, sscn_params *out);
  * box 3) unchanged between them.  The paper runs a fixed number of steps;
  * this criterion is the library's.  In complex64 mode the bulk runs in FP32
  * until its plateau (|dmu| < switch_tol, or, once |dmu| < 10 switch_tol, no
- * new minimum of |dmu| for 5 checks), then the state is upcast into fp64_psi_dev (caller-owned
- * complex128 buffer, borrowed from then on as by sscn_set_mode) and the run
- * continues in FP64 to tol.  *steps_out = steps taken, *converged = 1 if the
- * criterion was met within max_steps.  Synchronises at every check. */
+ * new minimum of |dmu| for 5 checks), then the state is upcast into
+ * fp64_psi_dev (caller-owned complex128 buffer, borrowed from then on as by
+ * sscn_set_mode) and the run continues in FP64 to tol.  *steps_out = steps taken, *converged = 1 if the
+ * criterion was met within max_steps, *switch_out (may be NULL) = the step
+ * of the upcast, or -1 if the run stayed in one precision.  Synchronises at
+ * every check. */
 int sscn_converge(sscn_handle *h, int64_t max_steps, int check_every, double tol, double switch_tol,
-                  void *fp64_psi_dev, int64_t *steps_out, int *converged);
+                  void *fp64_psi_dev, int64_t *steps_out, int *converged, int64_t *switch_out);
 
 /* Advance nsteps >= 1 steps with a HIP event recorded on the handle's
  * stream before and after every sweep kernel, and return in ms_out[0..3] the
@@ -177,6 +179,17 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out);
  * to rounding.  SSCN_EINVAL if the fused plan is not available (3D, or a
  * window above 20 rows in complex128 / 32 in complex64). */
 int sscn_set_plan(sscn_handle *h, int plan);
+
+/* Average duration (ms) of one kernel of the step, from nlaunch >= 1
+ * back-to-back launches between two HIP events on the handle's stream:
+ * which = 0 the fused 2D step or the x-sweep (with H1 and the pending
+ * rescale), 1 the y-sweep, 2 the z-sweep.  The launches read the current
+ * state and write the library's work buffer and scratch partials, so the
+ * state is unchanged.  SSCN_EINVAL if the resolved plan has no such kernel
+ * (the fused plan has only kernel 0; 2D has no z-sweep) or the handle uses
+ * the exact whole-line path.  Resolves the plan first (as sscn_step).
+ * Synchronises the stream. */
+int sscn_profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms);
 
 /* Window (rows of look-ahead) used by the truncated line solves per axis
  * (0 means the exact whole-line solve), segment length per axis, the plan

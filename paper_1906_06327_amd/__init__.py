@@ -24,7 +24,7 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
 EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
-           "sscn_solver_info", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
+           "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_destroy",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
@@ -77,8 +77,9 @@ def lib():
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.sscn_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
+        L.sscn_profile_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
         L.sscn_converge.argtypes = [vp, i64, ctypes.c_int, ctypes.c_double, ctypes.c_double, vp,
-                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int)]
+                                    ctypes.POINTER(i64), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(i64)]
         L.sscn_get_params.argtypes = [vp, ctypes.POINTER(Params)]
         L.sscn_batch_init.argtypes = [ctypes.POINTER(Params), ctypes.c_int, ctypes.POINTER(vp), vp,
                                       ctypes.POINTER(vp)]
@@ -209,16 +210,18 @@ class Solver:
         """Run imaginary time to |dmu| < tol at two consecutive checks with an
         unchanged vortex count; complex64 runs switch to complex128 at their
         plateau (into a complex128 tensor allocated here, which becomes
-        self.psi).  Returns (steps, converged)."""
+        self.psi).  Returns (steps, converged); self.switch_step is the step
+        of the upcast (-1 if none)."""
         torch = self._torch
         new = None
         if self.params.precision == SSCN_C64:
             new = torch.empty(self.shape, dtype=torch.complex128, device=self.psi.device)
-        steps, ok = ctypes.c_int64(), ctypes.c_int()
+        steps, ok, sw = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
         _check(lib().sscn_converge(self._h, int(max_steps), int(check_every), float(tol),
                                    float(switch_tol),
                                    ctypes.c_void_p(new.data_ptr()) if new is not None else None,
-                                   ctypes.byref(steps), ctypes.byref(ok)))
+                                   ctypes.byref(steps), ctypes.byref(ok), ctypes.byref(sw)))
+        self.switch_step = int(sw.value)
         p = Params()
         _check(lib().sscn_get_params(self._h, ctypes.byref(p)))
         if new is not None and p.precision == SSCN_C128:
@@ -237,6 +240,13 @@ class Solver:
         ms = (ctypes.c_double * 4)()
         _check(lib().sscn_profile_step(self._h, int(n), ms))
         return {"x": ms[0], "y": ms[1], "z": ms[2], "step": ms[3]}
+
+    def profile_kernel(self, which=0, n=200):
+        """Average ms of kernel `which` (0 fused step or x-sweep, 1 y, 2 z)
+        over n back-to-back launches (HIP events on the solver's stream)."""
+        ms = ctypes.c_double()
+        _check(lib().sscn_profile_kernel(self._h, int(which), int(n), ctypes.byref(ms)))
+        return ms.value
 
     def set_plan(self, plan):
         _check(lib().sscn_set_plan(self._h, int(plan)))

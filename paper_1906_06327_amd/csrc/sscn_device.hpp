@@ -38,6 +38,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace sscn {
 
 // Largest number of state elements one thread of the x-sweep stages.
@@ -154,10 +156,46 @@ __device__ __forceinline__ Cx<R> minus_kv_st(const LineCoef<R> &L, Cx<R> vm, Cx<
 // (cst, rst) from row s-W on; then io[r] = v_{s+r} + 2 delta_{s+r} and
 // d_first = delta_s (both uncorrected for the wall; see above).
 // vals[r] = v_{s-W-1+r} (zero outside 1..n-1), loaded by the caller.
+//
+// In FP64 the solve is done in the Cayley form instead: (I + K) z = v and
+// psi' = 2 z - v, with z_first = z_s (uncorrected) in d_first.  It needs no
+// right-hand side -K v per row, and the wall correction is the same (it
+// depends on the matrix only: out_u -= z_1 zeta_u).  The delta form keeps
+// the rounding of 1 + k0 out of FP32 sweeps, where it matters.
 template <class R, int S, int W, int ST = 0>
 __device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Cx<R> cst, Cx<R> rst,
                                              const Cx<R> (&vals)[S + 2 * W + 2], Cx<R> (&io)[S], Cx<R> &d_first)
 {
+    if constexpr (std::is_same<R, double>::value) {
+        const Cx<R> zero = {R(0), R(0)};
+        const Cx<R> ma = L.Am * rst;
+        const Cx<R> alpha = {-ma.re, -ma.im};  // z'_u = r* v_u + alpha z'_{u-1}
+        Cx<R> zps[S + W];
+        Cx<R> zprev = zero;
+#pragma unroll
+        for (int r = 0; r < S + 2 * W; ++r) {
+            const int u = s - W + r;
+            const bool valid = (u >= 1) && (u <= n - 1);
+            Cx<R> zp = zero;
+            if (valid)
+                zp = rst * vals[r + 1] + alpha * zprev;
+            zprev = zp;
+            if (r >= W)
+                zps[r - W] = zp;
+        }
+        Cx<R> znext = zero;
+#pragma unroll
+        for (int r = S + 2 * W - 1; r >= W; --r) {
+            const Cx<R> z = zps[r - W] - cst * znext;
+            if (r < W + S)
+                io[r - W] = R(2) * z - vals[r + 1];
+            if (r == W)
+                d_first = z;
+            znext = z;
+        }
+        return;
+    }
+
     const Cx<R> zero = {R(0), R(0)};
     const Cx<R> ma = L.Am * rst;
     const Cx<R> alpha = {-ma.re, -ma.im};  // d'_u = r* rhs_u + alpha d'_{u-1}
@@ -336,12 +374,14 @@ __device__ __forceinline__ Cx<R> rescale(Cx<R> v, R sm1)
 // tab[0] = c*, tab[1] = r*, tab[1 + u] = zeta_u (u = 1..W).  Stride W + 2.
 
 // x-sweep with the H1 sub-step and the pending rescale (s - 1 read from
-// sm1p, NULL for none) fused in front.  A block stages L whole x-lines in LDS
-// (padded every S elements so that consecutive threads, which own
-// consecutive segments, hit distinct banks); thread p loads, transforms and
-// solves segment p % nseg of line p / nseg (L * nseg <= 256) and stores its
-// S outputs.  src may equal dst: a line is owned by exactly one block, and
-// every load precedes the block's first barrier.
+// sm1p, NULL for none) fused in front.  A block owns L whole x-lines (L a
+// power of two, L * nseg <= 256, nx * L <= 256 * kXLoad).  Staging and the
+// write-back give each line 256 / L consecutive threads that load (store)
+// its points u = m, m + 256/L, ... coalesced; the staged lines sit in LDS
+// padded every S elements so that the solve threads, which own consecutive
+// segments (thread p: segment p % nseg of line p / nseg), hit distinct banks.
+// src may equal dst: a line is owned by exactly one block, and every load
+// precedes the block's first barrier.
 template <class R, int S, int W, bool RT>
 __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
                                                 StepArgs a, int L, const double *__restrict__ sm1p,
@@ -358,21 +398,20 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
     const int line0 = blockIdx.x * L;
     const int tid = threadIdx.x;
 
-    // thread = (line l, segment q): it stages the S points of its segment
-    // and solves for them; every load is issued before any is used
-    const int l = tid / nseg, q = tid - l * nseg;
-    const int line = line0 + l;
-    const int j = line % ny, k = line / ny;
-    const bool inblk = l < L && line < nlines;
-    const bool active = inblk && j > 0 && (a.dim == 2 || k > 0);
-    const int s0 = 1 + q * S;
-    const int64_t base = (int64_t)line * nx;
-    Cx<R> pre[S];
+    // staging map: line sl, first point sm, stride tpl
+    const int tpl = 256 / L;
+    const int sl = tid / tpl, sm = tid - sl * tpl;
+    const int sline = line0 + sl;
+    const int sj = sline % ny, sk = sline / ny;
+    const bool sact = sline < nlines && sj > 0 && (a.dim == 2 || sk > 0);
+    const int64_t sbase = (int64_t)sline * nx;
+    Cx<R> pre[kXLoad];
 #pragma unroll
-    for (int r = 0; r < S; ++r) {
-        pre[r] = Cx<R>{R(0), R(0)};
-        if (active && s0 + r <= nx - 1)
-            pre[r] = ld<R>(src, base + s0 + r);
+    for (int c = 0; c < kXLoad; ++c) {
+        const int u = sm + c * tpl;
+        pre[c] = Cx<R>{R(0), R(0)};
+        if (sact && u >= 1 && u <= nx - 1)
+            pre[c] = ld<R>(src, sbase + u);
     }
     Cx<R> tpre[2];
 #pragma unroll
@@ -387,17 +426,17 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
         }
     }
     const R sr = R((!RT && sm1p) ? *sm1p : 0.0);  // the pending rescale, s - 1
-    if (inblk) {
-        Cx<R> *row = lin + l * LS;
-        const double y = a.y0 + j * a.hy, z = a.z0 + k * a.hz;
+    {
+        Cx<R> *row = lin + sl * LS;
+        const double y = a.y0 + sj * a.hy, z = a.z0 + sk * a.hz;
         const double vyz = a.vy * y * y + (a.dim == 3 ? a.vz * z * z : 0.0);
 #pragma unroll
-        for (int r = 0; r < S; ++r) {
-            const int u = s0 + r;
-            if (u <= nx - 1) {
+        for (int c = 0; c < kXLoad; ++c) {
+            const int u = sm + c * tpl;
+            if (u >= 1 && u <= nx - 1) {
                 Cx<R> v = {R(0), R(0)};
-                if (active) {
-                    v = rescale(pre[r], sr);
+                if (sact) {
+                    v = rescale(pre[c], sr);
                     const double x = a.x0 + u * a.hx;
                     const R w = R(a.vx * x * x + vyz) + R(a.g) * norm2(v);
                     v = h1_apply<R, RT>(v, w, R(a.dt));
@@ -412,6 +451,11 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
             ltab[tid + c2 * 256] = tpre[c2];
     __syncthreads();
 
+    const int l = tid / nseg, q = tid - l * nseg;
+    const int line = line0 + l;
+    const int j = line % ny, k = line / ny;
+    const bool active = l < L && line < nlines && j > 0 && (a.dim == 2 || k > 0);
+    const int s0 = 1 + q * S;
     Cx<R> io[S];
     if (active) {
         const LineCoef<R> Lc = line_coef<R>(a.ax[0], a.omega * (a.y0 + j * a.hy));
@@ -425,6 +469,7 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
     }
     __syncthreads();
     if (active) {
+        Cx<R> *row = lin + l * LS;
         const Cx<R> df = d1[l];
 #pragma unroll
         for (int r = 0; r < S; ++r) {
@@ -432,7 +477,17 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
             if (u <= W)
                 io[r] = io[r] - df * ltab[l * (W + 2) + 1 + u];
             if (u <= nx - 1)
-                st<R>(dst, base + u, io[r]);
+                row[u + u / S] = io[r];
+        }
+    }
+    __syncthreads();
+    if (sact) {
+        const Cx<R> *row = lin + sl * LS;
+#pragma unroll
+        for (int c = 0; c < kXLoad; ++c) {
+            const int u = sm + c * tpl;
+            if (u >= 1 && u <= nx - 1)
+                st<R>(dst, sbase + u, row[u + u / S]);
         }
     }
 }

@@ -242,7 +242,9 @@ int setup(sscn_handle *h)
     h->esize = p.precision == SSCN_C128 ? 16 : 8;
     // x-sweep staging: L lines per block, one (line, segment) per thread
     const int nseg = (p.nx - 2) / kSeg + 1;
-    const int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / p.nx, 512 / (h->W[0] + 2)}));
+    int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / p.nx, 512 / (h->W[0] + 2)}));
+    while (L & (L - 1))  // a power of two: 256 / L threads stage each line
+        L &= L - 1;
     h->xLmax = L;
     set_x_lines(h, L);
     if (nseg > 256 || p.nx > 256 * kXLoad || h->xlds > kXLdsCap)
@@ -373,23 +375,25 @@ unsigned round8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
 constexpr int kScaleSlot = 48;
 
 template <class R, int W, bool RT>
-void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st)
+void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce)
 {
     const int nlines = h->p.ny * (h->p.dim == 3 ? h->p.nz : 1);
     const int blocks = (nlines + h->xL - 1) / h->xL;
     double *sm1 = nullptr;
     if (!RT && npart > 0) {
         sm1 = h->obs_buf + kScaleSlot;
-        hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, st, h->partials, npart, h->args.dV, sm1);
+        if (reduce)
+            hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, st, h->partials, npart, h->args.dV, sm1);
     }
     hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
                        (V<R> *)dst, h->args, h->xL, (const double *)sm1, (const Cx<R> *)h->tab[0]);
 }
 
+// reduce = false reuses the s - 1 that the last reducing launch left
 template <class R, bool RT>
-void launch_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st)
+void launch_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce = true)
 {
-#define SSCN_CALL_X(Wc) go_x<R, Wc, RT>(h, src, dst, npart, st)
+#define SSCN_CALL_X(Wc) go_x<R, Wc, RT>(h, src, dst, npart, st, reduce)
     SSCN_W_SWITCH(h->W[0], SSCN_CALL_X)
 #undef SSCN_CALL_X
 }
@@ -879,7 +883,7 @@ int autotune(sscn_handle *h)
         std::lock_guard<std::mutex> g(g_tune_mu);
         tune_cache_load();
         auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end() && it->second.xl <= h->xLmax &&
+        if (it != g_tune_cache.end() && it->second.xl <= h->xLmax && !(it->second.xl & (it->second.xl - 1)) &&
             (it->second.plan == SSCN_PLAN_SWEEPS || h->fused_ok)) {
             set_x_lines(h, it->second.xl);
             h->active_plan = h->plan = it->second.plan;
@@ -1532,6 +1536,107 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out)
     return rc;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Launch kernel `which` of the step (0: the fused step or the x-sweep, 1:
+// y-sweep, 2: z-sweep) nlaunch times back to back from psi into the work
+// buffer, between two events on the handle's stream.
+template <class R>
+int profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms)
+{
+    const bool imag = h->p.mode == SSCN_IMAG;
+    const bool fused = h->active_plan == SSCN_PLAN_FUSED;
+    const int npk = std::max({h->nemit, h->ntiles, kRedBlocks});
+    double *scratch = nullptr;
+    if (hipMalloc(&scratch, sizeof(double) * 2 * npk) != hipSuccess)
+        return fail(SSCN_ENOMEM, "hipMalloc of the profiling partials failed");
+    HIPCHECK(hipMemsetAsync(scratch, 0, sizeof(double) * 2 * npk, h->stream));
+    sscn_handle t = *h;  // the same kernels with partials into the scratch
+    t.partials = scratch;
+    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0], &h->inst_host};
+    auto launch = [&](bool first) {
+        if (fused) {
+            if (imag)
+                launch_fused<R, false>(f, 0, scratch, scratch + npk, first ? 0 : 1, h->stream);
+            else
+                launch_fused<R, true>(f, 0, nullptr, nullptr, 0, h->stream);
+            if (imag && first)  // the partials of this state are the next launches' input
+                (void)hipMemcpyAsync(scratch, scratch + npk, sizeof(double) * npk, hipMemcpyDeviceToDevice,
+                                     h->stream);
+        } else if (which == 0) {
+            if (imag)
+                launch_x<R, false>(&t, h->psi, h->work, first ? 0 : h->nemit, h->stream, false);
+            else
+                launch_x<R, true>(&t, h->psi, h->work, 0, h->stream, false);
+        } else if (which == 1) {
+            if (imag && h->p.dim == 2)
+                launch_y<R, true>(&t, h->psi, h->work, h->stream);
+            else
+                launch_y<R, false>(&t, h->psi, h->work, h->stream);
+        } else {
+            if (imag)
+                launch_z<R, true>(&t, h->psi, h->work, h->stream);
+            else
+                launch_z<R, false>(&t, h->psi, h->work, h->stream);
+        }
+    };
+    if (!fused && which == 0 && imag) {  // partials of the state, and s - 1 from them
+        launch_y<R, false>(&t, h->psi, h->work, h->stream);
+        if (h->p.dim == 2)
+            launch_y<R, true>(&t, h->psi, h->work, h->stream);
+        else
+            launch_z<R, true>(&t, h->psi, h->work, h->stream);
+        hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, h->stream, scratch, h->nemit, h->args.dV,
+                           h->obs_buf + kScaleSlot);
+    }
+    launch(true);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = 0;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        rc = fail(SSCN_EHIP, "hipEventCreate failed");
+    if (!rc) {
+        (void)hipEventRecord(e0, h->stream);
+        for (int k = 0; k < nlaunch; ++k)
+            launch(false);
+        (void)hipEventRecord(e1, h->stream);
+        float ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            rc = fail(SSCN_EHIP, "event timing failed");
+        else if (hipGetLastError() != hipSuccess)
+            rc = fail(SSCN_EHIP, "kernel launch failed");
+        *avg_ms = ms / nlaunch;
+    }
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(h->stream);
+    (void)hipFree(scratch);
+    return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sscn_profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms)
+{
+    if (!h || !avg_ms || nlaunch < 1 || nlaunch > 100000 || which < 0 || which > 2)
+        return fail(SSCN_EINVAL, "bad profile_kernel arguments");
+    int rt = autotune(h);
+    if (rt)
+        return rt;
+    if (h->exact)
+        return fail(SSCN_EINVAL, "the exact whole-line path has no kernel to profile this way");
+    if ((h->active_plan == SSCN_PLAN_FUSED && which != 0) || (h->p.dim == 2 && which == 2))
+        return fail(SSCN_EINVAL, "this plan has no such kernel");
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return h->p.precision == SSCN_C128 ? profile_kernel<double>(h, which, nlaunch, avg_ms)
+                                       : profile_kernel<float>(h, which, nlaunch, avg_ms);
+}
+
 int sscn_set_plan(sscn_handle *h, int plan)
 {
     if (!h || plan < SSCN_PLAN_AUTO || plan > SSCN_PLAN_FUSED)
@@ -1571,8 +1676,10 @@ int sscn_get_params(sscn_handle *h, sscn_params *out)
 }
 
 int sscn_converge(sscn_handle *h, int64_t max_steps, int check_every, double tol, double switch_tol,
-                  void *fp64_psi_dev, int64_t *steps_out, int *converged)
+                  void *fp64_psi_dev, int64_t *steps_out, int *converged, int64_t *switch_out)
 {
+    if (switch_out)
+        *switch_out = -1;
     if (!h || max_steps < 0 || check_every < 1 || !(tol > 0))
         return fail(SSCN_EINVAL, "bad converge arguments");
     if (h->p.mode != SSCN_IMAG)
@@ -1608,6 +1715,8 @@ int sscn_converge(sscn_handle *h, int64_t max_steps, int check_every, double tol
                 r = sscn_set_mode(h, SSCN_IMAG, SSCN_C128, fp64_psi_dev);
                 if (r)
                     return r;
+                if (switch_out)
+                    *switch_out = done;
                 prev = std::nan("");
                 hits = 0;
                 count_prev = -1;

@@ -376,6 +376,35 @@ def test_autotuner_cache_file_and_x_lines(P, dim, tmp_path, monkeypatch):
     assert "%dx%d" % (other["nx"], other["ny"]) in text and '"x_lines": %d' % info["x_lines"] in text, text
 
 
+@pytest.mark.parametrize("dim,plan,mode", [(2, 2, 0), (2, 1, 0), (2, 1, 1), (3, 1, 0)])
+def test_profile_kernel_leaves_state_alone(P, dim, plan, mode):
+    """Per-kernel timing runs the step's kernels into scratch: positive
+    durations for the kernels the plan has, an error for the others, and the
+    state and the next steps unchanged (still equal to the oracle's)."""
+    if dim == 2:
+        cfg = dict(dim=2, nx=100, ny=90, nz=1, hx=0.12, hy=0.13, hz=0.1, gamma=1.0, nu=1.1, lam=1.0,
+                   g=50.0, omega=0.5, dt=2e-3, mode=mode, precision=0)
+    else:
+        cfg = dict(dim=3, nx=40, ny=36, nz=30, hx=0.3, hy=0.3, hz=0.3, gamma=1.0, nu=1.1, lam=2.0,
+                   g=30.0, omega=0.4, dt=2e-3, mode=mode, precision=0)
+    announce(f"profile_kernel dim={dim} plan={plan} mode={mode}")
+    s, op = both(P, cfg)
+    s.set_plan(plan)
+    ph = W.phase_field(6, cfg["ny"], cfg["nx"])
+    s.init_state(1, ph, 1.0)
+    s.step(5)
+    kernels = [0] if plan == 2 else ([0, 1] if dim == 2 else [0, 1, 2])
+    for which in kernels:
+        assert s.profile_kernel(which, 20) > 0
+    for which in set(range(3)) - set(kernels):
+        with pytest.raises(P.SSCNError):
+            s.profile_kernel(which, 5)
+    s.step(5)
+    ref = O.step(op, O.init_state(op, 1, ph, 1.0), 10)
+    assert rel(s.get_state(), ref) <= TOL64
+    s.close()
+
+
 def test_fused_plan_rejected_in_3d(P):
     cfg = dict(dim=3, nx=20, ny=20, nz=20, hx=0.2, hy=0.2, hz=0.2, gamma=1.0, nu=1.0, lam=2.0,
                g=10.0, omega=0.3, dt=1e-3, mode=0, precision=0)
@@ -405,5 +434,6 @@ def test_converge_fp64_and_mixed_precision(P):
     s32.init_state(1, ph, 1.0)
     steps32, ok32 = s32.converge(200000, check_every=20, tol=1e-9, switch_tol=1e-6)
     assert ok32 and s32.params.precision == 0 and s32.psi.dtype.itemsize == 16
+    assert 0 < s32.switch_step < steps32 and s.switch_step == -1
     assert abs(s32.observables()["mu"] - mu64) < 1e-7
     s32.close()
