@@ -255,6 +255,19 @@ int sscn_batch_set_state_device(sscn_batch *b, int k);
  * plaquette, density mask).  Synchronises the stream. */
 int sscn_batch_vortex_count(sscn_batch *b, int k, double density_frac, int box, int *count);
 
+/* Plan of the batch's steps: SSCN_PLAN_FUSED (one fused 2D step kernel over
+ * every instance's tiles), SSCN_PLAN_SWEEPS (an x-sweep kernel and a
+ * y-sweep kernel over every instance's line blocks and y tiles, with a
+ * per-instance rescale), or SSCN_PLAN_AUTO (default: the first stepping
+ * call times both from a saved copy of the states and keeps the faster).
+ * Both plans give the same steps within rounding.  SSCN_EINVAL for the
+ * sweep plan when an instance's lines are too long to stage. */
+int sscn_batch_set_plan(sscn_batch *b, int plan);
+
+/* The plan in use (SSCN_PLAN_AUTO until the first stepping call resolves
+ * it) and the common window W of the batch.  Either pointer may be NULL. */
+int sscn_batch_info(sscn_batch *b, int *plan, int *window);
+
 void sscn_batch_destroy(sscn_batch *b);
 
 const char *sscn_strerror(int code);

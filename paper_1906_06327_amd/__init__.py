@@ -26,7 +26,8 @@ EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
-           "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_destroy",
+           "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
+           "sscn_batch_info", "sscn_batch_destroy",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -92,6 +93,8 @@ def lib():
         L.sscn_batch_set_state_device.argtypes = [vp, ctypes.c_int]
         L.sscn_batch_vortex_count.argtypes = [vp, ctypes.c_int, ctypes.c_double, ctypes.c_int,
                                               ctypes.POINTER(ctypes.c_int)]
+        L.sscn_batch_set_plan.argtypes = [vp, ctypes.c_int]
+        L.sscn_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.sscn_batch_destroy.argtypes = [vp]
         L.sscn_batch_destroy.restype = None
         L.sscn_destroy.argtypes = [vp]
@@ -329,6 +332,14 @@ class Batch:
         out = np.empty((p.ny, p.nx), dtype=dtype)
         _check(lib().sscn_batch_get_state(self._h, int(k), out.ctypes.data))
         return out
+
+    def set_plan(self, plan):
+        _check(lib().sscn_batch_set_plan(self._h, int(plan)))
+
+    def info(self):
+        pl, w = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sscn_batch_info(self._h, ctypes.byref(pl), ctypes.byref(w)))
+        return {"plan": int(pl.value), "window": int(w.value)}
 
     def set_state_device(self, k):
         """Instance k's tensor self.psi[k] was written in place: zero its

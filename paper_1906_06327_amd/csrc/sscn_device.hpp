@@ -383,19 +383,17 @@ __device__ __forceinline__ Cx<R> rescale(Cx<R> v, R sm1)
 // src may equal dst: a line is owned by exactly one block, and every load
 // precedes the block's first barrier.
 template <class R, int S, int W, bool RT>
-__global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
-                                                StepArgs a, int L, const double *__restrict__ sm1p,
-                                                const Cx<R> *__restrict__ tab)
+__device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
+                                             const StepArgs &a, int L, const double *__restrict__ sm1p,
+                                             const Cx<R> *__restrict__ tab, int line0, unsigned char *smem)
 {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    Cx<R> *lin = reinterpret_cast<Cx<R> *>(smem_raw);
+    Cx<R> *lin = reinterpret_cast<Cx<R> *>(smem);
     const int nx = a.nx, ny = a.ny;
     const int LS = nx + nx / S + 1;
     Cx<R> *ltab = lin + (size_t)L * LS;      // L rows of W + 2 table entries
     Cx<R> *d1 = ltab + (size_t)L * (W + 2);  // delta_1 of each staged line
     const int nlines = ny * (a.dim == 3 ? a.nz : 1);
     const int nseg = (nx - 2) / S + 1;
-    const int line0 = blockIdx.x * L;
     const int tid = threadIdx.x;
 
     // staging map: line sl, first point sm, stride tpl
@@ -492,6 +490,15 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
     }
 }
 
+template <class R, int S, int W, bool RT>
+__global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
+                                                StepArgs a, int L, const double *__restrict__ sm1p,
+                                                const Cx<R> *__restrict__ tab)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    xsweep_block<R, S, W, RT>(src, dst, a, L, sm1p, tab, blockIdx.x * L, smem_raw);
+}
+
 // s - 1 of the pending rescale, s = 1/sqrt(dV sum of the npart norm
 // partials), summed in fixed order by one block.
 __global__ __launch_bounds__(256) void k_norm_scale(const double *partials, int npart, double dV, double *out)
@@ -586,18 +593,13 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
     }
 }
 
+// One y tile: columns bx*64 .. +63 of plane bz, segment group by; the norm
+// partial of its outputs (EMIT) goes to *partial.
 template <class R, int S, int W, bool EMIT>
-__global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__restrict__ src,
-                                                typename Vec<R>::T *__restrict__ dst, StepArgs a,
-                                                double *partials, int gx, int gy, int gz,
-                                                const Cx<R> *__restrict__ tab)
+__device__ __forceinline__ void ysweep_block(const typename Vec<R>::T *__restrict__ src,
+                                             typename Vec<R>::T *__restrict__ dst, const StepArgs &a, int bx, int by,
+                                             int bz, double *partial, const Cx<R> *__restrict__ tab, double *red)
 {
-    __shared__ double red[8];
-    const int lb = xcd_logical_block(gx * gy * gz);
-    if (lb < 0)
-        return;
-    const int by = lb % gy, rest = lb / gy;
-    const int bx = rest % gx, bz = rest / gx;
     const int nx = a.nx, ny = a.ny;
     const int i = bx * 64 + threadIdx.x;
     const bool plane_ok = (a.dim == 2 || bz > 0);
@@ -613,8 +615,23 @@ __global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__rest
     if (EMIT) {
         const double b = block_sum_256(acc, red);
         if (threadIdx.x == 0 && threadIdx.y == 0)
-            partials[lb] = b;
+            *partial = b;
     }
+}
+
+template <class R, int S, int W, bool EMIT>
+__global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__restrict__ src,
+                                                typename Vec<R>::T *__restrict__ dst, StepArgs a,
+                                                double *partials, int gx, int gy, int gz,
+                                                const Cx<R> *__restrict__ tab)
+{
+    __shared__ double red[8];
+    const int lb = xcd_logical_block(gx * gy * gz);
+    if (lb < 0)
+        return;
+    const int by = lb % gy, rest = lb / gy;
+    const int bx = rest % gx, bz = rest / gx;
+    ysweep_block<R, S, W, EMIT>(src, dst, a, bx, by, bz, partials + lb, tab, red);
 }
 
 template <class R, int S, int W, bool EMIT>
@@ -661,6 +678,7 @@ __global__ __launch_bounds__(256) void k_zsweep(const typename Vec<R>::T *__rest
 // different sizes and parameters.
 struct Inst2D {
     int nx, ny, tiles_x, tiles_y, poff, active;
+    int xl, ygx, ygy, ypoff;  // sweep plan: x lines per block, y tile grid, offset of its partials
     double hx, hy, x0, y0, vx, vy, g, omega, dt, dV;
     AxisCoef ax[2];
     void *buf[2];
@@ -680,7 +698,7 @@ constexpr int stage_stride(int SC, int S)
 template <class R, int S, int W, int TR, int TC>
 constexpr size_t step2d_lds_bytes()
 {
-    return (size_t)(TR + 2 * W + 2) * (stage_stride(TC + 2 * W + 2, S) + TC + 1) * sizeof(Cx<R>);
+    return (size_t)(TR + 2 * W + 2) * stage_stride(TC + 2 * W + 2, S) * sizeof(Cx<R>);
 }
 
 // One step of a 2D instance per tile.  ONE: a single instance passed by
@@ -696,16 +714,18 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
     constexpr int H = W + 1;
     constexpr int SR = TR + 2 * H, SC = TC + 2 * H;
     constexpr int SCP = stage_stride(SC, S);
-    constexpr int C2 = TC + 1;
     constexpr int NST = (SR * SC + NT - 1) / NT;
     constexpr int NSX = TC / S;
+    constexpr int NXI = (SR * NSX + NT - 1) / NT;  // x-segments per thread
     constexpr int SY = S / 2, NSY = TR / SY;
     constexpr int ST = RT ? 2 : 1;
     constexpr int PP = 4;  // norm partials prefetched per thread
     static_assert(TC % S == 0 && TR % SY == 0 && TC * NSY <= NT, "tile shape");
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    Cx<R> *st1 = reinterpret_cast<Cx<R> *>(smem_raw);  // SR x SCP staged, H1 applied
-    Cx<R> *st2 = st1 + SR * SCP;                         // SR x C2 after the x-solve
+    // SR x SCP staged points, H1 applied; the x-solve writes its outputs
+    // (the TC tile columns of every row) back in place
+    Cx<R> *st1 = reinterpret_cast<Cx<R> *>(smem_raw);
+    auto sx = [&](int rr, int cc) -> Cx<R> & { return st1[rr * SCP + cc + cc / S]; };
     __shared__ Cx<R> d1x[SR];
     __shared__ Cx<R> d1y[TC];
     __shared__ double red[20];
@@ -778,36 +798,45 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         }
         __syncthreads();
 
-        // x-lines of every staged row, outputs for the TC tile columns
-        for (int p = tid; p < SR * NSX; p += NT) {
+        // x-lines of every staged row, outputs for the TC tile columns: all
+        // windows are read before any output is written back
+        Cx<R> xo[NXI][S];
+#pragma unroll
+        for (int k = 0; k < NXI; ++k) {
+            const int p = tid + k * NT;
             const int rr = p / NSX, q = p - rr * NSX;
             const int j = jb + rr;
-            Cx<R> io[S];
 #pragma unroll
             for (int r = 0; r < S; ++r)
-                io[r] = Cx<R>{R(0), R(0)};
-            if (j >= 1 && j <= ny - 1) {
+                xo[k][r] = Cx<R>{R(0), R(0)};
+            if (p < SR * NSX && j >= 1 && j <= ny - 1) {
                 const LineCoef<R> Lc = line_coef<R>(I.ax[0], I.omega * (I.y0 + j * I.hy));
                 const Cx<R> *trow = tabx + (size_t)j * (W + 2);
                 Cx<R> vals[S + 2 * W + 2];
 #pragma unroll
-                for (int r = 0; r < S + 2 * W + 2; ++r) {
-                    const int cc = q * S + r;
-                    vals[r] = st1[rr * SCP + cc + cc / S];
-                }
+                for (int r = 0; r < S + 2 * W + 2; ++r)
+                    vals[r] = sx(rr, q * S + r);
                 Cx<R> df;
                 const int s = c0 + q * S;
-                window_solve<R, S, W, ST>(s, nx, Lc, trow[0], trow[1], vals, io, df);
+                window_solve<R, S, W, ST>(s, nx, Lc, trow[0], trow[1], vals, xo[k], df);
                 if (s == 1)
                     d1x[rr] = df;
 #pragma unroll
                 for (int r = 0; r < S; ++r)
                     if (s + r > nx - 1)
-                        io[r] = Cx<R>{R(0), R(0)};
+                        xo[k][r] = Cx<R>{R(0), R(0)};
             }
+        }
+        __syncthreads();
 #pragma unroll
-            for (int r = 0; r < S; ++r)
-                st2[rr * C2 + q * S + r] = io[r];
+        for (int k = 0; k < NXI; ++k) {
+            const int p = tid + k * NT;
+            const int rr = p / NSX, q = p - rr * NSX;
+            if (p < SR * NSX) {
+#pragma unroll
+                for (int r = 0; r < S; ++r)
+                    sx(rr, H + q * S + r) = xo[k][r];
+            }
         }
         __syncthreads();
         if (c0 == 1) {  // wall rows of the x-lines: Sherman-Morrison term
@@ -815,7 +844,7 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
                 const int rr = p / W, u = 1 + (p - rr * W);
                 const int j = jb + rr;
                 if (j >= 1 && j <= ny - 1 && u <= nx - 1 && u - c0 < TC)
-                    st2[rr * C2 + (u - c0)] = st2[rr * C2 + (u - c0)] - d1x[rr] * tabx[(size_t)j * (W + 2) + 1 + u];
+                    sx(rr, H + u - c0) = sx(rr, H + u - c0) - d1x[rr] * tabx[(size_t)j * (W + 2) + 1 + u];
             }
             __syncthreads();
         }
@@ -832,7 +861,7 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
             Cx<R> vals[SY + 2 * W + 2];
 #pragma unroll
             for (int r = 0; r < SY + 2 * W + 2; ++r)
-                vals[r] = st2[(q * SY + r) * C2 + col];
+                vals[r] = sx(q * SY + r, H + col);
             Cx<R> df;
             window_solve<R, SY, W, ST>(s, ny, Lc, trow[0], trow[1], vals, io, df);
             if (s == 1)
@@ -1246,16 +1275,21 @@ __device__ __forceinline__ StepArgs inst_args(const Inst2D &I)
     a.omega = I.omega;
     a.dt = I.dt;
     a.dV = I.dV;
+    a.ax[0] = I.ax[0];
+    a.ax[1] = I.ax[1];
+    a.ax[2] = I.ax[1];
     return a;
 }
 
 // End of a batched stepping call: for every listed (instance, chunk) item,
 // buf[0] = s buf[parity] with s = 1/sqrt(dV sum of the instance's partials)
 // (imaginary time, rescale = 1) or a plain copy (rescale = 0).
+// With scale != NULL, s - 1 of instance k is scale[k] (sweep plan).
 template <class R>
 __global__ __launch_bounds__(256) void k_batch_finish(const Inst2D *__restrict__ insts, const int2 *__restrict__ fwork,
                                                       const int *__restrict__ nf, int parity,
-                                                      const double *__restrict__ partials, int rescale_on)
+                                                      const double *__restrict__ partials, int rescale_on,
+                                                      const double *__restrict__ scale)
 {
     __shared__ double red[20];
     const int nfw = *nf;
@@ -1264,7 +1298,9 @@ __global__ __launch_bounds__(256) void k_batch_finish(const Inst2D *__restrict__
         const Inst2D &I = insts[wk.x];
         const int64_t n = (int64_t)I.nx * I.ny;
         double sm1 = 0.0;
-        if (rescale_on)
+        if (rescale_on && scale)
+            sm1 = scale[wk.x];
+        else if (rescale_on)
             sm1 = 1.0 / sqrt(I.dV * block_sum_partials_nt<256>(partials + I.poff, I.tiles_x * I.tiles_y, red)) - 1.0;
         const R sr = R(sm1);
         const typename Vec<R>::T *src = reinterpret_cast<const typename Vec<R>::T *>(I.buf[parity]);
@@ -1359,6 +1395,66 @@ __global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const int *_
             }
             mu_prev[k] = mu;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched sweep plan (2D instances): the x- and y-sweeps of every listed
+// instance in one launch each, over work lists of (instance, x line block)
+// and (instance, y tile).  State in buf[0]; the x-sweep writes buf[1] and
+// the y-sweep writes buf[0] back with one norm partial per y tile at
+// partials[I.ypoff + tile].
+
+// s - 1 of the pending rescale of each listed instance, from its partials.
+__global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__restrict__ insts, const int *__restrict__ klist,
+                                                     const int *__restrict__ nk, const double *__restrict__ partials,
+                                                     double *__restrict__ scale)
+{
+    __shared__ double red[8];
+    const int nkk = *nk;
+    for (int it = blockIdx.x; it < nkk; it += gridDim.x) {
+        const int k = klist[it];
+        const Inst2D &I = insts[k];
+        const double tot = block_sum_partials(partials + I.ypoff, I.ygx * I.ygy, red);
+        if (threadIdx.x == 0)
+            scale[k] = 1.0 / sqrt(I.dV * tot) - 1.0;
+    }
+}
+
+template <class R, int S, int W, bool RT>
+__global__ __launch_bounds__(256) void k_batch_xsweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ xwork,
+                                                      const int *__restrict__ nitems, const double *__restrict__ scale,
+                                                      int use_scale)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int nit = *nitems;
+    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+        const int2 wk = xwork[it];
+        const Inst2D &I = insts[wk.x];
+        const StepArgs a = inst_args(I);
+        xsweep_block<R, S, W, RT>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]),
+                                  reinterpret_cast<typename Vec<R>::T *>(I.buf[1]), a, I.xl,
+                                  use_scale ? scale + wk.x : nullptr, reinterpret_cast<const Cx<R> *>(I.tab[0]),
+                                  wk.y, smem_raw);
+        __syncthreads();  // LDS reuse by the next item
+    }
+}
+
+template <class R, int S, int W, bool EMIT>
+__global__ __launch_bounds__(256) void k_batch_ysweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ ywork,
+                                                      const int *__restrict__ nitems, double *__restrict__ partials)
+{
+    __shared__ double red[8];
+    const int nit = *nitems;
+    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
+        const int2 wk = ywork[it];
+        const Inst2D &I = insts[wk.x];
+        const StepArgs a = inst_args(I);
+        const int by = wk.y % I.ygy, bx = wk.y / I.ygy;
+        ysweep_block<R, S, W, EMIT>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[1]),
+                                    reinterpret_cast<typename Vec<R>::T *>(I.buf[0]), a, bx, by, 0,
+                                    partials + I.ypoff + wk.y, reinterpret_cast<const Cx<R> *>(I.tab[1]), red);
+        __syncthreads();
     }
 }
 

@@ -264,7 +264,7 @@ int setup(sscn_handle *h)
         h->nemit = kRedBlocks;
     }
     const size_t flds = (size_t)(kTileR + 2 * h->W[0] + 2) *
-                        (stage_stride(kTileC + 2 * h->W[0] + 2, kSeg) + kTileC + 1) * h->esize;
+                        stage_stride(kTileC + 2 * h->W[0] + 2, kSeg) * h->esize;
     h->fused_ok = p.dim == 2 && !h->exact && h->W[0] > 0 &&
                   h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32) && flds <= 150 * 1024;
     h->ntiles = ((p.nx - 2) / kTileC + 1) * ((p.ny - 2) / kTileR + 1);
@@ -992,6 +992,16 @@ struct sscn_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int graph_k = 0;
+    // sweep plan: x line blocks, y tiles, per-instance rescale
+    int plan = SSCN_PLAN_AUTO, active_plan = SSCN_PLAN_FUSED;
+    bool sweeps_ok = true;
+    std::vector<int> xitems, yitems;
+    int total_x = 0, total_y = 0, grid_x = 0, grid_y = 0, grid_k = 0;
+    size_t xlds = 0;
+    int2 *d_xwork = nullptr, *d_ywork = nullptr;
+    int *d_nx = nullptr, *d_ny = nullptr, *d_klist = nullptr, *d_nk = nullptr;
+    double *ypart = nullptr, *d_scale = nullptr;
+    float tune_ms[3] = {0, 0, 0};
 };
 
 namespace {
@@ -1005,12 +1015,20 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
         order[k] = k;
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return b->ntiles[x] > b->ntiles[y]; });
-    std::vector<int2> wl, fl, ol;
-    std::vector<int> obase(b->n, 0), ocount(b->n, 0);
+    std::vector<int2> wl, fl, ol, xl, yl;
+    std::vector<int> obase(b->n, 0), ocount(b->n, 0), kl;
     for (int k : order)
-        if (b->active[k])
+        if (b->active[k]) {
             for (int t = 0; t < b->ntiles[k]; ++t)
                 wl.push_back(int2{k, t});
+            kl.push_back(k);
+            if (b->sweeps_ok) {
+                for (int t = 0; t < b->xitems[k]; ++t)
+                    xl.push_back(int2{k, t * b->hinst[k].xl});
+                for (int t = 0; t < b->yitems[k]; ++t)
+                    yl.push_back(int2{k, t});
+            }
+        }
     for (int k = 0; k < b->n; ++k) {
         if (b->active[k])
             for (int c = 0; c < b->nchunk[k]; ++c)
@@ -1023,6 +1041,16 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
         }
     }
     const int nw = (int)wl.size(), nfl = (int)fl.size(), nol = (int)ol.size();
+    const int nxl = (int)xl.size(), nyl = (int)yl.size(), nkl = (int)kl.size();
+    if (nxl)
+        HIPCHECK(hipMemcpy(b->d_xwork, xl.data(), sizeof(int2) * nxl, hipMemcpyHostToDevice));
+    if (nyl)
+        HIPCHECK(hipMemcpy(b->d_ywork, yl.data(), sizeof(int2) * nyl, hipMemcpyHostToDevice));
+    if (nkl)
+        HIPCHECK(hipMemcpy(b->d_klist, kl.data(), sizeof(int) * nkl, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_nx, &nxl, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_ny, &nyl, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_nk, &nkl, sizeof(int), hipMemcpyHostToDevice));
     if (nw)
         HIPCHECK(hipMemcpy(b->d_work, wl.data(), sizeof(int2) * nw, hipMemcpyHostToDevice));
     if (nfl)
@@ -1037,16 +1065,78 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
     if (!all_for_obs) {
         b->grid_tiles = nw;
         b->grid_chunks = nfl;
+        b->grid_x = nxl;
+        b->grid_y = nyl;
+        b->grid_k = nkl;
     }
     return 0;
+}
+
+template <class R, int W, bool RT>
+void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st, b->d_inst,
+                       b->d_xwork, b->d_nx, b->d_scale, use_scale);
+}
+
+template <class R, int W, bool EMIT>
+void go_batch_y(const sscn_batch *b, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(std::max(grid, 1)), dim3(64, 4), 0, st, b->d_inst,
+                       b->d_ywork, b->d_ny, b->ypart);
+}
+
+// One step of the sweep plan for every listed instance (state in buf[0]).
+template <class R>
+void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k)
+{
+    const bool imag = b->mode == SSCN_IMAG;
+    const int sc = (imag && b->pending) ? 1 : 0;
+    if (sc)
+        hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
+                           b->d_nk, b->ypart, b->d_scale);
+#define SSCN_CALL_BX(Wc)                                 \
+    do {                                                 \
+        if (imag)                                        \
+            go_batch_x<R, Wc, false>(b, grid_x, sc, st); \
+        else                                             \
+            go_batch_x<R, Wc, true>(b, grid_x, 0, st);   \
+    } while (0)
+    SSCN_W_SWITCH(b->W, SSCN_CALL_BX);
+#undef SSCN_CALL_BX
+#define SSCN_CALL_BY(Wc)                             \
+    do {                                             \
+        if (imag)                                    \
+            go_batch_y<R, Wc, true>(b, grid_y, st);  \
+        else                                         \
+            go_batch_y<R, Wc, false>(b, grid_y, st); \
+    } while (0)
+    SSCN_W_SWITCH(b->W, SSCN_CALL_BY);
+#undef SSCN_CALL_BY
+    if (imag)
+        b->pending = true;
 }
 
 // nsteps fused steps of every listed instance, then the finish pass that
 // leaves each state normalised (imaginary time) in its caller buffer.
 template <class R>
-void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles, int grid_chunks)
+void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles, int grid_chunks, int grid_x,
+                   int grid_y, int grid_k)
 {
     const bool imag = b->mode == SSCN_IMAG;
+    if (b->active_plan == SSCN_PLAN_SWEEPS) {
+        for (int64_t s = 0; s < nsteps; ++s)
+            batch_sweep_step<R>(b, st, grid_x, grid_y, grid_k);
+        if (imag && b->pending) {
+            hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
+                               b->d_nk, b->ypart, b->d_scale);
+            hipLaunchKernelGGL((k_batch_finish<R>), dim3(std::max(grid_chunks, 1)), dim3(256), 0, st, b->d_inst,
+                               b->d_fwork, b->d_nf, 0, b->ypart, 1, (const double *)b->d_scale);
+        }
+        b->pending = false;
+        b->fparity = 0;
+        return;
+    }
     const FusedLaunch f{b->d_inst, b->d_work, b->d_nwork, std::max(grid_tiles, 1), b->W, nullptr};
     for (int64_t s = 0; s < nsteps; ++s) {
         if (imag)
@@ -1061,7 +1151,8 @@ void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles
     }
     if ((imag && b->pending) || b->fparity == 1)
         hipLaunchKernelGGL((k_batch_finish<R>), dim3(std::max(grid_chunks, 1)), dim3(256), 0, st, b->d_inst,
-                           b->d_fwork, b->d_nf, b->fparity, b->part[b->pbuf], (imag && b->pending) ? 1 : 0);
+                           b->d_fwork, b->d_nf, b->fparity, b->part[b->pbuf], (imag && b->pending) ? 1 : 0,
+                           (const double *)nullptr);
     b->pending = false;
     b->fparity = 0;
 }
@@ -1084,9 +1175,9 @@ int batch_graph(sscn_batch *b, int k)
     batch_drop_graph(b);
     HIPCHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
     if (b->precision == SSCN_C128)
-        batch_enqueue<double>(b, k, b->cap, b->total_tiles, b->total_chunks);
+        batch_enqueue<double>(b, k, b->cap, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
     else
-        batch_enqueue<float>(b, k, b->cap, b->total_tiles, b->total_chunks);
+        batch_enqueue<float>(b, k, b->cap, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
     hipError_t e = hipStreamEndCapture(b->cap, &b->graph);
     if (e != hipSuccess)
         return fail(SSCN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -1106,6 +1197,65 @@ void batch_obs_launch(sscn_batch *b, int nchunks, double tol)
                        b->opart, b->d_sums, b->d_mu_prev, b->d_hits, b->d_conv, tol, (long long)b->steps);
 }
 
+// The first stepping call of an SSCN_PLAN_AUTO batch times 8 steps of each
+// plan from a saved copy of every state, restores the states and keeps the
+// faster plan.
+int batch_autotune(sscn_batch *b)
+{
+    if (b->plan != SSCN_PLAN_AUTO)
+        return 0;
+    b->plan = b->active_plan = SSCN_PLAN_FUSED;
+    if (!b->sweeps_ok)
+        return 0;
+    const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
+    std::vector<size_t> off(b->n + 1, 0);
+    for (int k = 0; k < b->n; ++k)
+        off[k + 1] = off[k] + (size_t)b->p[k].nx * b->p[k].ny * esize;
+    char *saved = nullptr;
+    if (hipMalloc(&saved, off[b->n]) != hipSuccess)
+        return fail(SSCN_ENOMEM, "hipMalloc of the batch autotune copy failed");
+    for (int k = 0; k < b->n; ++k)
+        HIPCHECK(hipMemcpyAsync(saved + off[k], b->psi[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice, b->stream));
+    const int plans[2] = {SSCN_PLAN_FUSED, SSCN_PLAN_SWEEPS};
+    float best = 0.f;
+    for (int t = 0; t < 2; ++t) {
+        b->active_plan = plans[t];
+        b->pending = false;
+        b->fparity = 0;
+        b->pbuf = 0;
+        hipEvent_t e0, e1;
+        (void)hipEventCreate(&e0);
+        (void)hipEventCreate(&e1);
+        (void)hipEventRecord(e0, b->stream);
+        if (b->precision == SSCN_C128)
+            batch_enqueue<double>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+        else
+            batch_enqueue<float>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+        (void)hipEventRecord(e1, b->stream);
+        (void)hipEventSynchronize(e1);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        b->tune_ms[plans[t]] = ms;
+        if (t == 0 || ms < best) {
+            best = ms;
+            b->plan = plans[t];
+        }
+        for (int k = 0; k < b->n; ++k)
+            HIPCHECK(hipMemcpyAsync(b->psi[k], saved + off[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice,
+                                    b->stream));
+    }
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    (void)hipFree(saved);
+    HIPCHECK(hipGetLastError());
+    b->active_plan = b->plan;
+    b->pending = false;
+    b->fparity = 0;
+    b->pbuf = 0;
+    return 0;
+}
+
 void batch_free(sscn_batch *b)
 {
     batch_drop_graph(b);
@@ -1115,7 +1265,8 @@ void batch_free(sscn_batch *b)
                 (void)hipFree(q);
     void *bufs[] = {b->d_inst, b->d_work, b->d_fwork, b->d_owork, b->d_nwork, b->d_nf, b->d_no, b->d_obase,
                     b->d_ocount, b->part[0], b->part[1], b->opart, b->d_sums, b->d_mu_prev, b->d_hits, b->d_conv,
-                    b->phase};
+                    b->phase, b->d_xwork, b->d_ywork, b->d_nx, b->d_ny, b->d_klist, b->d_nk, b->ypart,
+                    b->d_scale};
     for (void *q : bufs)
         if (q)
             (void)hipFree(q);
@@ -1780,12 +1931,12 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         b->W = std::max(b->W, tmp[k].W[0]);
     }
     const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
-    const size_t flds = (size_t)(kTileR + 2 * b->W + 2) * (stage_stride(kTileC + 2 * b->W + 2, kSeg) + kTileC + 1) * esize;
+    const size_t flds = (size_t)(kTileR + 2 * b->W + 2) * stage_stride(kTileC + 2 * b->W + 2, kSeg) * esize;
     if (b->W > (b->precision == SSCN_C128 ? 20 : 32) || flds > 150 * 1024)
         return bail(fail(SSCN_EINVAL, "the common window of the batch is too large for the fused step"));
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(SSCN_EHIP, "hipStreamCreateWithFlags failed"));
-    int poff = 0;
+    int poff = 0, ypoff = 0;
     for (int k = 0; k < n; ++k) {
         sscn_handle &h = tmp[k];
         h.W[0] = h.W[1] = b->W;
@@ -1831,6 +1982,26 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         in.buf[1] = w;
         in.tab[0] = b->tabx.back();
         in.tab[1] = b->taby.back();
+        // sweep plan: x-sweep staging as for a single instance (L a power of
+        // two), the y tile grid and the offset of this instance's y partials
+        const int nseg = (h.p.nx - 2) / kSeg + 1;
+        int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / h.p.nx, 512 / (b->W + 2)}));
+        while (L & (L - 1))
+            L &= L - 1;
+        const size_t LS = (size_t)h.p.nx + h.p.nx / kSeg + 1;
+        const size_t xl = (L * LS + (size_t)L * (b->W + 2) + L) * esize;
+        if (nseg > 256 || h.p.nx > 256 * kXLoad || xl > kXLdsCap)
+            b->sweeps_ok = false;
+        b->xlds = std::max(b->xlds, xl);
+        in.xl = L;
+        in.ygx = (h.p.nx + 63) / 64;
+        in.ygy = ((h.p.ny - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock;
+        in.ypoff = ypoff;
+        b->xitems.push_back((h.p.ny + L - 1) / L);
+        b->yitems.push_back(in.ygx * in.ygy);
+        ypoff += in.ygx * in.ygy;
+        b->total_x += b->xitems.back();
+        b->total_y += b->yitems.back();
         b->hinst.push_back(in);
         poff += tx * ty;
         b->total_chunks += b->nchunk.back();
@@ -1852,7 +2023,13 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         hipMalloc(&b->d_sums, sizeof(double) * (14 * n + 2)) != hipSuccess ||
         hipMalloc(&b->d_mu_prev, sizeof(double) * n) != hipSuccess ||
         hipMalloc(&b->d_hits, sizeof(int) * n) != hipSuccess ||
-        hipMalloc(&b->d_conv, sizeof(long long) * n) != hipSuccess)
+        hipMalloc(&b->d_conv, sizeof(long long) * n) != hipSuccess ||
+        hipMalloc(&b->d_xwork, sizeof(int2) * std::max(b->total_x, 1)) != hipSuccess ||
+        hipMalloc(&b->d_ywork, sizeof(int2) * std::max(b->total_y, 1)) != hipSuccess ||
+        hipMalloc(&b->d_nx, sizeof(int)) != hipSuccess || hipMalloc(&b->d_ny, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->d_klist, sizeof(int) * n) != hipSuccess || hipMalloc(&b->d_nk, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->ypart, sizeof(double) * std::max(b->total_y, 1)) != hipSuccess ||
+        hipMalloc(&b->d_scale, sizeof(double) * n) != hipSuccess)
         return bail(fail(SSCN_ENOMEM, "hipMalloc of the batch buffers failed"));
     HIPCHECK(hipMemcpy(b->d_inst, b->hinst.data(), sizeof(Inst2D) * n, hipMemcpyHostToDevice));
     int r = sscn_batch_reset(b);
@@ -1922,10 +2099,15 @@ int sscn_batch_step(sscn_batch *b, int64_t nsteps)
 {
     if (!b || nsteps < 0)
         return fail(SSCN_EINVAL, "bad batch_step arguments");
+    if (nsteps == 0)
+        return 0;
+    int r = batch_autotune(b);
+    if (r)
+        return r;
     if (b->precision == SSCN_C128)
-        batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks);
+        batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
     else
-        batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks);
+        batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
     HIPCHECK(hipGetLastError());
     b->steps += nsteps;
     return 0;
@@ -1981,7 +2163,10 @@ int sscn_batch_run(sscn_batch *b, int64_t max_steps, int check_every, double tol
     if (!b || max_steps < 0 || check_every < 2 || !(tol_dmu > 0))
         return fail(SSCN_EINVAL, "bad batch_run arguments");
     const int K = check_every + (check_every & 1);
-    int r = batch_graph(b, K);
+    int r = batch_autotune(b);
+    if (r)
+        return r;
+    r = batch_graph(b, K);
     if (r)
         return r;
     int64_t done = 0;
@@ -2086,6 +2271,30 @@ int sscn_batch_vortex_count(sscn_batch *b, int k, double density_frac, int box, 
     HIPCHECK(hipMemcpyAsync(&c, out + 1, sizeof c, hipMemcpyDeviceToHost, b->stream));
     HIPCHECK(hipStreamSynchronize(b->stream));
     *count = (int)c;
+    return 0;
+}
+
+int sscn_batch_set_plan(sscn_batch *b, int plan)
+{
+    if (!b || plan < SSCN_PLAN_AUTO || plan > SSCN_PLAN_FUSED)
+        return fail(SSCN_EINVAL, "bad plan");
+    if (plan == SSCN_PLAN_SWEEPS && !b->sweeps_ok)
+        return fail(SSCN_EINVAL, "the batched sweep plan is not available for these instances");
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    batch_drop_graph(b);
+    b->plan = plan;
+    b->active_plan = plan == SSCN_PLAN_SWEEPS ? SSCN_PLAN_SWEEPS : SSCN_PLAN_FUSED;
+    return 0;
+}
+
+int sscn_batch_info(sscn_batch *b, int *plan, int *window)
+{
+    if (!b)
+        return fail(SSCN_EINVAL, "null argument");
+    if (plan)
+        *plan = b->plan == SSCN_PLAN_AUTO ? SSCN_PLAN_AUTO : b->active_plan;
+    if (window)
+        *window = b->W;
     return 0;
 }
 

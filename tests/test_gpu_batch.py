@@ -34,11 +34,13 @@ def mixed(prec, mode=0):
     return out
 
 
+@pytest.mark.parametrize("plan", [1, 2])
 @pytest.mark.parametrize("prec,mode", [(0, 0), (0, 1), (1, 0)])
-def test_batch_step_matches_oracle_per_instance(P, prec, mode):
-    print(f"[gpu-batch] step prec={prec} mode={mode}", flush=True)
+def test_batch_step_matches_oracle_per_instance(P, prec, mode, plan):
+    print(f"[gpu-batch] step prec={prec} mode={mode} plan={plan}", flush=True)
     cfgs = mixed(prec, mode)
     b = P.Batch(cfgs)
+    b.set_plan(plan)
     refs = []
     for k, c in enumerate(cfgs):
         ph = W.phase_field(30 + k, c["ny"], c["nx"])
@@ -58,19 +60,24 @@ def test_batch_step_matches_oracle_per_instance(P, prec, mode):
     b.close()
 
 
-def test_batch_run_drops_converged_instances(P):
+@pytest.mark.parametrize("plan", [0, 1, 2])
+def test_batch_run_drops_converged_instances(P, plan):
     """Instances converge at different steps; each stops exactly there: its
-    state equals the oracle's after that many steps."""
-    print("[gpu-batch] run to convergence", flush=True)
+    state equals the oracle's after that many steps (either plan, or the
+    one the autotuner picks)."""
+    print(f"[gpu-batch] run to convergence plan={plan}", flush=True)
     cfgs = []
     for t in range(4):
         cfgs.append(dict(dim=2, nx=48 + 8 * t, ny=44 + 4 * t, nz=1, hx=0.25, hy=0.25, hz=0.1,
                          gamma=1.0, nu=1.1, lam=1.0, g=5.0 + 20.0 * t, omega=0.2 + 0.1 * t,
                          dt=0.02, mode=0, precision=0))
     b = P.Batch(cfgs)
+    if plan:
+        b.set_plan(plan)
     for k, c in enumerate(cfgs):
         b.init_state(k, 0, W.phase_field(50 + k, c["ny"], c["nx"]), 1.0)
     steps = b.run(max_steps=20000, check_every=50, tol=1e-9)
+    assert b.info()["plan"] in (1, 2)
     assert all(s > 0 for s in steps), steps
     assert len(set(steps)) > 1, steps  # they do not all stop together
     for k, c in enumerate(cfgs):
@@ -80,12 +87,14 @@ def test_batch_run_drops_converged_instances(P):
     b.close()
 
 
-def test_batch_workload_sampled(P):
+@pytest.mark.parametrize("plan", [1, 2])
+def test_batch_workload_sampled(P, plan):
     """The 64-instance workload at full size: a few steps, sampled instances
     against the oracle."""
-    print("[gpu-batch] 64-instance workload", flush=True)
+    print(f"[gpu-batch] 64-instance workload plan={plan}", flush=True)
     cfgs = W.batch_instances()
     b = P.Batch(cfgs)
+    b.set_plan(plan)
     for k, c in enumerate(cfgs):
         b.init_state(k, 1, W.phase_field(c["seed"], c["ny"], c["nx"]), 1.0)
     b.step(10)
