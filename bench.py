@@ -165,7 +165,8 @@ def kernel_roofline(s, cfg, step_ms, nlaunch=200, traffic_key=None):
 
 
 def batch_run(P, torch, steps=200):
-    """The 64-instance batch: updates/s of the fused batched step."""
+    """The 64-instance batch: updates/s of the batched step (the plan the
+    batch autotuner picks: batched sweeps or the fused step)."""
     cfgs = W.batch_instances()
     b = P.Batch(cfgs)
     for k, c in enumerate(cfgs):
@@ -177,10 +178,12 @@ def batch_run(P, torch, steps=200):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     pts = sum(c["nx"] * c["ny"] for c in cfgs)
+    info = b.info()
     b.close()
     ups = pts * steps / dt
     return {"instances": len(cfgs), "points": pts, "updates_per_s": round(ups, 1),
             "ms_per_step": round(dt / steps * 1e3, 5),
+            "plan": {1: "batched sweeps", 2: "fused"}.get(info["plan"], info["plan"]), "window": info["window"],
             "algorithmic_GBps": round(64 * ups / 1e9, 1), "frac_of_8TBps": round(64 * ups / 8e12, 4)}
 
 
