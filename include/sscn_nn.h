@@ -90,11 +90,22 @@ int sscn_nn_loss(const float *pred, int ld, const float *psi, int B, int K, int 
 int sscn_nn_psi_to_f32(const void *psi, int precision, int64_t S, float scale, float *out, void *stream);
 int sscn_nn_f32_to_psi(const float *pred, int ld, int64_t S, double scale, void *psi, int precision, void *stream);
 
+/* Squared 2-norm of n fp32 values a (device), summed in fp64 in a fixed
+ * order (reproducible run to run).  work: device buffer of at least 257
+ * doubles owned by the caller; on completion work[0] holds the sum and
+ * work[1..256] are overwritten (partials).  Stream-ordered, no host sync. */
+int sscn_nn_sumsq(const float *a, int64_t n, double *work, void *stream);
+
 /* One Adam step (t >= 1) on fp32 master weights w with state m, v and
  * gradient g; if wbf16 is not NULL the updated weights are also written
- * there as bf16. */
+ * there as bf16.  Global-norm clipping: if gsq is not NULL it points to the
+ * squared norm of the whole gradient (device, e.g. work[0] of
+ * sscn_nn_sumsq over every parameter's gradient) and g is scaled by
+ * min(1, max_norm / sqrt(*gsq)) before the update; max_norm must then be
+ * > 0.  gsq NULL: no clipping, max_norm ignored.  Returns -1 on bad
+ * arguments. */
 int sscn_nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
-                 int t, void *wbf16, void *stream);
+                 int t, const double *gsq, float max_norm, void *wbf16, void *stream);
 
 /* b = bf16(a), round to nearest even. */
 int sscn_nn_f32_to_bf16(const float *a, void *b, int64_t n, void *stream);

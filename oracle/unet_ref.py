@@ -215,7 +215,16 @@ def unet_backward(dout, A, chans, bott, bf16_on=True):
     return G
 
 
-def adam(w, m, v, g, lr, b1, b2, eps, t):
+def clip_scale(grads, max_norm):
+    """Global-norm clipping factor: min(1, max_norm / ||g||) with ||g|| the
+    2-norm of every gradient array in `grads` taken together."""
+    norm = np.sqrt(sum(float(np.sum(np.asarray(g, dtype=np.float64) ** 2)) for g in grads))
+    return 1.0 if norm <= max_norm else max_norm / norm
+
+
+def adam(w, m, v, g, lr, b1, b2, eps, t, gscale=1.0):
+    """One Adam step (bias-corrected moments) on the gradient gscale * g."""
+    g = gscale * np.asarray(g, dtype=np.float64)
     m = b1 * m + (1 - b1) * g
     v = b2 * v + (1 - b2) * g * g
     w = w - lr * (m / (1 - b1 ** t)) / (np.sqrt(v / (1 - b2 ** t)) + eps)

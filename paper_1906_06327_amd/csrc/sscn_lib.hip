@@ -56,7 +56,7 @@ constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
 constexpr size_t kXLdsCap = 64 * 1024;
 
 // Supported window sizes (template instantiations).
-const int kWindows[] = {4, 6, 8, 10, 12, 16, 20, 24, 32};
+const int kWindows[] = {4, 6, 8, 10, 12, 13, 14, 16, 20, 24, 32};
 
 }  // namespace
 
@@ -362,6 +362,8 @@ template <class R> using V = typename Vec<R>::T;
     case 8: CALL(8); break;                                                                                  \
     case 10: CALL(10); break;                                                                                \
     case 12: CALL(12); break;                                                                                \
+    case 13: CALL(13); break;                                                                                \
+    case 14: CALL(14); break;                                                                                \
     case 16: CALL(16); break;                                                                                \
     case 20: CALL(20); break;                                                                                \
     case 24: CALL(24); break;                                                                                \
@@ -453,6 +455,8 @@ void launch_norm(sscn_handle *h, hipStream_t st)
     case 8: CALL(8); break;                                                                                  \
     case 10: CALL(10); break;                                                                                \
     case 12: CALL(12); break;                                                                                \
+    case 13: CALL(13); break;                                                                                \
+    case 14: CALL(14); break;                                                                                \
     case 16: CALL(16); break;                                                                                \
     default: CALL(20); break;                                                                                \
     }

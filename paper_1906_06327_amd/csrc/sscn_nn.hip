@@ -35,28 +35,46 @@ extern "C" {
 
 const char *sscn_nn_last_error(void) { return g_nn_err.c_str(); }
 
+}  // extern "C"
+
+namespace {
+
+template <int ACT, bool OUTF32>
+void launch_conv(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
+                 void *y, int ldy, int yoff, hipStream_t st)
+{
+    const int P = N * H * W;
+    if (Cout % 64 == 0)
+        hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 64>), dim3((P + 63) / 64, Cout / 64), dim3(256), 0, st, x, N, H, W,
+                           Cin, w, bias, Cout, y, ldy, yoff);
+    else if (Cout % 32 == 0)
+        hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 32>), dim3((P + 63) / 64, Cout / 32), dim3(256), 0, st, x, N, H, W,
+                           Cin, w, bias, Cout, y, ldy, yoff);
+    else
+        hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 16>), dim3((P + 63) / 64, Cout / 16), dim3(256), 0, st, x, N, H, W,
+                           Cin, w, bias, Cout, y, ldy, yoff);
+}
+
+}  // namespace
+
+extern "C" {
+
 int sscn_nn_conv3x3(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
                     int act, int out_f32, void *y, int ldy, int yoff, void *stream)
 {
     if (!x || !w || !y || N < 1 || H < 1 || W < 1 || Cin < 16 || Cin % 16 || Cout < 16 || Cout % 16 ||
         ldy < yoff + Cout || yoff < 0 || (act != ACT_NONE && act != ACT_LEAKY))
         return nn_fail(-1, "bad conv3x3 arguments");
-    const int P = N * H * W;
-    dim3 grid((P + 63) / 64, Cout / 16);
     hipStream_t st = (hipStream_t)stream;
     const uint16_t *xs = (const uint16_t *)x, *ws = (const uint16_t *)w;
     if (act == ACT_LEAKY && !out_f32)
-        hipLaunchKernelGGL((k_conv3x3<ACT_LEAKY, false>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
-                           y, ldy, yoff);
+        launch_conv<ACT_LEAKY, false>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
     else if (act == ACT_LEAKY)
-        hipLaunchKernelGGL((k_conv3x3<ACT_LEAKY, true>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
-                           y, ldy, yoff);
+        launch_conv<ACT_LEAKY, true>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
     else if (!out_f32)
-        hipLaunchKernelGGL((k_conv3x3<ACT_NONE, false>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
-                           y, ldy, yoff);
+        launch_conv<ACT_NONE, false>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
     else
-        hipLaunchKernelGGL((k_conv3x3<ACT_NONE, true>), grid, dim3(256), 0, st, xs, N, H, W, Cin, ws, bias, Cout,
-                           y, ldy, yoff);
+        launch_conv<ACT_NONE, true>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
     return launched("conv3x3");
 }
 
@@ -68,10 +86,8 @@ int sscn_nn_conv3x3_dgrad(const void *dy, int N, int H, int W, int Cout, const v
     hipStream_t st = (hipStream_t)stream;
     hipLaunchKernelGGL(k_wflip, dim3(blocks((int64_t)Cout * 9 * Cin)), dim3(256), 0, st, (const uint16_t *)w, Cout,
                        Cin, (uint16_t *)wt_scratch);
-    const int P = N * H * W;
-    hipLaunchKernelGGL((k_conv3x3<ACT_NONE, false>), dim3((P + 63) / 64, Cin / 16), dim3(256), 0, st,
-                       (const uint16_t *)dy, N, H, W, Cout, (const uint16_t *)wt_scratch, nullptr, Cin, dx, lddx,
-                       dxoff);
+    launch_conv<ACT_NONE, false>((const uint16_t *)dy, N, H, W, Cout, (const uint16_t *)wt_scratch, nullptr, Cin, dx,
+                                 lddx, dxoff, st);
     return launched("conv3x3_dgrad");
 }
 
@@ -99,7 +115,8 @@ int sscn_nn_conv3x3_wgrad(const void *x, int N, int H, int W, int Cin, const voi
     int chunk = (P + nsplit - 1) / nsplit;
     chunk = (chunk + 15) / 16 * 16;
     hipStream_t st = (hipStream_t)stream;
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsplit, Cout / 16, 9 * Cin / 16), dim3(64), 0, st,
+    const int cw = Cin % 32 == 0 ? 32 : 16;
+    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsplit, (Cout + 63) / 64, 9 * Cin / cw), dim3(256), 0, st,
                        (const uint16_t *)x, N, H, W, Cin, (const uint16_t *)dy, Cout, chunk, scratch);
     const int nw = Cout * 9 * Cin;
     hipLaunchKernelGGL(k_sum_splits, dim3(blocks(nw)), dim3(256), 0, st, scratch, nsplit, nw, dw);
@@ -207,14 +224,25 @@ int sscn_nn_f32_to_psi(const float *pred, int ld, int64_t S, double scale, void 
     return launched("f32_to_psi");
 }
 
-int sscn_nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
-                 int t, void *wbf16, void *stream)
+int sscn_nn_sumsq(const float *a, int64_t n, double *work, void *stream)
 {
-    if (!w || !m || !v || !g || n < 0 || t < 1)
+    if (!a || !work || n < 0)
+        return nn_fail(-1, "bad sumsq arguments");
+    const int np = (int)std::min<int64_t>(256, std::max<int64_t>(1, (n + 4095) / 4096));
+    hipLaunchKernelGGL(k_sumsq_part, dim3(np), dim3(256), 0, (hipStream_t)stream, a, n, work + 1);
+    hipLaunchKernelGGL(k_sumsq_fin, dim3(1), dim3(256), 0, (hipStream_t)stream, (const double *)(work + 1), np,
+                       work);
+    return launched("sumsq");
+}
+
+int sscn_nn_adam(float *w, float *m, float *v, const float *g, int64_t n, float lr, float b1, float b2, float eps,
+                 int t, const double *gsq, float max_norm, void *wbf16, void *stream)
+{
+    if (!w || !m || !v || !g || n < 0 || t < 1 || (gsq && !(max_norm > 0.f)))
         return nn_fail(-1, "bad adam arguments");
     const float c1 = 1.f - powf(b1, (float)t), c2 = 1.f - powf(b2, (float)t);
     hipLaunchKernelGGL(k_adam, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, w, m, v, g, (int)n, lr, b1, b2,
-                       eps, c1, c2, (uint16_t *)wbf16);
+                       eps, c1, c2, gsq, max_norm, (uint16_t *)wbf16);
     return launched("adam");
 }
 

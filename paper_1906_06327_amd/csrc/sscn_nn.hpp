@@ -47,55 +47,120 @@ __device__ __forceinline__ v4s load4(const uint16_t *p)
     return r;
 }
 
+// Staged tiles of the convolution kernels: rows of 32 bf16 values padded to
+// 40 (80 bytes), so that the 8-byte fragment reads of a wave's lanes spread
+// over the LDS banks.
+constexpr int kConvBK = 32;
+constexpr int kConvLd = kConvBK + 8;
+
+__device__ __forceinline__ v4s lds4(const uint16_t *p)
+{
+    const uint2 u = *reinterpret_cast<const uint2 *>(p);
+    v4s r;
+    r[0] = (short)(u.x & 0xffffu);
+    r[1] = (short)(u.x >> 16);
+    r[2] = (short)(u.y & 0xffffu);
+    r[3] = (short)(u.y >> 16);
+    return r;
+}
+
 // 3x3 convolution, padding 1, as an implicit GEMM: M = N*H*W pixels,
-// N = Cout, K = 9*Cin.  A wave computes 16 pixels x 16 output channels;
-// a block of 4 waves 64 pixels x 16 channels.  Output channel co of pixel p
+// N = Cout, K = 9*Cin.  A block computes 64 pixels x BN output channels
+// (BN | Cout).  The K loop takes chunks of KC = 32 (16 if Cin is an odd
+// multiple of 16) input channels of one tap: the block stages the chunk's
+// 64 x KC input values and BN x KC weights in LDS with one 16-byte load per
+// thread each (double-buffered, the next chunk's loads in flight during the
+// current chunk's matrix-core products); wave w multiplies pixels 16w..16w+15
+// with every 16-channel fragment of the block.  Output channel co of pixel p
 // goes to y[p*ldy + yoff + co] with bias and activation applied, bf16 or
-// fp32.  Grid: (ceil(P/64), Cout/16).
-template <int ACT, bool OUTF32>
+// fp32.  Grid: (ceil(P/64), Cout/BN).
+template <int ACT, bool OUTF32, int BN>
 __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x, int N, int H, int W, int Cin,
                                                  const uint16_t *__restrict__ w, const float *__restrict__ bias,
                                                  int Cout, void *__restrict__ y, int ldy, int yoff)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    constexpr int NF = BN / 16;
+    __shared__ __align__(16) uint16_t sA[2][64 * kConvLd];
+    __shared__ __align__(16) uint16_t sB[2][BN * kConvLd];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
     const int P = N * H * W;
-    const int p0 = (blockIdx.x * 4 + wave) * 16;
-    const int co0 = blockIdx.y * 16;
-    const int p = p0 + m;
-    int n = 0, yy = 0, xx = 0;
-    if (p < P) {
-        n = p / (H * W);
-        const int r = p - n * H * W;
-        yy = r / W;
-        xx = r - yy * W;
+    const int p0 = blockIdx.x * 64;
+    const int co0 = blockIdx.y * BN;
+    const int kc = (Cin % 32 == 0) ? 32 : 16;
+    const int ncc = Cin / kc;
+    const int nk = 9 * ncc;
+    // staging roles: thread t stages 8 channels (part t % 4) of pixel t / 4
+    // and 8 k-values of weight row t / 4
+    const int sp = tid >> 2, part = tid & 3;
+    const bool pact = part * 8 < kc;
+    const int pa = p0 + sp;
+    int an = 0, ay = 0, ax = 0;
+    if (pa < P) {
+        an = pa / (H * W);
+        const int r = pa - an * H * W;
+        ay = r / W;
+        ax = r - ay * W;
     }
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    const v4s zero = {0, 0, 0, 0};
-    const uint16_t *wrow = w + (size_t)(co0 + m) * 9 * Cin;
-    for (int tap = 0; tap < 9; ++tap) {
-        const int sy = yy + tap / 3 - 1, sx = xx + tap % 3 - 1;
-        const bool ok = p < P && sy >= 0 && sy < H && sx >= 0 && sx < W;
-        const uint16_t *xr = x + ((size_t)(n * H + sy) * W + sx) * Cin;
-        for (int c0 = 0; c0 < Cin; c0 += 16) {
-            const v4s a = ok ? load4(xr + c0 + 4 * g) : zero;
-            const v4s b = load4(wrow + tap * Cin + c0 + 4 * g);
-            acc = mfma16(a, b, acc);
+    auto load_chunk = [&](int kk, uint4 &ra, uint4 &rb) {
+        const int tap = kk / ncc, c0 = (kk - tap * ncc) * kc;
+        ra = make_uint4(0u, 0u, 0u, 0u);
+        rb = make_uint4(0u, 0u, 0u, 0u);
+        if (pact && pa < P) {
+            const int sy = ay + tap / 3 - 1, sx = ax + tap % 3 - 1;
+            if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+                ra = *reinterpret_cast<const uint4 *>(x + ((size_t)(an * H + sy) * W + sx) * Cin + c0 + part * 8);
         }
-    }
-    const int co = co0 + m;
-    const float bv = bias ? bias[co] : 0.f;
+        if (pact && sp < BN)
+            rb = *reinterpret_cast<const uint4 *>(w + ((size_t)(co0 + sp) * 9 + tap) * Cin + c0 + part * 8);
+    };
+    auto store_chunk = [&](int buf, const uint4 &ra, const uint4 &rb) {
+        if (pact) {
+            *reinterpret_cast<uint4 *>(&sA[buf][sp * kConvLd + part * 8]) = ra;
+            if (sp < BN)
+                *reinterpret_cast<uint4 *>(&sB[buf][sp * kConvLd + part * 8]) = rb;
+        }
+    };
+    v4f acc[NF];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int pp = p0 + 4 * g + i;
-        if (pp < P) {
-            float v = acc[i] + bv;
-            if (ACT == ACT_LEAKY)
-                v = v > 0.f ? v : kLeak * v;
-            if (OUTF32)
-                reinterpret_cast<float *>(y)[(size_t)pp * ldy + yoff + co] = v;
-            else
-                reinterpret_cast<uint16_t *>(y)[(size_t)pp * ldy + yoff + co] = f2bf(v);
+    for (int f = 0; f < NF; ++f)
+        acc[f] = v4f{0.f, 0.f, 0.f, 0.f};
+    uint4 ra, rb;
+    load_chunk(0, ra, rb);
+    store_chunk(0, ra, rb);
+    __syncthreads();
+    for (int kk = 0; kk < nk; ++kk) {
+        const int cur = kk & 1;
+        if (kk + 1 < nk)
+            load_chunk(kk + 1, ra, rb);
+        for (int k16 = 0; k16 < kc / 16; ++k16) {
+            const v4s a = lds4(&sA[cur][(wave * 16 + m) * kConvLd + k16 * 16 + 4 * g]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const v4s b = lds4(&sB[cur][(f * 16 + m) * kConvLd + k16 * 16 + 4 * g]);
+                acc[f] = mfma16(a, b, acc[f]);
+            }
+        }
+        if (kk + 1 < nk)
+            store_chunk(cur ^ 1, ra, rb);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const int co = co0 + f * 16 + m;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int pp = p0 + wave * 16 + 4 * g + i;
+            if (pp < P) {
+                float v = acc[f][i] + bv;
+                if (ACT == ACT_LEAKY)
+                    v = v > 0.f ? v : kLeak * v;
+                if (OUTF32)
+                    reinterpret_cast<float *>(y)[(size_t)pp * ldy + yoff + co] = v;
+                else
+                    reinterpret_cast<uint16_t *>(y)[(size_t)pp * ldy + yoff + co] = f2bf(v);
+            }
         }
     }
 }
@@ -113,46 +178,88 @@ __global__ __launch_bounds__(256) void k_wflip(const uint16_t *__restrict__ w, i
 }
 
 // Weight gradient, split over pixel ranges: part[s][co][tap][ci] =
-// sum over pixels p of split s of dy[p][co] * x[p shifted by tap][ci].
-// GEMM M = Cout, N = 9*Cin, K = pixels; a wave computes 16 co x 16 (tap, ci)
-// over its pixel range.  Grid: (nsplit, Cout/16, 9*Cin/16), 64 threads.
-__global__ __launch_bounds__(64) void k_conv3x3_wgrad(const uint16_t *__restrict__ x, int N, int H, int W,
+// sum over the pixels p of split s of dy[p][co] * x[p shifted by tap][ci].
+// GEMM M = Cout, N = 9*Cin, K = pixels.  A block computes 64 output
+// channels (co0..co0+63, those below Cout) x CW columns (one tap, CW = 32 or
+// 16 input channels) over its split; pixel chunks of 32 are staged in LDS
+// transposed (channel rows, pixel columns) so that every fragment read is
+// 8 contiguous bytes; wave w owns channels co0 + 16w .. +15.  Grid: (nsplit,
+// ceil(Cout/64), 9*Cin/CW), 256 threads.
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad(const uint16_t *__restrict__ x, int N, int H, int W,
                                                       int Cin, const uint16_t *__restrict__ dy, int Cout,
                                                       int chunk, float *__restrict__ part)
 {
-    const int lane = threadIdx.x;
+    __shared__ __align__(16) uint16_t sA[64 * kConvLd];  // dy^T: 64 channels x 32 pixels
+    __shared__ __align__(16) uint16_t sB[32 * kConvLd];  // x^T: CW channels x 32 pixels
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
-    const int s = blockIdx.x, co0 = blockIdx.y * 16, col0 = blockIdx.z * 16;
+    const int s = blockIdx.x, co0 = blockIdx.y * 64;
+    const int CW = (Cin % 32 == 0) ? 32 : 16;
+    const int ncw = Cin / CW;
+    const int tap = blockIdx.z / ncw, ci0 = (blockIdx.z - tap * ncw) * CW;
+    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
     const int P = N * H * W;
     const int pb = s * chunk, pe = min(P, pb + chunk);
-    const int col = col0 + m;  // (tap, ci) of this lane's B column
-    const int tap = col / Cin, ci = col - tap * Cin;
-    const int dyo = tap / 3 - 1, dxo = tap % 3 - 1;
-    v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = pb; k0 < pe; k0 += 16) {
-        v4s a, b;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int p = k0 + 4 * g + i;
-            short av = 0, bv = 0;
+    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+    // staging roles: dy: thread t takes 8 channels (t % 8) of pixel t / 8;
+    // x: thread t < 4 CW takes 8 channels (t % (CW/8)) of pixel t / (CW/8)
+    const int ap = tid >> 3, apart = tid & 7;
+    const int bq = CW / 8;
+    const int bp = tid / bq, bpart = tid - bp * bq;
+    for (int k0 = pb; k0 < pe; k0 += 32) {
+        uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb = make_uint4(0u, 0u, 0u, 0u);
+        {
+            const int p = k0 + ap;
+            if (p < pe && co0 + apart * 8 < Cout)
+                ra = *reinterpret_cast<const uint4 *>(dy + (size_t)p * Cout + co0 + apart * 8);
+        }
+        if (bp < 32) {
+            const int p = k0 + bp;
             if (p < pe) {
-                av = (short)dy[(size_t)p * Cout + co0 + m];
                 const int n = p / (H * W), r = p - n * H * W;
-                const int yy = r / W, xx = r - (r / W) * W;
+                const int yy = r / W, xx = r - yy * W;
                 const int sy = yy + dyo, sx = xx + dxo;
                 if (sy >= 0 && sy < H && sx >= 0 && sx < W)
-                    bv = (short)x[((size_t)(n * H + sy) * W + sx) * Cin + ci];
+                    rb = *reinterpret_cast<const uint4 *>(x + ((size_t)(n * H + sy) * W + sx) * Cin + ci0 + bpart * 8);
             }
-            a[i] = av;
-            b[i] = bv;
         }
-        acc = mfma16(a, b, acc);
+        __syncthreads();  // the previous chunk's fragment reads are done
+        {
+            const uint16_t *va = reinterpret_cast<const uint16_t *>(&ra);
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                sA[(apart * 8 + j) * kConvLd + ap] = va[j];
+            if (bp < 32) {
+                const uint16_t *vb = reinterpret_cast<const uint16_t *>(&rb);
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    sB[(bpart * 8 + j) * kConvLd + bp] = vb[j];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k16 = 0; k16 < 2; ++k16) {
+            const v4s a = lds4(&sA[(wave * 16 + m) * kConvLd + k16 * 16 + 4 * g]);
+#pragma unroll
+            for (int f = 0; f < 2; ++f)
+                if (f * 16 < CW) {
+                    const v4s b = lds4(&sB[(f * 16 + m) * kConvLd + k16 * 16 + 4 * g]);
+                    acc[f] = mfma16(a, b, acc[f]);
+                }
+        }
     }
-    // D[row = co0 + 4g + i][col0 + m]
+    // D[row = co0 + 16 wave + 4g + i][col = tap*Cin + ci0 + 16f + m]
     const int ncols = 9 * Cin;
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
-        part[((size_t)s * Cout + co0 + 4 * g + i) * ncols + col0 + m] = acc[i];
+    for (int f = 0; f < 2; ++f)
+        if (f * 16 < CW) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = co0 + wave * 16 + 4 * g + i;
+                if (co < Cout)
+                    part[((size_t)s * Cout + co) * ncols + tap * Cin + ci0 + f * 16 + m] = acc[f][i];
+            }
+        }
 }
 
 // out[e] = sum over s of part[s][e] in a fixed order (fp32).
@@ -167,17 +274,33 @@ __global__ __launch_bounds__(256) void k_sum_splits(const float *__restrict__ pa
     }
 }
 
-// Bias gradient partials: part[s][c] = sum over the pixels of split s of dy.
+// Bias gradient partials: part[s][c] = sum over the pixels of split s of
+// dy[p][c].  Thread t sums channel t % C over pixels t / C, t / C + 256 / C,
+// ... (C <= 256 divides 256 or not: threads beyond (256 / C) C idle); the
+// per-thread sums are added in fixed order through LDS.
 __global__ __launch_bounds__(256) void k_bias_grad(const uint16_t *__restrict__ dy, int P, int C, int chunk,
                                                    float *__restrict__ part)
 {
+    __shared__ float red[256];
     const int s = blockIdx.x;
     const int pb = s * chunk, pe = min(P, pb + chunk);
-    for (int c = threadIdx.x; c < C; c += 256) {
+    for (int c0 = 0; c0 < C; c0 += 256) {
+        const int cw = min(256, C - c0);
+        const int rows = 256 / cw;
+        const int t = threadIdx.x, c = t % cw, r = t / cw;
         float acc = 0.f;
-        for (int p = pb; p < pe; ++p)
-            acc += bf2f(dy[(size_t)p * C + c]);
-        part[(size_t)s * C + c] = acc;
+        if (r < rows)
+            for (int p = pb + r; p < pe; p += rows)
+                acc += bf2f(dy[(size_t)p * C + c0 + c]);
+        red[t] = acc;
+        __syncthreads();
+        if (t < cw) {
+            float v = 0.f;
+            for (int k = 0; k < rows; ++k)
+                v += red[k * cw + t];
+            part[(size_t)s * C + c0 + t] = v;
+        }
+        __syncthreads();
     }
 }
 
@@ -354,13 +477,60 @@ __global__ __launch_bounds__(256) void k_f32_to_psi(const float *__restrict__ pr
         psi[e] = (T)((double)pred[(e >> 1) * ld + (e & 1)] * scale);
 }
 
-// Adam on fp32 master weights, then the bf16 copy the kernels read.
+// Sum of squares, first pass: block b sums a[e]^2 in fp64 over e = b*256 +
+// t + k*gridDim*256 (t = thread, fixed order), then over its threads in a
+// fixed tree; part[b] = the block's sum.
+__global__ __launch_bounds__(256) void k_sumsq_part(const float *__restrict__ a, int64_t n, double *__restrict__ part)
+{
+    __shared__ double red[256];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const double x = a[e];
+        acc += x * x;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = red[0];
+}
+
+// Second pass, one block: out[0] = sum of part[0 .. np), np <= 256, in a
+// fixed tree.
+__global__ __launch_bounds__(256) void k_sumsq_fin(const double *__restrict__ part, int np, double *__restrict__ out)
+{
+    __shared__ double red[256];
+    red[threadIdx.x] = threadIdx.x < np ? part[threadIdx.x] : 0.0;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (threadIdx.x < h)
+            red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        out[0] = red[0];
+}
+
+// Adam on fp32 master weights, then the bf16 copy the kernels read.  With
+// gsq (the squared global gradient norm, on the device) the gradient is
+// first scaled by min(1, max_norm / sqrt(*gsq)).
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ wm, float *__restrict__ m, float *__restrict__ v,
                                               const float *__restrict__ g, int n, float lr, float b1, float b2,
-                                              float eps, float c1, float c2, uint16_t *__restrict__ wbf)
+                                              float eps, float c1, float c2, const double *__restrict__ gsq,
+                                              float max_norm, uint16_t *__restrict__ wbf)
 {
+    float gs = 1.f;
+    if (gsq) {
+        const double q = *gsq, mn = max_norm;
+        if (q > mn * mn)
+            gs = (float)(mn / sqrt(q));
+    }
     for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
-        const float ge = g[e];
+        const float ge = gs * g[e];
         const float me = b1 * m[e] + (1.f - b1) * ge;
         const float ve = b2 * v[e] + (1.f - b2) * ge * ge;
         m[e] = me;

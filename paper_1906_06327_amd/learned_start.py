@@ -173,16 +173,21 @@ def make_targets(plist, states, dt=2e-3):
     return T
 
 
-def train(net, X, T, epochs, lr=1e-3, seed=0, log=print, log_every=50):
+def train(net, X, T, epochs, lr=1e-3, seed=0, log=print, log_every=50, warmup=0, clip=0.0):
     """Adam over shuffled minibatches of net.N samples with a cosine
-    learning-rate decay.  X: (M, n, n, 16) bf16 device tensor; T: (M, 4, n,
-    n, 2) fp32 device tensor.  Returns the per-epoch mean loss."""
+    learning-rate decay after a linear warm-up over the first `warmup`
+    iterations.  clip > 0 bounds the global gradient norm of every step by
+    clip times a running average of the (clipped) norms of the earlier
+    steps, so that a single outlying batch cannot throw the weights far.
+    X: (M, n, n, 16) bf16 device tensor; T: (M, 4, n, n, 2) fp32 device
+    tensor.  Returns the per-epoch mean loss."""
     import torch
     M, B = X.shape[0], net.N
     per = M // B
     total = max(1, epochs * per)
     rng = np.random.default_rng(seed)
     hist, it = [], 0
+    gavg, nclip = None, 0
     for ep in range(epochs):
         perm = rng.permutation(M)
         acc = 0.0
@@ -191,11 +196,24 @@ def train(net, X, T, epochs, lr=1e-3, seed=0, log=print, log_every=50):
             net.forward(X.index_select(0, idx))
             lv = float(net.loss_and_grad(T.index_select(0, idx)).mean())
             net.backward(net.gacts["out"])
-            net.adam_step(lr=lr * 0.5 * (1.0 + math.cos(math.pi * it / total)))
+            ramp = min(1.0, (it + 1) / warmup) if warmup > 0 else 1.0
+            step_lr = lr * ramp * 0.5 * (1.0 + math.cos(math.pi * it / total))
+            if clip > 0:
+                gsq = net.grad_sqnorm()
+                bound = clip * gavg if gavg is not None else None
+                net.adam_step(lr=step_lr, max_norm=bound, gsq=gsq)
+                gn = math.sqrt(float(gsq[0]))
+                if bound is not None and gn > bound:
+                    nclip += 1
+                    gn = bound
+                gavg = gn if gavg is None else 0.98 * gavg + 0.02 * gn
+            else:
+                net.adam_step(lr=step_lr)
             acc += lv
             it += 1
             if log_every and it % log_every == 0:
-                log(f"[train] iter {it}/{total} loss {lv:.4f}")
+                extra = f" grad norm avg {gavg:.4g}, {nclip} clipped" if clip > 0 else ""
+                log(f"[train] iter {it}/{total} loss {lv:.4f}{extra}")
         hist.append(acc / max(1, per))
         log(f"[train] epoch {ep + 1}/{epochs} mean loss {hist[-1]:.4f}")
     return hist
@@ -329,6 +347,9 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--warmup", type=int, default=1000, help="iterations of linear learning-rate warm-up")
+    ap.add_argument("--clip", type=float, default=2.0,
+                    help="bound each step's gradient norm by this times the running average norm (0: off)")
     ap.add_argument("--dt", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=2019)
     ap.add_argument("--phase-seed", type=int, default=13,
@@ -361,7 +382,7 @@ def main(argv=None):
         del states
         net = nn.UNet(a.batch, N_GRID, N_GRID, chans=CHANS, bott=BOTT, seed=a.seed)
         t0 = time.perf_counter()
-        hist = train(net, X, T, a.epochs, lr=a.lr, seed=a.seed, log=log)
+        hist = train(net, X, T, a.epochs, lr=a.lr, seed=a.seed, log=log, warmup=a.warmup, clip=a.clip)
         torch.cuda.synchronize()
         res["train_s"] = round(time.perf_counter() - t0, 1)
         res["loss_history"] = [round(v, 5) for v in hist]

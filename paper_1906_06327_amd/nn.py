@@ -42,7 +42,8 @@ def _nn():
         L.sscn_nn_loss.argtypes = [vp, ci, vp, ci, ci, ci, vp, vp, vp]
         L.sscn_nn_psi_to_f32.argtypes = [vp, ci, i64, cf, vp, vp]
         L.sscn_nn_f32_to_psi.argtypes = [vp, ci, i64, ctypes.c_double, vp, ci, vp]
-        L.sscn_nn_adam.argtypes = [vp, vp, vp, vp, i64, cf, cf, cf, cf, ci, vp, vp]
+        L.sscn_nn_sumsq.argtypes = [vp, i64, vp, vp]
+        L.sscn_nn_adam.argtypes = [vp, vp, vp, vp, i64, cf, cf, cf, cf, ci, vp, cf, vp, vp]
         L.sscn_nn_f32_to_bf16.argtypes = [vp, vp, i64, vp]
         L.sscn_nn_last_error.restype = ctypes.c_char_p
         L._nn_ready = True
@@ -125,9 +126,18 @@ def _complex128():
     return torch.complex128
 
 
-def adam(w, m, v, g, lr, b1, b2, eps, t, wbf=None, stream=None):
+def sumsq(a, work, stream=None):
+    """work[0] = sum of a**2 (fp64, fixed order); work: >= 257 float64 on the device."""
+    if work.numel() < 257:
+        raise ValueError("sumsq needs a work buffer of at least 257 doubles")
+    _ck(_nn().sscn_nn_sumsq(_p(a), a.numel(), _p(work), stream))
+
+
+def adam(w, m, v, g, lr, b1, b2, eps, t, wbf=None, gsq=None, max_norm=0.0, stream=None):
+    """One Adam step; gsq (a one-element float64 device tensor holding the
+    squared global gradient norm) turns on clipping to max_norm."""
     _ck(_nn().sscn_nn_adam(_p(w), _p(m), _p(v), _p(g), w.numel(), float(lr), float(b1), float(b2),
-                           float(eps), int(t), _p(wbf), stream))
+                           float(eps), int(t), _p(gsq), float(max_norm), _p(wbf), stream))
 
 
 def f32_to_bf16(a, b, stream=None):
@@ -178,14 +188,22 @@ class UNet:
         p0 = params if params is not None else init_params(self.specs, seed)
         f32, bf = torch.float32, torch.int16
         self.w32, self.wbf, self.b, self.gw, self.gb, self.m, self.v = {}, {}, {}, {}, {}, {}, {}
+        # every parameter gradient is a view into one flat buffer, so that
+        # the global gradient norm is one reduction
+        ngrad = sum(int(np.prod(p0[n][0].shape)) + p0[n][1].size for n, _, _, _ in self.specs)
+        self.gflat = torch.zeros(ngrad, dtype=f32, device=self.dev)
+        self.gwork = torch.zeros(257, dtype=torch.float64, device=self.dev)
+        off = 0
         for name, cin, cout, act in self.specs:
             w, b = p0[name]
             self.w32[name] = torch.tensor(w, dtype=f32, device=self.dev)
             self.b[name] = torch.tensor(b, dtype=f32, device=self.dev)
             self.wbf[name] = torch.empty(w.shape, dtype=bf, device=self.dev)
             f32_to_bf16(self.w32[name], self.wbf[name])
-            self.gw[name] = torch.zeros_like(self.w32[name])
-            self.gb[name] = torch.zeros_like(self.b[name])
+            self.gw[name] = self.gflat[off:off + w.size].view(w.shape)
+            off += w.size
+            self.gb[name] = self.gflat[off:off + b.size]
+            off += b.size
             for d in (self.m, self.v):
                 d[name] = (torch.zeros_like(self.w32[name]), torch.zeros_like(self.b[name]))
         self.t = 0
@@ -341,12 +359,26 @@ class UNet:
         st = self.stats[:4 * self.N * K].view(self.N, K, 4).cpu().numpy()
         return (st[..., 2] + st[..., 3] - 2.0 * np.hypot(st[..., 0], st[..., 1])).min(axis=1)
 
-    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    def grad_sqnorm(self):
+        """Enqueue the squared global norm of the parameter gradients into
+        gwork[0] (device); returns that one-element view."""
+        sumsq(self.gflat, self.gwork)
+        return self.gwork[:1]
+
+    def adam_step(self, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, max_norm=None, gsq=None):
+        """One Adam step on every parameter; with max_norm the gradients are
+        first scaled so that their global norm is at most max_norm (gsq: the
+        grad_sqnorm() of this step if already enqueued)."""
         self.t += 1
+        if max_norm is None:
+            gsq = None
+        elif gsq is None:
+            gsq = self.grad_sqnorm()
+        mn = float(max_norm) if max_norm is not None else 0.0
         for name, _, _, _ in self.specs:
             m, v = self.m[name], self.v[name]
-            adam(self.w32[name], m[0], v[0], self.gw[name], lr, b1, b2, eps, self.t, self.wbf[name])
-            adam(self.b[name], m[1], v[1], self.gb[name], lr, b1, b2, eps, self.t, None)
+            adam(self.w32[name], m[0], v[0], self.gw[name], lr, b1, b2, eps, self.t, self.wbf[name], gsq, mn)
+            adam(self.b[name], m[1], v[1], self.gb[name], lr, b1, b2, eps, self.t, None, gsq, mn)
 
     def params_numpy(self):
         return {n: (self.w32[n].cpu().numpy(), self.b[n].cpu().numpy()) for n, _, _, _ in self.specs}

@@ -186,6 +186,50 @@ def test_loss_and_adam(nn, K):
     assert np.array_equal(from_bf(wbf), U.bf16(wd.cpu().numpy()))
 
 
+@pytest.mark.parametrize("n", [1, 255, 4097, 3 * 4096 * 256 + 17])
+def test_sumsq(nn, n):
+    """Fixed-order fp64 sum of squares: one block, a ragged tail, and more
+    elements than 256 blocks of 4096 (every block strides)."""
+    a = np.random.default_rng(n).standard_normal(n).astype(np.float32)
+    work = torch.full((257,), 7.0, dtype=torch.float64, device="cuda")
+    nn.sumsq(f32(a), work)
+    ref = float(np.sum(a.astype(np.float64) ** 2))
+    got = float(work[0])
+    assert abs(got - ref) <= 1e-13 * ref, (got, ref)
+    nn.sumsq(f32(a), work)
+    assert float(work[0]) == got  # reproducible bit for bit
+
+
+def test_adam_global_norm_clipping(nn):
+    """Two gradient arrays clipped together: the device scale read from the
+    sumsq result matches the oracle's clip_scale; a bound above the norm
+    leaves the step unclipped."""
+    rng = np.random.default_rng(21)
+    sizes = (600, 37)
+    ws = [rng.standard_normal(k).astype(np.float32) for k in sizes]
+    dev = [[f32(w), f32(np.zeros_like(w)), f32(np.zeros_like(w))] for w in ws]
+    ref = [[w.astype(np.float64), np.zeros(len(w)), np.zeros(len(w))] for w in ws]
+    flat = torch.zeros(sum(sizes), dtype=torch.float32, device="cuda")
+    work = torch.zeros(257, dtype=torch.float64, device="cuda")
+    for t, max_norm in ((1, 3.0), (2, 3.0), (3, 1e6)):
+        gs = [(rng.standard_normal(k) * 2.0).astype(np.float32) for k in sizes]
+        flat.copy_(torch.tensor(np.concatenate(gs)))
+        nn.sumsq(flat, work)
+        sc = U.clip_scale([g.astype(np.float64) for g in gs], max_norm)
+        assert (sc < 1.0) == (max_norm < 10.0)
+        off = 0
+        for k, (d, r, g) in enumerate(zip(dev, ref, gs)):
+            nn.adam(d[0], d[1], d[2], flat[off:off + sizes[k]], 1e-2, 0.9, 0.999, 1e-8, t,
+                    gsq=work[:1], max_norm=max_norm)
+            r[0], r[1], r[2] = U.adam(r[0], r[1], r[2], g.astype(np.float64), 1e-2, 0.9, 0.999, 1e-8, t,
+                                      gscale=sc)
+            off += sizes[k]
+    for d, r in zip(dev, ref):
+        assert np.allclose(d[0].cpu().numpy(), r[0], rtol=1e-5, atol=1e-6)
+        assert np.allclose(d[1].cpu().numpy(), r[1], rtol=1e-5, atol=1e-7)
+        assert np.allclose(d[2].cpu().numpy(), r[2], rtol=1e-4, atol=1e-9)
+
+
 def test_state_conversions(nn):
     rng = np.random.default_rng(12)
     S = 1000

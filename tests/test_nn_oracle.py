@@ -1,7 +1,7 @@
 """Pins of the reference U-Net (oracle/unet_ref.py): every backward formula
 against central finite differences of the FP64 forward pass, the loss
 against a brute-force minimisation over the global phase, and bf16 rounding
-against its definition."""
+against its definition, Adam and global-norm clipping against closed forms."""
 import numpy as np
 import pytest
 
@@ -123,3 +123,36 @@ def test_loss_over_candidates_is_least_candidate():
     f = lambda pp: float(U.loss_value(pp, cands).mean())
     for idx in [(0, 1, 2, 0), (1, 3, 4, 1)]:
         assert abs(g[idx] - fd(f, pred, idx)) < 1e-6
+
+
+def test_adam_closed_forms():
+    """Adam with zero initial moments: the first step moves every weight by
+    lr g / (|g| + eps) (the bias corrections turn the moments back into g
+    and g^2), and a constant gradient keeps moving it by the same amount at
+    every later step; with eps = 0 the step does not depend on the
+    gradient's scale, so a clipping factor changes nothing once the
+    moments are built from clipped gradients alone."""
+    rng = np.random.default_rng(5)
+    w0 = rng.standard_normal(50)
+    g = rng.standard_normal(50) * 10.0 ** rng.uniform(-3, 3, 50)
+    lr, eps = 1e-2, 1e-8
+    m = v = np.zeros(50)
+    w = w0
+    for t in range(1, 6):
+        w, m, v = U.adam(w, m, v, g, lr, 0.9, 0.999, eps, t)
+        assert np.allclose(w, w0 - t * lr * g / (np.abs(g) + eps), rtol=0, atol=1e-12)
+    wa, _, _ = U.adam(w0, np.zeros(50), np.zeros(50), g, lr, 0.9, 0.999, 0.0, 1)
+    wb, _, _ = U.adam(w0, np.zeros(50), np.zeros(50), g, lr, 0.9, 0.999, 0.0, 1, gscale=1e-3)
+    assert np.allclose(wa, wb, rtol=0, atol=1e-14)
+    assert np.allclose(wa, w0 - lr * np.sign(g), rtol=0, atol=1e-14)
+
+
+def test_clip_scale_is_global_norm():
+    a, b = np.array([3.0]), np.array([[0.0, 4.0]])
+    assert U.clip_scale([a, b], 1.0) == pytest.approx(0.2, rel=1e-15)
+    assert U.clip_scale([a, b], 5.0) == 1.0
+    assert U.clip_scale([a, b], 10.0) == 1.0
+    rng = np.random.default_rng(6)
+    gs = [rng.standard_normal(s) for s in ((7, 3), (11,), (2, 2, 5))]
+    c = U.clip_scale(gs, 0.5)
+    assert np.sqrt(sum(np.sum((c * x) ** 2) for x in gs)) == pytest.approx(0.5, rel=1e-14)
