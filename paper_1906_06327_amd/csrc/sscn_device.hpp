@@ -151,58 +151,117 @@ __device__ __forceinline__ Cx<R> minus_kv_st(const LineCoef<R> &L, Cx<R> vm, Cx<
     }
 }
 
+// a * y + t and t - a * y with the multiplications fused, so that a chain
+// of them through y is two dependent FMAs deep per link.
+template <class R>
+__device__ __forceinline__ Cx<R> cfma(Cx<R> a, Cx<R> y, Cx<R> t)
+{
+    return Cx<R>{fma(a.re, y.re, fma(-a.im, y.im, t.re)), fma(a.re, y.im, fma(a.im, y.re, t.im))};
+}
+template <class R>
+__device__ __forceinline__ Cx<R> cfnma(Cx<R> a, Cx<R> y, Cx<R> t)
+{
+    return Cx<R>{fma(-a.re, y.re, fma(a.im, y.im, t.re)), fma(-a.re, y.im, fma(-a.im, y.re, t.im))};
+}
+// Component-wise select (compiles to conditional moves, not branches).
+template <class R>
+__device__ __forceinline__ Cx<R> csel(bool c, Cx<R> a, Cx<R> b)
+{
+    return Cx<R>{c ? a.re : b.re, c ? a.im : b.im};
+}
+
 // Windowed solve of (I + K) delta = -K v for the S unknowns s..s+S-1 of a line
 // with unknowns 1..n-1, by Thomas elimination with the fixed-point factors
 // (cst, rst) from row s-W on; then io[r] = v_{s+r} + 2 delta_{s+r} and
 // d_first = delta_s (both uncorrected for the wall; see above).
-// vals[r] = v_{s-W-1+r} (zero outside 1..n-1), loaded by the caller.
+// vals[r] = v_{s-W-1+r} (zero at the walls), loaded by the caller.
 //
 // In FP64 the solve is done in the Cayley form instead: (I + K) z = v and
 // psi' = 2 z - v, with z_first = z_s (uncorrected) in d_first.  It needs no
 // right-hand side -K v per row, and the wall correction is the same (it
 // depends on the matrix only: out_u -= z_1 zeta_u).  The delta form keeps
 // the rounding of 1 + k0 out of FP32 sweeps, where it matters.
-template <class R, int S, int W, int ST = 0>
+//
+// FP64 (Cayley form) runs the elimination on scaled unknowns: with y = r*
+// yt and z = r* zt the recurrences are yt_u = v_u + alpha yt_{u-1} (alpha =
+// -A- r*) and zt_u = yt_u - c* zt_{u+1}, and r* multiplies only the S
+// outputs.  Rows of the window outside the unknowns 1..n-1 must see the
+// walls' zeros.  The right-hand side is the window value itself, which the
+// callers stage as zero outside the unknowns, so rows before the near wall
+// stay zero by themselves; rows beyond the far wall are zeroed in the back
+// substitution (their yt times 0), which starts from zero at the window's
+// end.  The mask is a product with 0 or 1, not a branch, so the window is
+// one basic block and each recurrence chain (two dependent FMAs per row)
+// overlaps the independent work.  The FP32 delta form does the same with
+// ISSUE = true (the fused step, bound by instruction issue): scaled
+// unknowns, and the right-hand side and coupling of rows outside the
+// unknowns multiplied by 0, so their eliminated values are exactly zero.
+// With ISSUE = false (the bandwidth-bound sweeps, where register count
+// matters more) it keeps the plain recurrence with those rows skipped.
+template <class R, int S, int W, int ST = 0, bool ISSUE = false>
 __device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Cx<R> cst, Cx<R> rst,
                                              const Cx<R> (&vals)[S + 2 * W + 2], Cx<R> (&io)[S], Cx<R> &d_first)
 {
+    constexpr int NR = S + 2 * W;
+    const Cx<R> zero = {R(0), R(0)};
+    const Cx<R> ma = L.Am * rst;
+    const Cx<R> alpha = {-ma.re, -ma.im};
     if constexpr (std::is_same<R, double>::value) {
-        const Cx<R> zero = {R(0), R(0)};
-        const Cx<R> ma = L.Am * rst;
-        const Cx<R> alpha = {-ma.re, -ma.im};  // z'_u = r* v_u + alpha z'_{u-1}
-        Cx<R> zps[S + W];
-        Cx<R> zprev = zero;
+        Cx<R> ys[S + W];
+        Cx<R> yp = zero;
 #pragma unroll
-        for (int r = 0; r < S + 2 * W; ++r) {
-            const int u = s - W + r;
-            const bool valid = (u >= 1) && (u <= n - 1);
-            Cx<R> zp = zero;
-            if (valid)
-                zp = rst * vals[r + 1] + alpha * zprev;
-            zprev = zp;
+        for (int r = 0; r < NR; ++r) {
+            yp = cfma(alpha, yp, vals[r + 1]);
             if (r >= W)
-                zps[r - W] = zp;
+                ys[r - W] = yp;
         }
-        Cx<R> znext = zero;
+        Cx<R> zn = zero;
 #pragma unroll
-        for (int r = S + 2 * W - 1; r >= W; --r) {
-            const Cx<R> z = zps[r - W] - cst * znext;
-            if (r < W + S)
-                io[r - W] = R(2) * z - vals[r + 1];
-            if (r == W)
-                d_first = z;
-            znext = z;
+        for (int r = NR - 1; r >= W; --r) {
+            const int u = s - W + r;
+            const Cx<R> zt = cfnma(cst, zn, ((u <= n - 1) ? R(1) : R(0)) * ys[r - W]);
+            if (r < W + S) {
+                const Cx<R> z = rst * zt;
+                io[r - W] = Cx<R>{fma(R(2), z.re, -vals[r + 1].re), fma(R(2), z.im, -vals[r + 1].im)};
+                if (r == W)
+                    d_first = z;
+            }
+            zn = zt;
         }
         return;
     }
 
-    const Cx<R> zero = {R(0), R(0)};
-    const Cx<R> ma = L.Am * rst;
-    const Cx<R> alpha = {-ma.re, -ma.im};  // d'_u = r* rhs_u + alpha d'_{u-1}
+    if constexpr (ISSUE) {
+        Cx<R> ys[S + W];
+        Cx<R> yp = zero;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int u = s - W + r;
+            const R m = (u >= 1 && u <= n - 1) ? R(1) : R(0);
+            yp = cfma(m * alpha, yp, m * minus_kv_st<R, ST>(L, vals[r], vals[r + 1], vals[r + 2]));
+            if (r >= W)
+                ys[r - W] = yp;
+        }
+        Cx<R> zn = zero;
+#pragma unroll
+        for (int r = NR - 1; r >= W; --r) {
+            const Cx<R> zt = cfnma(cst, zn, ys[r - W]);
+            if (r < W + S) {
+                const Cx<R> z = rst * zt;
+                io[r - W] = Cx<R>{fma(R(2), z.re, vals[r + 1].re), fma(R(2), z.im, vals[r + 1].im)};
+                if (r == W)
+                    d_first = z;
+            }
+            zn = zt;
+        }
+        return;
+    }
+
+    // delta form: d'_u = r* rhs_u + alpha d'_{u-1}, d_u = d'_u - c* d_{u+1}
     Cx<R> dps[S + W];
     Cx<R> dprev = zero;
 #pragma unroll
-    for (int r = 0; r < S + 2 * W; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int u = s - W + r;
         const bool valid = (u >= 1) && (u <= n - 1);
         if (r >= W && r < W + S)
@@ -216,7 +275,7 @@ __device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L,
     }
     Cx<R> dnext = zero;
 #pragma unroll
-    for (int r = S + 2 * W - 1; r >= W; --r) {
+    for (int r = NR - 1; r >= W; --r) {
         const Cx<R> d = dps[r - W] - cst * dnext;
         if (r < W + S)
             io[r - W] = io[r - W] + R(2) * d;
@@ -344,6 +403,59 @@ __device__ __forceinline__ double block_sum_partials(const double *part, int npa
 __device__ __forceinline__ void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
 
+// e^x - 1 for |x| <= 1/4 by its Taylor series x sum_k x^k / (k+1)!
+// (Horner), truncated where the first omitted term is below 2^-60 (FP64,
+// 13 terms) or 2^-30 (FP32, 8 terms) of the sum.
+template <class R>
+__device__ __forceinline__ R expm1_series(R x)
+{
+    constexpr int NT = std::is_same<R, double>::value ? 13 : 8;
+    R c = R(1);
+    R inv[NT];
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+        c = c / R(k + 1);  // 1 / (k+1)!, folded at compile time
+        inv[k] = c;
+    }
+    R q = inv[NT - 1];
+#pragma unroll
+    for (int k = NT - 2; k >= 0; --k)
+        q = fma(q, x, inv[k]);
+    return x * q;
+}
+
+// e^x - 1: the series where |x| <= 1/4, else the library expm1.  The H1
+// factors of the imaginary-time step have small arguments (dt times the
+// local energy), so the library branch is almost never taken.
+template <class R>
+__device__ __forceinline__ R expm1_small(R x)
+{
+    if (fabs(x) <= R(0.25))
+        return expm1_series(x);
+    return expm1(x);
+}
+
+// e[c] <- e^{e[c]} - 1 for the NP arguments a thread holds, with one branch
+// for all of them (so the NP series evaluations interleave): the series if
+// every |e[c]| <= 1/4, else the library expm1 for all.
+template <class R, int NP>
+__device__ __forceinline__ void expm1_all(R (&e)[NP])
+{
+    R amax = R(0);
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+        amax = fmax(amax, fabs(e[c]));
+    if (amax <= R(0.25)) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+            e[c] = expm1_series(e[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+            e[c] = expm1(e[c]);
+    }
+}
+
 // Pointwise H1 factor exp(-i tau w) applied as v + (exp(-i tau w) - 1) v, so
 // that only the small difference from 1 is rounded: real time (tau = dt)
 // exp(-i dt w) - 1 = -2 sin^2(dt w/2) - i sin(dt w); imaginary time
@@ -358,7 +470,7 @@ __device__ __forceinline__ Cx<R> h1_apply(Cx<R> v, R w, R dt)
         const Cx<R> f = {R(-2) * sh * sh, -sn};
         return v + f * v;
     } else {
-        return v + expm1(-dt * w) * v;
+        return v + expm1_small(-dt * w) * v;
     }
 }
 
@@ -424,7 +536,7 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
         }
     }
     const R sr = R((!RT && sm1p) ? *sm1p : 0.0);  // the pending rescale, s - 1
-    {
+    if constexpr (RT || !std::is_same<R, double>::value) {
         Cx<R> *row = lin + sl * LS;
         const double y = a.y0 + sj * a.hy, z = a.z0 + sk * a.hz;
         const double vyz = a.vy * y * y + (a.dim == 3 ? a.vz * z * z : 0.0);
@@ -441,6 +553,28 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
                 }
                 row[u + u / S] = v;
             }
+        }
+    } else {
+        // imaginary time: every argument -dt w first (zero off the line, whose
+        // staged value is zero anyway), then their expm1 together
+        Cx<R> *row = lin + sl * LS;
+        const double y = a.y0 + sj * a.hy, z = a.z0 + sk * a.hz;
+        const double vyz = a.vy * y * y + (a.dim == 3 ? a.vz * z * z : 0.0);
+        R ex[kXLoad];
+#pragma unroll
+        for (int c = 0; c < kXLoad; ++c) {
+            const int u = sm + c * tpl;
+            pre[c] = rescale(pre[c], sr);
+            const double x = a.x0 + u * a.hx;
+            const R arg = -R(a.dt) * (R(a.vx * x * x + vyz) + R(a.g) * norm2(pre[c]));
+            ex[c] = (sact && u >= 1 && u <= nx - 1) ? arg : R(0);
+        }
+        expm1_all(ex);
+#pragma unroll
+        for (int c = 0; c < kXLoad; ++c) {
+            const int u = sm + c * tpl;
+            if (u >= 1 && u <= nx - 1)
+                row[u + u / S] = pre[c] + ex[c] * pre[c];
         }
     }
 #pragma unroll
@@ -542,9 +676,9 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
         const int e = tid + c * 256;
         const int rr = e >> 6, col = e & 63;
         const int u = row0 + rr;
-        pre[c] = Cx<R>{R(0), R(0)};
-        if (e < TR * 64 && plane_ok && u >= 1 && u <= n - 1 && line0 + col < nlines)
-            pre[c] = ld<R>(src, base + (int64_t)u * stride + line0 + col);
+        const bool in = e < TR * 64 && plane_ok && u >= 1 && u <= n - 1 && line0 + col < nlines;
+        pre[c] = csel(in, ld<R>(src, in ? base + (int64_t)u * stride + line0 + col : (int64_t)0),
+                      Cx<R>{R(0), R(0)});
     }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
@@ -720,7 +854,7 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
     constexpr int SY = S / 2, NSY = TR / SY;
     constexpr int ST = RT ? 2 : 1;
     constexpr int PP = 4;  // norm partials prefetched per thread
-    static_assert(TC % S == 0 && TR % SY == 0 && TC * NSY <= NT, "tile shape");
+    static_assert(TC % S == 0 && TR % SY == 0 && TC * NSY <= NT && TC + SR <= NT, "tile shape");
     extern __shared__ __align__(16) unsigned char smem_raw[];
     // SR x SCP staged points, H1 applied; the x-solve writes its outputs
     // (the TC tile columns of every row) back in place
@@ -728,6 +862,8 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
     auto sx = [&](int rr, int cc) -> Cx<R> & { return st1[rr * SCP + cc + cc / S]; };
     __shared__ Cx<R> d1x[SR];
     __shared__ Cx<R> d1y[TC];
+    __shared__ Cx<R> tpx[SR][2];  // (c*, r*) of the x-line of each staged row
+    __shared__ Cx<R> tpy[TC][2];  // (c*, r*) of the y-line of each tile column
     __shared__ double red[20];
     const int tid = threadIdx.x;
     const int nw = ONE ? one.tiles_x * one.tiles_y : *nwork;
@@ -758,15 +894,32 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
             if (!RT && use_pin && tid + k * NT < np)
                 pp[k] = pin[I.poff + tid + k * NT];
         }
+        // every load is issued (from a clamped in-bounds address where the
+        // point lies outside the grid) before any is consumed
         Cx<R> pre[NST];
 #pragma unroll
         for (int c = 0; c < NST; ++c) {
             const int e = tid + c * NT;
             const int rr = e / SC, cc = e - rr * SC;
             const int j = jb + rr, i = ib + cc;
-            pre[c] = Cx<R>{R(0), R(0)};
-            if (e < SR * SC && j >= 1 && j <= ny - 1 && i >= 1 && i <= nx - 1)
-                pre[c] = ld<R>(src, (int64_t)j * nx + i);
+            const bool in = e < SR * SC && j >= 1 && j <= ny - 1 && i >= 1 && i <= nx - 1;
+            pre[c] = ld<R>(src, in ? (int64_t)j * nx + i : (int64_t)0);
+            pre[c] = csel(in, pre[c], Cx<R>{R(0), R(0)});
+        }
+        // pivot pairs (c*, r*) of the x-lines of the staged rows and of the
+        // y-lines of the tile columns
+        Cx<R> pvt[2] = {Cx<R>{R(0), R(0)}, Cx<R>{R(0), R(0)}};
+        {
+            const int rr = tid - TC;
+            if (tid < TC) {
+                const int i = min(max(c0 + tid, 1), nx - 1);
+                pvt[0] = taby[(size_t)i * (W + 2)];
+                pvt[1] = taby[(size_t)i * (W + 2) + 1];
+            } else if (rr < SR) {
+                const int j = min(max(jb + rr, 1), ny - 1);
+                pvt[0] = tabx[(size_t)j * (W + 2)];
+                pvt[1] = tabx[(size_t)j * (W + 2) + 1];
+            }
         }
         double sm1 = 0.0;
         if (!RT && use_pin) {
@@ -780,21 +933,49 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
             sm1 = 1.0 / sqrt(I.dV * red[16]) - 1.0;
         }
         const R sr = R(sm1);
+        // rescale and H1 on every staged point (a point outside the grid
+        // holds zero and stays zero)
+        if constexpr (RT) {
 #pragma unroll
-        for (int c = 0; c < NST; ++c) {
-            const int e = tid + c * NT;
-            if (e < SR * SC) {
+            for (int c = 0; c < NST; ++c) {
+                const int e = tid + c * NT;
                 const int rr = e / SC, cc = e - rr * SC;
                 const int j = jb + rr, i = ib + cc;
-                Cx<R> v = {R(0), R(0)};
-                if (j >= 1 && j <= ny - 1 && i >= 1 && i <= nx - 1) {
-                    v = rescale(pre[c], sr);
-                    const double x = I.x0 + i * I.hx, y = I.y0 + j * I.hy;
-                    const R w = R(I.vx * x * x + I.vy * y * y) + R(I.g) * norm2(v);
-                    v = h1_apply<R, RT>(v, w, R(I.dt));
-                }
-                st1[rr * SCP + cc + cc / S] = v;
+                Cx<R> v = rescale(pre[c], sr);
+                const double x = I.x0 + i * I.hx, y = I.y0 + j * I.hy;
+                const R w = R(I.vx * x * x + I.vy * y * y) + R(I.g) * norm2(v);
+                v = h1_apply<R, RT>(v, w, R(I.dt));
+                if (e < SR * SC)
+                    st1[rr * SCP + cc + cc / S] = v;
             }
+        } else {
+            // imaginary time: all arguments -dt w first, then their expm1
+            // together, then v + expm1(-dt w) v
+            R ex[NST];
+#pragma unroll
+            for (int c = 0; c < NST; ++c) {
+                const int e = tid + c * NT;
+                const int rr = e / SC, cc = e - rr * SC;
+                const int j = jb + rr, i = ib + cc;
+                pre[c] = rescale(pre[c], sr);
+                const double x = I.x0 + i * I.hx, y = I.y0 + j * I.hy;
+                ex[c] = -R(I.dt) * (R(I.vx * x * x + I.vy * y * y) + R(I.g) * norm2(pre[c]));
+            }
+            expm1_all(ex);
+#pragma unroll
+            for (int c = 0; c < NST; ++c) {
+                const int e = tid + c * NT;
+                const int rr = e / SC, cc = e - rr * SC;
+                if (e < SR * SC)
+                    st1[rr * SCP + cc + cc / S] = pre[c] + ex[c] * pre[c];
+            }
+        }
+        if (tid < TC) {
+            tpy[tid][0] = pvt[0];
+            tpy[tid][1] = pvt[1];
+        } else if (tid - TC < SR) {
+            tpx[tid - TC][0] = pvt[0];
+            tpx[tid - TC][1] = pvt[1];
         }
         __syncthreads();
 
@@ -811,20 +992,18 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
                 xo[k][r] = Cx<R>{R(0), R(0)};
             if (p < SR * NSX && j >= 1 && j <= ny - 1) {
                 const LineCoef<R> Lc = line_coef<R>(I.ax[0], I.omega * (I.y0 + j * I.hy));
-                const Cx<R> *trow = tabx + (size_t)j * (W + 2);
                 Cx<R> vals[S + 2 * W + 2];
 #pragma unroll
                 for (int r = 0; r < S + 2 * W + 2; ++r)
                     vals[r] = sx(rr, q * S + r);
                 Cx<R> df;
                 const int s = c0 + q * S;
-                window_solve<R, S, W, ST>(s, nx, Lc, trow[0], trow[1], vals, xo[k], df);
+                window_solve<R, S, W, ST, true>(s, nx, Lc, tpx[rr][0], tpx[rr][1], vals, xo[k], df);
                 if (s == 1)
                     d1x[rr] = df;
 #pragma unroll
                 for (int r = 0; r < S; ++r)
-                    if (s + r > nx - 1)
-                        xo[k][r] = Cx<R>{R(0), R(0)};
+                    xo[k][r] = csel(s + r <= nx - 1, xo[k][r], Cx<R>{R(0), R(0)});
             }
         }
         __syncthreads();
@@ -857,13 +1036,12 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         Cx<R> io[SY];
         if (act) {
             const LineCoef<R> Lc = line_coef<R>(I.ax[1], -I.omega * (I.x0 + i * I.hx));
-            const Cx<R> *trow = taby + (size_t)i * (W + 2);
             Cx<R> vals[SY + 2 * W + 2];
 #pragma unroll
             for (int r = 0; r < SY + 2 * W + 2; ++r)
                 vals[r] = sx(q * SY + r, H + col);
             Cx<R> df;
-            window_solve<R, SY, W, ST>(s, ny, Lc, trow[0], trow[1], vals, io, df);
+            window_solve<R, SY, W, ST, true>(s, ny, Lc, tpy[col][0], tpy[col][1], vals, io, df);
             if (s == 1)
                 d1y[col] = df;
         }
