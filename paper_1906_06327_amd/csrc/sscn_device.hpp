@@ -456,18 +456,82 @@ __device__ __forceinline__ void expm1_all(R (&e)[NP])
     }
 }
 
+// e^{-i th} - 1 = (cos th - 1) - i sin th for |th| <= 1/4 by the Taylor
+// series of cos th - 1 (in th^2, Horner) and sin th, truncated where the
+// first omitted term is below 2^-60 (FP64: 7 and 8 terms) or 2^-30 (FP32: 4
+// and 4 terms) of the sum.
+template <class R>
+__device__ __forceinline__ Cx<R> expim1_series(R th)
+{
+    constexpr bool dbl = std::is_same<R, double>::value;
+    constexpr int NC = dbl ? 7 : 4, NS = dbl ? 8 : 4;
+    R cc[NC], sc[NS];
+    R f = R(1);
+#pragma unroll
+    for (int k = 1; k <= 2 * NS; ++k) {  // 1/k!, folded at compile time
+        f = f / R(k);
+        const R sg = ((k / 2) % 2) ? R(-1) : R(1);
+        if (k % 2 == 0 && k / 2 <= NC)
+            cc[k / 2 - 1] = sg * f;  // (-1)^m / (2m)!, m = k/2
+        if (k % 2 == 1 && (k - 1) / 2 < NS)
+            sc[(k - 1) / 2] = sg * f;  // (-1)^m / (2m+1)!, m = (k-1)/2
+    }
+    const R t = th * th;
+    R pc = cc[NC - 1];
+#pragma unroll
+    for (int m = NC - 2; m >= 0; --m)
+        pc = fma(pc, t, cc[m]);
+    R ps = sc[NS - 1];
+#pragma unroll
+    for (int m = NS - 2; m >= 0; --m)
+        ps = fma(ps, t, sc[m]);
+    return Cx<R>{t * pc, -(th * ps)};
+}
+
+// e^{-i th} - 1 from one library sincos of th/2: -2 sin^2(th/2) - i 2
+// sin(th/2) cos(th/2).
+template <class R>
+__device__ __forceinline__ Cx<R> expim1_lib(R th)
+{
+    R sh, ch;
+    sin_cos(R(0.5) * th, &sh, &ch);
+    return Cx<R>{R(-2) * sh * sh, R(-2) * sh * ch};
+}
+
+// e^{-i th[c]} - 1 for the NP arguments a thread holds, with one branch for
+// all of them: the series if every |th[c]| <= 1/4, else the library.
+template <class R, int NP>
+__device__ __forceinline__ void expim1_all(const R (&th)[NP], Cx<R> (&f)[NP])
+{
+    R amax = R(0);
+#pragma unroll
+    for (int c = 0; c < NP; ++c)
+        amax = fmax(amax, fabs(th[c]));
+    if (amax <= R(0.25)) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+            f[c] = expim1_series(th[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+            f[c] = expim1_lib(th[c]);
+    }
+}
+
 // Pointwise H1 factor exp(-i tau w) applied as v + (exp(-i tau w) - 1) v, so
 // that only the small difference from 1 is rounded: real time (tau = dt)
-// exp(-i dt w) - 1 = -2 sin^2(dt w/2) - i sin(dt w); imaginary time
+// exp(-i dt w) - 1 = (cos(dt w) - 1) - i sin(dt w); imaginary time
 // (tau = -i dt) expm1(-dt w).
 template <class R, bool RT>
 __device__ __forceinline__ Cx<R> h1_apply(Cx<R> v, R w, R dt)
 {
     if constexpr (RT) {
-        R sn, cs, sh, ch;
-        sin_cos(dt * w, &sn, &cs);
-        sin_cos(R(0.5) * dt * w, &sh, &ch);
-        const Cx<R> f = {R(-2) * sh * sh, -sn};
+        const R th = dt * w;
+        Cx<R> f;
+        if (fabs(th) <= R(0.25))
+            f = expim1_series(th);
+        else
+            f = expim1_lib(th);
         return v + f * v;
     } else {
         return v + expm1_small(-dt * w) * v;
@@ -867,7 +931,17 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
     __shared__ double red[20];
     const int tid = threadIdx.x;
     const int nw = ONE ? one.tiles_x * one.tiles_y : *nwork;
-    for (int it = blockIdx.x; it < nw; it += gridDim.x) {
+    // ONE: one block per tile on a grid of 8 ceil(nw / 8) blocks; the
+    // hardware deals consecutive blocks to the 8 XCDs in turn, and the remap
+    // gives each XCD a contiguous run of row-major tiles, so that the halos
+    // neighbouring tiles share are fetched once into that XCD's L2
+    int it0 = blockIdx.x;
+    if (ONE) {
+        it0 = xcd_logical_block(nw);
+        if (it0 < 0)
+            return;
+    }
+    for (int it = it0; it < nw; it += gridDim.x) {
         int ik = 0, tile = it;
         if (!ONE) {
             const int2 wk = work[it];
@@ -936,17 +1010,25 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         // rescale and H1 on every staged point (a point outside the grid
         // holds zero and stays zero)
         if constexpr (RT) {
+            // real time: all angles dt w first, then e^{-i dt w} - 1
+            // together, then v + (e^{-i dt w} - 1) v
+            R th[NST];
 #pragma unroll
             for (int c = 0; c < NST; ++c) {
                 const int e = tid + c * NT;
                 const int rr = e / SC, cc = e - rr * SC;
                 const int j = jb + rr, i = ib + cc;
-                Cx<R> v = rescale(pre[c], sr);
                 const double x = I.x0 + i * I.hx, y = I.y0 + j * I.hy;
-                const R w = R(I.vx * x * x + I.vy * y * y) + R(I.g) * norm2(v);
-                v = h1_apply<R, RT>(v, w, R(I.dt));
+                th[c] = R(I.dt) * (R(I.vx * x * x + I.vy * y * y) + R(I.g) * norm2(pre[c]));
+            }
+            Cx<R> f[NST];
+            expim1_all(th, f);
+#pragma unroll
+            for (int c = 0; c < NST; ++c) {
+                const int e = tid + c * NT;
+                const int rr = e / SC, cc = e - rr * SC;
                 if (e < SR * SC)
-                    st1[rr * SCP + cc + cc / S] = v;
+                    st1[rr * SCP + cc + cc / S] = pre[c] + f[c] * pre[c];
             }
         } else {
             // imaginary time: all arguments -dt w first, then their expm1

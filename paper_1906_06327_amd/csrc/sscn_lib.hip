@@ -477,8 +477,9 @@ template <class R, int W, bool RT>
 void go_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
 {
     constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
-    if (f.one)
-        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>), dim3(f.grid), dim3(kTileNT),
+    if (f.one)  // one block per tile, the grid rounded up to the 8 XCDs (see k_step2d)
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>), dim3(round8(f.grid)),
+                           dim3(kTileNT),
                            lds, st, f.inst, f.work, f.nwork, *f.one, parity, pin, pout, use_pin);
     else
         hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>), dim3(f.grid), dim3(kTileNT),
