@@ -312,13 +312,45 @@ __device__ __forceinline__ int xcd_logical_block(int nblocks)
     return l < nblocks ? l : -1;
 }
 
+// One DPP lane permutation of a double within rows of 16 lanes (CTRL: a
+// gfx9 DPP control code; every lane reads an active lane of its own row).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ double readlane_f64(double v, int lane)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum of v over the 64 lanes of a wave (all lanes active), the same bits in
+// every lane and in every wave that sums the same values: pairs (lane xor
+// 1), then quads (xor 2), then halves of rows mirrored (lane i with 7 - i),
+// then rows mirrored (i with 15 - i), all with DPP row permutations, so each
+// lane of a 16-lane row holds the row's sum; then the four row sums in the
+// fixed order (r0 + r1) + (r2 + r3).
+__device__ __forceinline__ double wave_sum_f64(double v)
+{
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+}
+
 // Deterministic block sum of one double over a 256-thread block; the result
-// is valid in thread 0.  Fixed butterfly order, no atomics.
+// is valid in thread 0.  Fixed reduction order, no atomics.
 __device__ __forceinline__ double block_sum_256(double v, double *red)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off, 64);
+    v = wave_sum_f64(v);
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     __syncthreads();
     if ((tid & 63) == 0)
@@ -350,9 +382,7 @@ __device__ __forceinline__ double block_max_256(double v, double *red)
 template <int NT>
 __device__ __forceinline__ double block_sum_nt(double v, double *red)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1)
-        v += __shfl_xor(v, off, 64);
+    v = wave_sum_f64(v);
     const int tid = threadIdx.x + threadIdx.y * blockDim.x;
     __syncthreads();
     if ((tid & 63) == 0)
@@ -893,10 +923,16 @@ constexpr int stage_stride(int SC, int S)
     return v;
 }
 
+// Dynamic LDS of the fused step, in complex elements: the staged tile.
+constexpr size_t step2d_lds_elems(int S, int W, int TR, int TC)
+{
+    return (size_t)(TR + 2 * W + 2) * stage_stride(TC + 2 * W + 2, S);
+}
+
 template <class R, int S, int W, int TR, int TC>
 constexpr size_t step2d_lds_bytes()
 {
-    return (size_t)(TR + 2 * W + 2) * stage_stride(TC + 2 * W + 2, S) * sizeof(Cx<R>);
+    return step2d_lds_elems(S, W, TR, TC) * sizeof(Cx<R>);
 }
 
 // One step of a 2D instance per tile.  ONE: a single instance passed by
@@ -960,13 +996,16 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
 
         // norm partials of the previous step first (their wait does not
         // wait for the state), then every load of the staged tile
+        // (every wave sums all np partials itself, lane l taking l, l + 64,
+        // ..., so that the rescale needs no block barrier)
         const int np = I.tiles_x * I.tiles_y;
+        const int lane = tid & 63;
         double pp[PP];
 #pragma unroll
         for (int k = 0; k < PP; ++k) {
             pp[k] = 0.0;
-            if (!RT && use_pin && tid + k * NT < np)
-                pp[k] = pin[I.poff + tid + k * NT];
+            if (!RT && use_pin && lane + k * 64 < np)
+                pp[k] = pin[I.poff + lane + k * 64];
         }
         // every load is issued (from a clamped in-bounds address where the
         // point lies outside the grid) before any is consumed
@@ -982,29 +1021,17 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         }
         // pivot pairs (c*, r*) of the x-lines of the staged rows and of the
         // y-lines of the tile columns
-        Cx<R> pvt[2] = {Cx<R>{R(0), R(0)}, Cx<R>{R(0), R(0)}};
-        {
-            const int rr = tid - TC;
-            if (tid < TC) {
-                const int i = min(max(c0 + tid, 1), nx - 1);
-                pvt[0] = taby[(size_t)i * (W + 2)];
-                pvt[1] = taby[(size_t)i * (W + 2) + 1];
-            } else if (rr < SR) {
-                const int j = min(max(jb + rr, 1), ny - 1);
-                pvt[0] = tabx[(size_t)j * (W + 2)];
-                pvt[1] = tabx[(size_t)j * (W + 2) + 1];
-            }
-        }
+        // (thread t < TC: y-line of column c0 + t; TC <= t < TC + SR: x-line
+        // of staged row t - TC; the table row index clamped into the grid)
+        const Cx<R> *prow = tid < TC ? taby + (size_t)min(max(c0 + tid, 1), nx - 1) * (W + 2)
+                                     : tabx + (size_t)min(max(jb + tid - TC, 1), ny - 1) * (W + 2);
+        const Cx<R> pv0 = prow[0], pv1 = prow[1];
         double sm1 = 0.0;
         if (!RT && use_pin) {
             double v = (pp[0] + pp[1]) + (pp[2] + pp[3]);
-            for (int t = tid + PP * NT; t < np; t += NT)
+            for (int t = lane + PP * 64; t < np; t += 64)
                 v += pin[I.poff + t];
-            v = block_sum_nt<NT>(v, red);
-            if (tid == 0)
-                red[16] = v;
-            __syncthreads();
-            sm1 = 1.0 / sqrt(I.dV * red[16]) - 1.0;
+            sm1 = 1.0 / sqrt(I.dV * wave_sum_f64(v)) - 1.0;
         }
         const R sr = R(sm1);
         // rescale and H1 on every staged point (a point outside the grid
@@ -1053,11 +1080,11 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
             }
         }
         if (tid < TC) {
-            tpy[tid][0] = pvt[0];
-            tpy[tid][1] = pvt[1];
+            tpy[tid][0] = pv0;
+            tpy[tid][1] = pv1;
         } else if (tid - TC < SR) {
-            tpx[tid - TC][0] = pvt[0];
-            tpx[tid - TC][1] = pvt[1];
+            tpx[tid - TC][0] = pv0;
+            tpx[tid - TC][1] = pv1;
         }
         __syncthreads();
 

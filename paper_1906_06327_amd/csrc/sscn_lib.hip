@@ -263,8 +263,7 @@ int setup(sscn_handle *h)
         h->W[0] = h->W[1] = h->W[2] = 0;
         h->nemit = kRedBlocks;
     }
-    const size_t flds = (size_t)(kTileR + 2 * h->W[0] + 2) *
-                        stage_stride(kTileC + 2 * h->W[0] + 2, kSeg) * h->esize;
+    const size_t flds = step2d_lds_elems(kSeg, h->W[0], kTileR, kTileC) * h->esize;
     h->fused_ok = p.dim == 2 && !h->exact && h->W[0] > 0 &&
                   h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32) && flds <= 150 * 1024;
     h->ntiles = ((p.nx - 2) / kTileC + 1) * ((p.ny - 2) / kTileR + 1);
@@ -1936,7 +1935,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         b->W = std::max(b->W, tmp[k].W[0]);
     }
     const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
-    const size_t flds = (size_t)(kTileR + 2 * b->W + 2) * stage_stride(kTileC + 2 * b->W + 2, kSeg) * esize;
+    const size_t flds = step2d_lds_elems(kSeg, b->W, kTileR, kTileC) * esize;
     if (b->W > (b->precision == SSCN_C128 ? 20 : 32) || flds > 150 * 1024)
         return bail(fail(SSCN_EINVAL, "the common window of the batch is too large for the fused step"));
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
