@@ -346,7 +346,7 @@ def main(argv=None):
     ap.add_argument("--eval-steps", type=int, default=2000000)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--warmup", type=int, default=1000, help="iterations of linear learning-rate warm-up")
     ap.add_argument("--clip", type=float, default=2.0,
                     help="bound each step's gradient norm by this times the running average norm (0: off)")
