@@ -581,14 +581,14 @@ __device__ __forceinline__ Cx<R> rescale(Cx<R> v, R sm1)
 
 // x-sweep with the H1 sub-step and the pending rescale (s - 1 read from
 // sm1p, NULL for none) fused in front.  A block owns L whole x-lines (L a
-// power of two, L * nseg <= 256, nx * L <= 256 * kXLoad).  Staging and the
+// power of two, L * nseg <= 256, nx * L <= 256 * KX).  Staging and the
 // write-back give each line 256 / L consecutive threads that load (store)
 // its points u = m, m + 256/L, ... coalesced; the staged lines sit in LDS
 // padded every S elements so that the solve threads, which own consecutive
 // segments (thread p: segment p % nseg of line p / nseg), hit distinct banks.
 // src may equal dst: a line is owned by exactly one block, and every load
 // precedes the block's first barrier.
-template <class R, int S, int W, bool RT>
+template <class R, int S, int W, bool RT, int KX = kXLoad>
 __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
                                              const StepArgs &a, int L, const double *__restrict__ sm1p,
                                              const Cx<R> *__restrict__ tab, int line0, unsigned char *smem)
@@ -609,9 +609,9 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
     const int sj = sline % ny, sk = sline / ny;
     const bool sact = sline < nlines && sj > 0 && (a.dim == 2 || sk > 0);
     const int64_t sbase = (int64_t)sline * nx;
-    Cx<R> pre[kXLoad];
+    Cx<R> pre[KX];
 #pragma unroll
-    for (int c = 0; c < kXLoad; ++c) {
+    for (int c = 0; c < KX; ++c) {
         const int u = sm + c * tpl;
         pre[c] = Cx<R>{R(0), R(0)};
         if (sact && u >= 1 && u <= nx - 1)
@@ -635,7 +635,7 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
         const double y = a.y0 + sj * a.hy, z = a.z0 + sk * a.hz;
         const double vyz = a.vy * y * y + (a.dim == 3 ? a.vz * z * z : 0.0);
 #pragma unroll
-        for (int c = 0; c < kXLoad; ++c) {
+        for (int c = 0; c < KX; ++c) {
             const int u = sm + c * tpl;
             if (u >= 1 && u <= nx - 1) {
                 Cx<R> v = {R(0), R(0)};
@@ -654,9 +654,9 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
         Cx<R> *row = lin + sl * LS;
         const double y = a.y0 + sj * a.hy, z = a.z0 + sk * a.hz;
         const double vyz = a.vy * y * y + (a.dim == 3 ? a.vz * z * z : 0.0);
-        R ex[kXLoad];
+        R ex[KX];
 #pragma unroll
-        for (int c = 0; c < kXLoad; ++c) {
+        for (int c = 0; c < KX; ++c) {
             const int u = sm + c * tpl;
             pre[c] = rescale(pre[c], sr);
             const double x = a.x0 + u * a.hx;
@@ -665,7 +665,7 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
         }
         expm1_all(ex);
 #pragma unroll
-        for (int c = 0; c < kXLoad; ++c) {
+        for (int c = 0; c < KX; ++c) {
             const int u = sm + c * tpl;
             if (u >= 1 && u <= nx - 1)
                 row[u + u / S] = pre[c] + ex[c] * pre[c];
@@ -710,7 +710,7 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
     if (sact) {
         const Cx<R> *row = lin + sl * LS;
 #pragma unroll
-        for (int c = 0; c < kXLoad; ++c) {
+        for (int c = 0; c < KX; ++c) {
             const int u = sm + c * tpl;
             if (u >= 1 && u <= nx - 1)
                 st<R>(dst, sbase + u, row[u + u / S]);
@@ -718,13 +718,15 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
     }
 }
 
-template <class R, int S, int W, bool RT>
+// KX: staged points per thread, nx * L <= 256 * KX (fewer registers for
+// short lines, hence more waves per SIMD in this bandwidth-bound kernel).
+template <class R, int S, int W, bool RT, int KX>
 __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
                                                 StepArgs a, int L, const double *__restrict__ sm1p,
                                                 const Cx<R> *__restrict__ tab)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    xsweep_block<R, S, W, RT>(src, dst, a, L, sm1p, tab, blockIdx.x * L, smem_raw);
+    xsweep_block<R, S, W, RT, KX>(src, dst, a, L, sm1p, tab, blockIdx.x * L, smem_raw);
 }
 
 // s - 1 of the pending rescale, s = 1/sqrt(dV sum of the npart norm

@@ -386,8 +386,13 @@ void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream
         if (reduce)
             hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, st, h->partials, npart, h->args.dV, sm1);
     }
-    hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
-                       (V<R> *)dst, h->args, h->xL, (const double *)sm1, (const Cx<R> *)h->tab[0]);
+    if ((int64_t)h->p.nx * h->xL <= 256 * 8)
+        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, 8>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
+                           (V<R> *)dst, h->args, h->xL, (const double *)sm1, (const Cx<R> *)h->tab[0]);
+    else
+        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, kXLoad>), dim3(blocks), dim3(256), h->xlds, st,
+                           (const V<R> *)src, (V<R> *)dst, h->args, h->xL, (const double *)sm1,
+                           (const Cx<R> *)h->tab[0]);
 }
 
 // reduce = false reuses the s - 1 that the last reducing launch left

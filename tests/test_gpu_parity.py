@@ -318,6 +318,31 @@ def test_plans_2d(P, plan, mode, prec, shape):
 
 
 @pytest.mark.parametrize("plan", [1, 2])
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1])
+def test_large_h1_arguments(P, plan, mode, prec):
+    """dt times the potential reaches 0.86 at the box edge, so the threads
+    holding edge points take the library branch of the H1 factor (|dt w| >
+    1/4) while the others use its series; both must match the oracle."""
+    nx, ny = 100, 77
+    announce(f"large H1 arguments plan={plan} mode={mode} prec={prec}")
+    cfg = dict(dim=2, nx=nx, ny=ny, nz=1, hx=0.2, hy=0.2, hz=0.1, gamma=1.0, nu=1.1,
+               lam=1.0, g=60.0, omega=0.55, dt=1e-2, mode=mode, precision=prec)
+    s, op = both(P, cfg)
+    s.set_plan(plan)
+    x = -nx * 0.1 + 0.2 * np.arange(nx)
+    assert 1e-2 * 0.5 * x.max() ** 2 > 0.25  # the library branch is exercised
+    psi0 = W.random_field(23, (ny, nx)) / np.sqrt(0.2 * 0.2)
+    s.set_state(psi0)
+    s.step(60)
+    assert s.solver_info()["plan"] == plan
+    ref = O.step(op, psi0, 60)
+    got = s.get_state().astype(np.complex128)
+    assert rel(got, ref) <= (TOL64 if prec == 0 else TOL32)
+    s.close()
+
+
+@pytest.mark.parametrize("plan", [1, 2])
 def test_plans_config2_full_size(P, plan):
     cfg = W.CONFIGS["c2"]
     announce(f"c2 full size plan={plan}")
