@@ -1710,7 +1710,7 @@ __global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__restrict__ 
     }
 }
 
-template <class R, int S, int W, bool RT>
+template <class R, int S, int W, bool RT, int KX>
 __global__ __launch_bounds__(256) void k_batch_xsweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ xwork,
                                                       const int *__restrict__ nitems, const double *__restrict__ scale,
                                                       int use_scale)
@@ -1721,7 +1721,7 @@ __global__ __launch_bounds__(256) void k_batch_xsweep(const Inst2D *__restrict__
         const int2 wk = xwork[it];
         const Inst2D &I = insts[wk.x];
         const StepArgs a = inst_args(I);
-        xsweep_block<R, S, W, RT>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]),
+        xsweep_block<R, S, W, RT, KX>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]),
                                   reinterpret_cast<typename Vec<R>::T *>(I.buf[1]), a, I.xl,
                                   use_scale ? scale + wk.x : nullptr, reinterpret_cast<const Cx<R> *>(I.tab[0]),
                                   wk.y, smem_raw);

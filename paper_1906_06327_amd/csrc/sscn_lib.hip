@@ -1004,6 +1004,7 @@ struct sscn_batch {
     // sweep plan: x line blocks, y tiles, per-instance rescale
     int plan = SSCN_PLAN_AUTO, active_plan = SSCN_PLAN_FUSED;
     bool sweeps_ok = true;
+    bool xshort = true;  // every instance has nx * L <= 2048: 8 staged points per x-sweep thread
     std::vector<int> xitems, yitems;
     int total_x = 0, total_y = 0, grid_x = 0, grid_y = 0, grid_k = 0;
     size_t xlds = 0;
@@ -1084,8 +1085,12 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
 template <class R, int W, bool RT>
 void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st, b->d_inst,
-                       b->d_xwork, b->d_nx, b->d_scale, use_scale);
+    if (b->xshort)
+        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
+                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
+    else
+        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
+                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
 }
 
 template <class R, int W, bool EMIT>
@@ -2001,6 +2006,8 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         const size_t xl = (L * LS + (size_t)L * (b->W + 2) + L) * esize;
         if (nseg > 256 || h.p.nx > 256 * kXLoad || xl > kXLdsCap)
             b->sweeps_ok = false;
+        if ((int64_t)h.p.nx * L > 256 * 8)
+            b->xshort = false;
         b->xlds = std::max(b->xlds, xl);
         in.xl = L;
         in.ygx = (h.p.nx + 63) / 64;
