@@ -25,7 +25,9 @@ def P():
 
 
 def mixed(prec, mode=0):
-    shapes = [(100, 77), (64, 64), (130, 47), (33, 200), (128, 128)]
+    # nx = 129 takes 16 lines per x-sweep block (nx * L > 2048): the batch then
+    # stages 16 points per x-sweep thread instead of 8
+    shapes = [(100, 77), (64, 64), (130, 47), (33, 200), (128, 128), (129, 40)]
     out = []
     for t, (nx, ny) in enumerate(shapes):
         out.append(dict(dim=2, nx=nx, ny=ny, nz=1, hx=0.1 + 0.01 * t, hy=0.09 + 0.005 * t, hz=0.1,

@@ -299,8 +299,11 @@ def test_precision_upcast(P):
 
 @pytest.mark.parametrize("plan", [1, 2])
 @pytest.mark.parametrize("mode", [0, 1])
-@pytest.mark.parametrize("prec,shape", [(0, (100, 77)), (0, (130, 47)), (1, (96, 70)), (0, (33, 200))])
+@pytest.mark.parametrize("prec,shape", [(0, (100, 77)), (0, (130, 47)), (1, (96, 70)), (0, (33, 200)),
+                                        (0, (129, 40)), (1, (129, 52))])
 def test_plans_2d(P, plan, mode, prec, shape):
+    """nx = 129 gives 16 lines per x-sweep block, nx * L > 2048, so the
+    x-sweep stages 16 points per thread (the others 8)."""
     nx, ny = shape
     announce(f"plan={plan} mode={mode} prec={prec} shape={shape}")
     cfg = dict(dim=2, nx=nx, ny=ny, nz=1, hx=0.11, hy=0.09, hz=0.1, gamma=1.0, nu=1.1,
@@ -399,6 +402,36 @@ def test_autotuner_cache_file_and_x_lines(P, dim, tmp_path, monkeypatch):
     s.close()
     text = out.read_text()
     assert "%dx%d" % (other["nx"], other["ny"]) in text and '"x_lines": %d' % info["x_lines"] in text, text
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("nx", [128, 129])
+def test_x_sweep_staging_depths(P, nx, prec, tmp_path, monkeypatch):
+    """With the largest lines-per-block value (forced through the tune
+    cache) nx = 128 stages 8 points per x-sweep thread (nx * L = 2048) and
+    nx = 129 stages 16 (nx * L = 2064); both match the oracle."""
+    cfg = dict(dim=2, nx=nx, ny=41, nz=1, hx=0.12, hy=0.15, hz=0.1, gamma=1.0, nu=1.1, lam=1.0,
+               g=40.0, omega=0.5, dt=2e-3, mode=0, precision=prec)
+    monkeypatch.setenv("SSCN_TUNE_CACHE", str(tmp_path / "none.json"))
+    probe = P.Solver(cfg)
+    win, lmax = probe.solver_info()["window"][0], probe.solver_info()["x_lines"]
+    probe.close()
+    assert lmax == 16, lmax
+    key = "gfx950|2d|%dx%dx1|%s|imag|W%d" % (nx, cfg["ny"], "c128" if prec == 0 else "c64", win)
+    path = tmp_path / "tune.json"
+    path.write_text('{\n  "%s": {"plan": 1, "x_lines": %d, "ms_per_step": 0.0}\n}\n' % (key, lmax))
+    monkeypatch.setenv("SSCN_TUNE_CACHE", str(path))
+    announce(f"x-sweep staging nx={nx} prec={prec} x_lines={lmax}")
+    ph = W.phase_field(6, cfg["ny"], nx)
+    op = O.make_params(**cfg)
+    ref = O.step(op, O.init_state(op, 1, ph, 1.0), 25)
+    s = P.Solver(cfg)
+    s.init_state(1, ph, 1.0)
+    s.step(25)
+    info = s.solver_info()
+    assert info["plan"] == 1 and info["x_lines"] == lmax, info
+    assert rel(s.get_state().astype(np.complex128), ref) <= (TOL64 if prec == 0 else TOL32)
+    s.close()
 
 
 @pytest.mark.parametrize("dim,plan,mode", [(2, 2, 0), (2, 1, 0), (2, 1, 1), (3, 1, 0)])
