@@ -740,17 +740,22 @@ __global__ __launch_bounds__(256) void k_norm_scale(const double *partials, int 
 }
 
 // ---------------------------------------------------------------------------
-// Strided sweeps (y: stride nx, z: stride nx*ny).  A block takes 64
-// consecutive lines (the lanes of a wave) and kSegBlock consecutive segments
-// (its waves); it stages the tile of kSegBlock*S + 2W + 2 rows x 64 lines
-// those windows cover in LDS with one coalesced pass (each row a contiguous
-// run), so the halo rows shared by neighbouring segments are read once.
-// Thread (lane, wave) solves one segment from LDS and writes its outputs
-// straight to global memory (coalesced across the lanes).  src != dst.  With
-// EMIT the block writes the FP64 partial sum of |psi'|^2 of its outputs at
-// its logical block index.  Grid: 1-D, rounded up to a multiple of 8 logical
+// Strided sweeps (y: stride nx, z: stride nx*ny).  A block (kYLines x
+// kSegBlock threads) takes kYLines consecutive lines and kSegBlock
+// consecutive segments; it stages the tile of kSegBlock*S + 2W + 2 rows x
+// kYLines lines those windows cover in LDS with one coalesced pass (each row
+// a contiguous run), so the halo rows shared by neighbouring segments are
+// read once.  Thread (tx, ty) solves segment ty of line tx from LDS and
+// writes its outputs straight to global memory (coalesced across tx).  The
+// tile is tall (8 segments, 64 output rows) so that the 2W + 2 halo rows
+// add little to the reads, and narrow (32 lines) so that its LDS leaves room
+// for three blocks per CU at W = 14 in FP64.  src != dst.  With EMIT the
+// block writes the FP64 partial sum of |psi'|^2 of its outputs at its
+// logical block index.  Grid: 1-D, rounded up to a multiple of 8 logical
 // blocks (gx line tiles x gy segment groups x gz planes).
-constexpr int kSegBlock = 4;
+constexpr int kYLines = 32;
+constexpr int kSegBlock = 8;
+static_assert(kYLines * kSegBlock == 256, "strided sweep blocks have 256 threads");
 
 template <class R, int S, int W>
 __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__restrict__ src,
@@ -760,26 +765,27 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
                                                    bool emit, double &acc)
 {
     constexpr int TR = kSegBlock * S + 2 * W + 2;
-    constexpr int K = (TR * 64 + 255) / 256;
-    __shared__ Cx<R> tile[TR * 64];
-    __shared__ Cx<R> d1[64];
+    constexpr int LN = kYLines;
+    constexpr int K = (TR * LN + 255) / 256;
+    __shared__ Cx<R> tile[TR * LN];
+    __shared__ Cx<R> d1[LN];
     const int tx = threadIdx.x, ty = threadIdx.y;
-    const int tid = tx + 64 * ty;
+    const int tid = tx + LN * ty;
     const int row0 = by * kSegBlock * S - W;  // line index u of tile row 0
     Cx<R> pre[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         const int e = tid + c * 256;
-        const int rr = e >> 6, col = e & 63;
+        const int rr = e / LN, col = e - rr * LN;
         const int u = row0 + rr;
-        const bool in = e < TR * 64 && plane_ok && u >= 1 && u <= n - 1 && line0 + col < nlines;
+        const bool in = e < TR * LN && plane_ok && u >= 1 && u <= n - 1 && line0 + col < nlines;
         pre[c] = csel(in, ld<R>(src, in ? base + (int64_t)u * stride + line0 + col : (int64_t)0),
                       Cx<R>{R(0), R(0)});
     }
 #pragma unroll
     for (int c = 0; c < K; ++c) {
         const int e = tid + c * 256;
-        if (e < TR * 64)
+        if (e < TR * LN)
             tile[e] = pre[c];
     }
     __syncthreads();
@@ -792,7 +798,7 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
         Cx<R> vals[S + 2 * W + 2];
 #pragma unroll
         for (int r = 0; r < S + 2 * W + 2; ++r)
-            vals[r] = tile[(ty * S + r) * 64 + tx];
+            vals[r] = tile[(ty * S + r) * LN + tx];
         Cx<R> df;
         window_solve<R, S, W>(s0, n, Lc, trow[0], trow[1], vals, io, df);
         if (q == 0)
@@ -823,15 +829,15 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
     }
 }
 
-// One y tile: columns bx*64 .. +63 of plane bz, segment group by; the norm
-// partial of its outputs (EMIT) goes to *partial.
+// One y tile: columns bx*kYLines .. +kYLines-1 of plane bz, segment group
+// by; the norm partial of its outputs (EMIT) goes to *partial.
 template <class R, int S, int W, bool EMIT>
 __device__ __forceinline__ void ysweep_block(const typename Vec<R>::T *__restrict__ src,
                                              typename Vec<R>::T *__restrict__ dst, const StepArgs &a, int bx, int by,
                                              int bz, double *partial, const Cx<R> *__restrict__ tab, double *red)
 {
     const int nx = a.nx, ny = a.ny;
-    const int i = bx * 64 + threadIdx.x;
+    const int i = bx * kYLines + threadIdx.x;
     const bool plane_ok = (a.dim == 2 || bz > 0);
     const Cx<R> *trow = nullptr;
     LineCoef<R> Lc{};
@@ -840,8 +846,8 @@ __device__ __forceinline__ void ysweep_block(const typename Vec<R>::T *__restric
         trow = tab + (size_t)i * (W + 2);
     }
     double acc = 0.0;
-    strided_sweep_tile<R, S, W>(src, dst, ny, (int64_t)bz * nx * ny, nx, nx, bx * 64, by, plane_ok, Lc, trow,
-                                EMIT, acc);
+    strided_sweep_tile<R, S, W>(src, dst, ny, (int64_t)bz * nx * ny, nx, nx, bx * kYLines, by, plane_ok, Lc,
+                                trow, EMIT, acc);
     if (EMIT) {
         const double b = block_sum_256(acc, red);
         if (threadIdx.x == 0 && threadIdx.y == 0)
@@ -876,7 +882,7 @@ __global__ __launch_bounds__(256) void k_zsweep(const typename Vec<R>::T *__rest
         return;
     const int by = lb % gy, bx = lb / gy;
     const int nx = a.nx, ny = a.ny;
-    const int pidx = bx * 64 + threadIdx.x;
+    const int pidx = bx * kYLines + threadIdx.x;
     const int i = pidx % nx, j = pidx / nx;
     const Cx<R> *trow = nullptr;
     LineCoef<R> Lc{};
@@ -885,8 +891,8 @@ __global__ __launch_bounds__(256) void k_zsweep(const typename Vec<R>::T *__rest
         trow = tab;
     }
     double acc = 0.0;
-    strided_sweep_tile<R, S, W>(src, dst, a.nz, 0, (int64_t)nx * ny, nx * ny, bx * 64, by, true, Lc, trow, EMIT,
-                                acc);
+    strided_sweep_tile<R, S, W>(src, dst, a.nz, 0, (int64_t)nx * ny, nx * ny, bx * kYLines, by, true, Lc, trow,
+                                EMIT, acc);
     if (EMIT) {
         const double b = block_sum_256(acc, red);
         if (threadIdx.x == 0 && threadIdx.y == 0)

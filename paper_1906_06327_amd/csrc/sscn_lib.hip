@@ -250,10 +250,10 @@ int setup(sscn_handle *h)
     if (nseg > 256 || p.nx > 256 * kXLoad || h->xlds > kXLdsCap)
         h->exact = true;  // lines too long to stage; whole-line path
     // strided sweeps: logical grids and the partials written by the last one
-    h->ygrid[0] = (p.nx + 63) / 64;
+    h->ygrid[0] = (p.nx + kYLines - 1) / kYLines;
     h->ygrid[1] = ((p.ny - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock;
     h->ygrid[2] = p.dim == 3 ? p.nz : 1;
-    h->zgrid[0] = (int)(((int64_t)p.nx * p.ny + 63) / 64);
+    h->zgrid[0] = (int)(((int64_t)p.nx * p.ny + kYLines - 1) / kYLines);
     h->zgrid[1] = p.dim == 3 ? ((p.nz - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock : 1;
     if (p.dim == 2)
         h->nemit = h->ygrid[0] * h->ygrid[1];
@@ -408,7 +408,7 @@ template <class R, int W, bool EMIT>
 void go_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
 {
     const int *g = h->ygrid;
-    hipLaunchKernelGGL((k_ysweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1] * g[2])), dim3(64, 4), 0,
+    hipLaunchKernelGGL((k_ysweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1] * g[2])), dim3(kYLines, kSegBlock), 0,
                        st, (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1], g[2],
                        (const Cx<R> *)h->tab[1]);
 }
@@ -425,7 +425,7 @@ template <class R, int W, bool EMIT>
 void go_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
 {
     const int *g = h->zgrid;
-    hipLaunchKernelGGL((k_zsweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1])), dim3(64, 4), 0, st,
+    hipLaunchKernelGGL((k_zsweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1])), dim3(kYLines, kSegBlock), 0, st,
                        (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1],
                        (const Cx<R> *)h->tab[2]);
 }
@@ -1096,7 +1096,7 @@ void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
 template <class R, int W, bool EMIT>
 void go_batch_y(const sscn_batch *b, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(std::max(grid, 1)), dim3(64, 4), 0, st, b->d_inst,
+    hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(std::max(grid, 1)), dim3(kYLines, kSegBlock), 0, st, b->d_inst,
                        b->d_ywork, b->d_ny, b->ypart);
 }
 
@@ -2010,7 +2010,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
             b->xshort = false;
         b->xlds = std::max(b->xlds, xl);
         in.xl = L;
-        in.ygx = (h.p.nx + 63) / 64;
+        in.ygx = (h.p.nx + kYLines - 1) / kYLines;
         in.ygy = ((h.p.ny - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock;
         in.ypoff = ypoff;
         b->xitems.push_back((h.p.ny + L - 1) / L);
