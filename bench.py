@@ -18,7 +18,11 @@ Also reported on the same JSON line:
                 changing by < 1e-8 over 0.1 time units at two consecutive
                 checks with an unchanged vortex count);
   cpu_baseline  the FP64 CPU oracle on a bounded sample of the default
-                workload, on the host cores.
+                workload, on the host cores (and on one thread).
+The roofline object also carries the bandwidth of a plain 1 GiB device copy
+(copy_GBps), the achievable figure next to the 8 TB/s specification, and the
+converge object the oracle's time for the same lattice, extrapolated from
+its measured rate.
 """
 import argparse
 import hashlib
@@ -208,9 +212,20 @@ def converge_run(P, torch, cfg, precision, max_steps=3000000):
     return out
 
 
-def cpu_baseline(cfg, seconds):
-    """The FP64 oracle as it stands on the host cores, on a bounded sample
-    (consecutive steps of the same workload from the same initial state)."""
+def _omp_threads(n):
+    """Set the OpenMP thread count of this process's runtime (the oracle's
+    library shares it); returns False where libgomp cannot be loaded."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def oracle_rate(cfg, seconds, chunk=25):
+    """Updates/s of the FP64 oracle over consecutive steps of cfg from its
+    initial state, for about `seconds` of host time."""
     import oracle as O
     p = O.make_params(**W.solver_params(cfg))
     ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
@@ -218,15 +233,47 @@ def cpu_baseline(cfg, seconds):
     psi = O.step(p, psi, 2)  # warm-up
     steps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < seconds:
-        psi = O.step(p, psi, 25)
-        steps += 25
+        psi = O.step(p, psi, chunk)
+        steps += chunk
     dt = time.perf_counter() - t0
+    return cfg["nx"] * cfg["ny"] * steps / dt, steps, dt
+
+
+def cpu_baseline(cfg, seconds):
+    """The FP64 oracle as it stands on the host cores, on a bounded sample
+    (consecutive steps of the same workload from the same initial state),
+    and the same on one thread."""
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    pts = cfg["nx"] * cfg["ny"]
-    return {"value": round(pts * steps / dt, 1), "unit": "updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} consecutive imaginary-time steps of the 512x512 complex128 "
-                      f"workload ({dt:.1f} s), OpenMP over lines with {threads} threads"}
+    rate, steps, dt = oracle_rate(cfg, seconds)
+    out = {"value": round(rate, 1), "unit": "updates/s", "cores": threads, "kind": "oracle",
+           "sample": f"{steps} consecutive imaginary-time steps of the 512x512 complex128 "
+                     f"workload ({dt:.1f} s), OpenMP over lines with {threads} threads"}
+    if _omp_threads(1):
+        r1, s1, d1 = oracle_rate(cfg, seconds / 2, chunk=5)
+        _omp_threads(threads)
+        out["single_thread"] = {"value": round(r1, 1), "unit": "updates/s", "cores": 1,
+                                "sample": f"{s1} consecutive steps of the same workload ({d1:.1f} s)"}
+    return out
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
+    """GB/s of a plain device-to-device copy (read + write counted), timed
+    with HIP events: the achievable HBM bandwidth the kernels are also
+    compared with."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def main():
@@ -250,6 +297,9 @@ def main():
     value = pts * a.steps / dt
     roof = kernel_roofline(s, cfg, step_ms, traffic_key=f"fused2d_512_{a.precision}")
     s.close()
+    copy_gbs = copy_bandwidth(torch)
+    roof["copy_GBps"] = round(copy_gbs, 1)
+    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
 
     out = {
         "metric": "grid-point updates/s per SSCN step (% HBM roofline) + time-to-converged lattice",
@@ -293,6 +343,12 @@ def main():
                              "vortex count unchanged"}
         conv["c128"] = converge_run(P, torch, c1, 0)
         conv["c64_then_c128"] = converge_run(P, torch, c1, 1)
+        if not a.no_cpu:
+            # the oracle on the same lattice: its measured rate times the
+            # GPU run's step count (a full oracle run would take minutes)
+            rate, steps, dt = oracle_rate(c1, 3.0)
+            conv["c128"]["oracle_extrapolated_s"] = round(conv["c128"]["steps"] * c1["nx"] * c1["ny"] / rate, 1)
+            conv["c128"]["oracle_sample"] = f"{steps} oracle steps in {dt:.1f} s on the host cores"
         out["converge"] = conv
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline(W.CONFIGS["c2"], a.cpu_seconds)
