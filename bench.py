@@ -12,8 +12,11 @@ Also reported on the same JSON line:
   roofline      the dominant sweep kernel: algorithmic bytes (one read and
                 one write of the state) / its average duration measured with
                 HIP events on the stream it runs on, against 8 TB/s HBM;
-  variants      the same workload with complex64 sweeps, its real-time
-                phase, and the 3D 256 x 256 x 64 complex64 workload;
+  variants      the same workload with complex64 sweeps, in real time from
+                the start, and in real time from the timed run's state
+                (10 000 steps, norm and energy drift); the 3D 256 x 256 x 64
+                complex64 workload (then 1 000 real-time steps); the
+                64-instance batch;
   converge      time to a converged lattice on the 128^2 workload (mu
                 changing by < 1e-8 over 0.1 time units at two consecutive
                 checks with an unchanged vortex count);
@@ -125,6 +128,25 @@ def timed_steps(P, torch, cfg, steps, warmup, mode=0):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return s, dt, e0.elapsed_time(e1) / steps
+
+
+def real_time_phase(P, torch, s, steps):
+    """From the solver's current imaginary-time state, `steps` real-time
+    steps (same grid and precision): wall time and the drift of the norm
+    and of the full energy functional, which real time conserves up to the
+    splitting error."""
+    o0 = s.observables()
+    s.set_mode(P.SSCN_REAL)
+    s.step(64)  # the plan for real time is tuned on its first step
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.step(steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    o1 = s.observables()
+    return {"steps": steps + 64, "ms_per_step_timed": round(dt / steps * 1e3, 6),
+            "norm_drift": o1["norm"] - o0["norm"],
+            "energy_full_rel_drift": (o1["energy_full"] - o0["energy_full"]) / abs(o0["energy_full"])}
 
 
 def kernel_roofline(s, cfg, step_ms, nlaunch=200, traffic_key=None):
@@ -296,6 +318,7 @@ def main():
     pts = cfg["nx"] * cfg["ny"]
     value = pts * a.steps / dt
     roof = kernel_roofline(s, cfg, step_ms, traffic_key=f"fused2d_512_{a.precision}")
+    rt_phase = None if a.no_extras else real_time_phase(P, torch, s, 10000)
     s.close()
     copy_gbs = copy_bandwidth(torch)
     roof["copy_GBps"] = round(copy_gbs, 1)
@@ -333,7 +356,9 @@ def main():
                                        "ms_per_step": round(dt / 1000 * 1e3, 6),
                                        "roofline": kernel_roofline(s, c3, sm, 100,
                                                                    traffic_key="xsweep_3d_256x256x64_c64")}
+        variants["c3_3d_complex64"]["then_real_time"] = real_time_phase(P, torch, s, 1000)
         s.close()
+        variants["c2_then_real_time"] = rt_phase
         variants["c4_batch_64_instances_complex128"] = batch_run(P, torch)
         out["variants"] = variants
         c1 = W.CONFIGS["c1"]
