@@ -126,6 +126,23 @@ int sscn_set_state(sscn_handle *h, const void *host_psi);
  * walls.  Asynchronous. */
 int sscn_set_state_device(sscn_handle *h);
 
+/* Continuation start (Sec. 3): a converged state of smaller nonlinearity
+ * or rotation seeds the run for larger ones, on a larger grid of the same
+ * spacing to hold the larger condensate.  Centred embedding:
+ * dst[k][j][i] = src[k - oz][j - oy][i - ox] with o = (n - n_src) / 2 per
+ * axis, so the grids' centres x = 0 coincide; zero where that index lies
+ * outside src (a smaller dst crops) and on the walls of dst (index 0).
+ * src: device buffer nz_src x ny_src x nx_src, dst: device buffer
+ * nz x ny x nx, x fastest, both in `precision` (SSCN_C128 or SSCN_C64),
+ * caller-owned, not overlapping; 2D: nz_src = nz = 1.  n - n_src must be
+ * even on every axis, else SSCN_EINVAL (likewise for null or non-positive
+ * arguments and overlap).  Enqueued on `stream` (hipStream_t, NULL for the
+ * null stream), asynchronous; no normalisation (an enlarged normalised
+ * state stays normalised).  Independent of any handle: fill a handle's
+ * buffer and call sscn_set_state_device, or embed into a scratch buffer. */
+int sscn_embed_state(const void *src, int nx_src, int ny_src, int nz_src, void *dst, int nx, int ny, int nz,
+                     int precision, void *stream);
+
 /* Copy psi to a host buffer of the same layout.  Synchronises the stream. */
 int sscn_get_state(sscn_handle *h, void *host_psi);
 

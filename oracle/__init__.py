@@ -147,3 +147,77 @@ def vortex_count(p, psi, density_frac=0.05, box=3):
     a = _buf(p, psi)
     return int(lib().orc_vortex_count(ctypes.byref(p), a.ctypes.data,
                                       float(density_frac), int(box)))
+
+
+def embed(psi, shape):
+    """Continuation start of Sec. 3: place a state (ny, nx) or (nz, ny, nx)
+    at the centre of a grid of `shape` with the same spacing, the index
+    offset on each axis being half the difference of the sizes (the paper's
+    Fortran reads the old grid into I = NX2 - NXOLD2 .. NX2 + NXOLD2).  Points
+    of the new grid not covered by the old one are zero, old points falling
+    outside the new grid are dropped, and the new grid's walls (index 0) are
+    zero.  The size differences must be even, so the two grids' points
+    coincide."""
+    src = np.asarray(psi, dtype=np.complex128)
+    if src.ndim != len(shape) or src.ndim not in (2, 3):
+        raise ValueError("shape rank mismatch")
+    if any((n - m) % 2 for n, m in zip(shape, src.shape)):
+        raise ValueError("grid sizes must differ by an even number of points")
+    out = np.zeros(shape, dtype=np.complex128)
+    for idx in np.ndindex(*shape):
+        if 0 in idx:
+            continue
+        sidx = tuple(i - (n - m) // 2 for i, n, m in zip(idx, shape, src.shape))
+        if all(0 <= si < m for si, m in zip(sidx, src.shape)):
+            out[idx] = src[sidx]
+    return out
+
+
+def _d1_fourth(f, axis, h):
+    """First derivative along `axis` by the fourth-order central difference
+    (-f[i+2] + 8 f[i+1] - 8 f[i-1] + f[i-2]) / (12 h), the field taken as
+    zero beyond the grid (the walls)."""
+    pad = [(0, 0)] * f.ndim
+    pad[axis] = (2, 2)
+    fp = np.pad(f, pad)
+    n = f.shape[axis]
+
+    def at(k):
+        return np.take(fp, np.arange(2 + k, 2 + k + n), axis=axis)
+    return (-at(2) + 8 * at(1) - 8 * at(-1) + at(-2)) / (12 * h)
+
+
+def functional_fourth_order(p, psi):
+    """Energy and chemical potential of Eqs. (e2d) / (e3d) in the rotating
+    frame, E = integral of 1/2 |grad psi|^2 + V |psi|^2 + g/2 |psi|^4 -
+    Omega psi* L_z psi with L_z = -i (x d/dy - y d/dx), and mu = E + g/2
+    integral |psi|^4, per unit norm, with every derivative taken by the
+    fourth-order central difference and integrals as h^d times plain sums.
+    The continuum functional evaluated to O(h^4): the printed values of
+    Table 1 are reproduced this way from the converged lattices (the
+    library's own mu and E use the operators of the discrete step, whose
+    O(h^2) terms grow with the phase gradients of fast rotation)."""
+    psi = np.asarray(psi, dtype=np.complex128)
+    dim = p.dim
+    hs = (p.hz, p.hy, p.hx)[3 - dim:]
+    ns = psi.shape
+    axes = [-ns[k] * hs[k] / 2 + hs[k] * np.arange(ns[k]) for k in range(dim)]
+    grids = np.meshgrid(*axes, indexing="ij")
+    X, Y = grids[-1], grids[-2]
+    V = 0.5 * (p.gamma ** 2 * X ** 2 + p.nu ** 2 * Y ** 2)
+    if dim == 3:
+        V = V + 0.5 * p.lam ** 2 * grids[0] ** 2
+    dvol = float(np.prod(hs))
+    dx = _d1_fourth(psi, dim - 1, p.hx)
+    dy = _d1_fourth(psi, dim - 2, p.hy)
+    grad2 = np.abs(dx) ** 2 + np.abs(dy) ** 2
+    if dim == 3:
+        grad2 = grad2 + np.abs(_d1_fourth(psi, 0, p.hz)) ** 2
+    dens = np.abs(psi) ** 2
+    norm = dens.sum() * dvol
+    kin = 0.5 * grad2.sum() * dvol
+    pot = (V * dens).sum() * dvol
+    inter = 0.5 * p.g * (dens ** 2).sum() * dvol
+    lz = (np.conj(psi) * (-1j) * (X * dy - Y * dx)).sum().real * dvol
+    energy = (kin + pot + inter - p.omega * lz) / norm
+    return {"energy": energy, "mu": energy + inter / norm, "lz": lz / norm, "norm": norm}

@@ -27,7 +27,7 @@ EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
-           "sscn_batch_info", "sscn_batch_destroy",
+           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -95,6 +95,8 @@ def lib():
                                               ctypes.POINTER(ctypes.c_int)]
         L.sscn_batch_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.sscn_embed_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, ctypes.c_int, vp]
         L.sscn_batch_destroy.argtypes = [vp]
         L.sscn_batch_destroy.restype = None
         L.sscn_destroy.argtypes = [vp]
@@ -123,6 +125,28 @@ def make_params(dim=2, nx=64, ny=64, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu
 
 OBS_KEYS = ("norm", "mu", "energy", "mu_full", "energy_full", "rms_x", "rms_y", "rms_z",
             "rms_r", "max_density")
+
+
+def embed_state(src, dst, stream=None):
+    """Centred embedding of the device state tensor `src` into `dst` (same
+    spacing, grid sizes differing by an even number of points per axis;
+    shapes (ny, nx) or (nz, ny, nx), both complex128 or both complex64):
+    the continuation start of Sec. 3.  Asynchronous on `stream` (default:
+    the current torch stream)."""
+    import torch
+    if src.dtype != dst.dtype or src.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError("src and dst must both be complex128 or both complex64")
+    if src.dim() != dst.dim() or src.dim() not in (2, 3):
+        raise ValueError("states are (ny, nx) or (nz, ny, nx)")
+    if not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("states must be contiguous")
+    shs = (1,) * (3 - src.dim()) + tuple(src.shape)
+    shd = (1,) * (3 - dst.dim()) + tuple(dst.shape)
+    prec = SSCN_C128 if src.dtype == torch.complex128 else SSCN_C64
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().sscn_embed_state(ctypes.c_void_p(src.data_ptr()), shs[2], shs[1], shs[0],
+                                  ctypes.c_void_p(dst.data_ptr()), shd[2], shd[1], shd[0], prec,
+                                  ctypes.c_void_p(st.cuda_stream)))
 
 
 class Solver:

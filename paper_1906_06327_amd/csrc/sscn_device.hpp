@@ -1339,6 +1339,28 @@ __global__ __launch_bounds__(256) void k_convert(const typename Vec<RS>::T *src,
 }
 
 // Zero every wall point (index 0 on any axis).
+// Centred embedding (continuation start): dst[k][j][i] = src[k-oz][j-oy][i-ox]
+// where that index lies inside src, else zero; zero on the walls of dst.
+template <class R>
+__global__ __launch_bounds__(256) void k_embed(const typename Vec<R>::T *__restrict__ src, int nxs, int nys,
+                                               int nzs, typename Vec<R>::T *__restrict__ dst, int nx, int ny,
+                                               int nz, int ox, int oy, int oz, int dim)
+{
+    const int64_t n = (int64_t)nx * ny * nz;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int i = (int)(e % nx);
+        const int64_t r = e / nx;
+        const int j = (int)(r % ny), k = (int)(r / ny);
+        const int is = i - ox, js = j - oy, ks = k - oz;
+        const bool wall = i == 0 || j == 0 || (dim == 3 && k == 0);
+        const bool in = !wall && is >= 0 && is < nxs && js >= 0 && js < nys && ks >= 0 && ks < nzs;
+        Cx<R> v = {R(0), R(0)};
+        if (in)
+            v = ld<R>(src, ((int64_t)ks * nys + js) * nxs + is);
+        st<R>(dst, e, v);
+    }
+}
+
 template <class R>
 __global__ __launch_bounds__(256) void k_zero_walls(typename Vec<R>::T *psi, StepArgs a)
 {

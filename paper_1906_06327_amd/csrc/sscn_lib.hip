@@ -1525,6 +1525,33 @@ int sscn_set_state_device(sscn_handle *h)
     return 0;
 }
 
+int sscn_embed_state(const void *src, int nx_src, int ny_src, int nz_src, void *dst, int nx, int ny, int nz,
+                     int precision, void *stream)
+{
+    if (!src || !dst || nx_src < 1 || ny_src < 1 || nz_src < 1 || nx < 1 || ny < 1 || nz < 1)
+        return fail(SSCN_EINVAL, "bad embed arguments");
+    if (precision != SSCN_C128 && precision != SSCN_C64)
+        return fail(SSCN_EINVAL, "precision must be SSCN_C128 or SSCN_C64");
+    if ((nx - nx_src) % 2 || (ny - ny_src) % 2 || (nz - nz_src) % 2)
+        return fail(SSCN_EINVAL, "grid sizes must differ by an even number of points on every axis");
+    const int dim = (nz == 1 && nz_src == 1) ? 2 : 3;
+    const size_t es = precision == SSCN_C128 ? 16 : 8;
+    const char *s0 = (const char *)src, *s1 = s0 + (size_t)nx_src * ny_src * nz_src * es;
+    const char *d0 = (const char *)dst, *d1 = d0 + (size_t)nx * ny * nz * es;
+    if (s0 < d1 && d0 < s1)
+        return fail(SSCN_EINVAL, "src and dst overlap");
+    const int ox = (nx - nx_src) / 2, oy = (ny - ny_src) / 2, oz = (nz - nz_src) / 2;
+    const int nb = red_blocks((int64_t)nx * ny * nz);
+    if (precision == SSCN_C128)
+        hipLaunchKernelGGL((k_embed<double>), dim3(nb), dim3(256), 0, (hipStream_t)stream, (const V<double> *)src,
+                           nx_src, ny_src, nz_src, (V<double> *)dst, nx, ny, nz, ox, oy, oz, dim);
+    else
+        hipLaunchKernelGGL((k_embed<float>), dim3(nb), dim3(256), 0, (hipStream_t)stream, (const V<float> *)src,
+                           nx_src, ny_src, nz_src, (V<float> *)dst, nx, ny, nz, ox, oy, oz, dim);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
 int sscn_get_state(sscn_handle *h, void *host_psi)
 {
     if (!h || !host_psi)

@@ -495,3 +495,25 @@ def test_converge_fp64_and_mixed_precision(P):
     assert 0 < s32.switch_step < steps32 and s.switch_step == -1
     assert abs(s32.observables()["mu"] - mu64) < 1e-7
     s32.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("src_shape,dst_shape", [((30, 40), (50, 64)), ((50, 64), (30, 40)),
+                                                 ((30, 64), (50, 40)), ((10, 16, 20), (14, 20, 28)),
+                                                 ((14, 20, 28), (10, 16, 20))])
+def test_embed_state_matches_oracle(P, prec, src_shape, dst_shape):
+    """Centred embedding (continuation start) against the oracle: pure data
+    movement, so bit-exact; an odd size difference is rejected."""
+    import torch
+    announce(f"embed {src_shape} -> {dst_shape} prec={prec}")
+    rng = np.random.default_rng(len(src_shape) * 100 + src_shape[-1])
+    a = rng.standard_normal(src_shape) + 1j * rng.standard_normal(src_shape)
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    src = torch.tensor(a).to(dt).cuda()
+    dst = torch.full(dst_shape, 7.0 + 7.0j, dtype=dt, device="cuda")
+    P.embed_state(src, dst)
+    ref = O.embed(src.cpu().numpy().astype(np.complex128), dst_shape)
+    assert np.array_equal(dst.cpu().numpy().astype(np.complex128), ref)
+    bad = torch.zeros(tuple(n + (1 if k == 0 else 0) for k, n in enumerate(dst_shape)), dtype=dt, device="cuda")
+    with pytest.raises(P.SSCNError):
+        P.embed_state(src, bad)

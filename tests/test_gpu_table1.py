@@ -1,0 +1,65 @@
+"""The paper's Table 1 and vortex counts, reproduced on the GPU.
+
+The lattices of Fig. 2 (a) and (b) are computed with the library's kernels
+the way the paper computes them (Sec. 3): (a) g = 100, Omega = 0.8 from the
+one-vortex random-phase state of Eq. (fun) for the paper's NPAS = 3 x 10^6
+imaginary-time steps, then (b) g = 100, Omega = 0.95 from the converged (a),
+embedded at the centre of the larger grid (sscn_embed_state), h = 0.05 and
+Delta = 0.00025 throughout.  Their chemical potential and energy, evaluated
+by the oracle's fourth-order functional, must match the printed values of
+Table 1 (tests/golden/table1.json) and the vortex counts those of Sec. 4.
+Tolerance 2e-3: the printed rounding (5e-4) plus the relaxation left after
+the paper's step counts (mu still moves by about 1e-4 per 2.5 x 10^5 steps).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "table1.json")))
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1906_06327_amd as P
+    P.lib()
+    return P
+
+
+def test_table1_lattices_a_and_b(P):
+    from paper_1906_06327_amd import continuation as C
+    cols = GOLDEN["columns"]
+    steps = (3000000, 600000)
+    prev = None
+    for k, (g, omega, n, nv) in enumerate(C.CHAIN[:2]):
+        col = cols[k]
+        assert (col["g2d"], col["omega"], col["grid_2d"], col["vortices"]) == (g, omega, n + 1, nv)
+        print(f"[table1] lattice g={g} Omega={omega} on {n}^2, {steps[k]} steps", flush=True)
+        s = P.Solver(C.params(g, omega, n))
+        if prev is None:
+            s.init_state(1, W.phase_field(13, n, n), 1.0)
+        else:
+            P.embed_state(prev.psi, s.psi)
+            s.set_state_device()
+            prev.close()
+        s.step(steps[k])
+        psi = s.get_state()
+        count = s.vortex_count()
+        f = O.functional_fourth_order(O.make_params(**C.params(g, omega, n)), psi)
+        print(f"[table1]   mu {f['mu']:.5f} (paper {col['mu_2d']}), E {f['energy']:.5f} "
+              f"(paper {col['E_2d']}), {count} vortices (paper {nv})", flush=True)
+        assert count == nv
+        assert abs(f["mu"] - col["mu_2d"]) <= 2e-3
+        assert abs(f["energy"] - col["E_2d"]) <= 2e-3
+        assert abs(f["norm"] - 1.0) < 1e-12
+        prev = s
+    prev.close()

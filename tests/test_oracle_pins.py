@@ -417,3 +417,81 @@ def test_vortex_count_synthetic():
     psi = _synthetic(n, h, zeros[:2] + [5.9 + 0.05j])
     assert O.vortex_count(p, psi) == 2
     assert O.vortex_count(p, psi, density_frac=0.0) == 3
+
+
+def _field(n_y, n_x, h):
+    """A smooth complex field sampled on the paper's grid x_i = -n h/2 + i h
+    (h a power of two, so every coordinate is exact)."""
+    x = -n_x * h / 2 + h * np.arange(n_x)
+    y = -n_y * h / 2 + h * np.arange(n_y)
+    X, Y = np.meshgrid(x, y)
+    return (X + 1j * Y) * np.exp(-(X ** 2 + 2 * Y ** 2) / 4)
+
+
+@pytest.mark.parametrize("small,big", [((10, 14), (16, 22)), ((16, 22), (10, 14)), ((10, 22), (16, 14))])
+def test_embed_keeps_physical_coordinates(small, big):
+    """The embedded value at a point of the new grid is the old grid's value
+    at the same (x, y); points the old grid does not cover, and the walls of
+    the new grid, are zero (Sec. 3, continuation start)."""
+    h = 0.125
+    src = _field(*small, h)
+    src[0, :] = 0
+    src[:, 0] = 0
+    out = O.embed(src, big)
+    ref = _field(*big, h)
+    ny, nx = big
+    y = -ny * h / 2 + h * np.arange(ny)
+    x = -nx * h / 2 + h * np.arange(nx)
+    covered = ((np.abs(y) < small[0] * h / 2)[:, None] | (y == -small[0] * h / 2)[:, None]) & \
+              ((np.abs(x) < small[1] * h / 2)[None, :] | (x == -small[1] * h / 2)[None, :])
+    covered[0, :] = False
+    covered[:, 0] = False
+    # the old grid's own wall row and column hold zero
+    oy, ox = (ny - small[0]) // 2, (nx - small[1]) // 2
+    if 0 <= oy < ny:
+        covered[oy, :] = False
+    if 0 <= ox < nx:
+        covered[:, ox] = False
+    assert np.array_equal(out[covered], ref[covered])
+    assert np.all(out[~covered] == 0)
+
+
+def test_embed_round_trip_norm_and_parity():
+    rng = np.random.default_rng(3)
+    src = rng.standard_normal((6, 12, 10)) + 1j * rng.standard_normal((6, 12, 10))
+    src[0], src[:, 0], src[:, :, 0] = 0, 0, 0
+    big = O.embed(src, (10, 16, 18))
+    assert np.array_equal(O.embed(big, src.shape), src)
+    assert np.sum(np.abs(big) ** 2) == pytest.approx(np.sum(np.abs(src) ** 2), rel=1e-15)
+    with pytest.raises(ValueError):
+        O.embed(src, (10, 16, 17))
+
+
+def test_functional_fourth_order_closed_forms():
+    """The fourth-order functional against closed forms of the continuum:
+    the anisotropic Gaussian (E = mu = (gamma + nu) / 2 at g = 0), the
+    one-vortex state (x + i y) e^{-r^2/2} of the isotropic trap (E = 2 -
+    Omega, L_z = 1), and the GP identity mu - E = g/2 int |psi|^4; the
+    error falls as h^4."""
+    gam, nu = 1.0, 1.4
+    errs = []
+    for n, h in ((96, 0.2), (192, 0.1)):
+        x = D.coords(n, h)
+        Y, X = np.meshgrid(x, x, indexing="ij")
+        p = O.make_params(dim=2, nx=n, ny=n, hx=h, hy=h, gamma=gam, nu=nu, g=0.0, omega=0.3, dt=1e-3, mode=0)
+        psi = np.exp(-(gam * X ** 2 + nu * Y ** 2) / 2).astype(complex)
+        psi[0, :] = 0
+        psi[:, 0] = 0
+        f = O.functional_fourth_order(p, psi)
+        errs.append(abs(f["mu"] - (gam + nu) / 2))
+        pv = O.make_params(dim=2, nx=n, ny=n, hx=h, hy=h, gamma=1.0, nu=1.0, g=7.0, omega=0.45, dt=1e-3, mode=0)
+        v = (X + 1j * Y) * np.exp(-(X ** 2 + Y ** 2) / 2)
+        v[0, :] = 0
+        v[:, 0] = 0
+        fv = O.functional_fourth_order(pv, v)
+        nv = np.sum(np.abs(v) ** 2) * h * h
+        inter = 0.5 * 7.0 * np.sum(np.abs(v) ** 4) * h * h / nv
+        assert abs(fv["lz"] - 1.0) < 5e-4
+        assert abs(fv["energy"] - inter - (2 - 0.45)) < 1e-3
+        assert fv["mu"] - fv["energy"] == pytest.approx(inter, rel=1e-12)
+    assert 12 < errs[0] / errs[1] < 20
