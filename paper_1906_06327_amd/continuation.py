@@ -35,9 +35,19 @@ DT = 2.5e-4
 CHAIN = ((100.0, 0.8, 256, 7), (100.0, 0.95, 320, 19), (500.0, 0.92, 400, 37), (500.0, 0.978, 440, 61))
 
 
-def params(g, omega, n):
+# The 3D chain of Fig. 5 / Table 1: lambda = 100, h_z = 0.025, 33 points in
+# z (32 stored), g_3D = g_2D sqrt(2 pi / lambda), and (d) on 451 x 451 points.
+LAM_3D, HZ_3D, NZ_3D = 100.0, 0.025, 32
+CHAIN_3D = ((25.0662827, 0.8, 256, 7), (25.0662827, 0.95, 320, 19), (125.33141, 0.92, 400, 37),
+            (125.33141, 0.978, 450, 61))
+
+
+def params(g, omega, n, dim=2, precision=SSCN_C128):
+    if dim == 3:
+        return dict(dim=3, nx=n, ny=n, nz=NZ_3D, hx=H, hy=H, hz=HZ_3D, gamma=1.0, nu=1.0, lam=LAM_3D, g=g,
+                    omega=omega, dt=DT, mode=SSCN_IMAG, precision=precision)
     return dict(dim=2, nx=n, ny=n, nz=1, hx=H, hy=H, hz=0.1, gamma=1.0, nu=1.0, lam=1.0, g=g,
-                omega=omega, dt=DT, mode=SSCN_IMAG, precision=SSCN_C128)
+                omega=omega, dt=DT, mode=SSCN_IMAG, precision=precision)
 
 
 def _converge(torch, s, max_steps, tol):
@@ -80,14 +90,15 @@ def _fixed(torch, s, npas, every, settle):
 
 
 def run_chain(max_steps=2000000, tol=1e-8, seed=13, scratch=False, scratch_steps=3000000, log=print,
-              chain=CHAIN, npas=0, every=50000, settle=1e-4, save=None):
+              chain=CHAIN, npas=0, every=50000, settle=1e-4, save=None, dim=2, precision=SSCN_C128,
+              npas_next=0):
     """Converge the chain; returns one record per lattice (continuation
     start from the previous lattice, and with `scratch` from Eq. (fun))."""
     import torch
     import workloads as W
     out, prev = [], None
     for k, (g, omega, n, nv) in enumerate(chain):
-        s = Solver(params(g, omega, n))
+        s = Solver(params(g, omega, n, dim, precision))
         if prev is None:
             s.init_state(1, W.phase_field(seed, n, n), 1.0)
             start = "Eq. (fun)"
@@ -96,7 +107,8 @@ def run_chain(max_steps=2000000, tol=1e-8, seed=13, scratch=False, scratch_steps
             s.set_state_device()
             start = f"lattice {chain[k - 1][:2]} embedded {chain[k - 1][2]} -> {n}"
         rec = {"g": g, "omega": omega, "n": n, "paper_vortices": nv, "start": start}
-        run = (lambda sv, cap: _fixed(torch, sv, npas, every, settle)) if npas > 0 else \
+        nfix = npas_next if (prev is not None and npas_next > 0) else npas
+        run = (lambda sv, cap: _fixed(torch, sv, nfix, every, settle)) if npas > 0 else \
               (lambda sv, cap: _converge(torch, sv, cap, tol))
         rec.update(run(s, max_steps))
         if log:
@@ -104,7 +116,7 @@ def run_chain(max_steps=2000000, tol=1e-8, seed=13, scratch=False, scratch_steps
                 f"{rec['wall_s']} s, mu {rec['mu']:.6f}, E {rec['energy']:.6f}, {rec['vortices']} vortices"
                 + (f", mu settled to {settle:g} at step {rec['settled_step']}" if npas > 0 else ""))
         if scratch and prev is not None:
-            s0 = Solver(params(g, omega, n))
+            s0 = Solver(params(g, omega, n, dim, precision))
             s0.init_state(1, W.phase_field(seed, n, n), 1.0)
             rec["from_fun"] = run(s0, scratch_steps)
             s0.close()
@@ -115,7 +127,7 @@ def run_chain(max_steps=2000000, tol=1e-8, seed=13, scratch=False, scratch_steps
                     + (f", mu settled at step {f['settled_step']}" if npas > 0 else ""))
         if save:
             import numpy as np
-            np.save(f"{save}/lattice_g{g:g}_omega{omega:g}_n{n}.npy", s.get_state())
+            np.save(f"{save}/lattice{dim}d_g{g:g}_omega{omega:g}_n{n}.npy", s.get_state())
         if prev is not None:
             prev.close()
         prev = s
@@ -138,10 +150,16 @@ def main(argv=None):
     ap.add_argument("--settle", type=float, default=1e-4, help="mu band for the settled step with --npas")
     ap.add_argument("--save-states", default=None, help="directory for each lattice's final state (.npy)")
     ap.add_argument("--lattices", type=int, default=len(CHAIN), help="run only the first k lattices")
+    ap.add_argument("--npas-next", type=int, default=0,
+                    help="with --npas: steps for the continued lattices (default: --npas)")
+    ap.add_argument("--dim", type=int, default=2, choices=(2, 3), help="the 2D chain of Fig. 2 or the 3D one of Fig. 5")
+    ap.add_argument("--c64", action="store_true", help="complex64 sweeps (FP64 reductions)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
+    chain = CHAIN if a.dim == 2 else CHAIN_3D
     res = run_chain(a.max_steps, a.tol, a.seed, a.scratch, a.scratch_steps, npas=a.npas, every=a.every,
-                    settle=a.settle, save=a.save_states, chain=CHAIN[:a.lattices])
+                    settle=a.settle, save=a.save_states, chain=chain[:a.lattices], dim=a.dim,
+                    precision=1 if a.c64 else SSCN_C128, npas_next=a.npas_next)
     text = json.dumps({"h": H, "dt": DT, "tol": a.tol, "npas": a.npas, "chain": res}, indent=1)
     if a.out:
         with open(a.out, "w") as fh:
