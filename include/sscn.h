@@ -77,10 +77,13 @@ typedef struct sscn_obs {
     double norm;          /* h^d sum |psi|^2                                  */
     double mu, energy;    /* real-part form                                   */
     double mu_full, energy_full; /* full functional, divided by the norm      */
+    double mu_4th, energy_4th;   /* the same with fourth-order central
+                                    differences: the continuum values to
+                                    O(h^4), the form Table 1 prints           */
     double rms_x, rms_y, rms_z, rms_r;
     double max_density;   /* max |psi|^2                                      */
     int64_t step;         /* steps taken since sscn_init                      */
-    double sums[14];      /* the raw reductions (see sscn_observables)        */
+    double sums[16];      /* the raw reductions (see sscn_observables)        */
 } sscn_obs;
 
 typedef struct sscn_handle sscn_handle;
@@ -115,7 +118,13 @@ int sscn_step(sscn_handle *h, int64_t nsteps);
  * sums[]: 0 |psi|^2, 1 psi_R^2, 2 kinetic(psi_R), 3 V psi_R^2,
  * 4 g|psi|^2 psi_R^2, 5 rotation(psi_R, psi_I), 6 kinetic(psi), 7 V|psi|^2,
  * 8 g|psi|^4, 9 Omega Im[psi^*(y d/dx - x d/dy)psi], 10-12 x^2,y^2,z^2
- * |psi|^2 (all times h^d), 13 max |psi|^2. */
+ * |psi|^2 (all times h^d), 13 max |psi|^2, 14 1/2 |grad psi|^2 and 15
+ * Omega Im[psi^*(y d/dx - x d/dy)psi] with fourth-order central differences
+ * (-f[i+2] + 8 f[i+1] - 8 f[i-1] + f[i-2]) / (12 h) (times h^d): mu_4th and
+ * energy_4th.  The discrete-operator forms (mu, energy, mu_full,
+ * energy_full) are what the iteration converges; they differ from the
+ * continuum values by O(h^2) terms that grow with the phase gradients of
+ * fast rotation. */
 int sscn_observables(sscn_handle *h, sscn_obs *out);
 
 /* Copy a host state (same layout and precision as psi) into psi, zeroing

@@ -33,10 +33,11 @@ class OrcParams(ctypes.Structure):
 class OrcObs(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_double), ("mu", ctypes.c_double),
                 ("energy", ctypes.c_double), ("mu_full", ctypes.c_double),
-                ("energy_full", ctypes.c_double), ("rms_x", ctypes.c_double),
+                ("energy_full", ctypes.c_double), ("mu_4th", ctypes.c_double),
+                ("energy_4th", ctypes.c_double), ("rms_x", ctypes.c_double),
                 ("rms_y", ctypes.c_double), ("rms_z", ctypes.c_double),
                 ("rms_r", ctypes.c_double), ("max_density", ctypes.c_double),
-                ("sums", ctypes.c_double * 14)]
+                ("sums", ctypes.c_double * 16)]
 
 
 def lib():
@@ -130,7 +131,7 @@ def init_state(p, kind=1, phase=None, d_xy=1.0, d_z=None):
     return out
 
 
-OBS_KEYS = ("norm", "mu", "energy", "mu_full", "energy_full", "rms_x",
+OBS_KEYS = ("norm", "mu", "energy", "mu_full", "energy_full", "mu_4th", "energy_4th", "rms_x",
             "rms_y", "rms_z", "rms_r", "max_density")
 
 

@@ -269,10 +269,13 @@ void orc_observables(const orc_params *p, const double complex *psi, orc_obs *ou
      *  [6] 1/2 |grad psi|^2 [7] V |psi|^2   [8] g |psi|^4
      *  [9] Omega Im[psi^* (y d/dx - x d/dy) psi]  (= -Omega <L_z> density)
      *  [10..12] x^2, y^2, z^2 times |psi|^2       [13] max |psi|^2
+     *  [14] 1/2 |grad psi|^2 and [15] Omega Im[psi^* (y d/dx - x d/dy) psi]
+     *       with fourth-order central differences
+     *       (-f[i+2] + 8 f[i+1] - 8 f[i-1] + f[i-2]) / (12 h)
      * Reading of Eq. (e2dr)/(e3dr): the kinetic term enters with +1/2, as
      * integrating psi_R times Eq. (real) by parts gives. */
     const int nz = (p->dim == 3) ? p->nz : 1;
-    double s[14];
+    double s[16];
     memset(s, 0, sizeof s);
     for (int k = 0; k < nz; k++)
         for (int j = 0; j < p->ny; j++)
@@ -303,6 +306,21 @@ void orc_observables(const orc_params *p, const double complex *psi, orc_obs *ou
                                   / (2.0 * p->hy);
                 double complex lz = y * cx - x * cy; /* (y d/dx - x d/dy) psi */
 
+                /* fourth-order central differences */
+                double complex qx = (-at(p, psi, i + 2, j, k) + 8.0 * at(p, psi, i + 1, j, k)
+                                     - 8.0 * at(p, psi, i - 1, j, k) + at(p, psi, i - 2, j, k))
+                                    / (12.0 * p->hx);
+                double complex qy = (-at(p, psi, i, j + 2, k) + 8.0 * at(p, psi, i, j + 1, k)
+                                     - 8.0 * at(p, psi, i, j - 1, k) + at(p, psi, i, j - 2, k))
+                                    / (12.0 * p->hy);
+                double complex qz = 0.0;
+                if (p->dim == 3)
+                    qz = (-at(p, psi, i, j, k + 2) + 8.0 * at(p, psi, i, j, k + 1)
+                          - 8.0 * at(p, psi, i, j, k - 1) + at(p, psi, i, j, k - 2))
+                         / (12.0 * p->hz);
+                double kin4 = cabs(qx) * cabs(qx) + cabs(qy) * cabs(qy) + cabs(qz) * cabs(qz);
+                double complex lz4 = y * qx - x * qy;
+
                 s[0] += dens;
                 s[1] += vr * vr;
                 s[2] += 0.5 * kin_r;
@@ -318,16 +336,21 @@ void orc_observables(const orc_params *p, const double complex *psi, orc_obs *ou
                 s[12] += z * z * dens;
                 if (dens > s[13])
                     s[13] = dens;
+                s[14] += 0.5 * kin4;
+                s[15] += p->omega * cimag(conj(v) * lz4);
             }
     double dv = volume_element(p);
-    for (int t = 0; t < 13; t++)
-        s[t] *= dv;
+    for (int t = 0; t < 16; t++)
+        if (t != 13)
+            s[t] *= dv;
     memcpy(out->sums, s, sizeof s);
     out->norm = s[0];
     out->mu = (s[2] + s[3] + s[4] + s[5]) / s[1];
     out->energy = (s[2] + s[3] + 0.5 * s[4] + s[5]) / s[1];
     out->mu_full = (s[6] + s[7] + s[8] + s[9]) / s[0];
     out->energy_full = (s[6] + s[7] + 0.5 * s[8] + s[9]) / s[0];
+    out->mu_4th = (s[14] + s[7] + s[8] + s[15]) / s[0];
+    out->energy_4th = (s[14] + s[7] + 0.5 * s[8] + s[15]) / s[0];
     out->rms_x = sqrt(s[10] / s[0]);
     out->rms_y = sqrt(s[11] / s[0]);
     out->rms_z = sqrt(s[12] / s[0]);

@@ -35,10 +35,11 @@ typedef struct {
     double norm;             /* h^d sum |psi|^2 */
     double mu, energy;       /* real-part form, Eq. (e2dr)/(e3dr), alpha = 1 and 1/2 */
     double mu_full, energy_full; /* full functional, Eq. (e2d)/(e3d) */
+    double mu_4th, energy_4th;   /* the same functional with fourth-order central differences */
     double rms_x, rms_y, rms_z, rms_r;
     double max_density;
     /* the raw sums, each already multiplied by the volume element */
-    double sums[14];
+    double sums[16];
 } orc_obs;
 
 /* Thomas algorithm (Gaussian elimination without pivoting) for

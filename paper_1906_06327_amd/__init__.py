@@ -48,9 +48,10 @@ class Params(ctypes.Structure):
 class Obs(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_double), ("mu", ctypes.c_double), ("energy", ctypes.c_double),
                 ("mu_full", ctypes.c_double), ("energy_full", ctypes.c_double),
+                ("mu_4th", ctypes.c_double), ("energy_4th", ctypes.c_double),
                 ("rms_x", ctypes.c_double), ("rms_y", ctypes.c_double), ("rms_z", ctypes.c_double),
                 ("rms_r", ctypes.c_double), ("max_density", ctypes.c_double),
-                ("step", ctypes.c_int64), ("sums", ctypes.c_double * 14)]
+                ("step", ctypes.c_int64), ("sums", ctypes.c_double * 16)]
 
 
 _lib = None
@@ -123,7 +124,7 @@ def make_params(dim=2, nx=64, ny=64, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu
                   float(dt), int(mode), int(precision))
 
 
-OBS_KEYS = ("norm", "mu", "energy", "mu_full", "energy_full", "rms_x", "rms_y", "rms_z",
+OBS_KEYS = ("norm", "mu", "energy", "mu_full", "energy_full", "mu_4th", "energy_4th", "rms_x", "rms_y", "rms_z",
             "rms_r", "max_density")
 
 

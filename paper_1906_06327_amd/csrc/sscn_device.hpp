@@ -1411,7 +1411,9 @@ __global__ __launch_bounds__(256) void k_init(typename Vec<R>::T *psi, StepArgs 
     }
 }
 
-// Observables: 13 FP64 sums + max density per block (see sscn_obs.sums).
+// Observables: 15 FP64 sums + max density (index 13) per block (see
+// sscn_obs.sums).
+constexpr int kObsN = 16;
 template <class R>
 __device__ __forceinline__ Cx<double> at(const typename Vec<R>::T *psi, const StepArgs &a, int i, int j, int k)
 {
@@ -1424,7 +1426,8 @@ __device__ __forceinline__ Cx<double> at(const typename Vec<R>::T *psi, const St
 
 // The 13 sums and the max of the observables at grid point p (see sscn_obs).
 template <class R>
-__device__ __forceinline__ void obs_point(const typename Vec<R>::T *psi, const StepArgs &a, int64_t p, double (&s)[14])
+__device__ __forceinline__ void obs_point(const typename Vec<R>::T *psi, const StepArgs &a, int64_t p,
+                                          double (&s)[kObsN])
 {
     const int i = (int)(p % a.nx);
     const int64_t rest = p / a.nx;
@@ -1446,6 +1449,14 @@ __device__ __forceinline__ void obs_point(const typename Vec<R>::T *psi, const S
     const double kin = norm2(fx) + norm2(fy) + norm2(fz);
     const Cx<double> cxd = (1.0 / (2.0 * a.hx)) * (xp - xm), cyd = (1.0 / (2.0 * a.hy)) * (yp - ym);
     const Cx<double> lz = y * cxd - x * cyd;  // (y d/dx - x d/dy) psi
+    // fourth-order central differences (-f[i+2] + 8 f[i+1] - 8 f[i-1] + f[i-2]) / (12 h)
+    const Cx<double> qx = (1.0 / (12.0 * a.hx)) * (8.0 * (xp - xm) - (at<R>(psi, a, i + 2, j, k) - at<R>(psi, a, i - 2, j, k)));
+    const Cx<double> qy = (1.0 / (12.0 * a.hy)) * (8.0 * (yp - ym) - (at<R>(psi, a, i, j + 2, k) - at<R>(psi, a, i, j - 2, k)));
+    Cx<double> qz = {0.0, 0.0};
+    if (a.dim == 3)
+        qz = (1.0 / (12.0 * a.hz)) * (8.0 * (at<R>(psi, a, i, j, k + 1) - at<R>(psi, a, i, j, k - 1)) -
+                                      (at<R>(psi, a, i, j, k + 2) - at<R>(psi, a, i, j, k - 2)));
+    const Cx<double> lz4 = y * qx - x * qy;
     s[0] += dens;
     s[1] += v.re * v.re;
     s[2] += 0.5 * kin_r;
@@ -1460,20 +1471,19 @@ __device__ __forceinline__ void obs_point(const typename Vec<R>::T *psi, const S
     s[11] += y * y * dens;
     s[12] += z * z * dens;
     s[13] = fmax(s[13], dens);
+    s[14] += 0.5 * (norm2(qx) + norm2(qy) + norm2(qz));
+    s[15] += a.omega * (v.re * lz4.im - v.im * lz4.re);  // Im(conj(v) lz4)
 }
 
 template <class R>
-__device__ __forceinline__ void obs_block_write(double (&s)[14], double *red, double *out)
+__device__ __forceinline__ void obs_block_write(double (&s)[kObsN], double *red, double *out)
 {
 #pragma unroll
-    for (int t = 0; t < 13; ++t) {
-        const double b = block_sum_256(s[t], red);
+    for (int t = 0; t < kObsN; ++t) {
+        const double b = t == 13 ? block_max_256(s[t], red) : block_sum_256(s[t], red);
         if (threadIdx.x == 0)
             out[t] = b;
     }
-    const double m = block_max_256(s[13], red);
-    if (threadIdx.x == 0)
-        out[13] = m;
 }
 
 template <class R>
@@ -1481,13 +1491,13 @@ __global__ __launch_bounds__(256) void k_observables(const typename Vec<R>::T *p
 {
     __shared__ double red[8];
     const int64_t n = (int64_t)a.nx * a.ny * (a.dim == 3 ? a.nz : 1);
-    double s[14];
+    double s[kObsN];
 #pragma unroll
-    for (int t = 0; t < 14; ++t)
+    for (int t = 0; t < kObsN; ++t)
         s[t] = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
         obs_point<R>(psi, a, p, s);
-    obs_block_write<R>(s, red, partials + (int64_t)blockIdx.x * 14);
+    obs_block_write<R>(s, red, partials + (int64_t)blockIdx.x * kObsN);
 }
 
 // Fixed-order final reduction of nblk rows of nval partials: values with
@@ -1641,7 +1651,7 @@ __global__ __launch_bounds__(256) void k_batch_finish(const Inst2D *__restrict__
     }
 }
 
-// Observables of every listed (instance, chunk) item into opart[item * 14].
+// Observables of every listed (instance, chunk) item into opart[item * kObsN].
 template <class R>
 __global__ __launch_bounds__(256) void k_batch_obs(const Inst2D *__restrict__ insts, const int2 *__restrict__ owork,
                                                    const int *__restrict__ no, double *__restrict__ opart)
@@ -1655,14 +1665,14 @@ __global__ __launch_bounds__(256) void k_batch_obs(const Inst2D *__restrict__ in
         const typename Vec<R>::T *psi = reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]);
         const int64_t n = (int64_t)I.nx * I.ny;
         const int64_t base = (int64_t)wk.y * kChunk;
-        double s[14];
+        double s[kObsN];
 #pragma unroll
-        for (int t = 0; t < 14; ++t)
+        for (int t = 0; t < kObsN; ++t)
             s[t] = 0.0;
         for (int c = threadIdx.x; c < kChunk; c += 256)
             if (base + c < n)
                 obs_point<R>(psi, a, base + c, s);
-        obs_block_write<R>(s, red, opart + (int64_t)it * 14);
+        obs_block_write<R>(s, red, opart + (int64_t)it * kObsN);
         __syncthreads();
     }
 }
@@ -1685,20 +1695,20 @@ __global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const int *_
     const int cnt = ocount[k], b0 = obase[k];
     if (cnt == 0)
         return;
-    double acc[14];
-    for (int v = 0; v < 14; ++v) {
+    double acc[kObsN];
+    for (int v = 0; v < kObsN; ++v) {
         const bool mx = v == 13;
         double x = 0.0;
         for (int b = threadIdx.x; b < cnt; b += 256) {
-            const double y = opart[(int64_t)(b0 + b) * 14 + v];
+            const double y = opart[(int64_t)(b0 + b) * kObsN + v];
             x = mx ? fmax(x, y) : x + y;
         }
         acc[v] = mx ? block_max_256(x, red) : block_sum_256(x, red);
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        for (int v = 0; v < 14; ++v)
-            sums[(int64_t)k * 14 + v] = acc[v];
+        for (int v = 0; v < kObsN; ++v)
+            sums[(int64_t)k * kObsN + v] = acc[v];
         if (tol > 0.0) {  // a convergence check (tol <= 0: observables only)
             const double mu = (acc[2] + acc[3] + acc[4] + acc[5]) / acc[1];
             const double prev = mu_prev[k];

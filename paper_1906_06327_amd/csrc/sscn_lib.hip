@@ -1344,7 +1344,7 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
         return bail(r);
     const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, (size_t)h->ntiles});
     if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess ||
-        hipMalloc(&h->obs_part, (size_t)kRedBlocks * 14 * sizeof(double)) != hipSuccess ||
+        hipMalloc(&h->obs_part, (size_t)kRedBlocks * kObsN * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_buf, 64 * sizeof(double)) != hipSuccess)
         return bail(fail(SSCN_ENOMEM, "hipMalloc of reduction buffers failed"));
     if (hipMemsetAsync(h->partials, 0, npart * sizeof(double), h->stream) != hipSuccess)
@@ -1472,14 +1472,16 @@ int sscn_observables(sscn_handle *h, sscn_obs *out)
     else
         hipLaunchKernelGGL((k_observables<float>), dim3(nb), dim3(256), 0, h->stream, (const V<float> *)h->psi,
                            h->args, h->obs_part);
-    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->obs_part, nb, 14, 1u << 13, h->obs_buf);
-    double s[14];
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, h->stream, h->obs_part, nb, kObsN, 1u << 13,
+                       h->obs_buf);
+    double s[kObsN];
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipMemcpyAsync(s, h->obs_buf, sizeof s, hipMemcpyDeviceToHost, h->stream));
     HIPCHECK(hipStreamSynchronize(h->stream));
     const double dV = h->args.dV;
-    for (int t = 0; t < 13; ++t)
-        s[t] *= dV;
+    for (int t = 0; t < kObsN; ++t)
+        if (t != 13)
+            s[t] *= dV;
     std::memset(out, 0, sizeof *out);
     std::memcpy(out->sums, s, sizeof s);
     out->norm = s[0];
@@ -1487,13 +1489,15 @@ int sscn_observables(sscn_handle *h, sscn_obs *out)
     out->energy = (s[2] + s[3] + 0.5 * s[4] + s[5]) / s[1];
     out->mu_full = (s[6] + s[7] + s[8] + s[9]) / s[0];
     out->energy_full = (s[6] + s[7] + 0.5 * s[8] + s[9]) / s[0];
+    out->mu_4th = (s[14] + s[7] + s[8] + s[15]) / s[0];
+    out->energy_4th = (s[14] + s[7] + 0.5 * s[8] + s[15]) / s[0];
     out->rms_x = std::sqrt(s[10] / s[0]);
     out->rms_y = std::sqrt(s[11] / s[0]);
     out->rms_z = std::sqrt(s[12] / s[0]);
     out->rms_r = std::sqrt((s[10] + s[11] + s[12]) / s[0]);
     out->max_density = s[13];
     out->step = h->steps;
-    for (int t = 0; t < 14; ++t)
+    for (int t = 0; t < kObsN; ++t)
         if (!std::isfinite(s[t]))
             return fail(SSCN_ENONFINITE, "non-finite reduction in the observables");
     return 0;
@@ -2052,7 +2056,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
     b->total_tiles = poff;
     b->active.assign(n, 1);
     b->conv.assign(n, -1);
-    const size_t nopart = std::max((size_t)b->total_chunks * 14, (size_t)kRedBlocks);
+    const size_t nopart = std::max((size_t)b->total_chunks * kObsN, (size_t)kRedBlocks);
     if (hipMalloc(&b->d_inst, sizeof(Inst2D) * n) != hipSuccess ||
         hipMalloc(&b->d_work, sizeof(int2) * b->total_tiles) != hipSuccess ||
         hipMalloc(&b->d_fwork, sizeof(int2) * b->total_chunks) != hipSuccess ||
@@ -2063,7 +2067,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         hipMalloc(&b->part[0], sizeof(double) * std::max(b->total_tiles, kRedBlocks)) != hipSuccess ||
         hipMalloc(&b->part[1], sizeof(double) * std::max(b->total_tiles, kRedBlocks)) != hipSuccess ||
         hipMalloc(&b->opart, sizeof(double) * nopart) != hipSuccess ||
-        hipMalloc(&b->d_sums, sizeof(double) * (14 * n + 2)) != hipSuccess ||
+        hipMalloc(&b->d_sums, sizeof(double) * (kObsN * n + 2)) != hipSuccess ||
         hipMalloc(&b->d_mu_prev, sizeof(double) * n) != hipSuccess ||
         hipMalloc(&b->d_hits, sizeof(int) * n) != hipSuccess ||
         hipMalloc(&b->d_conv, sizeof(long long) * n) != hipSuccess ||
@@ -2167,20 +2171,22 @@ int sscn_batch_observables(sscn_batch *b, sscn_obs *out)
         batch_obs_launch<double>(b, b->total_chunks, 0.0);
     else
         batch_obs_launch<float>(b, b->total_chunks, 0.0);
-    std::vector<double> sums((size_t)14 * b->n);
+    std::vector<double> sums((size_t)kObsN * b->n);
     HIPCHECK(hipGetLastError());
-    HIPCHECK(hipMemcpyAsync(sums.data(), b->d_sums, sizeof(double) * 14 * b->n, hipMemcpyDeviceToHost, b->stream));
+    HIPCHECK(hipMemcpyAsync(sums.data(), b->d_sums, sizeof(double) * kObsN * b->n, hipMemcpyDeviceToHost,
+                            b->stream));
     HIPCHECK(hipStreamSynchronize(b->stream));
     r = batch_lists(b);
     if (r)
         return r;
     int rc = 0;
     for (int k = 0; k < b->n; ++k) {
-        double s[14];
-        std::memcpy(s, &sums[(size_t)14 * k], sizeof s);
+        double s[kObsN];
+        std::memcpy(s, &sums[(size_t)kObsN * k], sizeof s);
         const double dV = b->args[k].dV;
-        for (int t = 0; t < 13; ++t)
-            s[t] *= dV;
+        for (int t = 0; t < kObsN; ++t)
+            if (t != 13)
+                s[t] *= dV;
         sscn_obs &o = out[k];
         std::memset(&o, 0, sizeof o);
         std::memcpy(o.sums, s, sizeof s);
@@ -2189,12 +2195,14 @@ int sscn_batch_observables(sscn_batch *b, sscn_obs *out)
         o.energy = (s[2] + s[3] + 0.5 * s[4] + s[5]) / s[1];
         o.mu_full = (s[6] + s[7] + s[8] + s[9]) / s[0];
         o.energy_full = (s[6] + s[7] + 0.5 * s[8] + s[9]) / s[0];
+        o.mu_4th = (s[14] + s[7] + s[8] + s[15]) / s[0];
+        o.energy_4th = (s[14] + s[7] + 0.5 * s[8] + s[15]) / s[0];
         o.rms_x = std::sqrt(s[10] / s[0]);
         o.rms_y = std::sqrt(s[11] / s[0]);
         o.rms_r = std::sqrt((s[10] + s[11]) / s[0]);
         o.max_density = s[13];
         o.step = b->conv[k] >= 0 ? b->conv[k] : b->steps;
-        for (int t = 0; t < 14; ++t)
+        for (int t = 0; t < kObsN; ++t)
             if (!std::isfinite(s[t]))
                 rc = fail(SSCN_ENONFINITE, "non-finite reduction in the batch observables");
     }
@@ -2292,7 +2300,7 @@ int sscn_batch_vortex_count(sscn_batch *b, int k, double density_frac, int box, 
         return fail(SSCN_EINVAL, "bad batch_vortex_count arguments");
     const sscn_params &p = b->p[k];
     const StepArgs &a = b->args[k];
-    double *out = b->d_sums + (size_t)14 * b->n;  // two doubles past the observable sums
+    double *out = b->d_sums + (size_t)kObsN * b->n;  // two doubles past the observable sums
     const int nb = red_blocks((int64_t)p.nx * p.ny);
     const int nbv = red_blocks((int64_t)(p.nx - 1) * (p.ny - 1));
     if (b->precision == SSCN_C128) {

@@ -40,7 +40,8 @@ def both(P, cfg):
 
 def check_obs(go, oo, tol):
     errs = {}
-    for k in ("norm", "mu", "energy", "mu_full", "energy_full", "rms_x", "rms_y", "rms_r"):
+    for k in ("norm", "mu", "energy", "mu_full", "energy_full", "mu_4th", "energy_4th", "rms_x", "rms_y",
+              "rms_r"):
         errs[k] = abs(go[k] - oo[k]) / max(1.0, abs(oo[k]))
         assert errs[k] <= tol, (k, go[k], oo[k])
     print("[gpu-parity] observable errors vs oracle: " +

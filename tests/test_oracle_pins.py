@@ -494,4 +494,8 @@ def test_functional_fourth_order_closed_forms():
         assert abs(fv["lz"] - 1.0) < 5e-4
         assert abs(fv["energy"] - inter - (2 - 0.45)) < 1e-3
         assert fv["mu"] - fv["energy"] == pytest.approx(inter, rel=1e-12)
+        # the C oracle's observables compute the same functional
+        ov = O.observables(pv, v)
+        assert ov["mu_4th"] == pytest.approx(fv["mu"], rel=1e-12)
+        assert ov["energy_4th"] == pytest.approx(fv["energy"], rel=1e-12)
     assert 12 < errs[0] / errs[1] < 20
