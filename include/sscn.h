@@ -162,6 +162,22 @@ int sscn_get_state(sscn_handle *h, void *host_psi);
  * parameters are validated as in sscn_init; on error nothing changes. */
 int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev);
 
+/* Density profiles, the paper's density outputs (Sec. 3: full density,
+ * densities integrated over the other dimensions, cross-sections), written
+ * as FP64 into the caller-owned device buffer out_dev:
+ *   SSCN_DEN_FULL   |psi|^2 at every point (layout of psi);
+ *   SSCN_DEN_XY     integral over z of |psi|^2, ny x nx (2D: |psi|^2);
+ *   SSCN_DEN_X / _Y / _Z  integral over the two other axes, nx / ny / nz
+ *                   values (2D: over the one other axis);
+ *   SSCN_DEN_CUT_X / _Y / _Z  |psi|^2 along one axis through the centre
+ *                   indices ny/2, nx/2 (and nz/2) of the others.
+ * Integrals are h times plain sums in a fixed order (reading R4).  The z
+ * profiles need a 3D handle (else SSCN_EINVAL, as for a bad kind or a null
+ * pointer).  Enqueued on the handle's stream; asynchronous. */
+enum { SSCN_DEN_FULL = 0, SSCN_DEN_XY = 1, SSCN_DEN_X = 2, SSCN_DEN_Y = 3, SSCN_DEN_Z = 4,
+       SSCN_DEN_CUT_X = 5, SSCN_DEN_CUT_Y = 6, SSCN_DEN_CUT_Z = 7 };
+int sscn_density(sscn_handle *h, int kind, double *out_dev);
+
 /* Vortex count on the z = 0 plane (k = nz/2 in 3D; the only plane in 2D):
  * plaquettes whose counter-clockwise sum of wrapped phase differences is
  * 2 pi w, w > 0, counted w times, when the largest density within `box`

@@ -222,3 +222,36 @@ def functional_fourth_order(p, psi):
     lz = (np.conj(psi) * (-1j) * (X * dy - Y * dx)).sum().real * dvol
     energy = (kin + pot + inter - p.omega * lz) / norm
     return {"energy": energy, "mu": energy + inter / norm, "lz": lz / norm, "norm": norm}
+
+
+DENSITY_KINDS = ("full", "xy", "x", "y", "z", "cut_x", "cut_y", "cut_z")
+
+
+def density(p, psi, kind):
+    """The paper's density outputs (Sec. 3) from a state (ny, nx) or (nz,
+    ny, nx): 'full' |psi|^2; 'xy' its integral over z; 'x', 'y', 'z' the
+    integrals over the other axes; 'cut_x', 'cut_y', 'cut_z' the values along
+    one axis through the centre indices of the others.  Integrals are h
+    times plain sums."""
+    d = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    if d.ndim == 2:
+        d = d[None]
+    nz, ny, nx = d.shape
+    hz = p.hz if nz > 1 else 1.0
+    if kind == "full":
+        return d if p.dim == 3 else d[0]
+    if kind == "xy":
+        return d.sum(axis=0) * hz
+    if kind == "x":
+        return d.sum(axis=(0, 1)) * p.hy * hz
+    if kind == "y":
+        return d.sum(axis=(0, 2)) * p.hx * hz
+    if kind == "z":
+        return d.sum(axis=(1, 2)) * p.hx * p.hy
+    if kind == "cut_x":
+        return d[nz // 2, ny // 2, :]
+    if kind == "cut_y":
+        return d[nz // 2, :, nx // 2]
+    if kind == "cut_z":
+        return d[:, ny // 2, nx // 2]
+    raise ValueError(kind)

@@ -27,7 +27,7 @@ EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
-           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state",
+           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state", "sscn_density",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -96,6 +96,7 @@ def lib():
                                               ctypes.POINTER(ctypes.c_int)]
         L.sscn_batch_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.sscn_density.argtypes = [vp, ctypes.c_int, vp]
         L.sscn_embed_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, vp]
         L.sscn_batch_destroy.argtypes = [vp]
@@ -261,6 +262,23 @@ class Solver:
         c = ctypes.c_int()
         _check(lib().sscn_vortex_count(self._h, float(density_frac), int(box), ctypes.byref(c)))
         return int(c.value)
+
+    DENSITY_KINDS = {"full": 0, "xy": 1, "x": 2, "y": 3, "z": 4, "cut_x": 5, "cut_y": 6, "cut_z": 7}
+
+    def density(self, kind="full"):
+        """A density profile (sscn_density) as a float64 device tensor:
+        'full' (the state's shape), 'xy' (ny, nx), 'x', 'y', 'z' (integrals
+        over the other axes), 'cut_x', 'cut_y', 'cut_z' (through the
+        centre)."""
+        torch = self._torch
+        k = self.DENSITY_KINDS[kind]
+        p = self.params
+        nz = p.nz if p.dim == 3 else 1
+        shape = {0: self.shape, 1: (p.ny, p.nx), 2: (p.nx,), 3: (p.ny,), 4: (nz,),
+                 5: (p.nx,), 6: (p.ny,), 7: (nz,)}[k]
+        out = torch.empty(shape, dtype=torch.float64, device=self.psi.device)
+        _check(lib().sscn_density(self._h, k, ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def profile_step(self, n):
         """Advance n steps, each kernel launched alone between HIP events;

@@ -1339,6 +1339,56 @@ __global__ __launch_bounds__(256) void k_convert(const typename Vec<RS>::T *src,
 }
 
 // Zero every wall point (index 0 on any axis).
+// Density profiles (the paper's density outputs): out[e] for e < nout of
+// `kind` (see sscn_density): full |psi|^2, integrals over the other axes
+// (sums times the spacings, in a fixed order), or the cut through the
+// centre index of the other axes.
+template <class R>
+__global__ __launch_bounds__(256) void k_density(const typename Vec<R>::T *__restrict__ psi, int nx, int ny,
+                                                 int nz, double hx, double hy, double hz, int kind, int64_t nout,
+                                                 double *__restrict__ out)
+{
+    auto dens = [&](int i, int j, int k) -> double {
+        const Cx<R> v = ld<R>(psi, ((int64_t)k * ny + j) * nx + i);
+        return (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+    };
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nout; e += (int64_t)gridDim.x * 256) {
+        double r = 0.0;
+        if (kind == 0) {
+            const int i = (int)(e % nx);
+            const int64_t t = e / nx;
+            r = dens(i, (int)(t % ny), (int)(t / ny));
+        } else if (kind == 1) {  // integral over z: (j, i)
+            const int i = (int)(e % nx), j = (int)(e / nx);
+            for (int k = 0; k < nz; ++k)
+                r += dens(i, j, k);
+            r *= nz > 1 ? hz : 1.0;
+        } else if (kind == 2) {  // integral over y, z: i
+            for (int k = 0; k < nz; ++k)
+                for (int j = 0; j < ny; ++j)
+                    r += dens((int)e, j, k);
+            r *= hy * (nz > 1 ? hz : 1.0);
+        } else if (kind == 3) {  // integral over x, z: j
+            for (int k = 0; k < nz; ++k)
+                for (int i = 0; i < nx; ++i)
+                    r += dens(i, (int)e, k);
+            r *= hx * (nz > 1 ? hz : 1.0);
+        } else if (kind == 4) {  // integral over x, y: k
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    r += dens(i, j, (int)e);
+            r *= hx * hy;
+        } else if (kind == 5) {  // cut along x through (ny/2, nz/2)
+            r = dens((int)e, ny / 2, nz / 2);
+        } else if (kind == 6) {  // cut along y
+            r = dens(nx / 2, (int)e, nz / 2);
+        } else {  // cut along z
+            r = dens(nx / 2, ny / 2, (int)e);
+        }
+        out[e] = r;
+    }
+}
+
 // Centred embedding (continuation start): dst[k][j][i] = src[k-oz][j-oy][i-ox]
 // where that index lies inside src, else zero; zero on the walls of dst.
 template <class R>

@@ -1627,6 +1627,30 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
     return 0;
 }
 
+int sscn_density(sscn_handle *h, int kind, double *out_dev)
+{
+    if (!h || !out_dev || kind < SSCN_DEN_FULL || kind > SSCN_DEN_CUT_Z)
+        return fail(SSCN_EINVAL, "bad density arguments");
+    const sscn_params &p = h->p;
+    const int nz = p.dim == 3 ? p.nz : 1;
+    if (p.dim == 2 && (kind == SSCN_DEN_Z || kind == SSCN_DEN_CUT_Z))
+        return fail(SSCN_EINVAL, "z profiles need a 3D handle");
+    const int64_t nout = kind == SSCN_DEN_FULL ? h->npts
+                         : kind == SSCN_DEN_XY ? (int64_t)p.nx * p.ny
+                         : (kind == SSCN_DEN_X || kind == SSCN_DEN_CUT_X) ? p.nx
+                         : (kind == SSCN_DEN_Y || kind == SSCN_DEN_CUT_Y) ? p.ny
+                                                                           : nz;
+    const int nb = red_blocks(nout);
+    if (p.precision == SSCN_C128)
+        hipLaunchKernelGGL((k_density<double>), dim3(nb), dim3(256), 0, h->stream, (const V<double> *)h->psi, p.nx,
+                           p.ny, nz, p.hx, p.hy, p.hz, kind, nout, out_dev);
+    else
+        hipLaunchKernelGGL((k_density<float>), dim3(nb), dim3(256), 0, h->stream, (const V<float> *)h->psi, p.nx,
+                           p.ny, nz, p.hx, p.hy, p.hz, kind, nout, out_dev);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
 int sscn_vortex_count(sscn_handle *h, double density_frac, int box, int *count)
 {
     if (!h || !count || box < 0 || !(density_frac >= 0))

@@ -518,3 +518,31 @@ def test_embed_state_matches_oracle(P, prec, src_shape, dst_shape):
     bad = torch.zeros(tuple(n + (1 if k == 0 else 0) for k, n in enumerate(dst_shape)), dtype=dt, device="cuda")
     with pytest.raises(P.SSCNError):
         P.embed_state(src, bad)
+
+
+@pytest.mark.parametrize("dim,prec", [(2, 0), (2, 1), (3, 0), (3, 1)])
+def test_density_profiles_match_oracle(P, dim, prec):
+    """Every density output of sscn_density against the oracle's definition
+    on the same (stepped, ragged) state; 2D handles reject the z profiles."""
+    announce(f"density profiles dim={dim} prec={prec}")
+    if dim == 2:
+        cfg = dict(dim=2, nx=70, ny=53, nz=1, hx=0.15, hy=0.17, hz=0.1, gamma=1.0, nu=1.1, lam=1.0, g=30.0,
+                   omega=0.4, dt=2e-3, mode=0, precision=prec)
+    else:
+        cfg = dict(dim=3, nx=34, ny=27, nz=19, hx=0.3, hy=0.3, hz=0.35, gamma=1.0, nu=1.1, lam=2.0, g=20.0,
+                   omega=0.4, dt=2e-3, mode=0, precision=prec)
+    s, op = both(P, cfg)
+    s.init_state(1, W.phase_field(4, cfg["ny"], cfg["nx"]), 1.0)
+    s.step(7)
+    psi = s.get_state().astype(np.complex128)
+    tol = 1e-13 if prec == 0 else 1e-6
+    for kind in O.DENSITY_KINDS:
+        if dim == 2 and kind in ("z", "cut_z"):
+            with pytest.raises(P.SSCNError):
+                s.density(kind)
+            continue
+        got = s.density(kind).cpu().numpy()
+        ref = O.density(op, psi, kind)
+        assert got.shape == ref.shape, kind
+        assert np.max(np.abs(got - ref)) <= tol * max(1.0, np.max(np.abs(ref))), kind
+    s.close()

@@ -499,3 +499,32 @@ def test_functional_fourth_order_closed_forms():
         assert ov["mu_4th"] == pytest.approx(fv["mu"], rel=1e-12)
         assert ov["energy_4th"] == pytest.approx(fv["energy"], rel=1e-12)
     assert 12 < errs[0] / errs[1] < 20
+
+
+def test_density_profiles_closed_forms():
+    """Integrated densities of the normalised anisotropic Gaussian
+    sqrt(gamma nu)/pi e^{-gamma x^2 - nu y^2} are its 1D marginals
+    sqrt(gamma/pi) e^{-gamma x^2} (and in y), the cuts through the centre
+    are the Gaussian at y = 0 (index ny/2 is y = 0 on the paper's grid), and
+    the 3D z profile of a product state is the z marginal."""
+    gam, nu, n, h = 1.3, 0.8, 96, 0.2
+    x = D.coords(n, h)
+    Y, X = np.meshgrid(x, x, indexing="ij")
+    psi = (gam * nu) ** 0.25 / np.sqrt(np.pi) * np.exp(-(gam * X ** 2 + nu * Y ** 2) / 2)
+    psi[0, :] = 0
+    psi[:, 0] = 0
+    p = O.make_params(dim=2, nx=n, ny=n, hx=h, hy=h, gamma=gam, nu=nu)
+    assert np.allclose(O.density(p, psi, "x"), np.sqrt(gam / np.pi) * np.exp(-gam * x ** 2), atol=1e-12)
+    assert np.allclose(O.density(p, psi, "y"), np.sqrt(nu / np.pi) * np.exp(-nu * x ** 2), atol=1e-12)
+    assert x[n // 2] == 0.0
+    assert np.allclose(O.density(p, psi, "cut_x"), np.sqrt(gam * nu) / np.pi * np.exp(-gam * x ** 2), atol=1e-15)
+    assert np.array_equal(O.density(p, psi, "xy"), np.abs(psi) ** 2)
+    nz, hz, lam = 40, 0.15, 2.0
+    z = D.coords(nz, hz)
+    fz = (lam / np.pi) ** 0.25 * np.exp(-lam * z ** 2 / 2)
+    fz[0] = 0
+    psi3 = fz[:, None, None] * psi[None]
+    p3 = O.make_params(dim=3, nx=n, ny=n, nz=nz, hx=h, hy=h, hz=hz, gamma=gam, nu=nu, lam=lam)
+    assert np.allclose(O.density(p3, psi3, "z"), fz ** 2, atol=1e-12)
+    assert np.allclose(O.density(p3, psi3, "xy"), np.abs(psi) ** 2, atol=1e-12)
+    assert np.allclose(O.density(p3, psi3, "x"), np.sqrt(gam / np.pi) * np.exp(-gam * x ** 2), atol=1e-12)
