@@ -9,7 +9,8 @@ and checks the vortex count that the paper's statements fix:
   Sec. 5);
 - without it, the one-vortex start ends with an odd and the Gaussian start
   with an even number of vortices (Sec. 2 and Sec. 5);
-- at fixed g the count does not decrease as Omega grows (Sec. 4, Figs. 1-2).
+- at fixed g the count does not decrease as Omega grows (Sec. 4, Figs. 1-2),
+  also on the batched path that maps it (`omega_maps`).
 
 The exact counts at these parameters are printed nowhere in the paper
 (parity unpinned); the tests check only what the statements fix.
@@ -75,3 +76,29 @@ def test_count_does_not_decrease_with_rotation(P):
     counts = [converged(P, 1, 13, om)[0] for om in (0.3, 0.5, 0.6, 0.8)]
     assert all(a <= b for a, b in zip(counts, counts[1:])), counts
     assert counts[-1] > counts[0]
+
+
+def test_batched_count_map_and_omega_c(P):
+    """The rotation maps of Sec. 4 (Figs. 1 and 4) as batched runs: counts
+    at g = 100 do not decrease with Omega, and the bisected Omega_c lies
+    between the last vortex-free and the first vortex-holding Omega."""
+    from paper_1906_06327_amd import omega_maps as M
+    recs = M.count_map([100.0], [0.3, 0.5, 0.8], seeds=(13,), max_steps=MAX_STEPS)
+    print("[physics] batched counts:", [(r["omega"], r["vortices"], r["steps"]) for r in recs], flush=True)
+    assert all(r["converged"] and r["n"] == 128 for r in recs)
+    counts = [r["vortices"] for r in recs]
+    assert counts[0] == 0 and counts[1] >= 1 and counts[2] >= counts[1]
+    res = M.omega_c([100.0], seeds=(13,), lo=0.3, hi=0.5, rounds=3, max_steps=MAX_STEPS)[100.0]
+    a, b = res["brackets"][0]
+    print(f"[physics] Omega_c(g=100, seed 13) in [{a:.4f}, {b:.4f}]", flush=True)
+    assert 0.3 <= a < b <= 0.5 and b - a == pytest.approx(0.2 / 8)
+
+
+def test_omega_c_decreases_with_g(P):
+    """Fig. 1: the critical rotation of the first vortex falls as g_2D
+    grows (three bisection rounds from [0.1, 0.9], brackets 0.1 wide)."""
+    from paper_1906_06327_amd import omega_maps as M
+    res = M.omega_c([25.0, 400.0], seeds=(13,), lo=0.1, hi=0.9, rounds=3, max_steps=MAX_STEPS)
+    (a25, b25), (a400, b400) = res[25.0]["brackets"][0], res[400.0]["brackets"][0]
+    print(f"[physics] Omega_c: g=25 in [{a25:.3f}, {b25:.3f}], g=400 in [{a400:.3f}, {b400:.3f}]", flush=True)
+    assert b400 <= a25
