@@ -152,6 +152,21 @@ int sscn_set_state_device(sscn_handle *h);
 int sscn_embed_state(const void *src, int nx_src, int ny_src, int nz_src, void *dst, int nx, int ny, int nz,
                      int precision, void *stream);
 
+/* Product start of the 3D form of Eq. (fun) (Sec. 2): the z dependence is
+ * a Gaussian of width d_z, so a 2D field xy(x, y) becomes
+ * dst[k][j][i] = xy[j][i] exp(-z_k^2 / (2 d_z^2)) / sqrt(hz S), with
+ * z_k = -nz hz / 2 + k hz (the grid convention above) and
+ * S = sum_{k=1}^{nz-1} exp(-z_k^2 / d_z^2): a 2D field normalised on its
+ * grid gives a 3D state normalised over the interior.  The wall plane k = 0
+ * is written too; call sscn_set_state_device on the 3D handle to zero it.
+ * xy: device buffer ny x nx, dst: device buffer nz x ny x nx, x fastest,
+ * both in `precision` (SSCN_C128 or SSCN_C64), caller-owned, not
+ * overlapping.  SSCN_EINVAL for null or overlapping buffers, sizes below 2,
+ * or hz, d_z not positive and finite.  Enqueued on `stream` (hipStream_t,
+ * NULL for the null stream), asynchronous. */
+int sscn_extend_z(const void *xy, int nx, int ny, void *dst, int nz, double hz, double d_z, int precision,
+                  void *stream);
+
 /* Copy psi to a host buffer of the same layout.  Synchronises the stream. */
 int sscn_get_state(sscn_handle *h, void *host_psi);
 

@@ -174,6 +174,23 @@ def embed(psi, shape):
     return out
 
 
+def extend_z(xy, nz, hz, d_z):
+    """The 3D form of Eq. (fun) is a 2D function times a Gaussian in z of
+    width d_z.  Given a 2D field, return the (nz, ny, nx) product with the
+    Gaussian exp(-z^2 / (2 d_z^2)) at z_k = -nz hz / 2 + k hz, divided by
+    sqrt(hz sum_{k=1}^{nz-1} exp(-z_k^2 / d_z^2)) so that a 2D field normalised
+    on its grid gives a 3D state normalised over the interior; the wall plane
+    k = 0 is included (the caller zeroes it)."""
+    xy = np.asarray(xy)
+    z = -0.5 * nz * hz + np.arange(nz) * hz
+    gz = np.exp(-0.5 * (z / d_z) ** 2)
+    norm = np.sqrt(hz * np.sum(gz[1:] ** 2))
+    out = np.empty((nz,) + xy.shape, dtype=np.complex128)
+    for k in range(nz):
+        out[k] = xy.astype(np.complex128) * (gz[k] / norm)
+    return out
+
+
 def _d1_fourth(f, axis, h):
     """First derivative along `axis` by the fourth-order central difference
     (-f[i+2] + 8 f[i+1] - 8 f[i-1] + f[i-2]) / (12 h), the field taken as

@@ -27,7 +27,7 @@ EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
-           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state", "sscn_density",
+           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state", "sscn_extend_z", "sscn_density",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -99,6 +99,8 @@ def lib():
         L.sscn_density.argtypes = [vp, ctypes.c_int, vp]
         L.sscn_embed_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, vp]
+        L.sscn_extend_z.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_int, vp]
         L.sscn_batch_destroy.argtypes = [vp]
         L.sscn_batch_destroy.restype = None
         L.sscn_destroy.argtypes = [vp]
@@ -149,6 +151,26 @@ def embed_state(src, dst, stream=None):
     _check(lib().sscn_embed_state(ctypes.c_void_p(src.data_ptr()), shs[2], shs[1], shs[0],
                                   ctypes.c_void_p(dst.data_ptr()), shd[2], shd[1], shd[0], prec,
                                   ctypes.c_void_p(st.cuda_stream)))
+
+
+def extend_z(xy, dst, hz, d_z, stream=None):
+    """The 3D product start of Eq. (fun): dst[k] = xy * Gaussian(z_k) of
+    width d_z, normalised over the interior z points (include/sscn.h,
+    sscn_extend_z).  xy: (ny, nx), dst: (nz, ny, nx) contiguous device
+    tensors, both complex128 or both complex64.  Asynchronous on `stream`
+    (default: the current torch stream)."""
+    import torch
+    if xy.dtype != dst.dtype or xy.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError("xy and dst must both be complex128 or both complex64")
+    if xy.dim() != 2 or dst.dim() != 3 or tuple(dst.shape[1:]) != tuple(xy.shape):
+        raise ValueError("xy is (ny, nx) and dst (nz, ny, nx)")
+    if not (xy.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("tensors must be contiguous")
+    prec = SSCN_C128 if xy.dtype == torch.complex128 else SSCN_C64
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().sscn_extend_z(ctypes.c_void_p(xy.data_ptr()), xy.shape[1], xy.shape[0],
+                               ctypes.c_void_p(dst.data_ptr()), dst.shape[0], float(hz), float(d_z), prec,
+                               ctypes.c_void_p(st.cuda_stream)))
 
 
 class Solver:

@@ -1426,6 +1426,23 @@ __global__ __launch_bounds__(256) void k_embed(const typename Vec<R>::T *__restr
     }
 }
 
+// Product state of the 3D form of Eq. (fun): dst[k][j][i] = xy[j][i] c g_k
+// with g_k = exp(-z_k^2 / (2 d_z^2)), z_k = z0 + k hz, c given.
+template <class R>
+__global__ __launch_bounds__(256) void k_extend_z(const typename Vec<R>::T *__restrict__ xy, int nx, int ny,
+                                                  typename Vec<R>::T *__restrict__ dst, int nz, double z0,
+                                                  double hz, double dz, double c)
+{
+    const int64_t nxy = (int64_t)nx * ny, n = nxy * nz;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int k = (int)(e / nxy);
+        const double t = (z0 + k * hz) / dz;
+        const double f = c * exp(-0.5 * t * t);
+        const Cx<R> v = ld<R>(xy, e - k * nxy);
+        st<R>(dst, e, Cx<R>{R((double)v.re * f), R((double)v.im * f)});
+    }
+}
+
 template <class R>
 __global__ __launch_bounds__(256) void k_zero_walls(typename Vec<R>::T *psi, StepArgs a)
 {

@@ -1556,6 +1556,40 @@ int sscn_embed_state(const void *src, int nx_src, int ny_src, int nz_src, void *
     return 0;
 }
 
+int sscn_extend_z(const void *xy, int nx, int ny, void *dst, int nz, double hz, double d_z, int precision,
+                  void *stream)
+{
+    if (!xy || !dst || nx < 2 || ny < 2 || nz < 2)
+        return fail(SSCN_EINVAL, "bad extend_z arguments");
+    if (!(hz > 0.0) || !(d_z > 0.0) || !std::isfinite(hz) || !std::isfinite(d_z))
+        return fail(SSCN_EINVAL, "hz and d_z must be positive and finite");
+    if (precision != SSCN_C128 && precision != SSCN_C64)
+        return fail(SSCN_EINVAL, "precision must be SSCN_C128 or SSCN_C64");
+    const size_t es = precision == SSCN_C128 ? 16 : 8;
+    const char *s0 = (const char *)xy, *s1 = s0 + (size_t)nx * ny * es;
+    const char *d0 = (const char *)dst, *d1 = d0 + (size_t)nx * ny * nz * es;
+    if (s0 < d1 && d0 < s1)
+        return fail(SSCN_EINVAL, "xy and dst overlap");
+    // z_k = -nz hz / 2 + k hz; the Gaussian normalised over the interior
+    // points k = 1 .. nz - 1 (the wall k = 0 is zeroed by the caller)
+    const double z0 = -0.5 * nz * hz;
+    double sum = 0.0;
+    for (int k = 1; k < nz; ++k) {
+        const double t = (z0 + k * hz) / d_z;
+        sum += std::exp(-t * t);
+    }
+    const double c = 1.0 / std::sqrt(hz * sum);
+    const int nb = red_blocks((int64_t)nx * ny * nz);
+    if (precision == SSCN_C128)
+        hipLaunchKernelGGL((k_extend_z<double>), dim3(nb), dim3(256), 0, (hipStream_t)stream,
+                           (const V<double> *)xy, nx, ny, (V<double> *)dst, nz, z0, hz, d_z, c);
+    else
+        hipLaunchKernelGGL((k_extend_z<float>), dim3(nb), dim3(256), 0, (hipStream_t)stream,
+                           (const V<float> *)xy, nx, ny, (V<float> *)dst, nz, z0, hz, d_z, c);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
 int sscn_get_state(sscn_handle *h, void *host_psi)
 {
     if (!h || !host_psi)

@@ -318,6 +318,79 @@ def evaluate(net_params, plist, seeds, dt=2e-3, max_steps=2000000, tol=1e-8, pla
         rows=rows)
 
 
+def tf_instance_3d(omega, g2d, nu, lam, nz, hz, n=N_GRID, dt=2e-3, precision=0):
+    """3D parameters whose x-y grid is the Thomas-Fermi-scaled grid of the 2D
+    instance (Omega, g2d, nu): trap lam in z, nz points of spacing hz, and the
+    3D nonlinearity g2d sqrt(2 pi / lam) of the quasi-2D reduction of Sec. 2
+    (g_2D = g_3D sqrt(lam / (2 pi)))."""
+    p = tf_instance(omega, g2d, nu, n=n, dt=dt, precision=precision)
+    return dict(p, dim=3, nz=nz, hz=hz, lam=lam, g=g2d * math.sqrt(2.0 * math.pi / lam))
+
+
+def evaluate_3d(net_params, plist, seeds, lam=100.0, nz=16, hz=0.05, dt=2e-3, max_steps=1000000, tol=1e-8,
+                log=print, chans=CHANS, bott=BOTT):
+    """The learned start in 3D: the 2D network's state for (Omega, g_2D, nu),
+    normalised on its grid, times the normalised Gaussian of width
+    1 / sqrt(lam) in z (the product form of Eq. (fun), sscn_extend_z), against
+    Eq. (fun) itself; each instance alone on its 3D handle, to the same
+    criterion."""
+    import torch
+    import workloads as W
+    from . import Solver, extend_z
+    n, d_z = N_GRID, 1.0 / math.sqrt(lam)
+    chk = max(2, int(round(0.1 / dt)))
+    rows = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    starts = propose(net_params, plist, chans, bott)
+    b2 = Batch([tf_instance(*p, n=n, dt=dt) for p in plist])
+    for k in range(len(plist)):
+        nn.f32_to_psi(starts[k], nn.OUT_CH, n * n, 1.0, b2.psi[k])
+        b2.set_state_device(k)  # walls zeroed, normalised on the 2D grid
+    torch.cuda.synchronize()
+    t_inf = time.perf_counter() - t0
+    for k, (om, g, nu) in enumerate(plist):
+        p3 = tf_instance_3d(om, g, nu, lam, nz, hz, n=n, dt=dt)
+        rec = dict(omega=om, g_2d=g, g_3d=p3["g"], nu=nu)
+        for tag in ("one_vortex", "learned"):
+            s = Solver(p3)
+            log(f"[evaluate_3d] {k + 1}/{len(plist)} {tag} start: converging")
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if tag == "one_vortex":
+                s.init_state(1, W.phase_field(seeds[k], n, n), 1.0, d_z)
+            else:
+                extend_z(b2.psi[k], s.psi, hz, d_z)
+                s.set_state_device()
+            steps, ok = s.converge(max_steps, check_every=chk, tol=tol)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t1
+            o = s.observables()
+            rec.update({f"steps_{tag}": steps if ok else -1, f"wall_{tag}_s": round(wall, 3),
+                        f"mu_{tag}": o["mu"], f"vortices_{tag}": s.vortex_count()})
+            s.close()
+        rows.append(rec)
+        log(f"[evaluate_3d] {k + 1}/{len(plist)} Omega={om:.3f} g2D={g:.0f}: Eq. (fun) "
+            f"{rec['steps_one_vortex']} steps {rec['wall_one_vortex_s']} s {rec['vortices_one_vortex']} vortices; "
+            f"learned {rec['steps_learned']} steps {rec['wall_learned_s']} s {rec['vortices_learned']} vortices")
+    b2.close()
+    s0 = np.array([r["steps_one_vortex"] for r in rows])
+    s1 = np.array([r["steps_learned"] for r in rows])
+    both = (s0 > 0) & (s1 > 0)
+    w0 = sum(r["wall_one_vortex_s"] for r in rows)
+    w1 = sum(r["wall_learned_s"] for r in rows) + t_inf
+    return dict(instances=len(plist), lam=lam, nz=nz, hz=hz, dt=dt, tol=tol, grid=n,
+                inference_and_setup_s=round(t_inf, 3), wall_one_vortex_s=round(w0, 3), wall_learned_s=round(w1, 3),
+                wall_speedup=round(w0 / w1, 3),
+                converged_one_vortex=int((s0 > 0).sum()), converged_learned=int((s1 > 0).sum()),
+                both_converged=int(both.sum()),
+                total_steps_both_converged_one_vortex=int(s0[both].sum()),
+                total_steps_both_converged_learned=int(s1[both].sum()),
+                learned_fewer_steps=int((s1[both] < s0[both]).sum()),
+                same_vortex_count=int(sum(1 for r in rows if r["vortices_one_vortex"] == r["vortices_learned"])),
+                rows=rows)
+
+
 def phase_distance(a, b):
     """min over phi of |a/|a| - e^{i phi} b/|b||: sqrt(2 - 2 |<a, b>|) for
     unit vectors (0 = the same state up to a global phase, sqrt 2 =
@@ -361,6 +434,11 @@ def main(argv=None):
     ap.add_argument("--plain", action="store_true",
                     help="also run every evaluation instance alone from Eq. (fun)")
     ap.add_argument("--no-eval", action="store_true", help="generate and train only")
+    ap.add_argument("--eval-3d", type=int, default=0,
+                    help="with --weights: evaluate this many 3D instances (product start) instead")
+    ap.add_argument("--lam", type=float, default=100.0, help="3D: trap frequency in z")
+    ap.add_argument("--nz", type=int, default=16, help="3D: stored z points")
+    ap.add_argument("--hz", type=float, default=0.05, help="3D: z spacing")
     a = ap.parse_args(argv)
     import torch
 
@@ -391,6 +469,16 @@ def main(argv=None):
             save_params(a.save_weights, params)
         del X, T, net
     if a.no_eval:
+        if a.out:
+            with open(a.out, "w") as f:
+                json.dump(res, f, indent=1)
+        return
+    if a.eval_3d:
+        pl3 = draw(a.eval_3d, a.seed + 2)
+        sd3 = [a.seed * 10 + 6000000 + k if a.phase_seed < 0 else a.phase_seed for k in range(a.eval_3d)]
+        res["evaluate_3d"] = evaluate_3d(params, pl3, sd3, lam=a.lam, nz=a.nz, hz=a.hz, dt=a.dt,
+                                         max_steps=a.eval_steps, log=log)
+        log(json.dumps({k: v for k, v in res["evaluate_3d"].items() if k != "rows"}))
         if a.out:
             with open(a.out, "w") as f:
                 json.dump(res, f, indent=1)

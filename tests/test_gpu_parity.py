@@ -520,6 +520,44 @@ def test_embed_state_matches_oracle(P, prec, src_shape, dst_shape):
         P.embed_state(src, bad)
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("shape", [(37, 29, 11), (64, 64, 32)])
+def test_extend_z_matches_oracle(P, prec, shape):
+    """The 3D product start (a 2D field times the normalised z Gaussian of
+    Eq. (fun)) against the oracle; the extended oracle initial state, walls
+    zeroed by the handle, steps like the handle's own 3D initial state."""
+    import torch
+    nx, ny, nz = shape
+    announce(f"extend_z {shape} prec={prec}")
+    rng = np.random.default_rng(nx + ny + nz)
+    a = rng.standard_normal((ny, nx)) + 1j * rng.standard_normal((ny, nx))
+    dt = torch.complex128 if prec == 0 else torch.complex64
+    xy = torch.tensor(a).to(dt).cuda()
+    dst = torch.full((nz, ny, nx), 7.0 + 7.0j, dtype=dt, device="cuda")
+    hz, d_z = 0.17, 0.6
+    P.extend_z(xy, dst, hz, d_z)
+    ref = O.extend_z(xy.cpu().numpy(), nz, hz, d_z)
+    assert rel(dst.cpu().numpy(), ref) <= (1e-15 if prec == 0 else 1e-7)
+    with pytest.raises(P.SSCNError):
+        P.extend_z(xy, dst, 0.0, d_z)
+    # through a handle: the extended 2D Eq. (fun) state equals the 3D one
+    cfg = dict(dim=3, nx=nx, ny=ny, nz=nz, hx=0.3, hy=0.3, hz=hz, gamma=1.0, nu=1.0, lam=1.0 / d_z ** 2, g=20.0,
+               omega=0.4, dt=2e-3, mode=0, precision=prec)
+    s = P.Solver(cfg)
+    s2 = P.Solver(dict(cfg, dim=2, nz=1))
+    ph = W.phase_field(3, ny, nx)
+    s2.init_state(1, ph, 1.0)
+    P.extend_z(s2.psi, s.psi, hz, d_z)
+    s.set_state_device()
+    s.step(5)
+    s3 = P.Solver(cfg)
+    s3.init_state(1, ph, 1.0, d_z)
+    s3.step(5)
+    assert rel(s.get_state(), s3.get_state()) <= (1e-13 if prec == 0 else 2e-6)
+    for x in (s, s2, s3):
+        x.close()
+
+
 @pytest.mark.parametrize("dim,prec", [(2, 0), (2, 1), (3, 0), (3, 1)])
 def test_density_profiles_match_oracle(P, dim, prec):
     """Every density output of sscn_density against the oracle's definition

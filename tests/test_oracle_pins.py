@@ -528,3 +528,28 @@ def test_density_profiles_closed_forms():
     assert np.allclose(O.density(p3, psi3, "z"), fz ** 2, atol=1e-12)
     assert np.allclose(O.density(p3, psi3, "xy"), np.abs(psi) ** 2, atol=1e-12)
     assert np.allclose(O.density(p3, psi3, "x"), np.sqrt(gam / np.pi) * np.exp(-gam * x ** 2), atol=1e-12)
+
+
+def test_extend_z_gives_the_3d_form_of_eq_fun():
+    """The 3D initial state of Eq. (fun) is the 2D one times a Gaussian in z
+    (Sec. 2): extending the oracle's normalised 2D state along z and zeroing
+    the wall plane reproduces the oracle's own 3D initial state (built by its
+    C code from Eq. (fun) directly), normalised."""
+    import workloads as W
+    n, nz, h, hz, lam = 20, 14, 0.3, 0.15, 4.0
+    ph = W.phase_field(5, n, n)
+    p2 = O.make_params(dim=2, nx=n, ny=n, hx=h, hy=h, g=10.0, omega=0.5)
+    p3 = O.make_params(dim=3, nx=n, ny=n, nz=nz, hx=h, hy=h, hz=hz, lam=lam, g=10.0, omega=0.5)
+    d_z = 1.0 / np.sqrt(lam)
+    for kind in (0, 1):
+        xy = O.init_state(p2, kind=kind, phase=ph, d_xy=1.0)
+        ext = O.extend_z(xy, nz, hz, d_z)
+        ext[0] = 0
+        ref = O.init_state(p3, kind=kind, phase=ph, d_xy=1.0, d_z=d_z)
+        assert np.linalg.norm(ext - ref) <= 1e-13 * np.linalg.norm(ref)
+        assert abs(h * h * hz * np.sum(np.abs(ext) ** 2) - 1.0) <= 1e-14
+    # the Gaussian's width: ratio of planes k and k' is exp(-(z_k^2 - z_k'^2) / (2 d_z^2))
+    ext = O.extend_z(np.ones((3, 3)), nz, hz, d_z)
+    z = -0.5 * nz * hz + np.arange(nz) * hz
+    assert ext[3, 1, 1].real / ext[7, 1, 1].real == pytest.approx(np.exp(-(z[3] ** 2 - z[7] ** 2) / (2 * d_z ** 2)),
+                                                                  rel=1e-14)
