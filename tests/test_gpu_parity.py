@@ -228,6 +228,35 @@ def test_real_time_norm_conserved(P):
     s.close()
 
 
+def test_real_time_energy_excursion_is_first_order_in_dt(P):
+    """Real time on the full 512^2 workload from a partly relaxed state: the
+    norm stays at 1 to rounding and the largest excursion of the
+    full-functional energy over 2 time units halves with dt (the splitting
+    is first order; the continuum dynamics conserve E)."""
+    announce("real-time energy excursion, 512^2")
+    cfg = W.CONFIGS["c2"]
+    s = P.Solver(W.solver_params(cfg))
+    s.init_state(1, W.phase_field(13, cfg["ny"], cfg["nx"]), 1.0)
+    s.step(4000)
+    psi0 = s.get_state()
+    s.close()
+    dev = []
+    for dt in (cfg["dt"], cfg["dt"] / 2):
+        r = P.Solver(W.solver_params(cfg, mode=1, dt=dt))
+        r.set_state(psi0)
+        o0 = r.observables()
+        mx, k = 0.0, int(round(0.05 / dt))
+        for _ in range(40):
+            r.step(k)
+            o = r.observables()
+            mx = max(mx, abs(o["energy_full"] - o0["energy_full"]))
+            assert abs(o["norm"] - o0["norm"]) <= 1e-12
+        dev.append(mx)
+        r.close()
+    assert dev[0] < 1e-3 * abs(o0["energy_full"])
+    assert 1.8 <= dev[0] / dev[1] <= 2.4, dev
+
+
 def test_observables_and_vortex_count_match_oracle(P):
     announce("observables / vortex count")
     cfg = dict(dim=2, nx=128, ny=128, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu=1.2,
