@@ -6,9 +6,14 @@ Muruganandam, Adhikari, Balaz, "C and Fortran OpenMP programs for rotating
 Bose-Einstein condensates").  It shares no code with the GPU library and is
 used only by the tests, the smoke check and the benchmark's CPU baseline.
 
-The arithmetic lives in ``sscn_oracle.c``; this module only marshals numpy
-arrays through ctypes.  Arrays are complex128 with shape (ny, nx) in 2D and
-(nz, ny, nx) in 3D (x fastest), index 0 of every axis being the wall.
+The solver's arithmetic (the step, the observables, the vortex count, the
+initial state) lives in ``sscn_oracle.c``, marshalled here through ctypes.
+Four plain numpy definitions live in this module: ``embed`` (continuation
+start), ``extend_z`` (3D product start), ``functional_fourth_order`` and
+``density``.  Each function is pinned in tests/test_oracle_pins.py against
+what the paper and the mathematics fix; none is parity unpinned.  Arrays are
+complex128 with shape (ny, nx) in 2D and (nz, ny, nx) in 3D (x fastest),
+index 0 of every axis being the wall.
 """
 import ctypes
 import os
