@@ -47,3 +47,23 @@ def test_omega_c_bisection_finds_a_synthetic_threshold(monkeypatch):
             assert a <= true_oc(g, s) <= b and b - a == pytest.approx(0.8 / 2 ** 8)
         mean = sum(true_oc(g, s) for s in (13, 14, 15)) / 3
         assert abs(r["omega_c"] - mean) <= 0.8 / 2 ** 9 + 1e-12
+
+
+def test_count_map_builds_the_full_grid(monkeypatch):
+    seen = []
+
+    def fake_run(specs, **_):
+        seen.extend(specs)
+        return [{"g": s["g"], "omega": s["omega"], "kind": s["kind"], "seed": s["seed"], "n": s["nx"]}
+                for s in specs]
+
+    monkeypatch.setattr(M, "run_instances", fake_run)
+    recs = M.count_map([50.0, 800.0], [0.3, 0.7], kinds=(1, 0), seeds=(13, None), h=0.1, dt=1e-3)
+    assert len(recs) == len(seen) == 2 * 2 * 2 * 2
+    combos = {(s["g"], s["omega"], s["kind"], s["seed"]) for s in seen}
+    assert len(combos) == 16
+    for s in seen:
+        assert s["dim"] == 2 and s["nx"] == s["ny"] == M.grid_side(s["g"], s["omega"], 0.1)
+        assert s["hx"] == s["hy"] == 0.1 and s["dt"] == 1e-3 and s["mode"] == 0
+    # a larger condensate gets a larger grid
+    assert max(s["nx"] for s in seen if s["g"] == 800.0) >= max(s["nx"] for s in seen if s["g"] == 50.0)
