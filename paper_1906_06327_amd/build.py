@@ -1,15 +1,24 @@
-"""Build the HIP library libsscn.so for gfx950 (in-tree)."""
+"""Build the HIP library libsscn.so for gfx950 (in-tree).
+
+Each translation unit is compiled to an object in its own hipcc process (in
+parallel), then the objects are linked into the shared library."""
 import os
 import subprocess
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", "sscn_lib.hip"), os.path.join(HERE, "csrc", "sscn_nn.hip")]
+CSRC = os.path.join(HERE, "csrc")
+# (source, extra defines): the kernel launchers are compiled once per part
+# (1 sweeps, 2 fused 2D step, 3 batched sweeps) and precision
+UNITS = [(os.path.join(CSRC, "sscn_lib.hip"), []), (os.path.join(CSRC, "sscn_nn.hip"), [])] + [
+    (os.path.join(CSRC, "sscn_kernels.hip"), [f"-DSSCN_PART={part}", f"-DSSCN_REAL_T={real}"])
+    for part in (2, 1, 3) for real in ("double", "float")]
 LIB = os.path.join(HERE, "libsscn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # packed FP32 instructions (v_pk_*_f32) stay off: some of their forms have
     # produced wrong results without any error on gfx950 parts
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -19,10 +28,22 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + ["-o", LIB + ".tmp"] + SRCS
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
+    with tempfile.TemporaryDirectory(prefix="sscn_build_") as tmp:
+        objs, procs = [], []
+        for n, (src, defs) in enumerate(UNITS):
+            obj = os.path.join(tmp, f"{n}_{os.path.basename(src)}.o")
+            cmd = [HIPCC] + FLAGS + defs + ["-c", "-o", obj, src]
+            if verbose:
+                print(" ".join(cmd), flush=True)
+            procs.append((cmd, subprocess.Popen(cmd)))
+            objs.append(obj)
+        for cmd, pr in procs:
+            if pr.wait() != 0:
+                raise subprocess.CalledProcessError(pr.returncode, cmd)
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

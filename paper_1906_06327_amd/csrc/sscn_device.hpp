@@ -731,7 +731,7 @@ __global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, t
 
 // s - 1 of the pending rescale, s = 1/sqrt(dV sum of the npart norm
 // partials), summed in fixed order by one block.
-__global__ __launch_bounds__(256) void k_norm_scale(const double *partials, int npart, double dV, double *out)
+static __global__ __launch_bounds__(256) void k_norm_scale(const double *partials, int npart, double dV, double *out)
 {
     __shared__ double red[8];
     const double tot = block_sum_partials(partials, npart, red);
@@ -1584,7 +1584,7 @@ __global__ __launch_bounds__(256) void k_observables(const typename Vec<R>::T *p
 
 // Fixed-order final reduction of nblk rows of nval partials: values with
 // maxmask bit set take the max, the others the sum.  One 256-thread block.
-__global__ __launch_bounds__(256) void k_reduce_final(const double *partials, int nblk, int nval, unsigned maxmask,
+static __global__ __launch_bounds__(256) void k_reduce_final(const double *partials, int nblk, int nval, unsigned maxmask,
                                                       double *out)
 {
     __shared__ double red[8];
@@ -1764,7 +1764,7 @@ __global__ __launch_bounds__(256) void k_batch_obs(const Inst2D *__restrict__ in
 // for instances not listed), then the convergence bookkeeping: mu of the
 // real-part form, hits counts consecutive checks with |mu - mu_prev| < tol,
 // and an instance is flagged converged (conv[k] = step) at two hits.
-__global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const int *__restrict__ obase,
+static __global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const int *__restrict__ obase,
                                                          const int *__restrict__ ocount,
                                                          const double *__restrict__ opart, double *__restrict__ sums,
                                                          double *__restrict__ mu_prev, int *__restrict__ hits,
@@ -1815,7 +1815,7 @@ __global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const int *_
 // partials[I.ypoff + tile].
 
 // s - 1 of the pending rescale of each listed instance, from its partials.
-__global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__restrict__ insts, const int *__restrict__ klist,
+static __global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__restrict__ insts, const int *__restrict__ klist,
                                                      const int *__restrict__ nk, const double *__restrict__ partials,
                                                      double *__restrict__ scale)
 {

@@ -1,0 +1,199 @@
+// Host-side definitions shared by the library's translation units: tuning
+// constants, the solver and batch handles, the window-size dispatch and the
+// kernel launchers.  The launchers are templates defined in sscn_kernels.hip,
+// which is compiled once per (part, precision) so that the many window-size
+// instantiations of the sweep and fused-step kernels build in parallel.
+#pragma once
+
+#include "sscn.h"
+#include "sscn_device.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <vector>
+
+using namespace sscn;
+
+namespace sscn {
+
+constexpr int kSeg = 8;             // outputs per thread segment (all axes)
+constexpr int kGraphSteps = 64;     // steps per captured graph
+constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
+#ifndef SSCN_TILE_R
+#define SSCN_TILE_R 32
+#endif
+#ifndef SSCN_TILE_C
+#define SSCN_TILE_C 32
+#endif
+#ifndef SSCN_TILE_NT
+#define SSCN_TILE_NT 256
+#endif
+constexpr int kTileR = SSCN_TILE_R;   // fused 2D step: output tile rows (y)
+constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
+constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
+constexpr size_t kXLdsCap = 64 * 1024;
+
+// Supported window sizes (template instantiations).
+const int kWindows[] = {4, 6, 8, 10, 12, 13, 14, 16, 20, 24, 32};
+
+}  // namespace sscn
+
+struct sscn_handle {
+    sscn_params p;
+    void *psi = nullptr;    // caller-owned state
+    void *work = nullptr;   // second state-sized buffer (strided sweeps)
+    void *ws = nullptr;     // exact-path workspace
+    hipStream_t stream = nullptr;
+    hipStream_t cap = nullptr;
+    int64_t npts = 0;
+    size_t esize = 0;
+    StepArgs args{};
+    int W[3] = {0, 0, 0};   // window per axis; 0 = exact whole-line path
+    bool exact = false;
+    int xL = 1;             // lines per block of the x-sweep
+    int xLmax = 1;          // largest admissible xL
+    size_t xlds = 0;
+    int nemit = 0;          // partials written by the last sweep
+    double *partials = nullptr;  // norm partials between steps
+    double *obs_part = nullptr;  // observables / vortex partials
+    double *obs_buf = nullptr;   // finished reductions (device)
+    double *phase = nullptr;
+    void *tab[3] = {nullptr, nullptr, nullptr};  // per-axis pivot tables
+    int ygrid[3] = {0, 0, 0};  // strided-sweep logical grids (gx, gy, gz)
+    int zgrid[2] = {0, 0};
+    bool pending = false;   // partials hold the norm of an unnormalised state
+    int64_t steps = 0;
+    // fused 2D step (one launch per step over a work list of tiles)
+    int plan = SSCN_PLAN_AUTO;   // requested plan
+    int active_plan = SSCN_PLAN_SWEEPS;
+    bool fused_ok = false;
+    Inst2D *d_inst = nullptr;
+    Inst2D inst_host{};     // the same descriptor, passed by value to the fused step
+    int2 *d_work = nullptr;
+    int *d_nwork = nullptr;
+    int ntiles = 0;
+    double *partials2 = nullptr;
+    int fparity = 0;        // buffer (0 = psi, 1 = work) holding the state
+    int pbuf = 0;           // partial buffer holding the pending norm
+    float tune_ms[3] = {0, 0, 0};
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+namespace sscn {
+
+template <class R> using V = typename Vec<R>::T;
+
+// Dispatch on the window size W (a template parameter of the sweeps).
+#define SSCN_W_SWITCH(Wv, CALL)                                                                             \
+    switch (Wv) {                                                                                            \
+    case 4: CALL(4); break;                                                                                  \
+    case 6: CALL(6); break;                                                                                  \
+    case 8: CALL(8); break;                                                                                  \
+    case 10: CALL(10); break;                                                                                \
+    case 12: CALL(12); break;                                                                                \
+    case 13: CALL(13); break;                                                                                \
+    case 14: CALL(14); break;                                                                                \
+    case 16: CALL(16); break;                                                                                \
+    case 20: CALL(20); break;                                                                                \
+    case 24: CALL(24); break;                                                                                \
+    default: CALL(32); break;                                                                                \
+    }
+
+inline unsigned round8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
+
+// The rescale of the pending norm (npart > 0 partials) is reduced once by
+// k_norm_scale into obs_buf[kScaleSlot], which every x-sweep block reads.
+constexpr int kScaleSlot = 48;
+
+#define SSCN_W_SWITCH_FUSED(R, Wv, CALL)                                                                   \
+    switch (Wv) {                                                                                            \
+    case 4: CALL(4); break;                                                                                  \
+    case 6: CALL(6); break;                                                                                  \
+    case 8: CALL(8); break;                                                                                  \
+    case 10: CALL(10); break;                                                                                \
+    case 12: CALL(12); break;                                                                                \
+    case 13: CALL(13); break;                                                                                \
+    case 14: CALL(14); break;                                                                                \
+    case 16: CALL(16); break;                                                                                \
+    default: CALL(20); break;                                                                                \
+    }
+
+// Launch geometry of one fused 2D step: a work list of (instance, tile)
+// over the descriptors inst, or (one != NULL) a single instance whose
+// descriptor goes by value with the tiles as work items.
+struct FusedLaunch {
+    const Inst2D *inst;
+    const int2 *work;
+    const int *nwork;
+    int grid;
+    int W;
+    const Inst2D *one;
+};
+
+}  // namespace sscn
+
+struct sscn_batch {
+    int n = 0, precision = 0, mode = 0, W = 0;
+    hipStream_t stream = nullptr, cap = nullptr;
+    std::vector<sscn_params> p;
+    std::vector<StepArgs> args;
+    std::vector<void *> psi, work, tabx, taby;
+    std::vector<int> ntiles, nchunk;
+    std::vector<char> active;
+    std::vector<long long> conv;
+    std::vector<Inst2D> hinst;
+    Inst2D *d_inst = nullptr;
+    int2 *d_work = nullptr, *d_fwork = nullptr, *d_owork = nullptr;
+    int *d_nwork = nullptr, *d_nf = nullptr, *d_no = nullptr, *d_obase = nullptr, *d_ocount = nullptr;
+    int total_tiles = 0, total_chunks = 0;
+    int grid_tiles = 0, grid_chunks = 0;  // list lengths at the last rebuild
+    double *part[2] = {nullptr, nullptr};
+    double *opart = nullptr, *d_sums = nullptr, *d_mu_prev = nullptr;
+    int *d_hits = nullptr;
+    long long *d_conv = nullptr;
+    double *phase = nullptr;
+    int fparity = 0, pbuf = 0;
+    bool pending = false;
+    int64_t steps = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int graph_k = 0;
+    // sweep plan: x line blocks, y tiles, per-instance rescale
+    int plan = SSCN_PLAN_AUTO, active_plan = SSCN_PLAN_FUSED;
+    bool sweeps_ok = true;
+    bool xshort = true;  // every instance has nx * L <= 2048: 8 staged points per x-sweep thread
+    std::vector<int> xitems, yitems;
+    int total_x = 0, total_y = 0, grid_x = 0, grid_y = 0, grid_k = 0;
+    size_t xlds = 0;
+    int2 *d_xwork = nullptr, *d_ywork = nullptr;
+    int *d_nx = nullptr, *d_ny = nullptr, *d_klist = nullptr, *d_nk = nullptr;
+    double *ypart = nullptr, *d_scale = nullptr;
+    float tune_ms[3] = {0, 0, 0};
+};
+
+namespace sscn {
+
+// Kernel launchers (sscn_kernels.hip), explicitly instantiated for R = double
+// and float.
+// x-sweep with H1 and the pending rescale (npart > 0 partials of the last
+// step's norm; reduce = false reuses the s - 1 the last reducing launch left).
+template <class R, bool RT>
+void launch_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce = true);
+// y- and z-sweeps; EMIT: write the norm partials of the outputs.
+template <class R, bool EMIT>
+void launch_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st);
+template <class R, bool EMIT>
+void launch_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st);
+// One fused 2D step over a work list (or one instance).
+template <class R, bool RT>
+void launch_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st);
+// Raise the dynamic-LDS limit of the fused-step kernels for window W.
+template <class R>
+hipError_t allow_fused_lds_all(int W);
+// One step of the batched sweep plan for every listed instance.
+template <class R>
+void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k);
+
+}  // namespace sscn

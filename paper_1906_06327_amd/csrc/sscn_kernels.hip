@@ -1,0 +1,212 @@
+// Kernel launchers of the solver, compiled once per (part, precision):
+// SSCN_PART 1 = the x-, y- and z-sweeps, 2 = the fused 2D step, 3 = the
+// batched sweeps; SSCN_REAL_T = double or float.  Each compilation
+// explicitly instantiates its part's launchers (declared in sscn_host.hpp)
+// for one precision.
+#include "sscn_host.hpp"
+
+#if !defined(SSCN_PART) || !defined(SSCN_REAL_T)
+#error "compile with -DSSCN_PART=1|2|3 -DSSCN_REAL_T=double|float"
+#endif
+
+namespace sscn {
+
+#if SSCN_PART == 1
+
+template <class R, int W, bool RT>
+void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce)
+{
+    const int nlines = h->p.ny * (h->p.dim == 3 ? h->p.nz : 1);
+    const int blocks = (nlines + h->xL - 1) / h->xL;
+    double *sm1 = nullptr;
+    if (!RT && npart > 0) {
+        sm1 = h->obs_buf + kScaleSlot;
+        if (reduce)
+            hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, st, h->partials, npart, h->args.dV, sm1);
+    }
+    if ((int64_t)h->p.nx * h->xL <= 256 * 8)
+        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, 8>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
+                           (V<R> *)dst, h->args, h->xL, (const double *)sm1, (const Cx<R> *)h->tab[0]);
+    else
+        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, kXLoad>), dim3(blocks), dim3(256), h->xlds, st,
+                           (const V<R> *)src, (V<R> *)dst, h->args, h->xL, (const double *)sm1,
+                           (const Cx<R> *)h->tab[0]);
+}
+
+template <class R, bool RT>
+void launch_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce)
+{
+#define SSCN_CALL_X(Wc) go_x<R, Wc, RT>(h, src, dst, npart, st, reduce)
+    SSCN_W_SWITCH(h->W[0], SSCN_CALL_X)
+#undef SSCN_CALL_X
+}
+
+template <class R, int W, bool EMIT>
+void go_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+    const int *g = h->ygrid;
+    hipLaunchKernelGGL((k_ysweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1] * g[2])), dim3(kYLines, kSegBlock), 0,
+                       st, (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1], g[2],
+                       (const Cx<R> *)h->tab[1]);
+}
+
+template <class R, bool EMIT>
+void launch_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+#define SSCN_CALL_Y(Wc) go_y<R, Wc, EMIT>(h, src, dst, st)
+    SSCN_W_SWITCH(h->W[1], SSCN_CALL_Y)
+#undef SSCN_CALL_Y
+}
+
+template <class R, int W, bool EMIT>
+void go_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+    const int *g = h->zgrid;
+    hipLaunchKernelGGL((k_zsweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1])), dim3(kYLines, kSegBlock), 0, st,
+                       (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1],
+                       (const Cx<R> *)h->tab[2]);
+}
+
+template <class R, bool EMIT>
+void launch_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
+{
+#define SSCN_CALL_Z(Wc) go_z<R, Wc, EMIT>(h, src, dst, st)
+    SSCN_W_SWITCH(h->W[2], SSCN_CALL_Z)
+#undef SSCN_CALL_Z
+}
+
+template void launch_x<SSCN_REAL_T, false>(const sscn_handle *, const void *, void *, int, hipStream_t, bool);
+template void launch_x<SSCN_REAL_T, true>(const sscn_handle *, const void *, void *, int, hipStream_t, bool);
+template void launch_y<SSCN_REAL_T, false>(const sscn_handle *, const void *, void *, hipStream_t);
+template void launch_y<SSCN_REAL_T, true>(const sscn_handle *, const void *, void *, hipStream_t);
+template void launch_z<SSCN_REAL_T, false>(const sscn_handle *, const void *, void *, hipStream_t);
+template void launch_z<SSCN_REAL_T, true>(const sscn_handle *, const void *, void *, hipStream_t);
+
+#elif SSCN_PART == 2
+
+template <class R, int W, bool RT>
+void go_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
+{
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
+    if (f.one)  // one block per tile, the grid rounded up to the 8 XCDs (see k_step2d)
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>), dim3(round8(f.grid)),
+                           dim3(kTileNT),
+                           lds, st, f.inst, f.work, f.nwork, *f.one, parity, pin, pout, use_pin);
+    else
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>), dim3(f.grid), dim3(kTileNT),
+                           lds, st, f.inst, f.work, f.nwork, Inst2D{}, parity, pin, pout, use_pin);
+}
+
+template <class R, bool RT>
+void launch_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
+{
+#define SSCN_CALL_F(Wc) go_fused<R, Wc, RT>(f, parity, pin, pout, use_pin, st)
+    if constexpr (std::is_same<R, float>::value) {
+        if (f.W > 20) {
+            if (f.W <= 24)
+                go_fused<R, 24, RT>(f, parity, pin, pout, use_pin, st);
+            else
+                go_fused<R, 32, RT>(f, parity, pin, pout, use_pin, st);
+            return;
+        }
+    }
+    SSCN_W_SWITCH_FUSED(R, f.W, SSCN_CALL_F)
+#undef SSCN_CALL_F
+}
+
+template <class R, int W, bool RT>
+hipError_t allow_fused_lds()
+{
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
+    hipError_t e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>,
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return e;
+}
+
+template <class R>
+hipError_t allow_fused_lds_all(int W)
+{
+    hipError_t e = hipSuccess;
+#define SSCN_ALLOW(Wc)                                         \
+    do {                                                       \
+        e = allow_fused_lds<R, Wc, false>();                   \
+        if (e == hipSuccess)                                   \
+            e = allow_fused_lds<R, Wc, true>();                \
+    } while (0)
+    if constexpr (std::is_same<R, float>::value) {
+        if (W > 20) {
+            if (W <= 24)
+                SSCN_ALLOW(24);
+            else
+                SSCN_ALLOW(32);
+            return e;
+        }
+    }
+    SSCN_W_SWITCH_FUSED(R, W, SSCN_ALLOW)
+#undef SSCN_ALLOW
+    return e;
+}
+
+template void launch_fused<SSCN_REAL_T, false>(const FusedLaunch &, int, const double *, double *, int, hipStream_t);
+template void launch_fused<SSCN_REAL_T, true>(const FusedLaunch &, int, const double *, double *, int, hipStream_t);
+template hipError_t allow_fused_lds_all<SSCN_REAL_T>(int);
+
+#elif SSCN_PART == 3
+
+template <class R, int W, bool RT>
+void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
+{
+    if (b->xshort)
+        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
+                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
+    else
+        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
+                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
+}
+
+template <class R, int W, bool EMIT>
+void go_batch_y(const sscn_batch *b, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(std::max(grid, 1)), dim3(kYLines, kSegBlock), 0, st, b->d_inst,
+                       b->d_ywork, b->d_ny, b->ypart);
+}
+
+// One step of the sweep plan for every listed instance (state in buf[0]).
+template <class R>
+void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k)
+{
+    const bool imag = b->mode == SSCN_IMAG;
+    const int sc = (imag && b->pending) ? 1 : 0;
+    if (sc)
+        hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
+                           b->d_nk, b->ypart, b->d_scale);
+#define SSCN_CALL_BX(Wc)                                 \
+    do {                                                 \
+        if (imag)                                        \
+            go_batch_x<R, Wc, false>(b, grid_x, sc, st); \
+        else                                             \
+            go_batch_x<R, Wc, true>(b, grid_x, 0, st);   \
+    } while (0)
+    SSCN_W_SWITCH(b->W, SSCN_CALL_BX);
+#undef SSCN_CALL_BX
+#define SSCN_CALL_BY(Wc)                             \
+    do {                                             \
+        if (imag)                                    \
+            go_batch_y<R, Wc, true>(b, grid_y, st);  \
+        else                                         \
+            go_batch_y<R, Wc, false>(b, grid_y, st); \
+    } while (0)
+    SSCN_W_SWITCH(b->W, SSCN_CALL_BY);
+#undef SSCN_CALL_BY
+    if (imag)
+        b->pending = true;
+}
+
+template void batch_sweep_step<SSCN_REAL_T>(sscn_batch *, hipStream_t, int, int, int);
+
+#endif
+
+}  // namespace sscn

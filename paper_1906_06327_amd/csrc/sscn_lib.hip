@@ -1,8 +1,7 @@
 // Host side of the SSCN C ABI (include/sscn.h): parameter validation, the
 // per-axis Crank-Nicolson coefficients, window selection, kernel dispatch,
 // step sequencing with HIP graphs, observables and vortex counting.
-#include "sscn.h"
-#include "sscn_device.hpp"
+#include "sscn_host.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -37,72 +36,6 @@ int fail(int code, const std::string &msg)
         if (e_ != hipSuccess)                                                            \
             return fail(SSCN_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
     } while (0)
-
-constexpr int kSeg = 8;             // outputs per thread segment (all axes)
-constexpr int kGraphSteps = 64;     // steps per captured graph
-constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
-#ifndef SSCN_TILE_R
-#define SSCN_TILE_R 32
-#endif
-#ifndef SSCN_TILE_C
-#define SSCN_TILE_C 32
-#endif
-#ifndef SSCN_TILE_NT
-#define SSCN_TILE_NT 256
-#endif
-constexpr int kTileR = SSCN_TILE_R;   // fused 2D step: output tile rows (y)
-constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
-constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
-constexpr size_t kXLdsCap = 64 * 1024;
-
-// Supported window sizes (template instantiations).
-const int kWindows[] = {4, 6, 8, 10, 12, 13, 14, 16, 20, 24, 32};
-
-}  // namespace
-
-struct sscn_handle {
-    sscn_params p;
-    void *psi = nullptr;    // caller-owned state
-    void *work = nullptr;   // second state-sized buffer (strided sweeps)
-    void *ws = nullptr;     // exact-path workspace
-    hipStream_t stream = nullptr;
-    hipStream_t cap = nullptr;
-    int64_t npts = 0;
-    size_t esize = 0;
-    StepArgs args{};
-    int W[3] = {0, 0, 0};   // window per axis; 0 = exact whole-line path
-    bool exact = false;
-    int xL = 1;             // lines per block of the x-sweep
-    int xLmax = 1;          // largest admissible xL
-    size_t xlds = 0;
-    int nemit = 0;          // partials written by the last sweep
-    double *partials = nullptr;  // norm partials between steps
-    double *obs_part = nullptr;  // observables / vortex partials
-    double *obs_buf = nullptr;   // finished reductions (device)
-    double *phase = nullptr;
-    void *tab[3] = {nullptr, nullptr, nullptr};  // per-axis pivot tables
-    int ygrid[3] = {0, 0, 0};  // strided-sweep logical grids (gx, gy, gz)
-    int zgrid[2] = {0, 0};
-    bool pending = false;   // partials hold the norm of an unnormalised state
-    int64_t steps = 0;
-    // fused 2D step (one launch per step over a work list of tiles)
-    int plan = SSCN_PLAN_AUTO;   // requested plan
-    int active_plan = SSCN_PLAN_SWEEPS;
-    bool fused_ok = false;
-    Inst2D *d_inst = nullptr;
-    Inst2D inst_host{};     // the same descriptor, passed by value to the fused step
-    int2 *d_work = nullptr;
-    int *d_nwork = nullptr;
-    int ntiles = 0;
-    double *partials2 = nullptr;
-    int fparity = 0;        // buffer (0 = psi, 1 = work) holding the state
-    int pbuf = 0;           // partial buffer holding the pending norm
-    float tune_ms[3] = {0, 0, 0};
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
-};
-
-namespace {
 
 int64_t npoints(const sscn_params &p)
 {
@@ -349,94 +282,8 @@ int build_tables(sscn_handle *h)
 int red_blocks(int64_t n) { return (int)std::min<int64_t>(kRedBlocks, std::max<int64_t>(1, (n + 255) / 256)); }
 
 // ---------------------------------------------------------------------------
-// Kernel dispatch.
-
-template <class R> using V = typename Vec<R>::T;
-
-// Dispatch on the window size W (a template parameter of the sweeps).
-#define SSCN_W_SWITCH(Wv, CALL)                                                                             \
-    switch (Wv) {                                                                                            \
-    case 4: CALL(4); break;                                                                                  \
-    case 6: CALL(6); break;                                                                                  \
-    case 8: CALL(8); break;                                                                                  \
-    case 10: CALL(10); break;                                                                                \
-    case 12: CALL(12); break;                                                                                \
-    case 13: CALL(13); break;                                                                                \
-    case 14: CALL(14); break;                                                                                \
-    case 16: CALL(16); break;                                                                                \
-    case 20: CALL(20); break;                                                                                \
-    case 24: CALL(24); break;                                                                                \
-    default: CALL(32); break;                                                                                \
-    }
-
-unsigned round8(int64_t n) { return (unsigned)((n + 7) / 8 * 8); }
-
-// The rescale of the pending norm (npart > 0 partials) is reduced once by
-// k_norm_scale into obs_buf[kScaleSlot], which every x-sweep block reads.
-constexpr int kScaleSlot = 48;
-
-template <class R, int W, bool RT>
-void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce)
-{
-    const int nlines = h->p.ny * (h->p.dim == 3 ? h->p.nz : 1);
-    const int blocks = (nlines + h->xL - 1) / h->xL;
-    double *sm1 = nullptr;
-    if (!RT && npart > 0) {
-        sm1 = h->obs_buf + kScaleSlot;
-        if (reduce)
-            hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, st, h->partials, npart, h->args.dV, sm1);
-    }
-    if ((int64_t)h->p.nx * h->xL <= 256 * 8)
-        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, 8>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
-                           (V<R> *)dst, h->args, h->xL, (const double *)sm1, (const Cx<R> *)h->tab[0]);
-    else
-        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, kXLoad>), dim3(blocks), dim3(256), h->xlds, st,
-                           (const V<R> *)src, (V<R> *)dst, h->args, h->xL, (const double *)sm1,
-                           (const Cx<R> *)h->tab[0]);
-}
-
-// reduce = false reuses the s - 1 that the last reducing launch left
-template <class R, bool RT>
-void launch_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce = true)
-{
-#define SSCN_CALL_X(Wc) go_x<R, Wc, RT>(h, src, dst, npart, st, reduce)
-    SSCN_W_SWITCH(h->W[0], SSCN_CALL_X)
-#undef SSCN_CALL_X
-}
-
-template <class R, int W, bool EMIT>
-void go_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
-{
-    const int *g = h->ygrid;
-    hipLaunchKernelGGL((k_ysweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1] * g[2])), dim3(kYLines, kSegBlock), 0,
-                       st, (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1], g[2],
-                       (const Cx<R> *)h->tab[1]);
-}
-
-template <class R, bool EMIT>
-void launch_y(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
-{
-#define SSCN_CALL_Y(Wc) go_y<R, Wc, EMIT>(h, src, dst, st)
-    SSCN_W_SWITCH(h->W[1], SSCN_CALL_Y)
-#undef SSCN_CALL_Y
-}
-
-template <class R, int W, bool EMIT>
-void go_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
-{
-    const int *g = h->zgrid;
-    hipLaunchKernelGGL((k_zsweep<R, kSeg, W, EMIT>), dim3(round8((int64_t)g[0] * g[1])), dim3(kYLines, kSegBlock), 0, st,
-                       (const V<R> *)src, (V<R> *)dst, h->args, h->partials, g[0], g[1],
-                       (const Cx<R> *)h->tab[2]);
-}
-
-template <class R, bool EMIT>
-void launch_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
-{
-#define SSCN_CALL_Z(Wc) go_z<R, Wc, EMIT>(h, src, dst, st)
-    SSCN_W_SWITCH(h->W[2], SSCN_CALL_Z)
-#undef SSCN_CALL_Z
-}
+// Kernel dispatch (the sweep and fused-step launchers are in
+// sscn_kernels.hip).
 
 template <class R>
 void launch_rescale(sscn_handle *h, hipStream_t st)
@@ -452,96 +299,7 @@ void launch_norm(sscn_handle *h, hipStream_t st)
                        h->partials);
 }
 
-#define SSCN_W_SWITCH_FUSED(R, Wv, CALL)                                                                   \
-    switch (Wv) {                                                                                            \
-    case 4: CALL(4); break;                                                                                  \
-    case 6: CALL(6); break;                                                                                  \
-    case 8: CALL(8); break;                                                                                  \
-    case 10: CALL(10); break;                                                                                \
-    case 12: CALL(12); break;                                                                                \
-    case 13: CALL(13); break;                                                                                \
-    case 14: CALL(14); break;                                                                                \
-    case 16: CALL(16); break;                                                                                \
-    default: CALL(20); break;                                                                                \
-    }
 
-// Launch geometry of one fused 2D step: a work list of (instance, tile)
-// over the descriptors inst, or (one != NULL) a single instance whose
-// descriptor goes by value with the tiles as work items.
-struct FusedLaunch {
-    const Inst2D *inst;
-    const int2 *work;
-    const int *nwork;
-    int grid;
-    int W;
-    const Inst2D *one;
-};
-
-template <class R, int W, bool RT>
-void go_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
-{
-    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
-    if (f.one)  // one block per tile, the grid rounded up to the 8 XCDs (see k_step2d)
-        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>), dim3(round8(f.grid)),
-                           dim3(kTileNT),
-                           lds, st, f.inst, f.work, f.nwork, *f.one, parity, pin, pout, use_pin);
-    else
-        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>), dim3(f.grid), dim3(kTileNT),
-                           lds, st, f.inst, f.work, f.nwork, Inst2D{}, parity, pin, pout, use_pin);
-}
-
-template <class R, bool RT>
-void launch_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
-{
-#define SSCN_CALL_F(Wc) go_fused<R, Wc, RT>(f, parity, pin, pout, use_pin, st)
-    if constexpr (std::is_same<R, float>::value) {
-        if (f.W > 20) {
-            if (f.W <= 24)
-                go_fused<R, 24, RT>(f, parity, pin, pout, use_pin, st);
-            else
-                go_fused<R, 32, RT>(f, parity, pin, pout, use_pin, st);
-            return;
-        }
-    }
-    SSCN_W_SWITCH_FUSED(R, f.W, SSCN_CALL_F)
-#undef SSCN_CALL_F
-}
-
-template <class R, int W, bool RT>
-hipError_t allow_fused_lds()
-{
-    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kTileC>();
-    hipError_t e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, true>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>,
-                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    return e;
-}
-
-template <class R>
-hipError_t allow_fused_lds_all(int W)
-{
-    hipError_t e = hipSuccess;
-#define SSCN_ALLOW(Wc)                                         \
-    do {                                                       \
-        e = allow_fused_lds<R, Wc, false>();                   \
-        if (e == hipSuccess)                                   \
-            e = allow_fused_lds<R, Wc, true>();                \
-    } while (0)
-    if constexpr (std::is_same<R, float>::value) {
-        if (W > 20) {
-            if (W <= 24)
-                SSCN_ALLOW(24);
-            else
-                SSCN_ALLOW(32);
-            return e;
-        }
-    }
-    SSCN_W_SWITCH_FUSED(R, W, SSCN_ALLOW)
-#undef SSCN_ALLOW
-    return e;
-}
 
 // n fused steps (state ping-pongs between psi and work), ending with the
 // state in psi, normalised in imaginary time.
@@ -973,48 +731,6 @@ void free_buffers(sscn_handle *h)
 
 // ---------------------------------------------------------------------------
 // Batched 2D instances (one fused launch per step over all their tiles).
-}  // namespace
-
-struct sscn_batch {
-    int n = 0, precision = 0, mode = 0, W = 0;
-    hipStream_t stream = nullptr, cap = nullptr;
-    std::vector<sscn_params> p;
-    std::vector<StepArgs> args;
-    std::vector<void *> psi, work, tabx, taby;
-    std::vector<int> ntiles, nchunk;
-    std::vector<char> active;
-    std::vector<long long> conv;
-    std::vector<Inst2D> hinst;
-    Inst2D *d_inst = nullptr;
-    int2 *d_work = nullptr, *d_fwork = nullptr, *d_owork = nullptr;
-    int *d_nwork = nullptr, *d_nf = nullptr, *d_no = nullptr, *d_obase = nullptr, *d_ocount = nullptr;
-    int total_tiles = 0, total_chunks = 0;
-    int grid_tiles = 0, grid_chunks = 0;  // list lengths at the last rebuild
-    double *part[2] = {nullptr, nullptr};
-    double *opart = nullptr, *d_sums = nullptr, *d_mu_prev = nullptr;
-    int *d_hits = nullptr;
-    long long *d_conv = nullptr;
-    double *phase = nullptr;
-    int fparity = 0, pbuf = 0;
-    bool pending = false;
-    int64_t steps = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int graph_k = 0;
-    // sweep plan: x line blocks, y tiles, per-instance rescale
-    int plan = SSCN_PLAN_AUTO, active_plan = SSCN_PLAN_FUSED;
-    bool sweeps_ok = true;
-    bool xshort = true;  // every instance has nx * L <= 2048: 8 staged points per x-sweep thread
-    std::vector<int> xitems, yitems;
-    int total_x = 0, total_y = 0, grid_x = 0, grid_y = 0, grid_k = 0;
-    size_t xlds = 0;
-    int2 *d_xwork = nullptr, *d_ywork = nullptr;
-    int *d_nx = nullptr, *d_ny = nullptr, *d_klist = nullptr, *d_nk = nullptr;
-    double *ypart = nullptr, *d_scale = nullptr;
-    float tune_ms[3] = {0, 0, 0};
-};
-
-namespace {
 
 // Upload the work lists of the active instances: tiles (largest instances
 // first), finish chunks and observable chunks with each instance's range.
@@ -1082,54 +798,6 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
     return 0;
 }
 
-template <class R, int W, bool RT>
-void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
-{
-    if (b->xshort)
-        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
-    else
-        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
-}
-
-template <class R, int W, bool EMIT>
-void go_batch_y(const sscn_batch *b, int grid, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(std::max(grid, 1)), dim3(kYLines, kSegBlock), 0, st, b->d_inst,
-                       b->d_ywork, b->d_ny, b->ypart);
-}
-
-// One step of the sweep plan for every listed instance (state in buf[0]).
-template <class R>
-void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k)
-{
-    const bool imag = b->mode == SSCN_IMAG;
-    const int sc = (imag && b->pending) ? 1 : 0;
-    if (sc)
-        hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
-                           b->d_nk, b->ypart, b->d_scale);
-#define SSCN_CALL_BX(Wc)                                 \
-    do {                                                 \
-        if (imag)                                        \
-            go_batch_x<R, Wc, false>(b, grid_x, sc, st); \
-        else                                             \
-            go_batch_x<R, Wc, true>(b, grid_x, 0, st);   \
-    } while (0)
-    SSCN_W_SWITCH(b->W, SSCN_CALL_BX);
-#undef SSCN_CALL_BX
-#define SSCN_CALL_BY(Wc)                             \
-    do {                                             \
-        if (imag)                                    \
-            go_batch_y<R, Wc, true>(b, grid_y, st);  \
-        else                                         \
-            go_batch_y<R, Wc, false>(b, grid_y, st); \
-    } while (0)
-    SSCN_W_SWITCH(b->W, SSCN_CALL_BY);
-#undef SSCN_CALL_BY
-    if (imag)
-        b->pending = true;
-}
 
 // nsteps fused steps of every listed instance, then the finish pass that
 // leaves each state normalised (imaginary time) in its caller buffer.
