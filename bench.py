@@ -1,31 +1,37 @@
 """Benchmark of the SSCN hot path on one MI355X.
 
-Workload (default): the 2D rotating-GP problem on a 512 x 512 grid on
-[-12.8, 12.8)^2, gamma = 1, nu = 1.05, g = 1000, Omega = 0.9, dt = 5e-4,
-imaginary time with renormalisation every step, complex128 arithmetic,
-starting from the one-vortex random-phase state of Eq. (fun) (seed 13).
-One step = H1 + x-sweep + y-sweep + FP64 norm (the rescale is folded into
-the next step).  `value` = grid-point updates per second over exactly
---steps timed steps, inputs resident on the GPU.
+Workload (default, the headline): the batched 2D imaginary-time sweep of 64
+instances of uneven size and parameters (parameter seed 2019): grid sides
+from {128, 192, 256, 384, 512} at h = 0.1 (each side holding 2 x 1.4
+Thomas-Fermi radii), Omega ~ U[0.5, 0.95], g ~ logU[100, 3000],
+nu ~ U[1.0, 1.2], gamma = 1, dt = 1e-3, complex128 arithmetic, renormalised
+every step, each instance starting from the one-vortex random-phase state of
+Eq. (fun) (phase seed 13 + n).  One step advances every instance by one full
+SSCN step (H1 + x-sweep + y-sweep + FP64 norm; the rescale is folded into
+the next step).  `value` = grid-point updates per second, sum over the
+instances of their points times --steps, over the wall time of exactly
+--steps timed steps; the inputs are resident on the GPU and the steps are
+replayed from HIP graphs captured before the timed region.
 
 Also reported on the same JSON line:
-  roofline      the dominant sweep kernel: algorithmic bytes (one read and
-                one write of the state) / its average duration measured with
-                HIP events on the stream it runs on, against 8 TB/s HBM;
-  variants      the same workload with complex64 sweeps, in real time from
-                the start, and in real time from the timed run's state
-                (10 000 steps, norm and energy drift); the 3D 256 x 256 x 64
-                complex64 workload (then 1 000 real-time steps); the
-                64-instance batch;
-  converge      time to a converged lattice on the 128^2 workload (mu
-                changing by < 1e-8 over 0.1 time units at two consecutive
-                checks with an unchanged vortex count);
-  cpu_baseline  the FP64 CPU oracle on a bounded sample of the default
-                workload, on the host cores (and on one thread).
-The roofline object also carries the bandwidth of a plain 1 GiB device copy
-(copy_GBps), the achievable figure next to the 8 TB/s specification, and the
-converge object the oracle's time for the same lattice, extrapolated from
-its measured rate.
+  roofline      the dominant kernel of the batched step: algorithmic bytes
+                per launch (one read and one write of every instance's state
+                per sweep: 2 x 16 B per point) / its average duration,
+                measured with HIP events around every kernel of consecutive
+                steps on the stream it runs on, against 8 TB/s HBM; traffic =
+                counter bytes per launch from the committed rocprofv3 summary
+                (null when the kernel sources differ from the ones profiled);
+  variants      the 512^2 workload (complex128 and complex64, imaginary and
+                real time), the 3D 256 x 256 x 64 workload (complex64 and
+                complex128), each followed by real-time steps with norm and
+                energy drift;
+  converge      time to converged lattices: the 128^2 workload (complex128;
+                complex64 then complex128) and, per instance, the 64-instance
+                batch (mu changing by < 1e-8 over 0.1 time units at two
+                consecutive checks with an unchanged vortex count);
+  cpu_baseline  the FP64 CPU oracle on a bounded sample of the headline
+                workload (consecutive steps of each instance in turn) on the
+                host cores.
 """
 import argparse
 import hashlib
@@ -42,7 +48,11 @@ import numpy as np  # noqa: E402
 import workloads as W  # noqa: E402
 
 PEAK_HBM_GBS = 8000.0
-KERNEL_SOURCES = ("paper_1906_06327_amd/csrc/sscn_device.hpp", "paper_1906_06327_amd/csrc/sscn_lib.hip")
+KERNEL_SOURCES = ("paper_1906_06327_amd/csrc/sscn_device.hpp", "paper_1906_06327_amd/csrc/sscn_host.hpp",
+                  "paper_1906_06327_amd/csrc/sscn_kernels.hip", "paper_1906_06327_amd/csrc/sscn_lib.hip")
+HEADLINE = ("2D rotating GP, 64 instances (parameter seed 2019) with grid sides from "
+            "{128,192,256,384,512} at h=0.1, Omega~U[0.5,0.95], g~logU[100,3000], nu~U[1.0,1.2], "
+            "gamma=1, dt=1e-3, imaginary time, renormalised each step, one batched launch per kernel")
 
 
 def source_hash():
@@ -79,17 +89,35 @@ def measured_traffic(key):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20000)
-    ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--precision", choices=("c128", "c64"), default="c128")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip variants and convergence")
+    ap.add_argument("--no-extras", action="store_true", help="skip variants and convergence runs")
+    ap.add_argument("--no-batch-converge", action="store_true",
+                    help="skip the 64-instance convergence run (the longest extra)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--profile-sample", action="store_true",
                     help="run a short fixed sample for hardware-counter passes and exit: a "
-                         "256 MiB device copy (counter calibration), 50 steps of the 512^2 "
-                         "complex128 workload, 20 steps of the 3D complex64 workload")
+                         "256 MiB device copy (counter calibration), 20 steps of the 64-instance "
+                         "complex128 batch, 50 steps of the 512^2 complex128 workload, 20 steps "
+                         "of the 3D complex64 workload")
     return ap.parse_args()
+
+
+def sync(torch):
+    torch.cuda.synchronize()
+
+
+def make_batch(P, cfgs):
+    b = P.Batch(cfgs)
+    for k, c in enumerate(cfgs):
+        b.init_state(k, c.get("kind", 1), W.phase_field(c["seed"], c["ny"], c["nx"]), c.get("d_xy", 1.0))
+    return b
+
+
+def batch_cfgs(precision):
+    return [dict(c, precision=precision) for c in W.batch_instances()]
 
 
 def profile_sample(P, torch):
@@ -98,34 +126,104 @@ def profile_sample(P, torch):
     c = torch.empty_like(a)
     for _ in range(3):
         c.copy_(a)
-    torch.cuda.synchronize()
+    sync(torch)
     print("profile-sample: copy 256 MiB x3 done", flush=True)
+    del a, c
+    b = make_batch(P, batch_cfgs(0))
+    b.prepare_steps(20)
+    b.step(20)
+    sync(torch)
+    print(f"profile-sample: 64-instance batch, 20 steps, plan {b.info()['plan']}", flush=True)
+    b.close()
     for cfg, k in ((W.CONFIGS["c2"], 50), (W.CONFIGS["c3"], 20)):
         s = P.Solver(W.solver_params(cfg))
         s.init_state(1, W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"]), 1.0, cfg.get("d_z", 0.0))
         s.step(k)
-        torch.cuda.synchronize()
+        sync(torch)
         print(f"profile-sample: {cfg['nx']}x{cfg['ny']}x{cfg['nz']} {k} steps, "
               f"plan {s.solver_info()['plan']}", flush=True)
         s.close()
 
 
+def timed_batch(P, torch, cfgs, steps, warmup):
+    """The headline: warm up, capture the graphs of a `steps`-step call, then
+    time exactly `steps` steps (wall clock between two synchronisations, and
+    HIP events on the batch's stream around the same region)."""
+    b = make_batch(P, cfgs)
+    b.prepare_steps(warmup)
+    b.step(warmup)
+    b.prepare_steps(steps)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sync(torch)
+    t0 = time.perf_counter()
+    e0.record()
+    b.step(steps)
+    e1.record()
+    sync(torch)
+    dt = time.perf_counter() - t0
+    return b, dt, e0.elapsed_time(e1) / steps
+
+
+def batch_roofline(b, cfgs, nprof=20):
+    """Average duration of each kernel of the batched step, from HIP events
+    recorded around every kernel of nprof consecutive steps on the batch's
+    stream (sscn_batch_profile_step), and the algorithmic bandwidth of the
+    dominant one: one read and one write of every instance's state per sweep
+    (2 c bytes per point, c = complex size), i.e. 2 c sum(P) per sweep kernel
+    and 2 x 2 c sum(P) for the fused step (both sweeps in one launch)."""
+    prof = b.profile_step(nprof)
+    esize = 16 if cfgs[0]["precision"] == 0 else 8
+    pts = sum(c["nx"] * c["ny"] for c in cfgs)
+    prec = "c128" if esize == 16 else "c64"
+    if "fused" in prof:
+        names, per_launch, label = ("fused",), 2 * 2 * esize * pts, "batched fused 2D step (H1 + x + y)"
+        keys = {"fused": f"batch_fused2d_c4_{prec}"}
+    else:
+        names, per_launch = ("x", "y"), 2 * esize * pts
+        keys = {"x": f"batch_xsweep_c4_{prec}", "y": f"batch_ysweep_c4_{prec}"}
+    dom = max(names, key=lambda k: prof[k])
+    if "fused" not in prof:
+        label = {"x": "batched x-sweep (H1 + rescale + x-CN), k_batch_xsweep",
+                 "y": "batched y-sweep (y-CN + norm partials), k_batch_ysweep"}[dom]
+    gbs = per_launch / (prof[dom] * 1e-3) / 1e9
+    traffic = measured_traffic(keys[dom])
+    out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+           "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
+           "traffic_unit": "bytes per launch (counters)",
+           "traffic_over_algorithmic": round(traffic / per_launch, 3) if traffic else None,
+           "kernel": label, "bytes_per_launch": per_launch,
+           "kernel_ms": {k: round(v, 6) for k, v in prof.items()},
+           "timing": f"HIP events around every kernel of {nprof} consecutive steps"}
+    others = {}
+    for k in names:
+        if k != dom:
+            g = per_launch / (prof[k] * 1e-3) / 1e9
+            others[k] = {"achieved": round(g, 1), "frac": round(g / PEAK_HBM_GBS, 4),
+                         "traffic": measured_traffic(keys[k])}
+    if others:
+        out["other_kernels"] = others
+    return out
+
+
 def timed_steps(P, torch, cfg, steps, warmup, mode=0):
-    """Warm up, then time exactly `steps` steps: wall clock between two
-    synchronisations, and HIP events recorded on the solver's stream (the
-    current torch stream, which the solver launches on) around the same
-    region.  Returns (solver, wall seconds, event milliseconds per step)."""
+    """Warm up, capture the graphs of a `steps`-step call, then time exactly
+    `steps` steps: wall clock between two synchronisations, and HIP events
+    recorded on the solver's stream (the current torch stream, which the
+    solver launches on) around the same region.  Returns (solver, wall
+    seconds, event milliseconds per step)."""
     s = P.Solver(W.solver_params(cfg, mode=mode), stream=torch.cuda.current_stream())
     ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
     s.init_state(cfg.get("kind", 1), ph, cfg.get("d_xy", 1.0), cfg.get("d_z", 0.0))
+    s.prepare_steps(warmup)
     s.step(warmup)
+    s.prepare_steps(steps)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
+    sync(torch)
     t0 = time.perf_counter()
     e0.record()
     s.step(steps)
     e1.record()
-    torch.cuda.synchronize()
+    sync(torch)
     dt = time.perf_counter() - t0
     return s, dt, e0.elapsed_time(e1) / steps
 
@@ -137,80 +235,55 @@ def real_time_phase(P, torch, s, steps):
     splitting error."""
     o0 = s.observables()
     s.set_mode(P.SSCN_REAL)
-    s.step(64)  # the plan for real time is tuned on its first step
-    torch.cuda.synchronize()
+    s.prepare_steps(steps)
+    sync(torch)
     t0 = time.perf_counter()
     s.step(steps)
-    torch.cuda.synchronize()
+    sync(torch)
     dt = time.perf_counter() - t0
     o1 = s.observables()
-    return {"steps": steps + 64, "ms_per_step_timed": round(dt / steps * 1e3, 6),
+    return {"steps": steps, "ms_per_step_timed": round(dt / steps * 1e3, 6),
             "norm_drift": o1["norm"] - o0["norm"],
             "energy_full_rel_drift": (o1["energy_full"] - o0["energy_full"]) / abs(o0["energy_full"])}
 
 
-def kernel_roofline(s, cfg, step_ms, nlaunch=200, traffic_key=None):
-    """Average duration of the dominant kernel of a step and its algorithmic
-    bandwidth.  The fused 2D plan launches one kernel per step (plus one
-    final rescale per 64-step graph), so its duration is the event time of
-    the timed region per step, step_ms.  The sweep plans launch several;
-    each is timed over nlaunch back-to-back launches between two HIP events
-    on the solver's stream (sscn_profile_kernel).  Algorithmic bytes: 2*c
-    per point per axis sweep the kernel performs (one read and one write of
-    the state per sweep, complex size c), i.e. 2*c*P per sweep kernel and
-    2*d*c*P for the fused 2D step, which performs both sweeps of a step in
-    one launch."""
+def kernel_roofline(s, cfg, step_ms, nlaunch=200):
+    """Average duration of the dominant kernel of a single-instance step and
+    its algorithmic bandwidth.  The fused 2D plan launches one kernel per
+    step, so its duration is the event time of the timed region per step.
+    The sweep plans launch one kernel per axis; each is timed over nlaunch
+    back-to-back launches between two HIP events on the solver's stream
+    (sscn_profile_kernel).  Algorithmic bytes: 2 c per point per axis sweep
+    the kernel performs."""
     plan = s.solver_info()["plan"]
     dim = cfg["dim"]
     pts = cfg["nx"] * cfg["ny"] * (cfg["nz"] if dim == 3 else 1)
     esize = 16 if cfg.get("precision", 0) == 0 else 8
     if plan == 2:
-        names = ("fused",)
-        per_launch = 2 * dim * esize * pts
-    else:
-        names = ("x", "y", "z")[:dim]
-        per_launch = 2 * esize * pts
-    if plan == 2:
+        names, per_launch = ("fused",), 2 * dim * esize * pts
         ms = {"fused": step_ms}
     else:
+        names, per_launch = ("x", "y", "z")[:dim], 2 * esize * pts
         ms = {k: s.profile_kernel(w, nlaunch) for w, k in enumerate(names)}
     dom = max(names, key=lambda k: ms[k])
-    label = "fused 2D step (H1 + x + y)" if plan == 2 else f"{dom}-sweep"
     gbs = per_launch / (ms[dom] * 1e-3) / 1e9
-    kind = "fused2d" if plan == 2 else f"{dom}sweep"
-    traffic = measured_traffic(traffic_key) if traffic_key and traffic_key.startswith(kind) else None
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-            "frac": round(gbs / PEAK_HBM_GBS, 4), "traffic": traffic,
-            "traffic_unit": "bytes per launch (counters)",
-            "traffic_over_algorithmic": round(traffic / per_launch, 3) if traffic else None,
-            "kernel": label, "plan": {1: "sweeps", 2: "fused"}.get(plan, plan),
-            "x_lines_per_block": s.solver_info()["x_lines"],
-            "bytes_per_launch": per_launch, "kernel_ms": {k: round(v, 6) for k, v in ms.items()},
-            "timing": "events around the timed steps" if plan == 2 else "events around back-to-back launches",
-            "step_ms_events": round(step_ms, 6)}
+            "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "kernel": "fused 2D step (H1 + x + y)" if plan == 2 else f"{dom}-sweep",
+            "plan": {1: "sweeps", 2: "fused"}.get(plan, plan), "bytes_per_launch": per_launch,
+            "kernel_ms": {k: round(v, 6) for k, v in ms.items()},
+            "timing": "events around the timed steps" if plan == 2 else "events around back-to-back launches"}
 
 
-def batch_run(P, torch, steps=200):
-    """The 64-instance batch: updates/s of the batched step (the plan the
-    batch autotuner picks: batched sweeps or the fused step)."""
-    cfgs = W.batch_instances()
-    b = P.Batch(cfgs)
-    for k, c in enumerate(cfgs):
-        b.init_state(k, 1, W.phase_field(c["seed"], c["ny"], c["nx"]), 1.0)
-    b.step(20)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.step(steps)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    pts = sum(c["nx"] * c["ny"] for c in cfgs)
-    info = b.info()
-    b.close()
-    ups = pts * steps / dt
-    return {"instances": len(cfgs), "points": pts, "updates_per_s": round(ups, 1),
-            "ms_per_step": round(dt / steps * 1e3, 5),
-            "plan": {1: "batched sweeps", 2: "fused"}.get(info["plan"], info["plan"]), "window": info["window"],
-            "algorithmic_GBps": round(64 * ups / 1e9, 1), "frac_of_8TBps": round(64 * ups / 8e12, 4)}
+def single_variant(P, torch, cfg, steps, warmup, real_steps=0, mode=0):
+    s, dt, sm = timed_steps(P, torch, cfg, steps, warmup, mode=mode)
+    pts = cfg["nx"] * cfg["ny"] * (cfg["nz"] if cfg["dim"] == 3 else 1)
+    out = {"updates_per_s": round(pts * steps / dt, 1), "ms_per_step": round(dt / steps * 1e3, 6),
+           "steps": steps, "roofline": kernel_roofline(s, cfg, sm)}
+    if real_steps:
+        out["then_real_time"] = real_time_phase(P, torch, s, real_steps)
+    s.close()
+    return out
 
 
 def converge_run(P, torch, cfg, precision, max_steps=3000000):
@@ -220,11 +293,11 @@ def converge_run(P, torch, cfg, precision, max_steps=3000000):
     s = P.Solver(W.solver_params(cfg, precision=precision))
     ph = W.phase_field(cfg["seed"], cfg["ny"], cfg["nx"])
     chk = max(1, int(round(0.1 / cfg["dt"])))
-    torch.cuda.synchronize()
+    sync(torch)
     t0 = time.perf_counter()
     s.init_state(1, ph, 1.0)
     steps, ok = s.converge(max_steps, check_every=chk, tol=1e-8, switch_tol=3e-7)
-    torch.cuda.synchronize()
+    sync(torch)
     wall = time.perf_counter() - t0
     ob = s.observables()
     out = {"precision": "c128" if precision == 0 else "c64 bulk -> c128", "steps": steps,
@@ -232,6 +305,45 @@ def converge_run(P, torch, cfg, precision, max_steps=3000000):
            "vortices": s.vortex_count(), "fp32_steps": s.switch_step if precision == 1 else 0}
     s.close()
     return out
+
+
+def batch_converge(P, torch, cfgs, max_steps=2000000, chunk=20000):
+    """The 64 instances from Eq. (fun) to the convergence criterion, all in
+    one batch (sscn_batch_run, checks every 0.1 time units on the device,
+    converged instances leave the batch).  The run is driven in calls of
+    `chunk` steps, so that each instance's convergence is also timed (to the
+    end of the call in which it converged)."""
+    chk = max(2, int(round(0.1 / cfgs[0]["dt"])))
+    sync(torch)
+    t0 = time.perf_counter()
+    b = make_batch(P, cfgs)
+    conv = [-1] * len(cfgs)
+    when = [None] * len(cfgs)
+    done = 0
+    while done < max_steps and min(conv) < 0:
+        st = b.run(min(chunk, max_steps - done), check_every=chk, tol=1e-8)
+        done += min(chunk, max_steps - done)
+        now = time.perf_counter() - t0
+        for k, v in enumerate(st):
+            if v >= 0 and conv[k] < 0:
+                conv[k], when[k] = v, now
+    wall = time.perf_counter() - t0
+    counts = [b.vortex_count(k) for k in range(len(cfgs))]
+    obs = b.observables()
+    b.close()
+    ok = [k for k in range(len(cfgs)) if conv[k] >= 0]
+    pts = [c["nx"] * c["ny"] for c in cfgs]
+    st = sorted(conv[k] for k in ok)
+    tm = sorted(when[k] for k in ok)
+    return {"instances": len(cfgs), "converged": len(ok), "wall_s": round(wall, 3),
+            "max_steps": max_steps, "check_every": chk,
+            "steps_min_median_max": [st[0], st[len(st) // 2], st[-1]] if st else None,
+            "seconds_min_median_max": [round(tm[0], 3), round(tm[len(tm) // 2], 3), round(tm[-1], 3)] if tm else None,
+            "per_instance": [{"n": c["nx"], "omega": round(c["omega"], 4), "g": round(c["g"], 2),
+                              "nu": round(c["nu"], 4), "steps": conv[k],
+                              "seconds": None if when[k] is None else round(when[k], 3),
+                              "vortices": counts[k], "mu": obs[k]["mu"]} for k, c in enumerate(cfgs)],
+            "updates": int(sum(pts[k] * (conv[k] if conv[k] >= 0 else done) for k in range(len(cfgs))))}
 
 
 def _omp_threads(n):
@@ -261,20 +373,45 @@ def oracle_rate(cfg, seconds, chunk=25):
     return cfg["nx"] * cfg["ny"] * steps / dt, steps, dt
 
 
-def cpu_baseline(cfg, seconds):
-    """The FP64 oracle as it stands on the host cores, on a bounded sample
-    (consecutive steps of the same workload from the same initial state),
-    and the same on one thread."""
+def oracle_batch_rate(cfgs, seconds, steps_each=2):
+    """Updates/s of the FP64 oracle on the batch workload: rounds over the
+    instances, each advancing its own state by `steps_each` consecutive steps
+    (timed; the initial states are not), until about `seconds` of stepping.
+    Returns (rate, rounds, instances stepped in the last round, seconds)."""
+    import oracle as O
+    ps = [O.make_params(**W.solver_params(c)) for c in cfgs]
+    states = [None] * len(cfgs)
+    upd, spent, rounds, inst = 0, 0.0, 0, 0
+    while spent < seconds:
+        rounds += 1
+        for k, c in enumerate(cfgs):
+            if states[k] is None:
+                states[k] = O.init_state(ps[k], 1, W.phase_field(c["seed"], c["ny"], c["nx"]), 1.0)
+            t0 = time.perf_counter()
+            states[k] = O.step(ps[k], states[k], steps_each)
+            spent += time.perf_counter() - t0
+            upd += c["nx"] * c["ny"] * steps_each
+            inst = k + 1
+            if spent >= seconds:
+                break
+    return upd / spent, rounds, inst, spent
+
+
+def cpu_baseline(cfgs, seconds):
+    """The FP64 oracle as it stands on the host cores, on a bounded sample of
+    the headline workload (rounds over the 64 instances, two consecutive
+    steps of each per round)."""
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    rate, steps, dt = oracle_rate(cfg, seconds)
+    rate, rounds, inst, dt = oracle_batch_rate(cfgs, seconds)
     out = {"value": round(rate, 1), "unit": "updates/s", "cores": threads, "kind": "oracle",
-           "sample": f"{steps} consecutive imaginary-time steps of the 512x512 complex128 "
-                     f"workload ({dt:.1f} s), OpenMP over lines with {threads} threads"}
+           "sample": f"imaginary-time steps of the 64 batch instances (complex128), 2 consecutive steps of "
+                     f"each instance per round, {rounds} round(s), the last ending at instance {inst}; "
+                     f"{dt:.1f} s of stepping, OpenMP over lines with {threads} threads"}
     if _omp_threads(1):
-        r1, s1, d1 = oracle_rate(cfg, seconds / 2, chunk=5)
+        r1, rd1, i1, d1 = oracle_batch_rate(cfgs, seconds / 3)
         _omp_threads(threads)
         out["single_thread"] = {"value": round(r1, 1), "unit": "updates/s", "cores": 1,
-                                "sample": f"{s1} consecutive steps of the same workload ({d1:.1f} s)"}
+                                "sample": f"the same, {rd1} round(s) ending at instance {i1} ({d1:.1f} s)"}
     return out
 
 
@@ -285,13 +422,13 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     b = torch.empty_like(a)
     b.copy_(a)
-    torch.cuda.synchronize()
+    sync(torch)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
     for _ in range(reps):
         b.copy_(a)
     e1.record()
-    torch.cuda.synchronize()
+    sync(torch)
     gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
     del a, b
     torch.cuda.empty_cache()
@@ -302,64 +439,54 @@ def main():
     a = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus > 1 or world > 1:
-        print(f"bench.py measures one GPU only: this solver has no multi-GPU path "
-              f"(asked for --gpus {a.gpus}, WORLD_SIZE {world}).", flush=True)
+        print(f"bench.py measures one GPU only: this build runs on a single GPU and has no "
+              f"multi-GPU path (asked for --gpus {a.gpus}, WORLD_SIZE {world}).", flush=True)
         sys.exit(2)
     import torch
     import paper_1906_06327_amd as P
     P.lib()
-    cfg = dict(W.CONFIGS["c2"], precision=0 if a.precision == "c128" else 1)
     torch.cuda.set_device(0)
     if a.profile_sample:
         profile_sample(P, torch)
         return
 
-    s, dt, step_ms = timed_steps(P, torch, cfg, a.steps, a.warmup)
-    pts = cfg["nx"] * cfg["ny"]
+    prec = 0 if a.precision == "c128" else 1
+    cfgs = batch_cfgs(prec)
+    pts = sum(c["nx"] * c["ny"] for c in cfgs)
+    b, dt, step_ms = timed_batch(P, torch, cfgs, a.steps, a.warmup)
     value = pts * a.steps / dt
-    roof = kernel_roofline(s, cfg, step_ms, traffic_key=f"fused2d_512_{a.precision}")
-    rt_phase = None if a.no_extras else real_time_phase(P, torch, s, 10000)
-    s.close()
-    copy_gbs = copy_bandwidth(torch)
-    roof["copy_GBps"] = round(copy_gbs, 1)
-    roof["frac_of_copy"] = round(roof["achieved"] / copy_gbs, 4)
+    roof = batch_roofline(b, cfgs)
+    info = b.info()
+    b.close()
+    roof["copy_GBps"] = round(copy_bandwidth(torch), 1)
+    roof["frac_of_copy"] = round(roof["achieved"] / roof["copy_GBps"], 4)
+    sizes = {}
+    for c in cfgs:
+        sizes[c["nx"]] = sizes.get(c["nx"], 0) + 1
 
     out = {
         "metric": "grid-point updates/s per SSCN step (% HBM roofline) + time-to-converged lattice",
         "value": round(value, 1), "unit": "updates/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": round(dt / a.steps * 1e3, 6), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if a.precision == "c128" else "f32",
-        "data": "synthetic (one-vortex random-phase initial state, seed 13)",
-        "config": {"workload": "2D rotating GP, 512x512 on [-12.8,12.8)^2, gamma=1, nu=1.05, "
-                               "g=1000, Omega=0.9, dt=5e-4, imaginary time, renormalised each step",
-                   "grid": [cfg["nx"], cfg["ny"]], "precision": a.precision,
-                   "parallelism": "single GPU"},
+        "dtype": "f64" if prec == 0 else "f32",
+        "data": "synthetic (one-vortex random-phase initial states, phase seeds 13 + n)",
+        "config": {"workload": HEADLINE, "instances": len(cfgs), "points": pts,
+                   "grid_sides": {str(k): v for k, v in sorted(sizes.items())},
+                   "precision": a.precision, "plan": {1: "batched sweeps", 2: "batched fused step"}.get(
+                       info["plan"], info["plan"]), "window": info["window"],
+                   "step_ms_events": round(step_ms, 6), "parallelism": "single GPU"},
         "roofline": roof,
     }
     if not a.no_extras:
         variants = {}
-        c64 = dict(W.CONFIGS["c2"], precision=1)
-        s, dt, sm = timed_steps(P, torch, c64, 5000, 256)
-        variants["c2_complex64"] = {"updates_per_s": round(pts * 5000 / dt, 1),
-                                    "ms_per_step": round(dt / 5000 * 1e3, 6),
-                                    "roofline": kernel_roofline(s, c64, sm)}
-        s.close()
-        s, dt, _ = timed_steps(P, torch, W.CONFIGS["c2"], 5000, 256, mode=1)
-        variants["c2_real_time_complex128"] = {"updates_per_s": round(pts * 5000 / dt, 1),
-                                               "ms_per_step": round(dt / 5000 * 1e3, 6)}
-        s.close()
+        c2 = W.CONFIGS["c2"]
+        variants["c2_512_complex128"] = single_variant(P, torch, c2, 5120, 256, real_steps=10240)
+        variants["c2_512_complex64"] = single_variant(P, torch, dict(c2, precision=1), 5120, 256)
+        variants["c2_512_real_time_complex128"] = single_variant(P, torch, c2, 5120, 256, mode=1)
         c3 = W.CONFIGS["c3"]
-        s, dt, sm = timed_steps(P, torch, c3, 1000, 64)
-        p3 = c3["nx"] * c3["ny"] * c3["nz"]
-        variants["c3_3d_complex64"] = {"updates_per_s": round(p3 * 1000 / dt, 1),
-                                       "ms_per_step": round(dt / 1000 * 1e3, 6),
-                                       "roofline": kernel_roofline(s, c3, sm, 100,
-                                                                   traffic_key="xsweep_3d_256x256x64_c64")}
-        variants["c3_3d_complex64"]["then_real_time"] = real_time_phase(P, torch, s, 1000)
-        s.close()
-        variants["c2_then_real_time"] = rt_phase
-        variants["c4_batch_64_instances_complex128"] = batch_run(P, torch)
+        variants["c3_3d_complex64"] = single_variant(P, torch, c3, 1024, 64, real_steps=1024)
+        variants["c3_3d_complex128"] = single_variant(P, torch, dict(c3, precision=0), 512, 64, real_steps=512)
         out["variants"] = variants
         c1 = W.CONFIGS["c1"]
         conv = {"workload": "2D 128x128 on [-6.4,6.4)^2, g=100, Omega=0.6, dt=1e-3, one-vortex "
@@ -371,12 +498,14 @@ def main():
         if not a.no_cpu:
             # the oracle on the same lattice: its measured rate times the
             # GPU run's step count (a full oracle run would take minutes)
-            rate, steps, dt = oracle_rate(c1, 3.0)
+            rate, steps, dto = oracle_rate(c1, 3.0)
             conv["c128"]["oracle_extrapolated_s"] = round(conv["c128"]["steps"] * c1["nx"] * c1["ny"] / rate, 1)
-            conv["c128"]["oracle_sample"] = f"{steps} oracle steps in {dt:.1f} s on the host cores"
+            conv["c128"]["oracle_sample"] = f"{steps} oracle steps in {dto:.1f} s on the host cores"
+        if not a.no_batch_converge:
+            conv["batch_64_complex128"] = batch_converge(P, torch, batch_cfgs(0))
         out["converge"] = conv
     if not a.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(W.CONFIGS["c2"], a.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(cfgs, a.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

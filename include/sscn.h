@@ -110,8 +110,20 @@ int sscn_init_state(sscn_handle *h, int kind, const double *phase_host,
 
 /* Enqueue nsteps >= 0 SSCN steps (paper's NPAS loop body).  Asynchronous:
  * no host synchronisation.  In imaginary time the state left in psi after
- * the call is normalised. */
+ * the call is normalised.  A call of n >= 2 steps replays captured HIP
+ * graphs: n = q G + r with G = min(n, 64), q launches of the G-step graph,
+ * then an r-step graph (r >= 2) or one directly launched step; graphs are
+ * captured on first use and kept per handle (the four most recent step
+ * counts).  The first call of an SSCN_PLAN_AUTO handle also picks the plan
+ * (sscn_set_plan). */
 int sscn_step(sscn_handle *h, int64_t nsteps);
+
+/* Do, without advancing the state, the one-time work of a later
+ * sscn_step(h, nsteps): pick the plan (timed on a saved copy of the state,
+ * which is restored) and capture the graphs that call replays, so that its
+ * duration is the steps alone.  Synchronises the stream.  SSCN_EINVAL for a
+ * null handle or nsteps < 0. */
+int sscn_prepare_steps(sscn_handle *h, int64_t nsteps);
 
 /* Observables of the current state; synchronises the stream.  Returns
  * SSCN_ENONFINITE (and still fills *out) when any reduction is NaN/Inf.
@@ -281,17 +293,41 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
 int sscn_batch_init_state(sscn_batch *b, int k, int kind, const double *phase_host, double d_xy);
 
 /* Enqueue nsteps steps of every active instance; each state is left
- * normalised (imaginary time) in its buffer.  Asynchronous. */
+ * normalised (imaginary time) in its buffer.  Asynchronous.  A call of
+ * n >= 2 steps replays captured HIP graphs: n = q G + r with G = min(n, 256),
+ * q launches of the G-step graph, then an r-step graph (r >= 2) or one
+ * directly launched step (graphs captured on first use, the four most recent
+ * step counts kept).  The first stepping call of an SSCN_PLAN_AUTO batch also
+ * picks the plan (sscn_batch_set_plan). */
 int sscn_batch_step(sscn_batch *b, int64_t nsteps);
+
+/* The one-time work of a later sscn_batch_step(b, nsteps) without advancing
+ * the states: plan choice (timed on saved copies, restored) and graph
+ * capture.  Synchronises the stream.  SSCN_EINVAL for a null batch or
+ * nsteps < 0. */
+int sscn_batch_prepare_steps(sscn_batch *b, int64_t nsteps);
+
+/* Advance nsteps (1..100000) steps launched one by one (no graph), with a HIP
+ * event recorded on the batch's stream around every kernel, and return the
+ * average durations in milliseconds: sweep plan ms_out[0] the batched
+ * x-sweep (with H1 and the rescale), [1] the batched y-sweep, [2] the
+ * per-instance rescale kernel; fused plan ms_out[0] the fused step, [1] =
+ * [2] = 0; ms_out[3] a whole step (the finish pass at the end of the call is
+ * not timed).  For measurement: the kernels run in the order and on the
+ * data of ordinary steps.  Synchronises the stream. */
+int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out);
 
 /* Observables of all n instances into out[0..n-1] (out[k].step: the step at
  * which instance k converged, else the batch step count).  Synchronises. */
 int sscn_batch_observables(sscn_batch *b, sscn_obs *out);
 
-/* Imaginary-time run to convergence: replay check_every (rounded up to even)
- * steps, evaluate mu of every active instance on the device, and flag an
- * instance converged when |mu - mu_prev| < tol_dmu at two consecutive checks;
- * flagged instances leave the work list.  Stops when all have converged or
+/* Imaginary-time run to convergence with the criterion of sscn_converge,
+ * evaluated per instance on the device: replay check_every (rounded up to
+ * even) steps, compute mu (real-part form) of every active instance, and
+ * when |mu - mu_prev| < tol_dmu also its vortex count (density_frac 0.05,
+ * box 3, as sscn_vortex_count); an instance is converged at two consecutive
+ * checks with |mu - mu_prev| < tol_dmu and an unchanged vortex count.
+ * Converged instances leave the work list.  Stops when all have converged or
  * max_steps steps were taken.  steps_out[k] (may be NULL): the batch step
  * count at instance k's convergence, or -1.  Synchronises at every check. */
 int sscn_batch_run(sscn_batch *b, int64_t max_steps, int check_every, double tol_dmu, int64_t *steps_out);

@@ -21,10 +21,10 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
           -4: "SSCN_ENONFINITE", -5: "SSCN_EHIP", -6: "SSCN_ENOMEM"}
 
 # Every symbol include/sscn.h declares.
-EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_observables",
+EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_prepare_steps", "sscn_observables",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
-           "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step",
+           "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step", "sscn_batch_prepare_steps", "sscn_batch_profile_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
            "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state", "sscn_extend_z", "sscn_density",
@@ -69,6 +69,7 @@ def lib():
         L.sscn_init.argtypes = [ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
         L.sscn_init_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double]
         L.sscn_step.argtypes = [vp, i64]
+        L.sscn_prepare_steps.argtypes = [vp, i64]
         L.sscn_observables.argtypes = [vp, ctypes.POINTER(Obs)]
         L.sscn_set_state.argtypes = [vp, vp]
         L.sscn_set_state_device.argtypes = [vp]
@@ -87,6 +88,8 @@ def lib():
                                       ctypes.POINTER(vp)]
         L.sscn_batch_init_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_double]
         L.sscn_batch_step.argtypes = [vp, i64]
+        L.sscn_batch_prepare_steps.argtypes = [vp, i64]
+        L.sscn_batch_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
         L.sscn_batch_observables.argtypes = [vp, ctypes.POINTER(Obs)]
         L.sscn_batch_run.argtypes = [vp, i64, ctypes.c_int, ctypes.c_double, ctypes.POINTER(i64)]
         L.sscn_batch_reset.argtypes = [vp]
@@ -216,6 +219,10 @@ class Solver:
     def step(self, n=1):
         _check(lib().sscn_step(self._h, int(n)))
 
+    def prepare_steps(self, n):
+        """Plan choice and graph capture of a later step(n), without stepping."""
+        _check(lib().sscn_prepare_steps(self._h, int(n)))
+
     def observables(self, raise_nonfinite=True):
         o = Obs()
         code = lib().sscn_observables(self._h, ctypes.byref(o))
@@ -268,16 +275,20 @@ class Solver:
         if self.params.precision == SSCN_C64:
             new = torch.empty(self.shape, dtype=torch.complex128, device=self.psi.device)
         steps, ok, sw = ctypes.c_int64(), ctypes.c_int(), ctypes.c_int64()
-        _check(lib().sscn_converge(self._h, int(max_steps), int(check_every), float(tol),
-                                   float(switch_tol),
-                                   ctypes.c_void_p(new.data_ptr()) if new is not None else None,
-                                   ctypes.byref(steps), ctypes.byref(ok), ctypes.byref(sw)))
+        try:
+            _check(lib().sscn_converge(self._h, int(max_steps), int(check_every), float(tol),
+                                       float(switch_tol),
+                                       ctypes.c_void_p(new.data_ptr()) if new is not None else None,
+                                       ctypes.byref(steps), ctypes.byref(ok), ctypes.byref(sw)))
+        finally:
+            # the handle borrows `new` from the upcast on, even when a later
+            # call of the run failed: keep the tensor alive with it
+            p = Params()
+            if lib().sscn_get_params(self._h, ctypes.byref(p)) == 0:
+                if new is not None and p.precision == SSCN_C128:
+                    self.psi = new
+                self.params = p
         self.switch_step = int(sw.value)
-        p = Params()
-        _check(lib().sscn_get_params(self._h, ctypes.byref(p)))
-        if new is not None and p.precision == SSCN_C128:
-            self.psi = new
-        self.params = p
         return int(steps.value), bool(ok.value)
 
     def vortex_count(self, density_frac=0.05, box=3):
@@ -372,6 +383,20 @@ class Batch:
 
     def step(self, n=1):
         _check(lib().sscn_batch_step(self._h, int(n)))
+
+    def prepare_steps(self, n):
+        """Plan choice and graph capture of a later step(n), without stepping."""
+        _check(lib().sscn_batch_prepare_steps(self._h, int(n)))
+
+    def profile_step(self, n):
+        """Advance n steps launched one by one with HIP events around every
+        kernel; average ms of the x-sweep, y-sweep, rescale kernel (sweep
+        plan) or of the fused step, and of a whole step."""
+        ms = (ctypes.c_double * 4)()
+        _check(lib().sscn_batch_profile_step(self._h, int(n), ms))
+        if self.info()["plan"] == PLAN_SWEEPS:
+            return {"x": ms[0], "y": ms[1], "rescale": ms[2], "step": ms[3]}
+        return {"fused": ms[0], "step": ms[3]}
 
     def run(self, max_steps, check_every=100, tol=1e-8):
         out = (ctypes.c_int64 * self.n)()

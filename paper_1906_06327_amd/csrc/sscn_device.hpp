@@ -45,6 +45,14 @@ namespace sscn {
 // Largest number of state elements one thread of the x-sweep stages.
 constexpr int kXLoad = 16;
 
+// Waves per SIMD the bandwidth-bound sweep kernels are compiled for (the
+// register budget: 512 / kSweepWaves VGPRs per lane).
+#ifndef SSCN_SWEEP_WAVES
+#define SSCN_SWEEP_WAVES 1
+#endif
+constexpr int kSweepWaves = SSCN_SWEEP_WAVES;
+
+
 template <class R> struct Cx {
     R re, im;
 };
@@ -174,7 +182,9 @@ __device__ __forceinline__ Cx<R> csel(bool c, Cx<R> a, Cx<R> b)
 // with unknowns 1..n-1, by Thomas elimination with the fixed-point factors
 // (cst, rst) from row s-W on; then io[r] = v_{s+r} + 2 delta_{s+r} and
 // d_first = delta_s (both uncorrected for the wall; see above).
-// vals[r] = v_{s-W-1+r} (zero at the walls), loaded by the caller.
+// ld(r) returns v_{s-W-1+r}, r = 0..S+2W+1 (zero outside the unknowns
+// 1..n-1): the callers read the window straight from the values they staged
+// in LDS, so a window never sits in registers as a whole.
 //
 // In FP64 the solve is done in the Cayley form instead: (I + K) z = v and
 // psi' = 2 z - v, with z_first = z_s (uncorrected) in d_first.  It needs no
@@ -186,116 +196,126 @@ __device__ __forceinline__ Cx<R> csel(bool c, Cx<R> a, Cx<R> b)
 // yt and z = r* zt the recurrences are yt_u = v_u + alpha yt_{u-1} (alpha =
 // -A- r*) and zt_u = yt_u - c* zt_{u+1}, and r* multiplies only the S
 // outputs.  Rows of the window outside the unknowns 1..n-1 must see the
-// walls' zeros.  The right-hand side is the window value itself, which the
-// callers stage as zero outside the unknowns, so rows before the near wall
-// stay zero by themselves; rows beyond the far wall are zeroed in the back
-// substitution (their yt times 0), which starts from zero at the window's
-// end.  The mask is a product with 0 or 1, not a branch, so the window is
-// one basic block and each recurrence chain (two dependent FMAs per row)
-// overlaps the independent work.  The FP32 delta form does the same with
+// walls' zeros.  The right-hand side is the window value itself, which is
+// zero outside the unknowns, so rows before the near wall stay zero by
+// themselves; rows beyond the far wall are zeroed in the back substitution
+// (their yt times 0).  The mask is a product with 0 or 1, not a branch, so
+// the window is one basic block.  The FP32 delta form does the same with
 // ISSUE = true (the fused step, bound by instruction issue): scaled
 // unknowns, and the right-hand side and coupling of rows outside the
 // unknowns multiplied by 0, so their eliminated values are exactly zero.
-// With ISSUE = false (the bandwidth-bound sweeps, where register count
-// matters more) it keeps the plain recurrence with those rows skipped.
-template <class R, int S, int W, int ST = 0, bool ISSUE = false>
-__device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Cx<R> cst, Cx<R> rst,
-                                             const Cx<R> (&vals)[S + 2 * W + 2], Cx<R> (&io)[S], Cx<R> &d_first)
+// With ISSUE = false (the bandwidth-bound sweeps) it keeps the plain
+// recurrence with those rows skipped.
+//
+// Only the S eliminated values of the output rows are kept.  The back
+// substitution enters them with zt at the first row after them, which is the
+// sum over the W rows after the outputs of (-c*)^t times their eliminated
+// values (the back recurrence unrolled, the rows beyond the far wall masked):
+// the forward pass accumulates that sum as it goes, so the registers a
+// window needs do not grow with W.
+template <class R, int S, int W, int ST = 0, bool ISSUE = false, class Ld>
+__device__ __forceinline__ void window_solve(int s, int n, const LineCoef<R> &L, Cx<R> cst, Cx<R> rst, Ld ld,
+                                             Cx<R> (&io)[S], Cx<R> &d_first)
 {
     constexpr int NR = S + 2 * W;
     const Cx<R> zero = {R(0), R(0)};
     const Cx<R> ma = L.Am * rst;
     const Cx<R> alpha = {-ma.re, -ma.im};
+    const Cx<R> mc = {-cst.re, -cst.im};
     if constexpr (std::is_same<R, double>::value) {
-        Cx<R> ys[S + W];
-        Cx<R> yp = zero;
+        Cx<R> ym[S];
+        Cx<R> yp = zero, zs = zero, pw = {R(1), R(0)};
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-            yp = cfma(alpha, yp, vals[r + 1]);
-            if (r >= W)
-                ys[r - W] = yp;
-        }
-        Cx<R> zn = zero;
-#pragma unroll
-        for (int r = NR - 1; r >= W; --r) {
-            const int u = s - W + r;
-            const Cx<R> zt = cfnma(cst, zn, ((u <= n - 1) ? R(1) : R(0)) * ys[r - W]);
-            if (r < W + S) {
-                const Cx<R> z = rst * zt;
-                io[r - W] = Cx<R>{fma(R(2), z.re, -vals[r + 1].re), fma(R(2), z.im, -vals[r + 1].im)};
-                if (r == W)
-                    d_first = z;
+            yp = cfma(alpha, yp, ld(r + 1));
+            const R m = (s - W + r <= n - 1) ? R(1) : R(0);
+            if (r >= W && r < W + S)
+                ym[r - W] = m * yp;
+            if (r >= W + S) {
+                zs = cfma(pw, m * yp, zs);
+                if (r + 1 < NR)
+                    pw = pw * mc;
             }
+        }
+        // psi' = 2 r* zt - v, one complex multiply-add per output
+        const Cx<R> r2 = {R(2) * rst.re, R(2) * rst.im};
+        Cx<R> zn = zs;
+#pragma unroll
+        for (int r = W + S - 1; r >= W; --r) {
+            const Cx<R> zt = cfnma(cst, zn, ym[r - W]);
+            const Cx<R> v = ld(r + 1);
+            io[r - W] = cfma(r2, zt, Cx<R>{-v.re, -v.im});
+            if (r == W)
+                d_first = rst * zt;
             zn = zt;
         }
         return;
     }
 
     if constexpr (ISSUE) {
-        Cx<R> ys[S + W];
-        Cx<R> yp = zero;
+        Cx<R> ym[S];
+        Cx<R> yp = zero, zs = zero, pw = {R(1), R(0)};
+        Cx<R> vm = ld(0), v0 = ld(1);
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
+            const Cx<R> vp = ld(r + 2);
             const int u = s - W + r;
             const R m = (u >= 1 && u <= n - 1) ? R(1) : R(0);
-            yp = cfma(m * alpha, yp, m * minus_kv_st<R, ST>(L, vals[r], vals[r + 1], vals[r + 2]));
-            if (r >= W)
-                ys[r - W] = yp;
-        }
-        Cx<R> zn = zero;
-#pragma unroll
-        for (int r = NR - 1; r >= W; --r) {
-            const Cx<R> zt = cfnma(cst, zn, ys[r - W]);
-            if (r < W + S) {
-                const Cx<R> z = rst * zt;
-                io[r - W] = Cx<R>{fma(R(2), z.re, vals[r + 1].re), fma(R(2), z.im, vals[r + 1].im)};
-                if (r == W)
-                    d_first = z;
+            yp = cfma(m * alpha, yp, m * minus_kv_st<R, ST>(L, vm, v0, vp));
+            if (r >= W && r < W + S)
+                ym[r - W] = yp;
+            if (r >= W + S) {
+                zs = cfma(pw, yp, zs);
+                if (r + 1 < NR)
+                    pw = pw * mc;
             }
+            vm = v0;
+            v0 = vp;
+        }
+        const Cx<R> r2 = {R(2) * rst.re, R(2) * rst.im};
+        Cx<R> zn = zs;
+#pragma unroll
+        for (int r = W + S - 1; r >= W; --r) {
+            const Cx<R> zt = cfnma(cst, zn, ym[r - W]);
+            io[r - W] = cfma(r2, zt, ld(r + 1));  // v + 2 r* zt
+            if (r == W)
+                d_first = rst * zt;
             zn = zt;
         }
         return;
     }
 
     // delta form: d'_u = r* rhs_u + alpha d'_{u-1}, d_u = d'_u - c* d_{u+1}
-    Cx<R> dps[S + W];
-    Cx<R> dprev = zero;
+    Cx<R> dm[S];
+    Cx<R> dprev = zero, ds = zero, pw = {R(1), R(0)};
+    Cx<R> vm = ld(0), v0 = ld(1);
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
+        const Cx<R> vp = ld(r + 2);
         const int u = s - W + r;
         const bool valid = (u >= 1) && (u <= n - 1);
-        if (r >= W && r < W + S)
-            io[r - W] = vals[r + 1];
         Cx<R> dp = zero;
         if (valid)
-            dp = rst * minus_kv_st<R, ST>(L, vals[r], vals[r + 1], vals[r + 2]) + alpha * dprev;
+            dp = rst * minus_kv_st<R, ST>(L, vm, v0, vp) + alpha * dprev;
         dprev = dp;
-        if (r >= W)
-            dps[r - W] = dp;
+        if (r >= W && r < W + S)
+            dm[r - W] = dp;
+        if (r >= W + S) {
+            ds = cfma(pw, dp, ds);
+            if (r + 1 < NR)
+                pw = pw * mc;
+        }
+        vm = v0;
+        v0 = vp;
     }
-    Cx<R> dnext = zero;
+    Cx<R> dnext = ds;
 #pragma unroll
-    for (int r = NR - 1; r >= W; --r) {
-        const Cx<R> d = dps[r - W] - cst * dnext;
-        if (r < W + S)
-            io[r - W] = io[r - W] + R(2) * d;
+    for (int r = W + S - 1; r >= W; --r) {
+        const Cx<R> d = dm[r - W] - cst * dnext;
+        io[r - W] = ld(r + 1) + R(2) * d;
         if (r == W)
             d_first = d;
         dnext = d;
-    }
-}
-
-// Load the window values v_{s-W-1} .. v_{s+S+W} of one segment (zero outside
-// the unknowns 1..n-1), every load issued before any is consumed.
-template <class R, int S, int W, class Load>
-__device__ __forceinline__ void window_load(int s, int n, Load load, Cx<R> (&vals)[S + 2 * W + 2])
-{
-#pragma unroll
-    for (int r = 0; r < S + 2 * W + 2; ++r) {
-        const int u = s - W - 1 + r;
-        vals[r] = Cx<R>{R(0), R(0)};
-        if (u >= 1 && u <= n - 1)
-            vals[r] = load(u);
     }
 }
 
@@ -310,6 +330,20 @@ __device__ __forceinline__ int xcd_logical_block(int nblocks)
     const int per = (nblocks + 7) / 8;
     const int l = (b % 8) * per + b / 8;
     return l < nblocks ? l : -1;
+}
+
+// The work-list item of this block in a launch of at least 8 ceil(n / 8)
+// blocks over a list of n items (n read on the device, so a launch captured
+// for a longer list stays valid when the list shrinks): as
+// xcd_logical_block, each XCD takes a contiguous run of the list, whose
+// neighbouring items share halo rows in that XCD's L2.  -1 for the blocks
+// beyond the list.
+__device__ __forceinline__ int xcd_item(int n)
+{
+    const int b = blockIdx.x;
+    const int per = (n + 7) / 8;
+    const int l = (b % 8) * per + b / 8;
+    return (b / 8 < per && l < n) ? l : -1;
 }
 
 // One DPP lane permutation of a double within rows of 16 lanes (CTRL: a
@@ -395,40 +429,30 @@ __device__ __forceinline__ double block_sum_nt(double v, double *red)
     return r;
 }
 
-template <int NT>
-__device__ __forceinline__ double block_sum_partials_nt(const double *part, int npart, double *red)
+// Fixed-order sum of n FP64 partials by one wave (all 64 lanes active): lane
+// l adds ((p_l + p_{l+64}) + (p_{l+128} + p_{l+192})), then p_{l+256},
+// p_{l+320}, ... in turn; then the DPP wave sum.  Every wave of every kernel
+// that sums the same partials gets the same bits, so the rescale of a pending
+// norm is the same number whether it is folded into the next step or applied
+// by a kernel of its own, and a run restarted from a saved state repeats the
+// uninterrupted run bit for bit.  (The fused step prefetches the first four
+// partials itself and combines them in this order.)
+__device__ __forceinline__ double wave_partials_sum(const double *part, int n)
 {
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    double v = 0.0;
-    for (int t = tid; t < npart; t += NT)
+    const int lane = (threadIdx.x + threadIdx.y * blockDim.x) & 63;
+    double pp[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        pp[k] = lane + 64 * k < n ? part[lane + 64 * k] : 0.0;
+    double v = (pp[0] + pp[1]) + (pp[2] + pp[3]);
+    for (int t = lane + 256; t < n; t += 64)
         v += part[t];
-    double r = block_sum_nt<NT>(v, red);
-    __syncthreads();
-    if (tid == 0)
-        red[16] = r;
-    __syncthreads();
-    r = red[16];
-    __syncthreads();
-    return r;
+    return wave_sum_f64(v);
 }
 
-// Sum of npart FP64 partials by a 256-thread block, in a fixed order; every
-// block that calls this gets the same bits.  Result broadcast to all threads.
-__device__ __forceinline__ double block_sum_partials(const double *part, int npart, double *red)
-{
-    const int tid = threadIdx.x + threadIdx.y * blockDim.x;
-    double v = 0.0;
-    for (int t = tid; t < npart; t += 256)
-        v += part[t];
-    double r = block_sum_256(v, red);
-    __syncthreads();
-    if (tid == 0)
-        red[4] = r;
-    __syncthreads();
-    r = red[4];
-    __syncthreads();
-    return r;
-}
+// s - 1 of the rescale s = 1 / sqrt(dV tot) that normalises a state whose
+// sum of |psi|^2 is tot (the one expression every path evaluates).
+__device__ __forceinline__ double norm_scale_m1(double tot, double dV) { return 1.0 / sqrt(dV * tot) - 1.0; }
 
 __device__ __forceinline__ void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
@@ -586,12 +610,61 @@ __device__ __forceinline__ Cx<R> rescale(Cx<R> v, R sm1)
 // its points u = m, m + 256/L, ... coalesced; the staged lines sit in LDS
 // padded every S elements so that the solve threads, which own consecutive
 // segments (thread p: segment p % nseg of line p / nseg), hit distinct banks.
-// src may equal dst: a line is owned by exactly one block, and every load
-// precedes the block's first barrier.
-template <class R, int S, int W, bool RT, int KX = kXLoad>
-__device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
-                                             const StepArgs &a, int L, const double *__restrict__ sm1p,
-                                             const Cx<R> *__restrict__ tab, int line0, unsigned char *smem)
+// A block loads its line group into registers (xsweep_load), then finishes
+// it (xsweep_finish).  Making the kernels persistent, with the next group's
+// loads issued during the current group's solve, measured slower than one
+// group per block with the hardware dealing blocks to the CUs.  src may
+// equal dst: a line is owned by exactly one block and loaded before that
+// block writes it.
+
+// The values one thread stages for a line group: KX state points and two
+// pivot-table entries.
+template <class R, int KX>
+struct XStage {
+    Cx<R> pre[KX];
+    Cx<R> tpre[2];
+};
+
+// Issue the loads of the line group starting at line0 (L lines).
+template <class R, int S, int W, int KX>
+__device__ __forceinline__ void xsweep_load(const typename Vec<R>::T *src, const StepArgs &a, int L,
+                                            const Cx<R> *__restrict__ tab, int line0, XStage<R, KX> &g)
+{
+    const int nx = a.nx, ny = a.ny;
+    const int nlines = ny * (a.dim == 3 ? a.nz : 1);
+    const int tid = threadIdx.x;
+    const int tpl = 256 / L;
+    const int sl = tid / tpl, sm = tid - sl * tpl;
+    const int sline = line0 + sl;
+    const int sj = sline % ny, sk = sline / ny;
+    const bool sact = sline < nlines && sj > 0 && (a.dim == 2 || sk > 0);
+    const int64_t sbase = (int64_t)sline * nx;
+#pragma unroll
+    for (int c = 0; c < KX; ++c) {
+        const int u = sm + c * tpl;
+        g.pre[c] = Cx<R>{R(0), R(0)};
+        if (sact && u >= 1 && u <= nx - 1)
+            g.pre[c] = ld<R>(src, sbase + u);
+    }
+#pragma unroll
+    for (int c2 = 0; c2 < 2; ++c2) {
+        const int te = tid + c2 * 256;
+        g.tpre[c2] = Cx<R>{R(0), R(0)};
+        if (te < L * (W + 2)) {
+            const int tl = te / (W + 2), c = te - tl * (W + 2);
+            const int tline = line0 + tl;
+            if (tline < nlines)
+                g.tpre[c2] = tab[(size_t)(tline % ny) * (W + 2) + c];
+        }
+    }
+}
+
+// The rest of the group from its loaded values: rescale and H1 into LDS,
+// the windowed solves, the wall terms and the write-back.
+template <class R, int S, int W, bool RT, int KX>
+__device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const StepArgs &a, int L,
+                                              const double *__restrict__ sm1p, int line0, XStage<R, KX> &g,
+                                              unsigned char *smem)
 {
     Cx<R> *lin = reinterpret_cast<Cx<R> *>(smem);
     const int nx = a.nx, ny = a.ny;
@@ -601,34 +674,13 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
     const int nlines = ny * (a.dim == 3 ? a.nz : 1);
     const int nseg = (nx - 2) / S + 1;
     const int tid = threadIdx.x;
-
-    // staging map: line sl, first point sm, stride tpl
     const int tpl = 256 / L;
     const int sl = tid / tpl, sm = tid - sl * tpl;
     const int sline = line0 + sl;
     const int sj = sline % ny, sk = sline / ny;
     const bool sact = sline < nlines && sj > 0 && (a.dim == 2 || sk > 0);
     const int64_t sbase = (int64_t)sline * nx;
-    Cx<R> pre[KX];
-#pragma unroll
-    for (int c = 0; c < KX; ++c) {
-        const int u = sm + c * tpl;
-        pre[c] = Cx<R>{R(0), R(0)};
-        if (sact && u >= 1 && u <= nx - 1)
-            pre[c] = ld<R>(src, sbase + u);
-    }
-    Cx<R> tpre[2];
-#pragma unroll
-    for (int c2 = 0; c2 < 2; ++c2) {
-        const int te = tid + c2 * 256;
-        tpre[c2] = Cx<R>{R(0), R(0)};
-        if (te < L * (W + 2)) {
-            const int tl = te / (W + 2), c = te - tl * (W + 2);
-            const int tline = line0 + tl;
-            if (tline < nlines)
-                tpre[c2] = tab[(size_t)(tline % ny) * (W + 2) + c];
-        }
-    }
+    Cx<R>(&pre)[KX] = g.pre;
     const R sr = R((!RT && sm1p) ? *sm1p : 0.0);  // the pending rescale, s - 1
     if constexpr (RT || !std::is_same<R, double>::value) {
         Cx<R> *row = lin + sl * LS;
@@ -674,7 +726,7 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2)
         if (tid + c2 * 256 < L * (W + 2))
-            ltab[tid + c2 * 256] = tpre[c2];
+            ltab[tid + c2 * 256] = g.tpre[c2];
     __syncthreads();
 
     const int l = tid / nseg, q = tid - l * nseg;
@@ -686,10 +738,16 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
     if (active) {
         const LineCoef<R> Lc = line_coef<R>(a.ax[0], a.omega * (a.y0 + j * a.hy));
         const Cx<R> *row = lin + l * LS;
-        Cx<R> vals[S + 2 * W + 2];
-        window_load<R, S, W>(s0, nx, [&](int u) { return row[u + u / S]; }, vals);
+        // window value r: point u = s0 - W - 1 + r of the staged line (zero
+        // outside the unknowns 1..nx-1, which the line does not stage)
+        auto ld = [&](int r) -> Cx<R> {
+            const int u = s0 - W - 1 + r;
+            const bool in = u >= 1 && u <= nx - 1;
+            const Cx<R> v = row[in ? u + u / S : 0];
+            return csel(in, v, Cx<R>{R(0), R(0)});
+        };
         Cx<R> df;
-        window_solve<R, S, W, RT ? 2 : 1>(s0, nx, Lc, ltab[l * (W + 2)], ltab[l * (W + 2) + 1], vals, io, df);
+        window_solve<R, S, W, RT ? 2 : 1>(s0, nx, Lc, ltab[l * (W + 2)], ltab[l * (W + 2) + 1], ld, io, df);
         if (q == 0)
             d1[l] = df;
     }
@@ -720,23 +778,25 @@ __device__ __forceinline__ void xsweep_block(const typename Vec<R>::T *src, type
 
 // KX: staged points per thread, nx * L <= 256 * KX (fewer registers for
 // short lines, hence more waves per SIMD in this bandwidth-bound kernel).
+// Block b takes line group b (lines b L .. b L + L - 1).
 template <class R, int S, int W, bool RT, int KX>
-__global__ __launch_bounds__(256) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
+__global__ __launch_bounds__(256, kSweepWaves) void k_xsweep(const typename Vec<R>::T *src, typename Vec<R>::T *dst,
                                                 StepArgs a, int L, const double *__restrict__ sm1p,
                                                 const Cx<R> *__restrict__ tab)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    xsweep_block<R, S, W, RT, KX>(src, dst, a, L, sm1p, tab, blockIdx.x * L, smem_raw);
+    XStage<R, KX> g;
+    xsweep_load<R, S, W, KX>(src, a, L, tab, blockIdx.x * L, g);
+    xsweep_finish<R, S, W, RT, KX>(dst, a, L, sm1p, blockIdx.x * L, g, smem_raw);
 }
 
 // s - 1 of the pending rescale, s = 1/sqrt(dV sum of the npart norm
 // partials), summed in fixed order by one block.
 static __global__ __launch_bounds__(256) void k_norm_scale(const double *partials, int npart, double dV, double *out)
 {
-    __shared__ double red[8];
-    const double tot = block_sum_partials(partials, npart, red);
+    const double sm1 = norm_scale_m1(wave_partials_sum(partials, npart), dV);
     if (threadIdx.x == 0)
-        out[0] = 1.0 / sqrt(dV * tot) - 1.0;
+        out[0] = sm1;
 }
 
 // ---------------------------------------------------------------------------
@@ -795,12 +855,9 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
     const bool active = trow != nullptr && q < nseg;
     Cx<R> io[S];
     if (active) {
-        Cx<R> vals[S + 2 * W + 2];
-#pragma unroll
-        for (int r = 0; r < S + 2 * W + 2; ++r)
-            vals[r] = tile[(ty * S + r) * LN + tx];
         Cx<R> df;
-        window_solve<R, S, W>(s0, n, Lc, trow[0], trow[1], vals, io, df);
+        window_solve<R, S, W>(s0, n, Lc, trow[0], trow[1], [&](int r) { return tile[(ty * S + r) * LN + tx]; },
+                              io, df);
         if (q == 0)
             d1[tx] = df;
     }
@@ -856,7 +913,7 @@ __device__ __forceinline__ void ysweep_block(const typename Vec<R>::T *__restric
 }
 
 template <class R, int S, int W, bool EMIT>
-__global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__restrict__ src,
+__global__ __launch_bounds__(256, kSweepWaves) void k_ysweep(const typename Vec<R>::T *__restrict__ src,
                                                 typename Vec<R>::T *__restrict__ dst, StepArgs a,
                                                 double *partials, int gx, int gy, int gz,
                                                 const Cx<R> *__restrict__ tab)
@@ -871,7 +928,7 @@ __global__ __launch_bounds__(256) void k_ysweep(const typename Vec<R>::T *__rest
 }
 
 template <class R, int S, int W, bool EMIT>
-__global__ __launch_bounds__(256) void k_zsweep(const typename Vec<R>::T *__restrict__ src,
+__global__ __launch_bounds__(256, kSweepWaves) void k_zsweep(const typename Vec<R>::T *__restrict__ src,
                                                 typename Vec<R>::T *__restrict__ dst, StepArgs a,
                                                 double *partials, int gx, int gy,
                                                 const Cx<R> *__restrict__ tab)
@@ -975,16 +1032,13 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
     __shared__ double red[20];
     const int tid = threadIdx.x;
     const int nw = ONE ? one.tiles_x * one.tiles_y : *nwork;
-    // ONE: one block per tile on a grid of 8 ceil(nw / 8) blocks; the
+    // one block per tile on a grid of at least 8 ceil(nw / 8) blocks; the
     // hardware deals consecutive blocks to the 8 XCDs in turn, and the remap
     // gives each XCD a contiguous run of tiles, so that the halos
     // neighbouring tiles share are fetched once into that XCD's L2
-    int it0 = blockIdx.x;
-    if (ONE) {
-        it0 = xcd_logical_block(nw);
-        if (it0 < 0)
-            return;
-    }
+    const int it0 = ONE ? xcd_logical_block(nw) : xcd_item(nw);
+    if (it0 < 0)
+        return;
     for (int it = it0; it < nw; it += gridDim.x) {
         int ik = 0, tile = it;
         if (!ONE) {
@@ -1054,7 +1108,7 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
             double v = (pp[0] + pp[1]) + (pp[2] + pp[3]);
             for (int t = lane + PP * 64; t < np; t += 64)
                 v += pin[I.poff + t];
-            sm1 = 1.0 / sqrt(I.dV * wave_sum_f64(v)) - 1.0;
+            sm1 = norm_scale_m1(wave_sum_f64(v), I.dV);
         }
         const R sr = R(sm1);
         // rescale and H1 on every staged point (a point outside the grid
@@ -1124,13 +1178,10 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
                 xo[k][r] = Cx<R>{R(0), R(0)};
             if (p < SR * NSX && j >= 1 && j <= ny - 1) {
                 const LineCoef<R> Lc = line_coef<R>(I.ax[0], I.omega * (I.y0 + j * I.hy));
-                Cx<R> vals[S + 2 * W + 2];
-#pragma unroll
-                for (int r = 0; r < S + 2 * W + 2; ++r)
-                    vals[r] = sx(rr, q * S + r);
                 Cx<R> df;
                 const int s = c0 + q * S;
-                window_solve<R, S, W, ST, true>(s, nx, Lc, tpx[rr][0], tpx[rr][1], vals, xo[k], df);
+                window_solve<R, S, W, ST, true>(s, nx, Lc, tpx[rr][0], tpx[rr][1],
+                                                [&](int r) { return sx(rr, q * S + r); }, xo[k], df);
                 if (s == 1)
                     d1x[rr] = df;
 #pragma unroll
@@ -1168,12 +1219,9 @@ __global__ __launch_bounds__(NT) void k_step2d(const Inst2D *__restrict__ insts,
         Cx<R> io[SY];
         if (act) {
             const LineCoef<R> Lc = line_coef<R>(I.ax[1], -I.omega * (I.x0 + i * I.hx));
-            Cx<R> vals[SY + 2 * W + 2];
-#pragma unroll
-            for (int r = 0; r < SY + 2 * W + 2; ++r)
-                vals[r] = sx(q * SY + r, H + col);
             Cx<R> df;
-            window_solve<R, SY, W, ST, true>(s, ny, Lc, tpy[col][0], tpy[col][1], vals, io, df);
+            window_solve<R, SY, W, ST, true>(s, ny, Lc, tpy[col][0], tpy[col][1],
+                                             [&](int r) { return sx(q * SY + r, H + col); }, io, df);
             if (s == 1)
                 d1y[col] = df;
         }
@@ -1212,10 +1260,9 @@ template <class R, bool RT>
 __global__ __launch_bounds__(256) void k_h1(const typename Vec<R>::T *src, typename Vec<R>::T *dst, StepArgs a,
                                             const double *partials, int npart)
 {
-    __shared__ double red[8];
     double sm1 = 0.0;
     if (!RT && npart > 0)
-        sm1 = 1.0 / sqrt(a.dV * block_sum_partials(partials, npart, red)) - 1.0;
+        sm1 = norm_scale_m1(wave_partials_sum(partials, npart), a.dV);
     const R sr = R(sm1);
     const int64_t n = (int64_t)a.nx * a.ny * (a.dim == 3 ? a.nz : 1);
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
@@ -1321,14 +1368,14 @@ template <class R>
 __global__ __launch_bounds__(256) void k_rescale(const typename Vec<R>::T *src, typename Vec<R>::T *dst, int64_t n,
                                                  double dV, const double *partials, int npart)
 {
-    __shared__ double red[8];
-    const double s = 1.0 / sqrt(dV * block_sum_partials(partials, npart, red));
-    if (fabs(s - 1.0) < 0.25) {
-        const R sr = R(s - 1.0);
+    const double tot = wave_partials_sum(partials, npart);
+    const double sm1 = norm_scale_m1(tot, dV);
+    if (fabs(sm1) < 0.25) {
+        const R sr = R(sm1);
         for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
             st<R>(dst, p, rescale(ld<R>(src, p), sr));
     } else {
-        const R sc = R(s);
+        const R sc = R(1.0 / sqrt(dV * tot));
         for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
             const Cx<R> v = ld<R>(src, p);
             st<R>(dst, p, Cx<R>{v.re * sc, v.im * sc});
@@ -1552,7 +1599,7 @@ __device__ __forceinline__ void obs_point(const typename Vec<R>::T *psi, const S
     s[10] += x * x * dens;
     s[11] += y * y * dens;
     s[12] += z * z * dens;
-    s[13] = fmax(s[13], dens);
+    s[13] = fmax(s[13], __dadd_rn(__dmul_rn(v.re, v.re), __dmul_rn(v.im, v.im)));  // as k_plane_max
     s[14] += 0.5 * (norm2(qx) + norm2(qy) + norm2(qz));
     s[15] += a.omega * (v.re * lz4.im - v.im * lz4.re);  // Im(conj(v) lz4)
 }
@@ -1619,6 +1666,39 @@ __global__ __launch_bounds__(256) void k_plane_max(const typename Vec<R>::T *psi
         partials[blockIdx.x] = b;
 }
 
+// Vortex windings counted at plaquette (i, j) of plane k0 (corners (i, j),
+// (i+1, j), (i+1, j+1), (i, j+1)): w = round(sum of the wrapped phase
+// differences counter-clockwise / 2 pi) when w > 0, no corner is exactly
+// zero and the largest density within `box` points reaches thr; else 0.
+template <class R>
+__device__ __forceinline__ int plaquette_count(const typename Vec<R>::T *psi, const StepArgs &a, int k0, int i, int j,
+                                               double thr, int box)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    const Cx<double> c00 = at<R>(psi, a, i, j, k0), c10 = at<R>(psi, a, i + 1, j, k0);
+    const Cx<double> c11 = at<R>(psi, a, i + 1, j + 1, k0), c01 = at<R>(psi, a, i, j + 1, k0);
+    auto zero = [](Cx<double> c) { return c.re == 0.0 && c.im == 0.0; };
+    if (zero(c00) || zero(c10) || zero(c11) || zero(c01))
+        return 0;
+    // arg(b conj(a)) with the products rounded as written (no contraction)
+    auto darg = [](Cx<double> b, Cx<double> c) {
+        const double re = __dadd_rn(__dmul_rn(b.re, c.re), __dmul_rn(b.im, c.im));
+        const double im = __dsub_rn(__dmul_rn(b.im, c.re), __dmul_rn(b.re, c.im));
+        return atan2(im, re);
+    };
+    const double sum = darg(c10, c00) + darg(c11, c10) + darg(c01, c11) + darg(c00, c01);
+    const int w = (int)llround(sum / two_pi);
+    if (w <= 0)
+        return 0;
+    double local = 0.0;
+    for (int jj = j - box; jj <= j + 1 + box; ++jj)
+        for (int ii = i - box; ii <= i + 1 + box; ++ii) {
+            const Cx<double> v = at<R>(psi, a, ii, jj, k0);
+            local = fmax(local, __dadd_rn(__dmul_rn(v.re, v.re), __dmul_rn(v.im, v.im)));
+        }
+    return local >= thr ? w : 0;
+}
+
 // Vortex count on plane k0: per plaquette winding of the wrapped phase
 // differences, masked by the largest density within `box` points.
 template <class R>
@@ -1626,36 +1706,13 @@ __global__ __launch_bounds__(256) void k_vortex(const typename Vec<R>::T *psi, S
                                                 int box, const double *dmax, double *partials)
 {
     __shared__ double red[8];
-    const double two_pi = 6.283185307179586476925286766559;
     const int nx = a.nx, ny = a.ny;
     const int64_t n = (int64_t)(nx - 1) * (ny - 1);
     const double thr = frac * dmax[0];
     double cnt = 0.0;
     for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
         const int i = (int)(p % (nx - 1)), j = (int)(p / (nx - 1));
-        const Cx<double> c00 = at<R>(psi, a, i, j, k0), c10 = at<R>(psi, a, i + 1, j, k0);
-        const Cx<double> c11 = at<R>(psi, a, i + 1, j + 1, k0), c01 = at<R>(psi, a, i, j + 1, k0);
-        auto zero = [](Cx<double> c) { return c.re == 0.0 && c.im == 0.0; };
-        if (zero(c00) || zero(c10) || zero(c11) || zero(c01))
-            continue;
-        // arg(b conj(a)) with the products rounded as written (no contraction)
-        auto darg = [](Cx<double> b, Cx<double> c) {
-            const double re = __dadd_rn(__dmul_rn(b.re, c.re), __dmul_rn(b.im, c.im));
-            const double im = __dsub_rn(__dmul_rn(b.im, c.re), __dmul_rn(b.re, c.im));
-            return atan2(im, re);
-        };
-        const double sum = darg(c10, c00) + darg(c11, c10) + darg(c01, c11) + darg(c00, c01);
-        const int w = (int)llround(sum / two_pi);
-        if (w <= 0)
-            continue;
-        double local = 0.0;
-        for (int jj = j - box; jj <= j + 1 + box; ++jj)
-            for (int ii = i - box; ii <= i + 1 + box; ++ii) {
-                const Cx<double> v = at<R>(psi, a, ii, jj, k0);
-                local = fmax(local, __dadd_rn(__dmul_rn(v.re, v.re), __dmul_rn(v.im, v.im)));
-            }
-        if (local >= thr)
-            cnt += w;
+        cnt += plaquette_count<R>(psi, a, k0, i, j, thr, box);
     }
     const double b = block_sum_256(cnt, red);
     if (threadIdx.x == 0)
@@ -1700,7 +1757,6 @@ __global__ __launch_bounds__(256) void k_batch_finish(const Inst2D *__restrict__
                                                       const double *__restrict__ partials, int rescale_on,
                                                       const double *__restrict__ scale)
 {
-    __shared__ double red[20];
     const int nfw = *nf;
     for (int it = blockIdx.x; it < nfw; it += gridDim.x) {
         const int2 wk = fwork[it];
@@ -1710,7 +1766,7 @@ __global__ __launch_bounds__(256) void k_batch_finish(const Inst2D *__restrict__
         if (rescale_on && scale)
             sm1 = scale[wk.x];
         else if (rescale_on)
-            sm1 = 1.0 / sqrt(I.dV * block_sum_partials_nt<256>(partials + I.poff, I.tiles_x * I.tiles_y, red)) - 1.0;
+            sm1 = norm_scale_m1(wave_partials_sum(partials + I.poff, I.tiles_x * I.tiles_y), I.dV);
         const R sr = R(sm1);
         const typename Vec<R>::T *src = reinterpret_cast<const typename Vec<R>::T *>(I.buf[parity]);
         typename Vec<R>::T *dst = reinterpret_cast<typename Vec<R>::T *>(I.buf[0]);
@@ -1761,14 +1817,11 @@ __global__ __launch_bounds__(256) void k_batch_obs(const Inst2D *__restrict__ in
 
 // Per instance (one block each): fixed-order sum of its items' partials
 // (items obase[k] .. obase[k] + ocount[k] - 1 of the current list; ocount 0
-// for instances not listed), then the convergence bookkeeping: mu of the
-// real-part form, hits counts consecutive checks with |mu - mu_prev| < tol,
-// and an instance is flagged converged (conv[k] = step) at two hits.
+// for instances not listed) into sums[k * kObsN ..].
 static __global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const int *__restrict__ obase,
-                                                         const int *__restrict__ ocount,
-                                                         const double *__restrict__ opart, double *__restrict__ sums,
-                                                         double *__restrict__ mu_prev, int *__restrict__ hits,
-                                                         long long *__restrict__ conv, double tol, long long step)
+                                                                const int *__restrict__ ocount,
+                                                                const double *__restrict__ opart,
+                                                                double *__restrict__ sums)
 {
     __shared__ double red[8];
     const int k = blockIdx.x;
@@ -1788,23 +1841,82 @@ static __global__ __launch_bounds__(256) void k_batch_obs_final(int ninst, const
         acc[v] = mx ? block_max_256(x, red) : block_sum_256(x, red);
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0)
         for (int v = 0; v < kObsN; ++v)
             sums[(int64_t)k * kObsN + v] = acc[v];
-        if (tol > 0.0) {  // a convergence check (tol <= 0: observables only)
-            const double mu = (acc[2] + acc[3] + acc[4] + acc[5]) / acc[1];
-            const double prev = mu_prev[k];
-            if (conv[k] < 0) {
-                if (prev == prev && fabs(mu - prev) < tol)
-                    hits[k] += 1;
-                else
-                    hits[k] = 0;
-                if (hits[k] >= 2)
-                    conv[k] = step;
-            }
-            mu_prev[k] = mu;
+}
+
+// Vortex windings of every listed (instance, chunk) item: the plaquettes
+// p = chunk * kChunk .. + kChunk - 1 of the (nx - 1) (ny - 1) plaquettes,
+// counted as plaquette_count with the instance's max density sums[k * kObsN
+// + 13] (from k_batch_obs_final); one partial per item into vpart[item].
+template <class R>
+__global__ __launch_bounds__(256) void k_batch_vortex(const Inst2D *__restrict__ insts, const int2 *__restrict__ owork,
+                                                      const int *__restrict__ no, const double *__restrict__ sums,
+                                                      double frac, int box, double *__restrict__ vpart)
+{
+    __shared__ double red[8];
+    const int now = *no;
+    for (int it = blockIdx.x; it < now; it += gridDim.x) {
+        const int2 wk = owork[it];
+        const Inst2D &I = insts[wk.x];
+        const StepArgs a = inst_args(I);
+        const typename Vec<R>::T *psi = reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]);
+        const int64_t n = (int64_t)(I.nx - 1) * (I.ny - 1);
+        const int64_t base = (int64_t)wk.y * kChunk;
+        const double thr = frac * sums[(int64_t)wk.x * kObsN + 13];
+        double cnt = 0.0;
+        for (int c = threadIdx.x; c < kChunk; c += 256) {
+            const int64_t p = base + c;
+            if (p < n)
+                cnt += plaquette_count<R>(psi, a, 0, (int)(p % (I.nx - 1)), (int)(p / (I.nx - 1)), thr, box);
+        }
+        const double b = block_sum_256(cnt, red);
+        if (threadIdx.x == 0)
+            vpart[it] = b;
+        __syncthreads();
+    }
+}
+
+// Convergence bookkeeping of every listed instance (one thread each), the
+// criterion of sscn_converge: mu of the real-part form (from sums), its
+// change since the last check d; when d < tol the instance's vortex count c
+// (sum of its vpart items, exact in FP64) is compared with the count at the
+// previous hit, and hits counts consecutive checks with d < tol and an
+// unchanged count (a changed count restarts the run of hits at 1); an
+// instance is flagged converged (conv[k] = step) at two hits.  counts[k]
+// receives every listed instance's current count.
+static __global__ __launch_bounds__(256) void k_batch_conv(int ninst, const int *__restrict__ obase,
+                                                           const int *__restrict__ ocount,
+                                                           const double *__restrict__ vpart,
+                                                           const double *__restrict__ sums,
+                                                           double *__restrict__ mu_prev, int *__restrict__ hits,
+                                                           int *__restrict__ count_prev, int *__restrict__ counts,
+                                                           long long *__restrict__ conv, double tol, long long step)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ninst || ocount[k] == 0)
+        return;
+    double c = 0.0;
+    for (int b = 0; b < ocount[k]; ++b)
+        c += vpart[obase[k] + b];
+    const int cnt = (int)c;
+    counts[k] = cnt;
+    const double *s = sums + (int64_t)k * kObsN;
+    const double mu = (s[2] + s[3] + s[4] + s[5]) / s[1];
+    const double prev = mu_prev[k];
+    if (conv[k] < 0) {
+        if (prev == prev && fabs(mu - prev) < tol) {
+            hits[k] = (count_prev[k] < 0 || cnt == count_prev[k]) ? hits[k] + 1 : 1;
+            count_prev[k] = cnt;
+            if (hits[k] >= 2)
+                conv[k] = step;
+        } else {
+            hits[k] = 0;
+            count_prev[k] = -1;
         }
     }
+    mu_prev[k] = mu;
 }
 
 // ---------------------------------------------------------------------------
@@ -1819,52 +1931,53 @@ static __global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__rest
                                                      const int *__restrict__ nk, const double *__restrict__ partials,
                                                      double *__restrict__ scale)
 {
-    __shared__ double red[8];
     const int nkk = *nk;
     for (int it = blockIdx.x; it < nkk; it += gridDim.x) {
         const int k = klist[it];
         const Inst2D &I = insts[k];
-        const double tot = block_sum_partials(partials + I.ypoff, I.ygx * I.ygy, red);
+        const double sm1 = norm_scale_m1(wave_partials_sum(partials + I.ypoff, I.ygx * I.ygy), I.dV);
         if (threadIdx.x == 0)
-            scale[k] = 1.0 / sqrt(I.dV * tot) - 1.0;
+            scale[k] = sm1;
     }
 }
 
+// One work-list item (instance, first line) per block.
 template <class R, int S, int W, bool RT, int KX>
-__global__ __launch_bounds__(256) void k_batch_xsweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ xwork,
+__global__ __launch_bounds__(256, kSweepWaves) void k_batch_xsweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ xwork,
                                                       const int *__restrict__ nitems, const double *__restrict__ scale,
                                                       int use_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int nit = *nitems;
-    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
-        const int2 wk = xwork[it];
-        const Inst2D &I = insts[wk.x];
-        const StepArgs a = inst_args(I);
-        xsweep_block<R, S, W, RT, KX>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]),
-                                  reinterpret_cast<typename Vec<R>::T *>(I.buf[1]), a, I.xl,
-                                  use_scale ? scale + wk.x : nullptr, reinterpret_cast<const Cx<R> *>(I.tab[0]),
-                                  wk.y, smem_raw);
-        __syncthreads();  // LDS reuse by the next item
-    }
+    const int it = blockIdx.x;
+    if (it >= *nitems)
+        return;
+    const int2 wk = xwork[it];
+    const Inst2D &I = insts[wk.x];
+    const StepArgs a = inst_args(I);
+    XStage<R, KX> g;
+    xsweep_load<R, S, W, KX>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]), a, I.xl,
+                             reinterpret_cast<const Cx<R> *>(I.tab[0]), wk.y, g);
+    xsweep_finish<R, S, W, RT, KX>(reinterpret_cast<typename Vec<R>::T *>(I.buf[1]), a, I.xl,
+                                   use_scale ? scale + wk.x : nullptr, wk.y, g, smem_raw);
 }
 
+// One item per block, XCD-aware (xcd_item): the launch has at least
+// 8 ceil(nitems / 8) blocks.
 template <class R, int S, int W, bool EMIT>
-__global__ __launch_bounds__(256) void k_batch_ysweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ ywork,
+__global__ __launch_bounds__(256, kSweepWaves) void k_batch_ysweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ ywork,
                                                       const int *__restrict__ nitems, double *__restrict__ partials)
 {
     __shared__ double red[8];
-    const int nit = *nitems;
-    for (int it = blockIdx.x; it < nit; it += gridDim.x) {
-        const int2 wk = ywork[it];
-        const Inst2D &I = insts[wk.x];
-        const StepArgs a = inst_args(I);
-        const int by = wk.y % I.ygy, bx = wk.y / I.ygy;
-        ysweep_block<R, S, W, EMIT>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[1]),
-                                    reinterpret_cast<typename Vec<R>::T *>(I.buf[0]), a, bx, by, 0,
-                                    partials + I.ypoff + wk.y, reinterpret_cast<const Cx<R> *>(I.tab[1]), red);
-        __syncthreads();
-    }
+    const int it = xcd_item(*nitems);
+    if (it < 0)
+        return;
+    const int2 wk = ywork[it];
+    const Inst2D &I = insts[wk.x];
+    const StepArgs a = inst_args(I);
+    const int by = wk.y % I.ygy, bx = wk.y / I.ygy;
+    ysweep_block<R, S, W, EMIT>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[1]),
+                                reinterpret_cast<typename Vec<R>::T *>(I.buf[0]), a, bx, by, 0,
+                                partials + I.ypoff + wk.y, reinterpret_cast<const Cx<R> *>(I.tab[1]), red);
 }
 
 }  // namespace sscn

@@ -11,14 +11,23 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 using namespace sscn;
 
 namespace sscn {
 
-constexpr int kSeg = 8;             // outputs per thread segment (all axes)
-constexpr int kGraphSteps = 64;     // steps per captured graph
+constexpr int kSeg = 8;             // outputs per thread segment (y, z and the fused step)
+#ifndef SSCN_SEGX
+#define SSCN_SEGX 8
+#endif
+constexpr int kSegX = SSCN_SEGX;    // outputs per thread segment of the x-sweeps
+constexpr int kGraphSteps = 64;     // most steps per captured graph (single instance)
+constexpr int kBatchGraphSteps = 256;  // most steps per captured graph (batch)
+constexpr size_t kGraphCache = 4;   // graphs of different step counts kept per handle
 constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
 #ifndef SSCN_TILE_R
 #define SSCN_TILE_R 32
@@ -32,7 +41,7 @@ constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
 constexpr int kTileR = SSCN_TILE_R;   // fused 2D step: output tile rows (y)
 constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
 constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
-constexpr size_t kXLdsCap = 64 * 1024;
+constexpr size_t kXLdsCap = 150 * 1024;  // dynamic LDS of an x-sweep block
 
 // Supported window sizes (template instantiations).
 const int kWindows[] = {4, 6, 8, 10, 12, 13, 14, 16, 20, 24, 32};
@@ -77,8 +86,7 @@ struct sscn_handle {
     int fparity = 0;        // buffer (0 = psi, 1 = work) holding the state
     int pbuf = 0;           // partial buffer holding the pending norm
     float tune_ms[3] = {0, 0, 0};
-    hipGraphExec_t gexec = nullptr;
-    hipGraph_t graph = nullptr;
+    std::vector<std::pair<int64_t, hipGraphExec_t>> graphs;  // sscn_step graphs by step count
 };
 
 namespace sscn {
@@ -151,15 +159,17 @@ struct sscn_batch {
     int grid_tiles = 0, grid_chunks = 0;  // list lengths at the last rebuild
     double *part[2] = {nullptr, nullptr};
     double *opart = nullptr, *d_sums = nullptr, *d_mu_prev = nullptr;
-    int *d_hits = nullptr;
+    double *vpart = nullptr;  // vortex windings per observable chunk (convergence checks)
+    int *d_hits = nullptr, *d_count_prev = nullptr, *d_counts = nullptr;
     long long *d_conv = nullptr;
     double *phase = nullptr;
     int fparity = 0, pbuf = 0;
     bool pending = false;
     int64_t steps = 0;
-    hipGraph_t graph = nullptr;
+    hipGraph_t graph = nullptr;  // the convergence run's graph of graph_k steps
     hipGraphExec_t gexec = nullptr;
     int graph_k = 0;
+    std::vector<std::pair<int64_t, hipGraphExec_t>> step_graphs;  // sscn_batch_step graphs by step count
     // sweep plan: x line blocks, y tiles, per-instance rescale
     int plan = SSCN_PLAN_AUTO, active_plan = SSCN_PLAN_FUSED;
     bool sweeps_ok = true;
@@ -192,8 +202,15 @@ void launch_fused(const FusedLaunch &f, int parity, const double *pin, double *p
 // Raise the dynamic-LDS limit of the fused-step kernels for window W.
 template <class R>
 hipError_t allow_fused_lds_all(int W);
-// One step of the batched sweep plan for every listed instance.
+// The same for the x-sweep kernels (kXLdsCap), single-instance and batched.
 template <class R>
-void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k);
+hipError_t allow_x_lds_all(int W);
+template <class R>
+hipError_t batch_allow_x_lds_all(int W);
+// One step of the batched sweep plan for every listed instance; ev
+// (optional): 4 events recorded before the rescale, x- and y-sweep kernels
+// and after the y-sweep.
+template <class R>
+void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k, hipEvent_t *ev = nullptr);
 
 }  // namespace sscn

@@ -11,13 +11,20 @@
 
 namespace sscn {
 
+// Raise the dynamic-LDS limit of an x-sweep kernel to kXLdsCap (the default
+// limit is 64 KiB).
+inline hipError_t allow_x_lds(const void *kernel)
+{
+    return hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kXLdsCap);
+}
+
 #if SSCN_PART == 1
 
 template <class R, int W, bool RT>
 void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream_t st, bool reduce)
 {
     const int nlines = h->p.ny * (h->p.dim == 3 ? h->p.nz : 1);
-    const int blocks = (nlines + h->xL - 1) / h->xL;
+    const int groups = (nlines + h->xL - 1) / h->xL;
     double *sm1 = nullptr;
     if (!RT && npart > 0) {
         sm1 = h->obs_buf + kScaleSlot;
@@ -25,10 +32,10 @@ void go_x(const sscn_handle *h, const void *src, void *dst, int npart, hipStream
             hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, st, h->partials, npart, h->args.dV, sm1);
     }
     if ((int64_t)h->p.nx * h->xL <= 256 * 8)
-        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, 8>), dim3(blocks), dim3(256), h->xlds, st, (const V<R> *)src,
+        hipLaunchKernelGGL((k_xsweep<R, kSegX, W, RT, 8>), dim3(groups), dim3(256), h->xlds, st, (const V<R> *)src,
                            (V<R> *)dst, h->args, h->xL, (const double *)sm1, (const Cx<R> *)h->tab[0]);
     else
-        hipLaunchKernelGGL((k_xsweep<R, kSeg, W, RT, kXLoad>), dim3(blocks), dim3(256), h->xlds, st,
+        hipLaunchKernelGGL((k_xsweep<R, kSegX, W, RT, kXLoad>), dim3(groups), dim3(256), h->xlds, st,
                            (const V<R> *)src, (V<R> *)dst, h->args, h->xL, (const double *)sm1,
                            (const Cx<R> *)h->tab[0]);
 }
@@ -75,7 +82,31 @@ void launch_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st)
 #undef SSCN_CALL_Z
 }
 
+template <class R, int W>
+hipError_t allow_x_lds_w()
+{
+    hipError_t e = allow_x_lds((const void *)k_xsweep<R, kSegX, W, false, 8>);
+    if (e == hipSuccess)
+        e = allow_x_lds((const void *)k_xsweep<R, kSegX, W, false, kXLoad>);
+    if (e == hipSuccess)
+        e = allow_x_lds((const void *)k_xsweep<R, kSegX, W, true, 8>);
+    if (e == hipSuccess)
+        e = allow_x_lds((const void *)k_xsweep<R, kSegX, W, true, kXLoad>);
+    return e;
+}
+
+template <class R>
+hipError_t allow_x_lds_all(int W)
+{
+    hipError_t e = hipSuccess;
+#define SSCN_CALL_A(Wc) e = allow_x_lds_w<R, Wc>()
+    SSCN_W_SWITCH(W, SSCN_CALL_A)
+#undef SSCN_CALL_A
+    return e;
+}
+
 template void launch_x<SSCN_REAL_T, false>(const sscn_handle *, const void *, void *, int, hipStream_t, bool);
+template hipError_t allow_x_lds_all<SSCN_REAL_T>(int);
 template void launch_x<SSCN_REAL_T, true>(const sscn_handle *, const void *, void *, int, hipStream_t, bool);
 template void launch_y<SSCN_REAL_T, false>(const sscn_handle *, const void *, void *, hipStream_t);
 template void launch_y<SSCN_REAL_T, true>(const sscn_handle *, const void *, void *, hipStream_t);
@@ -93,7 +124,7 @@ void go_fused(const FusedLaunch &f, int parity, const double *pin, double *pout,
                            dim3(kTileNT),
                            lds, st, f.inst, f.work, f.nwork, *f.one, parity, pin, pout, use_pin);
     else
-        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>), dim3(f.grid), dim3(kTileNT),
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kTileC, kTileNT, RT, false>), dim3(round8(f.grid)), dim3(kTileNT),
                            lds, st, f.inst, f.work, f.nwork, Inst2D{}, parity, pin, pout, use_pin);
 }
 
@@ -160,26 +191,34 @@ template <class R, int W, bool RT>
 void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
 {
     if (b->xshort)
-        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
+        hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
                            b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
     else
-        hipLaunchKernelGGL((k_batch_xsweep<R, kSeg, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
+        hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
                            b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
 }
 
 template <class R, int W, bool EMIT>
 void go_batch_y(const sscn_batch *b, int grid, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(std::max(grid, 1)), dim3(kYLines, kSegBlock), 0, st, b->d_inst,
-                       b->d_ywork, b->d_ny, b->ypart);
+    // one block per item on a grid of whole XCD rounds (xcd_item)
+    hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(round8(std::max(grid, 1))), dim3(kYLines, kSegBlock), 0,
+                       st, b->d_inst, b->d_ywork, b->d_ny, b->ypart);
 }
 
 // One step of the sweep plan for every listed instance (state in buf[0]).
+// ev (optional, 4 events): recorded before the rescale kernel, before the
+// x-sweep, before the y-sweep and after it.
 template <class R>
-void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k)
+void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k, hipEvent_t *ev)
 {
+    auto mark = [&](int t) {
+        if (ev)
+            (void)hipEventRecord(ev[t], st);
+    };
     const bool imag = b->mode == SSCN_IMAG;
     const int sc = (imag && b->pending) ? 1 : 0;
+    mark(0);
     if (sc)
         hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
                            b->d_nk, b->ypart, b->d_scale);
@@ -190,8 +229,10 @@ void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int
         else                                             \
             go_batch_x<R, Wc, true>(b, grid_x, 0, st);   \
     } while (0)
+    mark(1);
     SSCN_W_SWITCH(b->W, SSCN_CALL_BX);
 #undef SSCN_CALL_BX
+    mark(2);
 #define SSCN_CALL_BY(Wc)                             \
     do {                                             \
         if (imag)                                    \
@@ -201,11 +242,36 @@ void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int
     } while (0)
     SSCN_W_SWITCH(b->W, SSCN_CALL_BY);
 #undef SSCN_CALL_BY
+    mark(3);
     if (imag)
         b->pending = true;
 }
 
-template void batch_sweep_step<SSCN_REAL_T>(sscn_batch *, hipStream_t, int, int, int);
+template <class R, int W>
+hipError_t batch_allow_x_lds_w()
+{
+    hipError_t e = allow_x_lds((const void *)k_batch_xsweep<R, kSegX, W, false, 8>);
+    if (e == hipSuccess)
+        e = allow_x_lds((const void *)k_batch_xsweep<R, kSegX, W, false, kXLoad>);
+    if (e == hipSuccess)
+        e = allow_x_lds((const void *)k_batch_xsweep<R, kSegX, W, true, 8>);
+    if (e == hipSuccess)
+        e = allow_x_lds((const void *)k_batch_xsweep<R, kSegX, W, true, kXLoad>);
+    return e;
+}
+
+template <class R>
+hipError_t batch_allow_x_lds_all(int W)
+{
+    hipError_t e = hipSuccess;
+#define SSCN_CALL_A(Wc) e = batch_allow_x_lds_w<R, Wc>()
+    SSCN_W_SWITCH(W, SSCN_CALL_A)
+#undef SSCN_CALL_A
+    return e;
+}
+
+template void batch_sweep_step<SSCN_REAL_T>(sscn_batch *, hipStream_t, int, int, int, hipEvent_t *);
+template hipError_t batch_allow_x_lds_all<SSCN_REAL_T>(int);
 
 #endif
 

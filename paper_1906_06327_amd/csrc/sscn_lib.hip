@@ -24,6 +24,11 @@ namespace {
 
 thread_local std::string g_err;
 
+// Vortex count of the convergence criterion (sscn_converge, sscn_batch_run):
+// density fraction and box of sscn_vortex_count.
+constexpr double kConvDensityFrac = 0.05;
+constexpr int kConvBox = 3;
+
 int fail(int code, const std::string &msg)
 {
     g_err = msg;
@@ -131,7 +136,7 @@ int axis_setup(const sscn_params &p, int axis, AxisCoef &c, int &W)
 // + 1 padded points, the pivot-table rows and the wall terms.
 void set_x_lines(sscn_handle *h, int L)
 {
-    const size_t LS = (size_t)h->p.nx + h->p.nx / kSeg + 1;
+    const size_t LS = (size_t)h->p.nx + h->p.nx / kSegX + 1;
     h->xL = L;
     h->xlds = (L * LS + (size_t)L * (h->W[0] + 2) + L) * h->esize;
 }
@@ -174,7 +179,7 @@ int setup(sscn_handle *h)
     h->npts = npoints(p);
     h->esize = p.precision == SSCN_C128 ? 16 : 8;
     // x-sweep staging: L lines per block, one (line, segment) per thread
-    const int nseg = (p.nx - 2) / kSeg + 1;
+    const int nseg = (p.nx - 2) / kSegX + 1;
     int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / p.nx, 512 / (h->W[0] + 2)}));
     while (L & (L - 1))  // a power of two: 256 / L threads stage each line
         L &= L - 1;
@@ -201,6 +206,30 @@ int setup(sscn_handle *h)
                   h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32) && flds <= 150 * 1024;
     h->ntiles = ((p.nx - 2) / kTileC + 1) * ((p.ny - 2) / kTileR + 1);
     return 0;
+}
+
+// The fixed point c* = A+ / (A0 - A- c*) of the Thomas recurrence of a
+// diagonally dominant line: the root of A- c^2 - A0 c + A+ = 0 of smaller
+// modulus, c* = 2 A+ / (A0 + s) with s = sqrt(A0^2 - 4 A- A+) taken with
+// Re(conj(A0) s) >= 0 (no cancellation in A0 + s), then polished by the
+// recurrence itself.  Each iteration multiplies the error by
+// |A- c* r*| < 1/2 (r* = 1/(A0 - A- c*)), so it stops after a few, when the
+// change is within 4 ulps (at most 16 iterations).
+std::complex<double> pivot_fixed_point(std::complex<double> A0, std::complex<double> Am, std::complex<double> Ap)
+{
+    using cd = std::complex<double>;
+    cd sq = std::sqrt(A0 * A0 - 4.0 * Am * Ap);
+    if ((std::conj(A0) * sq).real() < 0.0)
+        sq = -sq;
+    cd c = 2.0 * Ap / (A0 + sq);
+    for (int it = 0; it < 16; ++it) {
+        const cd nc = Ap / (A0 - Am * c);
+        const bool done = std::abs(nc - c) <= 4.0 * 2.220446049250313e-16 * std::abs(nc);
+        c = nc;
+        if (done)
+            break;
+    }
+    return c;
 }
 
 // Pivot tables of the windowed solves, one row per distinct line of an axis
@@ -236,14 +265,7 @@ int build_tables(sscn_handle *h)
             else if (ax == 1)
                 rot = -p.omega * (h->args.x0 + ty * p.hx);
             const cd Ap = u + q * rot, Am = u - q * rot;
-            cd cs = 0.0;
-            for (int it = 0; it < 100000; ++it) {
-                const cd nc = Ap / (A0 - Am * cs);
-                const bool done = std::abs(nc - cs) <= 1e-18 * std::abs(nc);
-                cs = nc;
-                if (done)
-                    break;
-            }
+            const cd cs = pivot_fixed_point(A0, Am, Ap);
             const cd rs = 1.0 / (A0 - Am * cs);
             // z = T_abs^{-1} e_1: forward d'_1 = r*, d'_k = -A- r* d'_{k-1};
             // back z_m = d'_m, z_k = d'_k - c* z_{k+1}
@@ -392,6 +414,19 @@ int setup_fused(sscn_handle *h)
     return 0;
 }
 
+// Dynamic-LDS limit of the handle's x-sweep kernels (lines longer than the
+// default 64 KiB allow).
+int allow_x_lds(sscn_handle *h)
+{
+    if (h->exact)
+        return 0;
+    const hipError_t e = h->p.precision == SSCN_C128 ? allow_x_lds_all<double>(h->W[0])
+                                                     : allow_x_lds_all<float>(h->W[0]);
+    if (e != hipSuccess)
+        return fail(SSCN_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
+    return 0;
+}
+
 // One SSCN step on stream st.  npart > 0: the partials hold the norm of the
 // (unnormalised) state and the rescale is folded into H1.  ev (optional, 4
 // events) is recorded before the x-, y-, z-sweeps and after the step.
@@ -483,39 +518,94 @@ void enqueue_direct(sscn_handle *h, int64_t n, hipStream_t st)
     }
 }
 
-int build_graph(sscn_handle *h)
+// Find, or capture and instantiate, the graph of k steps in `cache` (at most
+// kGraphCache entries: the oldest is destroyed first).  enqueue(k, stream)
+// records the k steps; `capture` is the handle's capture stream.
+template <class Enq>
+int cached_graph(std::vector<std::pair<int64_t, hipGraphExec_t>> &cache, hipStream_t capture, int64_t k, Enq enqueue,
+                 hipGraphExec_t *out)
 {
-    if (h->gexec)
-        return 0;
-    HIPCHECK(hipStreamBeginCapture(h->cap, hipStreamCaptureModeThreadLocal));
-    const bool was = h->pending;
-    h->pending = false;
-    if (h->p.precision == SSCN_C128)
-        enqueue_direct<double>(h, kGraphSteps, h->cap);
-    else
-        enqueue_direct<float>(h, kGraphSteps, h->cap);
-    h->pending = was;
-    hipError_t e = hipStreamEndCapture(h->cap, &h->graph);
+    for (const auto &e : cache)
+        if (e.first == k) {
+            *out = e.second;
+            return 0;
+        }
+    HIPCHECK(hipStreamBeginCapture(capture, hipStreamCaptureModeThreadLocal));
+    enqueue(k, capture);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(capture, &g);
     if (e != hipSuccess)
         return fail(SSCN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    e = hipGraphInstantiate(&h->gexec, h->graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(h->graph);
-        h->graph = nullptr;
-        h->gexec = nullptr;
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess)
         return fail(SSCN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    if (cache.size() >= kGraphCache) {
+        (void)hipGraphExecDestroy(cache.front().second);
+        cache.erase(cache.begin());
     }
+    cache.emplace_back(k, x);
+    *out = x;
     return 0;
 }
 
-void drop_graph(sscn_handle *h)
+void drop_graphs(std::vector<std::pair<int64_t, hipGraphExec_t>> &cache)
 {
-    if (h->gexec)
-        (void)hipGraphExecDestroy(h->gexec);
-    if (h->graph)
-        (void)hipGraphDestroy(h->graph);
-    h->gexec = nullptr;
-    h->graph = nullptr;
+    for (auto &e : cache)
+        (void)hipGraphExecDestroy(e.second);
+    cache.clear();
+}
+
+// The graph of k steps of a single instance.  A stepping call leaves the
+// state normalised with no pending rescale, so every graph is captured from
+// that state; the host-side step bookkeeping is restored after the capture.
+int step_graph(sscn_handle *h, int64_t k, hipGraphExec_t *out)
+{
+    auto enq = [h](int64_t n, hipStream_t st) {
+        const bool pending = h->pending;
+        const int fparity = h->fparity, pbuf = h->pbuf;
+        h->pending = false;
+        if (h->p.precision == SSCN_C128)
+            enqueue_direct<double>(h, n, st);
+        else
+            enqueue_direct<float>(h, n, st);
+        h->pending = pending;
+        h->fparity = fparity;
+        h->pbuf = pbuf;
+    };
+    return cached_graph(h->graphs, h->cap, k, enq, out);
+}
+
+void drop_graph(sscn_handle *h) { drop_graphs(h->graphs); }
+
+// The graphs a call of nsteps steps replays: nsteps = q G + r with G =
+// min(nsteps, kGraphSteps): q launches of the G-step graph, then the r-step
+// graph (r >= 2) or one direct step (r = 1).  launch = false only captures
+// them.
+int run_step_graphs(sscn_handle *h, int64_t nsteps, bool launch)
+{
+    const int64_t G = std::min<int64_t>(nsteps, kGraphSteps);
+    const int64_t q = nsteps / G, r = nsteps % G;
+    hipGraphExec_t x = nullptr;
+    int rc = step_graph(h, G, &x);
+    if (rc)
+        return rc;
+    for (int64_t t = 0; launch && t < q; ++t)
+        HIPCHECK(hipGraphLaunch(x, h->stream));
+    if (r >= 2) {
+        rc = step_graph(h, r, &x);
+        if (rc)
+            return rc;
+        if (launch)
+            HIPCHECK(hipGraphLaunch(x, h->stream));
+    } else if (r == 1 && launch) {
+        if (h->p.precision == SSCN_C128)
+            enqueue_direct<double>(h, 1, h->stream);
+        else
+            enqueue_direct<float>(h, 1, h->stream);
+    }
+    return 0;
 }
 
 // Autotuner: on the first step of a handle whose plan is SSCN_PLAN_AUTO,
@@ -729,6 +819,27 @@ void free_buffers(sscn_handle *h)
     h->ws = nullptr;
 }
 
+// Free the device buffers that depend on the grid and parameters (work,
+// exact-path workspace, pivot tables, norm partials and the fused-step
+// descriptors), leaving the handle's observables buffers, phase buffer and
+// capture stream.
+void release_step_buffers(sscn_handle *h)
+{
+    free_buffers(h);
+    for (int ax = 0; ax < 3; ++ax) {
+        if (h->tab[ax])
+            (void)hipFree(h->tab[ax]);
+        h->tab[ax] = nullptr;
+    }
+    void **bufs[] = {(void **)&h->partials, (void **)&h->d_inst, (void **)&h->d_work, (void **)&h->d_nwork,
+                     (void **)&h->partials2};
+    for (void **q : bufs) {
+        if (*q)
+            (void)hipFree(*q);
+        *q = nullptr;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Batched 2D instances (one fused launch per step over all their tiles).
 
@@ -801,14 +912,17 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
 
 // nsteps fused steps of every listed instance, then the finish pass that
 // leaves each state normalised (imaginary time) in its caller buffer.
+// ev (optional, 4 events per step): the sweep plan records them around its
+// kernels (batch_sweep_step); the fused plan records ev[4s] before step s's
+// launch and the other three after it.
 template <class R>
 void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles, int grid_chunks, int grid_x,
-                   int grid_y, int grid_k)
+                   int grid_y, int grid_k, hipEvent_t *ev = nullptr)
 {
     const bool imag = b->mode == SSCN_IMAG;
     if (b->active_plan == SSCN_PLAN_SWEEPS) {
         for (int64_t s = 0; s < nsteps; ++s)
-            batch_sweep_step<R>(b, st, grid_x, grid_y, grid_k);
+            batch_sweep_step<R>(b, st, grid_x, grid_y, grid_k, ev ? ev + 4 * s : nullptr);
         if (imag && b->pending) {
             hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
                                b->d_nk, b->ypart, b->d_scale);
@@ -821,10 +935,15 @@ void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles
     }
     const FusedLaunch f{b->d_inst, b->d_work, b->d_nwork, std::max(grid_tiles, 1), b->W, nullptr};
     for (int64_t s = 0; s < nsteps; ++s) {
+        if (ev)
+            (void)hipEventRecord(ev[4 * s], st);
         if (imag)
             launch_fused<R, false>(f, b->fparity, b->part[b->pbuf], b->part[b->pbuf ^ 1], b->pending ? 1 : 0, st);
         else
             launch_fused<R, true>(f, b->fparity, nullptr, nullptr, 0, st);
+        if (ev)
+            for (int t = 1; t < 4; ++t)
+                (void)hipEventRecord(ev[4 * s + t], st);
         b->fparity ^= 1;
         if (imag) {
             b->pbuf ^= 1;
@@ -848,18 +967,38 @@ void batch_drop_graph(sscn_batch *b)
     b->gexec = nullptr;
     b->graph = nullptr;
     b->graph_k = 0;
+    drop_graphs(b->step_graphs);
+}
+
+// Record k steps of every listed instance on stream st for a graph: the
+// launch grids cover every instance (the kernels read the current list
+// lengths on the device, so the graph stays valid when converged instances
+// leave the lists); the host-side step bookkeeping is restored after.
+void batch_capture_steps(sscn_batch *b, int64_t k, hipStream_t st)
+{
+    const int fparity = b->fparity, pbuf = b->pbuf;
+    const bool pending = b->pending;
+    if (b->precision == SSCN_C128)
+        batch_enqueue<double>(b, k, st, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
+    else
+        batch_enqueue<float>(b, k, st, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
+    b->fparity = fparity;
+    b->pbuf = pbuf;
+    b->pending = pending;
 }
 
 int batch_graph(sscn_batch *b, int k)
 {
     if (b->gexec && b->graph_k == k)
         return 0;
-    batch_drop_graph(b);
+    if (b->gexec)
+        (void)hipGraphExecDestroy(b->gexec);
+    if (b->graph)
+        (void)hipGraphDestroy(b->graph);
+    b->gexec = nullptr;
+    b->graph = nullptr;
     HIPCHECK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
-    if (b->precision == SSCN_C128)
-        batch_enqueue<double>(b, k, b->cap, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
-    else
-        batch_enqueue<float>(b, k, b->cap, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
+    batch_capture_steps(b, k, b->cap);
     hipError_t e = hipStreamEndCapture(b->cap, &b->graph);
     if (e != hipSuccess)
         return fail(SSCN_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
@@ -870,13 +1009,53 @@ int batch_graph(sscn_batch *b, int k)
     return 0;
 }
 
+// The graphs a sscn_batch_step call of nsteps steps replays: nsteps = q G +
+// r, G = min(nsteps, kBatchGraphSteps); q launches of the G-step graph, then
+// the r-step graph (r >= 2) or one direct step.  launch = false only
+// captures them.
+int batch_run_step_graphs(sscn_batch *b, int64_t nsteps, bool launch)
+{
+    const int64_t G = std::min<int64_t>(nsteps, kBatchGraphSteps);
+    const int64_t q = nsteps / G, r = nsteps % G;
+    auto enq = [b](int64_t n, hipStream_t st) { batch_capture_steps(b, n, st); };
+    hipGraphExec_t x = nullptr;
+    int rc = cached_graph(b->step_graphs, b->cap, G, enq, &x);
+    if (rc)
+        return rc;
+    for (int64_t t = 0; launch && t < q; ++t)
+        HIPCHECK(hipGraphLaunch(x, b->stream));
+    if (r >= 2) {
+        rc = cached_graph(b->step_graphs, b->cap, r, enq, &x);
+        if (rc)
+            return rc;
+        if (launch)
+            HIPCHECK(hipGraphLaunch(x, b->stream));
+    } else if (r == 1 && launch) {
+        if (b->precision == SSCN_C128)
+            batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+        else
+            batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+    }
+    return 0;
+}
+
+// Observables of the listed instances into d_sums; with tol > 0 also a
+// convergence check: the vortex count of every listed instance and the
+// criterion of sscn_converge (k_batch_conv).
 template <class R>
 void batch_obs_launch(sscn_batch *b, int nchunks, double tol)
 {
     hipLaunchKernelGGL((k_batch_obs<R>), dim3(std::max(nchunks, 1)), dim3(256), 0, b->stream, b->d_inst, b->d_owork,
                        b->d_no, b->opart);
     hipLaunchKernelGGL(k_batch_obs_final, dim3(b->n), dim3(256), 0, b->stream, b->n, b->d_obase, b->d_ocount,
-                       b->opart, b->d_sums, b->d_mu_prev, b->d_hits, b->d_conv, tol, (long long)b->steps);
+                       b->opart, b->d_sums);
+    if (tol > 0.0) {
+        hipLaunchKernelGGL((k_batch_vortex<R>), dim3(std::max(nchunks, 1)), dim3(256), 0, b->stream, b->d_inst,
+                           b->d_owork, b->d_no, (const double *)b->d_sums, kConvDensityFrac, kConvBox, b->vpart);
+        hipLaunchKernelGGL(k_batch_conv, dim3((b->n + 255) / 256), dim3(256), 0, b->stream, b->n, b->d_obase,
+                           b->d_ocount, (const double *)b->vpart, (const double *)b->d_sums, b->d_mu_prev, b->d_hits,
+                           b->d_count_prev, b->d_counts, b->d_conv, tol, (long long)b->steps);
+    }
 }
 
 // The first stepping call of an SSCN_PLAN_AUTO batch times 8 steps of each
@@ -905,6 +1084,15 @@ int batch_autotune(sscn_batch *b)
         b->pending = false;
         b->fparity = 0;
         b->pbuf = 0;
+        // one untimed step first: the first launch of a kernel also loads its
+        // code object, which must not count against the plan
+        if (b->precision == SSCN_C128)
+            batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+        else
+            batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+        for (int k = 0; k < b->n; ++k)
+            HIPCHECK(hipMemcpyAsync(b->psi[k], saved + off[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice,
+                                    b->stream));
         hipEvent_t e0, e1;
         (void)hipEventCreate(&e0);
         (void)hipEventCreate(&e1);
@@ -947,6 +1135,7 @@ void batch_free(sscn_batch *b)
                 (void)hipFree(q);
     void *bufs[] = {b->d_inst, b->d_work, b->d_fwork, b->d_owork, b->d_nwork, b->d_nf, b->d_no, b->d_obase,
                     b->d_ocount, b->part[0], b->part[1], b->opart, b->d_sums, b->d_mu_prev, b->d_hits, b->d_conv,
+                    b->d_count_prev, b->d_counts, b->vpart,
                     b->phase, b->d_xwork, b->d_ywork, b->d_nx, b->d_ny, b->d_klist, b->d_nk, b->ypart,
                     b->d_scale};
     for (void *q : bufs)
@@ -1018,6 +1207,9 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
     if (hipMemsetAsync(h->partials, 0, npart * sizeof(double), h->stream) != hipSuccess)
         return bail(fail(SSCN_EHIP, "hipMemsetAsync failed"));
     r = setup_fused(h);
+    if (r)
+        return bail(r);
+    r = allow_x_lds(h);
     if (r)
         return bail(r);
     if (const char *env = std::getenv("SSCN_PLAN")) {
@@ -1101,6 +1293,19 @@ int sscn_init_state(sscn_handle *h, int kind, const double *phase_host, double d
     return 0;
 }
 
+int sscn_prepare_steps(sscn_handle *h, int64_t nsteps)
+{
+    if (!h || nsteps < 0)
+        return fail(SSCN_EINVAL, "bad prepare_steps arguments");
+    int r = autotune(h);
+    if (!r && nsteps >= 2)
+        r = run_step_graphs(h, nsteps, false);
+    if (r)
+        return r;
+    HIPCHECK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
 int sscn_step(sscn_handle *h, int64_t nsteps)
 {
     if (!h || nsteps < 0)
@@ -1110,20 +1315,15 @@ int sscn_step(sscn_handle *h, int64_t nsteps)
     int r0 = autotune(h);
     if (r0)
         return r0;
-    int64_t rem = nsteps;
-    if (nsteps >= kGraphSteps && !h->pending) {
-        int r = build_graph(h);
+    if (nsteps >= 2 && !h->pending) {
+        int r = run_step_graphs(h, nsteps, true);
         if (r)
             return r;
-        while (rem >= kGraphSteps) {
-            HIPCHECK(hipGraphLaunch(h->gexec, h->stream));
-            rem -= kGraphSteps;
-        }
+    } else if (h->p.precision == SSCN_C128) {
+        enqueue_direct<double>(h, nsteps, h->stream);
+    } else {
+        enqueue_direct<float>(h, nsteps, h->stream);
     }
-    if (h->p.precision == SSCN_C128)
-        enqueue_direct<double>(h, rem, h->stream);
-    else
-        enqueue_direct<float>(h, rem, h->stream);
     HIPCHECK(hipGetLastError());
     h->steps += nsteps;
     return 0;
@@ -1280,14 +1480,34 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
     const bool conv = precision != h->p.precision;
     if (conv && !new_psi_dev)
         return fail(SSCN_EINVAL, "a precision change needs the new state buffer");
-    sscn_handle tmp;
-    tmp.p = np;
-    r = setup(&tmp);
-    if (r)
-        return r;
     HIPCHECK(hipStreamSynchronize(h->stream));
-    drop_graph(h);
-    if (conv) {
+    // The new configuration is built completely in a second handle (every
+    // device allocation included) before anything of h changes, so that an
+    // error leaves h as it was.
+    sscn_handle *t = new sscn_handle();
+    t->p = np;
+    t->psi = conv ? new_psi_dev : h->psi;
+    t->stream = h->stream;
+    auto drop_t = [&](int code) {
+        release_step_buffers(t);
+        delete t;
+        return code;
+    };
+    r = setup(t);
+    if (!r)
+        r = alloc_buffers(t);
+    if (!r)
+        r = build_tables(t);
+    if (!r) {
+        const size_t npart = std::max({(size_t)t->nemit, (size_t)kRedBlocks, (size_t)t->ntiles});
+        if (hipMalloc(&t->partials, npart * sizeof(double)) != hipSuccess)
+            r = fail(SSCN_ENOMEM, "hipMalloc of the partials failed");
+    }
+    if (!r)
+        r = setup_fused(t);
+    if (!r)
+        r = allow_x_lds(t);
+    if (!r && conv) {
         const int nb = red_blocks(h->npts);
         if (h->p.precision == SSCN_C64)
             hipLaunchKernelGGL((k_convert<float, double>), dim3(nb), dim3(256), 0, h->stream,
@@ -1295,37 +1515,37 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
         else
             hipLaunchKernelGGL((k_convert<double, float>), dim3(nb), dim3(256), 0, h->stream,
                                (const V<double> *)h->psi, (V<float> *)new_psi_dev, h->npts);
-        HIPCHECK(hipGetLastError());
-        HIPCHECK(hipStreamSynchronize(h->stream));
-        h->psi = new_psi_dev;
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(h->stream) != hipSuccess)
+            r = fail(SSCN_EHIP, "the precision conversion failed");
     }
-    free_buffers(h);
+    if (r)
+        return drop_t(r);
+    // commit: h takes t's configuration and buffers, t takes h's old buffers
+    drop_graph(h);
+    release_step_buffers(h);
     const int64_t steps = h->steps;
+    const int plan = h->plan;
     h->p = np;
-    r = setup(h);
-    if (r)
-        return r;
-    r = alloc_buffers(h);
-    if (r)
-        return r;
-    r = build_tables(h);
-    if (r)
-        return r;
-    // the partials buffer must hold the new emit count
-    (void)hipFree(h->partials);
-    const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, (size_t)h->ntiles});
-    if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess)
-        return fail(SSCN_ENOMEM, "hipMalloc of the partials failed");
-    r = setup_fused(h);
-    if (r)
-        return r;
-    if (h->plan == SSCN_PLAN_FUSED && !h->fused_ok)
-        h->plan = SSCN_PLAN_AUTO;
+    h->psi = t->psi;
+    r = setup(h);  // host-side geometry; cannot fail (it succeeded for t)
+    (void)r;
+    h->work = t->work;
+    h->ws = t->ws;
+    for (int ax = 0; ax < 3; ++ax)
+        h->tab[ax] = t->tab[ax];
+    h->partials = t->partials;
+    h->d_inst = t->d_inst;
+    h->d_work = t->d_work;
+    h->d_nwork = t->d_nwork;
+    h->partials2 = t->partials2;
+    h->inst_host = t->inst_host;
+    delete t;  // owns nothing now
+    h->plan = (plan == SSCN_PLAN_FUSED && !h->fused_ok) ? SSCN_PLAN_AUTO : plan;
     h->active_plan = h->plan == SSCN_PLAN_FUSED ? SSCN_PLAN_FUSED : SSCN_PLAN_SWEEPS;
     h->fparity = 0;
+    h->pbuf = 0;
     h->steps = steps;
     h->pending = false;
-    HIPCHECK(hipStreamSynchronize(h->stream));
     return 0;
 }
 
@@ -1584,7 +1804,7 @@ int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *pla
         if (window_xyz)
             window_xyz[a] = h->exact ? 0 : h->W[a];
         if (segment_xyz)
-            segment_xyz[a] = h->exact ? 0 : kSeg;
+            segment_xyz[a] = h->exact ? 0 : (a == 0 && h->active_plan != SSCN_PLAN_FUSED ? kSegX : kSeg);
     }
     return 0;
 }
@@ -1647,7 +1867,7 @@ int sscn_converge(sscn_handle *h, int64_t max_steps, int check_every, double tol
         }
         if (d < tol) {
             int c = 0;
-            r = sscn_vortex_count(h, 0.05, 3, &c);
+            r = sscn_vortex_count(h, kConvDensityFrac, kConvBox, &c);
             if (r)
                 return r;
             hits = (count_prev < 0 || c == count_prev) ? hits + 1 : 1;
@@ -1755,11 +1975,11 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         in.tab[1] = b->taby.back();
         // sweep plan: x-sweep staging as for a single instance (L a power of
         // two), the y tile grid and the offset of this instance's y partials
-        const int nseg = (h.p.nx - 2) / kSeg + 1;
+        const int nseg = (h.p.nx - 2) / kSegX + 1;
         int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / h.p.nx, 512 / (b->W + 2)}));
         while (L & (L - 1))
             L &= L - 1;
-        const size_t LS = (size_t)h.p.nx + h.p.nx / kSeg + 1;
+        const size_t LS = (size_t)h.p.nx + h.p.nx / kSegX + 1;
         const size_t xl = (L * LS + (size_t)L * (b->W + 2) + L) * esize;
         if (nseg > 256 || h.p.nx > 256 * kXLoad || xl > kXLdsCap)
             b->sweeps_ok = false;
@@ -1796,6 +2016,9 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         hipMalloc(&b->d_sums, sizeof(double) * (kObsN * n + 2)) != hipSuccess ||
         hipMalloc(&b->d_mu_prev, sizeof(double) * n) != hipSuccess ||
         hipMalloc(&b->d_hits, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&b->d_count_prev, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&b->d_counts, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&b->vpart, sizeof(double) * std::max(b->total_chunks, 1)) != hipSuccess ||
         hipMalloc(&b->d_conv, sizeof(long long) * n) != hipSuccess ||
         hipMalloc(&b->d_xwork, sizeof(int2) * std::max(b->total_x, 1)) != hipSuccess ||
         hipMalloc(&b->d_ywork, sizeof(int2) * std::max(b->total_y, 1)) != hipSuccess ||
@@ -1809,6 +2032,8 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
     if (r)
         return bail(r);
     hipError_t e = b->precision == SSCN_C128 ? allow_fused_lds_all<double>(b->W) : allow_fused_lds_all<float>(b->W);
+    if (e == hipSuccess && b->sweeps_ok)
+        e = b->precision == SSCN_C128 ? batch_allow_x_lds_all<double>(b->W) : batch_allow_x_lds_all<float>(b->W);
     if (e != hipSuccess)
         return bail(fail(SSCN_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e)));
     *out = b;
@@ -1826,6 +2051,9 @@ int sscn_batch_reset(sscn_batch *b)
     std::vector<long long> neg(b->n, -1);
     HIPCHECK(hipMemcpy(b->d_mu_prev, nan.data(), sizeof(double) * b->n, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b->d_hits, zero.data(), sizeof(int) * b->n, hipMemcpyHostToDevice));
+    std::vector<int> none(b->n, -1);
+    HIPCHECK(hipMemcpy(b->d_count_prev, none.data(), sizeof(int) * b->n, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_counts, none.data(), sizeof(int) * b->n, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b->d_conv, neg.data(), sizeof(long long) * b->n, hipMemcpyHostToDevice));
     return batch_lists(b);
 }
@@ -1868,6 +2096,19 @@ int sscn_batch_init_state(sscn_batch *b, int k, int kind, const double *phase_ho
     return 0;
 }
 
+int sscn_batch_prepare_steps(sscn_batch *b, int64_t nsteps)
+{
+    if (!b || nsteps < 0)
+        return fail(SSCN_EINVAL, "bad batch_prepare_steps arguments");
+    int r = batch_autotune(b);
+    if (!r && nsteps >= 2)
+        r = batch_run_step_graphs(b, nsteps, false);
+    if (r)
+        return r;
+    HIPCHECK(hipStreamSynchronize(b->stream));
+    return 0;
+}
+
 int sscn_batch_step(sscn_batch *b, int64_t nsteps)
 {
     if (!b || nsteps < 0)
@@ -1877,13 +2118,73 @@ int sscn_batch_step(sscn_batch *b, int64_t nsteps)
     int r = batch_autotune(b);
     if (r)
         return r;
-    if (b->precision == SSCN_C128)
+    if (nsteps >= 2) {
+        r = batch_run_step_graphs(b, nsteps, true);
+        if (r)
+            return r;
+    } else if (b->precision == SSCN_C128) {
         batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
-    else
+    } else {
         batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+    }
     HIPCHECK(hipGetLastError());
     b->steps += nsteps;
     return 0;
+}
+
+int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out)
+{
+    if (!b || !ms_out || nsteps < 1 || nsteps > 100000)
+        return fail(SSCN_EINVAL, "bad batch_profile_step arguments");
+    int r = batch_autotune(b);
+    if (r)
+        return r;
+    std::vector<hipEvent_t> ev((size_t)nsteps * 4, nullptr);
+    int rc = 0;
+    for (auto &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            rc = fail(SSCN_EHIP, "hipEventCreate failed");
+            break;
+        }
+    if (!rc) {
+        if (b->precision == SSCN_C128)
+            batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y,
+                                  b->grid_k, ev.data());
+        else
+            batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y,
+                                 b->grid_k, ev.data());
+        b->steps += nsteps;
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
+            rc = fail(SSCN_EHIP, "the profiled batch steps failed");
+    }
+    double acc[4] = {0, 0, 0, 0};
+    for (int64_t s = 0; s < nsteps && !rc; ++s) {
+        const hipEvent_t *e = &ev[(size_t)s * 4];
+        float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
+        if (hipEventElapsedTime(&t01, e[0], e[1]) != hipSuccess || hipEventElapsedTime(&t12, e[1], e[2]) != hipSuccess ||
+            hipEventElapsedTime(&t23, e[2], e[3]) != hipSuccess || hipEventElapsedTime(&t03, e[0], e[3]) != hipSuccess)
+            rc = fail(SSCN_EHIP, "hipEventElapsedTime failed");
+        acc[0] += t01;
+        acc[1] += t12;
+        acc[2] += t23;
+        acc[3] += t03;
+    }
+    if (!rc) {
+        const double n = (double)nsteps;
+        if (b->active_plan == SSCN_PLAN_SWEEPS) {
+            ms_out[0] = acc[1] / n;  // x-sweep
+            ms_out[1] = acc[2] / n;  // y-sweep
+            ms_out[2] = acc[0] / n;  // rescale kernel
+        } else {
+            ms_out[0] = acc[0] / n;  // fused step
+            ms_out[1] = ms_out[2] = 0.0;
+        }
+        ms_out[3] = acc[3] / n;
+    }
+    for (auto &e : ev)
+        if (e)
+            (void)hipEventDestroy(e);
+    return rc;
 }
 
 int sscn_batch_observables(sscn_batch *b, sscn_obs *out)

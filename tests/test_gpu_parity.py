@@ -299,7 +299,10 @@ def test_deterministic_and_restartable(P):
     a2.init_state(1, ph, 1.0)
     a2.step(300)
     assert np.array_equal(a2.get_state(), ra)       # run-to-run bitwise
-    assert rel(rc, ra) <= 1e-13                      # restart (graph split differs)
+    # restart bitwise: the rescale that ends a call (k_rescale) and the one
+    # folded into the next step sum the norm partials in the same order, so
+    # a run restarted from a saved state repeats the uninterrupted run
+    assert np.array_equal(rc, ra)
     for s in (a, a2, c):
         s.close()
 
