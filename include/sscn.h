@@ -139,6 +139,24 @@ int sscn_prepare_steps(sscn_handle *h, int64_t nsteps);
  * fast rotation. */
 int sscn_observables(sscn_handle *h, sscn_obs *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the raw
+ * sums of sscn_observables (sums[0..15] of sscn_obs, integrals already times
+ * h^d, sums_dev[13] the max density) of the state psi_dev, described by
+ * params (layout and precision as for sscn_init; the parameters are
+ * validated as there), written to the caller-owned device buffer sums_dev
+ * (16 doubles).  No handle; asynchronous on hip_stream (NULL: the null
+ * stream); it calls no allocating routine.  The per-block partial sums go
+ * to a static scratch array of the library (1024 rows of 16 doubles, 128
+ * KiB per GPU, held until the process ends), so concurrent calls on one GPU
+ * race: serialise them (one stream, or events).  The kernels and the
+ * reduction order are those of sscn_observables, so the sums are the same
+ * bits.  SSCN_EINVAL for null pointers or invalid parameters, SSCN_EOMEGA as
+ * sscn_init, SSCN_EHIP if the scratch address cannot be obtained or a launch
+ * fails. */
+int sscn_observables_noalloc(const sscn_params *params, const void *psi_dev, void *hip_stream,
+                             double *sums_dev);
+
 /* Copy a host state (same layout and precision as psi) into psi, zeroing
  * the walls (paper's NSTP = 0 restart).  Synchronises the stream. */
 int sscn_set_state(sscn_handle *h, const void *host_psi);

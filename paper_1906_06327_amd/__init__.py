@@ -21,7 +21,7 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
           -4: "SSCN_ENONFINITE", -5: "SSCN_EHIP", -6: "SSCN_ENOMEM"}
 
 # Every symbol include/sscn.h declares.
-EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_prepare_steps", "sscn_observables",
+EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_prepare_steps", "sscn_observables", "sscn_observables_noalloc",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step", "sscn_batch_prepare_steps", "sscn_batch_profile_step",
@@ -71,6 +71,7 @@ def lib():
         L.sscn_step.argtypes = [vp, i64]
         L.sscn_prepare_steps.argtypes = [vp, i64]
         L.sscn_observables.argtypes = [vp, ctypes.POINTER(Obs)]
+        L.sscn_observables_noalloc.argtypes = [ctypes.POINTER(Params), vp, vp, vp]
         L.sscn_set_state.argtypes = [vp, vp]
         L.sscn_set_state_device.argtypes = [vp]
         L.sscn_get_state.argtypes = [vp, vp]
@@ -174,6 +175,24 @@ def extend_z(xy, dst, hz, d_z, stream=None):
     _check(lib().sscn_extend_z(ctypes.c_void_p(xy.data_ptr()), xy.shape[1], xy.shape[0],
                                ctypes.c_void_p(dst.data_ptr()), dst.shape[0], float(hz), float(d_z), prec,
                                ctypes.c_void_p(st.cuda_stream)))
+
+
+def observables_noalloc(params, psi, sums, stream=None):
+    """The raw observable sums of the device state tensor `psi` (the
+    sscn_obs.sums of sscn_observables) into the float64 device tensor `sums`
+    (16 values), without a handle and without allocating: the library's
+    static scratch holds the partials (include/sscn.h,
+    sscn_observables_noalloc).  Asynchronous on `stream` (default: the
+    current torch stream)."""
+    import torch
+    p = params if isinstance(params, Params) else make_params(**params)
+    if sums.dtype != torch.float64 or sums.numel() < 16 or not sums.is_contiguous():
+        raise ValueError("sums must be a contiguous float64 device tensor of 16 values")
+    if not psi.is_contiguous():
+        raise ValueError("psi must be contiguous")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().sscn_observables_noalloc(ctypes.byref(p), ctypes.c_void_p(psi.data_ptr()),
+                                          ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(sums.data_ptr())))
 
 
 class Solver:

@@ -141,10 +141,10 @@ void set_x_lines(sscn_handle *h, int L)
     h->xlds = (L * LS + (size_t)L * (h->W[0] + 2) + L) * h->esize;
 }
 
-int setup(sscn_handle *h)
+// Grid geometry and physical constants of the step and observables kernels
+// (everything of StepArgs but the per-axis line coefficients).
+void fill_args(const sscn_params &p, StepArgs &a)
 {
-    const sscn_params &p = h->p;
-    StepArgs &a = h->args;
     a.dim = p.dim;
     a.nx = p.nx;
     a.ny = p.ny;
@@ -162,6 +162,13 @@ int setup(sscn_handle *h)
     a.omega = p.omega;
     a.dt = p.dt;
     a.dV = p.hx * p.hy * (p.dim == 3 ? p.hz : 1.0);
+}
+
+int setup(sscn_handle *h)
+{
+    const sscn_params &p = h->p;
+    StepArgs &a = h->args;
+    fill_args(p, a);
     h->exact = false;
     for (int ax = 0; ax < p.dim; ++ax) {
         int r = axis_setup(p, ax, a.ax[ax], h->W[ax]);
@@ -1329,6 +1336,83 @@ int sscn_step(sscn_handle *h, int64_t nsteps)
     return 0;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of sscn_observables_noalloc: the per-block partial sums of the
+// observables kernel (at most kRedBlocks rows of kObsN doubles, 128 KiB),
+// in device memory that exists from the library's load on, one copy per
+// GPU.  Host code must not use the name as an address: every call takes the
+// device address of the current GPU's copy from noalloc_scratch().
+constexpr int kNoallocRows = kRedBlocks;
+static __device__ __align__(256) double scratch[kNoallocRows * kObsN];
+
+std::mutex g_scratch_mu;
+std::map<int, double *> g_scratch_ptr;  // device ordinal -> address of its scratch
+
+// The current device's scratch address, looked up once per device with
+// hipGetSymbolAddress (no allocation).
+int noalloc_scratch(double **out)
+{
+    int dev = 0;
+    HIPCHECK(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        HIPCHECK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        it = g_scratch_ptr.emplace(dev, (double *)ptr).first;
+    }
+    *out = it->second;
+    return 0;
+}
+
+// sums[t] *= dV for every sum but the maximum density (t = 13), as the host
+// does for sscn_observables.
+__global__ __launch_bounds__(64) void k_scale_obs_sums(double *sums, double dV)
+{
+    const int t = threadIdx.x;
+    if (t < kObsN && t != 13)
+        sums[t] *= dV;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sscn_observables_noalloc(const sscn_params *params, const void *psi_dev, void *hip_stream, double *sums_dev)
+{
+    if (!params || !psi_dev || !sums_dev)
+        return fail(SSCN_EINVAL, "null argument");
+    sscn_params p = *params;
+    if (p.dim == 2)
+        p.nz = 1;
+    int r = validate(p);
+    if (r)
+        return r;
+    StepArgs a{};
+    fill_args(p, a);
+    const int64_t n = npoints(p);
+    const int nb = red_blocks(n);
+    if (nb > kNoallocRows)  // red_blocks never exceeds kRedBlocks; kept as the stated limit
+        return fail(SSCN_EINVAL, "more partial rows than the static scratch holds");
+    double *part = nullptr;
+    r = noalloc_scratch(&part);
+    if (r)
+        return r;
+    hipStream_t st = (hipStream_t)hip_stream;
+    if (p.precision == SSCN_C128)
+        hipLaunchKernelGGL((k_observables<double>), dim3(nb), dim3(256), 0, st, (const V<double> *)psi_dev, a, part);
+    else
+        hipLaunchKernelGGL((k_observables<float>), dim3(nb), dim3(256), 0, st, (const V<float> *)psi_dev, a, part);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, st, (const double *)part, nb, kObsN, 1u << 13,
+                       sums_dev);
+    hipLaunchKernelGGL(k_scale_obs_sums, dim3(1), dim3(64), 0, st, sums_dev, a.dV);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
 int sscn_observables(sscn_handle *h, sscn_obs *out)
 {
     if (!h || !out)
@@ -1691,21 +1775,21 @@ int profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms)
     const bool imag = h->p.mode == SSCN_IMAG;
     const bool fused = h->active_plan == SSCN_PLAN_FUSED;
     const int npk = std::max({h->nemit, h->ntiles, kRedBlocks});
-    double *scratch = nullptr;
-    if (hipMalloc(&scratch, sizeof(double) * 2 * npk) != hipSuccess)
+    double *prof_part = nullptr;
+    if (hipMalloc(&prof_part, sizeof(double) * 2 * npk) != hipSuccess)
         return fail(SSCN_ENOMEM, "hipMalloc of the profiling partials failed");
-    HIPCHECK(hipMemsetAsync(scratch, 0, sizeof(double) * 2 * npk, h->stream));
-    sscn_handle t = *h;  // the same kernels with partials into the scratch
-    t.partials = scratch;
+    HIPCHECK(hipMemsetAsync(prof_part, 0, sizeof(double) * 2 * npk, h->stream));
+    sscn_handle t = *h;  // the same kernels with partials into the prof_part
+    t.partials = prof_part;
     const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0], &h->inst_host};
     auto launch = [&](bool first) {
         if (fused) {
             if (imag)
-                launch_fused<R, false>(f, 0, scratch, scratch + npk, first ? 0 : 1, h->stream);
+                launch_fused<R, false>(f, 0, prof_part, prof_part + npk, first ? 0 : 1, h->stream);
             else
                 launch_fused<R, true>(f, 0, nullptr, nullptr, 0, h->stream);
             if (imag && first)  // the partials of this state are the next launches' input
-                (void)hipMemcpyAsync(scratch, scratch + npk, sizeof(double) * npk, hipMemcpyDeviceToDevice,
+                (void)hipMemcpyAsync(prof_part, prof_part + npk, sizeof(double) * npk, hipMemcpyDeviceToDevice,
                                      h->stream);
         } else if (which == 0) {
             if (imag)
@@ -1730,7 +1814,7 @@ int profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms)
             launch_y<R, true>(&t, h->psi, h->work, h->stream);
         else
             launch_z<R, true>(&t, h->psi, h->work, h->stream);
-        hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, h->stream, scratch, h->nemit, h->args.dV,
+        hipLaunchKernelGGL(k_norm_scale, dim3(1), dim3(256), 0, h->stream, prof_part, h->nemit, h->args.dV,
                            h->obs_buf + kScaleSlot);
     }
     launch(true);
@@ -1755,7 +1839,7 @@ int profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms)
     if (e1)
         (void)hipEventDestroy(e1);
     (void)hipStreamSynchronize(h->stream);
-    (void)hipFree(scratch);
+    (void)hipFree(prof_part);
     return rc;
 }
 
