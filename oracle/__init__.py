@@ -8,9 +8,11 @@ used only by the tests, the smoke check and the benchmark's CPU baseline.
 
 The solver's arithmetic (the step, the observables, the vortex count, the
 initial state) lives in ``sscn_oracle.c``, marshalled here through ctypes.
-Four plain numpy definitions live in this module: ``embed`` (continuation
-start), ``extend_z`` (3D product start), ``functional_fourth_order`` and
-``density``.  Each function is pinned in tests/test_oracle_pins.py against
+Seven plain numpy definitions live in this module: ``embed`` (continuation
+start), ``extend_z`` (3D product start), ``functional_fourth_order``,
+``density``, and for the learned initial state ``keys_cubic``, ``resample``
+(interpolation between grids) and ``angular_moments`` (lattice
+orientation).  Each function is pinned in tests/test_oracle_pins.py against
 what the paper and the mathematics fix; none is parity unpinned.  Arrays are
 complex128 with shape (ny, nx) in 2D and (nz, ny, nx) in 3D (x fastest),
 index 0 of every axis being the wall.
@@ -277,3 +279,83 @@ def density(p, psi, kind):
     if kind == "cut_z":
         return d[:, ny // 2, nx // 2]
     raise ValueError(kind)
+
+
+# ---------------------------------------------------------------------------
+# Grids of different spacing and extent (the learned initial state).  The
+# paper moves states between grids only by centred embedding on a common
+# spacing (``embed``); a network that works in coordinates scaled to each
+# condensate's size needs interpolation.  The interpolation is Keys' cubic
+# convolution (R. G. Keys, "Cubic convolution interpolation for digital
+# image processing", IEEE Trans. ASSP 29 (1981)) with a = -1/2, separable in
+# x and y; samples beyond a grid are zero, as the walls are.
+
+
+def keys_cubic(s):
+    """Keys' interpolation kernel with a = -1/2:
+    W(s) = 3/2 |s|^3 - 5/2 |s|^2 + 1 for |s| <= 1,
+    W(s) = -1/2 |s|^3 + 5/2 |s|^2 - 4 |s| + 2 for 1 < |s| < 2, else 0."""
+    s = np.abs(np.asarray(s, dtype=np.float64))
+    inner = 1.5 * s ** 3 - 2.5 * s ** 2 + 1.0
+    outer = -0.5 * s ** 3 + 2.5 * s ** 2 - 4.0 * s + 2.0
+    return np.where(s <= 1.0, inner, np.where(s < 2.0, outer, 0.0))
+
+
+def resample(psi, h_src, shape, h, angle=0.0):
+    """Interpolate the state psi (ny_s, nx_s) on its grid of spacings
+    h_src = (hx_s, hy_s) onto a grid of `shape` (ny, nx) and spacings
+    h = (hx, hy), both grids centred as the solver's (x_i = -n h / 2 + i h),
+    sampling the source at the destination points rotated by `angle` about
+    the origin: out(x, y) = f(cos a x - sin a y, sin a x + cos a y), with f
+    the cubic-convolution interpolant sum_ij W((X - X_i)/hx_s) W((Y - Y_j)/hy_s)
+    psi_ij over the source samples (zero beyond the source grid).  The
+    destination walls (index 0) are zero."""
+    src = np.asarray(psi, dtype=np.complex128)
+    nys, nxs = src.shape
+    ny, nx = shape
+    hxs, hys = h_src
+    hx, hy = h
+    x = -0.5 * nx * hx + hx * np.arange(nx)
+    y = -0.5 * ny * hy + hy * np.arange(ny)
+    X, Y = np.meshgrid(x, y)
+    ca, sa = np.cos(angle), np.sin(angle)
+    XS = ca * X - sa * Y
+    YS = sa * X + ca * Y
+    u = (XS + 0.5 * nxs * hxs) / hxs  # continuous source indices
+    v = (YS + 0.5 * nys * hys) / hys
+    i0 = np.floor(u).astype(np.int64)
+    j0 = np.floor(v).astype(np.int64)
+    out = np.zeros((ny, nx), dtype=np.complex128)
+    for b in range(-1, 3):
+        js = j0 + b
+        wy = keys_cubic(v - js)
+        for a in range(-1, 3):
+            is_ = i0 + a
+            wx = keys_cubic(u - is_)
+            ok = (is_ >= 0) & (is_ < nxs) & (js >= 0) & (js < nys)
+            vals = np.where(ok, src[np.clip(js, 0, nys - 1), np.clip(is_, 0, nxs - 1)], 0.0)
+            out += wx * wy * vals
+    out[0, :] = 0
+    out[:, 0] = 0
+    return out
+
+
+def angular_moments(psi, hx, hy, kmax):
+    """M_k = hx hy sum_ij |psi_ij|^2 exp(i k phi_ij), phi = atan2(y_j, x_i),
+    for k = 0..kmax (the angular Fourier components of the density about
+    the trap centre).  A point at the origin has no angle: it enters M_0
+    only."""
+    d = np.abs(np.asarray(psi, dtype=np.complex128)) ** 2
+    ny, nx = d.shape
+    x = -0.5 * nx * hx + hx * np.arange(nx)
+    y = -0.5 * ny * hy + hy * np.arange(ny)
+    X, Y = np.meshgrid(x, y)
+    phi = np.arctan2(Y, X)
+    at_origin = (X == 0) & (Y == 0)
+    out = []
+    for k in range(kmax + 1):
+        f = np.exp(1j * k * phi)
+        if k > 0:
+            f = np.where(at_origin, 0.0, f)
+        out.append(hx * hy * np.sum(d * f))
+    return np.array(out)
