@@ -327,6 +327,8 @@ def batch_converge(P, torch, cfgs, max_steps=2000000, chunk=20000):
         for k, v in enumerate(st):
             if v >= 0 and conv[k] < 0:
                 conv[k], when[k] = v, now
+        print(f"[bench] batch convergence: {done} steps, {sum(1 for v in conv if v >= 0)}/{len(conv)} "
+              f"converged, {now:.1f} s", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     counts = [b.vortex_count(k) for k in range(len(cfgs))]
     obs = b.observables()

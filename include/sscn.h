@@ -197,6 +197,37 @@ int sscn_embed_state(const void *src, int nx_src, int ny_src, int nz_src, void *
 int sscn_extend_z(const void *xy, int nx, int ny, void *dst, int nz, double hz, double d_z, int precision,
                   void *stream);
 
+/* Interpolation between 2D grids of different spacing and extent, for the
+ * learned initial state (a network working in coordinates scaled to each
+ * condensate's size, whose output seeds a run on the instance's own grid;
+ * the paper moves states between grids only by the centred embedding of
+ * sscn_embed_state).  Both grids are centred as the solver's (x_i =
+ * -n h / 2 + i h); the destination point (x, y) takes the value at
+ * (cos(angle) x - sin(angle) y, sin(angle) x + cos(angle) y) of Keys' cubic
+ * convolution interpolant of src (kernel parameter a = -1/2, separable, 4 x 4
+ * samples; third order; quadratics reproduced exactly), src samples beyond
+ * its grid taken as zero; the destination walls (index 0) are zero.  No
+ * normalisation (sscn_set_state_device or sscn_batch_set_state_device
+ * normalises a state written into a handle's buffer).  src: device buffer
+ * ny_src x nx_src, dst: device buffer ny x nx, x fastest, both in
+ * `precision` (SSCN_C128 or SSCN_C64; FP64 arithmetic in both), caller-owned,
+ * not overlapping.  SSCN_EINVAL for null or overlapping buffers, sizes below
+ * 2, spacings not positive and finite, or a non-finite angle.  Enqueued on
+ * `stream` (hipStream_t, NULL for the null stream), asynchronous. */
+int sscn_resample(const void *src, int nx_src, int ny_src, double hx_src, double hy_src, void *dst, int nx, int ny,
+                  double hx, double hy, double angle, int precision, void *stream);
+
+/* Angular Fourier components of a 2D state's density about the grid centre,
+ * M_k = hx hy sum |psi|^2 exp(i k phi), phi = atan2(y, x), k = 0..kmax
+ * (kmax <= 8), into out_dev[2k] (real part) and out_dev[2k + 1] (imaginary
+ * part), FP64, caller-owned device buffer of 2 kmax + 2 doubles; a point at
+ * the origin enters M_0 only.  The orientation arg(M_k) / k of a k-fold
+ * pattern fixes the canonical rotation of learned-start targets where the
+ * trap leaves the lattice orientation free.  psi: ny x nx device buffer in
+ * `precision`.  SSCN_EINVAL for bad arguments.  Asynchronous on `stream`. */
+int sscn_angular_moments(const void *psi, int nx, int ny, double hx, double hy, int kmax, int precision,
+                         double *out_dev, void *stream);
+
 /* Copy psi to a host buffer of the same layout.  Synchronises the stream. */
 int sscn_get_state(sscn_handle *h, void *host_psi);
 

@@ -27,7 +27,8 @@ EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_prepare_steps", "s
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step", "sscn_batch_prepare_steps", "sscn_batch_profile_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
-           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state", "sscn_extend_z", "sscn_density",
+           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state", "sscn_extend_z", "sscn_density", "sscn_resample",
+           "sscn_angular_moments",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
 
@@ -105,6 +106,11 @@ def lib():
                                        ctypes.c_int, ctypes.c_int, vp]
         L.sscn_extend_z.argtypes = [vp, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_int, vp]
+        cd = ctypes.c_double
+        L.sscn_resample.argtypes = [vp, ctypes.c_int, ctypes.c_int, cd, cd, vp, ctypes.c_int, ctypes.c_int, cd, cd,
+                                    cd, ctypes.c_int, vp]
+        L.sscn_angular_moments.argtypes = [vp, ctypes.c_int, ctypes.c_int, cd, cd, ctypes.c_int, ctypes.c_int, vp,
+                                           vp]
         L.sscn_batch_destroy.argtypes = [vp]
         L.sscn_batch_destroy.restype = None
         L.sscn_destroy.argtypes = [vp]
@@ -155,6 +161,43 @@ def embed_state(src, dst, stream=None):
     _check(lib().sscn_embed_state(ctypes.c_void_p(src.data_ptr()), shs[2], shs[1], shs[0],
                                   ctypes.c_void_p(dst.data_ptr()), shd[2], shd[1], shd[0], prec,
                                   ctypes.c_void_p(st.cuda_stream)))
+
+
+def resample(src, h_src, dst, h, angle=0.0, stream=None):
+    """Cubic-convolution interpolation of the 2D device state `src` (ny_s,
+    nx_s) with spacings h_src = (hx, hy) onto `dst` (ny, nx) with spacings
+    h, sampling src at the destination points rotated by `angle`
+    (include/sscn.h, sscn_resample).  Both complex128 or both complex64,
+    contiguous.  Asynchronous on `stream` (default: the current torch
+    stream)."""
+    import torch
+    if src.dtype != dst.dtype or src.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError("src and dst must both be complex128 or both complex64")
+    if src.dim() != 2 or dst.dim() != 2 or not (src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("src and dst are contiguous (ny, nx) tensors")
+    prec = SSCN_C128 if src.dtype == torch.complex128 else SSCN_C64
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().sscn_resample(ctypes.c_void_p(src.data_ptr()), src.shape[1], src.shape[0], float(h_src[0]),
+                               float(h_src[1]), ctypes.c_void_p(dst.data_ptr()), dst.shape[1], dst.shape[0],
+                               float(h[0]), float(h[1]), float(angle), prec, ctypes.c_void_p(st.cuda_stream)))
+
+
+def angular_moments(psi, h, kmax, out=None, stream=None):
+    """M_k = hx hy sum |psi|^2 exp(i k phi), k = 0..kmax, of the 2D device
+    state `psi` (include/sscn.h, sscn_angular_moments), as a float64 device
+    tensor (kmax + 1, 2) of real and imaginary parts (`out` if given).
+    Asynchronous on `stream`."""
+    import torch
+    if psi.dim() != 2 or not psi.is_contiguous() or psi.dtype not in (torch.complex128, torch.complex64):
+        raise ValueError("psi is a contiguous complex (ny, nx) tensor")
+    if out is None:
+        out = torch.empty((kmax + 1, 2), dtype=torch.float64, device=psi.device)
+    prec = SSCN_C128 if psi.dtype == torch.complex128 else SSCN_C64
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().sscn_angular_moments(ctypes.c_void_p(psi.data_ptr()), psi.shape[1], psi.shape[0], float(h[0]),
+                                      float(h[1]), int(kmax), prec, ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(st.cuda_stream)))
+    return out
 
 
 def extend_z(xy, dst, hz, d_z, stream=None):

@@ -11,7 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 # (source, extra defines): the kernel launchers are compiled once per part
 # (1 sweeps, 2 fused 2D step, 3 batched sweeps) and precision
-UNITS = [(os.path.join(CSRC, "sscn_lib.hip"), []), (os.path.join(CSRC, "sscn_nn.hip"), [])] + [
+UNITS = [(os.path.join(CSRC, "sscn_lib.hip"), []), (os.path.join(CSRC, "sscn_nn.hip"), []),
+         (os.path.join(CSRC, "sscn_setup.cpp"), [])] + [
     (os.path.join(CSRC, "sscn_kernels.hip"), [f"-DSSCN_PART={part}", f"-DSSCN_REAL_T={real}"])
     for part in (2, 1, 3) for real in ("double", "float")]
 LIB = os.path.join(HERE, "libsscn.so")
@@ -37,9 +38,10 @@ def build(verbose: bool = False) -> str:
                 print(" ".join(cmd), flush=True)
             procs.append((cmd, subprocess.Popen(cmd)))
             objs.append(obj)
-        for cmd, pr in procs:
-            if pr.wait() != 0:
-                raise subprocess.CalledProcessError(pr.returncode, cmd)
+        codes = [pr.wait() for _, pr in procs]  # every compiler finishes before the directory goes
+        for (cmd, _), rc in zip(procs, codes):
+            if rc != 0:
+                raise subprocess.CalledProcessError(rc, cmd)
         cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
         if verbose:
             print(" ".join(cmd), flush=True)

@@ -38,6 +38,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "sscn_types.hpp"
+
 #include <type_traits>
 
 namespace sscn {
@@ -89,22 +91,6 @@ template <class R> __device__ __forceinline__ void st(typename Vec<R>::T *p, int
     v.y = a.im;
     p[i] = v;
 }
-
-// Per-axis Crank-Nicolson coefficients (FP64, from the host):
-//   A0 = 1 + k0, k0 = i tau/(2h^2),  A+- = u +- q rot,  u = -i tau/(4h^2),
-//   q = tau/(4h); rot = Omega y_j (x-lines), -Omega x_i (y-lines), 0 (z).
-struct AxisCoef {
-    double a0r, a0i, k0r, k0i, ur, ui, qr, qi;
-};
-
-struct StepArgs {
-    int dim, nx, ny, nz;
-    double hx, hy, hz;
-    double x0, y0, z0;          // first stored coordinate, -n h / 2
-    double vx, vy, vz;          // 1/2 gamma^2, 1/2 nu^2, 1/2 lambda^2
-    double g, omega, dt, dV;
-    AxisCoef ax[3];
-};
 
 // Line coefficients for a line whose rotation coefficient is `rot`.
 template <class R> struct LineCoef {
@@ -1487,6 +1473,118 @@ __global__ __launch_bounds__(256) void k_extend_z(const typename Vec<R>::T *__re
         const double f = c * exp(-0.5 * t * t);
         const Cx<R> v = ld<R>(xy, e - k * nxy);
         st<R>(dst, e, Cx<R>{R((double)v.re * f), R((double)v.im * f)});
+    }
+}
+
+// Keys' cubic convolution weights (a = -1/2) of the samples at offsets -1,
+// 0, 1, 2 from a point at fraction t in [0, 1) past the sample at offset 0:
+// W(t + 1), W(t), W(1 - t), W(2 - t) with W the piecewise cubic of the
+// kernel (expanded in t).
+__device__ __forceinline__ void keys_weights(double t, double (&w)[4])
+{
+    w[0] = ((-t + 2.0) * t - 1.0) * t * 0.5;
+    w[1] = ((3.0 * t - 5.0) * t * t + 2.0) * 0.5;
+    w[2] = ((-3.0 * t + 4.0) * t + 1.0) * t * 0.5;
+    w[3] = (t - 1.0) * t * t * 0.5;
+}
+
+// Grid-to-grid interpolation: dst point (x, y) (both grids centred,
+// x_i = -n h / 2 + i h) takes the cubic-convolution interpolant of src at
+// (ca x - sa y, sa x + ca y); src samples beyond its grid are zero; dst
+// walls (index 0) are zero.  FP64 arithmetic in both precisions.
+template <class R>
+__global__ __launch_bounds__(256) void k_resample(const typename Vec<R>::T *__restrict__ src, int nxs, int nys,
+                                                  double hxs, double hys, typename Vec<R>::T *__restrict__ dst,
+                                                  int nx, int ny, double hx, double hy, double ca, double sa)
+{
+    const int64_t n = (int64_t)nx * ny;
+    for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        double re = 0.0, im = 0.0;
+        const double x = -0.5 * nx * hx + i * hx, y = -0.5 * ny * hy + j * hy;
+        const double u = (ca * x - sa * y + 0.5 * nxs * hxs) / hxs;
+        const double v = (sa * x + ca * y + 0.5 * nys * hys) / hys;
+        // beyond the source grid by more than the stencil: zero (and the
+        // integer conversion below stays in range)
+        if (i > 0 && j > 0 && u > -2.0 && u < nxs + 1.0 && v > -2.0 && v < nys + 1.0) {
+            const double fu = floor(u), fv = floor(v);
+            const int i0 = (int)fu, j0 = (int)fv;
+            double wx[4], wy[4];
+            keys_weights(u - fu, wx);
+            keys_weights(v - fv, wy);
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int js = j0 - 1 + b;
+                if (js < 0 || js >= nys)
+                    continue;
+                double rr = 0.0, ri = 0.0;
+#pragma unroll
+                for (int a = 0; a < 4; ++a) {
+                    const int is = i0 - 1 + a;
+                    if (is < 0 || is >= nxs)
+                        continue;
+                    const Cx<R> f = ld<R>(src, (int64_t)js * nxs + is);
+                    rr += wx[a] * (double)f.re;
+                    ri += wx[a] * (double)f.im;
+                }
+                re += wy[b] * rr;
+                im += wy[b] * ri;
+            }
+        }
+        st<R>(dst, p, Cx<R>{R(re), R(im)});
+    }
+}
+
+// Angular moments of the density about the origin, one block of 1024
+// threads: out[2k], out[2k + 1] = hx hy sum |psi|^2 (cos k phi, sin k phi),
+// k = 0..kmax (kmax <= 8); a point at the origin enters k = 0 only.  Each
+// thread sums a grid-stride share, then a fixed-order block sum.
+template <class R>
+__global__ __launch_bounds__(1024) void k_angular_moments(const typename Vec<R>::T *__restrict__ psi, int nx, int ny,
+                                                          double hx, double hy, int kmax, double *__restrict__ out)
+{
+    __shared__ double red[16];
+    double c[9], s[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k)
+        c[k] = s[k] = 0.0;
+    const int64_t n = (int64_t)nx * ny;
+    for (int64_t p = threadIdx.x; p < n; p += 1024) {
+        const int i = (int)(p % nx), j = (int)(p / nx);
+        const double x = -0.5 * nx * hx + i * hx, y = -0.5 * ny * hy + j * hy;
+        const Cx<R> v = ld<R>(psi, p);
+        const double d = (double)v.re * (double)v.re + (double)v.im * (double)v.im;
+        // e^{i phi}, zero at the origin (the grid point 2i = nx, 2j = ny,
+        // found by index: a contracted x = -nx hx / 2 + i hx need not be 0
+        // there), so that the origin adds to k = 0 only
+        const bool origin = 2 * i == nx && 2 * j == ny;
+        const double r = sqrt(x * x + y * y);
+        const double er = origin ? 0.0 : x / r, ei = origin ? 0.0 : y / r;
+        double pr = 1.0, pi = 0.0;  // e^{i k phi}, k = 0 first
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            c[k] += d * pr;
+            s[k] += d * pi;
+            const double t = pr * er - pi * ei;
+            pi = pr * ei + pi * er;
+            pr = t;
+        }
+    }
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int k = 0; k <= kmax && k < 9; ++k) {
+        for (int part = 0; part < 2; ++part) {
+            const double w = wave_sum_f64(part ? s[k] : c[k]);
+            if (lane == 0)
+                red[wave] = w;
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                double t = 0.0;
+                for (int q = 0; q < 16; ++q)
+                    t += red[q];
+                out[2 * k + part] = hx * hy * t;
+            }
+            __syncthreads();
+        }
     }
 }
 

@@ -43,8 +43,6 @@ constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
 constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
 constexpr size_t kXLdsCap = 150 * 1024;  // dynamic LDS of an x-sweep block
 
-// Supported window sizes (template instantiations).
-const int kWindows[] = {4, 6, 8, 10, 12, 13, 14, 16, 20, 24, 32};
 
 }  // namespace sscn
 

@@ -2,6 +2,7 @@
 // per-axis Crank-Nicolson coefficients, window selection, kernel dispatch,
 // step sequencing with HIP graphs, observables and vortex counting.
 #include "sscn_host.hpp"
+#include "sscn_setup.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -22,18 +23,10 @@ using namespace sscn;
 
 namespace {
 
-thread_local std::string g_err;
-
 // Vortex count of the convergence criterion (sscn_converge, sscn_batch_run):
 // density fraction and box of sscn_vortex_count.
 constexpr double kConvDensityFrac = 0.05;
 constexpr int kConvBox = 3;
-
-int fail(int code, const std::string &msg)
-{
-    g_err = msg;
-    return code;
-}
 
 #define HIPCHECK(call)                                                                   \
     do {                                                                                 \
@@ -47,91 +40,6 @@ int64_t npoints(const sscn_params &p)
     return (int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
 }
 
-// Bound on the truncation error of a windowed line solve (relative to the
-// largest |rhs| on the line) for a strictly diagonally dominant tridiagonal
-// Toeplitz system with |A-| <= ab, |A0| = bb, |A+| <= cb:
-//  - Thomas factors satisfy |c'_k| <= mu = cb / (bb - ab);
-//  - the forward sweep damps by lam = ab / (bb - ab mu) per row;
-//  - the exact solution just outside a window is at most 1/(bb - ab - cb)
-//    times max|rhs| (Varah's bound), and enters the window through one
-//    off-diagonal coefficient at each end;
-//  - so at W rows from both window ends the error of y is at most
-//    yb kappa (ab lam^W / (1 - mu lam) + cb mu^W), kappa = 1/(bb - ab mu),
-//    and the Cayley output 2y - v doubles it.
-// Returns the smallest W meeting tol, or -1 if not diagonally dominant.
-int window_rows(double ab, double bb, double cb, double tol)
-{
-    if (!(ab + cb < bb))
-        return -1;
-    const double mu = cb / (bb - ab);
-    const double lam = ab / (bb - ab * mu);
-    const double kappa = 1.0 / (bb - ab * mu);
-    const double yb = 1.0 / (bb - ab - cb);
-    for (int w = 0; w <= 4096; ++w) {
-        const double err = 2.0 * yb * kappa * (ab * std::pow(lam, w) / (1.0 - mu * lam) + cb * std::pow(mu, w));
-        if (err <= tol)
-            return w;
-    }
-    return 4097;
-}
-
-int validate(const sscn_params &p)
-{
-    if (p.dim != 2 && p.dim != 3)
-        return fail(SSCN_EINVAL, "dim must be 2 or 3");
-    if (p.nx < 3 || p.ny < 3 || (p.dim == 3 && p.nz < 3))
-        return fail(SSCN_EINVAL, "every axis needs at least 3 stored points");
-    if ((int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1) > ((int64_t)1 << 40))
-        return fail(SSCN_EINVAL, "grid too large");
-    if (!(p.hx > 0) || !(p.hy > 0) || (p.dim == 3 && !(p.hz > 0)) || !(p.dt > 0))
-        return fail(SSCN_EINVAL, "space and time steps must be positive");
-    if (p.mode != SSCN_IMAG && p.mode != SSCN_REAL)
-        return fail(SSCN_EINVAL, "mode must be SSCN_IMAG or SSCN_REAL");
-    if (p.precision != SSCN_C128 && p.precision != SSCN_C64)
-        return fail(SSCN_EINVAL, "precision must be SSCN_C128 or SSCN_C64");
-    if (!std::isfinite(p.g) || !std::isfinite(p.omega) || !std::isfinite(p.gamma) || !std::isfinite(p.nu) ||
-        (p.dim == 3 && !std::isfinite(p.lambda)))
-        return fail(SSCN_EINVAL, "non-finite physical parameter");
-    if (!(std::fabs(p.omega) < std::min(p.gamma, p.nu)))
-        return fail(SSCN_EOMEGA, "|omega| must be below min(gamma, nu)");
-    return 0;
-}
-
-// Crank-Nicolson coefficients of one axis and its window size.
-int axis_setup(const sscn_params &p, int axis, AxisCoef &c, int &W)
-{
-    using cd = std::complex<double>;
-    const cd I(0.0, 1.0);
-    const cd tau = p.mode == SSCN_REAL ? cd(p.dt, 0.0) : cd(0.0, -p.dt);
-    const double h = axis == 0 ? p.hx : axis == 1 ? p.hy : p.hz;
-    const int n = axis == 0 ? p.nx : axis == 1 ? p.ny : p.nz;
-    const cd k0 = I * tau / (2.0 * h * h);
-    const cd A0 = 1.0 + k0;
-    const cd u = -I * tau / (4.0 * h * h);
-    const cd q = tau / (4.0 * h);
-    c = AxisCoef{A0.real(), A0.imag(), k0.real(), k0.imag(), u.real(), u.imag(), q.real(), q.imag()};
-    // the largest rotation coefficient on this axis's lines
-    double rmax = 0.0;
-    if (axis == 0)
-        rmax = std::fabs(p.omega) * 0.5 * p.ny * p.hy;
-    else if (axis == 1)
-        rmax = std::fabs(p.omega) * 0.5 * p.nx * p.hx;
-    const double amax = std::max(std::abs(u + q * rmax), std::abs(u - q * rmax));
-    const double tol = p.precision == SSCN_C128 ? std::ldexp(1.0, -56) : std::ldexp(1.0, -27);
-    const int w = window_rows(amax, std::abs(A0), amax, tol);
-    if (w < 0)
-        return fail(SSCN_EUNSTABLE, "line system of axis " + std::to_string(axis) +
-                                        " is not strictly diagonally dominant (dt*|omega|*max|coord|/(2h) too large)");
-    W = 0;
-    for (int cand : kWindows)
-        if (cand >= w) {
-            W = cand;
-            break;
-        }
-    (void)n;
-    return 0;
-}
-
 // Lines per block of the x-sweep and the LDS it stages: L lines of nx + nx/S
 // + 1 padded points, the pivot-table rows and the wall terms.
 void set_x_lines(sscn_handle *h, int L)
@@ -139,29 +47,6 @@ void set_x_lines(sscn_handle *h, int L)
     const size_t LS = (size_t)h->p.nx + h->p.nx / kSegX + 1;
     h->xL = L;
     h->xlds = (L * LS + (size_t)L * (h->W[0] + 2) + L) * h->esize;
-}
-
-// Grid geometry and physical constants of the step and observables kernels
-// (everything of StepArgs but the per-axis line coefficients).
-void fill_args(const sscn_params &p, StepArgs &a)
-{
-    a.dim = p.dim;
-    a.nx = p.nx;
-    a.ny = p.ny;
-    a.nz = p.dim == 3 ? p.nz : 1;
-    a.hx = p.hx;
-    a.hy = p.hy;
-    a.hz = p.dim == 3 ? p.hz : 1.0;
-    a.x0 = -0.5 * p.nx * p.hx;
-    a.y0 = -0.5 * p.ny * p.hy;
-    a.z0 = p.dim == 3 ? -0.5 * p.nz * p.hz : 0.0;
-    a.vx = 0.5 * p.gamma * p.gamma;
-    a.vy = 0.5 * p.nu * p.nu;
-    a.vz = p.dim == 3 ? 0.5 * p.lambda * p.lambda : 0.0;
-    a.g = p.g;
-    a.omega = p.omega;
-    a.dt = p.dt;
-    a.dV = p.hx * p.hy * (p.dim == 3 ? p.hz : 1.0);
 }
 
 int setup(sscn_handle *h)
@@ -215,30 +100,6 @@ int setup(sscn_handle *h)
     return 0;
 }
 
-// The fixed point c* = A+ / (A0 - A- c*) of the Thomas recurrence of a
-// diagonally dominant line: the root of A- c^2 - A0 c + A+ = 0 of smaller
-// modulus, c* = 2 A+ / (A0 + s) with s = sqrt(A0^2 - 4 A- A+) taken with
-// Re(conj(A0) s) >= 0 (no cancellation in A0 + s), then polished by the
-// recurrence itself.  Each iteration multiplies the error by
-// |A- c* r*| < 1/2 (r* = 1/(A0 - A- c*)), so it stops after a few, when the
-// change is within 4 ulps (at most 16 iterations).
-std::complex<double> pivot_fixed_point(std::complex<double> A0, std::complex<double> Am, std::complex<double> Ap)
-{
-    using cd = std::complex<double>;
-    cd sq = std::sqrt(A0 * A0 - 4.0 * Am * Ap);
-    if ((std::conj(A0) * sq).real() < 0.0)
-        sq = -sq;
-    cd c = 2.0 * Ap / (A0 + sq);
-    for (int it = 0; it < 16; ++it) {
-        const cd nc = Ap / (A0 - Am * c);
-        const bool done = std::abs(nc - c) <= 4.0 * 2.220446049250313e-16 * std::abs(nc);
-        c = nc;
-        if (done)
-            break;
-    }
-    return c;
-}
-
 // Pivot tables of the windowed solves, one row per distinct line of an axis
 // (x-lines by j, y-lines by i, one for z), stride W + 2: the fixed point c*,
 // r* of the Thomas recurrence c' = A+ r, r = 1/(A0 - A- c'), then the wall
@@ -247,7 +108,6 @@ std::complex<double> pivot_fixed_point(std::complex<double> A0, std::complex<dou
 // one diagonal entry in which the line matrix differs from T_abs).  FP64.
 int build_tables(sscn_handle *h)
 {
-    using cd = std::complex<double>;
     const sscn_params &p = h->p;
     for (int ax = 0; ax < 3; ++ax) {
         if (h->tab[ax])
@@ -258,39 +118,8 @@ int build_tables(sscn_handle *h)
         return 0;
     for (int ax = 0; ax < p.dim; ++ax) {
         const int W = h->W[ax];
-        const AxisCoef &c = h->args.ax[ax];
-        const cd A0(c.a0r, c.a0i), u(c.ur, c.ui), q(c.qr, c.qi);
-        const int ntypes = ax == 0 ? p.ny : ax == 1 ? p.nx : 1;
-        const int m = (ax == 0 ? p.nx : ax == 1 ? p.ny : p.nz) - 1;  // unknowns per line
-        const int stride = W + 2;
-        std::vector<cd> t((size_t)ntypes * stride);
-        std::vector<cd> z((size_t)m + 2);
-        for (int ty = 0; ty < ntypes; ++ty) {
-            double rot = 0.0;
-            if (ax == 0)
-                rot = p.omega * (h->args.y0 + ty * p.hy);
-            else if (ax == 1)
-                rot = -p.omega * (h->args.x0 + ty * p.hx);
-            const cd Ap = u + q * rot, Am = u - q * rot;
-            const cd cs = pivot_fixed_point(A0, Am, Ap);
-            const cd rs = 1.0 / (A0 - Am * cs);
-            // z = T_abs^{-1} e_1: forward d'_1 = r*, d'_k = -A- r* d'_{k-1};
-            // back z_m = d'_m, z_k = d'_k - c* z_{k+1}
-            cd d = rs;
-            z[1] = d;
-            for (int k = 2; k <= m; ++k) {
-                d = -Am * rs * d;
-                z[k] = d;
-            }
-            for (int k = m - 1; k >= 1; --k)
-                z[k] = z[k] - cs * z[k + 1];
-            const cd gam = Am * cs / (1.0 + Am * cs * z[1]);
-            cd *row = &t[(size_t)ty * stride];
-            row[0] = cs;
-            row[1] = rs;
-            for (int k = 1; k <= W; ++k)
-                row[1 + k] = k <= m ? 2.0 * gam * z[k] : cd(0.0);
-        }
+        std::vector<std::complex<double>> t;
+        pivot_table(p, h->args, ax, W, t);
         const size_t n = t.size();
         if (p.precision == SSCN_C128) {
             if (hipMalloc(&h->tab[ax], n * sizeof(Cx<double>)) != hipSuccess)
@@ -1159,7 +988,7 @@ void batch_free(sscn_batch *b)
 
 extern "C" {
 
-const char *sscn_last_error(void) { return g_err.c_str(); }
+const char *sscn_last_error(void) { return last_error(); }
 
 const char *sscn_strerror(int code)
 {
@@ -1538,6 +1367,50 @@ int sscn_extend_z(const void *xy, int nx, int ny, void *dst, int nz, double hz, 
     else
         hipLaunchKernelGGL((k_extend_z<float>), dim3(nb), dim3(256), 0, (hipStream_t)stream,
                            (const V<float> *)xy, nx, ny, (V<float> *)dst, nz, z0, hz, d_z, c);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+int sscn_resample(const void *src, int nx_src, int ny_src, double hx_src, double hy_src, void *dst, int nx, int ny,
+                  double hx, double hy, double angle, int precision, void *stream)
+{
+    if (!src || !dst || nx_src < 2 || ny_src < 2 || nx < 2 || ny < 2)
+        return fail(SSCN_EINVAL, "bad resample arguments");
+    if (!(hx_src > 0) || !(hy_src > 0) || !(hx > 0) || !(hy > 0) || !std::isfinite(hx_src) ||
+        !std::isfinite(hy_src) || !std::isfinite(hx) || !std::isfinite(hy) || !std::isfinite(angle))
+        return fail(SSCN_EINVAL, "spacings must be positive and finite, the angle finite");
+    if (precision != SSCN_C128 && precision != SSCN_C64)
+        return fail(SSCN_EINVAL, "precision must be SSCN_C128 or SSCN_C64");
+    const size_t es = precision == SSCN_C128 ? 16 : 8;
+    const char *s0 = (const char *)src, *s1 = s0 + (size_t)nx_src * ny_src * es;
+    const char *d0 = (const char *)dst, *d1 = d0 + (size_t)nx * ny * es;
+    if (s0 < d1 && d0 < s1)
+        return fail(SSCN_EINVAL, "src and dst overlap");
+    const double ca = std::cos(angle), sa = std::sin(angle);
+    const int nb = red_blocks((int64_t)nx * ny);
+    if (precision == SSCN_C128)
+        hipLaunchKernelGGL((k_resample<double>), dim3(nb), dim3(256), 0, (hipStream_t)stream, (const V<double> *)src,
+                           nx_src, ny_src, hx_src, hy_src, (V<double> *)dst, nx, ny, hx, hy, ca, sa);
+    else
+        hipLaunchKernelGGL((k_resample<float>), dim3(nb), dim3(256), 0, (hipStream_t)stream, (const V<float> *)src,
+                           nx_src, ny_src, hx_src, hy_src, (V<float> *)dst, nx, ny, hx, hy, ca, sa);
+    HIPCHECK(hipGetLastError());
+    return 0;
+}
+
+int sscn_angular_moments(const void *psi, int nx, int ny, double hx, double hy, int kmax, int precision,
+                         double *out_dev, void *stream)
+{
+    if (!psi || !out_dev || nx < 1 || ny < 1 || kmax < 0 || kmax > 8 || !(hx > 0) || !(hy > 0))
+        return fail(SSCN_EINVAL, "bad angular_moments arguments");
+    if (precision != SSCN_C128 && precision != SSCN_C64)
+        return fail(SSCN_EINVAL, "precision must be SSCN_C128 or SSCN_C64");
+    if (precision == SSCN_C128)
+        hipLaunchKernelGGL((k_angular_moments<double>), dim3(1), dim3(1024), 0, (hipStream_t)stream,
+                           (const V<double> *)psi, nx, ny, hx, hy, kmax, out_dev);
+    else
+        hipLaunchKernelGGL((k_angular_moments<float>), dim3(1), dim3(1024), 0, (hipStream_t)stream,
+                           (const V<float> *)psi, nx, ny, hx, hy, kmax, out_dev);
     HIPCHECK(hipGetLastError());
     return 0;
 }

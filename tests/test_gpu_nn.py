@@ -249,7 +249,10 @@ def test_state_conversions(nn):
         assert np.array_equal(back.cpu().numpy(), want)
 
 
-@pytest.mark.parametrize("chans,bott,N,H", [((16, 32), 32, 2, 16), ((16, 32, 64, 64), 128, 2, 32)])
+@pytest.mark.parametrize("chans,bott,N,H", [((16, 32), 32, 2, 16), ((16, 32, 64, 64), 128, 2, 32),
+                                            # the learned start's network at full size: 6 levels,
+                                            # 32-64-128-256-256 and a 256-channel bottleneck, 256 x 256
+                                            ((32, 64, 128, 256, 256), 256, 1, 256)])
 def test_unet_forward_backward(nn, chans, bott, N, H):
     """Whole network on the GPU against the reference with the same bf16
     rounding points.  The two differ only where fp32 and FP64 accumulation
@@ -260,6 +263,7 @@ def test_unet_forward_backward(nn, chans, bott, N, H):
     the GPU gradient must be as close to the bf16 reference as bf16
     arithmetic itself is to exact arithmetic.  A wrong index or operand
     layout gives errors of order one."""
+    print(f"[gpu-nn] whole network chans={chans} bott={bott} N={N} H={H}", flush=True)
     rng = np.random.default_rng(11)
     net = nn.UNet(N, H, H, chans=chans, bott=bott, seed=3)
     # non-zero biases so the bias path is exercised
