@@ -359,10 +359,11 @@ int sscn_batch_prepare_steps(sscn_batch *b, int64_t nsteps);
 /* Advance nsteps (1..100000) steps launched one by one (no graph), with a HIP
  * event recorded on the batch's stream around every kernel, and return the
  * average durations in milliseconds: sweep plan ms_out[0] the batched
- * x-sweep (with H1 and the rescale), [1] the batched y-sweep, [2] the
- * per-instance rescale kernel; fused plan ms_out[0] the fused step, [1] =
- * [2] = 0; ms_out[3] a whole step (the finish pass at the end of the call is
- * not timed).  For measurement: the kernels run in the order and on the
+ * x-sweep (with H1 and the pending rescale, which it forms from the norm
+ * partials itself), [1] the batched y-sweep, [2] = 0 (no kernel of its own
+ * remains for the rescale); fused plan ms_out[0] the fused step, [1] = [2] =
+ * 0; ms_out[3] a whole step (the finish pass at the end of the call is not
+ * timed).  For measurement: the kernels run in the order and on the
  * data of ordinary steps.  Synchronises the stream. */
 int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out);
 

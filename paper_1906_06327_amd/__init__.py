@@ -452,12 +452,12 @@ class Batch:
 
     def profile_step(self, n):
         """Advance n steps launched one by one with HIP events around every
-        kernel; average ms of the x-sweep, y-sweep, rescale kernel (sweep
-        plan) or of the fused step, and of a whole step."""
+        kernel; average ms of the x-sweep and y-sweep (sweep plan) or of the
+        fused step, and of a whole step."""
         ms = (ctypes.c_double * 4)()
         _check(lib().sscn_batch_profile_step(self._h, int(n), ms))
         if self.info()["plan"] == PLAN_SWEEPS:
-            return {"x": ms[0], "y": ms[1], "rescale": ms[2], "step": ms[3]}
+            return {"x": ms[0], "y": ms[1], "step": ms[3]}
         return {"fused": ms[0], "step": ms[3]}
 
     def run(self, max_steps, check_every=100, tol=1e-8):

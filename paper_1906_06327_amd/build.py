@@ -28,12 +28,14 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, extra_flags=(), out: str = LIB) -> str:
+    """Compile every translation unit (extra_flags appended to each hipcc
+    line, e.g. -D overrides of the tuning constants) and link `out`."""
     with tempfile.TemporaryDirectory(prefix="sscn_build_") as tmp:
         objs, procs = [], []
         for n, (src, defs) in enumerate(UNITS):
             obj = os.path.join(tmp, f"{n}_{os.path.basename(src)}.o")
-            cmd = [HIPCC] + FLAGS + defs + ["-c", "-o", obj, src]
+            cmd = [HIPCC] + FLAGS + defs + list(extra_flags) + ["-c", "-o", obj, src]
             if verbose:
                 print(" ".join(cmd), flush=True)
             procs.append((cmd, subprocess.Popen(cmd)))
@@ -42,12 +44,12 @@ def build(verbose: bool = False) -> str:
         for (cmd, _), rc in zip(procs, codes):
             if rc != 0:
                 raise subprocess.CalledProcessError(rc, cmd)
-        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+        cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", out + ".tmp"] + objs
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
-    return LIB
+    os.replace(out + ".tmp", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -54,6 +54,13 @@ constexpr int kXLoad = 16;
 #endif
 constexpr int kSweepWaves = SSCN_SWEEP_WAVES;
 
+// The batched sweeps stream the state (nontemporal loads and stores where a
+// point is touched once): their working set exceeds the caches.
+#ifndef SSCN_BATCH_STREAM
+#define SSCN_BATCH_STREAM 1
+#endif
+constexpr bool kBatchStream = SSCN_BATCH_STREAM != 0;
+
 
 template <class R> struct Cx {
     R re, im;
@@ -79,17 +86,56 @@ template <class R> struct Vec;
 template <> struct Vec<double> { using T = double2; };
 template <> struct Vec<float> { using T = float2; };
 
+// State values are read and written through the global address space (a
+// C-style cast: the only cast that changes the address space): every state
+// buffer is device memory, and pointers loaded from a work-list descriptor
+// would otherwise be accessed as generic (flat) pointers, whose loads also
+// count against the LDS wait counter.
+template <class R> struct GVec;
+template <> struct GVec<double> {
+    typedef double V __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) V T;
+};
+template <> struct GVec<float> {
+    typedef float V __attribute__((ext_vector_type(2)));
+    typedef __attribute__((address_space(1))) V T;
+};
+
 template <class R> __device__ __forceinline__ Cx<R> ld(const typename Vec<R>::T *p, int64_t i)
 {
-    typename Vec<R>::T v = p[i];
+    const typename GVec<R>::V v = ((const typename GVec<R>::T *)p)[i];
     return {v.x, v.y};
 }
 template <class R> __device__ __forceinline__ void st(typename Vec<R>::T *p, int64_t i, Cx<R> a)
 {
-    typename Vec<R>::T v;
+    typename GVec<R>::V v;
     v.x = a.re;
     v.y = a.im;
-    p[i] = v;
+    ((typename GVec<R>::T *)p)[i] = v;
+}
+
+// A complex value (a pivot-table entry) read through the global address space.
+template <class R> __device__ __forceinline__ Cx<R> ldg(const Cx<R> *p, int64_t i)
+{
+    const typename GVec<R>::V v = ((const typename GVec<R>::T *)p)[i];
+    return {v.x, v.y};
+}
+
+// Streaming forms for state the kernel touches once (nontemporal hint: the
+// line is not kept in the caches for reuse).  A sweep over a state larger
+// than the caches reads each point once and writes it once; the hint lets
+// the memory system stream those accesses.
+template <class R> __device__ __forceinline__ Cx<R> ld_stream(const typename Vec<R>::T *p, int64_t i)
+{
+    const typename GVec<R>::V v = __builtin_nontemporal_load(((const typename GVec<R>::T *)p) + i);
+    return {v.x, v.y};
+}
+template <class R> __device__ __forceinline__ void st_stream(typename Vec<R>::T *p, int64_t i, Cx<R> a)
+{
+    typename GVec<R>::V v;
+    v.x = a.re;
+    v.y = a.im;
+    __builtin_nontemporal_store(v, ((typename GVec<R>::T *)p) + i);
 }
 
 // Line coefficients for a line whose rotation coefficient is `rot`.
@@ -443,13 +489,10 @@ __device__ __forceinline__ double norm_scale_m1(double tot, double dV) { return 
 __device__ __forceinline__ void sin_cos(double x, double *s, double *c) { sincos(x, s, c); }
 __device__ __forceinline__ void sin_cos(float x, float *s, float *c) { sincosf(x, s, c); }
 
-// e^x - 1 for |x| <= 1/4 by its Taylor series x sum_k x^k / (k+1)!
-// (Horner), truncated where the first omitted term is below 2^-60 (FP64,
-// 13 terms) or 2^-30 (FP32, 8 terms) of the sum.
-template <class R>
-__device__ __forceinline__ R expm1_series(R x)
+// e^x - 1 by its Taylor series x sum_{k < NT} x^k / (k+1)! (Horner).
+template <class R, int NT>
+__device__ __forceinline__ R expm1_taylor(R x)
 {
-    constexpr int NT = std::is_same<R, double>::value ? 13 : 8;
     R c = R(1);
     R inv[NT];
 #pragma unroll
@@ -464,20 +507,41 @@ __device__ __forceinline__ R expm1_series(R x)
     return x * q;
 }
 
-// e^x - 1: the series where |x| <= 1/4, else the library expm1.  The H1
-// factors of the imaginary-time step have small arguments (dt times the
-// local energy), so the library branch is almost never taken.
+// The series truncated where the first omitted term is below 2^-60 (FP64)
+// or 2^-30 (FP32) of the sum: for |x| <= 1/4, 13 and 8 terms; for |x| <= 1
+// (the sum is then at least 1 - 1/e of its first term), 19 and 12 terms.
+template <class R>
+__device__ __forceinline__ R expm1_series(R x)
+{
+    return expm1_taylor<R, std::is_same<R, double>::value ? 13 : 8>(x);
+}
+
+template <class R>
+__device__ __forceinline__ R expm1_wide(R x)
+{
+    return expm1_taylor<R, std::is_same<R, double>::value ? 19 : 12>(x);
+}
+
+// e^x - 1: the short series where |x| <= 1/4, the long one where |x| <= 1,
+// else the library expm1.  The H1 factors of the imaginary-time step have
+// arguments dt times the local energy; at the corners of the large grids
+// (the harmonic potential grows to several hundred there) they pass 1/4 but
+// stay below 1 at the time steps used, so the library branch is rare.
 template <class R>
 __device__ __forceinline__ R expm1_small(R x)
 {
-    if (fabs(x) <= R(0.25))
+    const R ax = fabs(x);
+    if (ax <= R(0.25))
         return expm1_series(x);
+    if (ax <= R(1))
+        return expm1_wide(x);
     return expm1(x);
 }
 
 // e[c] <- e^{e[c]} - 1 for the NP arguments a thread holds, with one branch
-// for all of them (so the NP series evaluations interleave): the series if
-// every |e[c]| <= 1/4, else the library expm1 for all.
+// for all of them (so the NP series evaluations interleave): by the range of
+// the largest |e[c]|, the short series, the long series or the library
+// expm1 for all.
 template <class R, int NP>
 __device__ __forceinline__ void expm1_all(R (&e)[NP])
 {
@@ -489,6 +553,10 @@ __device__ __forceinline__ void expm1_all(R (&e)[NP])
 #pragma unroll
         for (int c = 0; c < NP; ++c)
             e[c] = expm1_series(e[c]);
+    } else if (amax <= R(1)) {
+#pragma unroll
+        for (int c = 0; c < NP; ++c)
+            e[c] = expm1_wide(e[c]);
     } else {
 #pragma unroll
         for (int c = 0; c < NP; ++c)
@@ -612,7 +680,7 @@ struct XStage {
 };
 
 // Issue the loads of the line group starting at line0 (L lines).
-template <class R, int S, int W, int KX>
+template <class R, int S, int W, int KX, bool NT = false>
 __device__ __forceinline__ void xsweep_load(const typename Vec<R>::T *src, const StepArgs &a, int L,
                                             const Cx<R> *__restrict__ tab, int line0, XStage<R, KX> &g)
 {
@@ -630,7 +698,7 @@ __device__ __forceinline__ void xsweep_load(const typename Vec<R>::T *src, const
         const int u = sm + c * tpl;
         g.pre[c] = Cx<R>{R(0), R(0)};
         if (sact && u >= 1 && u <= nx - 1)
-            g.pre[c] = ld<R>(src, sbase + u);
+            g.pre[c] = NT ? ld_stream<R>(src, sbase + u) : ld<R>(src, sbase + u);
     }
 #pragma unroll
     for (int c2 = 0; c2 < 2; ++c2) {
@@ -640,21 +708,25 @@ __device__ __forceinline__ void xsweep_load(const typename Vec<R>::T *src, const
             const int tl = te / (W + 2), c = te - tl * (W + 2);
             const int tline = line0 + tl;
             if (tline < nlines)
-                g.tpre[c2] = tab[(size_t)(tline % ny) * (W + 2) + c];
+                g.tpre[c2] = ldg(tab, (int64_t)(tline % ny) * (W + 2) + c);
         }
     }
 }
 
 // The rest of the group from its loaded values: rescale and H1 into LDS,
-// the windowed solves, the wall terms and the write-back.
-template <class R, int S, int W, bool RT, int KX>
-__device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const StepArgs &a, int L,
-                                              const double *__restrict__ sm1p, int line0, XStage<R, KX> &g,
-                                              unsigned char *smem)
+// the windowed solves, the wall terms and the write-back.  The staged lines
+// use the padded layout of x_row_index: the zero entries around the
+// unknowns let each window read the row at compile-time offsets from its
+// segment's base entry.
+template <class R, int S, int W, bool RT, int KX, bool NT = false>
+__device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const StepArgs &a, int L, double sm1,
+                                              int line0, XStage<R, KX> &g, unsigned char *smem)
 {
+    constexpr int OFF = x_row_off(S, W);
+    constexpr int OFFE = x_row_index(OFF, S);  // entry of point u = 0
     Cx<R> *lin = reinterpret_cast<Cx<R> *>(smem);
     const int nx = a.nx, ny = a.ny;
-    const int LS = nx + nx / S + 1;
+    const int LS = x_row_len(nx, S, W);
     Cx<R> *ltab = lin + (size_t)L * LS;      // L rows of W + 2 table entries
     Cx<R> *d1 = ltab + (size_t)L * (W + 2);  // delta_1 of each staged line
     const int nlines = ny * (a.dim == 3 ? a.nz : 1);
@@ -666,8 +738,10 @@ __device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const Ste
     const int sj = sline % ny, sk = sline / ny;
     const bool sact = sline < nlines && sj > 0 && (a.dim == 2 || sk > 0);
     const int64_t sbase = (int64_t)sline * nx;
+    // LDS entry of point u >= 0 of a staged line
+    auto xe = [](int u) { return OFFE + u + u / S; };
     Cx<R>(&pre)[KX] = g.pre;
-    const R sr = R((!RT && sm1p) ? *sm1p : 0.0);  // the pending rescale, s - 1
+    const R sr = R(RT ? 0.0 : sm1);  // the pending rescale, s - 1
     if constexpr (RT || !std::is_same<R, double>::value) {
         Cx<R> *row = lin + sl * LS;
         const double y = a.y0 + sj * a.hy, z = a.z0 + sk * a.hz;
@@ -683,7 +757,7 @@ __device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const Ste
                     const R w = R(a.vx * x * x + vyz) + R(a.g) * norm2(v);
                     v = h1_apply<R, RT>(v, w, R(a.dt));
                 }
-                row[u + u / S] = v;
+                row[xe(u)] = v;
             }
         }
     } else {
@@ -706,7 +780,16 @@ __device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const Ste
         for (int c = 0; c < KX; ++c) {
             const int u = sm + c * tpl;
             if (u >= 1 && u <= nx - 1)
-                row[u + u / S] = pre[c] + ex[c] * pre[c];
+                row[xe(u)] = pre[c] + ex[c] * pre[c];
+        }
+    }
+    // zeros around the unknowns: points -OFF..0 and nx..nx-1+S+W of each line
+    {
+        constexpr int NPAD = OFF + 1 + S + W;
+        for (int e = tid; e < L * NPAD; e += 256) {
+            const int pl = e / NPAD, pk = e - pl * NPAD;
+            const int U = pk <= OFF ? pk : nx + OFF + (pk - OFF - 1);  // U = u + OFF
+            lin[pl * LS + x_row_index(U, S)] = Cx<R>{R(0), R(0)};
         }
     }
 #pragma unroll
@@ -723,15 +806,11 @@ __device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const Ste
     Cx<R> io[S];
     if (active) {
         const LineCoef<R> Lc = line_coef<R>(a.ax[0], a.omega * (a.y0 + j * a.hy));
-        const Cx<R> *row = lin + l * LS;
-        // window value r: point u = s0 - W - 1 + r of the staged line (zero
-        // outside the unknowns 1..nx-1, which the line does not stage)
-        auto ld = [&](int r) -> Cx<R> {
-            const int u = s0 - W - 1 + r;
-            const bool in = u >= 1 && u <= nx - 1;
-            const Cx<R> v = row[in ? u + u / S : 0];
-            return csel(in, v, Cx<R>{R(0), R(0)});
-        };
+        // window value r: point u = s0 - W - 1 + r = q S - W + r, i.e. U = u +
+        // OFF = q S + (OFF - W + r) >= 0, at entry q (S + 1) + x_row_index(OFF
+        // - W + r, S) (OFF is a multiple of S): a constant offset per r
+        const Cx<R> *seg = lin + l * LS + q * (S + 1);
+        auto ld = [&](int r) -> Cx<R> { return seg[x_row_index(OFF - W + r, S)]; };
         Cx<R> df;
         window_solve<R, S, W, RT ? 2 : 1>(s0, nx, Lc, ltab[l * (W + 2)], ltab[l * (W + 2) + 1], ld, io, df);
         if (q == 0)
@@ -739,16 +818,19 @@ __device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const Ste
     }
     __syncthreads();
     if (active) {
-        Cx<R> *row = lin + l * LS;
-        const Cx<R> df = d1[l];
+        // the outputs back into the row; points beyond nx - 1 land in the
+        // row's trailing zeros, which nothing reads any more
+        Cx<R> *seg = lin + l * LS + q * (S + 1) + OFFE + 1;  // entry of point s0
+        if (q * S < W) {  // the wall rows 1..W lie in the first segments
+            const Cx<R> df = d1[l];
 #pragma unroll
-        for (int r = 0; r < S; ++r) {
-            const int u = s0 + r;
-            if (u <= W)
-                io[r] = io[r] - df * ltab[l * (W + 2) + 1 + u];
-            if (u <= nx - 1)
-                row[u + u / S] = io[r];
+            for (int r = 0; r < S; ++r)
+                if (s0 + r <= W)
+                    io[r] = io[r] - df * ltab[l * (W + 2) + 1 + s0 + r];
         }
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+            seg[x_row_index(1 + r, S) - 1] = io[r];
     }
     __syncthreads();
     if (sact) {
@@ -756,8 +838,12 @@ __device__ __forceinline__ void xsweep_finish(typename Vec<R>::T *dst, const Ste
 #pragma unroll
         for (int c = 0; c < KX; ++c) {
             const int u = sm + c * tpl;
-            if (u >= 1 && u <= nx - 1)
-                st<R>(dst, sbase + u, row[u + u / S]);
+            if (u >= 1 && u <= nx - 1) {
+                if (NT)
+                    st_stream<R>(dst, sbase + u, row[xe(u)]);
+                else
+                    st<R>(dst, sbase + u, row[xe(u)]);
+            }
         }
     }
 }
@@ -773,7 +859,7 @@ __global__ __launch_bounds__(256, kSweepWaves) void k_xsweep(const typename Vec<
     extern __shared__ __align__(16) unsigned char smem_raw[];
     XStage<R, KX> g;
     xsweep_load<R, S, W, KX>(src, a, L, tab, blockIdx.x * L, g);
-    xsweep_finish<R, S, W, RT, KX>(dst, a, L, sm1p, blockIdx.x * L, g, smem_raw);
+    xsweep_finish<R, S, W, RT, KX>(dst, a, L, sm1p ? *sm1p : 0.0, blockIdx.x * L, g, smem_raw);
 }
 
 // s - 1 of the pending rescale, s = 1/sqrt(dV sum of the npart norm
@@ -803,7 +889,7 @@ constexpr int kYLines = 32;
 constexpr int kSegBlock = 8;
 static_assert(kYLines * kSegBlock == 256, "strided sweep blocks have 256 threads");
 
-template <class R, int S, int W>
+template <class R, int S, int W, bool NT = false>
 __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__restrict__ src,
                                                    typename Vec<R>::T *__restrict__ dst, int n, int64_t base,
                                                    int64_t stride, int nlines, int line0, int by, bool plane_ok,
@@ -842,7 +928,7 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
     Cx<R> io[S];
     if (active) {
         Cx<R> df;
-        window_solve<R, S, W>(s0, n, Lc, trow[0], trow[1], [&](int r) { return tile[(ty * S + r) * LN + tx]; },
+        window_solve<R, S, W>(s0, n, Lc, ldg(trow, 0), ldg(trow, 1), [&](int r) { return tile[(ty * S + r) * LN + tx]; },
                               io, df);
         if (q == 0)
             d1[tx] = df;
@@ -855,7 +941,7 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
             for (int r = 0; r < S; ++r) {
                 const int u = s0 + r;
                 if (u <= W)
-                    io[r] = io[r] - df * trow[1 + u];
+                    io[r] = io[r] - df * ldg(trow, 1 + u);
             }
         }
     }
@@ -864,7 +950,10 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
         for (int r = 0; r < S; ++r) {
             const int u = s0 + r;
             if (u <= n - 1) {
-                st<R>(dst, base + (int64_t)u * stride + line0 + tx, io[r]);
+                if (NT)
+                    st_stream<R>(dst, base + (int64_t)u * stride + line0 + tx, io[r]);
+                else
+                    st<R>(dst, base + (int64_t)u * stride + line0 + tx, io[r]);
                 if (emit)
                     acc += (double)io[r].re * (double)io[r].re + (double)io[r].im * (double)io[r].im;
             }
@@ -874,7 +963,7 @@ __device__ __forceinline__ void strided_sweep_tile(const typename Vec<R>::T *__r
 
 // One y tile: columns bx*kYLines .. +kYLines-1 of plane bz, segment group
 // by; the norm partial of its outputs (EMIT) goes to *partial.
-template <class R, int S, int W, bool EMIT>
+template <class R, int S, int W, bool EMIT, bool NT = false>
 __device__ __forceinline__ void ysweep_block(const typename Vec<R>::T *__restrict__ src,
                                              typename Vec<R>::T *__restrict__ dst, const StepArgs &a, int bx, int by,
                                              int bz, double *partial, const Cx<R> *__restrict__ tab, double *red)
@@ -889,8 +978,8 @@ __device__ __forceinline__ void ysweep_block(const typename Vec<R>::T *__restric
         trow = tab + (size_t)i * (W + 2);
     }
     double acc = 0.0;
-    strided_sweep_tile<R, S, W>(src, dst, ny, (int64_t)bz * nx * ny, nx, nx, bx * kYLines, by, plane_ok, Lc,
-                                trow, EMIT, acc);
+    strided_sweep_tile<R, S, W, NT>(src, dst, ny, (int64_t)bz * nx * ny, nx, nx, bx * kYLines, by, plane_ok, Lc,
+                                    trow, EMIT, acc);
     if (EMIT) {
         const double b = block_sum_256(acc, red);
         if (threadIdx.x == 0 && threadIdx.y == 0)
@@ -2039,11 +2128,15 @@ static __global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__rest
     }
 }
 
-// One work-list item (instance, first line) per block.
+// One work-list item (instance, first line) per block.  With use_scale the
+// pending rescale of the instance is formed here, from the norm partials the
+// previous y-sweep left at partials[I.ypoff ..] (every wave sums them in
+// the fixed order of wave_partials_sum while its state loads are in flight,
+// so every block, and the finish pass, gets the same bits).
 template <class R, int S, int W, bool RT, int KX>
 __global__ __launch_bounds__(256, kSweepWaves) void k_batch_xsweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ xwork,
-                                                      const int *__restrict__ nitems, const double *__restrict__ scale,
-                                                      int use_scale)
+                                                      const int *__restrict__ nitems,
+                                                      const double *__restrict__ partials, int use_scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int it = blockIdx.x;
@@ -2053,10 +2146,11 @@ __global__ __launch_bounds__(256, kSweepWaves) void k_batch_xsweep(const Inst2D 
     const Inst2D &I = insts[wk.x];
     const StepArgs a = inst_args(I);
     XStage<R, KX> g;
-    xsweep_load<R, S, W, KX>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]), a, I.xl,
-                             reinterpret_cast<const Cx<R> *>(I.tab[0]), wk.y, g);
-    xsweep_finish<R, S, W, RT, KX>(reinterpret_cast<typename Vec<R>::T *>(I.buf[1]), a, I.xl,
-                                   use_scale ? scale + wk.x : nullptr, wk.y, g, smem_raw);
+    xsweep_load<R, S, W, KX, kBatchStream>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]), a, I.xl,
+                                   reinterpret_cast<const Cx<R> *>(I.tab[0]), wk.y, g);
+    const double sm1 = use_scale ? norm_scale_m1(wave_partials_sum(partials + I.ypoff, I.ygx * I.ygy), I.dV) : 0.0;
+    xsweep_finish<R, S, W, RT, KX, kBatchStream>(reinterpret_cast<typename Vec<R>::T *>(I.buf[1]), a, I.xl, sm1, wk.y, g,
+                                         smem_raw);
 }
 
 // One item per block, XCD-aware (xcd_item): the launch has at least
@@ -2073,9 +2167,9 @@ __global__ __launch_bounds__(256, kSweepWaves) void k_batch_ysweep(const Inst2D 
     const Inst2D &I = insts[wk.x];
     const StepArgs a = inst_args(I);
     const int by = wk.y % I.ygy, bx = wk.y / I.ygy;
-    ysweep_block<R, S, W, EMIT>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[1]),
-                                reinterpret_cast<typename Vec<R>::T *>(I.buf[0]), a, bx, by, 0,
-                                partials + I.ypoff + wk.y, reinterpret_cast<const Cx<R> *>(I.tab[1]), red);
+    ysweep_block<R, S, W, EMIT, kBatchStream>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[1]),
+                                      reinterpret_cast<typename Vec<R>::T *>(I.buf[0]), a, bx, by, 0,
+                                      partials + I.ypoff + wk.y, reinterpret_cast<const Cx<R> *>(I.tab[1]), red);
 }
 
 }  // namespace sscn

@@ -192,10 +192,10 @@ void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
 {
     if (b->xshort)
         hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
+                           b->d_inst, b->d_xwork, b->d_nx, (const double *)b->ypart, use_scale);
     else
         hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, b->d_xwork, b->d_nx, b->d_scale, use_scale);
+                           b->d_inst, b->d_xwork, b->d_nx, (const double *)b->ypart, use_scale);
 }
 
 template <class R, int W, bool EMIT>
@@ -207,11 +207,13 @@ void go_batch_y(const sscn_batch *b, int grid, hipStream_t st)
 }
 
 // One step of the sweep plan for every listed instance (state in buf[0]).
-// ev (optional, 4 events): recorded before the rescale kernel, before the
-// x-sweep, before the y-sweep and after it.
+// The x-sweep forms the pending rescale itself.  ev (optional, 4 events):
+// recorded before the x-sweep (twice: the step has no rescale kernel of its
+// own), before the y-sweep and after it.
 template <class R>
 void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k, hipEvent_t *ev)
 {
+    (void)grid_k;
     auto mark = [&](int t) {
         if (ev)
             (void)hipEventRecord(ev[t], st);
@@ -219,9 +221,6 @@ void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int
     const bool imag = b->mode == SSCN_IMAG;
     const int sc = (imag && b->pending) ? 1 : 0;
     mark(0);
-    if (sc)
-        hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
-                           b->d_nk, b->ypart, b->d_scale);
 #define SSCN_CALL_BX(Wc)                                 \
     do {                                                 \
         if (imag)                                        \

@@ -40,11 +40,11 @@ int64_t npoints(const sscn_params &p)
     return (int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
 }
 
-// Lines per block of the x-sweep and the LDS it stages: L lines of nx + nx/S
-// + 1 padded points, the pivot-table rows and the wall terms.
+// Lines per block of the x-sweep and the LDS it stages: L padded lines
+// (x_row_len entries), the pivot-table rows and the wall terms.
 void set_x_lines(sscn_handle *h, int L)
 {
-    const size_t LS = (size_t)h->p.nx + h->p.nx / kSegX + 1;
+    const size_t LS = (size_t)x_row_len(h->p.nx, kSegX, h->W[0]);
     h->xL = L;
     h->xlds = (L * LS + (size_t)L * (h->W[0] + 2) + L) * h->esize;
 }
@@ -1936,7 +1936,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / h.p.nx, 512 / (b->W + 2)}));
         while (L & (L - 1))
             L &= L - 1;
-        const size_t LS = (size_t)h.p.nx + h.p.nx / kSegX + 1;
+        const size_t LS = (size_t)x_row_len(h.p.nx, kSegX, b->W);
         const size_t xl = (L * LS + (size_t)L * (b->W + 2) + L) * esize;
         if (nseg > 256 || h.p.nx > 256 * kXLoad || xl > kXLdsCap)
             b->sweeps_ok = false;

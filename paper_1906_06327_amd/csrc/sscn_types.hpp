@@ -20,4 +20,16 @@ struct StepArgs {
     AxisCoef ax[3];
 };
 
+// Staged x-line layout of the x-sweeps (segments of S outputs, window halo
+// W).  Point u of a line sits at LDS entry x_row_index(u + x_row_off(S, W),
+// S): one padding entry after every S points, so that the threads of
+// consecutive segments hit different banks.  The row covers u = -off ..
+// nx - 1 + S + W, where off = x_row_off(S, W) >= W + 1 is a multiple of S;
+// the entries outside the unknowns 1..nx-1 hold zeros, so every window of a
+// segment (points s - W - 1 .. s + S + W) reads the row at constant offsets
+// from the segment's base entry without a bounds test.
+constexpr int x_row_off(int S, int W) { return S * ((W + S) / S); }
+constexpr int x_row_index(int U, int S) { return U + U / S; }
+constexpr int x_row_len(int nx, int S, int W) { return x_row_index(nx + S + W + x_row_off(S, W), S) + 1; }
+
 }  // namespace sscn

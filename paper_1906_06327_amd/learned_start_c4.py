@@ -300,7 +300,8 @@ def _batch_arm(params, cfgs, max_steps, tol, learned, log, tag):
 def evaluate(params, arms=("batched", "single"), seed=EVAL_SEED, max_steps=2000000, tol=1e-8,
              log=_log_stderr):
     """The four arms on the held-out draws of `seed` (see the module
-    docstring); `arms` selects the batched pair, the single pair or both."""
+    docstring); `arms` selects among "batched" (both batched arms),
+    "single" (both one-at-a-time arms), "plain" and "learned_alone"."""
     cfgs = draws(seed)
     res = dict(seed=seed, instances=len(cfgs), tol=tol, max_steps=max_steps, dt=cfgs[0]["dt"],
                grid_sides=[c["nx"] for c in cfgs],
@@ -314,10 +315,11 @@ def evaluate(params, arms=("batched", "single"), seed=EVAL_SEED, max_steps=20000
         res["distance_to_converged"] = dict(
             one_vortex=[round(phase_distance(s0[k], f0[k]), 5) for k in range(len(cfgs))],
             learned=[round(phase_distance(s1[k], f0[k]), 5) for k in range(len(cfgs))])
-    if "single" in arms:
+    if "single" in arms or "plain" in arms:
         r2, w2, _ = _single_arm(params, cfgs, max_steps, tol, False, log, "plain")
-        r3, w3, i3 = _single_arm(params, cfgs, max_steps, tol, True, log, "learned alone")
         res["plain"] = dict(wall_s=round(w2, 3), rows=r2)
+    if "single" in arms or "learned_alone" in arms:
+        r3, w3, i3 = _single_arm(params, cfgs, max_steps, tol, True, log, "learned alone")
         res["learned_alone"] = dict(wall_s=round(w3, 3), inference_and_resampling_s=round(i3, 3), rows=r3)
     return res
 
@@ -332,7 +334,7 @@ def main(argv=None):
     ap.add_argument("--clip", type=float, default=2.0)
     ap.add_argument("--weights", default=None, help="load weights (npz) and skip generation and training")
     ap.add_argument("--save-weights", default=None)
-    ap.add_argument("--evaluate", default="", help="comma list of arms: batched, single")
+    ap.add_argument("--evaluate", default="", help="comma list of arms: batched, single, plain, learned_alone")
     ap.add_argument("--eval-steps", type=int, default=2000000)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)

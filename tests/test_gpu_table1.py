@@ -11,6 +11,13 @@ oracle's evaluation of the same state) must match the printed values of
 Table 1 (tests/golden/table1.json) and the vortex counts those of Sec. 4.
 Tolerance 2e-3: the printed rounding (5e-4) plus the relaxation left after
 the paper's step counts (mu still moves by about 1e-4 per 2.5 x 10^5 steps).
+
+The 3D column (Fig. 5: lambda = 100, h_z = 0.025, 33 points in z) is
+checked for lattice (a): the converged 2D lattice times the normalised
+Gaussian of width d_z = 1/sqrt(lambda) in z (the product form of Eq. (fun),
+sscn_extend_z), with g_3D = g_2D sqrt(2 pi / lambda) (the quasi-2D
+reduction of Sec. 2), relaxed in 3D imaginary time in complex128.  Table 1
+prints the 3D values to two decimals: tolerance 1e-2.
 """
 import json
 import os
@@ -36,6 +43,19 @@ def P():
     return P
 
 
+N3D = 100000  # 3D relaxation steps from the product start (mu_4th settles to 1e-5 within them)
+
+
+def lattice_a_2d(P):
+    """The 2D lattice (a) after the paper's NPAS from Eq. (fun)."""
+    from paper_1906_06327_amd import continuation as C
+    g, omega, n, _ = C.CHAIN[0]
+    s = P.Solver(C.params(g, omega, n))
+    s.init_state(1, W.phase_field(13, n, n), 1.0)
+    s.step(3000000)
+    return s
+
+
 def test_table1_lattices_a_and_b(P):
     from paper_1906_06327_amd import continuation as C
     cols = GOLDEN["columns"]
@@ -45,14 +65,14 @@ def test_table1_lattices_a_and_b(P):
         col = cols[k]
         assert (col["g2d"], col["omega"], col["grid_2d"], col["vortices"]) == (g, omega, n + 1, nv)
         print(f"[table1] lattice g={g} Omega={omega} on {n}^2, {steps[k]} steps", flush=True)
-        s = P.Solver(C.params(g, omega, n))
         if prev is None:
-            s.init_state(1, W.phase_field(13, n, n), 1.0)
+            s = lattice_a_2d(P)
         else:
+            s = P.Solver(C.params(g, omega, n))
             P.embed_state(prev.psi, s.psi)
             s.set_state_device()
             prev.close()
-        s.step(steps[k])
+            s.step(steps[k])
         psi = s.get_state()
         count = s.vortex_count()
         obs = s.observables()
@@ -68,3 +88,37 @@ def test_table1_lattices_a_and_b(P):
         assert abs(f["norm"] - 1.0) < 1e-12
         prev = s
     prev.close()
+
+
+def test_table1_3d_lattice_a(P):
+    import math
+    from paper_1906_06327_amd import continuation as C
+    col = GOLDEN["columns"][0]
+    g3, omega, n, nv = C.CHAIN_3D[0]
+    assert (omega, n + 1, C.NZ_3D + 1, nv) == (col["omega"], col["grid_3d"][0], col["grid_3d"][2], col["vortices"])
+    assert abs(g3 - col["g2d"] * math.sqrt(2 * math.pi / C.LAM_3D)) < 1e-6
+    print(f"[table1-3d] 2D lattice (a), 3000000 steps", flush=True)
+    s2 = lattice_a_2d(P)
+    p3 = C.params(g3, omega, n, dim=3)
+    s3 = P.Solver(p3)
+    P.extend_z(s2.psi, s3.psi, C.HZ_3D, 1.0 / math.sqrt(C.LAM_3D))
+    s3.set_state_device()
+    s2.close()
+    done, every = 0, 50000
+    while done < N3D:
+        s3.step(every)
+        done += every
+        o = s3.observables()
+        print(f"[table1-3d] {done} steps: mu_4th {o['mu_4th']:.5f} E_4th {o['energy_4th']:.5f} "
+              f"(paper {col['mu_3d']}, {col['E_3d']}), mu {o['mu']:.6f}", flush=True)
+    count = s3.vortex_count()
+    psi = s3.get_state()
+    o = s3.observables()
+    s3.close()
+    f = O.functional_fourth_order(O.make_params(**p3), psi)
+    print(f"[table1-3d] {count} vortices in the z = 0 plane (paper {nv})", flush=True)
+    assert count == nv
+    assert abs(o["mu_4th"] - col["mu_3d"]) <= 1e-2
+    assert abs(o["energy_4th"] - col["E_3d"]) <= 1e-2
+    assert abs(o["mu_4th"] - f["mu"]) <= 1e-10 * abs(f["mu"])
+    assert abs(o["energy_4th"] - f["energy"]) <= 1e-10 * abs(f["energy"])
