@@ -24,7 +24,9 @@ Also reported on the same JSON line:
   variants      the 512^2 workload (complex128 and complex64, imaginary and
                 real time), the 3D 256 x 256 x 64 workload (complex64 and
                 complex128), each followed by real-time steps with norm and
-                energy drift;
+                energy drift; the learned start's network (forward pass and
+                training iteration at 256^2, batch 16, against the bf16
+                matrix-core peak);
   converge      time to converged lattices: the 128^2 workload (complex128;
                 complex64 then complex128) and, per instance, the 64-instance
                 batch (mu changing by < 1e-8 over 0.1 time units at two
@@ -102,6 +104,9 @@ def parse():
                          "256 MiB device copy (counter calibration), 20 steps of the 64-instance "
                          "complex128 batch, 50 steps of the 512^2 complex128 workload, 20 steps "
                          "of the 3D complex64 workload")
+    ap.add_argument("--profile-network", action="store_true",
+                    help="run a short fixed sample of the learned start's network for a kernel trace and "
+                         "exit: 3 forward passes and 2 training iterations at 256^2, batch 16")
     return ap.parse_args()
 
 
@@ -130,6 +135,9 @@ def profile_sample(P, torch):
     print("profile-sample: copy 256 MiB x3 done", flush=True)
     del a, c
     b = make_batch(P, batch_cfgs(0))
+    # the plan the headline's autotuner picks on this workload (under a
+    # counter-collecting profiler the autotuner's own timings are distorted)
+    b.set_plan(P.PLAN_SWEEPS)
     b.prepare_steps(20)
     b.step(20)
     sync(torch)
@@ -417,6 +425,63 @@ def cpu_baseline(cfgs, seconds):
     return out
 
 
+PEAK_BF16_TFLOPS = 2500.0
+
+
+def conv_flops(net):
+    """Multiply-add flops (2 per product) of the network's 3x3 convolutions
+    in one forward pass of net.N samples."""
+    return sum(2.0 * net.N * net.shapes[n][0] * net.shapes[n][1] * 9 * cin * cout for n, cin, cout, _ in net.specs)
+
+
+def network_rate(P, torch, N=16, H=256, reps=10):
+    """The learned start's network (6 levels, 32-64-128-256-256 channels and a
+    256-channel bottleneck, 256 x 256 points, batch N): average time of a
+    forward pass and of a training iteration (forward, loss, backward, Adam)
+    over `reps` calls between HIP events, and their convolution flop rates
+    against the dense bf16 matrix-core peak.  The backward pass does twice
+    the forward's convolution flops (input and weight gradients)."""
+    from paper_1906_06327_amd import nn
+    net = nn.UNet(N, H, H, chans=(32, 64, 128, 256, 256), bott=256, seed=7)
+    rng = np.random.default_rng(7)
+    xf = rng.standard_normal((N, H, H, nn.IN_CH)).astype(np.float32)
+    x = torch.tensor(xf, device="cuda").to(torch.bfloat16).view(torch.int16)
+    tgt = torch.tensor(rng.standard_normal((N, H, H, 2)).astype(np.float32), device="cuda")
+    fl = conv_flops(net)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        net.forward(x)
+    sync(torch)
+    e0.record()
+    for _ in range(reps):
+        net.forward(x)
+    e1.record()
+    sync(torch)
+    fwd_ms = e0.elapsed_time(e1) / reps
+
+    def train_iter():
+        net.forward(x)
+        net.loss_and_grad(tgt)
+        net.backward(net.gacts["out"])
+        net.adam_step(lr=1e-5)
+    train_iter()
+    sync(torch)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        train_iter()
+    sync(torch)
+    it_ms = (time.perf_counter() - t0) / reps * 1e3
+    fwd_tf = fl / (fwd_ms * 1e-3) / 1e12
+    it_tf = 3 * fl / (it_ms * 1e-3) / 1e12
+    return {"network": "U-Net, 6 levels, 32-64-128-256-256 + 256 bottleneck", "batch": N, "grid": [H, H],
+            "conv_gflop_forward": round(fl / 1e9, 1), "forward_ms": round(fwd_ms, 3),
+            "forward_tflops": round(fwd_tf, 1), "forward_frac_bf16_peak": round(fwd_tf / PEAK_BF16_TFLOPS, 4),
+            "train_iteration_ms": round(it_ms, 3), "train_tflops": round(it_tf, 1),
+            "train_frac_bf16_peak": round(it_tf / PEAK_BF16_TFLOPS, 4), "peak_tflops": PEAK_BF16_TFLOPS,
+            "timing": f"forward: HIP events over {reps} passes; training: wall clock over {reps} iterations "
+                      f"(the loss reads its value back to the host each iteration)"}
+
+
 def copy_bandwidth(torch, nbytes=1 << 30, reps=10):
     """GB/s of a plain device-to-device copy (read + write counted), timed
     with HIP events: the achievable HBM bandwidth the kernels are also
@@ -450,6 +515,11 @@ def main():
     torch.cuda.set_device(0)
     if a.profile_sample:
         profile_sample(P, torch)
+        return
+    if a.profile_network:
+        r = network_rate(P, torch, reps=2)
+        print(f"profile-network: forward {r['forward_ms']} ms ({r['forward_tflops']} TFLOP/s), training "
+              f"iteration {r['train_iteration_ms']} ms", flush=True)
         return
 
     prec = 0 if a.precision == "c128" else 1
@@ -489,6 +559,7 @@ def main():
         c3 = W.CONFIGS["c3"]
         variants["c3_3d_complex64"] = single_variant(P, torch, c3, 1024, 64, real_steps=1024)
         variants["c3_3d_complex128"] = single_variant(P, torch, dict(c3, precision=0), 512, 64, real_steps=512)
+        variants["learned_start_network"] = network_rate(P, torch)
         out["variants"] = variants
         c1 = W.CONFIGS["c1"]
         conv = {"workload": "2D 128x128 on [-6.4,6.4)^2, g=100, Omega=0.6, dt=1e-3, one-vortex "

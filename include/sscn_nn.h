@@ -31,15 +31,29 @@ extern "C" {
 #endif
 
 /* y = act(conv3x3(x, w) + bias), zero padding 1, stride 1.  Matrix-core
- * implicit GEMM (bf16 x bf16 -> fp32).  act: 0 none, 1 leaky ReLU (0.1).
- * out_f32: y is fp32 instead of bf16.  bias may be NULL. */
+ * implicit GEMM (bf16 x bf16 -> fp32): block tiles of 128 pixels x up to
+ * 128 output channels on the gfx950 16x16x32 bf16 instructions.  act: 0
+ * none, 1 leaky ReLU (0.1).  out_f32: y is fp32 instead of bf16.  bias may
+ * be NULL.  ws (device, ws_floats fp32 elements, may be NULL): workspace
+ * for splitting the K sum of small layers (a grid of fewer than 512 blocks)
+ * over more blocks; the partial sums are added in a fixed order, so results
+ * do not depend on the split.  With ws NULL or smaller than
+ * sscn_nn_conv_ws_floats reports, the layer runs unsplit (same values up
+ * to fp32 rounding order). */
 int sscn_nn_conv3x3(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
-                    int act, int out_f32, void *y, int ldy, int yoff, void *stream);
+                    int act, int out_f32, void *y, int ldy, int yoff, float *ws, int64_t ws_floats, void *stream);
+
+/* fp32 workspace elements a convolution of these sizes uses to split its K
+ * sum (0: it is not split).  For the input gradient of a convolution with
+ * Cin inputs and Cout outputs, ask for (Cin = Cout, Cout = Cin). */
+int sscn_nn_conv_ws_floats(int N, int H, int W, int Cin, int Cout, int64_t *floats);
 
 /* Input gradient of a convolution: dx = conv3x3(dy, w flipped and
- * transposed), bf16.  wt_scratch: 9*Cin*Cout bf16 elements. */
+ * transposed), bf16.  wt_scratch: 9*Cin*Cout bf16 elements.  ws, ws_floats:
+ * as sscn_nn_conv3x3 (the convolution with Cout inputs and Cin outputs). */
 int sscn_nn_conv3x3_dgrad(const void *dy, int N, int H, int W, int Cout, const void *w, int Cin,
-                          void *wt_scratch, void *dx, int lddx, int dxoff, void *stream);
+                          void *wt_scratch, void *dx, int lddx, int dxoff, float *ws, int64_t ws_floats,
+                          void *stream);
 
 /* Size (floats) of the scratch sscn_nn_conv3x3_wgrad needs. */
 int sscn_nn_wgrad_scratch(int N, int H, int W, int Cin, int Cout, int64_t *floats);

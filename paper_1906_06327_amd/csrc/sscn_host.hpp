@@ -42,6 +42,13 @@ constexpr int kTileR = SSCN_TILE_R;   // fused 2D step: output tile rows (y)
 constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
 constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
 constexpr size_t kXLdsCap = 150 * 1024;  // dynamic LDS of an x-sweep block
+// Infinity Cache budget of a group of batched instances (both state
+// buffers), MiB; SSCN_BATCH_GROUP_MB overrides it.  0 (the default) puts
+// every instance in one group: on the 64-instance complex128 workload (309
+// MB in two buffers) two groups of 155 MB measured 1.7 % faster with cached
+// state accesses and 10 % slower with streamed ones, so the batch runs as
+// one group with streamed accesses.
+constexpr int kBatchGroupMB = 0;
 
 
 }  // namespace sscn
@@ -176,7 +183,14 @@ struct sscn_batch {
     int total_x = 0, total_y = 0, grid_x = 0, grid_y = 0, grid_k = 0;
     size_t xlds = 0;
     int2 *d_xwork = nullptr, *d_ywork = nullptr;
-    int *d_nx = nullptr, *d_ny = nullptr, *d_klist = nullptr, *d_nk = nullptr;
+    int *d_nx = nullptr, *d_ny = nullptr, *d_klist = nullptr, *d_nk = nullptr;  // d_nx, d_ny: one per group
+    // Groups of the sweep plan: instances whose two state buffers together
+    // fit the Infinity Cache budget run all the steps of a call before the
+    // next group's.  Each group owns a fixed region of the x and y work
+    // lists (offset, items of all its instances, items of its active ones).
+    int ngroups = 1;
+    std::vector<int> group;  // group of each instance
+    std::vector<int> gx_off, gx_tot, gx_cnt, gy_off, gy_tot, gy_cnt;
     double *ypart = nullptr, *d_scale = nullptr;
     float tune_ms[3] = {0, 0, 0};
 };
@@ -209,6 +223,6 @@ hipError_t batch_allow_x_lds_all(int W);
 // (optional): 4 events recorded before the rescale, x- and y-sweep kernels
 // and after the y-sweep.
 template <class R>
-void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k, hipEvent_t *ev = nullptr);
+void batch_sweep_step(sscn_batch *b, hipStream_t st, int g, bool all, hipEvent_t *ev = nullptr);
 
 }  // namespace sscn

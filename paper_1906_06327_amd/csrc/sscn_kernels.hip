@@ -188,32 +188,36 @@ template hipError_t allow_fused_lds_all<SSCN_REAL_T>(int);
 #elif SSCN_PART == 3
 
 template <class R, int W, bool RT>
-void go_batch_x(const sscn_batch *b, int grid, int use_scale, hipStream_t st)
+void go_batch_x(const sscn_batch *b, int g, int grid, int use_scale, hipStream_t st)
 {
+    const int2 *work = b->d_xwork + b->gx_off[g];
     if (b->xshort)
         hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, b->d_xwork, b->d_nx, (const double *)b->ypart, use_scale);
+                           b->d_inst, work, b->d_nx + g, (const double *)b->ypart, use_scale);
     else
         hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, b->d_xwork, b->d_nx, (const double *)b->ypart, use_scale);
+                           b->d_inst, work, b->d_nx + g, (const double *)b->ypart, use_scale);
 }
 
 template <class R, int W, bool EMIT>
-void go_batch_y(const sscn_batch *b, int grid, hipStream_t st)
+void go_batch_y(const sscn_batch *b, int g, int grid, hipStream_t st)
 {
     // one block per item on a grid of whole XCD rounds (xcd_item)
     hipLaunchKernelGGL((k_batch_ysweep<R, kSeg, W, EMIT>), dim3(round8(std::max(grid, 1))), dim3(kYLines, kSegBlock), 0,
-                       st, b->d_inst, b->d_ywork, b->d_ny, b->ypart);
+                       st, b->d_inst, b->d_ywork + b->gy_off[g], b->d_ny + g, b->ypart);
 }
 
-// One step of the sweep plan for every listed instance (state in buf[0]).
-// The x-sweep forms the pending rescale itself.  ev (optional, 4 events):
-// recorded before the x-sweep (twice: the step has no rescale kernel of its
-// own), before the y-sweep and after it.
+// One step of the sweep plan for the listed instances of group g (state in
+// buf[0]); all: launch grids covering every instance of the group (graph
+// capture), else the current list lengths.  The x-sweep forms the pending
+// rescale itself.  ev (optional, 4 events): recorded before the x-sweep
+// (twice: the step has no rescale kernel of its own), before the y-sweep
+// and after it.
 template <class R>
-void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int grid_k, hipEvent_t *ev)
+void batch_sweep_step(sscn_batch *b, hipStream_t st, int g, bool all, hipEvent_t *ev)
 {
-    (void)grid_k;
+    const int grid_x = all ? b->gx_tot[g] : b->gx_cnt[g];
+    const int grid_y = all ? b->gy_tot[g] : b->gy_cnt[g];
     auto mark = [&](int t) {
         if (ev)
             (void)hipEventRecord(ev[t], st);
@@ -224,9 +228,9 @@ void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int
 #define SSCN_CALL_BX(Wc)                                 \
     do {                                                 \
         if (imag)                                        \
-            go_batch_x<R, Wc, false>(b, grid_x, sc, st); \
-        else                                             \
-            go_batch_x<R, Wc, true>(b, grid_x, 0, st);   \
+            go_batch_x<R, Wc, false>(b, g, grid_x, sc, st); \
+        else                                                \
+            go_batch_x<R, Wc, true>(b, g, grid_x, 0, st);   \
     } while (0)
     mark(1);
     SSCN_W_SWITCH(b->W, SSCN_CALL_BX);
@@ -235,9 +239,9 @@ void batch_sweep_step(sscn_batch *b, hipStream_t st, int grid_x, int grid_y, int
 #define SSCN_CALL_BY(Wc)                             \
     do {                                             \
         if (imag)                                    \
-            go_batch_y<R, Wc, true>(b, grid_y, st);  \
-        else                                         \
-            go_batch_y<R, Wc, false>(b, grid_y, st); \
+            go_batch_y<R, Wc, true>(b, g, grid_y, st);  \
+        else                                            \
+            go_batch_y<R, Wc, false>(b, g, grid_y, st); \
     } while (0)
     SSCN_W_SWITCH(b->W, SSCN_CALL_BY);
 #undef SSCN_CALL_BY
@@ -269,7 +273,7 @@ hipError_t batch_allow_x_lds_all(int W)
     return e;
 }
 
-template void batch_sweep_step<SSCN_REAL_T>(sscn_batch *, hipStream_t, int, int, int, hipEvent_t *);
+template void batch_sweep_step<SSCN_REAL_T>(sscn_batch *, hipStream_t, int, bool, hipEvent_t *);
 template hipError_t batch_allow_x_lds_all<SSCN_REAL_T>(int);
 
 #endif

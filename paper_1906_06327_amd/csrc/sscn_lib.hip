@@ -679,6 +679,52 @@ void release_step_buffers(sscn_handle *h)
 // ---------------------------------------------------------------------------
 // Batched 2D instances (one fused launch per step over all their tiles).
 
+// Groups of the sweep plan (sscn_batch::group): G = ceil(bytes / budget)
+// groups, where bytes counts both state buffers of every instance, filled
+// largest instance first into the group with the fewest bytes so far.  Each
+// group's regions of the x and y work lists follow the previous group's.
+void batch_groups(sscn_batch *b, size_t esize)
+{
+    int64_t mb = kBatchGroupMB;
+    if (const char *e = std::getenv("SSCN_BATCH_GROUP_MB"))
+        mb = std::max(0L, std::strtol(e, nullptr, 10));
+    std::vector<int64_t> bytes(b->n);
+    int64_t total = 0;
+    for (int k = 0; k < b->n; ++k) {
+        bytes[k] = 2 * (int64_t)b->p[k].nx * b->p[k].ny * (int64_t)esize;
+        total += bytes[k];
+    }
+    const int64_t budget = mb * (1 << 20);
+    int G = budget > 0 ? (int)((total + budget - 1) / budget) : 1;
+    G = std::max(1, std::min(G, b->n));
+    std::vector<int> order(b->n);
+    for (int k = 0; k < b->n; ++k)
+        order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return bytes[x] > bytes[y]; });
+    std::vector<int64_t> load(G, 0);
+    b->group.assign(b->n, 0);
+    for (int k : order) {
+        const int g = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        b->group[k] = g;
+        load[g] += bytes[k];
+    }
+    b->ngroups = G;
+    b->gx_tot.assign(G, 0);
+    b->gy_tot.assign(G, 0);
+    for (int k = 0; k < b->n; ++k) {
+        b->gx_tot[b->group[k]] += b->xitems[k];
+        b->gy_tot[b->group[k]] += b->yitems[k];
+    }
+    b->gx_off.assign(G, 0);
+    b->gy_off.assign(G, 0);
+    for (int g = 1; g < G; ++g) {
+        b->gx_off[g] = b->gx_off[g - 1] + b->gx_tot[g - 1];
+        b->gy_off[g] = b->gy_off[g - 1] + b->gy_tot[g - 1];
+    }
+    b->gx_cnt = b->gx_tot;
+    b->gy_cnt = b->gy_tot;
+}
+
 // Upload the work lists of the active instances: tiles (largest instances
 // first), finish chunks and observable chunks with each instance's range.
 int batch_lists(sscn_batch *b, bool all_for_obs = false)
@@ -688,18 +734,23 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
         order[k] = k;
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return b->ntiles[x] > b->ntiles[y]; });
-    std::vector<int2> wl, fl, ol, xl, yl;
+    std::vector<int2> wl, fl, ol;
+    std::vector<int2> xl(std::max(b->total_x, 1)), yl(std::max(b->total_y, 1));
     std::vector<int> obase(b->n, 0), ocount(b->n, 0), kl;
+    b->gx_cnt.assign(b->ngroups, 0);
+    b->gy_cnt.assign(b->ngroups, 0);
     for (int k : order)
         if (b->active[k]) {
             for (int t = 0; t < b->ntiles[k]; ++t)
                 wl.push_back(int2{k, t});
             kl.push_back(k);
             if (b->sweeps_ok) {
+                // within the region of the instance's group, active instances first
+                const int g = b->group[k];
                 for (int t = 0; t < b->xitems[k]; ++t)
-                    xl.push_back(int2{k, t * b->hinst[k].xl});
+                    xl[b->gx_off[g] + b->gx_cnt[g]++] = int2{k, t * b->hinst[k].xl};
                 for (int t = 0; t < b->yitems[k]; ++t)
-                    yl.push_back(int2{k, t});
+                    yl[b->gy_off[g] + b->gy_cnt[g]++] = int2{k, t};
             }
         }
     for (int k = 0; k < b->n; ++k) {
@@ -714,15 +765,20 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
         }
     }
     const int nw = (int)wl.size(), nfl = (int)fl.size(), nol = (int)ol.size();
-    const int nxl = (int)xl.size(), nyl = (int)yl.size(), nkl = (int)kl.size();
-    if (nxl)
-        HIPCHECK(hipMemcpy(b->d_xwork, xl.data(), sizeof(int2) * nxl, hipMemcpyHostToDevice));
-    if (nyl)
-        HIPCHECK(hipMemcpy(b->d_ywork, yl.data(), sizeof(int2) * nyl, hipMemcpyHostToDevice));
+    const int nkl = (int)kl.size();
+    int nxl = 0, nyl = 0;
+    for (int g = 0; g < b->ngroups; ++g) {
+        nxl += b->gx_cnt[g];
+        nyl += b->gy_cnt[g];
+    }
+    if (b->sweeps_ok) {
+        HIPCHECK(hipMemcpy(b->d_xwork, xl.data(), sizeof(int2) * b->total_x, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(b->d_ywork, yl.data(), sizeof(int2) * b->total_y, hipMemcpyHostToDevice));
+    }
     if (nkl)
         HIPCHECK(hipMemcpy(b->d_klist, kl.data(), sizeof(int) * nkl, hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(b->d_nx, &nxl, sizeof(int), hipMemcpyHostToDevice));
-    HIPCHECK(hipMemcpy(b->d_ny, &nyl, sizeof(int), hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_nx, b->gx_cnt.data(), sizeof(int) * b->ngroups, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_ny, b->gy_cnt.data(), sizeof(int) * b->ngroups, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b->d_nk, &nkl, sizeof(int), hipMemcpyHostToDevice));
     if (nw)
         HIPCHECK(hipMemcpy(b->d_work, wl.data(), sizeof(int2) * nw, hipMemcpyHostToDevice));
@@ -752,13 +808,21 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
 // kernels (batch_sweep_step); the fused plan records ev[4s] before step s's
 // launch and the other three after it.
 template <class R>
-void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles, int grid_chunks, int grid_x,
-                   int grid_y, int grid_k, hipEvent_t *ev = nullptr)
+void batch_enqueue(sscn_batch *b, int64_t nsteps, hipStream_t st, int grid_tiles, int grid_chunks, bool all,
+                   hipEvent_t *ev = nullptr)
 {
     const bool imag = b->mode == SSCN_IMAG;
     if (b->active_plan == SSCN_PLAN_SWEEPS) {
-        for (int64_t s = 0; s < nsteps; ++s)
-            batch_sweep_step<R>(b, st, grid_x, grid_y, grid_k, ev ? ev + 4 * s : nullptr);
+        // group by group (sscn_batch::group): all the steps of one group run
+        // before the next group's, so a group's two state buffers stay in the
+        // Infinity Cache between its sweeps
+        const bool pending = b->pending;
+        for (int g = 0; g < b->ngroups; ++g) {
+            b->pending = pending;
+            for (int64_t s = 0; s < nsteps; ++s)
+                batch_sweep_step<R>(b, st, g, all, ev ? ev + 4 * (g * nsteps + s) : nullptr);
+        }
+        const int grid_k = all ? b->n : b->grid_k;
         if (imag && b->pending) {
             hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist,
                                b->d_nk, b->ypart, b->d_scale);
@@ -815,9 +879,9 @@ void batch_capture_steps(sscn_batch *b, int64_t k, hipStream_t st)
     const int fparity = b->fparity, pbuf = b->pbuf;
     const bool pending = b->pending;
     if (b->precision == SSCN_C128)
-        batch_enqueue<double>(b, k, st, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
+        batch_enqueue<double>(b, k, st, b->total_tiles, b->total_chunks, true);
     else
-        batch_enqueue<float>(b, k, st, b->total_tiles, b->total_chunks, b->total_x, b->total_y, b->n);
+        batch_enqueue<float>(b, k, st, b->total_tiles, b->total_chunks, true);
     b->fparity = fparity;
     b->pbuf = pbuf;
     b->pending = pending;
@@ -868,9 +932,9 @@ int batch_run_step_graphs(sscn_batch *b, int64_t nsteps, bool launch)
             HIPCHECK(hipGraphLaunch(x, b->stream));
     } else if (r == 1 && launch) {
         if (b->precision == SSCN_C128)
-            batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+            batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
         else
-            batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+            batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
     }
     return 0;
 }
@@ -923,9 +987,9 @@ int batch_autotune(sscn_batch *b)
         // one untimed step first: the first launch of a kernel also loads its
         // code object, which must not count against the plan
         if (b->precision == SSCN_C128)
-            batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+            batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
         else
-            batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+            batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
         for (int k = 0; k < b->n; ++k)
             HIPCHECK(hipMemcpyAsync(b->psi[k], saved + off[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice,
                                     b->stream));
@@ -934,9 +998,9 @@ int batch_autotune(sscn_batch *b)
         (void)hipEventCreate(&e1);
         (void)hipEventRecord(e0, b->stream);
         if (b->precision == SSCN_C128)
-            batch_enqueue<double>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+            batch_enqueue<double>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, false);
         else
-            batch_enqueue<float>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+            batch_enqueue<float>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, false);
         (void)hipEventRecord(e1, b->stream);
         (void)hipEventSynchronize(e1);
         float ms = 0.f;
@@ -1959,6 +2023,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
     b->total_tiles = poff;
     b->active.assign(n, 1);
     b->conv.assign(n, -1);
+    batch_groups(b, esize);
     const size_t nopart = std::max((size_t)b->total_chunks * kObsN, (size_t)kRedBlocks);
     if (hipMalloc(&b->d_inst, sizeof(Inst2D) * n) != hipSuccess ||
         hipMalloc(&b->d_work, sizeof(int2) * b->total_tiles) != hipSuccess ||
@@ -1979,7 +2044,8 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         hipMalloc(&b->d_conv, sizeof(long long) * n) != hipSuccess ||
         hipMalloc(&b->d_xwork, sizeof(int2) * std::max(b->total_x, 1)) != hipSuccess ||
         hipMalloc(&b->d_ywork, sizeof(int2) * std::max(b->total_y, 1)) != hipSuccess ||
-        hipMalloc(&b->d_nx, sizeof(int)) != hipSuccess || hipMalloc(&b->d_ny, sizeof(int)) != hipSuccess ||
+        hipMalloc(&b->d_nx, sizeof(int) * b->ngroups) != hipSuccess ||
+        hipMalloc(&b->d_ny, sizeof(int) * b->ngroups) != hipSuccess ||
         hipMalloc(&b->d_klist, sizeof(int) * n) != hipSuccess || hipMalloc(&b->d_nk, sizeof(int)) != hipSuccess ||
         hipMalloc(&b->ypart, sizeof(double) * std::max(b->total_y, 1)) != hipSuccess ||
         hipMalloc(&b->d_scale, sizeof(double) * n) != hipSuccess)
@@ -2080,9 +2146,9 @@ int sscn_batch_step(sscn_batch *b, int64_t nsteps)
         if (r)
             return r;
     } else if (b->precision == SSCN_C128) {
-        batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+        batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, false);
     } else {
-        batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y, b->grid_k);
+        batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, false);
     }
     HIPCHECK(hipGetLastError());
     b->steps += nsteps;
@@ -2096,7 +2162,9 @@ int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out)
     int r = batch_autotune(b);
     if (r)
         return r;
-    std::vector<hipEvent_t> ev((size_t)nsteps * 4, nullptr);
+    // the sweep plan runs the steps group by group: 4 events per step and group
+    const int64_t nrec = nsteps * (b->active_plan == SSCN_PLAN_SWEEPS ? b->ngroups : 1);
+    std::vector<hipEvent_t> ev((size_t)nrec * 4, nullptr);
     int rc = 0;
     for (auto &e : ev)
         if (hipEventCreate(&e) != hipSuccess) {
@@ -2105,17 +2173,15 @@ int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out)
         }
     if (!rc) {
         if (b->precision == SSCN_C128)
-            batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y,
-                                  b->grid_k, ev.data());
+            batch_enqueue<double>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, false, ev.data());
         else
-            batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, b->grid_x, b->grid_y,
-                                 b->grid_k, ev.data());
+            batch_enqueue<float>(b, nsteps, b->stream, b->grid_tiles, b->grid_chunks, false, ev.data());
         b->steps += nsteps;
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(b->stream) != hipSuccess)
             rc = fail(SSCN_EHIP, "the profiled batch steps failed");
     }
     double acc[4] = {0, 0, 0, 0};
-    for (int64_t s = 0; s < nsteps && !rc; ++s) {
+    for (int64_t s = 0; s < nrec && !rc; ++s) {
         const hipEvent_t *e = &ev[(size_t)s * 4];
         float t01 = 0, t12 = 0, t23 = 0, t03 = 0;
         if (hipEventElapsedTime(&t01, e[0], e[1]) != hipSuccess || hipEventElapsedTime(&t12, e[1], e[2]) != hipSuccess ||

@@ -39,55 +39,153 @@ const char *sscn_nn_last_error(void) { return g_nn_err.c_str(); }
 
 namespace {
 
+#ifndef SSCN_NN_CONV_LEGACY
+#define SSCN_NN_CONV_LEGACY 0
+#endif
+
+// Raise a conv kernel's dynamic-LDS limit once (first launch of each
+// instantiation); returns the error of the attribute call.
+template <class K>
+hipError_t conv_lds_once(K kernel, int bytes)
+{
+    static hipError_t e = hipFuncSetAttribute((const void *)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+// Output-channel tile of a convolution with Cout output channels.
+int conv_bn(int Cout) { return Cout % 128 == 0 ? 128 : Cout % 64 == 0 ? 64 : Cout % 32 == 0 ? 32 : 16; }
+
+// K stages of a convolution with Cin input channels.
+int conv_stages(int Cin) { return 9 * (Cin % 64 == 0 ? Cin / 64 : Cin % 32 == 0 ? Cin / 32 : Cin / 16); }
+
+// Split-K factor: grids of fewer than 512 blocks (the deep, small layers)
+// are split over K so that the launch fills the chip, each part keeping at
+// least two stages; 1 = no split.
+int conv_splits(int P, int Cin, int Cout)
+{
+    const int64_t blocks = (int64_t)((P + 127) / 128) * (Cout / conv_bn(Cout));
+    if (blocks >= 512)
+        return 1;
+    const int64_t want = (512 + blocks - 1) / blocks;
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, conv_stages(Cin) / 2, 16}));
+}
+
+// Pixel splits of the bias gradient: chunks of about 1024 pixels, at most
+// 1024 of them.
+int bias_splits(int P) { return std::min(1024, std::max(1, (P + 1023) / 1024)); }
+
+template <int ACT, bool OUTF32, int BN, int WM, int KC>
+void go_conv_mfma(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
+                  void *y, int ldy, int yoff, float *ws, int nsplit, hipStream_t st)
+{
+    constexpr int lds = conv_mfma_lds_bytes<BN, KC>();
+    const int P = N * H * W;
+    if (nsplit > 1) {
+        if (conv_lds_once(k_conv3x3_mfma<ACT, OUTF32, BN, WM, KC, true>, lds) != hipSuccess)
+            return;  // reported by launched()
+        hipLaunchKernelGGL((k_conv3x3_mfma<ACT, OUTF32, BN, WM, KC, true>), dim3((P + 127) / 128, Cout / BN, nsplit),
+                           dim3(256), lds, st, x, N, H, W, Cin, w, bias, Cout, (void *)ws, Cout, 0, nsplit);
+        const int64_t n = (int64_t)P * Cout;
+        const int grid = (int)std::min<int64_t>(8192, (n + 255) / 256);
+        hipLaunchKernelGGL((k_conv_split_sum<ACT, OUTF32>), dim3(grid), dim3(256), 0, st, (const float *)ws, nsplit,
+                           P, Cout, bias, y, ldy, yoff);
+        return;
+    }
+    if (conv_lds_once(k_conv3x3_mfma<ACT, OUTF32, BN, WM, KC, false>, lds) != hipSuccess)
+        return;
+    hipLaunchKernelGGL((k_conv3x3_mfma<ACT, OUTF32, BN, WM, KC, false>), dim3((P + 127) / 128, Cout / BN), dim3(256),
+                       lds, st, x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, 1);
+}
+
+template <int ACT, bool OUTF32, int KC>
+void launch_conv_kc(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
+                    void *y, int ldy, int yoff, float *ws, int nsplit, hipStream_t st)
+{
+    switch (conv_bn(Cout)) {
+    case 128: go_conv_mfma<ACT, OUTF32, 128, 2, KC>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, ws, nsplit, st); break;
+    case 64: go_conv_mfma<ACT, OUTF32, 64, 2, KC>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, ws, nsplit, st); break;
+    case 32: go_conv_mfma<ACT, OUTF32, 32, 4, KC>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, ws, nsplit, st); break;
+    default: go_conv_mfma<ACT, OUTF32, 16, 4, KC>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, ws, nsplit, st); break;
+    }
+}
+
+// ws: nsplit * P * Cout floats when nsplit > 1 (conv_splits), else unused.
 template <int ACT, bool OUTF32>
 void launch_conv(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
-                 void *y, int ldy, int yoff, hipStream_t st)
+                 void *y, int ldy, int yoff, hipStream_t st, float *ws = nullptr, int nsplit = 1)
 {
     const int P = N * H * W;
-    if (Cout % 64 == 0)
-        hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 64>), dim3((P + 63) / 64, Cout / 64), dim3(256), 0, st, x, N, H, W,
-                           Cin, w, bias, Cout, y, ldy, yoff);
-    else if (Cout % 32 == 0)
-        hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 32>), dim3((P + 63) / 64, Cout / 32), dim3(256), 0, st, x, N, H, W,
-                           Cin, w, bias, Cout, y, ldy, yoff);
+    if (SSCN_NN_CONV_LEGACY) {
+        if (Cout % 64 == 0)
+            hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 64>), dim3((P + 63) / 64, Cout / 64), dim3(256), 0, st, x, N,
+                               H, W, Cin, w, bias, Cout, y, ldy, yoff);
+        else if (Cout % 32 == 0)
+            hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 32>), dim3((P + 63) / 64, Cout / 32), dim3(256), 0, st, x, N,
+                               H, W, Cin, w, bias, Cout, y, ldy, yoff);
+        else
+            hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 16>), dim3((P + 63) / 64, Cout / 16), dim3(256), 0, st, x, N,
+                               H, W, Cin, w, bias, Cout, y, ldy, yoff);
+        return;
+    }
+    if (Cin % 64 == 0)
+        launch_conv_kc<ACT, OUTF32, 64>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, ws, nsplit, st);
     else
-        hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 16>), dim3((P + 63) / 64, Cout / 16), dim3(256), 0, st, x, N, H, W,
-                           Cin, w, bias, Cout, y, ldy, yoff);
+        launch_conv_kc<ACT, OUTF32, 32>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, ws, nsplit, st);
 }
 
 }  // namespace
 
 extern "C" {
 
+int sscn_nn_conv_ws_floats(int N, int H, int W, int Cin, int Cout, int64_t *floats)
+{
+    if (!floats || N < 1 || H < 1 || W < 1 || Cin < 16 || Cin % 16 || Cout < 16 || Cout % 16)
+        return nn_fail(-1, "bad conv_ws_floats arguments");
+    const int P = N * H * W;
+    const int ns = SSCN_NN_CONV_LEGACY ? 1 : conv_splits(P, Cin, Cout);
+    *floats = ns > 1 ? (int64_t)ns * P * Cout : 0;
+    return 0;
+}
+
 int sscn_nn_conv3x3(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
-                    int act, int out_f32, void *y, int ldy, int yoff, void *stream)
+                    int act, int out_f32, void *y, int ldy, int yoff, float *ws, int64_t ws_floats, void *stream)
 {
     if (!x || !w || !y || N < 1 || H < 1 || W < 1 || Cin < 16 || Cin % 16 || Cout < 16 || Cout % 16 ||
-        ldy < yoff + Cout || yoff < 0 || (act != ACT_NONE && act != ACT_LEAKY))
+        ldy < yoff + Cout || yoff < 0 || (act != ACT_NONE && act != ACT_LEAKY) || ws_floats < 0)
         return nn_fail(-1, "bad conv3x3 arguments");
+    const int P = N * H * W;
+    int ns = SSCN_NN_CONV_LEGACY ? 1 : conv_splits(P, Cin, Cout);
+    if (!ws || ws_floats < (int64_t)ns * P * Cout)
+        ns = 1;  // no (or too small a) workspace: no split
     hipStream_t st = (hipStream_t)stream;
-    const uint16_t *xs = (const uint16_t *)x, *ws = (const uint16_t *)w;
+    const uint16_t *xs = (const uint16_t *)x, *wb = (const uint16_t *)w;
     if (act == ACT_LEAKY && !out_f32)
-        launch_conv<ACT_LEAKY, false>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
+        launch_conv<ACT_LEAKY, false>(xs, N, H, W, Cin, wb, bias, Cout, y, ldy, yoff, st, ws, ns);
     else if (act == ACT_LEAKY)
-        launch_conv<ACT_LEAKY, true>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
+        launch_conv<ACT_LEAKY, true>(xs, N, H, W, Cin, wb, bias, Cout, y, ldy, yoff, st, ws, ns);
     else if (!out_f32)
-        launch_conv<ACT_NONE, false>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
+        launch_conv<ACT_NONE, false>(xs, N, H, W, Cin, wb, bias, Cout, y, ldy, yoff, st, ws, ns);
     else
-        launch_conv<ACT_NONE, true>(xs, N, H, W, Cin, ws, bias, Cout, y, ldy, yoff, st);
+        launch_conv<ACT_NONE, true>(xs, N, H, W, Cin, wb, bias, Cout, y, ldy, yoff, st, ws, ns);
     return launched("conv3x3");
 }
 
 int sscn_nn_conv3x3_dgrad(const void *dy, int N, int H, int W, int Cout, const void *w, int Cin,
-                          void *wt_scratch, void *dx, int lddx, int dxoff, void *stream)
+                          void *wt_scratch, void *dx, int lddx, int dxoff, float *ws, int64_t ws_floats,
+                          void *stream)
 {
-    if (!dy || !w || !wt_scratch || !dx || Cin % 16 || Cout % 16 || Cin < 16 || Cout < 16 || lddx < dxoff + Cin)
+    if (!dy || !w || !wt_scratch || !dx || Cin % 16 || Cout % 16 || Cin < 16 || Cout < 16 || lddx < dxoff + Cin ||
+        ws_floats < 0)
         return nn_fail(-1, "bad conv3x3_dgrad arguments");
     hipStream_t st = (hipStream_t)stream;
+    const int P = N * H * W;
+    int ns = SSCN_NN_CONV_LEGACY ? 1 : conv_splits(P, Cout, Cin);  // the convolution with Cout inputs, Cin outputs
+    if (!ws || ws_floats < (int64_t)ns * P * Cin)
+        ns = 1;
     hipLaunchKernelGGL(k_wflip, dim3(blocks((int64_t)Cout * 9 * Cin)), dim3(256), 0, st, (const uint16_t *)w, Cout,
                        Cin, (uint16_t *)wt_scratch);
     launch_conv<ACT_NONE, false>((const uint16_t *)dy, N, H, W, Cout, (const uint16_t *)wt_scratch, nullptr, Cin, dx,
-                                 lddx, dxoff, st);
+                                 lddx, dxoff, st, ws, ns);
     return launched("conv3x3_dgrad");
 }
 
@@ -97,7 +195,7 @@ int sscn_nn_wgrad_scratch(int N, int H, int W, int Cin, int Cout, int64_t *float
         return nn_fail(-1, "null argument");
     const int P = N * H * W;
     const int nsplit = std::min(64, std::max(1, (P + 1023) / 1024));
-    *floats = (int64_t)nsplit * Cout * 9 * Cin + (int64_t)nsplit * Cout;
+    *floats = (int64_t)nsplit * Cout * 9 * Cin + (int64_t)bias_splits(P) * Cout;
     return 0;
 }
 
@@ -122,8 +220,10 @@ int sscn_nn_conv3x3_wgrad(const void *x, int N, int H, int W, int Cin, const voi
     hipLaunchKernelGGL(k_sum_splits, dim3(blocks(nw)), dim3(256), 0, st, scratch, nsplit, nw, dw);
     if (db) {
         float *bp = scratch + (size_t)nsplit * nw;
-        hipLaunchKernelGGL(k_bias_grad, dim3(nsplit), dim3(256), 0, st, (const uint16_t *)dy, P, Cout, chunk, bp);
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(Cout)), dim3(256), 0, st, bp, nsplit, Cout, db);
+        const int bs = bias_splits(P);
+        const int bchunk = (P + bs - 1) / bs;
+        hipLaunchKernelGGL(k_bias_grad, dim3(bs), dim3(256), 0, st, (const uint16_t *)dy, P, Cout, bchunk, bp);
+        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(Cout)), dim3(256), 0, st, bp, bs, Cout, db);
     }
     return launched("conv3x3_wgrad");
 }

@@ -165,6 +165,237 @@ __global__ __launch_bounds__(256) void k_conv3x3(const uint16_t *__restrict__ x,
     }
 }
 
+// 3x3 convolution on the gfx950 double-K matrix cores: the same implicit
+// GEMM (M = N*H*W pixels, N = Cout, K = 9*Cin), in block tiles of BM = 128
+// pixels x BN output channels with more products per staged byte.
+//
+// - v_mfma_f32_16x16x32_bf16: a lane supplies 8 consecutive k of row
+//   m = lane % 16 of A and of column m of B (k group lane / 16), and receives
+//   D[4 (lane / 16) + r][lane % 16], r = 0..3.  The order of k within a
+//   fragment is the same for A and B, so it does not enter the sum.
+// - The 4 waves tile the block WM x (4 / WM); a wave owns a TM x TN sub-tile
+//   of FM x FN 16 x 16 fragments, so every A fragment it reads from LDS
+//   feeds FN products and every B fragment FM.
+// - A K stage is KC = 64 consecutive k (64 input channels of one tap) when
+//   Cin is a multiple of 64, else 32 (Cin a multiple of 32) or 16 (the
+//   input layer: the upper 16 k of each staged row stay zero).  The stage's
+//   128 x KC inputs and BN x KC weights go to LDS with 16-byte loads, double
+//   buffered: the next stage's loads are in flight during the current
+//   stage's products.  LDS rows are padded by 8 bf16 against bank
+//   conflicts.
+// Output as k_conv3x3.  Grid: (ceil(P / 128), Cout / BN), 256 threads.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ v4f mfma16x32(v8bf a, v8bf b, v4f c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ v8bf lds8(const uint16_t *p)
+{
+    const uint4 u = *reinterpret_cast<const uint4 *>(p);
+    v8bf r;
+    __builtin_memcpy(&r, &u, 16);
+    return r;
+}
+
+template <int KC>
+constexpr int conv_mfma_ld() { return KC + 8; }
+
+template <int BN, int KC>
+constexpr int conv_mfma_lds_bytes() { return 2 * (128 + BN) * conv_mfma_ld<KC>() * 2; }
+
+template <int ACT, bool OUTF32, int BN, int WM, int KC, bool SPLIT>
+__global__ __launch_bounds__(256, 2) void k_conv3x3_mfma(const uint16_t *__restrict__ x, int N, int H, int W,
+                                                         int Cin, const uint16_t *__restrict__ w,
+                                                         const float *__restrict__ bias, int Cout,
+                                                         void *__restrict__ y, int ldy, int yoff, int nsplit)
+{
+    constexpr int BM = 128, WN = 4 / WM;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int FM = TM / 16, FN = TN / 16;
+    constexpr int LD = conv_mfma_ld<KC>();
+    constexpr int KQ = KC / 8;               // 16-byte parts of a staged row
+    constexpr int NA = BM * KQ / 256;        // A loads per thread and stage
+    constexpr int NB = (BN * KQ + 255) / 256;  // B loads per thread and stage
+    static_assert(WM * WN == 4 && FM >= 1 && FN >= 1, "4 waves tile the block");
+    static_assert(BM * KQ % 256 == 0, "A parts divide over the threads");
+    extern __shared__ __align__(16) uint16_t conv_smem[];
+    uint16_t *sA = conv_smem;                 // [2][BM][LD]
+    uint16_t *sB = conv_smem + 2 * BM * LD;   // [2][BN][LD]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, g = lane >> 4;
+    const int wm = wave % WM, wn = wave / WM;
+    const int P = N * H * W;
+    const int p0 = blockIdx.x * BM;
+    const int co0 = blockIdx.y * BN;
+    const int kc = Cin % KC == 0 ? KC : 16;  // channels per stage (16: the input layer, KC = 32)
+    const int ncc = Cin / kc;
+    const int nk_all = 9 * ncc;
+    // split K (SPLIT): block z takes stages [k_begin, k_end) and writes its
+    // fp32 partial sums to y + z * P * Cout ([z][p][co]), summed by
+    // k_conv_split_sum in a fixed order
+    const int z = SPLIT ? (int)blockIdx.z : 0;
+    const int k_begin = SPLIT ? (int)((int64_t)nk_all * z / nsplit) : 0;
+    const int k_end = SPLIT ? (int)((int64_t)nk_all * (z + 1) / nsplit) : nk_all;
+    // staging roles: A part e = tid + 256 i: pixel e / KQ, 8 channels (e % KQ);
+    // B part e: weight row e / KQ, 8 k-values (e % KQ)
+    int an[NA], ay[NA], ax[NA];
+    bool aok[NA];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+        const int pa = p0 + (tid + 256 * i) / KQ;
+        aok[i] = pa < P;
+        const int pp = aok[i] ? pa : 0;
+        an[i] = pp / (H * W);
+        const int r = pp - an[i] * H * W;
+        ay[i] = r / W;
+        ax[i] = r - ay[i] * W;
+    }
+    struct Regs {
+        uint4 a[NA], b[NB];
+    };
+    auto load_stage = [&](int kk, Regs &rg) {
+        const int tap = kk / ncc, c0 = (kk - tap * ncc) * kc;
+        const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int part = (tid + 256 * i) % KQ;
+            rg.a[i] = make_uint4(0u, 0u, 0u, 0u);
+            const int sy = ay[i] + dy, sx = ax[i] + dx;
+            if (aok[i] && part * 8 < kc && sy >= 0 && sy < H && sx >= 0 && sx < W)
+                rg.a[i] = *reinterpret_cast<const uint4 *>(x + ((size_t)(an[i] * H + sy) * W + sx) * Cin + c0 + part * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + 256 * i;
+            const int row = e / KQ, part = e % KQ;
+            rg.b[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < BN * KQ && part * 8 < kc)
+                rg.b[i] = *reinterpret_cast<const uint4 *>(w + ((size_t)(co0 + row) * 9 + tap) * Cin + c0 + part * 8);
+        }
+    };
+    auto store_stage = [&](int buf, const Regs &rg) {
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            const int e = tid + 256 * i;
+            *reinterpret_cast<uint4 *>(&sA[(buf * BM + e / KQ) * LD + (e % KQ) * 8]) = rg.a[i];
+        }
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + 256 * i;
+            if (e < BN * KQ)
+                *reinterpret_cast<uint4 *>(&sB[(buf * BN + e / KQ) * LD + (e % KQ) * 8]) = rg.b[i];
+        }
+    };
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](int buf) {
+        const uint16_t *cA = sA + (buf * BM + wm * TM) * LD;
+        const uint16_t *cB = sB + (buf * BN + wn * TN) * LD;
+#pragma unroll
+        for (int k32 = 0; k32 < KC / 32; ++k32) {
+            v8bf av[FM], bv[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+                av[i] = lds8(cA + (i * 16 + m) * LD + k32 * 32 + 8 * g);
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+                bv[j] = lds8(cB + (j * 16 + m) * LD + k32 * 32 + 8 * g);
+#pragma unroll
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    acc[i][j] = mfma16x32(av[i], bv[j], acc[i][j]);
+        }
+    };
+    // Two register sets, so a stage's global loads are issued two stages
+    // before their data is written to LDS (about two stages of products hide
+    // their latency); two LDS buffers, one barrier per stage.  The loop is
+    // unrolled by two so that the register sets are addressed statically.
+    Regs r0, r1;
+    const int nk = k_end - k_begin;
+    if (nk > 0)
+        load_stage(k_begin, r0);
+    if (nk > 1)
+        load_stage(k_begin + 1, r1);
+    if (nk > 0)
+        store_stage(0, r0);
+    __syncthreads();
+    for (int t = 0; t < nk; t += 2) {
+        // stage t in LDS buffer 0, its successor's loads in r1
+        if (t + 2 < nk)
+            load_stage(k_begin + t + 2, r0);
+        compute(0);
+        if (t + 1 < nk)
+            store_stage(1, r1);
+        __syncthreads();
+        if (t + 1 >= nk)
+            break;
+        // stage t + 1 in LDS buffer 1, stage t + 2's loads in r0
+        if (t + 3 < nk)
+            load_stage(k_begin + t + 3, r1);
+        compute(1);
+        if (t + 2 < nk)
+            store_stage(0, r0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int co = co0 + wn * TN + j * 16 + m;
+        const float bv = (!SPLIT && bias) ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pp = p0 + wm * TM + i * 16 + 4 * g + r;
+                if (pp < P) {
+                    if (SPLIT) {
+                        reinterpret_cast<float *>(y)[((size_t)z * P + pp) * Cout + co] = acc[i][j][r];
+                        continue;
+                    }
+                    float v = acc[i][j][r] + bv;
+                    if (ACT == ACT_LEAKY)
+                        v = v > 0.f ? v : kLeak * v;
+                    if (OUTF32)
+                        reinterpret_cast<float *>(y)[(size_t)pp * ldy + yoff + co] = v;
+                    else
+                        reinterpret_cast<uint16_t *>(y)[(size_t)pp * ldy + yoff + co] = f2bf(v);
+                }
+            }
+    }
+}
+
+// The split-K sums: y[p * ldy + yoff + c] = act(sum over z of part[z][p][c]
+// (z = 0, 1, ... in order) + bias[c]), bf16 or fp32.  Grid-stride over the
+// P * C outputs.
+template <int ACT, bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv_split_sum(const float *__restrict__ part, int nsplit, int P, int C,
+                                                       const float *__restrict__ bias, void *__restrict__ y,
+                                                       int ldy, int yoff)
+{
+    const int64_t n = (int64_t)P * C;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c = (int)(e % C);
+        const int64_t p = e / C;
+        float v = 0.f;
+        for (int z = 0; z < nsplit; ++z)
+            v += part[(size_t)z * n + e];
+        if (bias)
+            v += bias[c];
+        if (ACT == ACT_LEAKY)
+            v = v > 0.f ? v : kLeak * v;
+        if (OUTF32)
+            reinterpret_cast<float *>(y)[p * ldy + yoff + c] = v;
+        else
+            reinterpret_cast<uint16_t *>(y)[p * ldy + yoff + c] = f2bf(v);
+    }
+}
+
 // Weights of the input-gradient convolution: wt[ci][8 - tap][co] = w[co][tap][ci].
 __global__ __launch_bounds__(256) void k_wflip(const uint16_t *__restrict__ w, int Cout, int Cin,
                                                uint16_t *__restrict__ wt)

@@ -29,8 +29,9 @@ def _nn():
     L = _sscn_lib()
     if not getattr(L, "_nn_ready", False):
         vp, ci, i64, cf = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
-        L.sscn_nn_conv3x3.argtypes = [vp, ci, ci, ci, ci, vp, vp, ci, ci, ci, vp, ci, ci, vp]
-        L.sscn_nn_conv3x3_dgrad.argtypes = [vp, ci, ci, ci, ci, vp, ci, vp, vp, ci, ci, vp]
+        L.sscn_nn_conv3x3.argtypes = [vp, ci, ci, ci, ci, vp, vp, ci, ci, ci, vp, ci, ci, vp, i64, vp]
+        L.sscn_nn_conv_ws_floats.argtypes = [ci, ci, ci, ci, ci, ctypes.POINTER(i64)]
+        L.sscn_nn_conv3x3_dgrad.argtypes = [vp, ci, ci, ci, ci, vp, ci, vp, vp, ci, ci, vp, i64, vp]
         L.sscn_nn_wgrad_scratch.argtypes = [ci, ci, ci, ci, ci, ctypes.POINTER(i64)]
         L.sscn_nn_conv3x3_wgrad.argtypes = [vp, ci, ci, ci, ci, vp, ci, vp, vp, vp, i64, vp]
         L.sscn_nn_act_bwd.argtypes = [vp, vp, i64, vp]
@@ -62,14 +63,20 @@ def _p(t):
 # ---------------------------------------------------------------------------
 # thin wrappers (argument marshalling only)
 
-def conv3x3(x, N, H, W, Cin, w, b, Cout, act, y, ldy=None, yoff=0, out_f32=False, stream=None):
+def conv_ws_floats(N, H, W, Cin, Cout):
+    n = ctypes.c_int64()
+    _ck(_nn().sscn_nn_conv_ws_floats(N, H, W, Cin, Cout, ctypes.byref(n)))
+    return n.value
+
+
+def conv3x3(x, N, H, W, Cin, w, b, Cout, act, y, ldy=None, yoff=0, out_f32=False, ws=None, stream=None):
     _ck(_nn().sscn_nn_conv3x3(_p(x), N, H, W, Cin, _p(w), _p(b), Cout, int(act), int(out_f32), _p(y),
-                              ldy or Cout, yoff, stream))
+                              ldy or Cout, yoff, _p(ws), ws.numel() if ws is not None else 0, stream))
 
 
-def conv3x3_dgrad(dy, N, H, W, Cout, w, Cin, wt, dx, lddx=None, dxoff=0, stream=None):
+def conv3x3_dgrad(dy, N, H, W, Cout, w, Cin, wt, dx, lddx=None, dxoff=0, ws=None, stream=None):
     _ck(_nn().sscn_nn_conv3x3_dgrad(_p(dy), N, H, W, Cout, _p(w), Cin, _p(wt), _p(dx), lddx or Cin,
-                                    dxoff, stream))
+                                    dxoff, _p(ws), ws.numel() if ws is not None else 0, stream))
 
 
 def wgrad_scratch(N, H, W, Cin, Cout):
@@ -253,7 +260,10 @@ class UNet:
         self.gin = self._act(H, W, IN_CH)
         maxw = max(cin * cout * 9 for _, cin, cout, _ in self.specs)
         self.wt = self.torch.empty(maxw, dtype=self.torch.int16, device=self.dev)
-        need = max(wgrad_scratch(N, *self.shapes[n], cin, cout) for n, cin, cout, _ in self.specs)
+        # one fp32 scratch for the weight gradients and for the split-K
+        # partial sums of the small layers (used one call at a time)
+        need = max(max(wgrad_scratch(N, *self.shapes[n], cin, cout), conv_ws_floats(N, *self.shapes[n], cin, cout),
+                       conv_ws_floats(N, *self.shapes[n], cout, cin)) for n, cin, cout, _ in self.specs)
         self.scratch = self.torch.empty(need, dtype=self.torch.float32, device=self.dev)
         self.stats = self.torch.zeros(4 * N, dtype=self.torch.float64, device=self.dev)
 
@@ -270,7 +280,7 @@ class UNet:
             h, w = self.shapes[name]
             conv3x3(inp, N, h, w, cin, self.wbf[name], self.b[name], cout, act,
                     out if out is not None else self.acts[name], ldy=ldy, yoff=yoff,
-                    out_f32=(name == "out"))
+                    out_f32=(name == "out"), ws=self.scratch)
 
         cur = x
         for lv, c in enumerate(self.chans):
@@ -308,7 +318,7 @@ class UNet:
             conv3x3_wgrad(inp, N, h, w, cin, dy, cout, self.gw[name], self.gb[name], self.scratch)
             if dinp is not None:
                 conv3x3_dgrad(dy, N, h, w, cout, self.wbf[name], cin, self.wt, dinp, lddx=lddx,
-                              dxoff=dxoff)
+                              dxoff=dxoff, ws=self.scratch)
 
         lv0 = len(self.chans) - 1
         top = self.acts["dec0b"]

@@ -136,3 +136,43 @@ def test_batch_set_state_device_and_vortex_count(P, prec):
         assert rel(got, ref) <= (1e-13 if prec == 0 else 1e-6), k
         assert b.vortex_count(k) == O.vortex_count(op, got), k
     b.close()
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_groups_give_the_same_bits(P, prec, monkeypatch):
+    """The sweep plan runs its instances group by group (groups sized for the
+    Infinity Cache, SSCN_BATCH_GROUP_MB).  Instances are independent, so any
+    grouping gives the same bits: one group per instance against one group
+    for all, over direct steps, graph-replayed steps and a convergence run
+    with drop-out, and each against the oracle."""
+    print(f"[gpu-batch] groups prec={prec}", flush=True)
+    cfgs = mixed(prec, 0)
+    res = {}
+    for mb in ("0", "1"):
+        monkeypatch.setenv("SSCN_BATCH_GROUP_MB", mb)
+        b = P.Batch(cfgs)
+        b.set_plan(1)
+        for k, c in enumerate(cfgs):
+            b.init_state(k, 1, W.phase_field(40 + k, c["ny"], c["nx"]), 1.0)
+        b.step(1)
+        b.step(37)
+        st = b.run(3000, check_every=100, tol=1e-5)
+        res[mb] = ([b.get_state(k) for k in range(len(cfgs))], list(st), b.observables())
+        b.close()
+    for k in range(len(cfgs)):
+        assert np.array_equal(res["0"][0][k], res["1"][0][k]), k
+    assert res["0"][1] == res["1"][1]
+    # and the grouped states match the oracle after the direct and replayed steps
+    monkeypatch.setenv("SSCN_BATCH_GROUP_MB", "1")
+    bb = P.Batch(cfgs)
+    bb.set_plan(1)
+    for k, c in enumerate(cfgs):
+        bb.init_state(k, 1, W.phase_field(40 + k, c["ny"], c["nx"]), 1.0)
+    bb.step(1)
+    bb.step(37)
+    tol = 1e-10 if prec == 0 else 1e-5
+    for k, c in enumerate(cfgs):
+        op = O.make_params(**c)
+        ref = O.step(op, O.init_state(op, 1, W.phase_field(40 + k, c["ny"], c["nx"]), 1.0), 38)
+        assert rel(bb.get_state(k).astype(np.complex128), ref) <= tol, k
+    bb.close()

@@ -51,7 +51,14 @@ def close_bf(gpu, ref, absum, name):
 
 
 @pytest.mark.parametrize("N,H,W,Cin,Cout,act", [(3, 13, 11, 48, 32, 1), (1, 8, 8, 16, 16, 0),
-                                                 (2, 24, 20, 160, 64, 1)])
+                                                 (2, 24, 20, 160, 64, 1),
+                                                 # every block shape and K stage of the matrix-core
+                                                 # kernel, with pixel counts that leave a ragged
+                                                 # last block: BN 128 / 64 / 32 / 16, stages of 64,
+                                                 # 32 and 16 channels
+                                                 (2, 9, 13, 64, 128, 1), (1, 10, 10, 128, 256, 0),
+                                                 (2, 7, 9, 96, 64, 1), (1, 16, 16, 16, 32, 1),
+                                                 (1, 5, 6, 32, 48, 0), (1, 12, 12, 512, 256, 1)])
 def test_conv3x3(nn, N, H, W, Cin, Cout, act):
     rng = np.random.default_rng(N * 1000 + Cin)
     xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
@@ -63,6 +70,14 @@ def test_conv3x3(nn, N, H, W, Cin, Cout, act):
     nn.conv3x3(xd, N, H, W, Cin, wd, f32(b), Cout, act, y32, out_f32=True)
     g = y32.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(g - ref) <= 1e-5 * absum + 1e-30)
+    # with a workspace, small grids split their K sum over more blocks
+    nws = nn.conv_ws_floats(N, H, W, Cin, Cout)
+    if nws > 0:
+        ws = torch.full((nws,), float("nan"), dtype=torch.float32, device="cuda")
+        y32.zero_()
+        nn.conv3x3(xd, N, H, W, Cin, wd, f32(b), Cout, act, y32, out_f32=True, ws=ws)
+        gs = y32.cpu().numpy().astype(np.float64)
+        assert np.all(np.abs(gs - ref) <= 1e-5 * absum + 1e-30)
     # bf16 output into a channel slice of a wider tensor
     ld, off = Cout + 32, 16
     ybf = torch.full((N, H, W, ld), 7, dtype=torch.int16, device="cuda")
@@ -87,6 +102,14 @@ def test_conv3x3_dgrad_and_wgrad(nn):
     absum = U.conv3x3_dgrad(np.abs(dy), np.abs(w))
     close_bf(from_bf(dx)[..., off:], ref, absum, "dgrad")
     assert np.all(dx.cpu().numpy()[..., :off] == 0)
+    # the same with the K sum split over blocks (a workspace)
+    nws = nn.conv_ws_floats(N, H, W, Cout, Cin)
+    assert nws > 0
+    dx2 = torch.zeros((N, H, W, ld), dtype=torch.int16, device="cuda")
+    nn.conv3x3_dgrad(dyd, N, H, W, Cout, wd, Cin, wt, dx2, lddx=ld, dxoff=off,
+                     ws=torch.empty(nws, dtype=torch.float32, device="cuda"))
+    close_bf(from_bf(dx2)[..., off:], ref, absum, "dgrad split")
+    assert np.all(dx2.cpu().numpy()[..., :off] == 0)
 
     scr = torch.empty(nn.wgrad_scratch(N, H, W, Cin, Cout), dtype=torch.float32, device="cuda")
     dw = torch.zeros((Cout, 3, 3, Cin), dtype=torch.float32, device="cuda")
