@@ -24,7 +24,8 @@ Also reported on the same JSON line:
   variants      the 512^2 workload (complex128 and complex64, imaginary and
                 real time), the 3D 256 x 256 x 64 workload (complex64 and
                 complex128), each followed by real-time steps with norm and
-                energy drift; the learned start's network (forward pass and
+                energy drift; a batch of 8 3D instances (complex64 and
+                complex128); the learned start's network (forward pass and
                 training iteration at 256^2, batch 16, against the bf16
                 matrix-core peak);
   converge      time to converged lattices: the 128^2 workload (complex128;
@@ -185,10 +186,10 @@ def batch_roofline(b, cfgs, nprof=20):
     prec = "c128" if esize == 16 else "c64"
     if "fused" in prof:
         names, per_launch, label = ("fused",), 2 * 2 * esize * pts, "batched fused 2D step (H1 + x + y)"
-        keys = {"fused": f"batch_fused2d_c4_{prec}"}
+        keys = {"fused": f"batch64_fused2d_{prec}"}
     else:
         names, per_launch = ("x", "y"), 2 * esize * pts
-        keys = {"x": f"batch_xsweep_c4_{prec}", "y": f"batch_ysweep_c4_{prec}"}
+        keys = {"x": f"batch64_xsweep_{prec}", "y": f"batch64_ysweep_{prec}"}
     dom = max(names, key=lambda k: prof[k])
     if "fused" not in prof:
         label = {"x": "batched x-sweep (H1 + rescale + x-CN), k_batch_xsweep",
@@ -234,6 +235,28 @@ def timed_steps(P, torch, cfg, steps, warmup, mode=0):
     sync(torch)
     dt = time.perf_counter() - t0
     return s, dt, e0.elapsed_time(e1) / steps
+
+
+def batch3d_variant(P, torch, precision, steps=200, warmup=20):
+    """The batched 3D sweep (workloads.batch3d_instances: 8 instances of the
+    3D workload's trap with different rotations, couplings and in-plane
+    sides): updates/s over `steps` graph-replayed steps and the average
+    duration of its x-, y- and z-sweep kernels (HIP events around every
+    kernel of 10 steps), with their algorithmic bandwidth (2 c bytes per
+    point per sweep)."""
+    cfgs = [dict(c, precision=precision) for c in W.batch3d_instances()]
+    pts = sum(c["nx"] * c["ny"] * c["nz"] for c in cfgs)
+    b, dt, _ = timed_batch(P, torch, cfgs, steps, warmup)
+    prof = b.profile_step(10)
+    b.close()
+    esize = 16 if precision == 0 else 8
+    per = 2 * esize * pts
+    return {"instances": len(cfgs), "points": pts, "grid_sides": sorted({c["nx"] for c in cfgs}),
+            "nz": cfgs[0]["nz"], "updates_per_s": round(pts * steps / dt, 1),
+            "ms_per_step": round(dt / steps * 1e3, 6), "steps": steps,
+            "kernel_ms": {k: round(v, 6) for k, v in prof.items()},
+            "kernel_frac_of_8TBps": {k: round(per / (prof[k] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
+                                     for k in ("x", "y", "z")}}
 
 
 def real_time_phase(P, torch, s, steps):
@@ -559,6 +582,8 @@ def main():
         c3 = W.CONFIGS["c3"]
         variants["c3_3d_complex64"] = single_variant(P, torch, c3, 1024, 64, real_steps=1024)
         variants["c3_3d_complex128"] = single_variant(P, torch, dict(c3, precision=0), 512, 64, real_steps=512)
+        variants["batch_3d_8_complex64"] = batch3d_variant(P, torch, 1)
+        variants["batch_3d_8_complex128"] = batch3d_variant(P, torch, 0, steps=100)
         variants["learned_start_network"] = network_rate(P, torch)
         out["variants"] = variants
         c1 = W.CONFIGS["c1"]

@@ -108,6 +108,25 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream,
 int sscn_init_state(sscn_handle *h, int kind, const double *phase_host,
                     double d_xy, double d_z);
 
+/* The same initial state of Eq. (fun) with the random number R(x, y) drawn
+ * on the device from a counter-based generator (no host array): with
+ * random_phase != 0, R at point (i, j) is u = 2^-53 (h(seed XOR (j nx + i))
+ * >> 11), uniform in [0, 1), where h is the output function of the
+ * SplitMix64 generator (Steele, Lea and Flood, 2014: add
+ * 0x9E3779B97F4A7C15, then z = (z ^ z >> 30) * 0xBF58476D1CE4E5B9, z = (z ^
+ * z >> 27) * 0x94D049BB133111EB, z ^ z >> 31, all modulo 2^64); constant
+ * along z.  The paper leaves the generator of R unspecified (Sec. 2, after
+ * Eq. (fun)); integer arithmetic makes u the same bits on every platform
+ * (sscn_phase_field_seed returns them).  Synchronises the stream. */
+int sscn_init_state_seed(sscn_handle *h, int kind, int random_phase, uint64_t seed,
+                         double d_xy, double d_z);
+
+/* The random numbers sscn_init_state_seed uses: out_dev[j nx + i] = u(seed,
+ * j nx + i) for an ny x nx plane (caller-owned device buffer of nx*ny
+ * doubles).  Asynchronous on hip_stream.  SSCN_EINVAL for a null buffer or
+ * non-positive sizes. */
+int sscn_phase_field_seed(uint64_t seed, int nx, int ny, double *out_dev, void *hip_stream);
+
 /* Enqueue nsteps >= 0 SSCN steps (paper's NPAS loop body).  Asynchronous:
  * no host synchronisation.  In imaginary time the state left in psi after
  * the call is normalised.  A call of n >= 2 steps replays captured HIP
@@ -323,22 +342,27 @@ int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *pla
 void sscn_destroy(sscn_handle *h);
 
 /* ---------------------------------------------------------------------------
- * Batched 2D instances: n problems of different grid sizes and parameters
- * advanced together, one fused launch per step over all their 32 x 32 tiles
- * (the SSCN_PLAN_FUSED step with a work list), HIP-graph replayed, with the
- * convergence test done on the device and converged instances dropped from
- * the work list.  Every params[k] must be 2D with a common precision and
- * mode; the window (rows of look-ahead) is the largest any instance needs.
- * psi_devs[k] is instance k's caller-owned state buffer (layout as above),
- * borrowed until sscn_batch_destroy; the library owns one work buffer per
- * instance.  All work goes to hip_stream. */
+ * Batched instances: n problems of different grid sizes and parameters
+ * advanced together, HIP-graph replayed, with the convergence test done on
+ * the device and converged instances dropped from the work lists.  2D
+ * batches step with one fused launch over all instances' 32 x 32 tiles
+ * (SSCN_PLAN_FUSED) or with one launch per axis over work lists of line
+ * blocks and tiles (SSCN_PLAN_SWEEPS).  3D batches (the identical
+ * prescription of Sec. 2 for the third axis) take the sweep plan: x, y and
+ * z launches per step over every instance.  Every params[k] must have the
+ * same dim (2 or 3), precision and mode; the window (rows of look-ahead) is
+ * the largest any instance needs (the z window separately).  psi_devs[k] is
+ * instance k's caller-owned state buffer (layout as above), borrowed until
+ * sscn_batch_destroy; the library owns one work buffer per instance.  All
+ * work goes to hip_stream. */
 typedef struct sscn_batch sscn_batch;
 
 int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, void *hip_stream,
                     sscn_batch **out);
 
-/* Initial state of Eq. (fun) for instance k (2D form of sscn_init_state).
- * Synchronises the stream. */
+/* Initial state of Eq. (fun) for instance k (as sscn_init_state; in 3D
+ * the z Gaussian has width 1/sqrt(lambda), Eq. (anz)).  Synchronises the
+ * stream. */
 int sscn_batch_init_state(sscn_batch *b, int k, int kind, const double *phase_host, double d_xy);
 
 /* Enqueue nsteps steps of every active instance; each state is left
@@ -360,9 +384,9 @@ int sscn_batch_prepare_steps(sscn_batch *b, int64_t nsteps);
  * event recorded on the batch's stream around every kernel, and return the
  * average durations in milliseconds: sweep plan ms_out[0] the batched
  * x-sweep (with H1 and the pending rescale, which it forms from the norm
- * partials itself), [1] the batched y-sweep, [2] = 0 (no kernel of its own
- * remains for the rescale); fused plan ms_out[0] the fused step, [1] = [2] =
- * 0; ms_out[3] a whole step (the finish pass at the end of the call is not
+ * partials itself), [1] the batched y-sweep, [2] the batched z-sweep (3D
+ * batches; 0 in 2D); fused plan ms_out[0] the fused step, [1] = [2] = 0;
+ * ms_out[3] a whole step (the finish pass at the end of the call is not
  * timed).  For measurement: the kernels run in the order and on the
  * data of ordinary steps.  Synchronises the stream. */
 int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out);

@@ -8,9 +8,11 @@ used only by the tests, the smoke check and the benchmark's CPU baseline.
 
 The solver's arithmetic (the step, the observables, the vortex count, the
 initial state) lives in ``sscn_oracle.c``, marshalled here through ctypes.
-Seven plain numpy definitions live in this module: ``embed`` (continuation
-start), ``extend_z`` (3D product start), ``functional_fourth_order``,
-``density``, and for the learned initial state ``keys_cubic``, ``resample``
+Nine plain numpy/Python definitions live in this module: ``embed``
+(continuation start), ``extend_z`` (3D product start),
+``functional_fourth_order``, ``density``, ``splitmix64`` and
+``splitmix_phase`` (the counter-based random phase of the seeded initial
+state), and for the learned initial state ``keys_cubic``, ``resample``
 (interpolation between grids) and ``angular_moments`` (lattice
 orientation).  Each function is pinned in tests/test_oracle_pins.py against
 what the paper and the mathematics fix; none is parity unpinned.  Arrays are
@@ -299,6 +301,32 @@ def keys_cubic(s):
     inner = 1.5 * s ** 3 - 2.5 * s ** 2 + 1.0
     outer = -0.5 * s ** 3 + 2.5 * s ** 2 - 4.0 * s + 2.0
     return np.where(s <= 1.0, inner, np.where(s < 2.0, outer, 0.0))
+
+
+_MASK64 = (1 << 64) - 1
+
+
+def splitmix64(x):
+    """Output of the SplitMix64 generator (Steele, Lea and Flood, 2014) for
+    the state x (Python integers, modulo 2^64): the state advances by
+    0x9E3779B97F4A7C15, then z = (z ^ z >> 30) * 0xBF58476D1CE4E5B9,
+    z = (z ^ z >> 27) * 0x94D049BB133111EB, z ^ z >> 31."""
+    z = (x + 0x9E3779B97F4A7C15) & _MASK64
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def splitmix_phase(seed, ny, nx):
+    """The random number R(x, y) of Eq. (fun) on an ny x nx plane as the
+    library's counter-based draw defines it (reading of the unspecified
+    generator): R[j, i] = 2^-53 (splitmix64(seed XOR (j nx + i)) >> 11).
+    Pure-Python integers, one point at a time."""
+    out = np.empty((ny, nx), dtype=np.float64)
+    for j in range(ny):
+        for i in range(nx):
+            out[j, i] = (splitmix64((seed ^ (j * nx + i)) & _MASK64) >> 11) * 2.0 ** -53
+    return out
 
 
 def resample(psi, h_src, shape, h, angle=0.0):

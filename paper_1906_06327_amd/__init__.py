@@ -21,7 +21,7 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
           -4: "SSCN_ENONFINITE", -5: "SSCN_EHIP", -6: "SSCN_ENOMEM"}
 
 # Every symbol include/sscn.h declares.
-EXPORTS = ("sscn_init", "sscn_init_state", "sscn_step", "sscn_prepare_steps", "sscn_observables", "sscn_observables_noalloc",
+EXPORTS = ("sscn_init", "sscn_init_state", "sscn_init_state_seed", "sscn_phase_field_seed", "sscn_step", "sscn_prepare_steps", "sscn_observables", "sscn_observables_noalloc",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step", "sscn_batch_prepare_steps", "sscn_batch_profile_step",
@@ -69,6 +69,9 @@ def lib():
         vp, i64 = ctypes.c_void_p, ctypes.c_int64
         L.sscn_init.argtypes = [ctypes.POINTER(Params), vp, vp, ctypes.POINTER(vp)]
         L.sscn_init_state.argtypes = [vp, ctypes.c_int, vp, ctypes.c_double, ctypes.c_double]
+        L.sscn_init_state_seed.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_double,
+                                           ctypes.c_double]
+        L.sscn_phase_field_seed.argtypes = [ctypes.c_uint64, ctypes.c_int, ctypes.c_int, vp, vp]
         L.sscn_step.argtypes = [vp, i64]
         L.sscn_prepare_steps.argtypes = [vp, i64]
         L.sscn_observables.argtypes = [vp, ctypes.POINTER(Obs)]
@@ -139,6 +142,17 @@ def make_params(dim=2, nx=64, ny=64, nz=1, hx=0.1, hy=0.1, hz=0.1, gamma=1.0, nu
 
 OBS_KEYS = ("norm", "mu", "energy", "mu_full", "energy_full", "mu_4th", "energy_4th", "rms_x", "rms_y", "rms_z",
             "rms_r", "max_density")
+
+
+def phase_field_seed(seed, ny, nx, stream=None):
+    """R(x, y) of sscn_init_state_seed for an ny x nx plane, as a float64
+    device tensor (sscn_phase_field_seed)."""
+    import torch
+    out = torch.empty((ny, nx), dtype=torch.float64, device="cuda")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().sscn_phase_field_seed(int(seed) & (2**64 - 1), int(nx), int(ny), ctypes.c_void_p(out.data_ptr()),
+                                       ctypes.c_void_p(st.cuda_stream)))
+    return out
 
 
 def embed_state(src, dst, stream=None):
@@ -278,6 +292,12 @@ class Solver:
         _check(lib().sscn_init_state(self._h, int(kind), ph.ctypes.data if ph is not None else None,
                                      float(d_xy), float(d_z)))
 
+    def init_state_seed(self, kind=1, seed=13, d_xy=1.0, d_z=0.0, random_phase=True):
+        """Eq. (fun) with R(x, y) from the device's counter-based generator
+        (sscn_init_state_seed); random_phase=False: no random phase."""
+        _check(lib().sscn_init_state_seed(self._h, int(kind), 1 if random_phase else 0, int(seed) & (2**64 - 1),
+                                          float(d_xy), float(d_z)))
+
     def step(self, n=1):
         _check(lib().sscn_step(self._h, int(n)))
 
@@ -413,9 +433,9 @@ class Solver:
 
 
 class Batch:
-    """n 2D instances advanced together by the fused step (include/sscn.h,
+    """n instances (all 2D or all 3D) advanced together (include/sscn.h,
     sscn_batch_*).  State tensors are allocated here (torch, one per
-    instance) and borrowed by the library."""
+    instance, shape (ny, nx) or (nz, ny, nx)) and borrowed by the library."""
 
     def __init__(self, params_list, stream=None):
         import torch
@@ -425,7 +445,8 @@ class Batch:
         n = len(ps)
         arr = (Params * n)(*ps)
         dtype = torch.complex128 if ps[0].precision == SSCN_C128 else torch.complex64
-        self.psi = [torch.zeros((p.ny, p.nx), dtype=dtype, device="cuda") for p in ps]
+        self.psi = [torch.zeros((p.nz, p.ny, p.nx) if p.dim == 3 else (p.ny, p.nx), dtype=dtype, device="cuda")
+                    for p in ps]
         ptrs = (ctypes.c_void_p * n)(*[t.data_ptr() for t in self.psi])
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         h = ctypes.c_void_p()
@@ -457,7 +478,10 @@ class Batch:
         ms = (ctypes.c_double * 4)()
         _check(lib().sscn_batch_profile_step(self._h, int(n), ms))
         if self.info()["plan"] == PLAN_SWEEPS:
-            return {"x": ms[0], "y": ms[1], "step": ms[3]}
+            out = {"x": ms[0], "y": ms[1], "step": ms[3]}
+            if self.params[0].dim == 3:
+                out["z"] = ms[2]
+            return out
         return {"fused": ms[0], "step": ms[3]}
 
     def run(self, max_steps, check_every=100, tol=1e-8):
@@ -481,7 +505,7 @@ class Batch:
     def get_state(self, k):
         p = self.params[k]
         dtype = np.complex128 if p.precision == SSCN_C128 else np.complex64
-        out = np.empty((p.ny, p.nx), dtype=dtype)
+        out = np.empty((p.nz, p.ny, p.nx) if p.dim == 3 else (p.ny, p.nx), dtype=dtype)
         _check(lib().sscn_batch_get_state(self._h, int(k), out.ctypes.data))
         return out
 

@@ -1047,10 +1047,15 @@ __global__ __launch_bounds__(256, kSweepWaves) void k_zsweep(const typename Vec<
 struct Inst2D {
     int nx, ny, tiles_x, tiles_y, poff, active;
     int xl, ygx, ygy, ypoff;  // sweep plan: x lines per block, y tile grid, offset of its partials
+    // 3D instances (nz > 1, sweep plan only): the z tile grid and the offset
+    // of its partials; eoff / ecount: the norm partials of the sweep that
+    // emits them (y in 2D, z in 3D), which the next x-sweep sums
+    int nz, zgx, zgy, zpoff, eoff, ecount;
     double hx, hy, x0, y0, vx, vy, g, omega, dt, dV;
-    AxisCoef ax[2];
+    double hz, z0, vz;
+    AxisCoef ax[3];
     void *buf[2];
-    const void *tab[2];   // pivot tables of x-lines (by j) and y-lines (by i)
+    const void *tab[3];   // pivot tables of x-lines (by j), y-lines (by i) and z-lines (one)
 };
 
 // stage-buffer row stride: >= SC + SC/S + 1 and = 4 (mod 16), so that the
@@ -1691,9 +1696,38 @@ __global__ __launch_bounds__(256) void k_zero_walls(typename Vec<R>::T *psi, Ste
 }
 
 // Initial state of Eq. (fun) (not normalised; the host normalises after).
+// Counter-based uniform numbers for the random phase R(x, y) of Eq. (fun):
+// u = 2^-53 (h(seed XOR q) >> 11) for the point index q = j nx + i, with h
+// the output function of the SplitMix64 generator (Steele, Lea and Flood,
+// 2014): advance the state by the golden-ratio increment 0x9E3779B97F4A7C15,
+// then two xor-shift-multiply rounds and a final xor-shift.  Integer
+// arithmetic only, so every implementation gives the same bits.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t x)
+{
+    uint64_t z = x + 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ double seed_uniform(uint64_t seed, int64_t q)
+{
+    return (double)(splitmix64(seed ^ (uint64_t)q) >> 11) * 0x1.0p-53;
+}
+
+// out[j nx + i] = seed_uniform(seed, j nx + i) for an ny x nx plane.
+static __global__ __launch_bounds__(256) void k_phase_seed(double *out, int nx, int ny, uint64_t seed)
+{
+    const int64_t n = (int64_t)nx * ny;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < n; q += (int64_t)gridDim.x * 256)
+        out[q] = seed_uniform(seed, q);
+}
+
+// Initial state of Eq. (fun); the random phase from the host array phase
+// (NULL: none) or, with seeded, from seed_uniform(seed, j nx + i).
 template <class R>
 __global__ __launch_bounds__(256) void k_init(typename Vec<R>::T *psi, StepArgs a, int kind, const double *phase,
-                                              double dxy, double dz)
+                                              double dxy, double dz, int seeded = 0, uint64_t seed = 0)
 {
     const double pi = 3.14159265358979323846;
     const int64_t n = (int64_t)a.nx * a.ny * (a.dim == 3 ? a.nz : 1);
@@ -1709,9 +1743,10 @@ __global__ __launch_bounds__(256) void k_init(typename Vec<R>::T *psi, StepArgs 
             const double amp = exp(-(x * x + y * y) / (2.0 * dxy * dxy)) / sqrt(pi * dxy * dxy);
             re = fr * amp;
             im = fi * amp;
-            if (phase) {
+            if (phase || seeded) {
+                const int64_t q = (int64_t)j * a.nx + i;
                 double sn, cs;
-                sincos(2.0 * pi * phase[(int64_t)j * a.nx + i], &sn, &cs);
+                sincos(2.0 * pi * (seeded ? seed_uniform(seed, q) : phase[q]), &sn, &cs);
                 const double r2 = re * cs - im * sn, i2 = re * sn + im * cs;
                 re = r2;
                 im = i2;
@@ -1913,26 +1948,32 @@ constexpr int kChunk = 4096;
 __device__ __forceinline__ StepArgs inst_args(const Inst2D &I)
 {
     StepArgs a{};
-    a.dim = 2;
+    const bool d3 = I.nz > 1;
+    a.dim = d3 ? 3 : 2;
     a.nx = I.nx;
     a.ny = I.ny;
-    a.nz = 1;
+    a.nz = d3 ? I.nz : 1;
     a.hx = I.hx;
     a.hy = I.hy;
-    a.hz = 1.0;
+    a.hz = d3 ? I.hz : 1.0;
     a.x0 = I.x0;
     a.y0 = I.y0;
+    a.z0 = d3 ? I.z0 : 0.0;
     a.vx = I.vx;
     a.vy = I.vy;
+    a.vz = d3 ? I.vz : 0.0;
     a.g = I.g;
     a.omega = I.omega;
     a.dt = I.dt;
     a.dV = I.dV;
     a.ax[0] = I.ax[0];
     a.ax[1] = I.ax[1];
-    a.ax[2] = I.ax[1];
+    a.ax[2] = d3 ? I.ax[2] : I.ax[1];
     return a;
 }
+
+// Points of an instance's state.
+__device__ __forceinline__ int64_t inst_points(const Inst2D &I) { return (int64_t)I.nx * I.ny * (I.nz > 1 ? I.nz : 1); }
 
 // End of a batched stepping call: for every listed (instance, chunk) item,
 // buf[0] = s buf[parity] with s = 1/sqrt(dV sum of the instance's partials)
@@ -1948,7 +1989,7 @@ __global__ __launch_bounds__(256) void k_batch_finish(const Inst2D *__restrict__
     for (int it = blockIdx.x; it < nfw; it += gridDim.x) {
         const int2 wk = fwork[it];
         const Inst2D &I = insts[wk.x];
-        const int64_t n = (int64_t)I.nx * I.ny;
+        const int64_t n = inst_points(I);
         double sm1 = 0.0;
         if (rescale_on && scale)
             sm1 = scale[wk.x];
@@ -1988,7 +2029,7 @@ __global__ __launch_bounds__(256) void k_batch_obs(const Inst2D *__restrict__ in
         const Inst2D &I = insts[wk.x];
         const StepArgs a = inst_args(I);
         const typename Vec<R>::T *psi = reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]);
-        const int64_t n = (int64_t)I.nx * I.ny;
+        const int64_t n = inst_points(I);
         const int64_t base = (int64_t)wk.y * kChunk;
         double s[kObsN];
 #pragma unroll
@@ -2056,7 +2097,8 @@ __global__ __launch_bounds__(256) void k_batch_vortex(const Inst2D *__restrict__
         for (int c = threadIdx.x; c < kChunk; c += 256) {
             const int64_t p = base + c;
             if (p < n)
-                cnt += plaquette_count<R>(psi, a, 0, (int)(p % (I.nx - 1)), (int)(p / (I.nx - 1)), thr, box);
+                cnt += plaquette_count<R>(psi, a, I.nz > 1 ? I.nz / 2 : 0, (int)(p % (I.nx - 1)),
+                                          (int)(p / (I.nx - 1)), thr, box);
         }
         const double b = block_sum_256(cnt, red);
         if (threadIdx.x == 0)
@@ -2122,7 +2164,7 @@ static __global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__rest
     for (int it = blockIdx.x; it < nkk; it += gridDim.x) {
         const int k = klist[it];
         const Inst2D &I = insts[k];
-        const double sm1 = norm_scale_m1(wave_partials_sum(partials + I.ypoff, I.ygx * I.ygy), I.dV);
+        const double sm1 = norm_scale_m1(wave_partials_sum(partials + I.eoff, I.ecount), I.dV);
         if (threadIdx.x == 0)
             scale[k] = sm1;
     }
@@ -2148,9 +2190,11 @@ __global__ __launch_bounds__(256, kSweepWaves) void k_batch_xsweep(const Inst2D 
     XStage<R, KX> g;
     xsweep_load<R, S, W, KX, kBatchStream>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]), a, I.xl,
                                    reinterpret_cast<const Cx<R> *>(I.tab[0]), wk.y, g);
-    const double sm1 = use_scale ? norm_scale_m1(wave_partials_sum(partials + I.ypoff, I.ygx * I.ygy), I.dV) : 0.0;
-    xsweep_finish<R, S, W, RT, KX, kBatchStream>(reinterpret_cast<typename Vec<R>::T *>(I.buf[1]), a, I.xl, sm1, wk.y, g,
-                                         smem_raw);
+    const double sm1 = use_scale ? norm_scale_m1(wave_partials_sum(partials + I.eoff, I.ecount), I.dV) : 0.0;
+    // 2D: buf[0] -> buf[1]; 3D: in place (a block loads its lines whole
+    // before it writes them), so that the y- and z-sweeps end in buf[0]
+    xsweep_finish<R, S, W, RT, KX, kBatchStream>(reinterpret_cast<typename Vec<R>::T *>(I.buf[I.nz > 1 ? 0 : 1]), a,
+                                                 I.xl, sm1, wk.y, g, smem_raw);
 }
 
 // One item per block, XCD-aware (xcd_item): the launch has at least
@@ -2166,10 +2210,51 @@ __global__ __launch_bounds__(256, kSweepWaves) void k_batch_ysweep(const Inst2D 
     const int2 wk = ywork[it];
     const Inst2D &I = insts[wk.x];
     const StepArgs a = inst_args(I);
-    const int by = wk.y % I.ygy, bx = wk.y / I.ygy;
-    ysweep_block<R, S, W, EMIT, kBatchStream>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[1]),
-                                      reinterpret_cast<typename Vec<R>::T *>(I.buf[0]), a, bx, by, 0,
-                                      partials + I.ypoff + wk.y, reinterpret_cast<const Cx<R> *>(I.tab[1]), red);
+    // item wk.y: segment group by of column tile bx in plane bz
+    const int by = wk.y % I.ygy, rest = wk.y / I.ygy;
+    const int bx = rest % I.ygx, bz = rest / I.ygx;
+    // 2D: buf[1] -> buf[0] with the norm partials; 3D: buf[0] -> buf[1]
+    const int from = I.nz > 1 ? 0 : 1;
+    ysweep_block<R, S, W, EMIT, kBatchStream>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[from]),
+                                              reinterpret_cast<typename Vec<R>::T *>(I.buf[1 - from]), a, bx, by, bz,
+                                              partials + I.ypoff + wk.y, reinterpret_cast<const Cx<R> *>(I.tab[1]),
+                                              red);
+}
+
+// Batched z-sweep of 3D instances, one item (instance, z tile) per block,
+// XCD-aware: buf[1] -> buf[0] with the norm partials of the outputs (EMIT) at
+// partials[I.zpoff + tile].  Tile t: segment group t % zgy of the column
+// group t / zgy (32 consecutive (i, j) columns of the plane).
+template <class R, int S, int W, bool EMIT>
+__global__ __launch_bounds__(256, kSweepWaves) void k_batch_zsweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ zwork,
+                                                      const int *__restrict__ nitems, double *__restrict__ partials)
+{
+    __shared__ double red[8];
+    const int it = xcd_item(*nitems);
+    if (it < 0)
+        return;
+    const int2 wk = zwork[it];
+    const Inst2D &I = insts[wk.x];
+    const StepArgs a = inst_args(I);
+    const int by = wk.y % I.zgy, bx = wk.y / I.zgy;
+    const int nx = I.nx, ny = I.ny;
+    const int pidx = bx * kYLines + threadIdx.x;
+    const int i = pidx % nx, j = pidx / nx;
+    const Cx<R> *trow = nullptr;
+    LineCoef<R> Lc{};
+    if (pidx < nx * ny && i > 0 && j > 0) {
+        Lc = line_coef<R>(a.ax[2], 0.0);
+        trow = reinterpret_cast<const Cx<R> *>(I.tab[2]);
+    }
+    double acc = 0.0;
+    strided_sweep_tile<R, S, W, kBatchStream>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[1]),
+                                              reinterpret_cast<typename Vec<R>::T *>(I.buf[0]), I.nz, 0,
+                                              (int64_t)nx * ny, nx * ny, bx * kYLines, by, true, Lc, trow, EMIT, acc);
+    if (EMIT) {
+        const double b = block_sum_256(acc, red);
+        if (threadIdx.x == 0 && threadIdx.y == 0)
+            partials[I.zpoff + wk.y] = b;
+    }
 }
 
 }  // namespace sscn

@@ -193,6 +193,14 @@ struct sscn_batch {
     std::vector<int> gx_off, gx_tot, gx_cnt, gy_off, gy_tot, gy_cnt;
     double *ypart = nullptr, *d_scale = nullptr;
     float tune_ms[3] = {0, 0, 0};
+    // 3D instances (sweep plan): the z-sweep's window, tables and work list
+    bool dim3 = false;
+    int Wz = 0;
+    std::vector<void *> tabz;
+    std::vector<int> zitems;
+    int total_z = 0, grid_z = 0;
+    int2 *d_zwork = nullptr;
+    int *d_nzl = nullptr;
 };
 
 namespace sscn {

@@ -207,12 +207,19 @@ void go_batch_y(const sscn_batch *b, int g, int grid, hipStream_t st)
                        st, b->d_inst, b->d_ywork + b->gy_off[g], b->d_ny + g, b->ypart);
 }
 
+template <class R, int W, bool EMIT>
+void go_batch_z(const sscn_batch *b, int grid, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_batch_zsweep<R, kSeg, W, EMIT>), dim3(round8(std::max(grid, 1))), dim3(kYLines, kSegBlock), 0,
+                       st, b->d_inst, b->d_zwork, b->d_nzl, b->ypart);
+}
+
 // One step of the sweep plan for the listed instances of group g (state in
 // buf[0]); all: launch grids covering every instance of the group (graph
 // capture), else the current list lengths.  The x-sweep forms the pending
-// rescale itself.  ev (optional, 4 events): recorded before the x-sweep
-// (twice: the step has no rescale kernel of its own), before the y-sweep
-// and after it.
+// rescale itself.  A batch of 3D instances adds the z-sweep.  ev
+// (optional, 4 events): recorded before the x-sweep, before the y-sweep,
+// after it (before the z-sweep) and at the end of the step.
 template <class R>
 void batch_sweep_step(sscn_batch *b, hipStream_t st, int g, bool all, hipEvent_t *ev)
 {
@@ -232,19 +239,33 @@ void batch_sweep_step(sscn_batch *b, hipStream_t st, int g, bool all, hipEvent_t
         else                                                \
             go_batch_x<R, Wc, true>(b, g, grid_x, 0, st);   \
     } while (0)
-    mark(1);
     SSCN_W_SWITCH(b->W, SSCN_CALL_BX);
 #undef SSCN_CALL_BX
-    mark(2);
+    mark(1);
+    // the last sweep emits the norm partials: y in 2D, z in 3D
+    const bool emit_y = imag && !b->dim3;
 #define SSCN_CALL_BY(Wc)                             \
     do {                                             \
-        if (imag)                                    \
+        if (emit_y)                                  \
             go_batch_y<R, Wc, true>(b, g, grid_y, st);  \
         else                                            \
             go_batch_y<R, Wc, false>(b, g, grid_y, st); \
     } while (0)
     SSCN_W_SWITCH(b->W, SSCN_CALL_BY);
 #undef SSCN_CALL_BY
+    mark(2);
+    if (b->dim3) {
+        const int grid_z = all ? b->total_z : b->grid_z;
+#define SSCN_CALL_BZ(Wc)                              \
+    do {                                              \
+        if (imag)                                     \
+            go_batch_z<R, Wc, true>(b, grid_z, st);   \
+        else                                          \
+            go_batch_z<R, Wc, false>(b, grid_z, st);  \
+    } while (0)
+        SSCN_W_SWITCH(b->Wz, SSCN_CALL_BZ);
+#undef SSCN_CALL_BZ
+    }
     mark(3);
     if (imag)
         b->pending = true;

@@ -688,6 +688,8 @@ void batch_groups(sscn_batch *b, size_t esize)
     int64_t mb = kBatchGroupMB;
     if (const char *e = std::getenv("SSCN_BATCH_GROUP_MB"))
         mb = std::max(0L, std::strtol(e, nullptr, 10));
+    if (b->dim3)
+        mb = 0;  // the z-sweep's list is not split into groups
     std::vector<int64_t> bytes(b->n);
     int64_t total = 0;
     for (int k = 0; k < b->n; ++k) {
@@ -735,7 +737,7 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
     std::stable_sort(order.begin(), order.end(),
                      [&](int x, int y) { return b->ntiles[x] > b->ntiles[y]; });
     std::vector<int2> wl, fl, ol;
-    std::vector<int2> xl(std::max(b->total_x, 1)), yl(std::max(b->total_y, 1));
+    std::vector<int2> xl(std::max(b->total_x, 1)), yl(std::max(b->total_y, 1)), zl;
     std::vector<int> obase(b->n, 0), ocount(b->n, 0), kl;
     b->gx_cnt.assign(b->ngroups, 0);
     b->gy_cnt.assign(b->ngroups, 0);
@@ -751,6 +753,8 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
                     xl[b->gx_off[g] + b->gx_cnt[g]++] = int2{k, t * b->hinst[k].xl};
                 for (int t = 0; t < b->yitems[k]; ++t)
                     yl[b->gy_off[g] + b->gy_cnt[g]++] = int2{k, t};
+                for (int t = 0; t < b->zitems[k]; ++t)
+                    zl.push_back(int2{k, t});
             }
         }
     for (int k = 0; k < b->n; ++k) {
@@ -777,6 +781,10 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
     }
     if (nkl)
         HIPCHECK(hipMemcpy(b->d_klist, kl.data(), sizeof(int) * nkl, hipMemcpyHostToDevice));
+    const int nzl = (int)zl.size();
+    if (nzl)
+        HIPCHECK(hipMemcpy(b->d_zwork, zl.data(), sizeof(int2) * nzl, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(b->d_nzl, &nzl, sizeof(int), hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b->d_nx, b->gx_cnt.data(), sizeof(int) * b->ngroups, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b->d_ny, b->gy_cnt.data(), sizeof(int) * b->ngroups, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(b->d_nk, &nkl, sizeof(int), hipMemcpyHostToDevice));
@@ -796,6 +804,7 @@ int batch_lists(sscn_batch *b, bool all_for_obs = false)
         b->grid_chunks = nfl;
         b->grid_x = nxl;
         b->grid_y = nyl;
+        b->grid_z = nzl;
         b->grid_k = nkl;
     }
     return 0;
@@ -1029,7 +1038,7 @@ int batch_autotune(sscn_batch *b)
 void batch_free(sscn_batch *b)
 {
     batch_drop_graph(b);
-    for (auto *v : {&b->work, &b->tabx, &b->taby})
+    for (auto *v : {&b->work, &b->tabx, &b->taby, &b->tabz})
         for (void *q : *v)
             if (q)
                 (void)hipFree(q);
@@ -1037,7 +1046,7 @@ void batch_free(sscn_batch *b)
                     b->d_ocount, b->part[0], b->part[1], b->opart, b->d_sums, b->d_mu_prev, b->d_hits, b->d_conv,
                     b->d_count_prev, b->d_counts, b->vpart,
                     b->phase, b->d_xwork, b->d_ywork, b->d_nx, b->d_ny, b->d_klist, b->d_nk, b->ypart,
-                    b->d_scale};
+                    b->d_scale, b->d_zwork, b->d_nzl};
     for (void *q : bufs)
         if (q)
             (void)hipFree(q);
@@ -1154,7 +1163,10 @@ void sscn_destroy(sscn_handle *h)
     delete h;
 }
 
-int sscn_init_state(sscn_handle *h, int kind, const double *phase_host, double d_xy, double d_z)
+// The initial state of Eq. (fun) with the random phase from a host array
+// (phase_host), from the counter-based generator (seeded), or none.
+static int init_state_impl(sscn_handle *h, int kind, const double *phase_host, int seeded, uint64_t seed, double d_xy,
+                           double d_z)
 {
     if (!h || (kind != 0 && kind != 1) || !(d_xy > 0))
         return fail(SSCN_EINVAL, "bad init_state arguments");
@@ -1172,11 +1184,11 @@ int sscn_init_state(sscn_handle *h, int kind, const double *phase_host, double d
     const int nb = red_blocks(h->npts);
     if (p.precision == SSCN_C128) {
         hipLaunchKernelGGL((k_init<double>), dim3(nb), dim3(256), 0, h->stream, (V<double> *)h->psi, h->args, kind,
-                           ph, d_xy, d_z);
+                           ph, d_xy, d_z, seeded, seed);
         launch_norm<double>(h, h->stream);
     } else {
         hipLaunchKernelGGL((k_init<float>), dim3(nb), dim3(256), 0, h->stream, (V<float> *)h->psi, h->args, kind,
-                           ph, d_xy, d_z);
+                           ph, d_xy, d_z, seeded, seed);
         launch_norm<float>(h, h->stream);
     }
     // normalise: the norm partials use kRedBlocks blocks
@@ -1190,6 +1202,27 @@ int sscn_init_state(sscn_handle *h, int kind, const double *phase_host, double d
     h->pending = false;
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(h->stream));
+    return 0;
+}
+
+int sscn_init_state(sscn_handle *h, int kind, const double *phase_host, double d_xy, double d_z)
+{
+    return init_state_impl(h, kind, phase_host, 0, 0, d_xy, d_z);
+}
+
+int sscn_init_state_seed(sscn_handle *h, int kind, int random_phase, uint64_t seed, double d_xy, double d_z)
+{
+    return init_state_impl(h, kind, nullptr, random_phase ? 1 : 0, seed, d_xy, d_z);
+}
+
+int sscn_phase_field_seed(uint64_t seed, int nx, int ny, double *out_dev, void *hip_stream)
+{
+    if (!out_dev || nx < 1 || ny < 1)
+        return fail(SSCN_EINVAL, "bad phase_field_seed arguments");
+    const int64_t n = (int64_t)nx * ny;
+    const int nb = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_phase_seed, dim3(nb), dim3(256), 0, (hipStream_t)hip_stream, out_dev, nx, ny, seed);
+    HIPCHECK(hipGetLastError());
     return 0;
 }
 
@@ -1931,28 +1964,36 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         int r = validate(params[k]);
         if (r)
             return bail(r);
-        if (params[k].dim != 2 || params[k].precision != b->precision || params[k].mode != b->mode)
-            return bail(fail(SSCN_EINVAL, "batch instances must be 2D with a common precision and mode"));
+        if (params[k].dim != params[0].dim || params[k].precision != b->precision || params[k].mode != b->mode)
+            return bail(fail(SSCN_EINVAL, "batch instances must have a common dim, precision and mode"));
         tmp[k].p = params[k];
-        tmp[k].p.nz = 1;
+        if (params[k].dim == 2)
+            tmp[k].p.nz = 1;
         r = setup(&tmp[k]);
         if (r)
             return bail(r);
         if (tmp[k].exact)
             return bail(fail(SSCN_EINVAL, "a batch instance needs the exact whole-line path"));
         b->W = std::max(b->W, tmp[k].W[0]);
+        if (params[k].dim == 3)
+            b->Wz = std::max(b->Wz, tmp[k].W[2]);
     }
+    b->dim3 = params[0].dim == 3;
     const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
     const size_t flds = step2d_lds_elems(kSeg, b->W, kTileR, kTileC) * esize;
-    if (b->W > (b->precision == SSCN_C128 ? 20 : 32) || flds > 150 * 1024)
+    if (!b->dim3 && (b->W > (b->precision == SSCN_C128 ? 20 : 32) || flds > 150 * 1024))
         return bail(fail(SSCN_EINVAL, "the common window of the batch is too large for the fused step"));
+    if (b->dim3)
+        b->plan = b->active_plan = SSCN_PLAN_SWEEPS;  // the fused step is 2D
     if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess)
         return bail(fail(SSCN_EHIP, "hipStreamCreateWithFlags failed"));
-    int poff = 0, ypoff = 0;
+    int poff = 0, ypoff = 0, zoff = 0;
     for (int k = 0; k < n; ++k) {
         sscn_handle &h = tmp[k];
         h.W[0] = h.W[1] = b->W;
-        h.fused_ok = true;
+        if (b->dim3)
+            h.W[2] = b->Wz;
+        h.fused_ok = !b->dim3;
         int r = build_tables(&h);
         if (r)
             return bail(r);
@@ -1961,7 +2002,10 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         b->psi.push_back(psi_devs[k]);
         b->tabx.push_back(h.tab[0]);
         b->taby.push_back(h.tab[1]);
+        b->tabz.push_back(b->dim3 ? h.tab[2] : nullptr);
         h.tab[0] = h.tab[1] = nullptr;  // owned by the batch now
+        if (b->dim3)
+            h.tab[2] = nullptr;
         void *w = nullptr;
         const size_t bytes = (size_t)h.npts * esize;
         if (hipMalloc(&w, bytes) != hipSuccess)
@@ -1990,10 +2034,16 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         in.dV = h.args.dV;
         in.ax[0] = h.args.ax[0];
         in.ax[1] = h.args.ax[1];
+        in.ax[2] = h.args.ax[2];
+        in.nz = b->dim3 ? h.p.nz : 1;
+        in.hz = h.p.hz;
+        in.z0 = h.args.z0;
+        in.vz = h.args.vz;
         in.buf[0] = psi_devs[k];
         in.buf[1] = w;
         in.tab[0] = b->tabx.back();
         in.tab[1] = b->taby.back();
+        in.tab[2] = b->tabz.back();
         // sweep plan: x-sweep staging as for a single instance (L a power of
         // two), the y tile grid and the offset of this instance's y partials
         const int nseg = (h.p.nx - 2) / kSegX + 1;
@@ -2011,11 +2061,29 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         in.ygx = (h.p.nx + kYLines - 1) / kYLines;
         in.ygy = ((h.p.ny - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock;
         in.ypoff = ypoff;
-        b->xitems.push_back((h.p.ny + L - 1) / L);
-        b->yitems.push_back(in.ygx * in.ygy);
-        ypoff += in.ygx * in.ygy;
+        // 3D: y tiles in every plane, z tiles over the plane's columns; the
+        // z-sweep emits the norm partials (offsets shifted past the y ones
+        // below), in 2D the y-sweep
+        const int planes = b->dim3 ? h.p.nz : 1;
+        b->xitems.push_back((h.p.ny * planes + L - 1) / L);
+        b->yitems.push_back(in.ygx * in.ygy * planes);
+        ypoff += in.ygx * in.ygy * planes;
+        in.zgx = in.zgy = 0;
+        in.zpoff = 0;
+        in.eoff = in.ypoff;
+        in.ecount = in.ygx * in.ygy;
+        if (b->dim3) {
+            in.zgx = (int)(((int64_t)h.p.nx * h.p.ny + kYLines - 1) / kYLines);
+            in.zgy = ((h.p.nz - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock;
+            in.zpoff = zoff;
+            in.eoff = zoff;
+            in.ecount = in.zgx * in.zgy;
+            zoff += in.zgx * in.zgy;
+        }
+        b->zitems.push_back(in.zgx * in.zgy);
         b->total_x += b->xitems.back();
         b->total_y += b->yitems.back();
+        b->total_z += b->zitems.back();
         b->hinst.push_back(in);
         poff += tx * ty;
         b->total_chunks += b->nchunk.back();
@@ -2023,6 +2091,13 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
     b->total_tiles = poff;
     b->active.assign(n, 1);
     b->conv.assign(n, -1);
+    if (b->dim3 && !b->sweeps_ok)
+        return bail(fail(SSCN_EINVAL, "the lines of a 3D batch instance are too long to stage"));
+    if (b->dim3)
+        for (auto &in : b->hinst) {  // the z partials follow all the y ones
+            in.zpoff += ypoff;
+            in.eoff = in.zpoff;
+        }
     batch_groups(b, esize);
     const size_t nopart = std::max((size_t)b->total_chunks * kObsN, (size_t)kRedBlocks);
     if (hipMalloc(&b->d_inst, sizeof(Inst2D) * n) != hipSuccess ||
@@ -2047,7 +2122,9 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         hipMalloc(&b->d_nx, sizeof(int) * b->ngroups) != hipSuccess ||
         hipMalloc(&b->d_ny, sizeof(int) * b->ngroups) != hipSuccess ||
         hipMalloc(&b->d_klist, sizeof(int) * n) != hipSuccess || hipMalloc(&b->d_nk, sizeof(int)) != hipSuccess ||
-        hipMalloc(&b->ypart, sizeof(double) * std::max(b->total_y, 1)) != hipSuccess ||
+        hipMalloc(&b->ypart, sizeof(double) * std::max(b->total_y + b->total_z, 1)) != hipSuccess ||
+        hipMalloc(&b->d_zwork, sizeof(int2) * std::max(b->total_z, 1)) != hipSuccess ||
+        hipMalloc(&b->d_nzl, sizeof(int)) != hipSuccess ||
         hipMalloc(&b->d_scale, sizeof(double) * n) != hipSuccess)
         return bail(fail(SSCN_ENOMEM, "hipMalloc of the batch buffers failed"));
     HIPCHECK(hipMemcpy(b->d_inst, b->hinst.data(), sizeof(Inst2D) * n, hipMemcpyHostToDevice));
@@ -2087,28 +2164,30 @@ int sscn_batch_init_state(sscn_batch *b, int k, int kind, const double *phase_ho
         return fail(SSCN_EINVAL, "bad batch_init_state arguments");
     const sscn_params &p = b->p[k];
     const StepArgs &a = b->args[k];
-    const int64_t npts = (int64_t)p.nx * p.ny;
+    const int64_t plane = (int64_t)p.nx * p.ny;
+    const int64_t npts = plane * (p.dim == 3 ? p.nz : 1);
+    const double d_z = p.dim == 3 ? 1.0 / std::sqrt(p.lambda) : 0.0;
     const double *ph = nullptr;
     if (phase_host) {
         if (b->phase)
             (void)hipFree(b->phase);
         b->phase = nullptr;
-        if (hipMalloc(&b->phase, sizeof(double) * npts) != hipSuccess)
+        if (hipMalloc(&b->phase, sizeof(double) * plane) != hipSuccess)
             return fail(SSCN_ENOMEM, "hipMalloc of the phase buffer failed");
-        HIPCHECK(hipMemcpy(b->phase, phase_host, sizeof(double) * npts, hipMemcpyHostToDevice));
+        HIPCHECK(hipMemcpy(b->phase, phase_host, sizeof(double) * plane, hipMemcpyHostToDevice));
         ph = b->phase;
     }
     const int nb = red_blocks(npts);
     if (b->precision == SSCN_C128) {
         hipLaunchKernelGGL((k_init<double>), dim3(nb), dim3(256), 0, b->stream, (V<double> *)b->psi[k], a, kind, ph,
-                           d_xy, 0.0);
+                           d_xy, d_z, 0, (uint64_t)0);
         hipLaunchKernelGGL((k_norm_partials<double>), dim3(kRedBlocks), dim3(256), 0, b->stream,
                            (const V<double> *)b->psi[k], npts, b->opart);
         hipLaunchKernelGGL((k_rescale<double>), dim3(nb), dim3(256), 0, b->stream, (const V<double> *)b->psi[k],
                            (V<double> *)b->psi[k], npts, a.dV, b->opart, kRedBlocks);
     } else {
         hipLaunchKernelGGL((k_init<float>), dim3(nb), dim3(256), 0, b->stream, (V<float> *)b->psi[k], a, kind, ph,
-                           d_xy, 0.0);
+                           d_xy, d_z, 0, (uint64_t)0);
         hipLaunchKernelGGL((k_norm_partials<float>), dim3(kRedBlocks), dim3(256), 0, b->stream,
                            (const V<float> *)b->psi[k], npts, b->opart);
         hipLaunchKernelGGL((k_rescale<float>), dim3(nb), dim3(256), 0, b->stream, (const V<float> *)b->psi[k],
@@ -2195,9 +2274,9 @@ int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out)
     if (!rc) {
         const double n = (double)nsteps;
         if (b->active_plan == SSCN_PLAN_SWEEPS) {
-            ms_out[0] = acc[1] / n;  // x-sweep
-            ms_out[1] = acc[2] / n;  // y-sweep
-            ms_out[2] = acc[0] / n;  // rescale kernel
+            ms_out[0] = acc[0] / n;  // x-sweep
+            ms_out[1] = acc[1] / n;  // y-sweep
+            ms_out[2] = acc[2] / n;  // z-sweep (3D; 0 in 2D)
         } else {
             ms_out[0] = acc[0] / n;  // fused step
             ms_out[1] = ms_out[2] = 0.0;
@@ -2249,7 +2328,8 @@ int sscn_batch_observables(sscn_batch *b, sscn_obs *out)
         o.energy_4th = (s[14] + s[7] + 0.5 * s[8] + s[15]) / s[0];
         o.rms_x = std::sqrt(s[10] / s[0]);
         o.rms_y = std::sqrt(s[11] / s[0]);
-        o.rms_r = std::sqrt((s[10] + s[11]) / s[0]);
+        o.rms_z = std::sqrt(s[12] / s[0]);  // 0 in 2D (z = 0)
+        o.rms_r = std::sqrt((s[10] + s[11] + s[12]) / s[0]);
         o.max_density = s[13];
         o.step = b->conv[k] >= 0 ? b->conv[k] : b->steps;
         for (int t = 0; t < kObsN; ++t)
@@ -2311,7 +2391,7 @@ int sscn_batch_get_state(sscn_batch *b, int k, void *host_psi)
 {
     if (!b || k < 0 || k >= b->n || !host_psi)
         return fail(SSCN_EINVAL, "bad batch_get_state arguments");
-    const size_t bytes = (size_t)b->p[k].nx * b->p[k].ny * (b->precision == SSCN_C128 ? 16 : 8);
+    const size_t bytes = (size_t)npoints(b->p[k]) * (b->precision == SSCN_C128 ? 16 : 8);
     HIPCHECK(hipMemcpyAsync(host_psi, b->psi[k], bytes, hipMemcpyDeviceToHost, b->stream));
     HIPCHECK(hipStreamSynchronize(b->stream));
     return 0;
@@ -2322,7 +2402,7 @@ int sscn_batch_set_state_device(sscn_batch *b, int k)
     if (!b || k < 0 || k >= b->n)
         return fail(SSCN_EINVAL, "bad batch_set_state_device arguments");
     const StepArgs &a = b->args[k];
-    const int64_t npts = (int64_t)b->p[k].nx * b->p[k].ny;
+    const int64_t npts = npoints(b->p[k]);
     const int nb = red_blocks(npts);
     if (b->precision == SSCN_C128) {
         V<double> *psi = (V<double> *)b->psi[k];
@@ -2351,19 +2431,20 @@ int sscn_batch_vortex_count(sscn_batch *b, int k, double density_frac, int box, 
     const sscn_params &p = b->p[k];
     const StepArgs &a = b->args[k];
     double *out = b->d_sums + (size_t)kObsN * b->n;  // two doubles past the observable sums
+    const int k0 = p.dim == 3 ? p.nz / 2 : 0;           // 3D: the z = 0 plane, as sscn_vortex_count
     const int nb = red_blocks((int64_t)p.nx * p.ny);
     const int nbv = red_blocks((int64_t)(p.nx - 1) * (p.ny - 1));
     if (b->precision == SSCN_C128) {
         hipLaunchKernelGGL((k_plane_max<double>), dim3(nb), dim3(256), 0, b->stream, (const V<double> *)b->psi[k], a,
-                           0, b->opart);
+                           k0, b->opart);
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, b->stream, b->opart, nb, 1, 1u, out);
-        hipLaunchKernelGGL((k_vortex<double>), dim3(nbv), dim3(256), 0, b->stream, (const V<double> *)b->psi[k], a, 0,
+        hipLaunchKernelGGL((k_vortex<double>), dim3(nbv), dim3(256), 0, b->stream, (const V<double> *)b->psi[k], a, k0,
                            density_frac, box, out, b->opart);
     } else {
-        hipLaunchKernelGGL((k_plane_max<float>), dim3(nb), dim3(256), 0, b->stream, (const V<float> *)b->psi[k], a, 0,
-                           b->opart);
+        hipLaunchKernelGGL((k_plane_max<float>), dim3(nb), dim3(256), 0, b->stream, (const V<float> *)b->psi[k], a,
+                           k0, b->opart);
         hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, b->stream, b->opart, nb, 1, 1u, out);
-        hipLaunchKernelGGL((k_vortex<float>), dim3(nbv), dim3(256), 0, b->stream, (const V<float> *)b->psi[k], a, 0,
+        hipLaunchKernelGGL((k_vortex<float>), dim3(nbv), dim3(256), 0, b->stream, (const V<float> *)b->psi[k], a, k0,
                            density_frac, box, out, b->opart);
     }
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(256), 0, b->stream, b->opart, nbv, 1, 0u, out + 1);
@@ -2381,8 +2462,12 @@ int sscn_batch_set_plan(sscn_batch *b, int plan)
         return fail(SSCN_EINVAL, "bad plan");
     if (plan == SSCN_PLAN_SWEEPS && !b->sweeps_ok)
         return fail(SSCN_EINVAL, "the batched sweep plan is not available for these instances");
+    if (b->dim3 && plan == SSCN_PLAN_FUSED)
+        return fail(SSCN_EINVAL, "a 3D batch steps with the sweep plan only");
     HIPCHECK(hipStreamSynchronize(b->stream));
     batch_drop_graph(b);
+    if (b->dim3)
+        plan = SSCN_PLAN_SWEEPS;
     b->plan = plan;
     b->active_plan = plan == SSCN_PLAN_SWEEPS ? SSCN_PLAN_SWEEPS : SSCN_PLAN_FUSED;
     return 0;

@@ -29,6 +29,8 @@ int launched(const char *what)
 
 int blocks(int64_t n) { return (int)std::min<int64_t>(4096, std::max<int64_t>(1, (n + 255) / 256)); }
 
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 }  // namespace
 
 extern "C" {
@@ -97,6 +99,27 @@ void go_conv_mfma(const uint16_t *x, int N, int H, int W, int Cin, const uint16_
                        lds, st, x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, 1);
 }
 
+template <int ACT, bool OUTF32, int BN, int WM>
+void go_conv_halo(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
+                  void *y, int ldy, int yoff, hipStream_t st)
+{
+    // narrow layers stage a stencil row of taps per K stage
+    constexpr int TG = BN <= 32 ? 3 : 1;
+    constexpr int lds = conv_halo_lds_bytes<BN, 32, TG>();
+    if (conv_lds_once(k_conv3x3_halo<ACT, OUTF32, BN, WM, 32, TG>, lds) != hipSuccess)
+        return;  // reported by launched()
+    hipLaunchKernelGGL((k_conv3x3_halo<ACT, OUTF32, BN, WM, 32, TG>), dim3(N * (H / kPatchH) * (W / kPatchW), Cout / BN),
+                       dim3(256), lds, st, x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff);
+}
+
+// The halo-patch kernel takes images whose sides are multiples of the patch
+// (8 x 16) with enough patches to fill the chip (>= 256 blocks).
+bool conv_halo_ok(int N, int H, int W, int Cout)
+{
+    return H % kPatchH == 0 && W % kPatchW == 0 &&
+           (int64_t)N * (H / kPatchH) * (W / kPatchW) * (Cout / conv_bn(Cout)) >= 256;
+}
+
 template <int ACT, bool OUTF32, int KC>
 void launch_conv_kc(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
                     void *y, int ldy, int yoff, float *ws, int nsplit, hipStream_t st)
@@ -125,6 +148,15 @@ void launch_conv(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t
         else
             hipLaunchKernelGGL((k_conv3x3<ACT, OUTF32, 16>), dim3((P + 63) / 64, Cout / 16), dim3(256), 0, st, x, N,
                                H, W, Cin, w, bias, Cout, y, ldy, yoff);
+        return;
+    }
+    if (nsplit <= 1 && conv_halo_ok(N, H, W, Cout)) {
+        switch (conv_bn(Cout)) {
+        case 128: go_conv_halo<ACT, OUTF32, 128, 2>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
+        case 64: go_conv_halo<ACT, OUTF32, 64, 2>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
+        case 32: go_conv_halo<ACT, OUTF32, 32, 4>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
+        default: go_conv_halo<ACT, OUTF32, 16, 4>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
+        }
         return;
     }
     if (Cin % 64 == 0)
@@ -232,8 +264,12 @@ int sscn_nn_act_bwd(void *dy, const void *y, int64_t n, void *stream)
 {
     if (!dy || !y || n < 0)
         return nn_fail(-1, "bad act_bwd arguments");
-    hipLaunchKernelGGL(k_act_bwd, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, (uint16_t *)dy,
-                       (const uint16_t *)y, (int)n);
+    if (n % 8 == 0 && aligned16(dy) && aligned16(y))
+        hipLaunchKernelGGL(k_act_bwd_v8, dim3(blocks(n / 8)), dim3(256), 0, (hipStream_t)stream, (uint16_t *)dy,
+                           (const uint16_t *)y, n / 8);
+    else
+        hipLaunchKernelGGL(k_act_bwd, dim3(blocks(n)), dim3(256), 0, (hipStream_t)stream, (uint16_t *)dy,
+                           (const uint16_t *)y, (int)n);
     return launched("act_bwd");
 }
 
@@ -241,8 +277,12 @@ int sscn_nn_pool2(const void *x, int N, int H, int W, int C, void *y, void *stre
 {
     if (!x || !y || H % 2 || W % 2)
         return nn_fail(-1, "bad pool2 arguments");
-    hipLaunchKernelGGL(k_pool2, dim3(blocks((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
-                       (const uint16_t *)x, N, H, W, C, (uint16_t *)y);
+    if (C % 8 == 0 && aligned16(x) && aligned16(y))
+        hipLaunchKernelGGL(k_pool2_v8, dim3(blocks((int64_t)N * H * W * C / 32)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)x, N, H, W, C, (uint16_t *)y);
+    else
+        hipLaunchKernelGGL(k_pool2, dim3(blocks((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)x, N, H, W, C, (uint16_t *)y);
     return launched("pool2");
 }
 
@@ -250,8 +290,12 @@ int sscn_nn_pool2_bwd(const void *dy, int N, int H, int W, int C, void *dx, void
 {
     if (!dy || !dx || H % 2 || W % 2)
         return nn_fail(-1, "bad pool2_bwd arguments");
-    hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
-                       (const uint16_t *)dy, N, H, W, C, (uint16_t *)dx);
+    if (C % 8 == 0 && aligned16(dy) && aligned16(dx))
+        hipLaunchKernelGGL(k_pool2_bwd_v8, dim3(blocks((int64_t)N * H * W * C / 8)), dim3(256), 0,
+                           (hipStream_t)stream, (const uint16_t *)dy, N, H, W, C, (uint16_t *)dx);
+    else
+        hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)dy, N, H, W, C, (uint16_t *)dx);
     return launched("pool2_bwd");
 }
 
@@ -259,8 +303,12 @@ int sscn_nn_up2(const void *x, int N, int H, int W, int C, void *y, int ldy, int
 {
     if (!x || !y || ldy < yoff + C)
         return nn_fail(-1, "bad up2 arguments");
-    hipLaunchKernelGGL(k_up2, dim3(blocks((int64_t)N * 4 * H * W * C)), dim3(256), 0, (hipStream_t)stream,
-                       (const uint16_t *)x, N, H, W, C, (uint16_t *)y, ldy, yoff);
+    if (C % 8 == 0 && ldy % 8 == 0 && yoff % 8 == 0 && aligned16(x) && aligned16(y))
+        hipLaunchKernelGGL(k_up2_v8, dim3(blocks((int64_t)N * 4 * H * W * C / 8)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)x, N, H, W, C, (uint16_t *)y, ldy, yoff);
+    else
+        hipLaunchKernelGGL(k_up2, dim3(blocks((int64_t)N * 4 * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)x, N, H, W, C, (uint16_t *)y, ldy, yoff);
     return launched("up2");
 }
 
@@ -268,8 +316,12 @@ int sscn_nn_up2_bwd(const void *dy, int ldy, int yoff, int N, int H, int W, int 
 {
     if (!dy || !dx || ldy < yoff + C)
         return nn_fail(-1, "bad up2_bwd arguments");
-    hipLaunchKernelGGL(k_up2_bwd, dim3(blocks((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
-                       (const uint16_t *)dy, ldy, yoff, N, H, W, C, (uint16_t *)dx);
+    if (C % 8 == 0 && ldy % 8 == 0 && yoff % 8 == 0 && aligned16(dy) && aligned16(dx))
+        hipLaunchKernelGGL(k_up2_bwd_v8, dim3(blocks((int64_t)N * H * W * C / 8)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)dy, ldy, yoff, N, H, W, C, (uint16_t *)dx);
+    else
+        hipLaunchKernelGGL(k_up2_bwd, dim3(blocks((int64_t)N * H * W * C)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)dy, ldy, yoff, N, H, W, C, (uint16_t *)dx);
     return launched("up2_bwd");
 }
 
@@ -278,8 +330,13 @@ int sscn_nn_chan_copy(const void *src, int lds, int soff, void *dst, int ldd, in
 {
     if (!src || !dst || lds < soff + C || ldd < doff + C)
         return nn_fail(-1, "bad chan_copy arguments");
-    hipLaunchKernelGGL(k_chan_copy, dim3(blocks((int64_t)P * C)), dim3(256), 0, (hipStream_t)stream,
-                       (const uint16_t *)src, lds, soff, (uint16_t *)dst, ldd, doff, P, C, accumulate);
+    if (C % 8 == 0 && lds % 8 == 0 && soff % 8 == 0 && ldd % 8 == 0 && doff % 8 == 0 && aligned16(src) &&
+        aligned16(dst))
+        hipLaunchKernelGGL(k_chan_copy_v8, dim3(blocks((int64_t)P * C / 8)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)src, lds, soff, (uint16_t *)dst, ldd, doff, P, C, accumulate);
+    else
+        hipLaunchKernelGGL(k_chan_copy, dim3(blocks((int64_t)P * C)), dim3(256), 0, (hipStream_t)stream,
+                           (const uint16_t *)src, lds, soff, (uint16_t *)dst, ldd, doff, P, C, accumulate);
     return launched("chan_copy");
 }
 

@@ -370,6 +370,194 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_mfma(const uint16_t *__restr
     }
 }
 
+// 3x3 convolution from a staged halo patch (images with W % 16 == 0 and
+// H % 8 == 0).  The block's 128 output pixels are an 8 x 16 patch of one
+// image; for each chunk of KC input channels the block stages the patch's
+// 10 x 18 input pixels once in LDS, and the 9 taps read their A fragments
+// from it at shifted positions (fragment rows are 16 consecutive pixels of a
+// patch row, so a shifted fragment is 16 consecutive staged pixels).  That
+// loads each input value about 1.4 times instead of 9.  K stages are
+// (chunk, group of TG taps) with the weights of TG taps per stage (TG = 3,
+// a row of the stencil, for narrow layers: more products per barrier),
+// double-buffered and loaded two stages ahead as in k_conv3x3_mfma; the
+// next chunk's patch is loaded during the current chunk's first stage and
+// written to the other patch buffer after its last.  Output as k_conv3x3.
+// Grid: (N (H / 8) (W / 16), Cout / BN), 256 threads.
+constexpr int kPatchH = 8, kPatchW = 16;
+constexpr int kHaloPix = (kPatchH + 2) * (kPatchW + 2);
+
+template <int BN, int KC, int TG>
+constexpr int conv_halo_lds_bytes() { return 2 * (kHaloPix + TG * BN) * conv_mfma_ld<KC>() * 2; }
+
+template <int ACT, bool OUTF32, int BN, int WM, int KC, int TG>
+__global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restrict__ x, int N, int H, int W,
+                                                         int Cin, const uint16_t *__restrict__ w,
+                                                         const float *__restrict__ bias, int Cout,
+                                                         void *__restrict__ y, int ldy, int yoff)
+{
+    constexpr int BM = 128, WN = 4 / WM;
+    constexpr int TM = BM / WM, TN = BN / WN;
+    constexpr int FM = TM / 16, FN = TN / 16;
+    constexpr int LD = conv_mfma_ld<KC>();
+    constexpr int KQ = KC / 8;
+    constexpr int NP = (kHaloPix * KQ + 255) / 256;  // patch loads per thread and chunk
+    constexpr int NB = (TG * BN * KQ + 255) / 256;   // weight loads per thread and stage
+    constexpr int SPC = 9 / TG;                      // stages per chunk
+    static_assert(WM * WN == 4 && FM >= 1 && FN >= 1, "4 waves tile the block");
+    static_assert(BM == kPatchH * kPatchW, "the block's pixels are one patch");
+    static_assert(TG == 1 || TG == 3, "whole stencil rows or single taps");
+    extern __shared__ __align__(16) uint16_t conv_smem[];
+    uint16_t *sP = conv_smem;                      // [2][kHaloPix][LD]
+    uint16_t *sB = conv_smem + 2 * kHaloPix * LD;  // [2][TG][BN][LD]
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, g = lane >> 4;
+    const int wm = wave % WM, wn = wave / WM;
+    const int tiles_x = W / kPatchW, tiles_y = H / kPatchH;
+    const int bx = blockIdx.x % tiles_x, rest = blockIdx.x / tiles_x;
+    const int by = rest % tiles_y, bn = rest / tiles_y;
+    const int y0 = by * kPatchH - 1, x0 = bx * kPatchW - 1;  // image position of staged pixel 0
+    const int co0 = blockIdx.y * BN;
+    const int kc = Cin % KC == 0 ? KC : 16;
+    const int ncc = Cin / kc;
+    const int nk = SPC * ncc;
+    uint4 rp[NP];
+    auto load_patch = [&](int c) {
+        const int c0 = c * kc;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int e = tid + 256 * i;
+            const int pix = e / KQ, part = e % KQ;
+            const int sy = y0 + pix / (kPatchW + 2), sx = x0 + pix % (kPatchW + 2);
+            rp[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (pix < kHaloPix && part * 8 < kc && sy >= 0 && sy < H && sx >= 0 && sx < W)
+                rp[i] = *reinterpret_cast<const uint4 *>(x + ((size_t)(bn * H + sy) * W + sx) * Cin + c0 + part * 8);
+        }
+    };
+    auto store_patch = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) {
+            const int e = tid + 256 * i;
+            if (e < kHaloPix * KQ)
+                *reinterpret_cast<uint4 *>(&sP[(buf * kHaloPix + e / KQ) * LD + (e % KQ) * 8]) = rp[i];
+        }
+    };
+    struct Regs {
+        uint4 b[NB];
+    };
+    // stage s: chunk s / SPC, taps TG (s % SPC) .. + TG - 1; staged weight
+    // row tg * BN + co holds tap TG (s % SPC) + tg of output channel co0 + co
+    auto load_w = [&](int s, Regs &rg) {
+        const int c = s / SPC, tap0 = (s - SPC * c) * TG, c0 = c * kc;
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + 256 * i;
+            const int row = e / KQ, part = e % KQ;
+            const int tg = row / BN, co = row - tg * BN;
+            rg.b[i] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < TG * BN * KQ && part * 8 < kc)
+                rg.b[i] = *reinterpret_cast<const uint4 *>(w + ((size_t)(co0 + co) * 9 + tap0 + tg) * Cin + c0 + part * 8);
+        }
+    };
+    auto store_w = [&](int buf, const Regs &rg) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+            const int e = tid + 256 * i;
+            if (e < TG * BN * KQ)
+                *reinterpret_cast<uint4 *>(&sB[(buf * TG * BN + e / KQ) * LD + (e % KQ) * 8]) = rg.b[i];
+        }
+    };
+    v4f acc[FM][FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+        for (int j = 0; j < FN; ++j)
+            acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    // stage s: chunk s / SPC (patch buffer (s / SPC) & 1), weights in buffer wb
+    auto compute = [&](int s, int wb) {
+        const int c = s / SPC, tap0 = (s - SPC * c) * TG;
+        const uint16_t *cP = sP + (size_t)(c & 1) * kHaloPix * LD;
+#pragma unroll
+        for (int tg = 0; tg < TG; ++tg) {
+            const int tap = tap0 + tg;
+            const int dy = tap / 3, dx = tap % 3;  // offsets into the staged patch (halo 1)
+            const uint16_t *cB = sB + ((wb * TG + tg) * BN + wn * TN) * LD;
+#pragma unroll
+            for (int k32 = 0; k32 < KC / 32; ++k32) {
+                v8bf av[FM], bv[FN];
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const int py = (wm * TM + i * 16) / kPatchW;  // the fragment's patch row
+                    av[i] = lds8(cP + ((py + dy) * (kPatchW + 2) + dx + m) * LD + k32 * 32 + 8 * g);
+                }
+#pragma unroll
+                for (int j = 0; j < FN; ++j)
+                    bv[j] = lds8(cB + (j * 16 + m) * LD + k32 * 32 + 8 * g);
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j)
+                        acc[i][j] = mfma16x32(av[i], bv[j], acc[i][j]);
+            }
+        }
+    };
+    // the patch of the next chunk: loaded at its predecessor's first stage,
+    // stored after its predecessor's last
+    auto patch_io = [&](int s, bool before) {
+        const int c = s / SPC, q = s - SPC * c;
+        if (before && q == 0 && c + 1 < ncc)
+            load_patch(c + 1);
+        if (!before && q == SPC - 1 && c + 1 < ncc)
+            store_patch((c + 1) & 1);
+    };
+    Regs r0, r1;
+    load_patch(0);
+    load_w(0, r0);
+    if (nk > 1)
+        load_w(1, r1);
+    store_patch(0);
+    store_w(0, r0);
+    __syncthreads();
+    for (int t = 0; t < nk; t += 2) {
+        if (t + 2 < nk)
+            load_w(t + 2, r0);
+        patch_io(t, true);
+        compute(t, 0);
+        patch_io(t, false);
+        if (t + 1 < nk)
+            store_w(1, r1);
+        __syncthreads();
+        if (t + 1 >= nk)
+            break;
+        if (t + 3 < nk)
+            load_w(t + 3, r1);
+        patch_io(t + 1, true);
+        compute(t + 1, 1);
+        patch_io(t + 1, false);
+        if (t + 2 < nk)
+            store_w(0, r0);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int co = co0 + wn * TN + j * 16 + m;
+        const float bv = bias ? bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pm = wm * TM + i * 16 + 4 * g + r;  // pixel of the patch
+                const size_t pp = (size_t)(bn * H + by * kPatchH + pm / kPatchW) * W + bx * kPatchW + pm % kPatchW;
+                float v = acc[i][j][r] + bv;
+                if (ACT == ACT_LEAKY)
+                    v = v > 0.f ? v : kLeak * v;
+                if (OUTF32)
+                    reinterpret_cast<float *>(y)[pp * ldy + yoff + co] = v;
+                else
+                    reinterpret_cast<uint16_t *>(y)[pp * ldy + yoff + co] = f2bf(v);
+            }
+    }
+}
+
 // The split-K sums: y[p * ldy + yoff + c] = act(sum over z of part[z][p][c]
 // (z = 0, 1, ... in order) + bias[c]), bf16 or fp32.  Grid-stride over the
 // P * C outputs.
@@ -612,6 +800,144 @@ __global__ __launch_bounds__(256) void k_chan_copy(const uint16_t *__restrict__ 
         const float v = bf2f(src[(size_t)p * lds_ + soff + c]);
         uint16_t *d = dst + (size_t)p * ldd + doff + c;
         *d = f2bf(accumulate ? bf2f(*d) + v : v);
+    }
+}
+
+// The same five kernels on groups of 8 channels (one 16-byte access per
+// operand and thread); every channel count and channel offset a multiple of
+// 8.  The arithmetic per element is that of the scalar kernels above, so the
+// results are the same bits.
+__device__ __forceinline__ void unpack8(const uint4 &u, float (&f)[8])
+{
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = bf2f((uint16_t)(w[i] & 0xffffu));
+        f[2 * i + 1] = bf2f((uint16_t)(w[i] >> 16));
+    }
+}
+
+__device__ __forceinline__ uint4 pack8(const float (&f)[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+__global__ __launch_bounds__(256) void k_pool2_v8(const uint16_t *__restrict__ x, int N, int H, int W, int C,
+                                                  uint16_t *__restrict__ y)
+{
+    const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
+    const int64_t n = (int64_t)N * Ho * Wo * C8;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c8 = (int)(e % C8);
+        const int64_t q = e / C8;
+        const int j = (int)(q % Wo), i = (int)((q / Wo) % Ho), b = (int)(q / ((int64_t)Wo * Ho));
+        const size_t base = ((size_t)(b * H + 2 * i) * W + 2 * j) * C + 8 * c8;
+        float a[8], bb[8], c[8], d[8], o[8];
+        unpack8(*reinterpret_cast<const uint4 *>(x + base), a);
+        unpack8(*reinterpret_cast<const uint4 *>(x + base + C), bb);
+        unpack8(*reinterpret_cast<const uint4 *>(x + base + (size_t)W * C), c);
+        unpack8(*reinterpret_cast<const uint4 *>(x + base + (size_t)W * C + C), d);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            o[t] = 0.25f * (a[t] + bb[t] + c[t] + d[t]);
+        *reinterpret_cast<uint4 *>(y + (size_t)q * C + 8 * c8) = pack8(o);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pool2_bwd_v8(const uint16_t *__restrict__ dy, int N, int H, int W, int C,
+                                                      uint16_t *__restrict__ dx)
+{
+    const int C8 = C / 8;
+    const int64_t n = (int64_t)N * H * W * C8;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c8 = (int)(e % C8);
+        const int64_t q = e / C8;
+        const int j = (int)(q % W), i = (int)((q / W) % H), b = (int)(q / ((int64_t)W * H));
+        float g[8];
+        unpack8(*reinterpret_cast<const uint4 *>(dy + ((size_t)(b * (H / 2) + i / 2) * (W / 2) + j / 2) * C + 8 * c8), g);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            g[t] = 0.25f * g[t];
+        *reinterpret_cast<uint4 *>(dx + (size_t)q * C + 8 * c8) = pack8(g);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_up2_v8(const uint16_t *__restrict__ x, int N, int H, int W, int C,
+                                                uint16_t *__restrict__ y, int ldy, int yoff)
+{
+    const int Ho = 2 * H, Wo = 2 * W, C8 = C / 8;
+    const int64_t n = (int64_t)N * Ho * Wo * C8;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c8 = (int)(e % C8);
+        const int64_t q = e / C8;
+        const int j = (int)(q % Wo), i = (int)((q / Wo) % Ho), b = (int)(q / ((int64_t)Wo * Ho));
+        *reinterpret_cast<uint4 *>(y + (size_t)q * ldy + yoff + 8 * c8) =
+            *reinterpret_cast<const uint4 *>(x + ((size_t)(b * H + i / 2) * W + j / 2) * C + 8 * c8);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_up2_bwd_v8(const uint16_t *__restrict__ dy, int ldy, int yoff, int N, int H,
+                                                    int W, int C, uint16_t *__restrict__ dx)
+{
+    const int C8 = C / 8, Wo = 2 * W;
+    const int64_t n = (int64_t)N * H * W * C8;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c8 = (int)(e % C8);
+        const int64_t q = e / C8;
+        const int j = (int)(q % W), i = (int)((q / W) % H), b = (int)(q / ((int64_t)W * H));
+        const size_t r0 = (size_t)(b * 2 * H + 2 * i) * Wo + 2 * j;
+        float a[8], bb[8], c[8], d[8], o[8];
+        unpack8(*reinterpret_cast<const uint4 *>(dy + r0 * ldy + yoff + 8 * c8), a);
+        unpack8(*reinterpret_cast<const uint4 *>(dy + (r0 + 1) * ldy + yoff + 8 * c8), bb);
+        unpack8(*reinterpret_cast<const uint4 *>(dy + (r0 + Wo) * ldy + yoff + 8 * c8), c);
+        unpack8(*reinterpret_cast<const uint4 *>(dy + (r0 + Wo + 1) * ldy + yoff + 8 * c8), d);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            o[t] = a[t] + bb[t] + c[t] + d[t];
+        *reinterpret_cast<uint4 *>(dx + (size_t)q * C + 8 * c8) = pack8(o);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_chan_copy_v8(const uint16_t *__restrict__ src, int lds_, int soff,
+                                                      uint16_t *__restrict__ dst, int ldd, int doff, int P, int C,
+                                                      int accumulate)
+{
+    const int C8 = C / 8;
+    const int64_t n = (int64_t)P * C8;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int c8 = (int)(e % C8);
+        const int64_t p = e / C8;
+        const uint4 sv = *reinterpret_cast<const uint4 *>(src + (size_t)p * lds_ + soff + 8 * c8);
+        uint4 *d = reinterpret_cast<uint4 *>(dst + (size_t)p * ldd + doff + 8 * c8);
+        if (!accumulate) {
+            *d = sv;  // bf16 -> fp32 -> bf16 is exact
+        } else {
+            float a[8], b[8];
+            unpack8(sv, a);
+            unpack8(*d, b);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                a[t] = b[t] + a[t];
+            *d = pack8(a);
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_act_bwd_v8(uint16_t *__restrict__ dy, const uint16_t *__restrict__ y,
+                                                   int64_t n8)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n8; e += (int64_t)gridDim.x * 256) {
+        float g[8], v[8];
+        unpack8(reinterpret_cast<const uint4 *>(dy)[e], g);
+        unpack8(reinterpret_cast<const uint4 *>(y)[e], v);
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            g[t] = v[t] > 0.f ? g[t] : kLeak * g[t];
+        reinterpret_cast<uint4 *>(dy)[e] = pack8(g);
     }
 }
 

@@ -176,3 +176,53 @@ def test_batch_groups_give_the_same_bits(P, prec, monkeypatch):
         ref = O.step(op, O.init_state(op, 1, W.phase_field(40 + k, c["ny"], c["nx"]), 1.0), 38)
         assert rel(bb.get_state(k).astype(np.complex128), ref) <= tol, k
     bb.close()
+
+
+def mixed3d(prec, mode=0):
+    shapes = [(24, 20, 12), (32, 16, 10), (20, 28, 14)]
+    out = []
+    for t, (nx, ny, nz) in enumerate(shapes):
+        out.append(dict(dim=3, nx=nx, ny=ny, nz=nz, hx=0.3 + 0.02 * t, hy=0.28 + 0.01 * t, hz=0.35 - 0.03 * t,
+                        gamma=1.0, nu=1.0 + 0.05 * t, lam=2.0 + t, g=20.0 + 15.0 * t,
+                        omega=0.4 + 0.1 * t, dt=1e-3 * (1 + t % 2), mode=mode, precision=prec))
+    return out
+
+
+@pytest.mark.parametrize("prec,mode", [(0, 0), (0, 1), (1, 0)])
+def test_batch_3d_matches_oracle_per_instance(P, prec, mode):
+    """A batch of 3D instances of different shapes and parameters (x-, y-
+    and z-sweeps over work lists of every instance), stepped directly and
+    from graphs, against the oracle instance by instance; then a convergence
+    run with drop-out and the z = 0 plane's vortex count."""
+    print(f"[gpu-batch] 3D prec={prec} mode={mode}", flush=True)
+    cfgs = mixed3d(prec, mode)
+    b = P.Batch(cfgs)
+    assert b.info()["plan"] == 1
+    refs = []
+    for k, c in enumerate(cfgs):
+        ph = W.phase_field(50 + k, c["ny"], c["nx"])
+        b.init_state(k, 1, ph, 1.0)
+        op = O.make_params(**c)
+        r0 = O.init_state(op, 1, ph, 1.0)
+        assert rel(b.get_state(k), r0) <= (1e-14 if prec == 0 else 1e-6), k
+        refs.append((op, r0))
+    b.step(1)
+    b.step(40)
+    tol = 1e-10 if prec == 0 else 1e-5
+    obs = b.observables()
+    for k, (op, r0) in enumerate(refs):
+        ref = O.step(op, r0, 41)
+        got = b.get_state(k).astype(np.complex128)
+        assert rel(got, ref) <= tol, k
+        oo = O.observables(op, ref)
+        for key in ("norm", "mu", "energy", "rms_z"):
+            assert abs(obs[k][key] - oo[key]) <= tol * max(1.0, abs(oo[key])), (k, key)
+    prof = b.profile_step(3)
+    assert prof["z"] > 0 and prof["x"] > 0 and prof["y"] > 0
+    if mode == 0:
+        st = b.run(20000, check_every=100, tol=1e-4)
+        assert all(v > 0 for v in st), st
+        for k, c in enumerate(cfgs):
+            op = O.make_params(**c)
+            assert b.vortex_count(k) == O.vortex_count(op, b.get_state(k).astype(np.complex128))
+    b.close()

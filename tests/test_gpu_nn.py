@@ -58,7 +58,13 @@ def close_bf(gpu, ref, absum, name):
                                                  # 32 and 16 channels
                                                  (2, 9, 13, 64, 128, 1), (1, 10, 10, 128, 256, 0),
                                                  (2, 7, 9, 96, 64, 1), (1, 16, 16, 16, 32, 1),
-                                                 (1, 5, 6, 32, 48, 0), (1, 12, 12, 512, 256, 1)])
+                                                 (1, 5, 6, 32, 48, 0), (1, 12, 12, 512, 256, 1),
+                                                 # the halo-patch kernel (sides multiples of 8 x 16,
+                                                 # >= 256 patch blocks): BN 32 with 16- and 32-channel
+                                                 # chunks, 64, 128 (two column blocks) and 16
+                                                 (8, 64, 64, 16, 32, 1), (8, 64, 64, 96, 32, 1),
+                                                 (8, 64, 64, 64, 64, 0), (4, 64, 64, 64, 256, 1),
+                                                 (8, 64, 64, 32, 16, 0)])
 def test_conv3x3(nn, N, H, W, Cin, Cout, act):
     rng = np.random.default_rng(N * 1000 + Cin)
     xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
@@ -141,9 +147,12 @@ def test_wgrad_many_splits_and_ragged_tail(nn):
     assert torch.equal(dw, dw2)
 
 
-def test_elementwise_and_resampling(nn):
+# C = 32 with channel offsets that are multiples of 8 takes the 16-byte
+# kernels, C = 20 with odd offsets the element-wise ones
+@pytest.mark.parametrize("C,uoff,soff,doff,cc", [(32, 16, 8, 8, 24), (20, 4, 3, 5, 12)])
+def test_elementwise_and_resampling(nn, C, uoff, soff, doff, cc):
     rng = np.random.default_rng(9)
-    N, H, W, C = 2, 8, 6, 32
+    N, H, W = 2, 8, 6
     xd, x = to_bf(rng.standard_normal((N, H, W, C)))
     # pooling and its gradient
     y = torch.zeros((N, H // 2, W // 2, C), dtype=torch.int16, device="cuda")
@@ -153,20 +162,20 @@ def test_elementwise_and_resampling(nn):
     nn.pool2_bwd(y, N, H, W, C, dx)
     assert np.array_equal(from_bf(dx), U.bf16(U.pool2_bwd(from_bf(y))))
     # upsampling into a channel slice and its gradient
-    ld = C + 16
+    ld = C + uoff
     up = torch.zeros((N, 2 * H, 2 * W, ld), dtype=torch.int16, device="cuda")
-    nn.up2(xd, N, H, W, C, up, ld, 16)
-    assert np.array_equal(from_bf(up)[..., 16:], U.up2(x))
+    nn.up2(xd, N, H, W, C, up, ld, uoff)
+    assert np.array_equal(from_bf(up)[..., uoff:], U.up2(x))
     g = torch.zeros_like(xd)
-    nn.up2_bwd(up, ld, 16, N, H, W, C, g)
+    nn.up2_bwd(up, ld, uoff, N, H, W, C, g)
     assert np.array_equal(from_bf(g), U.bf16(U.up2_bwd(U.up2(x))))
     # channel copy and accumulate
     dst = torch.zeros((N, H, W, 48), dtype=torch.int16, device="cuda")
-    nn.chan_copy(xd, C, 0, dst, 48, 8, N * H * W, 24)
-    nn.chan_copy(xd, C, 8, dst, 48, 8, N * H * W, 24, accumulate=True)
+    nn.chan_copy(xd, C, 0, dst, 48, doff, N * H * W, cc)
+    nn.chan_copy(xd, C, soff, dst, 48, doff, N * H * W, cc, accumulate=True)
     got = from_bf(dst)
-    assert np.array_equal(got[..., 8:32], U.bf16(x[..., 0:24] + x[..., 8:32]))
-    assert np.all(got[..., :8] == 0) and np.all(got[..., 32:] == 0)
+    assert np.array_equal(got[..., doff:doff + cc], U.bf16(x[..., 0:cc] + x[..., soff:soff + cc]))
+    assert np.all(got[..., :doff] == 0) and np.all(got[..., doff + cc:] == 0)
     # leaky-ReLU gradient
     dyd, dy = to_bf(rng.standard_normal((N, H, W, C)))
     nn.act_bwd(dyd, xd)

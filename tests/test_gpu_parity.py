@@ -69,6 +69,30 @@ def test_init_state_matches_oracle(P):
         s.close()
 
 
+def test_seeded_init_state_matches_oracle(P):
+    """The device's counter-based random phase gives the oracle's numbers bit
+    for bit (integer hashing), and the seeded initial state of Eq. (fun)
+    matches the oracle's from those numbers, in 2D and 3D."""
+    announce("seeded phase field")
+    got = P.phase_field_seed(13, 37, 53).cpu().numpy()
+    assert np.array_equal(got, O.splitmix_phase(13, 37, 53))
+    big = P.phase_field_seed(2**63 + 5, 200, 256).cpu().numpy()
+    assert np.array_equal(big[::17, ::13], O.splitmix_phase(2**63 + 5, 200, 256)[::17, ::13])
+    for cfg in (dict(W.CONFIGS["c1"], nx=96, ny=80), dict(W.CONFIGS["c3"], nx=48, ny=40, nz=20, precision=0)):
+        announce(f"seeded init dim={cfg['dim']}")
+        s, op = both(P, cfg)
+        dz = cfg.get("d_z", 0.0)
+        for seed in (13, 7):
+            s.init_state_seed(1, seed, cfg["d_xy"], dz)
+            ref = O.init_state(op, 1, O.splitmix_phase(seed, cfg["ny"], cfg["nx"]), cfg["d_xy"],
+                               dz if dz > 0 else None)
+            assert rel(s.get_state(), ref) <= 1e-14
+        s.init_state_seed(0, 13, 1.3, dz, random_phase=False)
+        ref = O.init_state(op, 0, None, 1.3, dz if dz > 0 else None)
+        assert rel(s.get_state(), ref) <= 1e-14
+        s.close()
+
+
 def test_config1_full_run_matches_oracle(P):
     """128^2, g = 100, Omega = 0.6, dt = 1e-3, 1000 imaginary-time steps."""
     cfg = W.CONFIGS["c1"]

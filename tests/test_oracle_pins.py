@@ -553,3 +553,30 @@ def test_extend_z_gives_the_3d_form_of_eq_fun():
     z = -0.5 * nz * hz + np.arange(nz) * hz
     assert ext[3, 1, 1].real / ext[7, 1, 1].real == pytest.approx(np.exp(-(z[3] ** 2 - z[7] ** 2) / (2 * d_z ** 2)),
                                                                   rel=1e-14)
+
+
+def test_splitmix64_matches_the_published_generator():
+    """The first three outputs of the SplitMix64 generator seeded with 0, as
+    its reference implementation (Vigna, splitmix64.c, public domain) prints
+    them; the generator's state advances by the increment each call."""
+    want = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    state, got = 0, []
+    for _ in range(3):
+        got.append(O.splitmix64(state))
+        state = (state + 0x9E3779B97F4A7C15) & ((1 << 64) - 1)
+    assert got == want
+
+
+def test_splitmix_phase_is_a_53_bit_uniform_per_point():
+    ph = O.splitmix_phase(13, 40, 50)
+    assert ph.shape == (40, 50)
+    assert np.all(ph >= 0.0) and np.all(ph < 1.0)
+    # every value is an integer multiple of 2^-53
+    assert np.all(np.floor(ph * 2.0 ** 53) == ph * 2.0 ** 53)
+    # point (i, j) depends on the seed and its index j nx + i only
+    assert ph[3, 7] == (O.splitmix64(13 ^ (3 * 50 + 7)) >> 11) * 2.0 ** -53
+    assert O.splitmix_phase(13, 1, 2000)[0, 157] == ph[3, 7]
+    # uniform: mean and variance within 5 sigma of 1/2 and 1/12 over 2000 draws
+    assert abs(ph.mean() - 0.5) < 5 * np.sqrt(1 / 12 / ph.size)
+    assert abs(ph.var() - 1 / 12) < 5 * np.sqrt(1 / 180 / ph.size)
+    assert not np.array_equal(O.splitmix_phase(14, 40, 50), ph)

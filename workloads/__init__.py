@@ -95,6 +95,34 @@ def random_field(seed, shp, envelope=True):
 BATCH_SIZES = (128, 192, 256, 384, 512)
 
 
+def batch3d_instances(n=8, seed=2020, h=0.1, hz=0.2, nz=64, dt=2e-4):
+    """Parameter draws of a batched 3D imaginary-time sweep: the 3D workload's
+    trap (gamma = nu = 1, lambda = 4, h_z = 0.2, 64 points in z, dt = 2e-4)
+    with Omega ~ U[0.5, 0.9], g_3D ~ logU[200, 2000] and the in-plane side
+    drawn uniformly from the members of {128, 192, 256} whose extent holds
+    2 * 1.4 radii of the rotating condensate (largest if none does); the
+    radius is the 2D Thomas-Fermi one for g_2D = g_3D sqrt(lambda / (2 pi))
+    (the quasi-2D reduction), which over-estimates the 3D one."""
+    rng = np.random.default_rng(int(seed))
+    lam = 4.0
+    out = []
+    for t in range(n):
+        om = float(rng.uniform(0.5, 0.9))
+        g = float(math.exp(rng.uniform(math.log(200.0), math.log(2000.0))))
+        a = 1.0 - om * om
+        g2 = g * math.sqrt(lam / (2.0 * math.pi))
+        mu_tf = math.sqrt(g2 * a / math.pi)
+        r_tf = math.sqrt(2.0 * mu_tf) / math.sqrt(a)
+        ok = [s for s in (128, 192, 256) if s * h >= 2.0 * 1.4 * r_tf]
+        if not ok:
+            ok = [256]
+        side = int(ok[int(rng.integers(len(ok)))])
+        out.append(dict(dim=3, nx=side, ny=side, nz=nz, hx=h, hy=h, hz=hz,
+                        gamma=1.0, nu=1.0, lam=lam, g=g, omega=om, dt=dt,
+                        mode=0, precision=1, seed=13 + t, kind=1, d_xy=1.0))
+    return out
+
+
 def batch_instances(n=64, seed=2019, h=0.1, dt=1e-3):
     """Parameter draws of the batched 2D imaginary-time sweep.
 
