@@ -11,14 +11,18 @@ SSCN step (H1 + x-sweep + y-sweep + FP64 norm; the rescale is folded into
 the next step).  `value` = grid-point updates per second, sum over the
 instances of their points times --steps, over the wall time of exactly
 --steps timed steps; the inputs are resident on the GPU and the steps are
-replayed from HIP graphs captured before the timed region.
+replayed from HIP graphs captured before the timed region.  Before the
+--warmup steps, untimed chunks of 50 steps run until two consecutive chunks
+agree in time to 1 % (at most 2 s), so that a timed region of a few
+milliseconds does not measure the clock ramp of a GPU that was idle.
 
 Also reported on the same JSON line:
   roofline      the dominant kernel of the batched step: algorithmic bytes
                 per launch (one read and one write of every instance's state
                 per sweep: 2 x 16 B per point) / its average duration,
-                measured with HIP events around every kernel of consecutive
-                steps on the stream it runs on, against 8 TB/s HBM; traffic =
+                measured with HIP events (without system-scope fences)
+                around every kernel of consecutive steps on the stream it
+                runs on, against 8 TB/s HBM; traffic =
                 counter bytes per launch from the committed rocprofv3 summary
                 (null when the kernel sources differ from the ones profiled);
   variants      the 512^2 workload (complex128 and complex64, imaginary and
@@ -135,9 +139,12 @@ def profile_sample(P, torch):
     sync(torch)
     print("profile-sample: copy 256 MiB x3 done", flush=True)
     del a, c
+    # the plan and x-sweep lines-per-block option the headline's autotuner
+    # picks on this workload (under a counter-collecting profiler the
+    # autotuner's own timings are distorted)
+    os.environ["SSCN_BATCH_XLINES"] = "1"
     b = make_batch(P, batch_cfgs(0))
-    # the plan the headline's autotuner picks on this workload (under a
-    # counter-collecting profiler the autotuner's own timings are distorted)
+    del os.environ["SSCN_BATCH_XLINES"]
     b.set_plan(P.PLAN_SWEEPS)
     b.prepare_steps(20)
     b.step(20)
@@ -154,11 +161,35 @@ def profile_sample(P, torch):
         s.close()
 
 
-def timed_batch(P, torch, cfgs, steps, warmup):
-    """The headline: warm up, capture the graphs of a `steps`-step call, then
-    time exactly `steps` steps (wall clock between two synchronisations, and
-    HIP events on the batch's stream around the same region)."""
+def settle(obj, torch, chunk=50, tol=0.01, max_s=2.0):
+    """Untimed steps in chunks until two consecutive chunks take the same time
+    to within tol (HIP events on the current stream, which the object
+    launches on), at most max_s seconds: a GPU that has been idle runs its
+    first milliseconds of work at lower clocks, which a timed region of a few
+    milliseconds would otherwise measure.  Returns the chunks' ms per step."""
+    obj.prepare_steps(chunk)
+    times, t_end = [], time.perf_counter() + max_s
+    while time.perf_counter() < t_end:
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        obj.step(chunk)
+        e1.record()
+        e1.synchronize()
+        times.append(e0.elapsed_time(e1) / chunk)
+        if len(times) >= 3 and abs(times[-1] - times[-2]) <= tol * times[-1]:
+            break
+    return times
+
+
+def timed_batch(P, torch, cfgs, steps, warmup, info=None):
+    """The headline: settle the clocks (settle), warm up, capture the graphs
+    of a `steps`-step call, then time exactly `steps` steps (wall clock
+    between two synchronisations, and HIP events on the batch's stream around
+    the same region).  info (a dict) receives the settling chunks."""
     b = make_batch(P, cfgs)
+    st = settle(b, torch)  # the batch launches on torch's current stream
+    if info is not None:
+        info["settle_ms_per_step"] = [round(t, 5) for t in st]
     b.prepare_steps(warmup)
     b.step(warmup)
     b.prepare_steps(steps)
@@ -248,11 +279,12 @@ def batch3d_variant(P, torch, precision, steps=200, warmup=20):
     pts = sum(c["nx"] * c["ny"] * c["nz"] for c in cfgs)
     b, dt, _ = timed_batch(P, torch, cfgs, steps, warmup)
     prof = b.profile_step(10)
+    xopt = b.info()["x_lines_option"]
     b.close()
     esize = 16 if precision == 0 else 8
     per = 2 * esize * pts
     return {"instances": len(cfgs), "points": pts, "grid_sides": sorted({c["nx"] for c in cfgs}),
-            "nz": cfgs[0]["nz"], "updates_per_s": round(pts * steps / dt, 1),
+            "nz": cfgs[0]["nz"], "x_lines_option": xopt, "updates_per_s": round(pts * steps / dt, 1),
             "ms_per_step": round(dt / steps * 1e3, 6), "steps": steps,
             "kernel_ms": {k: round(v, 6) for k, v in prof.items()},
             "kernel_frac_of_8TBps": {k: round(per / (prof[k] * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)
@@ -548,7 +580,8 @@ def main():
     prec = 0 if a.precision == "c128" else 1
     cfgs = batch_cfgs(prec)
     pts = sum(c["nx"] * c["ny"] for c in cfgs)
-    b, dt, step_ms = timed_batch(P, torch, cfgs, a.steps, a.warmup)
+    sinfo = {}
+    b, dt, step_ms = timed_batch(P, torch, cfgs, a.steps, a.warmup, info=sinfo)
     value = pts * a.steps / dt
     roof = batch_roofline(b, cfgs)
     info = b.info()
@@ -570,8 +603,13 @@ def main():
                    "grid_sides": {str(k): v for k, v in sorted(sizes.items())},
                    "precision": a.precision, "plan": {1: "batched sweeps", 2: "batched fused step"}.get(
                        info["plan"], info["plan"]), "window": info["window"],
+                   "x_lines": {0: "most lines per block", 1: "lines per block capped at 40 KiB of LDS"}[
+                       info["x_lines_option"]],
+                   "x_lines_tune_ms_8_steps": [round(t, 4) for t in info["x_lines_tune_ms"]],
                    "step_ms_events": round(step_ms, 6), "parallelism": "single GPU"},
         "roofline": roof,
+        "settle": {"steps_per_chunk": 50, "ms_per_step": sinfo["settle_ms_per_step"],
+                   "note": "untimed chunks of steps before the warm-up, until two agree to 1 %"},
     }
     if not a.no_extras:
         variants = {}

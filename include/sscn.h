@@ -427,13 +427,28 @@ int sscn_batch_vortex_count(sscn_batch *b, int k, double density_frac, int box, 
  * y-sweep kernel over every instance's line blocks and y tiles, with a
  * per-instance rescale), or SSCN_PLAN_AUTO (default: the first stepping
  * call times both from a saved copy of the states and keeps the faster).
- * Both plans give the same steps within rounding.  SSCN_EINVAL for the
- * sweep plan when an instance's lines are too long to stage. */
+ * Both plans give the same steps within rounding.  The first stepping call
+ * under the sweep plan (chosen or forced) also times the x-sweep's two
+ * lines-per-block options (sscn_batch_x_lines), which give the same bits.
+ * SSCN_EINVAL for the sweep plan when an instance's lines are too long to
+ * stage. */
 int sscn_batch_set_plan(sscn_batch *b, int plan);
 
 /* The plan in use (SSCN_PLAN_AUTO until the first stepping call resolves
  * it) and the common window W of the batch.  Either pointer may be NULL. */
 int sscn_batch_info(sscn_batch *b, int *plan, int *window);
+
+/* Lines per block of the batched x-sweep (sweep plan, Sec. 3's x-direction
+ * Crank-Nicolson solves, one block per group of whole x-lines of an
+ * instance): *option = 0 for the most lines the segment count and staging
+ * allow, 1 for that number halved until a block's LDS is at most 40 KiB
+ * (four blocks per CU; the launch reserves the largest instance's LDS for
+ * every block).  Option 1 until the autotuner (first stepping call under the
+ * sweep plan) keeps the faster; the environment variable
+ * SSCN_BATCH_XLINES=0 or 1, read at sscn_batch_init, fixes it instead.
+ * tune_ms (2 floats, may be NULL) receives the autotuner's times of 8 steps
+ * under each option (0 if not timed). */
+int sscn_batch_x_lines(sscn_batch *b, int *option, float *tune_ms);
 
 void sscn_batch_destroy(sscn_batch *b);
 

@@ -27,7 +27,7 @@ EXPORTS = ("sscn_init", "sscn_init_state", "sscn_init_state_seed", "sscn_phase_f
            "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step", "sscn_batch_prepare_steps", "sscn_batch_profile_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
-           "sscn_batch_info", "sscn_batch_destroy", "sscn_embed_state", "sscn_extend_z", "sscn_density", "sscn_resample",
+           "sscn_batch_info", "sscn_batch_x_lines", "sscn_batch_destroy", "sscn_embed_state", "sscn_extend_z", "sscn_density", "sscn_resample",
            "sscn_angular_moments",
            "sscn_destroy", "sscn_strerror", "sscn_last_error")
 
@@ -104,6 +104,7 @@ def lib():
                                               ctypes.POINTER(ctypes.c_int)]
         L.sscn_batch_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_batch_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.sscn_batch_x_lines.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_float)]
         L.sscn_density.argtypes = [vp, ctypes.c_int, vp]
         L.sscn_embed_state.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int,
                                        ctypes.c_int, ctypes.c_int, vp]
@@ -515,7 +516,10 @@ class Batch:
     def info(self):
         pl, w = ctypes.c_int(), ctypes.c_int()
         _check(lib().sscn_batch_info(self._h, ctypes.byref(pl), ctypes.byref(w)))
-        return {"plan": int(pl.value), "window": int(w.value)}
+        xo, xt = ctypes.c_int(), (ctypes.c_float * 2)()
+        _check(lib().sscn_batch_x_lines(self._h, ctypes.byref(xo), xt))
+        return {"plan": int(pl.value), "window": int(w.value), "x_lines_option": int(xo.value),
+                "x_lines_tune_ms": [float(xt[0]), float(xt[1])]}
 
     def set_state_device(self, k):
         """Instance k's tensor self.psi[k] was written in place: zero its

@@ -42,6 +42,17 @@ constexpr int kTileR = SSCN_TILE_R;   // fused 2D step: output tile rows (y)
 constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
 constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
 constexpr size_t kXLdsCap = 150 * 1024;  // dynamic LDS of an x-sweep block
+// Dynamic LDS of a batched x-sweep block at most (bytes) under the capped
+// lines-per-block option: every instance's lines per block are halved until
+// its staging fits, so that the launch (which reserves the largest
+// instance's LDS for every block) holds four blocks of 256 threads per CU in
+// the 160 KiB.  Halving leaves some of a block's threads without a segment
+// to solve, so the batch autotuner times both options.  SSCN_BATCH_XLDS
+// overrides the cap.
+#ifndef SSCN_BATCH_XLDS
+#define SSCN_BATCH_XLDS 40960
+#endif
+constexpr size_t kBatchXLds = SSCN_BATCH_XLDS;
 // Infinity Cache budget of a group of batched instances (both state
 // buffers), MiB; SSCN_BATCH_GROUP_MB overrides it.  0 (the default) puts
 // every instance in one group: on the 64-instance complex128 workload (309
@@ -179,6 +190,15 @@ struct sscn_batch {
     int plan = SSCN_PLAN_AUTO, active_plan = SSCN_PLAN_FUSED;
     bool sweeps_ok = true;
     bool xshort = true;  // every instance has nx * L <= 2048: 8 staged points per x-sweep thread
+    // x-sweep lines per block of every instance under the two options: 0 the
+    // most the segment count and staging allow, 1 capped at kBatchXLds of LDS
+    // per block; xsel the option in use, xforce one forced by
+    // SSCN_BATCH_XLINES (-1: none), xtuned once the autotuner has timed them
+    std::vector<int> xl_opt[2];
+    int xsel = 1, xforce = -1;
+    bool xtuned = false;
+    float tune_x_ms[2] = {0, 0};
+    int xwork_cap = 0;  // entries of d_xwork (the larger option's list)
     std::vector<int> xitems, yitems;
     int total_x = 0, total_y = 0, grid_x = 0, grid_y = 0, grid_k = 0;
     size_t xlds = 0;

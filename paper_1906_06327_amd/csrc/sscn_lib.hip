@@ -35,6 +35,15 @@ constexpr int kConvBox = 3;
             return fail(SSCN_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));   \
     } while (0)
 
+// Events that time kernels between them: without the system-scope fence of
+// a default event, whose cache write-back and invalidation at every record
+// would slow the kernel that follows and add to the measured durations.  The
+// host reads them only after synchronising with the stream or the event.
+hipError_t timing_event(hipEvent_t *e)
+{
+    return hipEventCreateWithFlags(e, hipEventDisableSystemFence);
+}
+
 int64_t npoints(const sscn_params &p)
 {
     return (int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
@@ -679,6 +688,10 @@ void release_step_buffers(sscn_handle *h)
 // ---------------------------------------------------------------------------
 // Batched 2D instances (one fused launch per step over all their tiles).
 
+void batch_group_offsets(sscn_batch *b);
+int batch_lists(sscn_batch *b, bool all_for_obs = false);
+void batch_drop_graph(sscn_batch *b);
+
 // Groups of the sweep plan (sscn_batch::group): G = ceil(bytes / budget)
 // groups, where bytes counts both state buffers of every instance, filled
 // largest instance first into the group with the fewest bytes so far.  Each
@@ -711,6 +724,14 @@ void batch_groups(sscn_batch *b, size_t esize)
         load[g] += bytes[k];
     }
     b->ngroups = G;
+    batch_group_offsets(b);
+}
+
+// Each group's region of the x and y work lists from the instances' item
+// counts.
+void batch_group_offsets(sscn_batch *b)
+{
+    const int G = b->ngroups;
     b->gx_tot.assign(G, 0);
     b->gy_tot.assign(G, 0);
     for (int k = 0; k < b->n; ++k) {
@@ -727,9 +748,53 @@ void batch_groups(sscn_batch *b, size_t esize)
     b->gy_cnt = b->gy_tot;
 }
 
+// Dynamic LDS of a batched x-sweep block of instance k with L lines: the
+// padded lines, their pivot-table rows and wall terms.
+size_t batch_x_lds(const sscn_batch *b, int k, int L)
+{
+    const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
+    const size_t LS = (size_t)x_row_len(b->p[k].nx, kSegX, b->W);
+    return ((size_t)L * LS + (size_t)L * (b->W + 2) + L) * esize;
+}
+
+// x-sweep work items (line blocks) of instance k with L lines per block.
+int batch_x_items(const sscn_batch *b, int k, int L)
+{
+    const int lines = b->p[k].ny * (b->dim3 ? b->p[k].nz : 1);
+    return (lines + L - 1) / L;
+}
+
+// Put the x-sweep's lines-per-block option sel in force: every instance's
+// L, the x work items and group regions, the launch's LDS and staging width
+// (before the device buffers exist, host state only; after, also the
+// instance descriptors and work lists on the device, and the captured
+// graphs, whose launches carry the old grid and LDS, are dropped).
+int batch_xlines(sscn_batch *b, int sel)
+{
+    b->xsel = sel;
+    b->xlds = 0;
+    b->xshort = true;
+    b->total_x = 0;
+    for (int k = 0; k < b->n; ++k) {
+        const int L = b->xl_opt[sel][k];
+        b->hinst[k].xl = L;
+        b->xitems[k] = batch_x_items(b, k, L);
+        b->total_x += b->xitems[k];
+        b->xlds = std::max(b->xlds, batch_x_lds(b, k, L));
+        if ((int64_t)b->p[k].nx * L > 256 * 8)
+            b->xshort = false;
+    }
+    batch_group_offsets(b);
+    if (!b->d_inst)
+        return 0;
+    batch_drop_graph(b);
+    HIPCHECK(hipMemcpy(b->d_inst, b->hinst.data(), sizeof(Inst2D) * b->n, hipMemcpyHostToDevice));
+    return batch_lists(b);
+}
+
 // Upload the work lists of the active instances: tiles (largest instances
 // first), finish chunks and observable chunks with each instance's range.
-int batch_lists(sscn_batch *b, bool all_for_obs = false)
+int batch_lists(sscn_batch *b, bool all_for_obs)
 {
     std::vector<int> order(b->n);
     for (int k = 0; k < b->n; ++k)
@@ -967,71 +1032,138 @@ void batch_obs_launch(sscn_batch *b, int nchunks, double tol)
     }
 }
 
-// The first stepping call of an SSCN_PLAN_AUTO batch times 8 steps of each
-// plan from a saved copy of every state, restores the states and keeps the
-// faster plan.
-int batch_autotune(sscn_batch *b)
+// Time 8 steps of the batch as it stands (plan, x option) for the
+// autotuner: one untimed step first (the first launch of a kernel also
+// loads its code object), then the states restored from saved, the timed
+// steps, and the states restored again.
+int batch_time_steps(sscn_batch *b, const char *saved, const std::vector<size_t> &off, float *ms)
 {
-    if (b->plan != SSCN_PLAN_AUTO)
-        return 0;
-    b->plan = b->active_plan = SSCN_PLAN_FUSED;
-    if (!b->sweeps_ok)
-        return 0;
-    const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
-    std::vector<size_t> off(b->n + 1, 0);
-    for (int k = 0; k < b->n; ++k)
-        off[k + 1] = off[k] + (size_t)b->p[k].nx * b->p[k].ny * esize;
-    char *saved = nullptr;
-    if (hipMalloc(&saved, off[b->n]) != hipSuccess)
-        return fail(SSCN_ENOMEM, "hipMalloc of the batch autotune copy failed");
-    for (int k = 0; k < b->n; ++k)
-        HIPCHECK(hipMemcpyAsync(saved + off[k], b->psi[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice, b->stream));
-    const int plans[2] = {SSCN_PLAN_FUSED, SSCN_PLAN_SWEEPS};
-    float best = 0.f;
-    for (int t = 0; t < 2; ++t) {
-        b->active_plan = plans[t];
-        b->pending = false;
-        b->fparity = 0;
-        b->pbuf = 0;
-        // one untimed step first: the first launch of a kernel also loads its
-        // code object, which must not count against the plan
-        if (b->precision == SSCN_C128)
-            batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
-        else
-            batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
+    auto restore = [&]() -> int {
         for (int k = 0; k < b->n; ++k)
             HIPCHECK(hipMemcpyAsync(b->psi[k], saved + off[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice,
                                     b->stream));
-        hipEvent_t e0, e1;
-        (void)hipEventCreate(&e0);
-        (void)hipEventCreate(&e1);
+        return 0;
+    };
+    b->pending = false;
+    b->fparity = 0;
+    b->pbuf = 0;
+    if (b->precision == SSCN_C128)
+        batch_enqueue<double>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
+    else
+        batch_enqueue<float>(b, 1, b->stream, b->grid_tiles, b->grid_chunks, false);
+    int rc = restore();
+    if (rc)
+        return rc;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (timing_event(&e0) != hipSuccess || timing_event(&e1) != hipSuccess)
+        rc = fail(SSCN_EHIP, "hipEventCreate failed");
+    if (!rc) {
         (void)hipEventRecord(e0, b->stream);
         if (b->precision == SSCN_C128)
             batch_enqueue<double>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, false);
         else
             batch_enqueue<float>(b, 8, b->stream, b->grid_tiles, b->grid_chunks, false);
         (void)hipEventRecord(e1, b->stream);
-        (void)hipEventSynchronize(e1);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        b->tune_ms[plans[t]] = ms;
-        if (t == 0 || ms < best) {
-            best = ms;
-            b->plan = plans[t];
-        }
-        for (int k = 0; k < b->n; ++k)
-            HIPCHECK(hipMemcpyAsync(b->psi[k], saved + off[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice,
-                                    b->stream));
+        *ms = 0.f;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            rc = fail(SSCN_EHIP, "event timing failed");
     }
-    HIPCHECK(hipStreamSynchronize(b->stream));
+    if (e0)
+        (void)hipEventDestroy(e0);
+    if (e1)
+        (void)hipEventDestroy(e1);
+    return rc ? rc : restore();
+}
+
+// The first stepping call of a batch times its candidates from a saved copy
+// of every state, restores the states and keeps the fastest.  The
+// candidates: with SSCN_PLAN_AUTO the fused step and the sweep plan; with
+// the sweep plan (chosen or forced) its two x-sweep lines-per-block options
+// (sscn_batch::xl_opt), unless they coincide or SSCN_BATCH_XLINES fixes
+// one.  Every candidate is timed twice, in turn, and keeps its faster time,
+// so that a clock still rising during the first round does not favour the
+// later candidates.
+int batch_autotune(sscn_batch *b)
+{
+    const bool plan_auto = b->plan == SSCN_PLAN_AUTO;
+    if (plan_auto)
+        b->plan = b->active_plan = SSCN_PLAN_FUSED;
+    if (!b->sweeps_ok)
+        return 0;
+    const bool tune_x = !b->xtuned && b->xforce < 0 && b->xl_opt[0] != b->xl_opt[1];
+    if (!plan_auto && !(tune_x && b->plan == SSCN_PLAN_SWEEPS))
+        return 0;
+    struct Cand {
+        int plan, xsel;
+    };
+    std::vector<Cand> cand;
+    if (plan_auto)
+        cand.push_back({SSCN_PLAN_FUSED, b->xsel});
+    if (tune_x) {
+        cand.push_back({SSCN_PLAN_SWEEPS, 0});
+        cand.push_back({SSCN_PLAN_SWEEPS, 1});
+    } else {
+        cand.push_back({SSCN_PLAN_SWEEPS, b->xsel});
+    }
+    const size_t esize = b->precision == SSCN_C128 ? 16 : 8;
+    std::vector<size_t> off(b->n + 1, 0);
+    for (int k = 0; k < b->n; ++k)
+        off[k + 1] = off[k] + (size_t)b->p[k].nx * b->p[k].ny * (b->dim3 ? b->p[k].nz : 1) * esize;
+    char *saved = nullptr;
+    if (hipMalloc(&saved, off[b->n]) != hipSuccess)
+        return fail(SSCN_ENOMEM, "hipMalloc of the batch autotune copy failed");
+    int rc = 0;
+    for (int k = 0; k < b->n && !rc; ++k)
+        if (hipMemcpyAsync(saved + off[k], b->psi[k], off[k + 1] - off[k], hipMemcpyDeviceToDevice, b->stream) !=
+            hipSuccess)
+            rc = fail(SSCN_EHIP, "hipMemcpyAsync of the batch autotune copy failed");
+    std::vector<float> best(cand.size(), INFINITY);
+    for (int rep = 0; rep < 2 && !rc; ++rep)
+        for (size_t c = 0; c < cand.size() && !rc; ++c) {
+            b->active_plan = cand[c].plan;
+            if (cand[c].plan == SSCN_PLAN_SWEEPS && b->xsel != cand[c].xsel)
+                rc = batch_xlines(b, cand[c].xsel);
+            float ms = 0.f;
+            if (!rc)
+                rc = batch_time_steps(b, saved, off, &ms);
+            best[c] = std::min(best[c], ms);
+        }
+    if (!rc && hipStreamSynchronize(b->stream) != hipSuccess)
+        rc = fail(SSCN_EHIP, "the batch autotune steps failed");
     (void)hipFree(saved);
-    HIPCHECK(hipGetLastError());
+    if (rc)
+        return rc;
+    size_t win = 0, xwin = 0;
+    bool have_x = false;
+    b->tune_ms[SSCN_PLAN_FUSED] = b->tune_ms[SSCN_PLAN_SWEEPS] = 0.f;
+    for (size_t c = 0; c < cand.size(); ++c) {
+        if (best[c] < best[win])
+            win = c;
+        if (cand[c].plan == SSCN_PLAN_SWEEPS) {
+            b->tune_x_ms[cand[c].xsel] = best[c];
+            if (!have_x || best[c] < best[xwin])
+                xwin = c;
+            have_x = true;
+        }
+        float &tm = b->tune_ms[cand[c].plan];
+        tm = tm > 0.f ? std::min(tm, best[c]) : best[c];
+    }
+    if (tune_x)
+        b->xtuned = true;
+    // the faster x option stays in force, also when the fused plan wins (for
+    // a later sscn_batch_set_plan)
+    if (have_x && b->xsel != cand[xwin].xsel) {
+        rc = batch_xlines(b, cand[xwin].xsel);
+        if (rc)
+            return rc;
+    }
+    if (plan_auto)
+        b->plan = cand[win].plan;
     b->active_plan = b->plan;
     b->pending = false;
     b->fparity = 0;
     b->pbuf = 0;
+    HIPCHECK(hipGetLastError());
     return 0;
 }
 
@@ -1671,7 +1803,7 @@ int sscn_profile_step(sscn_handle *h, int64_t nsteps, double *ms_out)
     std::vector<hipEvent_t> ev((size_t)nsteps * 4, nullptr);
     int rc = 0;
     for (auto &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (timing_event(&e) != hipSuccess) {
             rc = fail(SSCN_EHIP, "hipEventCreate failed");
             break;
         }
@@ -1790,7 +1922,7 @@ int profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms)
     launch(true);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = 0;
-    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    if (timing_event(&e0) != hipSuccess || timing_event(&e1) != hipSuccess)
         rc = fail(SSCN_EHIP, "hipEventCreate failed");
     if (!rc) {
         (void)hipEventRecord(e0, h->stream);
@@ -2050,14 +2182,16 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         int L = std::max(1, std::min({256 / nseg, 256 * kXLoad / h.p.nx, 512 / (b->W + 2)}));
         while (L & (L - 1))
             L &= L - 1;
-        const size_t LS = (size_t)x_row_len(h.p.nx, kSegX, b->W);
-        const size_t xl = (L * LS + (size_t)L * (b->W + 2) + L) * esize;
-        if (nseg > 256 || h.p.nx > 256 * kXLoad || xl > kXLdsCap)
+        int Lc = L;  // the capped option
+        while (Lc > 1 && batch_x_lds(b, k, Lc) > kBatchXLds)
+            Lc >>= 1;
+        if (nseg > 256 || h.p.nx > 256 * kXLoad || batch_x_lds(b, k, Lc) > kXLdsCap)
             b->sweeps_ok = false;
-        if ((int64_t)h.p.nx * L > 256 * 8)
-            b->xshort = false;
-        b->xlds = std::max(b->xlds, xl);
-        in.xl = L;
+        if (batch_x_lds(b, k, L) > kXLdsCap)
+            L = Lc;
+        b->xl_opt[0].push_back(L);
+        b->xl_opt[1].push_back(Lc);
+        in.xl = Lc;  // set with the work lists by batch_xlines
         in.ygx = (h.p.nx + kYLines - 1) / kYLines;
         in.ygy = ((h.p.ny - 2) / kSeg + 1 + kSegBlock - 1) / kSegBlock;
         in.ypoff = ypoff;
@@ -2065,7 +2199,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         // z-sweep emits the norm partials (offsets shifted past the y ones
         // below), in 2D the y-sweep
         const int planes = b->dim3 ? h.p.nz : 1;
-        b->xitems.push_back((h.p.ny * planes + L - 1) / L);
+        b->xitems.push_back(0);
         b->yitems.push_back(in.ygx * in.ygy * planes);
         ypoff += in.ygx * in.ygy * planes;
         in.zgx = in.zgy = 0;
@@ -2081,7 +2215,6 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
             zoff += in.zgx * in.zgy;
         }
         b->zitems.push_back(in.zgx * in.zgy);
-        b->total_x += b->xitems.back();
         b->total_y += b->yitems.back();
         b->total_z += b->zitems.back();
         b->hinst.push_back(in);
@@ -2098,7 +2231,16 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
             in.zpoff += ypoff;
             in.eoff = in.zpoff;
         }
+    if (const char *e = std::getenv("SSCN_BATCH_XLINES"))
+        b->xforce = (e[0] == '0') ? 0 : (e[0] == '1') ? 1 : -1;
+    for (int o = 0; o < 2; ++o) {
+        int64_t items = 0;
+        for (int k = 0; k < n; ++k)
+            items += batch_x_items(b, k, b->xl_opt[o][k]);
+        b->xwork_cap = (int)std::max<int64_t>(b->xwork_cap, items);
+    }
     batch_groups(b, esize);
+    batch_xlines(b, b->xforce >= 0 ? b->xforce : 1);
     const size_t nopart = std::max((size_t)b->total_chunks * kObsN, (size_t)kRedBlocks);
     if (hipMalloc(&b->d_inst, sizeof(Inst2D) * n) != hipSuccess ||
         hipMalloc(&b->d_work, sizeof(int2) * b->total_tiles) != hipSuccess ||
@@ -2117,7 +2259,7 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
         hipMalloc(&b->d_counts, sizeof(int) * n) != hipSuccess ||
         hipMalloc(&b->vpart, sizeof(double) * std::max(b->total_chunks, 1)) != hipSuccess ||
         hipMalloc(&b->d_conv, sizeof(long long) * n) != hipSuccess ||
-        hipMalloc(&b->d_xwork, sizeof(int2) * std::max(b->total_x, 1)) != hipSuccess ||
+        hipMalloc(&b->d_xwork, sizeof(int2) * std::max(b->xwork_cap, 1)) != hipSuccess ||
         hipMalloc(&b->d_ywork, sizeof(int2) * std::max(b->total_y, 1)) != hipSuccess ||
         hipMalloc(&b->d_nx, sizeof(int) * b->ngroups) != hipSuccess ||
         hipMalloc(&b->d_ny, sizeof(int) * b->ngroups) != hipSuccess ||
@@ -2246,7 +2388,7 @@ int sscn_batch_profile_step(sscn_batch *b, int64_t nsteps, double *ms_out)
     std::vector<hipEvent_t> ev((size_t)nrec * 4, nullptr);
     int rc = 0;
     for (auto &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
+        if (timing_event(&e) != hipSuccess) {
             rc = fail(SSCN_EHIP, "hipEventCreate failed");
             break;
         }
@@ -2470,6 +2612,18 @@ int sscn_batch_set_plan(sscn_batch *b, int plan)
         plan = SSCN_PLAN_SWEEPS;
     b->plan = plan;
     b->active_plan = plan == SSCN_PLAN_SWEEPS ? SSCN_PLAN_SWEEPS : SSCN_PLAN_FUSED;
+    return 0;
+}
+
+int sscn_batch_x_lines(sscn_batch *b, int *option, float *tune_ms)
+{
+    if (!b || !option)
+        return fail(SSCN_EINVAL, "null argument");
+    *option = b->xsel;
+    if (tune_ms) {
+        tune_ms[0] = b->tune_x_ms[0];
+        tune_ms[1] = b->tune_x_ms[1];
+    }
     return 0;
 }
 

@@ -178,6 +178,65 @@ def test_batch_groups_give_the_same_bits(P, prec, monkeypatch):
     bb.close()
 
 
+def x_option_runs(P, cfgs, monkeypatch, seed0):
+    """States, convergence steps and observables of the same stepping under
+    each x-sweep lines-per-block option (SSCN_BATCH_XLINES), and the
+    autotuner's times with neither forced."""
+    res = {}
+    for opt in ("0", "1"):
+        monkeypatch.setenv("SSCN_BATCH_XLINES", opt)
+        b = P.Batch(cfgs)
+        b.set_plan(1)
+        for k, c in enumerate(cfgs):
+            b.init_state(k, 1, W.phase_field(seed0 + k, c["ny"], c["nx"]), 1.0)
+        b.step(1)
+        b.step(37)
+        st = b.run(3000, check_every=100, tol=1e-5)
+        info = b.info()
+        assert info["x_lines_option"] == int(opt) and info["x_lines_tune_ms"] == [0.0, 0.0]
+        res[opt] = ([b.get_state(k) for k in range(len(cfgs))], list(st), b.observables())
+        b.close()
+    monkeypatch.delenv("SSCN_BATCH_XLINES")
+    b = P.Batch(cfgs)
+    b.set_plan(1)
+    for k, c in enumerate(cfgs):
+        b.init_state(k, 1, W.phase_field(seed0 + k, c["ny"], c["nx"]), 1.0)
+    b.step(1)
+    tune = b.info()["x_lines_tune_ms"]
+    b.close()
+    return res, tune
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_x_options_give_the_same_bits(P, prec, monkeypatch):
+    """The batched x-sweep's two lines-per-block options (the most lines a
+    block can stage, or that number halved until the block's LDS is at most
+    40 KiB) only regroup whole lines into blocks, so they give the same bits,
+    over direct steps, graph-replayed steps and a convergence run with
+    drop-out, in 2D and in 3D (where the x-sweep works in place).  With
+    neither forced, the autotuner times both where they differ (complex128:
+    W = 13 puts the 16-line blocks of nx = 100, 128, 129 above 40 KiB) and
+    neither where they coincide (complex64: W = 6, every block below)."""
+    print(f"[gpu-batch] x options prec={prec}", flush=True)
+    cfgs = mixed(prec, 0)
+    res, tune = x_option_runs(P, cfgs, monkeypatch, 60)
+    for k in range(len(cfgs)):
+        assert np.array_equal(res["0"][0][k], res["1"][0][k]), k
+    assert res["0"][1] == res["1"][1]
+    assert res["0"][2] == res["1"][2]
+    if prec == 0:
+        assert tune[0] > 0 and tune[1] > 0, tune
+    else:
+        assert tune == [0.0, 0.0], tune
+    if prec == 0:
+        c3 = [dict(c, nx=128 + 8 * t, ny=20 + 4 * t) for t, c in enumerate(mixed3d(0, 0)[:2])]
+        res3, tune3 = x_option_runs(P, c3, monkeypatch, 70)
+        for k in range(len(c3)):
+            assert np.array_equal(res3["0"][0][k], res3["1"][0][k]), k
+        assert res3["0"][1] == res3["1"][1]
+        assert tune3[0] > 0 and tune3[1] > 0, tune3
+
+
 def mixed3d(prec, mode=0):
     shapes = [(24, 20, 12), (32, 16, 10), (20, 28, 14)]
     out = []
