@@ -885,8 +885,11 @@ static __global__ __launch_bounds__(256) void k_norm_scale(const double *partial
 // block writes the FP64 partial sum of |psi'|^2 of its outputs at its
 // logical block index.  Grid: 1-D, rounded up to a multiple of 8 logical
 // blocks (gx line tiles x gy segment groups x gz planes).
-constexpr int kYLines = 32;
-constexpr int kSegBlock = 8;
+#ifndef SSCN_Y_LINES
+#define SSCN_Y_LINES 32
+#endif
+constexpr int kYLines = SSCN_Y_LINES;
+constexpr int kSegBlock = 256 / kYLines;
 static_assert(kYLines * kSegBlock == 256, "strided sweep blocks have 256 threads");
 
 template <class R, int S, int W, bool NT = false>
@@ -2170,15 +2173,18 @@ static __global__ __launch_bounds__(256) void k_batch_scale(const Inst2D *__rest
     }
 }
 
-// One work-list item (instance, first line) per block.  With use_scale the
+// One work-list item (instance, first line) per block.  use_scale = 1: the
 // pending rescale of the instance is formed here, from the norm partials the
-// previous y-sweep left at partials[I.ypoff ..] (every wave sums them in
-// the fixed order of wave_partials_sum while its state loads are in flight,
-// so every block, and the finish pass, gets the same bits).
+// previous step's last sweep left at partials[I.eoff ..] (every wave sums
+// them in the fixed order of wave_partials_sum while its state loads are in
+// flight, so every block, and the finish pass, gets the same bits); 2: it
+// is read from scale[instance], where k_batch_scale left it (the same sum,
+// once per instance, for instances with many partials); 0: none.
 template <class R, int S, int W, bool RT, int KX>
 __global__ __launch_bounds__(256, kSweepWaves) void k_batch_xsweep(const Inst2D *__restrict__ insts, const int2 *__restrict__ xwork,
                                                       const int *__restrict__ nitems,
-                                                      const double *__restrict__ partials, int use_scale)
+                                                      const double *__restrict__ partials, int use_scale,
+                                                      const double *__restrict__ scale)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int it = blockIdx.x;
@@ -2190,7 +2196,9 @@ __global__ __launch_bounds__(256, kSweepWaves) void k_batch_xsweep(const Inst2D 
     XStage<R, KX> g;
     xsweep_load<R, S, W, KX, kBatchStream>(reinterpret_cast<const typename Vec<R>::T *>(I.buf[0]), a, I.xl,
                                    reinterpret_cast<const Cx<R> *>(I.tab[0]), wk.y, g);
-    const double sm1 = use_scale ? norm_scale_m1(wave_partials_sum(partials + I.eoff, I.ecount), I.dV) : 0.0;
+    const double sm1 = use_scale == 1   ? norm_scale_m1(wave_partials_sum(partials + I.eoff, I.ecount), I.dV)
+                       : use_scale == 2 ? scale[wk.x]
+                                        : 0.0;
     // 2D: buf[0] -> buf[1]; 3D: in place (a block loads its lines whole
     // before it writes them), so that the y- and z-sweeps end in buf[0]
     xsweep_finish<R, S, W, RT, KX, kBatchStream>(reinterpret_cast<typename Vec<R>::T *>(I.buf[I.nz > 1 ? 0 : 1]), a,

@@ -53,6 +53,15 @@ constexpr size_t kXLdsCap = 150 * 1024;  // dynamic LDS of an x-sweep block
 #define SSCN_BATCH_XLDS 40960
 #endif
 constexpr size_t kBatchXLds = SSCN_BATCH_XLDS;
+// Norm partials of an instance above which the batched x-sweep reads its
+// pending rescale from a per-instance reduction (k_batch_scale) instead of
+// summing the partials in every block: each wave of an x-sweep block reads
+// all of them, which for the 2048 z tiles of a 256 x 256 x 64 instance is
+// four times the block's own state.
+#ifndef SSCN_BATCH_PRESCALE
+#define SSCN_BATCH_PRESCALE 256
+#endif
+constexpr int kBatchPrescale = SSCN_BATCH_PRESCALE;
 // Infinity Cache budget of a group of batched instances (both state
 // buffers), MiB; SSCN_BATCH_GROUP_MB overrides it.  0 (the default) puts
 // every instance in one group: on the 64-instance complex128 workload (309
@@ -212,6 +221,10 @@ struct sscn_batch {
     std::vector<int> group;  // group of each instance
     std::vector<int> gx_off, gx_tot, gx_cnt, gy_off, gy_tot, gy_cnt;
     double *ypart = nullptr, *d_scale = nullptr;
+    // the pending rescale is summed once per instance (k_batch_scale) before
+    // the x-sweep instead of in every x-sweep block: some instance has more
+    // than kBatchPrescale norm partials
+    bool prescale = false;
     float tune_ms[3] = {0, 0, 0};
     // 3D instances (sweep plan): the z-sweep's window, tables and work list
     bool dim3 = false;

@@ -193,10 +193,12 @@ void go_batch_x(const sscn_batch *b, int g, int grid, int use_scale, hipStream_t
     const int2 *work = b->d_xwork + b->gx_off[g];
     if (b->xshort)
         hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, 8>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, work, b->d_nx + g, (const double *)b->ypart, use_scale);
+                           b->d_inst, work, b->d_nx + g, (const double *)b->ypart, use_scale,
+                           (const double *)b->d_scale);
     else
         hipLaunchKernelGGL((k_batch_xsweep<R, kSegX, W, RT, kXLoad>), dim3(std::max(grid, 1)), dim3(256), b->xlds, st,
-                           b->d_inst, work, b->d_nx + g, (const double *)b->ypart, use_scale);
+                           b->d_inst, work, b->d_nx + g, (const double *)b->ypart, use_scale,
+                           (const double *)b->d_scale);
 }
 
 template <class R, int W, bool EMIT>
@@ -217,9 +219,12 @@ void go_batch_z(const sscn_batch *b, int grid, hipStream_t st)
 // One step of the sweep plan for the listed instances of group g (state in
 // buf[0]); all: launch grids covering every instance of the group (graph
 // capture), else the current list lengths.  The x-sweep forms the pending
-// rescale itself.  A batch of 3D instances adds the z-sweep.  ev
-// (optional, 4 events): recorded before the x-sweep, before the y-sweep,
-// after it (before the z-sweep) and at the end of the step.
+// rescale itself, or, where an instance has many norm partials
+// (sscn_batch::prescale), reads it from k_batch_scale, which sums them once
+// per instance first.  A batch of 3D instances adds the z-sweep.  ev
+// (optional, 4 events): recorded before the rescale reduction and x-sweep,
+// before the y-sweep, after it (before the z-sweep) and at the end of the
+// step.
 template <class R>
 void batch_sweep_step(sscn_batch *b, hipStream_t st, int g, bool all, hipEvent_t *ev)
 {
@@ -230,8 +235,13 @@ void batch_sweep_step(sscn_batch *b, hipStream_t st, int g, bool all, hipEvent_t
             (void)hipEventRecord(ev[t], st);
     };
     const bool imag = b->mode == SSCN_IMAG;
-    const int sc = (imag && b->pending) ? 1 : 0;
+    const int sc = (imag && b->pending) ? (b->prescale ? 2 : 1) : 0;
     mark(0);
+    if (sc == 2) {
+        const int grid_k = all ? b->n : b->grid_k;
+        hipLaunchKernelGGL(k_batch_scale, dim3(std::max(grid_k, 1)), dim3(256), 0, st, b->d_inst, b->d_klist, b->d_nk,
+                           (const double *)b->ypart, b->d_scale);
+    }
 #define SSCN_CALL_BX(Wc)                                 \
     do {                                                 \
         if (imag)                                        \

@@ -2231,6 +2231,9 @@ int sscn_batch_init(const sscn_params *params, int n, void *const *psi_devs, voi
             in.zpoff += ypoff;
             in.eoff = in.zpoff;
         }
+    for (const auto &in : b->hinst)
+        if (in.ecount > kBatchPrescale)
+            b->prescale = true;
     if (const char *e = std::getenv("SSCN_BATCH_XLINES"))
         b->xforce = (e[0] == '0') ? 0 : (e[0] == '1') ? 1 : -1;
     for (int o = 0; o < 2; ++o) {

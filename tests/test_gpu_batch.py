@@ -247,6 +247,35 @@ def mixed3d(prec, mode=0):
     return out
 
 
+@pytest.mark.parametrize("prec", [0, 1])
+def test_batch_3d_rescale_summed_per_instance(P, prec):
+    """An instance with more than 256 norm partials (96 x 88 x 10: 264 z
+    tiles) makes the batch sum each instance's partials once per step before
+    the x-sweep (k_batch_scale) instead of in every x-sweep block; the steps
+    and the observables still follow the oracle instance by instance."""
+    print(f"[gpu-batch] 3D per-instance rescale sum prec={prec}", flush=True)
+    big = dict(mixed3d(prec)[0], nx=96, ny=88, nz=10, hx=0.25, hy=0.25, hz=0.3)
+    cfgs = mixed3d(prec)[:2] + [big]
+    b = P.Batch(cfgs)
+    refs = []
+    for k, c in enumerate(cfgs):
+        ph = W.phase_field(80 + k, c["ny"], c["nx"])
+        b.init_state(k, 1, ph, 1.0)
+        op = O.make_params(**c)
+        refs.append((op, O.init_state(op, 1, ph, 1.0)))
+    b.step(1)
+    b.step(30)
+    tol = 1e-10 if prec == 0 else 1e-5
+    obs = b.observables()
+    for k, (op, r0) in enumerate(refs):
+        ref = O.step(op, r0, 31)
+        assert rel(b.get_state(k).astype(np.complex128), ref) <= tol, k
+        oo = O.observables(op, ref)
+        for key in ("norm", "mu", "energy"):
+            assert abs(obs[k][key] - oo[key]) <= tol * max(1.0, abs(oo[key])), (k, key)
+    b.close()
+
+
 @pytest.mark.parametrize("prec,mode", [(0, 0), (0, 1), (1, 0)])
 def test_batch_3d_matches_oracle_per_instance(P, prec, mode):
     """A batch of 3D instances of different shapes and parameters (x-, y-
