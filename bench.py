@@ -318,7 +318,8 @@ def kernel_roofline(s, cfg, step_ms, nlaunch=200):
     back-to-back launches between two HIP events on the solver's stream
     (sscn_profile_kernel).  Algorithmic bytes: 2 c per point per axis sweep
     the kernel performs."""
-    plan = s.solver_info()["plan"]
+    info = s.solver_info()
+    plan = info["plan"]
     dim = cfg["dim"]
     pts = cfg["nx"] * cfg["ny"] * (cfg["nz"] if dim == 3 else 1)
     esize = 16 if cfg.get("precision", 0) == 0 else 8
@@ -333,7 +334,8 @@ def kernel_roofline(s, cfg, step_ms, nlaunch=200):
     return {"bound": "hbm", "achieved": round(gbs, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
             "frac": round(gbs / PEAK_HBM_GBS, 4),
             "kernel": "fused 2D step (H1 + x + y)" if plan == 2 else f"{dom}-sweep",
-            "plan": {1: "sweeps", 2: "fused"}.get(plan, plan), "bytes_per_launch": per_launch,
+            "plan": {1: "sweeps", 2: "fused"}.get(plan, plan),
+            "tile": info["fused_tile"] if plan == 2 else None, "bytes_per_launch": per_launch,
             "kernel_ms": {k: round(v, 6) for k, v in ms.items()},
             "timing": "events around the timed steps" if plan == 2 else "events around back-to-back launches"}
 

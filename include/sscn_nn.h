@@ -68,9 +68,12 @@ int sscn_nn_conv3x3_wgrad(const void *x, int N, int H, int W, int Cin, const voi
  * layer's output y. */
 int sscn_nn_act_bwd(void *dy, const void *y, int64_t n, void *stream);
 
-/* 2x2 average pooling (H, W even; y is N x H/2 x W/2 x C) and its gradient
- * (dy is N x H/2 x W/2 x C, dx is N x H x W x C). */
-int sscn_nn_pool2(const void *x, int N, int H, int W, int C, void *y, void *stream);
+/* 2x2 average pooling (H, W even; y is N x H/2 x W/2 x C) of channels
+ * xoff .. xoff + C - 1 of x, whose pixels are ldx >= xoff + C channels apart
+ * (x may be a channel slice of a wider tensor, such as the decoder's
+ * concatenation buffer that the encoder's last convolution writes into),
+ * and its gradient (dy is N x H/2 x W/2 x C, dx is N x H x W x C). */
+int sscn_nn_pool2(const void *x, int ldx, int xoff, int N, int H, int W, int C, void *y, void *stream);
 int sscn_nn_pool2_bwd(const void *dy, int N, int H, int W, int C, void *dx, void *stream);
 
 /* Nearest 2x upsampling of x (N x H x W x C) into a channel slice of y

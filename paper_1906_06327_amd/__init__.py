@@ -24,7 +24,7 @@ ERRORS = {0: "SSCN_OK", -1: "SSCN_EINVAL", -2: "SSCN_EOMEGA", -3: "SSCN_EUNSTABL
 EXPORTS = ("sscn_init", "sscn_init_state", "sscn_init_state_seed", "sscn_phase_field_seed", "sscn_step", "sscn_prepare_steps", "sscn_observables", "sscn_observables_noalloc",
            "sscn_set_state", "sscn_set_state_device", "sscn_get_state",
            "sscn_set_mode", "sscn_vortex_count", "sscn_profile_step", "sscn_set_plan",
-           "sscn_solver_info", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step", "sscn_batch_prepare_steps", "sscn_batch_profile_step",
+           "sscn_solver_info", "sscn_fused_tile", "sscn_profile_kernel", "sscn_converge", "sscn_get_params", "sscn_batch_init", "sscn_batch_init_state", "sscn_batch_step", "sscn_batch_prepare_steps", "sscn_batch_profile_step",
            "sscn_batch_observables", "sscn_batch_run", "sscn_batch_reset", "sscn_batch_get_state",
            "sscn_batch_set_state_device", "sscn_batch_vortex_count", "sscn_batch_set_plan",
            "sscn_batch_info", "sscn_batch_x_lines", "sscn_batch_destroy", "sscn_embed_state", "sscn_extend_z", "sscn_density", "sscn_resample",
@@ -83,6 +83,7 @@ def lib():
         L.sscn_vortex_count.argtypes = [vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
         L.sscn_solver_info.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int),
                                        ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
+        L.sscn_fused_tile.argtypes = [vp, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]
         L.sscn_set_plan.argtypes = [vp, ctypes.c_int]
         L.sscn_profile_step.argtypes = [vp, i64, ctypes.POINTER(ctypes.c_double)]
         L.sscn_profile_kernel.argtypes = [vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -419,7 +420,10 @@ class Solver:
         pl = ctypes.c_int()
         xl = ctypes.c_int()
         _check(lib().sscn_solver_info(self._h, w, s, ctypes.byref(pl), ctypes.byref(xl)))
-        return {"window": list(w), "segment": list(s), "plan": int(pl.value), "x_lines": int(xl.value)}
+        tr, tc = ctypes.c_int(), ctypes.c_int()
+        _check(lib().sscn_fused_tile(self._h, ctypes.byref(tr), ctypes.byref(tc)))
+        return {"window": list(w), "segment": list(s), "plan": int(pl.value), "x_lines": int(xl.value),
+                "fused_tile": [int(tr.value), int(tc.value)]}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1442,18 +1442,21 @@ __global__ __launch_bounds__(256) void k_norm_partials(const typename Vec<R>::T 
         partials[blockIdx.x] = b;
 }
 
-// psi_dst = s psi_src with s = 1/sqrt(dV sum partials).  Near s = 1 (the
-// per-step renormalisation) as psi + (s - 1) psi, which keeps the small
-// correction exact in FP32; otherwise (a state of arbitrary scale) as the
-// product s psi, since s - 1 rounded to FP32 would then carry a relative
-// error of ulp(1) / s.
+// psi_dst = s psi_src with s = 1/sqrt(dV sum partials).  folded (the
+// renormalisation that ends a run of steps): always psi + (s - 1) psi, the
+// form the steps fold into their next H1, so that n steps in one call and n
+// calls of one step leave the same bits.  An imaginary-time step only lowers
+// the norm (s >= 1), where s - 1 from FP64 is at least as accurate as s.
+// Otherwise (a given state of arbitrary scale): the same form near s = 1,
+// and the product s psi for |s - 1| >= 1/4, since s - 1 rounded to FP32
+// would carry a relative error of ulp(1) / s for s << 1.
 template <class R>
 __global__ __launch_bounds__(256) void k_rescale(const typename Vec<R>::T *src, typename Vec<R>::T *dst, int64_t n,
-                                                 double dV, const double *partials, int npart)
+                                                 double dV, const double *partials, int npart, int folded)
 {
     const double tot = wave_partials_sum(partials, npart);
     const double sm1 = norm_scale_m1(tot, dV);
-    if (fabs(sm1) < 0.25) {
+    if (folded || fabs(sm1) < 0.25) {
         const R sr = R(sm1);
         for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p < n; p += (int64_t)gridDim.x * 256)
             st<R>(dst, p, rescale(ld<R>(src, p), sr));

@@ -44,6 +44,12 @@ hipError_t timing_event(hipEvent_t *e)
     return hipEventCreateWithFlags(e, hipEventDisableSystemFence);
 }
 
+// Output columns of the fused step's tile shape t (FusedLaunch::tile).
+int fused_tile_cols(int t)
+{
+    return t ? kTileCn : kTileC;
+}
+
 int64_t npoints(const sscn_params &p)
 {
     return (int64_t)p.nx * p.ny * (p.dim == 3 ? p.nz : 1);
@@ -102,10 +108,18 @@ int setup(sscn_handle *h)
         h->W[0] = h->W[1] = h->W[2] = 0;
         h->nemit = kRedBlocks;
     }
-    const size_t flds = step2d_lds_elems(kSeg, h->W[0], kTileR, kTileC) * h->esize;
-    h->fused_ok = p.dim == 2 && !h->exact && h->W[0] > 0 &&
-                  h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32) && flds <= 150 * 1024;
-    h->ntiles = ((p.nx - 2) / kTileC + 1) * ((p.ny - 2) / kTileR + 1);
+    for (int t = 0; t < 2; ++t) {
+        const int tc = fused_tile_cols(t);
+        const size_t flds = step2d_lds_elems(kSeg, h->W[0], kTileR, tc) * h->esize;
+        h->fused_ok_t[t] = p.dim == 2 && !h->exact && h->W[0] > 0 &&
+                           h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32) && flds <= 150 * 1024 &&
+                           (h->tile_force < 0 || h->tile_force == t);
+        h->ntiles_t[t] = ((p.nx - 2) / tc + 1) * ((p.ny - 2) / kTileR + 1);
+    }
+    if (!h->fused_ok_t[h->tile])
+        h->tile = h->fused_ok_t[0] ? 0 : 1;
+    h->fused_ok = h->fused_ok_t[0] || h->fused_ok_t[1];
+    h->ntiles = h->ntiles_t[h->tile];
     return 0;
 }
 
@@ -152,11 +166,13 @@ int red_blocks(int64_t n) { return (int)std::min<int64_t>(kRedBlocks, std::max<i
 // Kernel dispatch (the sweep and fused-step launchers are in
 // sscn_kernels.hip).
 
+// folded: the renormalisation that ends a run of steps (k_rescale); false
+// for a given state of arbitrary norm.
 template <class R>
-void launch_rescale(sscn_handle *h, hipStream_t st)
+void launch_rescale(sscn_handle *h, hipStream_t st, bool folded = true)
 {
     hipLaunchKernelGGL((k_rescale<R>), dim3(red_blocks(h->npts)), dim3(256), 0, st, (const V<R> *)h->psi,
-                       (V<R> *)h->psi, h->npts, h->args.dV, h->partials, h->nemit);
+                       (V<R> *)h->psi, h->npts, h->args.dV, h->partials, h->nemit, folded ? 1 : 0);
 }
 
 template <class R>
@@ -175,7 +191,7 @@ void enqueue_fused(sscn_handle *h, int64_t n, hipStream_t st, hipEvent_t *ev = n
 {
     const bool imag = h->p.mode == SSCN_IMAG;
     double *fp[2] = {h->partials, h->partials2};
-    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0], &h->inst_host};
+    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0], &h->inst_host, h->tile};
     for (int64_t s = 0; s < n; ++s) {
         if (ev)
             (void)hipEventRecord(ev[4 * s], st);
@@ -196,7 +212,7 @@ void enqueue_fused(sscn_handle *h, int64_t n, hipStream_t st, hipEvent_t *ev = n
     const int nb = red_blocks(h->npts);
     if (imag && h->pending) {
         hipLaunchKernelGGL((k_rescale<R>), dim3(nb), dim3(256), 0, st, (const V<R> *)bufs[h->fparity],
-                           (V<R> *)h->psi, h->npts, h->args.dV, fp[h->pbuf], h->ntiles);
+                           (V<R> *)h->psi, h->npts, h->args.dV, fp[h->pbuf], h->ntiles, 1);
         h->pending = false;
     } else if (h->fparity == 1) {
         hipLaunchKernelGGL((k_copy<R>), dim3(nb), dim3(256), 0, st, (const V<R> *)h->work, (V<R> *)h->psi,
@@ -213,7 +229,7 @@ int setup_fused(sscn_handle *h)
     Inst2D in{};
     in.nx = p.nx;
     in.ny = p.ny;
-    in.tiles_x = (p.nx - 2) / kTileC + 1;
+    in.tiles_x = (p.nx - 2) / fused_tile_cols(h->tile) + 1;
     in.tiles_y = (p.ny - 2) / kTileR + 1;
     in.poff = 0;
     in.active = 1;
@@ -246,7 +262,8 @@ int setup_fused(sscn_handle *h)
     h->d_work = nullptr;
     h->partials2 = nullptr;
     if (hipMalloc(&h->d_work, sizeof(int2) * wl.size()) != hipSuccess ||
-        hipMalloc(&h->partials2, sizeof(double) * std::max(h->ntiles, kRedBlocks)) != hipSuccess)
+        hipMalloc(&h->partials2, sizeof(double) * std::max({h->ntiles_t[0], h->ntiles_t[1], kRedBlocks})) !=
+            hipSuccess)
         return fail(SSCN_ENOMEM, "hipMalloc of the fused-step work list failed");
     h->inst_host = in;
     HIPCHECK(hipMemcpy(h->d_inst, &in, sizeof in, hipMemcpyHostToDevice));
@@ -257,6 +274,23 @@ int setup_fused(sscn_handle *h)
     if (e != hipSuccess)
         return fail(SSCN_EHIP, std::string("hipFuncSetAttribute: ") + hipGetErrorString(e));
     return 0;
+}
+
+void drop_graph(sscn_handle *h);
+
+// Put the fused step's tile shape t in force: the tile count, the
+// descriptor and work list on the device (setup_fused); the captured step
+// graphs carry the old grid and are dropped.
+int set_fused_tile(sscn_handle *h, int t)
+{
+    if (!h->fused_ok_t[t])
+        return fail(SSCN_EINVAL, "this fused tile shape is not available for the problem");
+    if (h->tile == t && h->d_work)
+        return 0;
+    drop_graph(h);
+    h->tile = t;
+    h->ntiles = h->ntiles_t[t];
+    return setup_fused(h);
 }
 
 // Dynamic-LDS limit of the handle's x-sweep kernels (lines longer than the
@@ -465,6 +499,7 @@ int run_step_graphs(sscn_handle *h, int64_t nsteps, bool launch)
 struct TuneChoice {
     int plan = SSCN_PLAN_SWEEPS;
     int xl = 0;
+    int tile = 0;  // the fused step's tile shape (plan SSCN_PLAN_FUSED)
     float ms = 0.f;
 };
 std::mutex g_tune_mu;
@@ -500,7 +535,8 @@ std::string tune_key(const sscn_handle *h)
 }
 
 // Entries are lines of the form
-//   "<key>": {"plan": 1|2, "x_lines": L, "ms_per_step": t},
+//   "<key>": {"plan": 1|2, "x_lines": L, "tile": 0|1, "ms_per_step": t},
+// ("tile" may be absent: 0).
 void tune_cache_load()
 {
     const char *path = std::getenv("SSCN_TUNE_CACHE");
@@ -517,13 +553,15 @@ void tune_cache_load()
         const char *pl = std::strstr(line, "\"plan\":");
         const char *xl = std::strstr(line, "\"x_lines\":");
         const char *ms = std::strstr(line, "\"ms_per_step\":");
+        const char *tl = std::strstr(line, "\"tile\":");
         if (!q1 || !pl || !xl)
             continue;
         TuneChoice c;
         c.plan = std::atoi(pl + 7);
         c.xl = std::atoi(xl + 10);
+        c.tile = tl ? std::atoi(tl + 7) : 0;
         c.ms = ms ? (float)std::atof(ms + 14) : 0.f;
-        if ((c.plan == SSCN_PLAN_SWEEPS || c.plan == SSCN_PLAN_FUSED) && c.xl >= 1)
+        if ((c.plan == SSCN_PLAN_SWEEPS || c.plan == SSCN_PLAN_FUSED) && c.xl >= 1 && (c.tile == 0 || c.tile == 1))
             g_tune_cache[std::string(q0 + 1, q1)] = c;
     }
     std::fclose(f);
@@ -541,8 +579,9 @@ void tune_cache_save()
     std::fprintf(f, "{\n");
     size_t k = 0;
     for (const auto &e : g_tune_cache)
-        std::fprintf(f, "  \"%s\": {\"plan\": %d, \"x_lines\": %d, \"ms_per_step\": %.6f}%s\n", e.first.c_str(),
-                     e.second.plan, e.second.xl, e.second.ms, ++k < g_tune_cache.size() ? "," : "");
+        std::fprintf(f, "  \"%s\": {\"plan\": %d, \"x_lines\": %d, \"tile\": %d, \"ms_per_step\": %.6f}%s\n",
+                     e.first.c_str(), e.second.plan, e.second.xl, e.second.tile, e.second.ms,
+                     ++k < g_tune_cache.size() ? "," : "");
     std::fprintf(f, "}\n");
     std::fclose(f);
     std::rename(tmp.c_str(), path);
@@ -586,8 +625,13 @@ int autotune(sscn_handle *h)
         tune_cache_load();
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end() && it->second.xl <= h->xLmax && !(it->second.xl & (it->second.xl - 1)) &&
-            (it->second.plan == SSCN_PLAN_SWEEPS || h->fused_ok)) {
+            (it->second.plan == SSCN_PLAN_SWEEPS || h->fused_ok_t[it->second.tile])) {
             set_x_lines(h, it->second.xl);
+            if (it->second.plan == SSCN_PLAN_FUSED) {
+                const int r = set_fused_tile(h, it->second.tile);
+                if (r)
+                    return r;
+            }
             h->active_plan = h->plan = it->second.plan;
             return 0;
         }
@@ -602,12 +646,14 @@ int autotune(sscn_handle *h)
             cand.push_back(c);
         }
     }
-    if (h->fused_ok) {
-        TuneChoice c;
-        c.plan = SSCN_PLAN_FUSED;
-        c.xl = h->xLmax;
-        cand.push_back(c);
-    }
+    for (int t = 0; t < 2; ++t)
+        if (h->fused_ok_t[t]) {
+            TuneChoice c;
+            c.plan = SSCN_PLAN_FUSED;
+            c.xl = h->xLmax;
+            c.tile = t;
+            cand.push_back(c);
+        }
     void *saved = nullptr;
     const size_t bytes = (size_t)h->npts * h->esize;
     if (hipMalloc(&saved, bytes) != hipSuccess)
@@ -617,6 +663,13 @@ int autotune(sscn_handle *h)
     size_t best = 0;
     for (size_t k = 0; k < cand.size(); ++k) {
         set_x_lines(h, cand[k].xl);
+        if (cand[k].plan == SSCN_PLAN_FUSED) {
+            const int r = set_fused_tile(h, cand[k].tile);
+            if (r) {
+                (void)hipFree(saved);
+                return r;
+            }
+        }
         const float ms = h->p.precision == SSCN_C128 ? time_plan<double>(h, cand[k].plan, saved, nsteps)
                                                      : time_plan<float>(h, cand[k].plan, saved, nsteps);
         cand[k].ms = ms / nsteps;
@@ -630,6 +683,11 @@ int autotune(sscn_handle *h)
     h->pending = false;
     h->fparity = 0;
     set_x_lines(h, cand[best].xl);
+    if (cand[best].plan == SSCN_PLAN_FUSED) {
+        const int r = set_fused_tile(h, cand[best].tile);
+        if (r)
+            return r;
+    }
     h->active_plan = h->plan = cand[best].plan;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = cand[best];
@@ -1223,6 +1281,8 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
         h->p.nz = 1;
     h->psi = psi_dev;
     h->stream = (hipStream_t)hip_stream;
+    if (const char *env = std::getenv("SSCN_FUSED_TILE"))
+        h->tile_force = (env[0] == '0') ? 0 : (env[0] == '1') ? 1 : -1;
     r = setup(h);
     if (r) {
         delete h;
@@ -1240,7 +1300,8 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
     r = build_tables(h);
     if (r)
         return bail(r);
-    const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, (size_t)h->ntiles});
+    const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, (size_t)h->ntiles_t[0],
+                                   (size_t)h->ntiles_t[1]});
     if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_part, (size_t)kRedBlocks * kObsN * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_buf, 64 * sizeof(double)) != hipSuccess)
@@ -1327,9 +1388,9 @@ static int init_state_impl(sscn_handle *h, int kind, const double *phase_host, i
     const int saved = h->nemit;
     h->nemit = kRedBlocks;
     if (p.precision == SSCN_C128)
-        launch_rescale<double>(h, h->stream);
+        launch_rescale<double>(h, h->stream, false);
     else
-        launch_rescale<float>(h, h->stream);
+        launch_rescale<float>(h, h->stream, false);
     h->nemit = saved;
     h->pending = false;
     HIPCHECK(hipGetLastError());
@@ -1674,6 +1735,8 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
     t->p = np;
     t->psi = conv ? new_psi_dev : h->psi;
     t->stream = h->stream;
+    t->tile = h->tile;  // the fused tile shape carries over where it still fits
+    t->tile_force = h->tile_force;
     auto drop_t = [&](int code) {
         release_step_buffers(t);
         delete t;
@@ -1685,7 +1748,8 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
     if (!r)
         r = build_tables(t);
     if (!r) {
-        const size_t npart = std::max({(size_t)t->nemit, (size_t)kRedBlocks, (size_t)t->ntiles});
+        const size_t npart = std::max({(size_t)t->nemit, (size_t)kRedBlocks, (size_t)t->ntiles_t[0],
+                                       (size_t)t->ntiles_t[1]});
         if (hipMalloc(&t->partials, npart * sizeof(double)) != hipSuccess)
             r = fail(SSCN_ENOMEM, "hipMalloc of the partials failed");
     }
@@ -1725,6 +1789,8 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
     h->d_nwork = t->d_nwork;
     h->partials2 = t->partials2;
     h->inst_host = t->inst_host;
+    h->tile = t->tile;
+    h->ntiles = t->ntiles;
     delete t;  // owns nothing now
     h->plan = (plan == SSCN_PLAN_FUSED && !h->fused_ok) ? SSCN_PLAN_AUTO : plan;
     h->active_plan = h->plan == SSCN_PLAN_FUSED ? SSCN_PLAN_FUSED : SSCN_PLAN_SWEEPS;
@@ -1883,7 +1949,7 @@ int profile_kernel(sscn_handle *h, int which, int nlaunch, double *avg_ms)
     HIPCHECK(hipMemsetAsync(prof_part, 0, sizeof(double) * 2 * npk, h->stream));
     sscn_handle t = *h;  // the same kernels with partials into the prof_part
     t.partials = prof_part;
-    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0], &h->inst_host};
+    const FusedLaunch f{h->d_inst, h->d_work, h->d_nwork, h->ntiles, h->W[0], &h->inst_host, h->tile};
     auto launch = [&](bool first) {
         if (fused) {
             if (imag)
@@ -1992,6 +2058,15 @@ int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *pla
         if (segment_xyz)
             segment_xyz[a] = h->exact ? 0 : (a == 0 && h->active_plan != SSCN_PLAN_FUSED ? kSegX : kSeg);
     }
+    return 0;
+}
+
+int sscn_fused_tile(sscn_handle *h, int *rows, int *cols)
+{
+    if (!h || !rows || !cols)
+        return fail(SSCN_EINVAL, "null argument");
+    *rows = kTileR;
+    *cols = fused_tile_cols(h->tile);
     return 0;
 }
 
@@ -2329,14 +2404,14 @@ int sscn_batch_init_state(sscn_batch *b, int k, int kind, const double *phase_ho
         hipLaunchKernelGGL((k_norm_partials<double>), dim3(kRedBlocks), dim3(256), 0, b->stream,
                            (const V<double> *)b->psi[k], npts, b->opart);
         hipLaunchKernelGGL((k_rescale<double>), dim3(nb), dim3(256), 0, b->stream, (const V<double> *)b->psi[k],
-                           (V<double> *)b->psi[k], npts, a.dV, b->opart, kRedBlocks);
+                           (V<double> *)b->psi[k], npts, a.dV, b->opart, kRedBlocks, 0);
     } else {
         hipLaunchKernelGGL((k_init<float>), dim3(nb), dim3(256), 0, b->stream, (V<float> *)b->psi[k], a, kind, ph,
                            d_xy, d_z, 0, (uint64_t)0);
         hipLaunchKernelGGL((k_norm_partials<float>), dim3(kRedBlocks), dim3(256), 0, b->stream,
                            (const V<float> *)b->psi[k], npts, b->opart);
         hipLaunchKernelGGL((k_rescale<float>), dim3(nb), dim3(256), 0, b->stream, (const V<float> *)b->psi[k],
-                           (V<float> *)b->psi[k], npts, a.dV, b->opart, kRedBlocks);
+                           (V<float> *)b->psi[k], npts, a.dV, b->opart, kRedBlocks, 0);
     }
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(b->stream));
@@ -2555,14 +2630,14 @@ int sscn_batch_set_state_device(sscn_batch *b, int k)
         hipLaunchKernelGGL((k_norm_partials<double>), dim3(kRedBlocks), dim3(256), 0, b->stream,
                            (const V<double> *)psi, npts, b->opart);
         hipLaunchKernelGGL((k_rescale<double>), dim3(nb), dim3(256), 0, b->stream, (const V<double> *)psi, psi, npts,
-                           a.dV, b->opart, kRedBlocks);
+                           a.dV, b->opart, kRedBlocks, 0);
     } else {
         V<float> *psi = (V<float> *)b->psi[k];
         hipLaunchKernelGGL((k_zero_walls<float>), dim3(nb), dim3(256), 0, b->stream, psi, a);
         hipLaunchKernelGGL((k_norm_partials<float>), dim3(kRedBlocks), dim3(256), 0, b->stream,
                            (const V<float> *)psi, npts, b->opart);
         hipLaunchKernelGGL((k_rescale<float>), dim3(nb), dim3(256), 0, b->stream, (const V<float> *)psi, psi, npts,
-                           a.dV, b->opart, kRedBlocks);
+                           a.dV, b->opart, kRedBlocks, 0);
     }
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipStreamSynchronize(b->stream));

@@ -273,16 +273,17 @@ int sscn_nn_act_bwd(void *dy, const void *y, int64_t n, void *stream)
     return launched("act_bwd");
 }
 
-int sscn_nn_pool2(const void *x, int N, int H, int W, int C, void *y, void *stream)
+int sscn_nn_pool2(const void *x, int ldx, int xoff, int N, int H, int W, int C, void *y, void *stream)
 {
-    if (!x || !y || H % 2 || W % 2)
+    if (!x || !y || H % 2 || W % 2 || C < 1 || xoff < 0 || ldx < xoff + C)
         return nn_fail(-1, "bad pool2 arguments");
-    if (C % 8 == 0 && aligned16(x) && aligned16(y))
+    const uint16_t *xs = (const uint16_t *)x + xoff;
+    if (C % 8 == 0 && ldx % 8 == 0 && aligned16(xs) && aligned16(y))
         hipLaunchKernelGGL(k_pool2_v8, dim3(blocks((int64_t)N * H * W * C / 32)), dim3(256), 0, (hipStream_t)stream,
-                           (const uint16_t *)x, N, H, W, C, (uint16_t *)y);
+                           xs, ldx, N, H, W, C, (uint16_t *)y);
     else
         hipLaunchKernelGGL(k_pool2, dim3(blocks((int64_t)N * H * W * C / 4)), dim3(256), 0, (hipStream_t)stream,
-                           (const uint16_t *)x, N, H, W, C, (uint16_t *)y);
+                           xs, ldx, N, H, W, C, (uint16_t *)y);
     return launched("pool2");
 }
 

@@ -734,7 +734,7 @@ __global__ __launch_bounds__(256) void k_act_bwd(uint16_t *__restrict__ dy, cons
 }
 
 // 2x2 average pooling (H, W even) and its gradient.
-__global__ __launch_bounds__(256) void k_pool2(const uint16_t *__restrict__ x, int N, int H, int W, int C,
+__global__ __launch_bounds__(256) void k_pool2(const uint16_t *__restrict__ x, int ldx, int N, int H, int W, int C,
                                                uint16_t *__restrict__ y)
 {
     const int Ho = H / 2, Wo = W / 2;
@@ -742,9 +742,9 @@ __global__ __launch_bounds__(256) void k_pool2(const uint16_t *__restrict__ x, i
     for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
         const int c = e % C, q = e / C;
         const int j = q % Wo, i = (q / Wo) % Ho, b = q / (Wo * Ho);
-        const size_t base = ((size_t)(b * H + 2 * i) * W + 2 * j) * C + c;
-        const float s = bf2f(x[base]) + bf2f(x[base + C]) + bf2f(x[base + (size_t)W * C]) +
-                        bf2f(x[base + (size_t)W * C + C]);
+        const size_t base = ((size_t)(b * H + 2 * i) * W + 2 * j) * ldx + c;
+        const float s = bf2f(x[base]) + bf2f(x[base + ldx]) + bf2f(x[base + (size_t)W * ldx]) +
+                        bf2f(x[base + (size_t)W * ldx + ldx]);
         y[e] = f2bf(0.25f * s);
     }
 }
@@ -826,8 +826,8 @@ __device__ __forceinline__ uint4 pack8(const float (&f)[8])
     return make_uint4(w[0], w[1], w[2], w[3]);
 }
 
-__global__ __launch_bounds__(256) void k_pool2_v8(const uint16_t *__restrict__ x, int N, int H, int W, int C,
-                                                  uint16_t *__restrict__ y)
+__global__ __launch_bounds__(256) void k_pool2_v8(const uint16_t *__restrict__ x, int ldx, int N, int H, int W,
+                                                  int C, uint16_t *__restrict__ y)
 {
     const int Ho = H / 2, Wo = W / 2, C8 = C / 8;
     const int64_t n = (int64_t)N * Ho * Wo * C8;
@@ -835,12 +835,12 @@ __global__ __launch_bounds__(256) void k_pool2_v8(const uint16_t *__restrict__ x
         const int c8 = (int)(e % C8);
         const int64_t q = e / C8;
         const int j = (int)(q % Wo), i = (int)((q / Wo) % Ho), b = (int)(q / ((int64_t)Wo * Ho));
-        const size_t base = ((size_t)(b * H + 2 * i) * W + 2 * j) * C + 8 * c8;
+        const size_t base = ((size_t)(b * H + 2 * i) * W + 2 * j) * ldx + 8 * c8;
         float a[8], bb[8], c[8], d[8], o[8];
         unpack8(*reinterpret_cast<const uint4 *>(x + base), a);
-        unpack8(*reinterpret_cast<const uint4 *>(x + base + C), bb);
-        unpack8(*reinterpret_cast<const uint4 *>(x + base + (size_t)W * C), c);
-        unpack8(*reinterpret_cast<const uint4 *>(x + base + (size_t)W * C + C), d);
+        unpack8(*reinterpret_cast<const uint4 *>(x + base + ldx), bb);
+        unpack8(*reinterpret_cast<const uint4 *>(x + base + (size_t)W * ldx), c);
+        unpack8(*reinterpret_cast<const uint4 *>(x + base + (size_t)W * ldx + ldx), d);
 #pragma unroll
         for (int t = 0; t < 8; ++t)
             o[t] = 0.25f * (a[t] + bb[t] + c[t] + d[t]);

@@ -35,7 +35,7 @@ def _nn():
         L.sscn_nn_wgrad_scratch.argtypes = [ci, ci, ci, ci, ci, ctypes.POINTER(i64)]
         L.sscn_nn_conv3x3_wgrad.argtypes = [vp, ci, ci, ci, ci, vp, ci, vp, vp, vp, i64, vp]
         L.sscn_nn_act_bwd.argtypes = [vp, vp, i64, vp]
-        L.sscn_nn_pool2.argtypes = [vp, ci, ci, ci, ci, vp, vp]
+        L.sscn_nn_pool2.argtypes = [vp, ci, ci, ci, ci, ci, ci, vp, vp]
         L.sscn_nn_pool2_bwd.argtypes = [vp, ci, ci, ci, ci, vp, vp]
         L.sscn_nn_up2.argtypes = [vp, ci, ci, ci, ci, vp, ci, ci, vp]
         L.sscn_nn_up2_bwd.argtypes = [vp, ci, ci, ci, ci, ci, ci, vp, vp]
@@ -94,8 +94,8 @@ def act_bwd(dy, y, stream=None):
     _ck(_nn().sscn_nn_act_bwd(_p(dy), _p(y), dy.numel(), stream))
 
 
-def pool2(x, N, H, W, C, y, stream=None):
-    _ck(_nn().sscn_nn_pool2(_p(x), N, H, W, C, _p(y), stream))
+def pool2(x, N, H, W, C, y, ldx=None, xoff=0, stream=None):
+    _ck(_nn().sscn_nn_pool2(_p(x), ldx or C, xoff, N, H, W, C, _p(y), stream))
 
 
 def pool2_bwd(dy, N, H, W, C, dx, stream=None):
@@ -268,6 +268,16 @@ class UNet:
         self.stats = self.torch.zeros(4 * N, dtype=self.torch.float64, device=self.dev)
 
     # -- forward ----------------------------------------------------------
+    def _cup_of(self):
+        """Channels of the upsampled half of each level's concatenation
+        buffer (the output channels of the level below)."""
+        spec = {s[0]: s for s in self.specs}
+        out, cup = {}, self.bott
+        for lv in range(len(self.chans) - 1, -1, -1):
+            out[lv] = cup
+            cup = spec[f"dec{lv}b"][2]
+        return out
+
     def forward(self, x):
         """x: (N, H, W, 16) bf16 tensor.  Returns the fp32 (N, H, W, 16)
         output; channels 0, 1 are Re, Im of psi."""
@@ -282,12 +292,18 @@ class UNet:
                     out if out is not None else self.acts[name], ldy=ldy, yoff=yoff,
                     out_f32=(name == "out"), ws=self.scratch)
 
+        # the encoder's second convolution of each level writes straight into
+        # the skip half of that level's concatenation buffer (channels cup ..
+        # cup + c - 1 of ld), which the pooling reads in place; the decoder
+        # fills the other half by upsampling
+        cup_of = self._cup_of()
         cur = x
         for lv, c in enumerate(self.chans):
+            ld = cup_of[lv] + c
             conv(f"enc{lv}a", cur)
-            conv(f"enc{lv}b", self.acts[f"enc{lv}a"])
+            conv(f"enc{lv}b", self.acts[f"enc{lv}a"], out=self.cat[lv], ldy=ld, yoff=cup_of[lv])
             h, w = self.shapes[f"enc{lv}b"]
-            pool2(self.acts[f"enc{lv}b"], N, h, w, c, self.pool[lv])
+            pool2(self.cat[lv], N, h, w, c, self.pool[lv], ldx=ld, xoff=cup_of[lv])
             cur = self.pool[lv]
         conv("bota", cur)
         conv("botb", self.acts["bota"])
@@ -296,8 +312,6 @@ class UNet:
             h, w = self.shapes[f"dec{lv}a"]
             ld = cup + self.chans[lv]
             up2(cur, N, h // 2, w // 2, cup, self.cat[lv], ld, 0)
-            chan_copy(self.acts[f"enc{lv}b"], self.chans[lv], 0, self.cat[lv], ld, cup, N * h * w,
-                      self.chans[lv])
             conv(f"dec{lv}a", self.cat[lv])
             conv(f"dec{lv}b", self.acts[f"dec{lv}a"])
             cur = self.acts[f"dec{lv}b"]
@@ -323,11 +337,7 @@ class UNet:
         lv0 = len(self.chans) - 1
         top = self.acts["dec0b"]
         conv_bwd("out", top, dout, self.gacts["dec0b"])
-        cup_of = {}
-        cup = self.bott
-        for lv in range(lv0, -1, -1):
-            cup_of[lv] = cup
-            cup = spec[f"dec{lv}b"][2]
+        cup_of = self._cup_of()
         for lv in range(0, lv0 + 1):
             h, w = self.shapes[f"dec{lv}a"]
             act_bwd(self.gacts[f"dec{lv}b"], self.acts[f"dec{lv}b"])
@@ -348,6 +358,8 @@ class UNet:
             ld = cup_of[lv] + c
             chan_copy(self.gcat[lv], ld, cup_of[lv], self.gacts[f"enc{lv}b"], c, 0, N * h * w, c,
                       accumulate=True)
+            # the layer's output lives in the concatenation buffer (forward)
+            chan_copy(self.cat[lv], ld, cup_of[lv], self.acts[f"enc{lv}b"], c, 0, N * h * w, c)
             act_bwd(self.gacts[f"enc{lv}b"], self.acts[f"enc{lv}b"])
             conv_bwd(f"enc{lv}b", self.acts[f"enc{lv}a"], self.gacts[f"enc{lv}b"], self.gacts[f"enc{lv}a"])
             act_bwd(self.gacts[f"enc{lv}a"], self.acts[f"enc{lv}a"])

@@ -82,10 +82,10 @@ def test_restart_is_bitwise(P, cfg):
         s.close()
 
 
-def test_prepare_steps_leaves_the_state(P):
-    """prepare_steps picks the plan and captures graphs without advancing
-    the state; the prepared call then gives the same bits as an unprepared
-    handle's."""
+def test_prepare_steps_leaves_the_state(P, monkeypatch):
+    """prepare_steps picks the plan (and the fused step's tile shape) and
+    captures graphs without advancing the state; the prepared call then
+    gives the same bits as an unprepared handle's with the same choices."""
     announce("prepare_steps")
     cfg = small()
     ph = W.phase_field(5, cfg["ny"], cfg["nx"])
@@ -96,6 +96,8 @@ def test_prepare_steps_leaves_the_state(P):
     assert np.array_equal(a.get_state(), s0)
     assert a.observables()["step"] == 0
     a.step(20)
+    # the same tile shape (the norm partials are summed per tile)
+    monkeypatch.setenv("SSCN_FUSED_TILE", "0" if a.solver_info()["fused_tile"][1] == 32 else "1")
     b = P.Solver(W.solver_params(cfg))
     b.init_state(1, ph, 1.0)
     b.set_plan(a.solver_info()["plan"])

@@ -158,6 +158,14 @@ def test_elementwise_and_resampling(nn, C, uoff, soff, doff, cc):
     y = torch.zeros((N, H // 2, W // 2, C), dtype=torch.int16, device="cuda")
     nn.pool2(xd, N, H, W, C, y)
     assert np.array_equal(from_bf(y), U.bf16(U.pool2(x)))
+    # the same channels read as a slice of a wider tensor (offset uoff, pixel
+    # stride C + uoff + 8), e.g. the skip half of a concatenation buffer
+    ldw = C + uoff + 8
+    wide = torch.zeros((N, H, W, ldw), dtype=torch.int16, device="cuda")
+    wide[..., uoff:uoff + C] = xd
+    ys = torch.zeros_like(y)
+    nn.pool2(wide, N, H, W, C, ys, ldx=ldw, xoff=uoff)
+    assert torch.equal(ys, y)
     dx = torch.zeros_like(xd)
     nn.pool2_bwd(y, N, H, W, C, dx)
     assert np.array_equal(from_bf(dx), U.bf16(U.pool2_bwd(from_bf(y))))

@@ -377,6 +377,39 @@ def test_plans_2d(P, plan, mode, prec, shape):
     s.close()
 
 
+@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("prec,shape", [(0, (100, 77)), (1, (96, 70)), (0, (33, 200)), (0, (129, 40))])
+def test_fused_tile_shapes(P, tile, mode, prec, shape, monkeypatch):
+    """The fused step's two tile shapes (32 x 32 and 32 x 16, fixed through
+    SSCN_FUSED_TILE) against the oracle on ragged grids, over graph-replayed
+    steps (an odd count: the buffer hand-back) and, bit for bit, the same
+    steps launched one at a time."""
+    nx, ny = shape
+    announce(f"fused tile={tile} mode={mode} prec={prec} shape={shape}")
+    monkeypatch.setenv("SSCN_FUSED_TILE", str(tile))
+    cfg = dict(dim=2, nx=nx, ny=ny, nz=1, hx=0.11, hy=0.09, hz=0.1, gamma=1.0, nu=1.1,
+               lam=1.0, g=60.0, omega=0.55, dt=2e-3, mode=mode, precision=prec)
+    psi0 = W.random_field(22, (ny, nx)) / np.sqrt(0.11 * 0.09)
+    s, op = both(P, cfg)
+    s.set_plan(2)
+    s.set_state(psi0)
+    s.step(131)
+    info = s.solver_info()
+    assert info["plan"] == 2 and info["fused_tile"] == [32, 32 if tile == 0 else 16], info
+    ref = O.step(op, psi0, 131)
+    got = s.get_state()
+    assert rel(got.astype(np.complex128), ref) <= (TOL64 if prec == 0 else TOL32)
+    s.close()
+    d = P.Solver(W.solver_params(cfg))
+    d.set_plan(2)
+    d.set_state(psi0)
+    for _ in range(131):
+        d.step(1)
+    assert np.array_equal(d.get_state(), got)
+    d.close()
+
+
 @pytest.mark.parametrize("plan", [1, 2])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("prec", [0, 1])
