@@ -341,12 +341,13 @@ int sscn_solver_info(sscn_handle *h, int *window_xyz, int *segment_xyz, int *pla
 
 /* Output tile (rows along y, columns along x) of the fused 2D step (Sec. 2's
  * x- and y-direction Crank-Nicolson solves with H1 in one launch, one block
- * per tile): 32 x 32, or 32 x 16 (twice the tiles, for grids whose wide
- * tiles leave most compute units idle).  The first step of an SSCN_PLAN_AUTO
- * handle times both shapes along with the sweep plans; the environment
- * variable SSCN_FUSED_TILE=0 (32 x 32) or 1 (32 x 16), read at sscn_init,
- * fixes the shape.  Both shapes give the same steps to rounding (the norm
- * partials are summed per tile).  SSCN_EINVAL for a NULL argument. */
+ * per tile): 32 x 32, 32 x 16 or 16 x 16 (more, smaller tiles for grids
+ * whose wide tiles leave most compute units idle).  The first step of an
+ * SSCN_PLAN_AUTO handle times every shape along with the sweep plans; the
+ * environment variable SSCN_FUSED_TILE=0 (32 x 32), 1 (32 x 16) or 2
+ * (16 x 16), read at sscn_init, fixes the shape.  The shapes give the same
+ * steps to rounding (the norm partials are summed per tile).  SSCN_EINVAL
+ * for a NULL argument. */
 int sscn_fused_tile(sscn_handle *h, int *rows, int *cols);
 
 void sscn_destroy(sscn_handle *h);

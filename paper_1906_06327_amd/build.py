@@ -10,12 +10,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 # (source, extra defines): the kernel launchers are compiled once per part
-# (1 sweeps, 2 and 4 the fused 2D step's two tile shapes, 3 batched sweeps)
-# and precision
+# (1 sweeps, 2, 4 and 5 the fused 2D step's three tile shapes, 3 batched
+# sweeps) and precision
 UNITS = [(os.path.join(CSRC, "sscn_lib.hip"), []), (os.path.join(CSRC, "sscn_nn.hip"), []),
          (os.path.join(CSRC, "sscn_setup.cpp"), [])] + [
     (os.path.join(CSRC, "sscn_kernels.hip"), [f"-DSSCN_PART={part}", f"-DSSCN_REAL_T={real}"])
-    for part in (2, 4, 1, 3) for real in ("double", "float")]
+    for part in (2, 4, 5, 1, 3) for real in ("double", "float")]
 LIB = os.path.join(HERE, "libsscn.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

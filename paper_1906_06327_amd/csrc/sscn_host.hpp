@@ -40,14 +40,17 @@ constexpr int kRedBlocks = 1024;    // blocks of the grid-stride reductions
 #endif
 constexpr int kTileR = SSCN_TILE_R;   // fused 2D step: output tile rows (y)
 constexpr int kTileC = SSCN_TILE_C;   // and columns (x)
-// The second tile shape of a single instance's fused step, kTileR x
-// kTileCn: twice the tiles of half the width, for grids whose kTileR x
-// kTileC tiles leave most CUs idle or whose real-time step is issue-bound.
-// The autotuner times both shapes.
+// The tile shapes of a single instance's fused step (FusedLaunch::tile):
+// 0 kTileR x kTileC; 1 kTileR x kTileCn (twice the tiles of half the width,
+// for grids whose wide tiles leave most CUs idle or whose real-time step is
+// issue-bound); 2 16 x 16 (small grids).  The autotuner times them all.
 #ifndef SSCN_TILE_CN
 #define SSCN_TILE_CN 16
 #endif
 constexpr int kTileCn = SSCN_TILE_CN;
+constexpr int kFusedTiles = 3;
+constexpr int kFusedTileR[kFusedTiles] = {kTileR, kTileR, 16};
+constexpr int kFusedTileC[kFusedTiles] = {kTileC, kTileCn, 16};
 constexpr int kTileNT = SSCN_TILE_NT; // threads per tile block
 constexpr size_t kXLdsCap = 150 * 1024;  // dynamic LDS of an x-sweep block
 // Dynamic LDS of a batched x-sweep block at most (bytes) under the capped
@@ -119,8 +122,8 @@ struct sscn_handle {
     // fits (window and LDS) and its tile count; tile_force >= 0 when
     // SSCN_FUSED_TILE fixes the shape
     int tile = 0, tile_force = -1;
-    bool fused_ok_t[2] = {false, false};
-    int ntiles_t[2] = {0, 0};
+    bool fused_ok_t[kFusedTiles] = {false, false, false};
+    int ntiles_t[kFusedTiles] = {0, 0, 0};
     double *partials2 = nullptr;
     int fparity = 0;        // buffer (0 = psi, 1 = work) holding the state
     int pbuf = 0;           // partial buffer holding the pending norm
@@ -177,7 +180,7 @@ struct FusedLaunch {
     int grid;
     int W;
     const Inst2D *one;
-    int tile = 0;  // 0: kTileR x kTileC tiles, 1: kTileR x kTileCn
+    int tile = 0;  // the tile shape: kFusedTileR[tile] x kFusedTileC[tile]
 };
 
 }  // namespace sscn
@@ -267,16 +270,21 @@ void launch_z(const sscn_handle *h, const void *src, void *dst, hipStream_t st);
 // One fused 2D step over a work list (or one instance).
 template <class R, bool RT>
 void launch_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st);
-// The launcher of the kTileR x kTileCn shape (launch_fused dispatches to it).
+// The launchers of tile shapes 1 and 2 (launch_fused dispatches to them).
 template <class R, bool RT>
 void launch_fused_narrow(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin,
                          hipStream_t st);
-// Raise the dynamic-LDS limit of the fused-step kernels for window W (both
-// tile shapes).
+template <class R, bool RT>
+void launch_fused_small(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin,
+                        hipStream_t st);
+// Raise the dynamic-LDS limit of the fused-step kernels for window W (every
+// tile shape).
 template <class R>
 hipError_t allow_fused_lds_all(int W);
 template <class R>
 hipError_t allow_fused_lds_narrow(int W);
+template <class R>
+hipError_t allow_fused_lds_small(int W);
 // The same for the x-sweep kernels (kXLdsCap), single-instance and batched.
 template <class R>
 hipError_t allow_x_lds_all(int W);

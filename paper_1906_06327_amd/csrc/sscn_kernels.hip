@@ -1,13 +1,13 @@
 // Kernel launchers of the solver, compiled once per (part, precision):
-// SSCN_PART 1 = the x-, y- and z-sweeps, 2 = the fused 2D step with
-// kTileR x kTileC tiles, 3 = the batched sweeps, 4 = the fused 2D step with
-// kTileR x kTileCn tiles; SSCN_REAL_T = double or float.  Each compilation
+// SSCN_PART 1 = the x-, y- and z-sweeps, 2, 4 and 5 = the fused 2D step
+// with tile shapes 0, 1 and 2 (kFusedTileR x kFusedTileC), 3 = the batched
+// sweeps; SSCN_REAL_T = double or float.  Each compilation
 // explicitly instantiates its part's launchers (declared in sscn_host.hpp)
 // for one precision.
 #include "sscn_host.hpp"
 
 #if !defined(SSCN_PART) || !defined(SSCN_REAL_T)
-#error "compile with -DSSCN_PART=1|2|3|4 -DSSCN_REAL_T=double|float"
+#error "compile with -DSSCN_PART=1|2|3|4|5 -DSSCN_REAL_T=double|float"
 #endif
 
 namespace sscn {
@@ -114,26 +114,28 @@ template void launch_y<SSCN_REAL_T, true>(const sscn_handle *, const void *, voi
 template void launch_z<SSCN_REAL_T, false>(const sscn_handle *, const void *, void *, hipStream_t);
 template void launch_z<SSCN_REAL_T, true>(const sscn_handle *, const void *, void *, hipStream_t);
 
-#elif SSCN_PART == 2 || SSCN_PART == 4
+#elif SSCN_PART == 2 || SSCN_PART == 4 || SSCN_PART == 5
 
-// The tile of this compilation: columns kTileC (part 2) or kTileCn (part 4).
-// The launchers below have the same names in both compilations, so they
+// The tile shape of this compilation: 0 (part 2), 1 (part 4) or 2 (part 5).
+// The launchers below have the same names in every compilation, so they
 // are kept local to each (an unnamed namespace): otherwise the linker would
-// keep one compilation's instances for both tile shapes.
-constexpr int kPartTileC = SSCN_PART == 2 ? kTileC : kTileCn;
+// keep one compilation's instances for every tile shape.
+constexpr int kPartTile = SSCN_PART == 2 ? 0 : SSCN_PART == 4 ? 1 : 2;
+constexpr int kPartTileR = kFusedTileR[kPartTile];
+constexpr int kPartTileC = kFusedTileC[kPartTile];
 
 namespace {
 
 template <class R, int W, bool RT>
 void go_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
 {
-    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kPartTileC>();
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kPartTileR, kPartTileC>();
     if (f.one)  // one block per tile, the grid rounded up to the 8 XCDs (see k_step2d)
-        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kPartTileC, kTileNT, RT, true>), dim3(round8(f.grid)),
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kPartTileR, kPartTileC, kTileNT, RT, true>), dim3(round8(f.grid)),
                            dim3(kTileNT),
                            lds, st, f.inst, f.work, f.nwork, *f.one, parity, pin, pout, use_pin);
     else
-        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kTileR, kPartTileC, kTileNT, RT, false>), dim3(round8(f.grid)), dim3(kTileNT),
+        hipLaunchKernelGGL((k_step2d<R, kSeg, W, kPartTileR, kPartTileC, kTileNT, RT, false>), dim3(round8(f.grid)), dim3(kTileNT),
                            lds, st, f.inst, f.work, f.nwork, Inst2D{}, parity, pin, pout, use_pin);
 }
 
@@ -158,11 +160,11 @@ void launch_fused_tile(const FusedLaunch &f, int parity, const double *pin, doub
 template <class R, int W, bool RT>
 hipError_t allow_fused_lds()
 {
-    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kTileR, kPartTileC>();
-    hipError_t e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kPartTileC, kTileNT, RT, true>,
+    constexpr size_t lds = step2d_lds_bytes<R, kSeg, W, kPartTileR, kPartTileC>();
+    hipError_t e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kPartTileR, kPartTileC, kTileNT, RT, true>,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e == hipSuccess)
-        e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kTileR, kPartTileC, kTileNT, RT, false>,
+        e = hipFuncSetAttribute((const void *)k_step2d<R, kSeg, W, kPartTileR, kPartTileC, kTileNT, RT, false>,
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     return e;
 }
@@ -198,8 +200,10 @@ hipError_t allow_fused_lds_tile(int W)
 template <class R, bool RT>
 void launch_fused(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin, hipStream_t st)
 {
-    if (f.tile)
+    if (f.tile == 1)
         launch_fused_narrow<R, RT>(f, parity, pin, pout, use_pin, st);
+    else if (f.tile == 2)
+        launch_fused_small<R, RT>(f, parity, pin, pout, use_pin, st);
     else
         launch_fused_tile<R, RT>(f, parity, pin, pout, use_pin, st);
 }
@@ -208,13 +212,15 @@ template <class R>
 hipError_t allow_fused_lds_all(int W)
 {
     hipError_t e = allow_fused_lds_tile<R>(W);
-    return e == hipSuccess ? allow_fused_lds_narrow<R>(W) : e;
+    if (e == hipSuccess)
+        e = allow_fused_lds_narrow<R>(W);
+    return e == hipSuccess ? allow_fused_lds_small<R>(W) : e;
 }
 
 template void launch_fused<SSCN_REAL_T, false>(const FusedLaunch &, int, const double *, double *, int, hipStream_t);
 template void launch_fused<SSCN_REAL_T, true>(const FusedLaunch &, int, const double *, double *, int, hipStream_t);
 template hipError_t allow_fused_lds_all<SSCN_REAL_T>(int);
-#else
+#elif SSCN_PART == 4
 template <class R, bool RT>
 void launch_fused_narrow(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin,
                          hipStream_t st)
@@ -233,6 +239,25 @@ template void launch_fused_narrow<SSCN_REAL_T, false>(const FusedLaunch &, int, 
 template void launch_fused_narrow<SSCN_REAL_T, true>(const FusedLaunch &, int, const double *, double *, int,
                                                      hipStream_t);
 template hipError_t allow_fused_lds_narrow<SSCN_REAL_T>(int);
+#else
+template <class R, bool RT>
+void launch_fused_small(const FusedLaunch &f, int parity, const double *pin, double *pout, int use_pin,
+                        hipStream_t st)
+{
+    launch_fused_tile<R, RT>(f, parity, pin, pout, use_pin, st);
+}
+
+template <class R>
+hipError_t allow_fused_lds_small(int W)
+{
+    return allow_fused_lds_tile<R>(W);
+}
+
+template void launch_fused_small<SSCN_REAL_T, false>(const FusedLaunch &, int, const double *, double *, int,
+                                                     hipStream_t);
+template void launch_fused_small<SSCN_REAL_T, true>(const FusedLaunch &, int, const double *, double *, int,
+                                                    hipStream_t);
+template hipError_t allow_fused_lds_small<SSCN_REAL_T>(int);
 #endif
 
 #elif SSCN_PART == 3

@@ -44,10 +44,18 @@ hipError_t timing_event(hipEvent_t *e)
     return hipEventCreateWithFlags(e, hipEventDisableSystemFence);
 }
 
-// Output columns of the fused step's tile shape t (FusedLaunch::tile).
-int fused_tile_cols(int t)
+// Output rows and columns of the fused step's tile shape t
+// (FusedLaunch::tile).
+int fused_tile_rows(int t) { return kFusedTileR[t]; }
+int fused_tile_cols(int t) { return kFusedTileC[t]; }
+
+// The most tiles of any of the fused step's shapes (partial buffers).
+size_t max_fused_tiles(const sscn_handle *h)
 {
-    return t ? kTileCn : kTileC;
+    size_t m = 0;
+    for (int t = 0; t < kFusedTiles; ++t)
+        m = std::max(m, (size_t)h->ntiles_t[t]);
+    return m;
 }
 
 int64_t npoints(const sscn_params &p)
@@ -108,17 +116,20 @@ int setup(sscn_handle *h)
         h->W[0] = h->W[1] = h->W[2] = 0;
         h->nemit = kRedBlocks;
     }
-    for (int t = 0; t < 2; ++t) {
-        const int tc = fused_tile_cols(t);
-        const size_t flds = step2d_lds_elems(kSeg, h->W[0], kTileR, tc) * h->esize;
+    int any = -1;
+    for (int t = 0; t < kFusedTiles; ++t) {
+        const int tr = fused_tile_rows(t), tc = fused_tile_cols(t);
+        const size_t flds = step2d_lds_elems(kSeg, h->W[0], tr, tc) * h->esize;
         h->fused_ok_t[t] = p.dim == 2 && !h->exact && h->W[0] > 0 &&
                            h->W[0] <= (p.precision == SSCN_C128 ? 20 : 32) && flds <= 150 * 1024 &&
                            (h->tile_force < 0 || h->tile_force == t);
-        h->ntiles_t[t] = ((p.nx - 2) / tc + 1) * ((p.ny - 2) / kTileR + 1);
+        h->ntiles_t[t] = ((p.nx - 2) / tc + 1) * ((p.ny - 2) / tr + 1);
+        if (h->fused_ok_t[t] && any < 0)
+            any = t;
     }
-    if (!h->fused_ok_t[h->tile])
-        h->tile = h->fused_ok_t[0] ? 0 : 1;
-    h->fused_ok = h->fused_ok_t[0] || h->fused_ok_t[1];
+    if (!h->fused_ok_t[h->tile] && any >= 0)
+        h->tile = any;
+    h->fused_ok = any >= 0;
     h->ntiles = h->ntiles_t[h->tile];
     return 0;
 }
@@ -230,7 +241,7 @@ int setup_fused(sscn_handle *h)
     in.nx = p.nx;
     in.ny = p.ny;
     in.tiles_x = (p.nx - 2) / fused_tile_cols(h->tile) + 1;
-    in.tiles_y = (p.ny - 2) / kTileR + 1;
+    in.tiles_y = (p.ny - 2) / fused_tile_rows(h->tile) + 1;
     in.poff = 0;
     in.active = 1;
     in.hx = p.hx;
@@ -262,8 +273,7 @@ int setup_fused(sscn_handle *h)
     h->d_work = nullptr;
     h->partials2 = nullptr;
     if (hipMalloc(&h->d_work, sizeof(int2) * wl.size()) != hipSuccess ||
-        hipMalloc(&h->partials2, sizeof(double) * std::max({h->ntiles_t[0], h->ntiles_t[1], kRedBlocks})) !=
-            hipSuccess)
+        hipMalloc(&h->partials2, sizeof(double) * std::max(max_fused_tiles(h), (size_t)kRedBlocks)) != hipSuccess)
         return fail(SSCN_ENOMEM, "hipMalloc of the fused-step work list failed");
     h->inst_host = in;
     HIPCHECK(hipMemcpy(h->d_inst, &in, sizeof in, hipMemcpyHostToDevice));
@@ -561,7 +571,7 @@ void tune_cache_load()
         c.xl = std::atoi(xl + 10);
         c.tile = tl ? std::atoi(tl + 7) : 0;
         c.ms = ms ? (float)std::atof(ms + 14) : 0.f;
-        if ((c.plan == SSCN_PLAN_SWEEPS || c.plan == SSCN_PLAN_FUSED) && c.xl >= 1 && (c.tile == 0 || c.tile == 1))
+        if ((c.plan == SSCN_PLAN_SWEEPS || c.plan == SSCN_PLAN_FUSED) && c.xl >= 1 && c.tile >= 0 && c.tile < kFusedTiles)
             g_tune_cache[std::string(q0 + 1, q1)] = c;
     }
     std::fclose(f);
@@ -646,7 +656,7 @@ int autotune(sscn_handle *h)
             cand.push_back(c);
         }
     }
-    for (int t = 0; t < 2; ++t)
+    for (int t = 0; t < kFusedTiles; ++t)
         if (h->fused_ok_t[t]) {
             TuneChoice c;
             c.plan = SSCN_PLAN_FUSED;
@@ -1282,7 +1292,7 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
     h->psi = psi_dev;
     h->stream = (hipStream_t)hip_stream;
     if (const char *env = std::getenv("SSCN_FUSED_TILE"))
-        h->tile_force = (env[0] == '0') ? 0 : (env[0] == '1') ? 1 : -1;
+        h->tile_force = (env[0] >= '0' && env[0] < '0' + kFusedTiles && env[1] == 0) ? env[0] - '0' : -1;
     r = setup(h);
     if (r) {
         delete h;
@@ -1300,8 +1310,7 @@ int sscn_init(const sscn_params *params, void *psi_dev, void *hip_stream, sscn_h
     r = build_tables(h);
     if (r)
         return bail(r);
-    const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, (size_t)h->ntiles_t[0],
-                                   (size_t)h->ntiles_t[1]});
+    const size_t npart = std::max({(size_t)h->nemit, (size_t)kRedBlocks, max_fused_tiles(h)});
     if (hipMalloc(&h->partials, npart * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_part, (size_t)kRedBlocks * kObsN * sizeof(double)) != hipSuccess ||
         hipMalloc(&h->obs_buf, 64 * sizeof(double)) != hipSuccess)
@@ -1748,8 +1757,7 @@ int sscn_set_mode(sscn_handle *h, int mode, int precision, void *new_psi_dev)
     if (!r)
         r = build_tables(t);
     if (!r) {
-        const size_t npart = std::max({(size_t)t->nemit, (size_t)kRedBlocks, (size_t)t->ntiles_t[0],
-                                       (size_t)t->ntiles_t[1]});
+        const size_t npart = std::max({(size_t)t->nemit, (size_t)kRedBlocks, max_fused_tiles(t)});
         if (hipMalloc(&t->partials, npart * sizeof(double)) != hipSuccess)
             r = fail(SSCN_ENOMEM, "hipMalloc of the partials failed");
     }
@@ -2065,7 +2073,7 @@ int sscn_fused_tile(sscn_handle *h, int *rows, int *cols)
 {
     if (!h || !rows || !cols)
         return fail(SSCN_EINVAL, "null argument");
-    *rows = kTileR;
+    *rows = fused_tile_rows(h->tile);
     *cols = fused_tile_cols(h->tile);
     return 0;
 }

@@ -87,7 +87,7 @@ def test_null_arguments_are_rejected():
 
 def test_fused_tile_launchers_are_local_to_their_compilation():
     """The fused step is compiled once per tile shape (sscn_kernels.hip,
-    parts 2 and 4) with launchers of the same names; they must have internal
+    parts 2, 4 and 5) with launchers of the same names; they must have internal
     linkage, or the linker keeps one shape's instances for both and the
     second shape silently runs the first shape's kernel (the results stay
     right, the work doubles)."""
@@ -98,6 +98,7 @@ def test_fused_tile_launchers_are_local_to_their_compilation():
     P = _lib()
     out = subprocess.run(["nm", "-C", "--defined-only", "--extern-only", P.LIB_PATH], capture_output=True,
                          text=True, check=True).stdout
-    assert "launch_fused_narrow<double, true>" in out  # the dispatch target is exported
+    assert "launch_fused_narrow<double, true>" in out  # the dispatch targets are exported
+    assert "launch_fused_small<double, true>" in out
     for name in ("launch_fused_tile<", "go_fused<", "allow_fused_lds_tile<", "allow_fused_lds<"):
         assert name not in out, name

@@ -97,7 +97,7 @@ def test_prepare_steps_leaves_the_state(P, monkeypatch):
     assert a.observables()["step"] == 0
     a.step(20)
     # the same tile shape (the norm partials are summed per tile)
-    monkeypatch.setenv("SSCN_FUSED_TILE", "0" if a.solver_info()["fused_tile"][1] == 32 else "1")
+    monkeypatch.setenv("SSCN_FUSED_TILE", str([[32, 32], [32, 16], [16, 16]].index(a.solver_info()["fused_tile"])))
     b = P.Solver(W.solver_params(cfg))
     b.init_state(1, ph, 1.0)
     b.set_plan(a.solver_info()["plan"])

@@ -377,14 +377,14 @@ def test_plans_2d(P, plan, mode, prec, shape):
     s.close()
 
 
-@pytest.mark.parametrize("tile", [0, 1])
+@pytest.mark.parametrize("tile", [0, 1, 2])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("prec,shape", [(0, (100, 77)), (1, (96, 70)), (0, (33, 200)), (0, (129, 40))])
 def test_fused_tile_shapes(P, tile, mode, prec, shape, monkeypatch):
-    """The fused step's two tile shapes (32 x 32 and 32 x 16, fixed through
-    SSCN_FUSED_TILE) against the oracle on ragged grids, over graph-replayed
-    steps (an odd count: the buffer hand-back) and, bit for bit, the same
-    steps launched one at a time."""
+    """The fused step's tile shapes (32 x 32, 32 x 16 and 16 x 16, fixed
+    through SSCN_FUSED_TILE) against the oracle on ragged grids, over
+    graph-replayed steps (an odd count: the buffer hand-back) and, bit for
+    bit, the same steps launched one at a time."""
     nx, ny = shape
     announce(f"fused tile={tile} mode={mode} prec={prec} shape={shape}")
     monkeypatch.setenv("SSCN_FUSED_TILE", str(tile))
@@ -396,7 +396,7 @@ def test_fused_tile_shapes(P, tile, mode, prec, shape, monkeypatch):
     s.set_state(psi0)
     s.step(131)
     info = s.solver_info()
-    assert info["plan"] == 2 and info["fused_tile"] == [32, 32 if tile == 0 else 16], info
+    assert info["plan"] == 2 and info["fused_tile"] == [[32, 32], [32, 16], [16, 16]][tile], info
     ref = O.step(op, psi0, 131)
     got = s.get_state()
     assert rel(got.astype(np.complex128), ref) <= (TOL64 if prec == 0 else TOL32)
