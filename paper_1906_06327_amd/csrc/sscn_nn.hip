@@ -254,8 +254,11 @@ int sscn_nn_conv3x3_wgrad(const void *x, int N, int H, int W, int Cin, const voi
         float *bp = scratch + (size_t)nsplit * nw;
         const int bs = bias_splits(P);
         const int bchunk = (P + bs - 1) / bs;
-        hipLaunchKernelGGL(k_bias_grad, dim3(bs), dim3(256), 0, st, (const uint16_t *)dy, P, Cout, bchunk, bp);
-        hipLaunchKernelGGL(k_sum_splits, dim3(blocks(Cout)), dim3(256), 0, st, bp, bs, Cout, db);
+        if (Cout % 8 == 0 && aligned16(dy))
+            hipLaunchKernelGGL(k_bias_grad_v8, dim3(bs), dim3(256), 0, st, (const uint16_t *)dy, P, Cout, bchunk, bp);
+        else
+            hipLaunchKernelGGL(k_bias_grad, dim3(bs), dim3(256), 0, st, (const uint16_t *)dy, P, Cout, bchunk, bp);
+        hipLaunchKernelGGL(k_sum_parts_wave, dim3(Cout), dim3(64), 0, st, bp, bs, Cout, db);
     }
     return launched("conv3x3_wgrad");
 }

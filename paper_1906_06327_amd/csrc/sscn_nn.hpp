@@ -941,6 +941,63 @@ __global__ __launch_bounds__(256) void k_act_bwd_v8(uint16_t *__restrict__ dy, c
     }
 }
 
+// Bias gradient partials as k_bias_grad, 8 channels per thread (16-byte
+// loads; C a multiple of 8): thread t takes channel group q0 + t % qw and
+// pixels t / qw, t / qw + 256 / qw, ... of the split (qw = the groups of one
+// pass, at most 256), and the per-thread sums are added in fixed order
+// through LDS.
+__global__ __launch_bounds__(256) void k_bias_grad_v8(const uint16_t *__restrict__ dy, int P, int C, int chunk,
+                                                      float *__restrict__ part)
+{
+    __shared__ float red[256 * 8];
+    const int s = blockIdx.x;
+    const int pb = s * chunk, pe = min(P, pb + chunk);
+    const int C8 = C / 8;
+    for (int q0 = 0; q0 < C8; q0 += 256) {
+        const int qw = min(256, C8 - q0);
+        const int rows = 256 / qw;
+        const int t = threadIdx.x, q = t % qw, r = t / qw;
+        float acc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (r < rows)
+            for (int p = pb + r; p < pe; p += rows) {
+                float v[8];
+                unpack8(*reinterpret_cast<const uint4 *>(dy + (size_t)p * C + 8 * (q0 + q)), v);
+#pragma unroll
+                for (int k = 0; k < 8; ++k)
+                    acc[k] += v[k];
+            }
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            red[t * 8 + k] = acc[k];
+        __syncthreads();
+        for (int e = t; e < qw * 8; e += 256) {
+            const int gq = e / 8, k = e % 8;
+            float v = 0.f;
+            for (int rr = 0; rr < rows; ++rr)
+                v += red[(rr * qw + gq) * 8 + k];
+            part[(size_t)s * C + 8 * (q0 + gq) + k] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// out[e] = sum over s of part[s][e] for few outputs and many parts: one
+// wave per output, lane l adding parts l, l + 64, ..., then a butterfly over
+// the 64 lanes (a fixed order).
+__global__ __launch_bounds__(64) void k_sum_parts_wave(const float *__restrict__ part, int nsplit, int n,
+                                                       float *__restrict__ out)
+{
+    const int e = blockIdx.x, lane = threadIdx.x;
+    float acc = 0.f;
+    for (int s = lane; s < nsplit; s += 64)
+        acc += part[(size_t)s * n + e];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1)
+        acc += __shfl_xor(acc, off, 64);
+    if (lane == 0)
+        out[e] = acc;
+}
+
 // Phase-aligned loss against K candidate targets per sample (the images of
 // one target under the symmetries of the problem).  Prediction in channels
 // 0,1 of pred (fp32, ld channels, S = H*W points per sample); targets psi

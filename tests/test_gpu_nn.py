@@ -147,6 +147,28 @@ def test_wgrad_many_splits_and_ragged_tail(nn):
     assert torch.equal(dw, dw2)
 
 
+@pytest.mark.parametrize("Cout", [48, 512])
+def test_bias_gradient_channel_groups(nn, Cout):
+    """The bias gradient's 16-byte kernel with channel groups that do not
+    divide the 256 threads (48: 6 groups, 42 pixel rows) and with 64 groups
+    (512), over several pixel splits with a partial last one, against the
+    plain sum; two calls give the same bits."""
+    rng = np.random.default_rng(11)
+    N, H, W, Cin = 1, 40, 52, 16
+    xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
+    dyd, dy = to_bf(rng.standard_normal((N, H, W, Cout)))
+    scr = torch.empty(nn.wgrad_scratch(N, H, W, Cin, Cout), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((Cout, 3, 3, Cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(Cout, dtype=torch.float32, device="cuda")
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw, db, scr)
+    ref = dy.reshape(-1, Cout).astype(np.float64).sum(axis=0)
+    asum = np.abs(dy).reshape(-1, Cout).astype(np.float64).sum(axis=0)
+    assert np.all(np.abs(db.cpu().numpy() - ref) <= 1e-5 * asum + 1e-6)
+    db2 = torch.zeros_like(db)
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw, db2, scr)
+    assert torch.equal(db, db2)
+
+
 # C = 32 with channel offsets that are multiples of 8 takes the 16-byte
 # kernels, C = 20 with odd offsets the element-wise ones
 @pytest.mark.parametrize("C,uoff,soff,doff,cc", [(32, 16, 8, 8, 24), (20, 4, 3, 5, 12)])
