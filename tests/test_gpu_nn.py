@@ -147,6 +147,25 @@ def test_wgrad_many_splits_and_ragged_tail(nn):
     assert torch.equal(dw, dw2)
 
 
+def test_wgrad_wave_summed_ranges(nn):
+    """An image large enough for more than 64 pixel ranges (2 x 192 x 192 =
+    73 728 pixels: 72 ranges), whose partial weight gradients are summed one
+    wave per weight, against the reference; two calls give the same bits."""
+    rng = np.random.default_rng(12)
+    N, H, W, Cin, Cout = 2, 192, 192, 16, 16
+    xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
+    dyd, dy = to_bf(rng.standard_normal((N, H, W, Cout)))
+    scr = torch.empty(nn.wgrad_scratch(N, H, W, Cin, Cout), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((Cout, 3, 3, Cin), dtype=torch.float32, device="cuda")
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw, None, scr)
+    rdw, _ = U.conv3x3_wgrad(x, dy)
+    adw, _ = U.conv3x3_wgrad(np.abs(x), np.abs(dy))
+    assert np.all(np.abs(dw.cpu().numpy() - rdw) <= 1e-5 * adw + 1e-30)
+    dw2 = torch.zeros_like(dw)
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw2, None, scr)
+    assert torch.equal(dw, dw2)
+
+
 @pytest.mark.parametrize("Cout", [48, 512])
 def test_bias_gradient_channel_groups(nn, Cout):
     """The bias gradient's 16-byte kernel with channel groups that do not
