@@ -258,8 +258,16 @@ int sscn_nn_conv3x3_wgrad(const void *x, int N, int H, int W, int Cin, const voi
     chunk = (chunk + 15) / 16 * 16;
     hipStream_t st = (hipStream_t)stream;
     const int cw = Cin % 32 == 0 ? 32 : 16;
-    hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsplit, (Cout + 63) / 64, 9 * Cin / cw), dim3(256), 0, st,
-                       (const uint16_t *)x, N, H, W, Cin, (const uint16_t *)dy, Cout, chunk, scratch);
+    // 32 or 16 output channels: several taps per block share the dy tile
+    if (Cout == 32)
+        hipLaunchKernelGGL(k_conv3x3_wgrad_narrow<32>, dim3(nsplit, 1, 5 * (Cin / cw)), dim3(256), 0, st,
+                           (const uint16_t *)x, N, H, W, Cin, (const uint16_t *)dy, Cout, chunk, scratch);
+    else if (Cout == 16)
+        hipLaunchKernelGGL(k_conv3x3_wgrad_narrow<16>, dim3(nsplit, 1, 3 * (Cin / cw)), dim3(256), 0, st,
+                           (const uint16_t *)x, N, H, W, Cin, (const uint16_t *)dy, Cout, chunk, scratch);
+    else
+        hipLaunchKernelGGL(k_conv3x3_wgrad, dim3(nsplit, (Cout + 63) / 64, 9 * Cin / cw), dim3(256), 0, st,
+                           (const uint16_t *)x, N, H, W, Cin, (const uint16_t *)dy, Cout, chunk, scratch);
     const int nw = Cout * 9 * Cin;
     // many ranges (the large images, whose weights are few): one wave per
     // weight; else one thread per weight

@@ -681,6 +681,116 @@ __global__ __launch_bounds__(256) void k_conv3x3_wgrad(const uint16_t *__restric
         }
 }
 
+// The weight gradient for layers with CO = 32 or 16 output channels: the
+// same GEMM, but a block stages the dy tile of its CO channels once and
+// applies it to TPB = 64 / CO taps (the x tiles of those taps staged side
+// by side), so that the four waves are all busy: wave w takes output rows
+// 16 (w % (CO / 16)) .. + 15 of tap slot w / (CO / 16).  Block z covers
+// taps TPB * (z / ncw) .. + TPB - 1 (those past the ninth idle) and input
+// channels (z % ncw) CW .. + CW - 1.  Each wave's products run in the same
+// order as in k_conv3x3_wgrad.
+template <int CO>
+__global__ __launch_bounds__(256) void k_conv3x3_wgrad_narrow(const uint16_t *__restrict__ x, int N, int H, int W,
+                                                             int Cin, const uint16_t *__restrict__ dy, int Cout,
+                                                             int chunk, float *__restrict__ part)
+{
+    constexpr int TPB = 64 / CO, FR = CO / 16;
+    __shared__ __align__(16) uint16_t sA[CO * kConvLd];        // dy^T: CO channels x 32 pixels
+    __shared__ __align__(16) uint16_t sB[TPB * 32 * kConvLd];  // x^T per tap slot: CW channels x 32 pixels
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, g = lane >> 4;
+    const int s = blockIdx.x;
+    const int CW = (Cin % 32 == 0) ? 32 : 16;
+    const int ncw = Cin / CW;
+    const int tap0 = TPB * (blockIdx.z / ncw), ci0 = (blockIdx.z % ncw) * CW;
+    const int P = N * H * W;
+    const int pb = s * chunk, pe = min(P, pb + chunk);
+    const int wfr = wave % FR, wslot = wave / FR;
+    const bool wtap = tap0 + wslot < 9;
+    v4f acc[2] = {v4f{0.f, 0.f, 0.f, 0.f}, v4f{0.f, 0.f, 0.f, 0.f}};
+    // staging roles: dy: thread t < 4 CO takes 8 channels (t % (CO/8)) of
+    // pixel t / (CO/8); x: item e < TPB 32 (CW/8) (thread t takes e = t,
+    // t + 256) is tap slot e / (4 CW), then 8 channels of one of the 32
+    // pixels
+    constexpr int aq = CO / 8;
+    constexpr int NBX = (TPB * 32 * 4 + 255) / 256;  // x items per thread at CW = 32
+    const int ap = tid / aq, apart = tid - ap * aq;
+    const int bq = CW / 8;
+    const int nbx = TPB * 32 * bq;
+    for (int k0 = pb; k0 < pe; k0 += 32) {
+        uint4 ra = make_uint4(0u, 0u, 0u, 0u), rb[NBX];
+        if (ap < 32) {
+            const int p = k0 + ap;
+            if (p < pe)
+                ra = *reinterpret_cast<const uint4 *>(dy + (size_t)p * Cout + apart * 8);
+        }
+#pragma unroll
+        for (int i = 0; i < NBX; ++i) {
+            const int e = tid + 256 * i;
+            rb[i] = make_uint4(0u, 0u, 0u, 0u);
+            const int bslot = e / (32 * bq), bt = e - bslot * 32 * bq;
+            const int bp = bt / bq, bpart = bt - bp * bq;
+            const int btap = tap0 + bslot;
+            const int p = k0 + bp;
+            if (e < nbx && btap < 9 && p < pe) {
+                const int n = p / (H * W), r = p - n * H * W;
+                const int yy = r / W, xx = r - yy * W;
+                const int sy = yy + btap / 3 - 1, sx = xx + btap % 3 - 1;
+                if (sy >= 0 && sy < H && sx >= 0 && sx < W)
+                    rb[i] = *reinterpret_cast<const uint4 *>(x + ((size_t)(n * H + sy) * W + sx) * Cin + ci0 +
+                                                             bpart * 8);
+            }
+        }
+        __syncthreads();  // the previous chunk's fragment reads are done
+        {
+            const uint16_t *va = reinterpret_cast<const uint16_t *>(&ra);
+            if (ap < 32) {
+#pragma unroll
+                for (int j = 0; j < 8; ++j)
+                    sA[(apart * 8 + j) * kConvLd + ap] = va[j];
+            }
+#pragma unroll
+            for (int i = 0; i < NBX; ++i) {
+                const int e = tid + 256 * i;
+                if (e < nbx) {
+                    const int bslot = e / (32 * bq), bt = e - bslot * 32 * bq;
+                    const int bp = bt / bq, bpart = bt - bp * bq;
+                    const uint16_t *vb = reinterpret_cast<const uint16_t *>(&rb[i]);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        sB[(bslot * 32 + bpart * 8 + j) * kConvLd + bp] = vb[j];
+                }
+            }
+        }
+        __syncthreads();
+        if (wtap) {
+#pragma unroll
+            for (int k16 = 0; k16 < 2; ++k16) {
+                const v4s a = lds4(&sA[(wfr * 16 + m) * kConvLd + k16 * 16 + 4 * g]);
+#pragma unroll
+                for (int f = 0; f < 2; ++f)
+                    if (f * 16 < CW) {
+                        const v4s b = lds4(&sB[(wslot * 32 + f * 16 + m) * kConvLd + k16 * 16 + 4 * g]);
+                        acc[f] = mfma16(a, b, acc[f]);
+                    }
+            }
+        }
+    }
+    if (!wtap)
+        return;
+    // D[row = 16 wfr + 4g + i][col = tap Cin + ci0 + 16f + m]
+    const int ncols = 9 * Cin, tap = tap0 + wslot;
+#pragma unroll
+    for (int f = 0; f < 2; ++f)
+        if (f * 16 < CW) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int co = wfr * 16 + 4 * g + i;
+                part[((size_t)s * Cout + co) * ncols + tap * Cin + ci0 + f * 16 + m] = acc[f][i];
+            }
+        }
+}
+
 // out[e] = sum over s of part[s][e] in a fixed order (fp32).
 __global__ __launch_bounds__(256) void k_sum_splits(const float *__restrict__ part, int nsplit, int n,
                                                     float *__restrict__ out)

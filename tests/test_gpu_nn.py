@@ -147,6 +147,30 @@ def test_wgrad_many_splits_and_ragged_tail(nn):
     assert torch.equal(dw, dw2)
 
 
+@pytest.mark.parametrize("Cin,Cout", [(32, 32), (16, 32), (64, 32), (32, 16), (48, 16)])
+def test_wgrad_narrow_outputs(nn, Cin, Cout):
+    """32 and 16 output channels take the weight-gradient kernel whose
+    blocks apply one staged dy tile to 2 or 4 taps (the ninth tap alone in
+    the last group), with 32- and 16-channel input slices, over several
+    pixel ranges with a partial last one; against the reference, and two
+    calls give the same bits."""
+    rng = np.random.default_rng(13)
+    N, H, W = 2, 29, 41
+    xd, x = to_bf(rng.standard_normal((N, H, W, Cin)))
+    dyd, dy = to_bf(rng.standard_normal((N, H, W, Cout)))
+    scr = torch.empty(nn.wgrad_scratch(N, H, W, Cin, Cout), dtype=torch.float32, device="cuda")
+    dw = torch.zeros((Cout, 3, 3, Cin), dtype=torch.float32, device="cuda")
+    db = torch.zeros(Cout, dtype=torch.float32, device="cuda")
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw, db, scr)
+    rdw, rdb = U.conv3x3_wgrad(x, dy)
+    adw, _ = U.conv3x3_wgrad(np.abs(x), np.abs(dy))
+    assert np.all(np.abs(dw.cpu().numpy() - rdw) <= 1e-5 * adw + 1e-30)
+    assert np.allclose(db.cpu().numpy(), rdb, rtol=1e-5, atol=1e-3)
+    dw2 = torch.zeros_like(dw)
+    nn.conv3x3_wgrad(xd, N, H, W, Cin, dyd, Cout, dw2, None, scr)
+    assert torch.equal(dw, dw2)
+
+
 def test_wgrad_wave_summed_ranges(nn):
     """An image large enough for more than 64 pixel ranges (2 x 192 x 192 =
     73 728 pixels: 72 ranges), whose partial weight gradients are summed one
