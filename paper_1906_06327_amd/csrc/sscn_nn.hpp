@@ -205,6 +205,77 @@ constexpr int conv_mfma_ld() { return KC + 8; }
 template <int BN, int KC>
 constexpr int conv_mfma_lds_bytes() { return 2 * (128 + BN) * conv_mfma_ld<KC>() * 2; }
 
+// Staging of a block's 128 x BN outputs for vector stores: rows of BN
+// values padded by 16 bytes.
+template <bool F32, int BN>
+constexpr int conv_out_ld() { return BN + (F32 ? 4 : 8); }
+template <bool F32, int BN>
+constexpr int conv_out_lds_bytes() { return 128 * conv_out_ld<F32, BN>() * (F32 ? 4 : 2); }
+
+// True if output rows y + p * ldy + off (in values) start on 16 bytes for
+// every pixel p, so that a pixel's run of channels can leave in 16-byte
+// stores.
+template <bool F32>
+__device__ __forceinline__ bool conv_out_vec_ok(const void *y, int ldy, int off)
+{
+    constexpr int q = F32 ? 4 : 8;
+    return ldy % q == 0 && off % q == 0 && (reinterpret_cast<uintptr_t>(y) & 15) == 0;
+}
+
+// The block's 128 x BN outputs, act(acc + bias), stored through LDS: each
+// wave writes its fragments (lane m, g of fragment (i, j) holds pixels
+// 4g..4g+3 of row block i, channel m of column block j) into a [128][BN]
+// staging tile, then every thread stores 16-byte runs of one pixel's
+// channels.  A fragment store of the lanes would otherwise write 2- or
+// 4-byte values, 16 channels of 4 pixels per instruction.  pix(pm) is the
+// output pixel of block pixel pm (-1: none); outputs go to y[pix * ldy +
+// off + c], c < BN, with conv_out_vec_ok(y, ldy, off).  The staging tile
+// reuses the kernel's LDS: the caller's last use of it must be behind a
+// barrier.
+template <int ACT, bool F32, int BN, int WM, int FM, int FN, class Pix>
+__device__ __forceinline__ void conv_store_vec(const v4f (&acc)[FM][FN], const float *bias, void *y, int ldy, int off,
+                                               void *smem, Pix pix)
+{
+    constexpr int WN = 4 / WM, TM = 128 / WM, TN = BN / WN;
+    constexpr int OE = F32 ? 4 : 2;
+    constexpr int LDO = conv_out_ld<F32, BN>();
+    constexpr int NPART = BN * OE / 16;  // 16-byte parts of a pixel's outputs
+    static_assert(NPART >= 2 && 128 * NPART % 256 == 0, "whole parts per thread");
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int m = lane & 15, g = lane >> 4;
+    const int wm = wave % WM, wn = wave / WM;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int c = wn * TN + j * 16 + m;
+        const float bv = bias ? bias[c] : 0.f;
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int pm = wm * TM + i * 16 + 4 * g + r;
+                float v = acc[i][j][r] + bv;
+                if (ACT == ACT_LEAKY)
+                    v = v > 0.f ? v : kLeak * v;
+                if (F32)
+                    reinterpret_cast<float *>(smem)[pm * LDO + c] = v;
+                else
+                    reinterpret_cast<uint16_t *>(smem)[pm * LDO + c] = f2bf(v);
+            }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 128 * NPART / 256; ++s) {
+        const int e = tid + 256 * s;
+        const int pm = e / NPART, part = e - pm * NPART;
+        const int64_t pp = pix(pm);
+        if (pp >= 0) {
+            const uint4 v = *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(smem) +
+                                                             (size_t)pm * LDO * OE + part * 16);
+            *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(y) + ((size_t)pp * ldy + off) * OE + part * 16) = v;
+        }
+    }
+}
+
 template <int ACT, bool OUTF32, int BN, int WM, int KC, bool SPLIT>
 __global__ __launch_bounds__(256, 2) void k_conv3x3_mfma(const uint16_t *__restrict__ x, int N, int H, int W,
                                                          int Cin, const uint16_t *__restrict__ w,
@@ -344,6 +415,21 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_mfma(const uint16_t *__restr
             store_stage(0, r0);
         __syncthreads();
     }
+    // the loop ended on a barrier: the staging LDS is free
+    auto pix = [&](int pm) -> int64_t { return p0 + pm < P ? (int64_t)p0 + pm : -1; };
+    if constexpr (SPLIT && conv_out_lds_bytes<true, BN>() <= conv_mfma_lds_bytes<BN, KC>()) {
+        float *part = reinterpret_cast<float *>(y) + (size_t)z * P * Cout;
+        if (conv_out_vec_ok<true>(part, Cout, co0)) {
+            conv_store_vec<ACT_NONE, true, BN, WM>(acc, nullptr, part, Cout, co0, conv_smem, pix);
+            return;
+        }
+    }
+    if constexpr (!SPLIT && conv_out_lds_bytes<OUTF32, BN>() <= conv_mfma_lds_bytes<BN, KC>()) {
+        if (conv_out_vec_ok<OUTF32>(y, ldy, yoff)) {
+            conv_store_vec<ACT, OUTF32, BN, WM>(acc, bias ? bias + co0 : nullptr, y, ldy, yoff + co0, conv_smem, pix);
+            return;
+        }
+    }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int co = co0 + wn * TN + j * 16 + m;
@@ -388,6 +474,10 @@ constexpr int kHaloPix = (kPatchH + 2) * (kPatchW + 2);
 
 template <int BN, int KC, int TG>
 constexpr int conv_halo_lds_bytes() { return 2 * (kHaloPix + TG * BN) * conv_mfma_ld<KC>() * 2; }
+// With one chunk of input channels (Cin <= KC) the patch is staged once and
+// needs one buffer: less LDS per block, more blocks per CU.
+template <int BN, int KC, int TG>
+constexpr int conv_halo_lds_bytes_1() { return (kHaloPix + 2 * TG * BN) * conv_mfma_ld<KC>() * 2; }
 
 template <int ACT, bool OUTF32, int BN, int WM, int KC, int TG>
 __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restrict__ x, int N, int H, int W,
@@ -407,8 +497,6 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
     static_assert(BM == kPatchH * kPatchW, "the block's pixels are one patch");
     static_assert(TG == 1 || TG == 3, "whole stencil rows or single taps");
     extern __shared__ __align__(16) uint16_t conv_smem[];
-    uint16_t *sP = conv_smem;                      // [2][kHaloPix][LD]
-    uint16_t *sB = conv_smem + 2 * kHaloPix * LD;  // [2][TG][BN][LD]
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int m = lane & 15, g = lane >> 4;
     const int wm = wave % WM, wn = wave / WM;
@@ -420,6 +508,8 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
     const int kc = Cin % KC == 0 ? KC : 16;
     const int ncc = Cin / kc;
     const int nk = SPC * ncc;
+    uint16_t *sP = conv_smem;                                   // [1 or 2][kHaloPix][LD]
+    uint16_t *sB = conv_smem + (ncc > 1 ? 2 : 1) * kHaloPix * LD;  // [2][TG][BN][LD]
     uint4 rp[NP];
     auto load_patch = [&](int c) {
         const int c0 = c * kc;
@@ -536,6 +626,16 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
         if (t + 2 < nk)
             store_w(0, r0);
         __syncthreads();
+    }
+    // the loop ended on a barrier: the staging LDS is free
+    if constexpr (conv_out_lds_bytes<OUTF32, BN>() <= conv_halo_lds_bytes_1<BN, KC, TG>()) {
+        if (conv_out_vec_ok<OUTF32>(y, ldy, yoff)) {
+            auto pix = [&](int pm) -> int64_t {
+                return (int64_t)(bn * H + by * kPatchH + pm / kPatchW) * W + bx * kPatchW + pm % kPatchW;
+            };
+            conv_store_vec<ACT, OUTF32, BN, WM>(acc, bias ? bias + co0 : nullptr, y, ldy, yoff + co0, conv_smem, pix);
+            return;
+        }
     }
 #pragma unroll
     for (int j = 0; j < FN; ++j) {

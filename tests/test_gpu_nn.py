@@ -92,6 +92,14 @@ def test_conv3x3(nn, N, H, W, Cin, Cout, act):
     close_bf(gb[..., off:off + Cout], ref, absum, "conv bf16")
     untouched = ybf.cpu().numpy()
     assert np.all(untouched[..., :off] == 7) and np.all(untouched[..., off + Cout:] == 7)
+    # the same values where the rows are not 16-byte aligned (per-value
+    # stores instead of the staged 16-byte runs)
+    ld2, off2 = Cout + 12, 4
+    yb2 = torch.full((N, H, W, ld2), 7, dtype=torch.int16, device="cuda")
+    nn.conv3x3(xd, N, H, W, Cin, wd, f32(b), Cout, act, yb2, ldy=ld2, yoff=off2)
+    g2 = yb2.cpu().numpy()
+    assert np.array_equal(g2[..., off2:off2 + Cout], untouched[..., off:off + Cout])
+    assert np.all(g2[..., :off2] == 7) and np.all(g2[..., off2 + Cout:] == 7)
 
 
 def test_conv3x3_dgrad_and_wgrad(nn):
