@@ -88,6 +88,14 @@ void go_conv_mfma(const uint16_t *x, int N, int H, int W, int Cin, const uint16_
         hipLaunchKernelGGL((k_conv3x3_mfma<ACT, OUTF32, BN, WM, KC, true>), dim3((P + 127) / 128, Cout / BN, nsplit),
                            dim3(256), lds, st, x, N, H, W, Cin, w, bias, Cout, (void *)ws, Cout, 0, nsplit);
         const int64_t n = (int64_t)P * Cout;
+        const uintptr_t run = OUTF32 ? 16 : 8;  // bytes of 4 output values
+        if (Cout % 4 == 0 && ldy % 4 == 0 && yoff % 4 == 0 && reinterpret_cast<uintptr_t>(y) % run == 0 &&
+            reinterpret_cast<uintptr_t>(ws) % 16 == 0 && (!bias || reinterpret_cast<uintptr_t>(bias) % 16 == 0)) {
+            const int grid = (int)std::min<int64_t>(8192, (n / 4 + 255) / 256);
+            hipLaunchKernelGGL((k_conv_split_sum_v4<ACT, OUTF32>), dim3(grid), dim3(256), 0, st, (const float *)ws,
+                               nsplit, P, Cout, bias, y, ldy, yoff);
+            return;
+        }
         const int grid = (int)std::min<int64_t>(8192, (n + 255) / 256);
         hipLaunchKernelGGL((k_conv_split_sum<ACT, OUTF32>), dim3(grid), dim3(256), 0, st, (const float *)ws, nsplit,
                            P, Cout, bias, y, ldy, yoff);

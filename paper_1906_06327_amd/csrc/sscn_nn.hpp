@@ -684,6 +684,51 @@ __global__ __launch_bounds__(256) void k_conv_split_sum(const float *__restrict_
     }
 }
 
+// The same sums four channels per thread (16-byte partial and bias loads),
+// for C, ldy and yoff multiples of 4 and y aligned to the output's 4-value
+// run: the same arithmetic per value, so the same bits.
+template <int ACT, bool OUTF32>
+__global__ __launch_bounds__(256) void k_conv_split_sum_v4(const float *__restrict__ part, int nsplit, int P, int C,
+                                                          const float *__restrict__ bias, void *__restrict__ y,
+                                                          int ldy, int yoff)
+{
+    const int64_t n = (int64_t)P * C, n4 = n / 4;
+    for (int64_t e4 = (int64_t)blockIdx.x * 256 + threadIdx.x; e4 < n4; e4 += (int64_t)gridDim.x * 256) {
+        const int64_t e = e4 * 4;
+        const int c = (int)(e % C);
+        const int64_t p = e / C;
+        float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+        for (int z = 0; z < nsplit; ++z) {
+            const float4 q = *reinterpret_cast<const float4 *>(part + (size_t)z * n + e);
+            v.x += q.x;
+            v.y += q.y;
+            v.z += q.z;
+            v.w += q.w;
+        }
+        if (bias) {
+            const float4 b = *reinterpret_cast<const float4 *>(bias + c);
+            v.x += b.x;
+            v.y += b.y;
+            v.z += b.z;
+            v.w += b.w;
+        }
+        if (ACT == ACT_LEAKY) {
+            v.x = v.x > 0.f ? v.x : kLeak * v.x;
+            v.y = v.y > 0.f ? v.y : kLeak * v.y;
+            v.z = v.z > 0.f ? v.z : kLeak * v.z;
+            v.w = v.w > 0.f ? v.w : kLeak * v.w;
+        }
+        if (OUTF32) {
+            *reinterpret_cast<float4 *>(reinterpret_cast<float *>(y) + p * ldy + yoff + c) = v;
+        } else {
+            uint2 o;
+            o.x = (uint32_t)f2bf(v.x) | ((uint32_t)f2bf(v.y) << 16);
+            o.y = (uint32_t)f2bf(v.z) | ((uint32_t)f2bf(v.w) << 16);
+            *reinterpret_cast<uint2 *>(reinterpret_cast<uint16_t *>(y) + p * ldy + yoff + c) = o;
+        }
+    }
+}
+
 // Weights of the input-gradient convolution: wt[ci][8 - tap][co] = w[co][tap][ci].
 __global__ __launch_bounds__(256) void k_wflip(const uint16_t *__restrict__ w, int Cout, int Cin,
                                                uint16_t *__restrict__ wt)

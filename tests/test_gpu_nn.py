@@ -94,12 +94,24 @@ def test_conv3x3(nn, N, H, W, Cin, Cout, act):
     assert np.all(untouched[..., :off] == 7) and np.all(untouched[..., off + Cout:] == 7)
     # the same values where the rows are not 16-byte aligned (per-value
     # stores instead of the staged 16-byte runs)
-    ld2, off2 = Cout + 12, 4
+    ld2, off2 = Cout + 6, 2
     yb2 = torch.full((N, H, W, ld2), 7, dtype=torch.int16, device="cuda")
     nn.conv3x3(xd, N, H, W, Cin, wd, f32(b), Cout, act, yb2, ldy=ld2, yoff=off2)
     g2 = yb2.cpu().numpy()
     assert np.array_equal(g2[..., off2:off2 + Cout], untouched[..., off:off + Cout])
     assert np.all(g2[..., :off2] == 7) and np.all(g2[..., off2 + Cout:] == 7)
+    # split K sums into both slices: four channels per thread where 4-value
+    # runs are 8-byte aligned, one where not, with the same bits
+    if nws > 0:
+        got = []
+        for l, o in ((ld, off), (ld2, off2)):
+            ys = torch.full((N, H, W, l), 7, dtype=torch.int16, device="cuda")
+            nn.conv3x3(xd, N, H, W, Cin, wd, f32(b), Cout, act, ys, ldy=l, yoff=o, ws=ws)
+            gs = ys.cpu().numpy()
+            close_bf(from_bf(ys)[..., o:o + Cout], ref, absum, "conv bf16 split")
+            assert np.all(gs[..., :o] == 7) and np.all(gs[..., o + Cout:] == 7)
+            got.append(gs[..., o:o + Cout])
+        assert np.array_equal(got[0], got[1])
 
 
 def test_conv3x3_dgrad_and_wgrad(nn):
