@@ -116,11 +116,8 @@ void go_conv_halo(const uint16_t *x, int N, int H, int W, int Cin, const uint16_
     constexpr int lds = conv_halo_lds_bytes<BN, 32, TG>();
     if (conv_lds_once(k_conv3x3_halo<ACT, OUTF32, BN, WM, 32, TG>, lds) != hipSuccess)
         return;  // reported by launched()
-    // one input chunk (the kernel's kc, ncc): one patch buffer
-    const int kc = Cin % 32 == 0 ? 32 : 16;
-    const int lds_used = Cin / kc > 1 ? lds : conv_halo_lds_bytes_1<BN, 32, TG>();
     hipLaunchKernelGGL((k_conv3x3_halo<ACT, OUTF32, BN, WM, 32, TG>), dim3(N * (H / kPatchH) * (W / kPatchW), Cout / BN),
-                       dim3(256), lds_used, st, x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff);
+                       dim3(256), lds, st, x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff);
 }
 
 // The halo-patch kernel takes images whose sides are multiples of the patch

@@ -466,18 +466,16 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_mfma(const uint16_t *__restr
 // (chunk, group of TG taps) with the weights of TG taps per stage (TG = 3,
 // a row of the stencil, for narrow layers: more products per barrier),
 // double-buffered and loaded two stages ahead as in k_conv3x3_mfma; the
-// next chunk's patch is loaded during the current chunk's first stage and
-// written to the other patch buffer after its last.  Output as k_conv3x3.
+// next chunk's patch is loaded into registers during the current chunk's
+// first stage and written over the one patch buffer behind a barrier after
+// its last (one buffer: less LDS per block, more blocks per CU).  Output as
+// k_conv3x3.
 // Grid: (N (H / 8) (W / 16), Cout / BN), 256 threads.
 constexpr int kPatchH = 8, kPatchW = 16;
 constexpr int kHaloPix = (kPatchH + 2) * (kPatchW + 2);
 
 template <int BN, int KC, int TG>
-constexpr int conv_halo_lds_bytes() { return 2 * (kHaloPix + TG * BN) * conv_mfma_ld<KC>() * 2; }
-// With one chunk of input channels (Cin <= KC) the patch is staged once and
-// needs one buffer: less LDS per block, more blocks per CU.
-template <int BN, int KC, int TG>
-constexpr int conv_halo_lds_bytes_1() { return (kHaloPix + 2 * TG * BN) * conv_mfma_ld<KC>() * 2; }
+constexpr int conv_halo_lds_bytes() { return (kHaloPix + 2 * TG * BN) * conv_mfma_ld<KC>() * 2; }
 
 template <int ACT, bool OUTF32, int BN, int WM, int KC, int TG>
 __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restrict__ x, int N, int H, int W,
@@ -508,8 +506,8 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
     const int kc = Cin % KC == 0 ? KC : 16;
     const int ncc = Cin / kc;
     const int nk = SPC * ncc;
-    uint16_t *sP = conv_smem;                                   // [1 or 2][kHaloPix][LD]
-    uint16_t *sB = conv_smem + (ncc > 1 ? 2 : 1) * kHaloPix * LD;  // [2][TG][BN][LD]
+    uint16_t *sP = conv_smem;                  // [kHaloPix][LD]
+    uint16_t *sB = conv_smem + kHaloPix * LD;  // [2][TG][BN][LD]
     uint4 rp[NP];
     auto load_patch = [&](int c) {
         const int c0 = c * kc;
@@ -565,7 +563,7 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
     // stage s: chunk s / SPC (patch buffer (s / SPC) & 1), weights in buffer wb
     auto compute = [&](int s, int wb) {
         const int c = s / SPC, tap0 = (s - SPC * c) * TG;
-        const uint16_t *cP = sP + (size_t)(c & 1) * kHaloPix * LD;
+        const uint16_t *cP = sP;
 #pragma unroll
         for (int tg = 0; tg < TG; ++tg) {
             const int tap = tap0 + tg;
@@ -590,14 +588,20 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
             }
         }
     };
-    // the patch of the next chunk: loaded at its predecessor's first stage,
-    // stored after its predecessor's last
-    auto patch_io = [&](int s, bool before) {
+    // the patch of the next chunk: loaded at its predecessor's first stage;
+    // stored after the barrier that ends its predecessor's last, then a
+    // barrier before the first stage that reads it
+    auto patch_load = [&](int s) {
         const int c = s / SPC, q = s - SPC * c;
-        if (before && q == 0 && c + 1 < ncc)
+        if (q == 0 && c + 1 < ncc)
             load_patch(c + 1);
-        if (!before && q == SPC - 1 && c + 1 < ncc)
-            store_patch((c + 1) & 1);
+    };
+    auto patch_flush = [&](int s) {
+        const int c = s / SPC, q = s - SPC * c;
+        if (q == SPC - 1 && c + 1 < ncc) {
+            store_patch(0);
+            __syncthreads();
+        }
     };
     Regs r0, r1;
     load_patch(0);
@@ -610,25 +614,25 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
     for (int t = 0; t < nk; t += 2) {
         if (t + 2 < nk)
             load_w(t + 2, r0);
-        patch_io(t, true);
+        patch_load(t);
         compute(t, 0);
-        patch_io(t, false);
         if (t + 1 < nk)
             store_w(1, r1);
         __syncthreads();
+        patch_flush(t);
         if (t + 1 >= nk)
             break;
         if (t + 3 < nk)
             load_w(t + 3, r1);
-        patch_io(t + 1, true);
+        patch_load(t + 1);
         compute(t + 1, 1);
-        patch_io(t + 1, false);
         if (t + 2 < nk)
             store_w(0, r0);
         __syncthreads();
+        patch_flush(t + 1);
     }
     // the loop ended on a barrier: the staging LDS is free
-    if constexpr (conv_out_lds_bytes<OUTF32, BN>() <= conv_halo_lds_bytes_1<BN, KC, TG>()) {
+    if constexpr (conv_out_lds_bytes<OUTF32, BN>() <= conv_halo_lds_bytes<BN, KC, TG>()) {
         if (conv_out_vec_ok<OUTF32>(y, ldy, yoff)) {
             auto pix = [&](int pm) -> int64_t {
                 return (int64_t)(bn * H + by * kPatchH + pm / kPatchW) * W + bx * kPatchW + pm % kPatchW;
