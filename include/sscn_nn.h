@@ -43,6 +43,20 @@ extern "C" {
 int sscn_nn_conv3x3(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
                     int act, int out_f32, void *y, int ldy, int yoff, float *ws, int64_t ws_floats, void *stream);
 
+/* A convolution with bf16 outputs (as sscn_nn_conv3x3 with out_f32 = 0)
+ * followed by the 2 x 2 average pooling of its outputs (as sscn_nn_pool2 of
+ * y, ldy, yoff with C = Cout) into pool_y, N x H/2 x W/2 x Cout bf16: the
+ * encoder's second convolution of a level and the pooling into the next
+ * (Sec. 3, the network's contracting path).  H and W even.  Where the
+ * halo-patch kernel runs with its staged 16-byte stores (sides multiples of
+ * 8 x 16, ldy and yoff multiples of 8, y and pool_y 16-byte aligned, no K
+ * split) the pooling is taken from the staged output tile in the same
+ * kernel; otherwise the two operations run one after the other.  Both give
+ * the same bits.  Returns -1 for bad arguments, like sscn_nn_conv3x3. */
+int sscn_nn_conv3x3_pool(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
+                         int act, void *y, int ldy, int yoff, void *pool_y, float *ws, int64_t ws_floats,
+                         void *stream);
+
 /* fp32 workspace elements a convolution of these sizes uses to split its K
  * sum (0: it is not split).  For the input gradient of a convolution with
  * Cin inputs and Cout outputs, ask for (Cin = Cout, Cout = Cin). */

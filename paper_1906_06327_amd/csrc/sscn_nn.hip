@@ -109,7 +109,7 @@ void go_conv_mfma(const uint16_t *x, int N, int H, int W, int Cin, const uint16_
 
 template <int ACT, bool OUTF32, int BN, int WM>
 void go_conv_halo(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
-                  void *y, int ldy, int yoff, hipStream_t st)
+                  void *y, int ldy, int yoff, hipStream_t st, uint16_t *pool)
 {
     // narrow layers stage a stencil row of taps per K stage
     constexpr int TG = BN <= 32 ? 3 : 1;
@@ -117,7 +117,7 @@ void go_conv_halo(const uint16_t *x, int N, int H, int W, int Cin, const uint16_
     if (conv_lds_once(k_conv3x3_halo<ACT, OUTF32, BN, WM, 32, TG>, lds) != hipSuccess)
         return;  // reported by launched()
     hipLaunchKernelGGL((k_conv3x3_halo<ACT, OUTF32, BN, WM, 32, TG>), dim3(N * (H / kPatchH) * (W / kPatchW), Cout / BN),
-                       dim3(256), lds, st, x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff);
+                       dim3(256), lds, st, x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, pool);
 }
 
 // The halo-patch kernel takes images whose sides are multiples of the patch
@@ -143,7 +143,8 @@ void launch_conv_kc(const uint16_t *x, int N, int H, int W, int Cin, const uint1
 // ws: nsplit * P * Cout floats when nsplit > 1 (conv_splits), else unused.
 template <int ACT, bool OUTF32>
 void launch_conv(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t *w, const float *bias, int Cout,
-                 void *y, int ldy, int yoff, hipStream_t st, float *ws = nullptr, int nsplit = 1)
+                 void *y, int ldy, int yoff, hipStream_t st, float *ws = nullptr, int nsplit = 1,
+                 uint16_t *pool = nullptr)
 {
     const int P = N * H * W;
     if (SSCN_NN_CONV_LEGACY) {
@@ -160,10 +161,10 @@ void launch_conv(const uint16_t *x, int N, int H, int W, int Cin, const uint16_t
     }
     if (nsplit <= 1 && conv_halo_ok(N, H, W, Cout)) {
         switch (conv_bn(Cout)) {
-        case 128: go_conv_halo<ACT, OUTF32, 128, 2>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
-        case 64: go_conv_halo<ACT, OUTF32, 64, 2>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
-        case 32: go_conv_halo<ACT, OUTF32, 32, 4>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
-        default: go_conv_halo<ACT, OUTF32, 16, 4>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st); break;
+        case 128: go_conv_halo<ACT, OUTF32, 128, 2>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st, pool); break;
+        case 64: go_conv_halo<ACT, OUTF32, 64, 2>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st, pool); break;
+        case 32: go_conv_halo<ACT, OUTF32, 32, 4>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st, pool); break;
+        default: go_conv_halo<ACT, OUTF32, 16, 4>(x, N, H, W, Cin, w, bias, Cout, y, ldy, yoff, st, pool); break;
         }
         return;
     }
@@ -220,6 +221,36 @@ int sscn_nn_conv3x3(const void *x, int N, int H, int W, int Cin, const void *w, 
     else
         launch_conv<ACT_NONE, true>(xs, N, H, W, Cin, wb, bias, Cout, y, ldy, yoff, st, ws, ns);
     return launched("conv3x3");
+}
+
+int sscn_nn_conv3x3_pool(const void *x, int N, int H, int W, int Cin, const void *w, const float *bias, int Cout,
+                         int act, void *y, int ldy, int yoff, void *pool_y, float *ws, int64_t ws_floats,
+                         void *stream)
+{
+    if (!pool_y || H % 2 || W % 2)
+        return nn_fail(-1, "bad conv3x3_pool arguments");
+    if (!x || !w || !y || N < 1 || H < 1 || W < 1 || Cin < 16 || Cin % 16 || Cout < 16 || Cout % 16 ||
+        ldy < yoff + Cout || yoff < 0 || (act != ACT_NONE && act != ACT_LEAKY) || ws_floats < 0)
+        return nn_fail(-1, "bad conv3x3_pool arguments");
+    const int P = N * H * W;
+    int ns = SSCN_NN_CONV_LEGACY ? 1 : conv_splits(P, Cin, Cout);
+    if (!ws || ws_floats < (int64_t)ns * P * Cout)
+        ns = 1;
+    // fused where the halo-patch kernel runs with its staged 16-byte stores
+    // (the conditions of conv_out_vec_ok); otherwise the two calls
+    const bool fused = !SSCN_NN_CONV_LEGACY && ns <= 1 && conv_halo_ok(N, H, W, Cout) && ldy % 8 == 0 &&
+                       yoff % 8 == 0 && aligned16(y) && aligned16(pool_y);
+    if (!fused) {
+        const int r = sscn_nn_conv3x3(x, N, H, W, Cin, w, bias, Cout, act, 0, y, ldy, yoff, ws, ws_floats, stream);
+        return r ? r : sscn_nn_pool2(y, ldy, yoff, N, H, W, Cout, pool_y, stream);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const uint16_t *xs = (const uint16_t *)x, *wb = (const uint16_t *)w;
+    if (act == ACT_LEAKY)
+        launch_conv<ACT_LEAKY, false>(xs, N, H, W, Cin, wb, bias, Cout, y, ldy, yoff, st, ws, 1, (uint16_t *)pool_y);
+    else
+        launch_conv<ACT_NONE, false>(xs, N, H, W, Cin, wb, bias, Cout, y, ldy, yoff, st, ws, 1, (uint16_t *)pool_y);
+    return launched("conv3x3_pool");
 }
 
 int sscn_nn_conv3x3_dgrad(const void *dy, int N, int H, int W, int Cout, const void *w, int Cin,

@@ -25,6 +25,27 @@ __device__ __forceinline__ uint16_t f2bf(float f)
     return (uint16_t)(u >> 16);
 }
 
+// Eight bf16 values of a 16-byte word to fp32 and back (round to nearest
+// even).
+__device__ __forceinline__ void unpack8(const uint4 &u, float (&f)[8])
+{
+    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        f[2 * i] = bf2f((uint16_t)(w[i] & 0xffffu));
+        f[2 * i + 1] = bf2f((uint16_t)(w[i] >> 16));
+    }
+}
+
+__device__ __forceinline__ uint4 pack8(const float (&f)[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 enum { ACT_NONE = 0, ACT_LEAKY = 1 };
 constexpr float kLeak = 0.1f;
 
@@ -469,7 +490,10 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_mfma(const uint16_t *__restr
 // next chunk's patch is loaded into registers during the current chunk's
 // first stage and written over the one patch buffer behind a barrier after
 // its last (one buffer: less LDS per block, more blocks per CU).  Output as
-// k_conv3x3.
+// k_conv3x3.  pool (bf16 outputs only; NULL for none): also the 2 x 2
+// average pooling of the outputs, N x H/2 x W/2 x Cout, from the staged
+// tile; the caller passes it only where the staged stores apply
+// (conv_out_vec_ok) and pool is 16-byte aligned.
 // Grid: (N (H / 8) (W / 16), Cout / BN), 256 threads.
 constexpr int kPatchH = 8, kPatchW = 16;
 constexpr int kHaloPix = (kPatchH + 2) * (kPatchW + 2);
@@ -481,7 +505,8 @@ template <int ACT, bool OUTF32, int BN, int WM, int KC, int TG>
 __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restrict__ x, int N, int H, int W,
                                                          int Cin, const uint16_t *__restrict__ w,
                                                          const float *__restrict__ bias, int Cout,
-                                                         void *__restrict__ y, int ldy, int yoff)
+                                                         void *__restrict__ y, int ldy, int yoff,
+                                                         uint16_t *__restrict__ pool)
 {
     constexpr int BM = 128, WN = 4 / WM;
     constexpr int TM = BM / WM, TN = BN / WN;
@@ -638,6 +663,32 @@ __global__ __launch_bounds__(256, 2) void k_conv3x3_halo(const uint16_t *__restr
                 return (int64_t)(bn * H + by * kPatchH + pm / kPatchW) * W + bx * kPatchW + pm % kPatchW;
             };
             conv_store_vec<ACT, OUTF32, BN, WM>(acc, bias ? bias + co0 : nullptr, y, ldy, yoff + co0, conv_smem, pix);
+            if constexpr (!OUTF32) {
+                // the 2 x 2 averages of the staged outputs (the bf16 values
+                // just stored), with the arithmetic of k_pool2_v8: the patch
+                // holds 4 x 8 whole pooling windows
+                if (pool) {
+                    constexpr int LDO = conv_out_ld<false, BN>(), NQ = BN / 8;
+                    constexpr int QH = kPatchH / 2, QW = kPatchW / 2;
+                    const uint16_t *so = conv_smem;
+                    const int Ho = H / 2, Wo = W / 2;
+                    for (int e = tid; e < QH * QW * NQ; e += 256) {
+                        const int pq = e / NQ, part = e - pq * NQ;
+                        const int pi = pq / QW, pj = pq - pi * QW;
+                        const int pm = 2 * pi * kPatchW + 2 * pj;
+                        float a[8], b[8], c[8], d[8], o[8];
+                        unpack8(*reinterpret_cast<const uint4 *>(so + pm * LDO + part * 8), a);
+                        unpack8(*reinterpret_cast<const uint4 *>(so + (pm + 1) * LDO + part * 8), b);
+                        unpack8(*reinterpret_cast<const uint4 *>(so + (pm + kPatchW) * LDO + part * 8), c);
+                        unpack8(*reinterpret_cast<const uint4 *>(so + (pm + kPatchW + 1) * LDO + part * 8), d);
+#pragma unroll
+                        for (int t = 0; t < 8; ++t)
+                            o[t] = 0.25f * (a[t] + b[t] + c[t] + d[t]);
+                        const size_t q = (size_t)(bn * Ho + by * QH + pi) * Wo + bx * QW + pj;
+                        *reinterpret_cast<uint4 *>(pool + q * Cout + co0 + part * 8) = pack8(o);
+                    }
+                }
+            }
             return;
         }
     }
@@ -1066,25 +1117,6 @@ __global__ __launch_bounds__(256) void k_chan_copy(const uint16_t *__restrict__ 
 // operand and thread); every channel count and channel offset a multiple of
 // 8.  The arithmetic per element is that of the scalar kernels above, so the
 // results are the same bits.
-__device__ __forceinline__ void unpack8(const uint4 &u, float (&f)[8])
-{
-    const uint32_t w[4] = {u.x, u.y, u.z, u.w};
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        f[2 * i] = bf2f((uint16_t)(w[i] & 0xffffu));
-        f[2 * i + 1] = bf2f((uint16_t)(w[i] >> 16));
-    }
-}
-
-__device__ __forceinline__ uint4 pack8(const float (&f)[8])
-{
-    uint32_t w[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-        w[i] = (uint32_t)f2bf(f[2 * i]) | ((uint32_t)f2bf(f[2 * i + 1]) << 16);
-    return make_uint4(w[0], w[1], w[2], w[3]);
-}
-
 __global__ __launch_bounds__(256) void k_pool2_v8(const uint16_t *__restrict__ x, int ldx, int N, int H, int W,
                                                   int C, uint16_t *__restrict__ y)
 {

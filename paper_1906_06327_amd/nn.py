@@ -30,6 +30,7 @@ def _nn():
     if not getattr(L, "_nn_ready", False):
         vp, ci, i64, cf = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
         L.sscn_nn_conv3x3.argtypes = [vp, ci, ci, ci, ci, vp, vp, ci, ci, ci, vp, ci, ci, vp, i64, vp]
+        L.sscn_nn_conv3x3_pool.argtypes = [vp, ci, ci, ci, ci, vp, vp, ci, ci, vp, ci, ci, vp, vp, i64, vp]
         L.sscn_nn_conv_ws_floats.argtypes = [ci, ci, ci, ci, ci, ctypes.POINTER(i64)]
         L.sscn_nn_conv3x3_dgrad.argtypes = [vp, ci, ci, ci, ci, vp, ci, vp, vp, ci, ci, vp, i64, vp]
         L.sscn_nn_wgrad_scratch.argtypes = [ci, ci, ci, ci, ci, ctypes.POINTER(i64)]
@@ -72,6 +73,11 @@ def conv_ws_floats(N, H, W, Cin, Cout):
 def conv3x3(x, N, H, W, Cin, w, b, Cout, act, y, ldy=None, yoff=0, out_f32=False, ws=None, stream=None):
     _ck(_nn().sscn_nn_conv3x3(_p(x), N, H, W, Cin, _p(w), _p(b), Cout, int(act), int(out_f32), _p(y),
                               ldy or Cout, yoff, _p(ws), ws.numel() if ws is not None else 0, stream))
+
+
+def conv3x3_pool(x, N, H, W, Cin, w, b, Cout, act, y, pool, ldy=None, yoff=0, ws=None, stream=None):
+    _ck(_nn().sscn_nn_conv3x3_pool(_p(x), N, H, W, Cin, _p(w), _p(b), Cout, int(act), _p(y), ldy or Cout, yoff,
+                                   _p(pool), _p(ws), ws.numel() if ws is not None else 0, stream))
 
 
 def conv3x3_dgrad(dy, N, H, W, Cout, w, Cin, wt, dx, lddx=None, dxoff=0, ws=None, stream=None):
@@ -294,16 +300,17 @@ class UNet:
 
         # the encoder's second convolution of each level writes straight into
         # the skip half of that level's concatenation buffer (channels cup ..
-        # cup + c - 1 of ld), which the pooling reads in place; the decoder
-        # fills the other half by upsampling
+        # cup + c - 1 of ld) and pools its outputs into the next level's
+        # input; the decoder fills the other half by upsampling
         cup_of = self._cup_of()
         cur = x
         for lv, c in enumerate(self.chans):
             ld = cup_of[lv] + c
             conv(f"enc{lv}a", cur)
-            conv(f"enc{lv}b", self.acts[f"enc{lv}a"], out=self.cat[lv], ldy=ld, yoff=cup_of[lv])
+            _, cin, _, act = spec[f"enc{lv}b"]
             h, w = self.shapes[f"enc{lv}b"]
-            pool2(self.cat[lv], N, h, w, c, self.pool[lv], ldx=ld, xoff=cup_of[lv])
+            conv3x3_pool(self.acts[f"enc{lv}a"], N, h, w, cin, self.wbf[f"enc{lv}b"], self.b[f"enc{lv}b"], c, act,
+                         self.cat[lv], self.pool[lv], ldy=ld, yoff=cup_of[lv], ws=self.scratch)
             cur = self.pool[lv]
         conv("bota", cur)
         conv("botb", self.acts["bota"])

@@ -114,6 +114,36 @@ def test_conv3x3(nn, N, H, W, Cin, Cout, act):
         assert np.array_equal(got[0], got[1])
 
 
+@pytest.mark.parametrize("N,H,W,Cin,Cout,ld,off,split", [
+    # halo-patch shapes with aligned channel slices: pooling fused
+    # (>= 256 patch blocks; BN 32, 64 with two input chunks, 128)
+    (8, 64, 64, 16, 32, 64, 32, False), (8, 64, 64, 64, 64, 64, 0, False), (8, 64, 64, 32, 128, 192, 64, False),
+    # the same where the rows are not 16-byte aligned, a small image (no
+    # halo kernel) and a split K sum: convolution, then the pooling kernel
+    (8, 64, 64, 16, 32, 38, 2, False), (2, 12, 10, 32, 48, 48, 0, False), (1, 16, 16, 128, 256, 512, 256, True)])
+def test_conv_pool_fused(nn, N, H, W, Cin, Cout, ld, off, split):
+    """sscn_nn_conv3x3_pool gives the bits of sscn_nn_conv3x3 followed by
+    sscn_nn_pool2, fused or not."""
+    rng = np.random.default_rng(H * W + Cin)
+    xd, _ = to_bf(rng.standard_normal((N, H, W, Cin)))
+    wd, _ = to_bf(rng.standard_normal((Cout, 3, 3, Cin)) / np.sqrt(9 * Cin))
+    b = f32(rng.standard_normal(Cout))
+    ws = None
+    if split:
+        nws = nn.conv_ws_floats(N, H, W, Cin, Cout)
+        assert nws > 0
+        ws = torch.empty(nws, dtype=torch.float32, device="cuda")
+    y1 = torch.full((N, H, W, ld), 7, dtype=torch.int16, device="cuda")
+    p1 = torch.full((N, H // 2, W // 2, Cout), 7, dtype=torch.int16, device="cuda")
+    nn.conv3x3(xd, N, H, W, Cin, wd, b, Cout, 1, y1, ldy=ld, yoff=off, ws=ws)
+    nn.pool2(y1, N, H, W, Cout, p1, ldx=ld, xoff=off)
+    y2 = torch.full((N, H, W, ld), 7, dtype=torch.int16, device="cuda")
+    p2 = torch.full((N, H // 2, W // 2, Cout), 9, dtype=torch.int16, device="cuda")
+    nn.conv3x3_pool(xd, N, H, W, Cin, wd, b, Cout, 1, y2, p2, ldy=ld, yoff=off, ws=ws)
+    assert torch.equal(y1, y2)
+    assert torch.equal(p1, p2)
+
+
 def test_conv3x3_dgrad_and_wgrad(nn):
     rng = np.random.default_rng(7)
     N, H, W, Cin, Cout = 2, 12, 10, 32, 48
